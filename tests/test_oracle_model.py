@@ -1,0 +1,186 @@
+"""Oracle pins: bath discretisation, model constants, eigen-solve (CPU only)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from oracle import bath, models, closed_forms
+from oracle import electronic as el
+from workloads import configs as wc
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _paper():
+    with open(os.path.join(GOLDEN, "paper_values.json")) as f:
+        return json.load(f)
+
+
+# ----------------------------------------------------------------- discretisation
+@pytest.mark.parametrize("M", [1, 7, 20, 200])
+def test_trapezoid_grid(M):
+    W = 0.1
+    eps, w = bath.trapezoid(M, -W / 2, W / 2)
+    assert eps[0] == -W / 2
+    assert np.allclose(np.diff(eps), W / M, rtol=0, atol=1e-15)
+    assert math.isclose(w.sum(), W, rel_tol=1e-14)
+    assert eps[-1] < W / 2
+
+
+@pytest.mark.parametrize("M", [2, 8, 40, 200])
+def test_gauss_legendre_weights_sum_and_exactness(M):
+    """Each half integrates polynomials up to degree M-1 exactly: check the
+    moments against the closed form of int eps^p over both halves."""
+    W = 0.1
+    a, b = -W / 2, W / 2
+    eps, w = bath.gauss_legendre(M, a, b, 0.0)
+    assert np.all(w > 0)
+    assert np.all(np.diff(eps) > 0)
+    assert math.isclose(w.sum(), W, rel_tol=1e-13)
+    half = M // 2
+    lo, hi = slice(0, half), slice(half, M)
+    for p in range(0, M):
+        exact_lo = (0.0 ** (p + 1) - a ** (p + 1)) / (p + 1)
+        exact_hi = (b ** (p + 1) - 0.0 ** (p + 1)) / (p + 1)
+        scale = (W / 2) ** (p + 1)
+        assert abs(np.sum(w[lo] * eps[lo] ** p) - exact_lo) <= 1e-13 * scale
+        assert abs(np.sum(w[hi] * eps[hi] ** p) - exact_hi) <= 1e-13 * scale
+
+
+def test_gauss_legendre_offcentre_split():
+    eps, w = bath.gauss_legendre(10, -1.0, 3.0, 0.5)
+    assert math.isclose(w[:5].sum(), 1.5, rel_tol=1e-14)
+    assert math.isclose(w[5:].sum(), 2.5, rel_tol=1e-14)
+    assert eps[4] < 0.5 < eps[5]
+
+
+@pytest.mark.parametrize("kind", ["trapezoid_midpoint", "gauss_legendre"])
+def test_discrete_hybridisation_function(kind):
+    """Lambda(E) = sum_k V_k^2/(E - eps_k) approaches the continuum
+    (Gamma/2pi) ln((E - a)/(E - b)) for E outside the band (Appendix A)."""
+    Gamma, W, E = 0.01, 0.1, 0.08
+    exact = Gamma / (2 * math.pi) * math.log((E + W / 2) / (E - W / 2))
+    errs = []
+    for M in (20, 80, 320):
+        eps, w = bath.discretise(kind, M, W)
+        V = bath.couplings(Gamma, w)
+        errs.append(abs(np.sum(V ** 2 / (E - eps)) - exact))
+    assert errs[-1] < 1e-3 * abs(exact)
+    assert errs[2] < errs[0]
+
+
+def test_coupling_sum_rule():
+    for kind in ("trapezoid", "gauss_legendre"):
+        eps, w = bath.discretise(kind, 40, 0.1)
+        V = bath.couplings(0.0064, w)
+        assert math.isclose(np.sum(V ** 2), 0.0064 * 0.1 / (2 * math.pi), rel_tol=1e-13)
+
+
+# ----------------------------------------------------------------- model constants
+def test_double_well_constants_match_paper():
+    p = _paper()["double_well"]
+    dw = wc.DOUBLE_WELL
+    assert dw["mass"] == p["mass"] and dw["omega"] == p["omega"]
+    assert dw["g"] == p["g"] and dw["dG"] == p["dG"]
+    assert wc.get_config("c1")["kT"] == p["kT"]
+
+
+def test_desorption_unit_conversions_and_classical_ratio():
+    """kT/(hbar omega) at 300 K for 1 u and 10.54 u and Q(beta, omega), printed
+    in Sec. III.C, from the Table et-parameters Morse constants."""
+    p = _paper()
+    t = p["desorption_table"]
+    De = wc.ev(t["De_eV"])
+    a = t["a_per_A"] * wc.BOHR_ANGSTROM
+    kT = 300.0 * wc.KB_HARTREE_PER_K
+    for mass_u, key in ((1.0, "kT_over_hbar_omega_1u_300K"), (10.54, "kT_over_hbar_omega_10p54u_300K")):
+        m = mass_u * wc.AMU_ME
+        omega = math.sqrt(2 * De * a * a / m)      # U0''(x0) = 2 De a^2
+        ratio = kT / omega
+        assert abs(ratio - p[key]["value"]) <= p[key]["unit_last_place"]
+    m = 10.54 * wc.AMU_ME
+    omega = math.sqrt(2 * De * a * a / m)
+    Q = closed_forms.harmonic_wigner_factor(1.0 / kT, omega)
+    assert abs(Q - p["wigner_Q_10p54u_300K"]["value"]) <= p["wigner_Q_10p54u_300K"]["unit_last_place"]
+
+
+def test_crossing_barrier():
+    """The U0/U1 crossing lies 1.83 eV above the far-field U1 level
+    (Fig. scattering caption)."""
+    p = _paper()
+    t = wc.DESORPTION_TABLE
+    eps, w = bath.discretise("gauss_legendre", 4, 1.0)
+    m = models.MorseTanh(eps, w, 0.0, t["mass"], t["De"], t["x0"], t["a"], t["D1"], t["D2"],
+                         t["ap"], t["Vinf"], t["q"], t["atil"], t["xtil"], t["c"])
+    f = lambda x: m.U0(np.array([x])) - m.U1(np.array([x]))
+    xc = brentq(f, 2.0, 10.0)
+    barrier_ev = (m.U0(np.array([xc])) - t["Vinf"]) * wc.HARTREE_EV
+    assert abs(barrier_ev - p["crossing_barrier_eV"]["value"]) <= p["crossing_barrier_eV"]["unit_last_place"]
+
+
+def test_model_derivatives_fd():
+    cfg3 = wc.get_config("c3")
+    for cfg, xs in ((wc.get_config("c1"), [-3.0, 0.0, 7.5]), (cfg3, [3.0, 5.0, 9.0])):
+        m = models.from_config(cfg, M=8) if cfg is cfg3 else models.from_config(cfg)
+        h = 1e-6
+        for x in xs:
+            X = np.array([x])
+            assert abs(m.dU0(X)[0] - (m.U0(X + h) - m.U0(X - h)) / (2 * h)) < 1e-7 * max(1, abs(m.dU0(X)[0]))
+            assert abs(m.dh(X)[0] - (m.h(X + h) - m.h(X - h)) / (2 * h)) < 1e-7 * max(1e-3, abs(m.dh(X)[0]))
+            dV = (m.V(X + h) - m.V(X - h)) / (2 * h)
+            assert np.allclose(m.dV(X)[:, 0], dV, atol=1e-9)
+
+
+# ------------------------------------------------------------------- eigen-solve
+def test_eig_two_level_closed_form():
+    eps, w = np.array([0.01]), np.array([0.1])
+    m = models.Harmonic(eps, w, 0.02, 2000.0, 2e-4, 20.0, -3.8e-3)
+    for x in (-5.0, 0.0, 3.0, 12.0):
+        X = np.array([x])
+        lam, Q = el.eig(m.H(X))
+        ref = closed_forms.two_level_eigenvalues(m.h(X), 0.01, m.V(X)[0])
+        assert np.allclose(lam, ref, rtol=0, atol=1e-16)
+        assert np.all(Q[0] > 0)
+
+
+@pytest.mark.parametrize("cfg_name,M", [("c1", 20), ("c2gl", 40), ("c3", 40)])
+def test_eig_arrowhead_identities(cfg_name, M):
+    """Dense eigh of the arrowhead Hamiltonian satisfies: reconstruction,
+    strict interlacing with the bath levels, the secular equation
+    lambda - h - sum V^2/(lambda - eps) = 0, the Loewner identity
+    V_k^2 = -prod_j (eps_k - lambda_j) / prod_{l != k} (eps_k - eps_l), and the
+    eigenvector form u_j ~ (1, V_k/(lambda_j - eps_k))."""
+    cfg = wc.get_config(cfg_name)
+    m = models.from_config(cfg, M=M)
+    xs = [-4.0, 0.5, 6.0] if cfg_name != "c3" else [2.5, 4.0, 9.0]
+    for x in xs:
+        X = np.array([x])
+        H = m.H(X)
+        lam, Q = el.eig(H)
+        assert np.max(np.abs(Q @ np.diag(lam) @ Q.T - H)) < 1e-15 * 50
+        eps, V, h = m.eps, m.V(X), m.h(X)
+        # interlacing lambda_0 < eps_1 < lambda_1 < ... < eps_M < lambda_M
+        assert np.all(lam[:-1] < eps) and np.all(eps < lam[1:])
+        for j in range(len(lam)):
+            terms = V ** 2 / (lam[j] - eps)
+            f = lam[j] - h - terms.sum()
+            fprime = 1.0 + np.sum(V ** 2 / (lam[j] - eps) ** 2)
+            # the Newton correction f/f' is at rounding level of the spectrum
+            assert abs(f / fprime) < 1e-14 * np.max(np.abs(lam))
+        for k in range(M):
+            num = np.prod((eps[k] - lam) / np.where(np.arange(M + 1) == 0, 1.0, 1.0))
+            den = np.prod(np.delete(eps[k] - eps, k))
+            # pair factors to stay in range: log form
+            lv = np.sum(np.log(np.abs(eps[k] - lam))) - np.sum(np.log(np.abs(np.delete(eps[k] - eps, k))))
+            # eigh's absolute eigenvalue error ~ eps*|H| propagates through
+            # every factor (eps_k - lambda_j)
+            tol = 20 * np.finfo(float).eps * np.max(np.abs(lam)) * np.sum(1.0 / np.abs(eps[k] - lam))
+            assert abs(math.exp(lv) / V[k] ** 2 - 1.0) < max(tol, 1e-13)
+            assert np.sign(num / den) == -1.0
+        for j in range(len(lam)):
+            u = np.concatenate([[1.0], V / (lam[j] - eps)])
+            u /= np.linalg.norm(u)
+            assert np.max(np.abs(u - Q[:, j])) < 1e-9

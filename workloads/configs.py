@@ -1,0 +1,99 @@
+"""Workload descriptions (constants only, atomic units throughout).
+
+Model constants follow the paper: the double-well harmonic diabats of
+Sec. III.B and the desorption/scattering model of Sec. III.C
+(Eqs. U0, U1, Vk and Table et-parameters).  Sizes, time steps, trajectory
+counts and seeds are the synthetic workloads this library is measured on.
+
+Unit conversions use CODATA 2018 values.
+"""
+from __future__ import annotations
+
+import copy
+
+# CODATA 2018
+HARTREE_EV = 27.211386245988
+BOHR_ANGSTROM = 0.529177210903
+AMU_ME = 1822.888486209          # unified atomic mass unit in electron masses
+KB_HARTREE_PER_K = 3.166811563e-6  # Boltzmann constant in Hartree/K
+FS_AU = 41.341373335             # 1 fs in atomic time units
+
+
+def ev(x):
+    return x / HARTREE_EV
+
+
+def angstrom(x):
+    return x / BOHR_ANGSTROM
+
+
+# Double-well model of Sec. III.B (harmonic diabats).  The paper's relaxation
+# study uses g = 20.6097; the throughput workloads below use g = 20.
+DOUBLE_WELL = dict(kind="harmonic", mass=2000.0, omega=2e-4, g=20.6097, dG=-3.8e-3)
+
+# Desorption / scattering model of Sec. III.C, Table et-parameters, in a.u.
+# The scattering workload replaces the Morse depth and range by D = 0.1 Ha and
+# a = 1.0 / bohr.
+DESORPTION_TABLE = dict(
+    De=ev(3.52), x0=angstrom(1.78), a=1.7361 * BOHR_ANGSTROM,
+    D1=ev(4.52), D2=ev(0.79), ap=1.379 * BOHR_ANGSTROM,
+    Vinf=ev(-1.5), q=0.05, atil=angstrom(0.5), xtil=angstrom(3.5),
+    mass=10.54 * AMU_ME, c=ev(-45.7e-3),
+)
+
+CONFIGS = {
+    # Plain IESH, FP64, small: the parity workload.
+    "c1": dict(
+        name="harmonic M=20 N=10, 128 trajectories, dt=50",
+        model=dict(kind="harmonic", mass=2000.0, omega=2e-4, g=20.0, dG=-3.8e-3,
+                   Gamma=0.01, eps_d=0.0),
+        bath=dict(kind="trapezoid", M=20, W=0.1),
+        n_elec=10, kT=9.5e-4, sample_kT_factor=1.0,
+        n_traj=128, n_steps=1000, dt=50.0, seed=0,
+    ),
+    # Plain IESH at scale: the headline throughput workload.
+    "c2": dict(
+        name="harmonic M=200 N=100, 4096 trajectories, dt=20",
+        model=dict(kind="harmonic", mass=2000.0, omega=2e-4, g=20.0, dG=-3.8e-3,
+                   Gamma=0.01, eps_d=0.0),
+        bath=dict(kind="trapezoid", M=200, W=0.1),
+        n_elec=100, kT=9.5e-4, sample_kT_factor=1.0,
+        n_traj=4096, n_steps=20000, dt=20.0, seed=0,
+    ),
+    # Same as c2 with the Gauss-Legendre two-half discretisation (App. A).
+    "c2gl": dict(
+        name="harmonic M=200 N=100 Gauss-Legendre bath, 4096 trajectories, dt=20",
+        model=dict(kind="harmonic", mass=2000.0, omega=2e-4, g=20.0, dG=-3.8e-3,
+                   Gamma=0.01, eps_d=0.0),
+        bath=dict(kind="gauss_legendre", M=200, W=0.1),
+        n_elec=100, kT=9.5e-4, sample_kT_factor=1.0,
+        n_traj=4096, n_steps=20000, dt=20.0, seed=0,
+    ),
+    # Uneven batched scattering (Morse / repulsive diabats, tanh coupling).
+    "c3": dict(
+        name="scattering, M in {40,80,160,320}, N=M/2, 16384 trajectories, dt=5",
+        model=dict(kind="morse_tanh", De=0.1, x0=DESORPTION_TABLE["x0"], a=1.0,
+                   D1=DESORPTION_TABLE["D1"], D2=DESORPTION_TABLE["D2"],
+                   ap=DESORPTION_TABLE["ap"], Vinf=DESORPTION_TABLE["Vinf"],
+                   q=DESORPTION_TABLE["q"], atil=DESORPTION_TABLE["atil"],
+                   xtil=DESORPTION_TABLE["xtil"], mass=DESORPTION_TABLE["mass"],
+                   c=DESORPTION_TABLE["c"], Gamma=ev(1.0), eps_d=0.0),
+        bath=dict(kind="gauss_legendre", M_classes=[40, 80, 160, 320], W=ev(64.0)),
+        kT=0.0, x_start=angstrom(5.0), E_inc=(ev(0.05), ev(1.0)),
+        exit_x=15.0, max_steps=20000,
+        n_traj=16384, dt=5.0, seed=0,
+    ),
+    # Adjoint workload: fixed nuclear paths.
+    "c4": dict(
+        name="adjoint, harmonic M=100 N=50, 1024 fixed paths, 2000 steps, dt=20",
+        model=dict(kind="harmonic", mass=2000.0, omega=2e-4, g=20.0, dG=-3.8e-3,
+                   Gamma=0.01, eps_d=0.0),
+        bath=dict(kind="trapezoid", M=100, W=0.1),
+        n_elec=50, kT=9.5e-4, n_traj=1024, n_steps=2000, dt=20.0, ckpt_every=100,
+        seed=0,
+    ),
+}
+
+
+def get_config(name: str) -> dict:
+    return copy.deepcopy(CONFIGS[name])
