@@ -1,0 +1,252 @@
+/*
+ * iesh.h -- C ABI of the MI355X (gfx950) ensemble engine for independent
+ * electron surface hopping (IESH) on discretised Newns-Anderson models.
+ *
+ * The library advances many independent trajectories by the IESH time step
+ * of Gardner et al., "Efficient implementation and performance analysis of
+ * the independent electron surface hopping method for dynamics at metal
+ * surfaces": per step and trajectory it
+ *   (a) diagonalises the one-electron Hamiltonian H(x) (Sec. II.B, Eq.
+ *       single_electron_discrete_electronic_hamiltonian),
+ *   (b) forms nonadiabatic couplings and Hellmann-Feynman forces (Sec. II.B,
+ *       Eq. classical_hamiltonian and the coupling definition after Eq.
+ *       electronic_schrodinger_equation),
+ *   (c) propagates the N orbitals with the exponential integrator (Sec. II.C,
+ *       Eq. exponential_integrator),
+ *   (d) evaluates the hop probabilities from Slater-determinant ratios
+ *       (Sec. II.B, Eqs. hopping_probability and hopping_rate), samples a
+ *       hop, rescales the velocity and completes velocity Verlet.
+ *
+ * Conventions (atomic units, hbar = 1):
+ *   n = M + 1 one-electron states: index 0 is the impurity |d>, 1..M the bath.
+ *   Adiabatic orbitals are ordered by ascending energy; the gauge makes the
+ *   impurity component of every orbital positive.
+ *   D[j][k] = <j| d/dx |k> = (Q^T dH/dx Q)[j][k] / (lambda_k - lambda_j).
+ *   The orbital equation of motion is i dc/dt = (diag(lambda) - i v D) c.
+ *   g(a -> b) = max(-2 dt v D[b][a] Re W[b][r(a)], 0), W = C S^-1,
+ *   S = C[s, :], r(a) the position of a in the sorted occupied set s.
+ *   Step order: half kick, drift, orbital propagation with the propagator
+ *   frozen at the midpoint geometry and velocity, eigen-solve at the new
+ *   geometry, half kick, hop (probabilities from the new orbitals, couplings
+ *   and velocity; one uniform per trajectory and step; rows of occupied
+ *   orbitals ascending, then targets ascending), rescaling along D[b][a] or
+ *   frustration (no change), force refresh after an accepted hop.
+ *   Hop uniforms: Philox4x32-10 with counter (step lo, step hi, trajectory,
+ *   0) and key (seed lo, seed hi); u = ((w1 << 32 | w0) >> 11) * 2^-53.
+ *
+ * Ownership and threading: every buffer passed in is owned by the caller and
+ * is not retained after the call returns.  A context is used by one host
+ * thread at a time.  All device work runs on the stream given at creation
+ * (NULL: a stream created and owned by the context).  Functions return IESH_OK or a negative error
+ * code; no C++ exception crosses the ABI.  iesh_last_error() describes the
+ * last failure on a context.  Numerical failures of single trajectories do
+ * not fail a call: they set that trajectory's status word and freeze it.
+ */
+#ifndef IESH_H
+#define IESH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define IESH_OK 0
+#define IESH_EINVAL (-1)   /* invalid argument                               */
+#define IESH_ENOMEM (-2)   /* device allocation failed                       */
+#define IESH_EDEVICE (-3)  /* HIP runtime / kernel launch error              */
+#define IESH_ESTATE (-4)   /* call not valid in the current context state   */
+#define IESH_ENOTSUP (-5)  /* combination not supported by this build        */
+
+/* ---- per-trajectory status bits (iesh_traj_status) -------------------- */
+#define IESH_TRAJ_OK 0
+#define IESH_TRAJ_EXITED 1      /* crossed the exit plane; frozen            */
+#define IESH_TRAJ_NONCONV 2     /* secular-equation root did not converge    */
+#define IESH_TRAJ_SINGULAR_S 4  /* occupied overlap S singular: hop skipped  */
+#define IESH_TRAJ_NONFINITE 8   /* non-finite position or velocity; frozen   */
+#define IESH_TRAJ_STEPCAP 16    /* reached run.max_steps; frozen             */
+
+/* ---- enumerations ------------------------------------------------------- */
+enum iesh_model_kind {
+  /* Double-well model (Sec. III.B): U0 = m w^2 x^2/2,
+     U1 = m w^2 (x-g)^2/2 + dG, h = U1 - U0 + eps_d, V_k constant.
+     params: [0] omega, [1] g, [2] dG, [3] eps_d.                           */
+  IESH_MODEL_HARMONIC = 0,
+  /* Desorption / scattering model (Sec. III.C, Eqs. U0, U1, Vk):
+     U0 = De (exp(-a(x-x0)) - 1)^2 + c,
+     U1 = D1 exp(-2a'(x-x0)) - D2 exp(-a'(x-x0)) + Vinf,
+     V_k(x) = Vbar_k [(1-q)/2 (1 - tanh((x - xt)/at)) + q].
+     params: [0] De, [1] x0, [2] a, [3] D1, [4] D2, [5] a', [6] Vinf, [7] q,
+             [8] at, [9] xt, [10] c, [11] eps_d.                            */
+  IESH_MODEL_MORSE_TANH = 1
+};
+
+enum iesh_precision {
+  IESH_FP64 = 0,  /* every step in FP64                                       */
+  IESH_MIXED = 1  /* orbitals and propagation in FP32; eigen-solve, overlap
+                     inverse, hop probabilities and rescaling in FP64;
+                     FP64 Loewdin re-orthonormalisation every lowdin_every   */
+};
+
+enum iesh_mem_kind { IESH_MEM_HOST = 0, IESH_MEM_DEVICE = 1 };
+
+enum iesh_bath_kind {
+  IESH_BATH_TRAPEZOID = 0,           /* eps_k = a + (k-1)(b-a)/M (App. A)    */
+  IESH_BATH_TRAPEZOID_MIDPOINT = 1,  /* eps_k = a + (k-1/2)(b-a)/M           */
+  IESH_BATH_GAUSS_LEGENDRE = 2       /* M/2 Gauss-Legendre nodes on [a, eps_f]
+                                        and M/2 on [eps_f, b] (App. A)        */
+};
+
+/* ---- descriptors -------------------------------------------------------- */
+typedef struct iesh_model_desc {
+  int32_t kind;        /* enum iesh_model_kind                                */
+  int32_t n_bath;      /* M >= 1; n = M + 1 <= IESH_MAX_STATES                */
+  int32_t n_elec;      /* N electrons, 1 <= N <= min(n - 1, IESH_MAX_ELEC)     */
+  int32_t reserved0;
+  const double* eps;   /* host, M bath energies, strictly ascending           */
+  const double* w;     /* host, M quadrature weights > 0 (V_k = sqrt(Gamma w_k / 2 pi)) */
+  double mass;         /* nuclear mass > 0                                    */
+  double Gamma;        /* hybridisation Gamma > 0 (Eq. hybridization)          */
+  double params[16];   /* model constants, layout per iesh_model_kind         */
+} iesh_model_desc;
+
+typedef struct iesh_run_desc {
+  int32_t n_traj;        /* number of trajectories >= 1                        */
+  int32_t precision;     /* enum iesh_precision                                 */
+  double dt;             /* time step > 0                                       */
+  double kT;             /* temperature of the initial Fermi occupations >= 0  */
+  uint64_t seed;         /* key of the hop uniforms                             */
+  int32_t lowdin_every;  /* IESH_MIXED: re-orthonormalise every L steps (0: never) */
+  int32_t record_every;  /* observables every R steps in iesh_run (0: none)    */
+  int32_t exit_enabled;  /* freeze trajectories once x > exit_x                */
+  int32_t reserved0;
+  double exit_x;
+  int64_t max_steps;     /* freeze a trajectory after this many steps (0: no cap) */
+} iesh_run_desc;
+
+#define IESH_MAX_STATES 224   /* n = M + 1 limit of this build                */
+#define IESH_MAX_ELEC 128     /* N limit of this build                        */
+
+/* Observables written per record and trajectory by iesh_run, in this order. */
+#define IESH_OBS_PD_SURF 0   /* sum_{a in s} Q[0][a]^2                         */
+#define IESH_OBS_PD_WF 1     /* sum_n |sum_a Q[0][a] C[a][n]|^2                */
+#define IESH_OBS_EKIN 2      /* m v^2 / 2                                      */
+#define IESH_OBS_EPOT 3      /* U0(x) + sum_{a in s} lambda_a                  */
+#define IESH_OBS_ETOT 4
+#define IESH_N_OBS 5
+
+/* Hop event record (iesh_events). */
+typedef struct iesh_event {
+  int64_t step;      /* global step index of the hop attempt                   */
+  int32_t traj;
+  int32_t a;         /* orbital left (adiabatic index)                         */
+  int32_t b;         /* orbital entered                                        */
+  int32_t accepted;  /* 1 accepted, 0 frustrated                               */
+  double margin;     /* min |cumulative sum - xi| over the sums formed         */
+  double g_total;    /* sum of all hop probabilities of this step              */
+} iesh_event;
+
+typedef struct iesh_ctx iesh_ctx;
+
+/* ---- lifecycle ------------------------------------------------------------ */
+
+/* Create a context for run->n_traj trajectories.  traj_model[t] in
+   [0, n_models) selects the model (bath size class) of trajectory t; NULL
+   means every trajectory uses models[0].  Copies every descriptor array.
+   hip_stream is a hipStream_t (NULL: the context creates and owns a stream).  Validates: sorted eps,
+   w > 0, N within limits, dt > 0, mass > 0, kT >= 0.  Allocates all device
+   memory up front. */
+int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* traj_model,
+                const iesh_run_desc* run, void* hip_stream, iesh_ctx** out);
+
+/* Free everything.  NULL is accepted. */
+int iesh_destroy(iesh_ctx* ctx);
+
+/* Bath discretisation of Appendix A on the band [a, b] (eps_f splits the
+   Gauss-Legendre halves; M must be even for it).  Writes M energies and
+   weights to host arrays.  Pure host computation. */
+int iesh_discretize(int32_t kind, int32_t M, double a, double b, double eps_f, double* eps,
+                    double* w);
+
+/* ---- state ----------------------------------------------------------------
+   Layouts (both for host and device buffers):
+     x, v   : n_traj doubles
+     C      : n_traj blocks; block t holds N_t * n_t complex doubles,
+              orbital-major (C[t][j][i] = coefficient of adiabatic state i in
+              orbital j), interleaved (re, im); blocks are packed with the
+              stride n_max * N_max complex values of the context
+              (iesh_query_sizes), i.e. element (t, j, i) sits at complex
+              offset t * n_max * N_max + j * n_t + i.
+     occ    : n_traj blocks of stride N_max int32, block t holds N_t sorted
+              occupied adiabatic indices.
+   mem_kind says whether the pointers are host or device (same device as the
+   context) memory.  set_state also recomputes the forces and clears status
+   words and the hop event log; the step counter is kept. */
+int iesh_set_state(iesh_ctx* ctx, const double* x, const double* v, const double* C,
+                   const int32_t* occ, int32_t mem_kind);
+int iesh_get_state(iesh_ctx* ctx, double* x, double* v, double* C, int32_t* occ,
+                   int32_t mem_kind);
+
+/* Initial state from positions and velocities (host arrays): occupations
+   sampled at run.kT over the adiabatic energies at x (fixed N: chemical
+   potential by bisection, one uniform per level from Philox stream 1 at
+   counter attempt*n + level, accept when exactly N levels are occupied;
+   kT = 0 or 4096 failed attempts give the lowest N), orbitals = occupied
+   adiabatic unit vectors (Sec. III.C). */
+int iesh_init_thermal(iesh_ctx* ctx, const double* x, const double* v);
+
+/* Global step counter (the hop-uniform counter of the next step). */
+int iesh_set_step(iesh_ctx* ctx, int64_t step);
+int iesh_get_step(const iesh_ctx* ctx, int64_t* step);
+
+/* ---- dynamics ------------------------------------------------------------- */
+
+/* One step of every active trajectory; asynchronous on the context stream. */
+int iesh_step(iesh_ctx* ctx);
+
+/* n_steps steps (replayed from a captured HIP graph).  If obs_out is not
+   NULL and run.record_every > 0, writes floor(n_steps / record_every)
+   records of n_traj * IESH_N_OBS doubles (host memory) taken after every
+   record_every-th step of this call.  Synchronises before returning. */
+int iesh_run(iesh_ctx* ctx, int64_t n_steps, double* obs_out);
+
+/* ---- queries ---------------------------------------------------------------- */
+
+/* Hop probabilities at the current state without sampling: for
+   trajectories traj0 .. traj0+ntraj-1 (one model class), writes N_t * n_t
+   doubles per trajectory (row r = occupied orbital s[r], column b = target
+   state; 0 for occupied targets), packed with stride N_max * n_max.
+   Couplings and energies are those at the current x, velocity the current v. */
+int iesh_hop_probs(iesh_ctx* ctx, int32_t traj0, int32_t ntraj, double* g_out, int32_t mem_kind);
+
+/* Adiabatic energies and impurity amplitudes Q[0][j] > 0 at the current x
+   (host arrays, n_t values per trajectory packed with stride n_max). */
+int iesh_adiabatic(iesh_ctx* ctx, int32_t traj0, int32_t ntraj, double* lam_out, double* q0_out);
+
+/* Status words (n_traj int32, host). */
+int iesh_traj_status(iesh_ctx* ctx, int32_t* status_out);
+
+/* Copy up to cap hop events (sorted by step, then trajectory) recorded
+   since the last set_state / clear into out (host); *count receives the
+   number recorded (may exceed cap; the log keeps the first IESH_EVENT_CAP). */
+#define IESH_EVENT_CAP (1 << 20)
+int iesh_events(iesh_ctx* ctx, iesh_event* out, int64_t cap, int64_t* count);
+int iesh_clear_events(iesh_ctx* ctx);
+
+typedef struct iesh_sizes {
+  int32_t n_traj, n_models, n_max, N_max;
+  int64_t device_bytes;
+} iesh_sizes;
+int iesh_query_sizes(const iesh_ctx* ctx, iesh_sizes* out);
+
+/* Wait for all work on the context stream; reports asynchronous errors. */
+int iesh_sync(iesh_ctx* ctx);
+
+const char* iesh_last_error(const iesh_ctx* ctx);
+int iesh_version(int* major, int* minor, int* patch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IESH_H */

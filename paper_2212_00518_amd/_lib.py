@@ -1,0 +1,290 @@
+"""ctypes binding of libiesh (the C ABI declared in include/iesh.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiesh.so")
+
+IESH_OK = 0
+IESH_MODEL_HARMONIC = 0
+IESH_MODEL_MORSE_TANH = 1
+IESH_FP64 = 0
+IESH_MIXED = 1
+IESH_MEM_HOST = 0
+IESH_MEM_DEVICE = 1
+IESH_BATH_TRAPEZOID = 0
+IESH_BATH_TRAPEZOID_MIDPOINT = 1
+IESH_BATH_GAUSS_LEGENDRE = 2
+IESH_N_OBS = 5
+IESH_MAX_STATES = 224
+IESH_MAX_ELEC = 128
+IESH_EVENT_CAP = 1 << 20
+
+TRAJ_EXITED, TRAJ_NONCONV, TRAJ_SINGULAR_S, TRAJ_NONFINITE, TRAJ_STEPCAP = 1, 2, 4, 8, 16
+
+OBS_NAMES = ("Pd_surf", "Pd_wf", "Ekin", "Epot", "Etot")
+
+# exported symbols (kept in sync with include/iesh.h)
+SYMBOLS = (
+    "iesh_create", "iesh_destroy", "iesh_discretize", "iesh_set_state", "iesh_get_state",
+    "iesh_init_thermal", "iesh_set_step", "iesh_get_step", "iesh_step", "iesh_run",
+    "iesh_hop_probs", "iesh_adiabatic", "iesh_traj_status", "iesh_events",
+    "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
+)
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_bath", C.c_int32), ("n_elec", C.c_int32),
+                ("reserved0", C.c_int32), ("eps", C.POINTER(C.c_double)),
+                ("w", C.POINTER(C.c_double)), ("mass", C.c_double), ("Gamma", C.c_double),
+                ("params", C.c_double * 16)]
+
+
+class RunDesc(C.Structure):
+    _fields_ = [("n_traj", C.c_int32), ("precision", C.c_int32), ("dt", C.c_double),
+                ("kT", C.c_double), ("seed", C.c_uint64), ("lowdin_every", C.c_int32),
+                ("record_every", C.c_int32), ("exit_enabled", C.c_int32),
+                ("reserved0", C.c_int32), ("exit_x", C.c_double), ("max_steps", C.c_int64)]
+
+
+class Event(C.Structure):
+    _fields_ = [("step", C.c_int64), ("traj", C.c_int32), ("a", C.c_int32), ("b", C.c_int32),
+                ("accepted", C.c_int32), ("margin", C.c_double), ("g_total", C.c_double)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("n_traj", C.c_int32), ("n_models", C.c_int32), ("n_max", C.c_int32),
+                ("N_max", C.c_int32), ("device_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"libiesh.so not found at {LIB_PATH}: build it with "
+                "`python -m paper_2212_00518_amd.build_lib` (there is no fallback path)")
+        L = C.CDLL(LIB_PATH)
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int32)
+        vp = C.c_void_p
+        L.iesh_create.argtypes = [C.POINTER(ModelDesc), C.c_int32, ip, C.POINTER(RunDesc), vp,
+                                  C.POINTER(vp)]
+        L.iesh_destroy.argtypes = [vp]
+        L.iesh_discretize.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                      dp, dp]
+        L.iesh_set_state.argtypes = [vp, vp, vp, vp, vp, C.c_int32]
+        L.iesh_get_state.argtypes = [vp, vp, vp, vp, vp, C.c_int32]
+        L.iesh_init_thermal.argtypes = [vp, dp, dp]
+        L.iesh_set_step.argtypes = [vp, C.c_int64]
+        L.iesh_get_step.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.iesh_step.argtypes = [vp]
+        L.iesh_run.argtypes = [vp, C.c_int64, dp]
+        L.iesh_hop_probs.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int32]
+        L.iesh_adiabatic.argtypes = [vp, C.c_int32, C.c_int32, dp, dp]
+        L.iesh_traj_status.argtypes = [vp, ip]
+        L.iesh_events.argtypes = [vp, C.POINTER(Event), C.c_int64, C.POINTER(C.c_int64)]
+        L.iesh_clear_events.argtypes = [vp]
+        L.iesh_query_sizes.argtypes = [vp, C.POINTER(Sizes)]
+        L.iesh_sync.argtypes = [vp]
+        L.iesh_last_error.argtypes = [vp]
+        L.iesh_last_error.restype = C.c_char_p
+        L.iesh_version.argtypes = [ip, ip, ip]
+        _lib = L
+    return _lib
+
+
+class IeshError(RuntimeError):
+    pass
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def discretize(kind: str, M: int, W: float, eps_f: float = 0.0):
+    """Bath energies and weights on [-W/2, W/2] from the library (Appendix A)."""
+    k = {"trapezoid": IESH_BATH_TRAPEZOID, "trapezoid_midpoint": IESH_BATH_TRAPEZOID_MIDPOINT,
+         "gauss_legendre": IESH_BATH_GAUSS_LEGENDRE}[kind]
+    eps = np.zeros(M)
+    w = np.zeros(M)
+    rc = lib().iesh_discretize(k, M, -0.5 * W, 0.5 * W, eps_f,
+                               eps.ctypes.data_as(C.POINTER(C.c_double)),
+                               w.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != IESH_OK:
+        raise IeshError(f"iesh_discretize failed ({rc})")
+    return eps, w
+
+
+def model_desc(model: dict, eps, w, n_elec: int):
+    """Fill an iesh_model_desc; `model` follows workloads.configs."""
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    d = ModelDesc()
+    d.n_bath = len(eps)
+    d.n_elec = int(n_elec)
+    d.eps = eps.ctypes.data_as(C.POINTER(C.c_double))
+    d.w = w.ctypes.data_as(C.POINTER(C.c_double))
+    d.mass = float(model["mass"])
+    d.Gamma = float(model["Gamma"])
+    p = [0.0] * 16
+    if model["kind"] == "harmonic":
+        d.kind = IESH_MODEL_HARMONIC
+        p[:4] = [model["omega"], model["g"], model["dG"], model.get("eps_d", 0.0)]
+    elif model["kind"] == "morse_tanh":
+        d.kind = IESH_MODEL_MORSE_TANH
+        p[:12] = [model[k] for k in ("De", "x0", "a", "D1", "D2", "ap", "Vinf", "q", "atil",
+                                     "xtil", "c")] + [model.get("eps_d", 0.0)]
+    else:
+        raise ValueError(model["kind"])
+    d.params[:] = p
+    # keep arrays alive with the descriptor
+    d._keep = (eps, w)
+    return d
+
+
+class Ensemble:
+    """An ensemble of independent IESH trajectories on one GPU."""
+
+    def __init__(self, models, run: dict, traj_model=None, stream=None):
+        L = lib()
+        self._descs = list(models)
+        arr = (ModelDesc * len(self._descs))(*self._descs)
+        self._arr = arr
+        r = RunDesc()
+        r.n_traj = int(run["n_traj"])
+        r.precision = IESH_MIXED if run.get("precision", "fp64") == "mixed" else IESH_FP64
+        r.dt = float(run["dt"])
+        r.kT = float(run.get("kT", 0.0))
+        r.seed = int(run.get("seed", 0))
+        r.lowdin_every = int(run.get("lowdin_every", 0))
+        r.record_every = int(run.get("record_every", 0))
+        r.exit_enabled = int(run.get("exit_enabled", 0))
+        r.exit_x = float(run.get("exit_x", 0.0))
+        r.max_steps = int(run.get("max_steps", 0))
+        self.run_desc = r
+        tm = None
+        if traj_model is not None:
+            self._tm = np.ascontiguousarray(traj_model, dtype=np.int32)
+            tm = self._tm.ctypes.data_as(C.POINTER(C.c_int32))
+        ctx = C.c_void_p()
+        st = C.c_void_p(stream) if stream is not None else None
+        rc = L.iesh_create(arr, len(self._descs), tm, C.byref(r), st, C.byref(ctx))
+        if rc != IESH_OK:
+            raise IeshError(f"iesh_create failed ({rc})")
+        self.ctx = ctx
+        s = Sizes()
+        L.iesh_query_sizes(ctx, C.byref(s))
+        self.n_traj, self.n_max, self.N_max = s.n_traj, s.n_max, s.N_max
+        self.device_bytes = s.device_bytes
+
+    def _check(self, rc, what):
+        if rc != IESH_OK:
+            msg = lib().iesh_last_error(self.ctx)
+            raise IeshError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().iesh_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- state
+    def set_state(self, x, v, Cmat, occ):
+        """x, v: (T,), Cmat: (T, N_max, n_max) complex (orbital-major, blocks
+        packed as documented in iesh.h), occ: (T, N_max) int32."""
+        T = self.n_traj
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(T)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(T)
+        Cc = np.ascontiguousarray(Cmat, dtype=np.complex128)
+        occ = np.ascontiguousarray(occ, dtype=np.int32)
+        self._check(lib().iesh_set_state(self.ctx, _ptr(x), _ptr(v), _ptr(Cc), _ptr(occ),
+                                         IESH_MEM_HOST), "iesh_set_state")
+
+    def get_state(self):
+        T = self.n_traj
+        x = np.zeros(T)
+        v = np.zeros(T)
+        Cc = np.zeros(T * self.n_max * self.N_max, dtype=np.complex128)
+        occ = np.zeros((T, self.N_max), dtype=np.int32)
+        self._check(lib().iesh_get_state(self.ctx, _ptr(x), _ptr(v), _ptr(Cc), _ptr(occ),
+                                         IESH_MEM_HOST), "iesh_get_state")
+        return x, v, Cc, occ
+
+    def init_thermal(self, x, v):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        self._check(lib().iesh_init_thermal(self.ctx, x.ctypes.data_as(C.POINTER(C.c_double)),
+                                            v.ctypes.data_as(C.POINTER(C.c_double))),
+                    "iesh_init_thermal")
+
+    def set_step(self, step: int):
+        self._check(lib().iesh_set_step(self.ctx, int(step)), "iesh_set_step")
+
+    # ------------------------------------------------------------- dynamics
+    def step(self):
+        self._check(lib().iesh_step(self.ctx), "iesh_step")
+
+    def run(self, n_steps: int, record: bool = False):
+        r = self.run_desc.record_every
+        obs = None
+        ptr = None
+        if record and r > 0:
+            obs = np.zeros((n_steps // r, self.n_traj, IESH_N_OBS))
+            ptr = obs.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(lib().iesh_run(self.ctx, int(n_steps), ptr), "iesh_run")
+        return obs
+
+    def sync(self):
+        self._check(lib().iesh_sync(self.ctx), "iesh_sync")
+
+    # --------------------------------------------------------------- queries
+    def hop_probs(self, traj0: int = 0, ntraj: int | None = None):
+        ntraj = self.n_traj - traj0 if ntraj is None else ntraj
+        g = np.zeros(ntraj * self.N_max * self.n_max)
+        self._check(lib().iesh_hop_probs(self.ctx, traj0, ntraj, _ptr(g), IESH_MEM_HOST),
+                    "iesh_hop_probs")
+        return g.reshape(ntraj, self.N_max * self.n_max)
+
+    def adiabatic(self, traj0: int = 0, ntraj: int | None = None):
+        ntraj = self.n_traj - traj0 if ntraj is None else ntraj
+        lam = np.zeros((ntraj, self.n_max))
+        q0 = np.zeros((ntraj, self.n_max))
+        self._check(lib().iesh_adiabatic(self.ctx, traj0, ntraj,
+                                         lam.ctypes.data_as(C.POINTER(C.c_double)),
+                                         q0.ctypes.data_as(C.POINTER(C.c_double))),
+                    "iesh_adiabatic")
+        return lam, q0
+
+    def status(self):
+        s = np.zeros(self.n_traj, dtype=np.int32)
+        self._check(lib().iesh_traj_status(self.ctx, s.ctypes.data_as(C.POINTER(C.c_int32))),
+                    "iesh_traj_status")
+        return s
+
+    def events(self, cap: int = 1 << 16):
+        buf = (Event * cap)()
+        n = C.c_int64()
+        self._check(lib().iesh_events(self.ctx, buf, cap, C.byref(n)), "iesh_events")
+        m = min(n.value, cap)
+        return [dict(step=buf[i].step, traj=buf[i].traj, a=buf[i].a, b=buf[i].b,
+                     accepted=bool(buf[i].accepted), margin=buf[i].margin,
+                     g_total=buf[i].g_total) for i in range(m)], n.value
+
+    def clear_events(self):
+        self._check(lib().iesh_clear_events(self.ctx), "iesh_clear_events")

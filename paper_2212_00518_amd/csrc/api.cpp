@@ -1,0 +1,671 @@
+// C ABI of libiesh: context, device memory, state transfer, step loop.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "iesh_internal.hpp"
+
+using namespace iesh;
+
+struct iesh_ctx {
+  std::vector<ClassDev> cls;
+  std::vector<int32_t> traj_class;  // global trajectory -> class
+  std::vector<int32_t> traj_local;  // global trajectory -> index inside its class
+  iesh_run_desc run{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;  // created here when the caller passes none
+  int device = 0;
+  Counters* cnt = nullptr;
+  iesh_event* events = nullptr;
+  int n_max = 0, N_max = 0;
+  int64_t step = 0;
+  size_t device_bytes = 0;
+  std::string err;
+  std::vector<void*> allocations;
+  // graph cache for iesh_run
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_record = -1;
+  int64_t obs_records = 0;  // capacity of the class observable buffers
+};
+
+namespace {
+
+int fail(iesh_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+#define HIPTRY(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, IESH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+template <typename T>
+int dalloc(iesh_ctx* ctx, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return IESH_OK;
+  void* q = nullptr;
+  const size_t bytes = count * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) return fail(ctx, IESH_ENOMEM, "hipMalloc failed: " + std::to_string(bytes) + " bytes");
+  ctx->allocations.push_back(q);
+  if (hipMemsetAsync(q, 0, bytes, ctx->stream) != hipSuccess)
+    return fail(ctx, IESH_EDEVICE, "hipMemsetAsync failed");
+  ctx->device_bytes += bytes;
+  *p = reinterpret_cast<T*>(q);
+  return IESH_OK;
+}
+
+void free_graph(iesh_ctx* ctx) {
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->graph_exec = nullptr;
+  ctx->graph = nullptr;
+  ctx->graph_record = -1;
+}
+
+int round16(int v) { return (v + 15) / 16 * 16; }
+
+// Propagation work split: column tiles of 8 orbitals, up to
+// prop_max_col_tiles per work-group, limited by the LDS footprint.
+void choose_slabs(ClassDev& c, int precision) {
+  const size_t lds_budget = 160 * 1024;
+  const int tiles = (c.md.N + 7) / 8;
+  int nct = std::min(prop_max_col_tiles(precision), tiles);
+  for (; nct > 1; --nct) {
+    c.nct_max = nct;
+    if (prop_lds_bytes(c, precision) <= lds_budget) break;
+  }
+  c.n_slabs = (tiles + nct - 1) / nct;
+  c.nct_max = (tiles + c.n_slabs - 1) / c.n_slabs;
+}
+
+int validate_model(const iesh_model_desc& m, std::string& why) {
+  if (m.kind != IESH_MODEL_HARMONIC && m.kind != IESH_MODEL_MORSE_TANH) {
+    why = "unknown model kind";
+    return 0;
+  }
+  if (m.n_bath < 1 || m.n_bath + 1 > IESH_MAX_STATES) {
+    why = "n_bath out of range [1, IESH_MAX_STATES-1]";
+    return 0;
+  }
+  if (m.n_elec < 1 || m.n_elec > m.n_bath || m.n_elec > IESH_MAX_ELEC) {
+    why = "n_elec out of range";
+    return 0;
+  }
+  if (!m.eps || !m.w) {
+    why = "eps and w must be given";
+    return 0;
+  }
+  for (int k = 0; k < m.n_bath; ++k) {
+    if (!(m.w[k] > 0.0) || !std::isfinite(m.eps[k])) {
+      why = "bath weights must be > 0 and energies finite";
+      return 0;
+    }
+    if (k && !(m.eps[k] > m.eps[k - 1])) {
+      why = "bath energies must be strictly ascending";
+      return 0;
+    }
+  }
+  if (!(m.mass > 0.0) || !(m.Gamma > 0.0)) {
+    why = "mass and Gamma must be > 0";
+    return 0;
+  }
+  return 1;
+}
+
+int upload_state(iesh_ctx* ctx, const double* x, const double* v, const double* C,
+                 const int32_t* occ) {
+  const int T = ctx->run.n_traj;
+  for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+    ClassDev& c = ctx->cls[ci];
+    const int Tc = c.n_traj, N = c.md.N, n = c.md.n, n_pad = c.md.n_pad;
+    std::vector<double> hx(Tc), hv(Tc);
+    std::vector<int32_t> hocc((size_t)Tc * N);
+    std::vector<double> hC;
+    std::vector<float> hC32;
+    const bool f64 = ctx->run.precision == IESH_FP64;
+    if (C) {
+      if (f64)
+        hC.assign((size_t)Tc * N * n_pad * 2, 0.0);
+      else
+        hC32.assign((size_t)Tc * N * n_pad * 2, 0.0f);
+    }
+    int tl = 0;
+    for (int t = 0; t < T; ++t) {
+      if (ctx->traj_class[t] != (int)ci) continue;
+      hx[tl] = x[t];
+      hv[tl] = v[t];
+      if (occ) {
+        for (int r = 0; r < N; ++r) {
+          const int a = occ[(size_t)t * ctx->N_max + r];
+          if (a < 0 || a >= n || (r && a <= occ[(size_t)t * ctx->N_max + r - 1]))
+            return fail(ctx, IESH_EINVAL, "occupations must be sorted, distinct, in [0, n)");
+          hocc[(size_t)tl * N + r] = a;
+        }
+      }
+      if (C) {
+        const double* src = C + (size_t)t * ctx->n_max * ctx->N_max * 2;
+        for (int j = 0; j < N; ++j)
+          for (int i = 0; i < n; ++i) {
+            const size_t d = (((size_t)tl * N + j) * n_pad + i) * 2;
+            const size_t s = ((size_t)j * n + i) * 2;
+            if (f64) {
+              hC[d] = src[s];
+              hC[d + 1] = src[s + 1];
+            } else {
+              hC32[d] = (float)src[s];
+              hC32[d + 1] = (float)src[s + 1];
+            }
+          }
+      }
+      ++tl;
+    }
+    HIPTRY(ctx, hipMemcpyAsync(c.x, hx.data(), Tc * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPTRY(ctx, hipMemcpyAsync(c.v, hv.data(), Tc * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    if (occ)
+      HIPTRY(ctx, hipMemcpyAsync(c.occ, hocc.data(), hocc.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, ctx->stream));
+    if (C) {
+      if (f64)
+        HIPTRY(ctx, hipMemcpyAsync(c.C64, hC.data(), hC.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, ctx->stream));
+      else
+        HIPTRY(ctx, hipMemcpyAsync(c.C32, hC32.data(), hC32.size() * sizeof(float),
+                                   hipMemcpyHostToDevice, ctx->stream));
+    }
+    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  return IESH_OK;
+}
+
+int reset_traj_words(iesh_ctx* ctx) {
+  for (auto& c : ctx->cls) {
+    HIPTRY(ctx, hipMemsetAsync(c.status, 0, c.n_traj * sizeof(int32_t), ctx->stream));
+    HIPTRY(ctx, hipMemsetAsync(c.nsteps, 0, c.n_traj * sizeof(int64_t), ctx->stream));
+  }
+  HIPTRY(ctx, hipMemsetAsync(&ctx->cnt->n_events, 0, sizeof(int64_t), ctx->stream));
+  return IESH_OK;
+}
+
+int set_counters(iesh_ctx* ctx, int64_t run_step0, int64_t record_every) {
+  Counters h{};
+  h.step = ctx->step;
+  h.run_step0 = run_step0;
+  h.record_every = record_every;
+  // keep n_events: copy it back first
+  int64_t nev = 0;
+  HIPTRY(ctx, hipMemcpyAsync(&nev, &ctx->cnt->n_events, sizeof(int64_t), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  h.n_events = nev;
+  HIPTRY(ctx, hipMemcpyAsync(ctx->cnt, &h, sizeof(Counters), hipMemcpyHostToDevice, ctx->stream));
+  return IESH_OK;
+}
+
+// Kernel sequence of one step for every class.
+int enqueue_step(iesh_ctx* ctx, int record) {
+  const iesh_run_desc& r = ctx->run;
+  for (auto& c : ctx->cls) {
+    if (c.n_traj == 0) continue;
+    HIPTRY(ctx, launch_eig_step(c, r.dt, ctx->stream));
+    HIPTRY(ctx, launch_prop(c, r.precision, ctx->stream));
+    HIPTRY(ctx, launch_hop(c, r.dt, r.seed, ctx->cnt, ctx->events, 0, 0, c.n_traj, record,
+                           r.exit_enabled, r.exit_x, r.max_steps, r.precision, ctx->stream));
+    if (r.precision == IESH_MIXED && r.lowdin_every > 0)
+      HIPTRY(ctx, launch_lowdin(c, ctx->cnt, r.lowdin_every, c.low, ctx->stream));
+  }
+  HIPTRY(ctx, launch_advance(ctx->cnt, ctx->stream));
+  return IESH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int iesh_version(int* major, int* minor, int* patch) {
+  if (major) *major = 0;
+  if (minor) *minor = 1;
+  if (patch) *patch = 0;
+  return IESH_OK;
+}
+
+const char* iesh_last_error(const iesh_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int iesh_discretize(int32_t kind, int32_t M, double a, double b, double eps_f, double* eps,
+                    double* w) {
+  return discretize(kind, M, a, b, eps_f, eps, w);
+}
+
+int iesh_destroy(iesh_ctx* ctx) {
+  if (!ctx) return IESH_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  free_graph(ctx);
+  for (void* p : ctx->allocations) (void)hipFree(p);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return IESH_OK;
+}
+
+int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* traj_model,
+                const iesh_run_desc* run, void* hip_stream, iesh_ctx** out) {
+  if (!out) return IESH_EINVAL;
+  *out = nullptr;
+  if (!models || n_models < 1 || !run) return IESH_EINVAL;
+  iesh_ctx* ctx = new (std::nothrow) iesh_ctx();
+  if (!ctx) return IESH_ENOMEM;
+  auto bail = [&](int code) {
+    // keep the message for the caller through a static buffer
+    static thread_local std::string last;
+    last = ctx->err;
+    iesh_destroy(ctx);
+    std::fprintf(stderr, "iesh_create: %s\n", last.c_str());
+    return code;
+  };
+  ctx->run = *run;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (!ctx->stream) {
+    // the step loop is captured into a graph, which needs a non-null stream
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
+      return (fail(ctx, IESH_EDEVICE, "stream creation failed"), bail(IESH_EDEVICE));
+    ctx->own_stream = true;
+  }
+  (void)hipGetDevice(&ctx->device);
+  const iesh_run_desc& r = ctx->run;
+  if (r.n_traj < 1) return (fail(ctx, IESH_EINVAL, "n_traj must be >= 1"), bail(IESH_EINVAL));
+  if (!(r.dt > 0.0)) return (fail(ctx, IESH_EINVAL, "dt must be > 0"), bail(IESH_EINVAL));
+  if (!(r.kT >= 0.0)) return (fail(ctx, IESH_EINVAL, "kT must be >= 0"), bail(IESH_EINVAL));
+  if (r.precision != IESH_FP64 && r.precision != IESH_MIXED)
+    return (fail(ctx, IESH_EINVAL, "unknown precision"), bail(IESH_EINVAL));
+  if (r.lowdin_every < 0 || r.record_every < 0)
+    return (fail(ctx, IESH_EINVAL, "negative cadence"), bail(IESH_EINVAL));
+  for (int m = 0; m < n_models; ++m) {
+    std::string why;
+    if (!validate_model(models[m], why))
+      return (fail(ctx, IESH_EINVAL, "model " + std::to_string(m) + ": " + why), bail(IESH_EINVAL));
+  }
+  ctx->traj_class.assign(r.n_traj, 0);
+  ctx->traj_local.assign(r.n_traj, 0);
+  std::vector<int> count(n_models, 0);
+  for (int t = 0; t < r.n_traj; ++t) {
+    const int m = traj_model ? traj_model[t] : 0;
+    if (m < 0 || m >= n_models)
+      return (fail(ctx, IESH_EINVAL, "traj_model out of range"), bail(IESH_EINVAL));
+    ctx->traj_class[t] = m;
+    ctx->traj_local[t] = count[m]++;
+  }
+  int rc = dalloc(ctx, &ctx->cnt, 1);
+  if (rc) return bail(rc);
+  rc = dalloc(ctx, &ctx->events, (size_t)IESH_EVENT_CAP);
+  if (rc) return bail(rc);
+  ctx->cls.resize(n_models);
+  for (int m = 0; m < n_models; ++m) {
+    const iesh_model_desc& d = models[m];
+    ClassDev& c = ctx->cls[m];
+    c.md.kind = d.kind;
+    c.md.M = d.n_bath;
+    c.md.n = d.n_bath + 1;
+    c.md.n_pad = round16(c.md.n);
+    c.md.N = d.n_elec;
+    c.md.mass = d.mass;
+    c.md.Gamma = d.Gamma;
+    for (int q = 0; q < 16; ++q) c.md.p[q] = d.params[q];
+    c.n_traj = count[m];
+    ctx->n_max = std::max(ctx->n_max, c.md.n);
+    ctx->N_max = std::max(ctx->N_max, c.md.N);
+    choose_slabs(c, r.precision);
+    const int T = c.n_traj, n_pad = c.md.n_pad, N = c.md.N, M = c.md.M;
+    if (T == 0) continue;
+    if ((rc = dalloc(ctx, &c.eps, M)) || (rc = dalloc(ctx, &c.vbar, M)) ||
+        (rc = dalloc(ctx, &c.x, T)) || (rc = dalloc(ctx, &c.v, T)) || (rc = dalloc(ctx, &c.F, T)) ||
+        (rc = dalloc(ctx, &c.occ, (size_t)T * N)) || (rc = dalloc(ctx, &c.status, T)) ||
+        (rc = dalloc(ctx, &c.gtraj, T)) || (rc = dalloc(ctx, &c.nsteps, T)) ||
+        (rc = dalloc(ctx, &c.lam, (size_t)T * n_pad)) || (rc = dalloc(ctx, &c.q0, (size_t)T * n_pad)) ||
+        (rc = dalloc(ctx, &c.lam_mid, (size_t)T * n_pad)) ||
+        (rc = dalloc(ctx, &c.geo, (size_t)T * kGeoStride)) ||
+        (rc = dalloc(ctx, &c.cheb, (size_t)T * kChebStride)) ||
+        (rc = dalloc(ctx, &c.gbuf, (size_t)T * N * n_pad)))
+      return bail(rc);
+    if (r.precision == IESH_FP64) {
+      if ((rc = dalloc(ctx, &c.C64, (size_t)T * N * n_pad * 2)) ||
+          (rc = dalloc(ctx, &c.Bt, (size_t)T * n_pad * n_pad)))
+        return bail(rc);
+    } else {
+      if ((rc = dalloc(ctx, &c.C32, (size_t)T * N * n_pad * 2)) ||
+          (rc = dalloc(ctx, &c.Bt32, (size_t)T * n_pad * n_pad)) ||
+          (rc = dalloc(ctx, &c.low, lowdin_scratch_elems(c))))
+        return bail(rc);
+    }
+    if (hipError_t e = prop_prepare(c, r.precision); e != hipSuccess)
+      return (fail(ctx, IESH_EDEVICE, std::string("propagation LDS attribute: ") +
+                                         hipGetErrorString(e)),
+              bail(IESH_EDEVICE));
+    std::vector<double> vb(M);
+    for (int k = 0; k < M; ++k) vb[k] = std::sqrt(d.Gamma * d.w[k] / (2.0 * M_PI));
+    std::vector<int32_t> gt;
+    for (int t = 0; t < r.n_traj; ++t)
+      if (ctx->traj_class[t] == m) gt.push_back(t);
+    if (hipMemcpyAsync(c.eps, d.eps, M * sizeof(double), hipMemcpyHostToDevice, ctx->stream) ||
+        hipMemcpyAsync(c.vbar, vb.data(), M * sizeof(double), hipMemcpyHostToDevice, ctx->stream) ||
+        hipMemcpyAsync(c.gtraj, gt.data(), T * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream) ||
+        hipStreamSynchronize(ctx->stream))
+      return (fail(ctx, IESH_EDEVICE, "upload of model data failed"), bail(IESH_EDEVICE));
+  }
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return (fail(ctx, IESH_EDEVICE, "device synchronisation failed"), bail(IESH_EDEVICE));
+  if (set_counters(ctx, 0, 0)) return bail(IESH_EDEVICE);
+  *out = ctx;
+  return IESH_OK;
+}
+
+int iesh_query_sizes(const iesh_ctx* ctx, iesh_sizes* out) {
+  if (!ctx || !out) return IESH_EINVAL;
+  out->n_traj = ctx->run.n_traj;
+  out->n_models = (int32_t)ctx->cls.size();
+  out->n_max = ctx->n_max;
+  out->N_max = ctx->N_max;
+  out->device_bytes = (int64_t)ctx->device_bytes;
+  return IESH_OK;
+}
+
+int iesh_set_step(iesh_ctx* ctx, int64_t step) {
+  if (!ctx || step < 0) return IESH_EINVAL;
+  ctx->step = step;
+  return set_counters(ctx, step, 0);
+}
+
+int iesh_get_step(const iesh_ctx* ctx, int64_t* step) {
+  if (!ctx || !step) return IESH_EINVAL;
+  *step = ctx->step;
+  return IESH_OK;
+}
+
+static std::vector<double> host_copy_d(iesh_ctx* ctx, const double* p, size_t count, int mem_kind) {
+  std::vector<double> h(count);
+  if (mem_kind == IESH_MEM_DEVICE) {
+    (void)hipMemcpy(h.data(), p, count * sizeof(double), hipMemcpyDeviceToHost);
+  } else {
+    std::memcpy(h.data(), p, count * sizeof(double));
+  }
+  (void)ctx;
+  return h;
+}
+
+int iesh_set_state(iesh_ctx* ctx, const double* x, const double* v, const double* C,
+                   const int32_t* occ, int32_t mem_kind) {
+  if (!ctx || !x || !v || !C || !occ) return fail(ctx, IESH_EINVAL, "null state pointer");
+  if (mem_kind != IESH_MEM_HOST && mem_kind != IESH_MEM_DEVICE)
+    return fail(ctx, IESH_EINVAL, "mem_kind");
+  const int T = ctx->run.n_traj;
+  std::vector<double> hx, hv, hC;
+  std::vector<int32_t> hocc;
+  const size_t csize = (size_t)T * ctx->n_max * ctx->N_max * 2;
+  if (mem_kind == IESH_MEM_DEVICE) {
+    hx = host_copy_d(ctx, x, T, mem_kind);
+    hv = host_copy_d(ctx, v, T, mem_kind);
+    hC = host_copy_d(ctx, C, csize, mem_kind);
+    hocc.resize((size_t)T * ctx->N_max);
+    HIPTRY(ctx, hipMemcpy(hocc.data(), occ, hocc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    x = hx.data();
+    v = hv.data();
+    C = hC.data();
+    occ = hocc.data();
+  }
+  int rc = upload_state(ctx, x, v, C, occ);
+  if (rc) return rc;
+  if ((rc = reset_traj_words(ctx))) return rc;
+  for (auto& c : ctx->cls)
+    if (c.n_traj) HIPTRY(ctx, launch_forces(c, ctx->stream));
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  return IESH_OK;
+}
+
+int iesh_init_thermal(iesh_ctx* ctx, const double* x, const double* v) {
+  if (!ctx || !x || !v) return fail(ctx, IESH_EINVAL, "null pointer");
+  int rc = upload_state(ctx, x, v, nullptr, nullptr);
+  if (rc) return rc;
+  if ((rc = reset_traj_words(ctx))) return rc;
+  for (auto& c : ctx->cls)
+    if (c.n_traj) HIPTRY(ctx, launch_init_thermal(c, ctx->run.kT, ctx->run.seed, ctx->stream));
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  return IESH_OK;
+}
+
+int iesh_get_state(iesh_ctx* ctx, double* x, double* v, double* C, int32_t* occ,
+                   int32_t mem_kind) {
+  if (!ctx) return IESH_EINVAL;
+  if (mem_kind != IESH_MEM_HOST && mem_kind != IESH_MEM_DEVICE)
+    return fail(ctx, IESH_EINVAL, "mem_kind");
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  const int T = ctx->run.n_traj;
+  const size_t csize = (size_t)T * ctx->n_max * ctx->N_max * 2;
+  std::vector<double> hx(T), hv(T), hC(C ? csize : 0, 0.0);
+  std::vector<int32_t> hocc(occ ? (size_t)T * ctx->N_max : 0, -1);
+  for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+    ClassDev& c = ctx->cls[ci];
+    const int Tc = c.n_traj, N = c.md.N, n = c.md.n, n_pad = c.md.n_pad;
+    if (!Tc) continue;
+    std::vector<double> cx(Tc), cv(Tc);
+    std::vector<int32_t> cocc((size_t)Tc * N);
+    HIPTRY(ctx, hipMemcpy(cx.data(), c.x, Tc * sizeof(double), hipMemcpyDeviceToHost));
+    HIPTRY(ctx, hipMemcpy(cv.data(), c.v, Tc * sizeof(double), hipMemcpyDeviceToHost));
+    HIPTRY(ctx, hipMemcpy(cocc.data(), c.occ, cocc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<double> cC;
+    if (C) {
+      cC.resize((size_t)Tc * N * n_pad * 2);
+      if (ctx->run.precision == IESH_FP64) {
+        HIPTRY(ctx, hipMemcpy(cC.data(), c.C64, cC.size() * sizeof(double), hipMemcpyDeviceToHost));
+      } else {
+        std::vector<float> f(cC.size());
+        HIPTRY(ctx, hipMemcpy(f.data(), c.C32, f.size() * sizeof(float), hipMemcpyDeviceToHost));
+        for (size_t q = 0; q < f.size(); ++q) cC[q] = f[q];
+      }
+    }
+    int tl = 0;
+    for (int t = 0; t < T; ++t) {
+      if (ctx->traj_class[t] != (int)ci) continue;
+      hx[t] = cx[tl];
+      hv[t] = cv[tl];
+      if (occ)
+        for (int r = 0; r < N; ++r) hocc[(size_t)t * ctx->N_max + r] = cocc[(size_t)tl * N + r];
+      if (C) {
+        double* dst = hC.data() + (size_t)t * ctx->n_max * ctx->N_max * 2;
+        for (int j = 0; j < N; ++j)
+          for (int i = 0; i < n; ++i) {
+            const size_t s = (((size_t)tl * N + j) * n_pad + i) * 2;
+            dst[((size_t)j * n + i) * 2] = cC[s];
+            dst[((size_t)j * n + i) * 2 + 1] = cC[s + 1];
+          }
+      }
+      ++tl;
+    }
+  }
+  auto put = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (!dst) return IESH_OK;
+    if (mem_kind == IESH_MEM_DEVICE) {
+      HIPTRY(ctx, hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    } else {
+      std::memcpy(dst, src, bytes);
+    }
+    return IESH_OK;
+  };
+  int rc;
+  if ((rc = put(x, hx.data(), T * sizeof(double)))) return rc;
+  if ((rc = put(v, hv.data(), T * sizeof(double)))) return rc;
+  if ((rc = put(C, hC.data(), hC.size() * sizeof(double)))) return rc;
+  if ((rc = put(occ, hocc.data(), hocc.size() * sizeof(int32_t)))) return rc;
+  return IESH_OK;
+}
+
+int iesh_step(iesh_ctx* ctx) {
+  if (!ctx) return IESH_EINVAL;
+  int rc = enqueue_step(ctx, 0);
+  if (rc) return rc;
+  ctx->step += 1;
+  return IESH_OK;
+}
+
+int iesh_sync(iesh_ctx* ctx) {
+  if (!ctx) return IESH_EINVAL;
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  return IESH_OK;
+}
+
+int iesh_run(iesh_ctx* ctx, int64_t n_steps, double* obs_out) {
+  if (!ctx || n_steps < 0) return IESH_EINVAL;
+  const iesh_run_desc& r = ctx->run;
+  const int record = (obs_out && r.record_every > 0) ? 1 : 0;
+  const int64_t n_rec = record ? n_steps / r.record_every : 0;
+  if (record && n_rec > ctx->obs_records) {
+    free_graph(ctx);  // observable pointers are captured in the graph
+    for (auto& c : ctx->cls) {
+      if (!c.n_traj) continue;
+      int rc = dalloc(ctx, &c.obs, (size_t)n_rec * c.n_traj * IESH_N_OBS);
+      if (rc) return rc;
+    }
+    ctx->obs_records = n_rec;
+  }
+  int rc = set_counters(ctx, ctx->step, record ? r.record_every : 0);
+  if (rc) return rc;
+  if (n_steps == 0) return IESH_OK;
+  if (ctx->graph_record != record) {
+    free_graph(ctx);
+    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIPTRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_step(ctx, record);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(ctx, IESH_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    ctx->graph = g;
+    HIPTRY(ctx, hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+    ctx->graph_record = record;
+  }
+  for (int64_t k = 0; k < n_steps; ++k) HIPTRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+  ctx->step += n_steps;
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (record) {
+    const int T = r.n_traj;
+    for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+      ClassDev& c = ctx->cls[ci];
+      if (!c.n_traj) continue;
+      std::vector<double> h((size_t)n_rec * c.n_traj * IESH_N_OBS);
+      HIPTRY(ctx, hipMemcpy(h.data(), c.obs, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+      int tl = 0;
+      for (int t = 0; t < T; ++t) {
+        if (ctx->traj_class[t] != (int)ci) continue;
+        for (int64_t q = 0; q < n_rec; ++q)
+          for (int o = 0; o < IESH_N_OBS; ++o)
+            obs_out[((size_t)q * T + t) * IESH_N_OBS + o] =
+                h[((size_t)q * c.n_traj + tl) * IESH_N_OBS + o];
+        ++tl;
+      }
+    }
+  }
+  return IESH_OK;
+}
+
+int iesh_hop_probs(iesh_ctx* ctx, int32_t traj0, int32_t ntraj, double* g_out, int32_t mem_kind) {
+  if (!ctx || !g_out || traj0 < 0 || ntraj < 1 || traj0 + ntraj > ctx->run.n_traj)
+    return fail(ctx, IESH_EINVAL, "trajectory range");
+  const int stride = ctx->n_max * ctx->N_max;
+  std::vector<double> host((size_t)ntraj * stride, 0.0);
+  for (int q = 0; q < ntraj; ++q) {
+    const int t = traj0 + q;
+    ClassDev& c = ctx->cls[ctx->traj_class[t]];
+    const int tl = ctx->traj_local[t];
+    HIPTRY(ctx, launch_eig_query(c, tl, 1, ctx->stream));
+    HIPTRY(ctx, launch_hop(c, ctx->run.dt, ctx->run.seed, ctx->cnt, ctx->events, 1, tl, 1, 0, 0,
+                           0.0, 0, ctx->run.precision, ctx->stream));
+    const int N = c.md.N, n = c.md.n, n_pad = c.md.n_pad;
+    std::vector<double> g((size_t)N * n_pad);
+    HIPTRY(ctx, hipMemcpyAsync(g.data(), c.gbuf + (size_t)tl * N * n_pad, g.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int rr = 0; rr < N; ++rr)
+      for (int b = 0; b < n; ++b) host[(size_t)q * stride + (size_t)rr * n + b] = g[(size_t)rr * n_pad + b];
+  }
+  if (mem_kind == IESH_MEM_DEVICE) {
+    HIPTRY(ctx, hipMemcpy(g_out, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    std::memcpy(g_out, host.data(), host.size() * sizeof(double));
+  }
+  return IESH_OK;
+}
+
+int iesh_adiabatic(iesh_ctx* ctx, int32_t traj0, int32_t ntraj, double* lam_out, double* q0_out) {
+  if (!ctx || traj0 < 0 || ntraj < 1 || traj0 + ntraj > ctx->run.n_traj)
+    return fail(ctx, IESH_EINVAL, "trajectory range");
+  for (int q = 0; q < ntraj; ++q) {
+    const int t = traj0 + q;
+    ClassDev& c = ctx->cls[ctx->traj_class[t]];
+    const int tl = ctx->traj_local[t];
+    HIPTRY(ctx, launch_eig_query(c, tl, 1, ctx->stream));
+    const int n = c.md.n, n_pad = c.md.n_pad;
+    std::vector<double> l(n_pad), qq(n_pad);
+    HIPTRY(ctx, hipMemcpyAsync(l.data(), c.lam + (size_t)tl * n_pad, n_pad * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPTRY(ctx, hipMemcpyAsync(qq.data(), c.q0 + (size_t)tl * n_pad, n_pad * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int j = 0; j < n; ++j) {
+      if (lam_out) lam_out[(size_t)q * ctx->n_max + j] = l[j];
+      if (q0_out) q0_out[(size_t)q * ctx->n_max + j] = qq[j];
+    }
+  }
+  return IESH_OK;
+}
+
+int iesh_traj_status(iesh_ctx* ctx, int32_t* status_out) {
+  if (!ctx || !status_out) return IESH_EINVAL;
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+    ClassDev& c = ctx->cls[ci];
+    if (!c.n_traj) continue;
+    std::vector<int32_t> s(c.n_traj);
+    HIPTRY(ctx, hipMemcpy(s.data(), c.status, s.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    int tl = 0;
+    for (int t = 0; t < ctx->run.n_traj; ++t)
+      if (ctx->traj_class[t] == (int)ci) status_out[t] = s[tl++];
+  }
+  return IESH_OK;
+}
+
+int iesh_events(iesh_ctx* ctx, iesh_event* out, int64_t cap, int64_t* count) {
+  if (!ctx || !count || cap < 0) return IESH_EINVAL;
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  int64_t n = 0;
+  HIPTRY(ctx, hipMemcpy(&n, &ctx->cnt->n_events, sizeof(int64_t), hipMemcpyDeviceToHost));
+  *count = n;
+  const int64_t have = std::min<int64_t>(n, IESH_EVENT_CAP);
+  if (out && cap > 0 && have > 0) {
+    std::vector<iesh_event> ev(have);
+    HIPTRY(ctx, hipMemcpy(ev.data(), ctx->events, have * sizeof(iesh_event), hipMemcpyDeviceToHost));
+    std::sort(ev.begin(), ev.end(), [](const iesh_event& a, const iesh_event& b) {
+      return a.step != b.step ? a.step < b.step : a.traj < b.traj;
+    });
+    const int64_t m = std::min(have, cap);
+    std::memcpy(out, ev.data(), m * sizeof(iesh_event));
+  }
+  return IESH_OK;
+}
+
+int iesh_clear_events(iesh_ctx* ctx) {
+  if (!ctx) return IESH_EINVAL;
+  HIPTRY(ctx, hipMemsetAsync(&ctx->cnt->n_events, 0, sizeof(int64_t), ctx->stream));
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  return IESH_OK;
+}
+
+}  // extern "C"

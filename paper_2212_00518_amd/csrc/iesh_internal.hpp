@@ -1,0 +1,188 @@
+// Internal declarations shared by the HIP translation units of libiesh.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/iesh.h"
+
+namespace iesh {
+
+constexpr int kMaxStates = IESH_MAX_STATES;  // n = M + 1
+constexpr int kMaxElec = IESH_MAX_ELEC;      // N
+constexpr int kMaxCheb = 64;                 // Chebyshev terms per step
+constexpr int kChebStride = 2 * kMaxCheb + 8;
+constexpr int kGeoStride = 8;
+
+// Status bits that stop a trajectory.
+constexpr int kFreezeMask = IESH_TRAJ_EXITED | IESH_TRAJ_NONCONV | IESH_TRAJ_NONFINITE |
+                            IESH_TRAJ_STEPCAP;
+
+// Per-trajectory scalars at the most recent geometry (layout of geo[]).
+enum GeoSlot { GEO_H = 0, GEO_DH = 1, GEO_RHO = 2, GEO_U0 = 3, GEO_DU0 = 4 };
+
+// Chebyshev parameter block (layout of cheb[]): [0] centre c, [1] 1/radius,
+// [2] number of terms K (as double), [3] radius*dt, then K complex
+// coefficients (re, im) starting at [8].
+enum ChebSlot { CHEB_C = 0, CHEB_INVR = 1, CHEB_K = 2, CHEB_RHO = 3, CHEB_COEF = 8 };
+
+// Model constants passed by value to kernels.
+struct ModelDev {
+  int kind;
+  int M;       // bath levels
+  int n;       // M + 1
+  int n_pad;   // n rounded up to 16
+  int N;       // electrons
+  int pad0;
+  double mass;
+  double Gamma;
+  double p[16];
+};
+
+// Device state of one bath-size class.
+struct ClassDev {
+  ModelDev md;
+  int n_traj;           // trajectories in this class
+  int traj_offset;      // first global trajectory index of this class
+  int nct_max;          // column tiles per propagation work-group
+  int n_slabs;          // propagation work-groups per trajectory
+  // device arrays (class-local trajectory index t)
+  double* eps = nullptr;    // [M]
+  double* vbar = nullptr;   // [M]  sqrt(Gamma w / 2 pi)
+  double* x = nullptr;      // [T]
+  double* v = nullptr;      // [T]
+  double* F = nullptr;      // [T]
+  int32_t* occ = nullptr;   // [T][N]
+  int32_t* status = nullptr;  // [T]
+  int32_t* gtraj = nullptr;   // [T] global trajectory index
+  int64_t* nsteps = nullptr;  // [T] steps taken
+  double* C64 = nullptr;    // [T][N][n_pad] complex (re, im)
+  float* C32 = nullptr;     // [T][N][n_pad] complex (re, im), mixed path
+  double* lam = nullptr;    // [T][n_pad] energies at the current geometry
+  double* q0 = nullptr;     // [T][n_pad] impurity amplitudes
+  double* lam_mid = nullptr;  // [T][n_pad]
+  double* geo = nullptr;    // [T][kGeoStride]
+  double* cheb = nullptr;   // [T][kChebStride]
+  double* Bt = nullptr;     // [T][n_pad/4][n_pad/16][64] v*D at the midpoint, MFMA A-tile order
+  float* Bt32 = nullptr;    // same in FP32 (mixed path)
+  double* gbuf = nullptr;   // [T][N][n_pad] hop probabilities (query mode)
+  double* obs = nullptr;    // [records][T][IESH_N_OBS] (class-local records)
+  double2* low = nullptr;   // Loewdin scratch (mixed path)
+};
+
+struct Counters {
+  int64_t step;       // global step counter (hop uniform counter)
+  int64_t run_step0;  // first step of the current iesh_run call
+  int64_t n_events;   // events recorded
+  int64_t record_every;
+};
+
+// -------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), host and device.
+struct Philox4 {
+  uint32_t v[4];
+};
+
+__host__ __device__ inline uint32_t mulhi32(uint32_t a, uint32_t b) {
+  return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
+}
+
+__host__ __device__ inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                  uint32_t c3, uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint32_t lo0 = M0 * c0, hi0 = mulhi32(M0, c0);
+    uint32_t lo1 = M1 * c2, hi1 = mulhi32(M1, c2);
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  Philox4 o;
+  o.v[0] = c0;
+  o.v[1] = c1;
+  o.v[2] = c2;
+  o.v[3] = c3;
+  return o;
+}
+
+// Uniform in [0, 1) for (seed, trajectory, counter, stream).
+__host__ __device__ inline double philox_uniform(uint64_t seed, uint32_t traj, uint64_t counter,
+                                                 uint32_t stream) {
+  Philox4 w = philox4x32_10((uint32_t)counter, (uint32_t)(counter >> 32), traj, stream,
+                            (uint32_t)seed, (uint32_t)(seed >> 32));
+  uint64_t u = ((uint64_t)w.v[1] << 32) | (uint64_t)w.v[0];
+  return (double)(u >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// -------------------------------------------------------------------------
+// Model scalars at x.  Couplings factor as V_k(x) = Vbar_k f(x); rho = f'/f.
+struct ModelAt {
+  double U0, dU0, h, dh, f, rho;
+};
+
+__host__ __device__ inline ModelAt model_at(const ModelDev& md, double x) {
+  ModelAt r;
+  if (md.kind == IESH_MODEL_HARMONIC) {
+    const double omega = md.p[0], g = md.p[1], dG = md.p[2], eps_d = md.p[3];
+    const double k = md.mass * omega * omega;
+    r.U0 = 0.5 * k * x * x;
+    r.dU0 = k * x;
+    const double U1 = 0.5 * k * (x - g) * (x - g) + dG;
+    r.h = U1 - r.U0 + eps_d;
+    r.dh = -k * g;
+    r.f = 1.0;
+    r.rho = 0.0;
+  } else {
+    const double De = md.p[0], x0 = md.p[1], a = md.p[2], D1 = md.p[3], D2 = md.p[4];
+    const double ap = md.p[5], Vinf = md.p[6], q = md.p[7], at = md.p[8], xt = md.p[9];
+    const double c = md.p[10], eps_d = md.p[11];
+    const double e = exp(-a * (x - x0));
+    r.U0 = De * (e - 1.0) * (e - 1.0) + c;
+    r.dU0 = -2.0 * De * a * e * (e - 1.0);
+    const double e1 = exp(-ap * (x - x0));
+    const double U1 = D1 * e1 * e1 - D2 * e1 + Vinf;
+    const double dU1 = -2.0 * ap * D1 * e1 * e1 + ap * D2 * e1;
+    r.h = U1 - r.U0 + eps_d;
+    r.dh = dU1 - r.dU0;
+    const double t = tanh((x - xt) / at);
+    r.f = 0.5 * (1.0 - q) * (1.0 - t) + q;
+    const double df = -0.5 * (1.0 - q) * (1.0 - t * t) / at;
+    r.rho = df / r.f;
+  }
+  return r;
+}
+
+// -------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files).
+hipError_t launch_eig_step(const ClassDev& c, double dt, hipStream_t s);
+hipError_t launch_eig_query(const ClassDev& c, int t0, int nt, hipStream_t s);
+hipError_t launch_init_thermal(const ClassDev& c, double kT, uint64_t seed, hipStream_t s);
+hipError_t launch_forces(const ClassDev& c, hipStream_t s);
+hipError_t launch_prop(const ClassDev& c, int precision, hipStream_t s);
+int prop_max_col_tiles(int precision);
+hipError_t prop_prepare(const ClassDev& c, int precision);
+size_t prop_lds_bytes(const ClassDev& c, int precision);
+hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt,
+                      iesh_event* events, int query_mode, int t0, int nt, int record,
+                      int exit_enabled, double exit_x, int64_t max_steps, int precision,
+                      hipStream_t s);
+hipError_t launch_lowdin(const ClassDev& c, const Counters* cnt, int every, double2* scratch,
+                         hipStream_t s);
+size_t lowdin_scratch_elems(const ClassDev& c);
+hipError_t launch_advance(Counters* cnt, hipStream_t s);
+
+// Host-side bath discretisation (bath.cpp).
+int discretize(int kind, int M, double a, double b, double eps_f, double* eps, double* w);
+
+}  // namespace iesh

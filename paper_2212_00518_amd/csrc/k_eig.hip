@@ -1,0 +1,583 @@
+// Arrowhead eigen-solver, couplings, Chebyshev set-up and velocity Verlet.
+//
+// The one-electron Hamiltonian of the Newns-Anderson model (Sec. II.B) is a
+// symmetric arrowhead matrix: h on [0][0], the bath energies eps_k on the
+// diagonal and the couplings V_k in row and column 0.  Its eigenvalues are
+// the roots of the secular function
+//     f(lambda) = lambda - h + sum_k V_k^2 / (eps_k - lambda),
+// one below eps_0, one between each pair of neighbouring bath levels and one
+// above eps_{M-1} (strict interlacing when every V_k != 0).  Each root is
+// found relative to its nearest pole, tau = lambda - eps_o, so that the
+// differences lambda_j - eps_k stay accurate for closely spaced levels; the
+// iteration fits a two-pole rational model to f and f' at the current point
+// (quadratic convergence) inside a bisection bracket.  The bath components
+// of the eigenvectors use couplings recomputed from the roots (Loewner
+// formula), which keeps the computed vectors orthogonal; only the impurity
+// components q0_j are kept, since every quantity of the step is a function
+// of (lambda, q0) alone:
+//   G_jk = (Q^T dH/dx Q)_jk = q0_j q0_k (h' + rho (lambda_j + lambda_k - 2h)),
+// with V_k(x) = Vbar_k f(x) and rho = f'/f (row 0 of the eigen-equation gives
+// sum_k V_k Q_kj = (lambda_j - h) q0_j).
+//
+// One work-group per trajectory; 256 threads; every array lives in LDS.
+
+#include "iesh_internal.hpp"
+
+namespace iesh {
+namespace {
+
+constexpr int kEigThreads = 256;
+constexpr double kEps = 2.220446049250313e-16;
+
+struct EigLds {
+  double e[kMaxStates];      // bath energies
+  double V2[kMaxStates];     // V_k(x)^2
+  double tau[kMaxStates];    // root relative to its origin pole
+  double Vh2[kMaxStates];    // Loewner couplings squared
+  double q0[kMaxStates];     // impurity amplitudes
+  double lam[kMaxStates];    // eigenvalues (eps_o + tau)
+  double red[kEigThreads];   // reductions
+  double red2[kEigThreads];
+  int org[kMaxStates];       // origin pole index of each root
+  int fail;
+  int count;
+  double sc[16];             // scalars
+};
+
+// f and its split derivative at tau (origin eo); terms with k < j are left
+// of the root.
+__device__ inline void secular_eval(int j, int M, const double* e, const double* V2, double eo,
+                                    double emh, double tau, double& f, double& dl, double& dr,
+                                    double& err) {
+  double psi = 0.0, l = 0.0, r = 0.0, abssum = 0.0;
+  for (int k = 0; k < M; ++k) {
+    const double d = (e[k] - eo) - tau;  // eps_k - lambda
+    const double inv = 1.0 / d;
+    const double t = V2[k] * inv;
+    psi += t;
+    abssum += fabs(t);
+    if (k < j)
+      l += t * inv;
+    else
+      r += t * inv;
+  }
+  f = emh + tau + psi;
+  dl = l;
+  dr = r;
+  err = 4.0 * kEps * (fabs(emh) + fabs(tau) + abssum);
+}
+
+// Root of a2 eta^2 + a1 eta + a0 inside (alpha, beta).
+__device__ inline double quad_root_in(double a2, double a1, double a0, double alpha, double beta) {
+  if (a2 == 0.0) return -a0 / a1;
+  const double sq = sqrt(fmax(a1 * a1 - 4.0 * a2 * a0, 0.0));
+  const double q = -0.5 * (a1 + copysign(sq, a1));
+  const double r1 = q / a2;
+  const double r2 = (q != 0.0) ? a0 / q : 0.0;
+  const bool in1 = r1 > alpha && r1 < beta;
+  const bool in2 = r2 > alpha && r2 < beta;
+  if (in1 && in2) return fabs(r1) < fabs(r2) ? r1 : r2;
+  if (in1) return r1;
+  if (in2) return r2;
+  return fabs(r1) < fabs(r2) ? r1 : r2;
+}
+
+// Root j (0..M) of the secular function.  Returns 1 on convergence.
+__device__ int secular_root(int j, int M, const double* e, const double* V2, double h,
+                            double vnorm, double& tau_out, int& org_out) {
+  int o;
+  double lo, hi, tau, f = 0.0, dl = 0.0, dr = 0.0, err = 0.0;
+  bool have_f = false;
+  if (j == 0) {
+    o = 0;
+    lo = (fmin(h, e[0]) - vnorm) - e[0];
+    hi = 0.0;
+    tau = lo;
+  } else if (j == M) {
+    o = M - 1;
+    lo = 0.0;
+    hi = (fmax(h, e[M - 1]) + vnorm) - e[M - 1];
+    tau = hi;
+  } else {
+    const double gap = e[j] - e[j - 1];
+    const double half = 0.5 * gap;
+    secular_eval(j, M, e, V2, e[j - 1], e[j - 1] - h, half, f, dl, dr, err);
+    if (f >= 0.0) {
+      o = j - 1;
+      lo = 0.0;
+      hi = half;
+      tau = half;
+      have_f = true;
+    } else {
+      o = j;
+      lo = -half * (1.0 + 4.0 * kEps);
+      hi = 0.0;
+      tau = lo;
+    }
+  }
+  const double eo = e[o];
+  const double emh = eo - h;
+  int ok = 0;
+  for (int it = 0; it < 128; ++it) {
+    if (!have_f) secular_eval(j, M, e, V2, eo, emh, tau, f, dl, dr, err);
+    have_f = false;
+    if (f == 0.0 || fabs(f) <= err) {
+      ok = 1;
+      break;
+    }
+    if (f < 0.0)
+      lo = tau;
+    else
+      hi = tau;
+    double eta;
+    if (j > 0 && j < M) {
+      const double alpha = (e[j - 1] - eo) - tau;
+      const double beta = (e[j] - eo) - tau;
+      double s1, s2;
+      if (o == j - 1) {
+        s1 = alpha * alpha * dl;
+        s2 = beta * beta * (dr + 1.0);
+      } else {
+        s1 = alpha * alpha * (dl + 1.0);
+        s2 = beta * beta * dr;
+      }
+      const double c = f - s1 / alpha - s2 / beta;
+      eta = quad_root_in(c, -(c * (alpha + beta) + s1 + s2), alpha * beta * f, alpha, beta);
+    } else if (j == 0) {
+      const double beta = -tau;
+      const double s = V2[0];
+      const double L = 1.0 + (dr - s / (beta * beta));
+      const double c0 = f - s / beta;
+      const double B = L * beta - c0;
+      const double sq = sqrt(fmax(B * B + 4.0 * L * beta * f, 0.0));
+      eta = (B > 0.0) ? (-2.0 * beta * f / (B + sq)) : ((B - sq) / (2.0 * L));
+    } else {
+      const double alpha = -tau;
+      const double s = V2[M - 1];
+      const double L = 1.0 + (dl - s / (alpha * alpha));
+      const double c0 = f - s / alpha;
+      const double B = L * alpha - c0;
+      const double sq = sqrt(fmax(B * B + 4.0 * L * alpha * f, 0.0));
+      eta = (B < 0.0) ? (2.0 * alpha * f / (sq - B)) : ((B + sq) / (2.0 * L));
+    }
+    double tn = tau + eta;
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+    if (fabs(tn - tau) <= 2.0 * kEps * fabs(tn) ||
+        hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi))) {
+      tau = tn;
+      ok = 1;
+      break;
+    }
+    tau = tn;
+  }
+  tau_out = tau;
+  org_out = o;
+  return ok;
+}
+
+// Solve the arrowhead problem of geometry x; fills lam, tau, org, q0 in LDS
+// (entries n..n_pad-1 of lam/q0 set to 0).  Returns model scalars.
+__device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict__ vbar, double x,
+                                   EigLds& L) {
+  const int M = md.M, n = md.n, tid = threadIdx.x;
+  const ModelAt ma = model_at(md, x);
+  for (int k = tid; k < M; k += kEigThreads) {
+    const double V = vbar[k] * ma.f;
+    L.V2[k] = V * V;
+  }
+  __syncthreads();
+  // ||V||^2 (fixed-order reduction)
+  double part = 0.0;
+  for (int k = tid; k < M; k += kEigThreads) part += L.V2[k];
+  L.red[tid] = part;
+  __syncthreads();
+  for (int s = kEigThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) L.red[tid] += L.red[tid + s];
+    __syncthreads();
+  }
+  const double vnorm = sqrt(L.red[0]);
+  __syncthreads();
+  for (int j = tid; j < n; j += kEigThreads) {
+    double tau;
+    int o;
+    const int ok = secular_root(j, M, L.e, L.V2, ma.h, vnorm, tau, o);
+    L.tau[j] = tau;
+    L.org[j] = o;
+    L.lam[j] = L.e[o] + tau;
+    if (!ok) atomicOr(&L.fail, 1);
+  }
+  __syncthreads();
+  // Loewner couplings: Vh_k^2 = -prod_j (e_k - lambda_j) / prod_{l != k} (e_k - e_l),
+  // factors paired so that each ratio stays near 1.
+  for (int k = tid; k < M; k += kEigThreads) {
+    const double ek = L.e[k];
+    const double dk = (ek - L.e[L.org[k]]) - L.tau[k];            // e_k - lambda_k  > 0
+    const double dk1 = (ek - L.e[L.org[k + 1]]) - L.tau[k + 1];   // e_k - lambda_k+1 < 0
+    double prod = dk * (-dk1);
+    for (int l = 0; l < M; ++l) {
+      if (l < k) {
+        prod *= ((ek - L.e[L.org[l]]) - L.tau[l]) / (ek - L.e[l]);
+      } else if (l > k) {
+        prod *= ((L.e[L.org[l + 1]] - ek) + L.tau[l + 1]) / (L.e[l] - ek);
+      }
+    }
+    L.Vh2[k] = prod;
+  }
+  __syncthreads();
+  for (int j = tid; j < md.n_pad; j += kEigThreads) {
+    if (j < n) {
+      const double eo = L.e[L.org[j]], tj = L.tau[j];
+      double s = 1.0;
+      for (int k = 0; k < M; ++k) {
+        const double d = (L.e[k] - eo) - tj;
+        s += L.Vh2[k] / (d * d);
+      }
+      L.q0[j] = 1.0 / sqrt(s);
+    } else {
+      L.q0[j] = 0.0;
+      L.lam[j] = 0.0;
+    }
+  }
+  __syncthreads();
+  return ma;
+}
+
+// lambda_k - lambda_j from the pole-relative representation.
+__device__ inline double lam_diff(const EigLds& L, int k, int j) {
+  return (L.e[L.org[k]] - L.e[L.org[j]]) + (L.tau[k] - L.tau[j]);
+}
+
+// v * D[j][k] for j != k < n.
+__device__ inline double vD_elem(const EigLds& L, const ModelAt& ma, double v, int j, int k) {
+  const double g = L.q0[j] * L.q0[k] * (ma.dh + ma.rho * ((L.lam[j] - ma.h) + (L.lam[k] - ma.h)));
+  return v * g / lam_diff(L, k, j);
+}
+
+// Bessel J_k(rho), k = 0..K, by Miller's downward recurrence normalised with
+// J_0 + 2 sum_{k>=1} J_{2k} = 1.
+__device__ void bessel_j(int K, double rho, double* J) {
+  for (int k = 0; k <= K; ++k) J[k] = 0.0;
+  if (rho < 1e-300) {
+    J[0] = 1.0;
+    return;
+  }
+  const int base = (K > (int)rho ? K : (int)rho);
+  int m = base + 30 + (int)sqrt(40.0 * (base + 1));
+  m += (m & 1);
+  double jp1 = 0.0, jk = 1e-280, norm = 0.0;
+  for (int k = m; k > 0; --k) {
+    const double jm1 = (2.0 * k / rho) * jk - jp1;  // J_{k-1}
+    jp1 = jk;
+    jk = jm1;
+    if (fabs(jk) > 1e250) {
+      jk *= 1e-250;
+      jp1 *= 1e-250;
+      norm *= 1e-250;
+      for (int q = 0; q <= K; ++q) J[q] *= 1e-250;
+    }
+    const int km1 = k - 1;
+    if (km1 <= K) J[km1] = jk;
+    if (km1 > 0 && (km1 & 1) == 0) norm += 2.0 * jk;
+  }
+  norm += jk;  // J_0
+  const double inv = 1.0 / norm;
+  for (int k = 0; k <= K; ++k) J[k] *= inv;
+}
+
+// Number of Chebyshev terms so that the tail sum_{k>K} 2|J_k(rho)| < tol,
+// bounding |J_k(rho)| by (rho/2)^k / k!.
+__device__ int cheb_terms(double rho, double tol) {
+  const double h = 0.5 * rho;
+  double term = 1.0;  // (rho/2)^k / k!
+  for (int k = 0; k < kMaxCheb - 1; ++k) {
+    const double next = term * h / (k + 1);  // bound of |J_{k+1}|
+    if (k + 2 > h) {
+      const double tail = 2.0 * next / (1.0 - h / (k + 2));
+      if (tail < tol) return k > 0 ? k : 1;
+    }
+    term = next;
+  }
+  return -1;
+}
+
+__device__ void write_model_geo(double* geo, const ModelAt& ma) {
+  geo[GEO_H] = ma.h;
+  geo[GEO_DH] = ma.dh;
+  geo[GEO_RHO] = ma.rho;
+  geo[GEO_U0] = ma.U0;
+  geo[GEO_DU0] = ma.dU0;
+}
+
+// Hellmann-Feynman force of the occupied set at the geometry held in L.
+__device__ double hf_force(const ModelDev& md, const ModelAt& ma, const int32_t* occ, EigLds& L) {
+  const int tid = threadIdx.x;
+  double part = 0.0;
+  if (tid < md.N) {
+    const int a = occ[tid];
+    part = L.q0[a] * L.q0[a] * (ma.dh + 2.0 * ma.rho * (L.lam[a] - ma.h));
+  }
+  L.red2[tid] = part;
+  __syncthreads();
+  for (int s = kEigThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) L.red2[tid] += L.red2[tid + s];
+    __syncthreads();
+  }
+  const double F = -ma.dU0 - L.red2[0];
+  __syncthreads();
+  return F;
+}
+
+__device__ void load_bath(const ClassDev& c, EigLds& L) {
+  for (int k = threadIdx.x; k < c.md.M; k += kEigThreads) L.e[k] = c.eps[k];
+  if (threadIdx.x == 0) {
+    L.fail = 0;
+    L.count = 0;
+  }
+  __syncthreads();
+}
+
+// One step for one trajectory up to (not including) the propagation.
+__global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt, int precision) {
+  __shared__ EigLds L;
+  const int t = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (c.status[t] & kFreezeMask) return;
+  const ModelDev& md = c.md;
+  load_bath(c, L);
+  if (tid == 0) {
+    const double x = c.x[t], v = c.v[t], F = c.F[t];
+    const double vh = v + 0.5 * dt * F / md.mass;
+    const double xn = x + dt * vh;
+    L.sc[0] = vh;
+    L.sc[1] = xn;
+    L.sc[2] = 0.5 * (x + xn);
+  }
+  __syncthreads();
+  const double vh = L.sc[0], xn = L.sc[1], xm = L.sc[2];
+
+  // ---- midpoint geometry: couplings for the propagator
+  const ModelAt mm = solve_arrowhead(md, c.vbar, xm, L);
+  const int n = md.n, n_pad = md.n_pad, RT = n_pad / 16;
+  double* Bt = c.Bt + (size_t)t * n_pad * n_pad;
+  float* Bt32 = c.Bt32 ? c.Bt32 + (size_t)t * n_pad * n_pad : nullptr;
+  double lo_part = 1e300, hi_part = -1e300;
+  for (int j = tid; j < n_pad; j += kEigThreads) {
+    const int rt = j >> 4, lane_lo = j & 15;
+    double rsum = 0.0;
+    for (int k = 0; k < n_pad; ++k) {
+      double val = 0.0;
+      if (j < n && k < n && j != k) val = vD_elem(L, mm, vh, j, k);
+      rsum += fabs(val);
+      const size_t off = ((size_t)((k >> 2) * RT + rt) << 6) + lane_lo + ((k & 3) << 4);
+      if (precision == IESH_FP64)
+        Bt[off] = val;
+      else
+        Bt32[off] = (float)val;
+    }
+    if (j < n) {
+      lo_part = fmin(lo_part, L.lam[j] - rsum);
+      hi_part = fmax(hi_part, L.lam[j] + rsum);
+    }
+    c.lam_mid[(size_t)t * n_pad + j] = (j < n) ? L.lam[j] : 0.0;
+  }
+  L.red[tid] = lo_part;
+  L.red2[tid] = hi_part;
+  __syncthreads();
+  for (int s = kEigThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      L.red[tid] = fmin(L.red[tid], L.red[tid + s]);
+      L.red2[tid] = fmax(L.red2[tid], L.red2[tid + s]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double* cb = c.cheb + (size_t)t * kChebStride;
+    const double lo = L.red[0], hi = L.red2[0];
+    const double cc = 0.5 * (lo + hi);
+    const double rr = fmax(0.5 * (hi - lo), 1e-300);
+    const double rho = rr * dt;
+    const int K = cheb_terms(rho, precision == IESH_FP64 ? 2e-16 : 1e-8);
+    if (K < 0) {
+      atomicOr(&L.fail, 2);
+    } else {
+      double J[kMaxCheb];
+      bessel_j(K, rho, J);
+      double sn, cs;
+      sincos(cc * dt, &sn, &cs);
+      // e^{-i c dt} * (2 - delta_k0) * (-i)^k * J_k
+      for (int k = 0; k <= K; ++k) {
+        const double a = (k ? 2.0 : 1.0) * J[k];
+        double ar, ai;  // (-i)^k * a
+        switch (k & 3) {
+          case 0: ar = a; ai = 0.0; break;
+          case 1: ar = 0.0; ai = -a; break;
+          case 2: ar = -a; ai = 0.0; break;
+          default: ar = 0.0; ai = a; break;
+        }
+        cb[CHEB_COEF + 2 * k] = cs * ar + sn * ai;
+        cb[CHEB_COEF + 2 * k + 1] = cs * ai - sn * ar;
+      }
+      cb[CHEB_C] = cc;
+      cb[CHEB_INVR] = 1.0 / rr;
+      cb[CHEB_K] = (double)K;
+      cb[CHEB_RHO] = rho;
+    }
+  }
+  __syncthreads();
+
+  // ---- end-point geometry: energies, amplitudes, forces
+  const ModelAt mn = solve_arrowhead(md, c.vbar, xn, L);
+  for (int j = tid; j < n_pad; j += kEigThreads) {
+    c.lam[(size_t)t * n_pad + j] = L.lam[j];
+    c.q0[(size_t)t * n_pad + j] = L.q0[j];
+  }
+  const double Fn = hf_force(md, mn, c.occ + (size_t)t * md.N, L);
+  if (tid == 0) {
+    write_model_geo(c.geo + (size_t)t * kGeoStride, mn);
+    const double vn = vh + 0.5 * dt * Fn / md.mass;
+    c.x[t] = xn;
+    c.v[t] = vn;
+    c.F[t] = Fn;
+    int st = c.status[t];
+    if (L.fail & 1) st |= IESH_TRAJ_NONCONV;
+    if (L.fail & 2) st |= IESH_TRAJ_NONCONV;
+    if (!isfinite(xn) || !isfinite(vn)) st |= IESH_TRAJ_NONFINITE;
+    c.status[t] = st;
+  }
+}
+
+// Eigen-solve at the current x (no dynamics): energies, amplitudes, model
+// scalars; mode 1 also refreshes the force of the current occupations.
+__global__ __launch_bounds__(kEigThreads) void k_eig_query(ClassDev c, int t0, int mode) {
+  __shared__ EigLds L;
+  const int t = t0 + blockIdx.x;
+  const int tid = threadIdx.x;
+  const ModelDev& md = c.md;
+  load_bath(c, L);
+  const double x = c.x[t];
+  const ModelAt ma = solve_arrowhead(md, c.vbar, x, L);
+  for (int j = tid; j < md.n_pad; j += kEigThreads) {
+    c.lam[(size_t)t * md.n_pad + j] = L.lam[j];
+    c.q0[(size_t)t * md.n_pad + j] = L.q0[j];
+  }
+  if (tid == 0) write_model_geo(c.geo + (size_t)t * kGeoStride, ma);
+  if (mode == 1) {
+    const double F = hf_force(md, ma, c.occ + (size_t)t * md.N, L);
+    if (tid == 0) {
+      c.F[t] = F;
+      if (L.fail) c.status[t] |= IESH_TRAJ_NONCONV;
+    }
+  }
+}
+
+// Initial occupations at kT (fixed N) and unit-vector orbitals.
+__global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double kT, uint64_t seed) {
+  __shared__ EigLds L;
+  const int t = blockIdx.x;
+  const int tid = threadIdx.x;
+  const ModelDev& md = c.md;
+  const int n = md.n, N = md.N;
+  load_bath(c, L);
+  const ModelAt ma = solve_arrowhead(md, c.vbar, c.x[t], L);
+  int32_t* occ = c.occ + (size_t)t * N;
+  __shared__ int chosen[kMaxStates];
+  bool done = false;
+  if (kT > 0.0) {
+    // chemical potential by bisection on sum_a f_a = N
+    double lo = L.lam[0] - 50.0 * kT - 1.0, hi = L.lam[n - 1] + 50.0 * kT + 1.0;
+    for (int it = 0; it < 200; ++it) {
+      const double mu = 0.5 * (lo + hi);
+      double part = 0.0;
+      for (int a = tid; a < n; a += kEigThreads) {
+        const double z = (L.lam[a] - mu) / kT;
+        part += (z > 0.0) ? exp(-z) / (1.0 + exp(-z)) : 1.0 / (1.0 + exp(z));
+      }
+      L.red[tid] = part;
+      __syncthreads();
+      for (int s = kEigThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) L.red[tid] += L.red[tid + s];
+        __syncthreads();
+      }
+      if (L.red[0] > (double)N)
+        hi = mu;
+      else
+        lo = mu;
+      __syncthreads();
+    }
+    const double mu = 0.5 * (lo + hi);
+    const uint32_t gt = (uint32_t)c.gtraj[t];
+    for (int attempt = 0; attempt < 4096 && !done; ++attempt) {
+      int cnt = 0;
+      for (int a = tid; a < n; a += kEigThreads) {
+        const double z = (L.lam[a] - mu) / kT;
+        const double fa = (z > 0.0) ? exp(-z) / (1.0 + exp(-z)) : 1.0 / (1.0 + exp(z));
+        const double u = philox_uniform(seed, gt, (uint64_t)attempt * n + a, 1u);
+        chosen[a] = (u < fa) ? 1 : 0;
+        cnt += chosen[a];
+      }
+      L.red[tid] = (double)cnt;
+      __syncthreads();
+      for (int s = kEigThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) L.red[tid] += L.red[tid + s];
+        __syncthreads();
+      }
+      done = ((int)L.red[0] == N);
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    int r = 0;
+    for (int a = 0; a < n; ++a) {
+      if (done ? chosen[a] : (a < N)) occ[r++] = a;
+    }
+  }
+  __syncthreads();
+  // orbitals: column j = unit vector of occ[j]
+  for (int idx = tid; idx < N * md.n_pad; idx += kEigThreads) {
+    const int j = idx / md.n_pad, i = idx % md.n_pad;
+    const double val = (i == occ[j]) ? 1.0 : 0.0;
+    if (c.C64) {
+      c.C64[((size_t)t * N * md.n_pad + idx) * 2] = val;
+      c.C64[((size_t)t * N * md.n_pad + idx) * 2 + 1] = 0.0;
+    }
+    if (c.C32) {
+      c.C32[((size_t)t * N * md.n_pad + idx) * 2] = (float)val;
+      c.C32[((size_t)t * N * md.n_pad + idx) * 2 + 1] = 0.0f;
+    }
+  }
+  for (int j = tid; j < md.n_pad; j += kEigThreads) {
+    c.lam[(size_t)t * md.n_pad + j] = L.lam[j];
+    c.q0[(size_t)t * md.n_pad + j] = L.q0[j];
+  }
+  const double F = hf_force(md, ma, occ, L);
+  if (tid == 0) {
+    write_model_geo(c.geo + (size_t)t * kGeoStride, ma);
+    c.F[t] = F;
+    c.status[t] = L.fail ? IESH_TRAJ_NONCONV : 0;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_eig_step(const ClassDev& c, double dt, hipStream_t s) {
+  const int precision = c.C64 ? IESH_FP64 : IESH_MIXED;
+  hipLaunchKernelGGL(k_eig_step, dim3(c.n_traj), dim3(kEigThreads), 0, s, c, dt, precision);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_query(const ClassDev& c, int t0, int nt, hipStream_t s) {
+  hipLaunchKernelGGL(k_eig_query, dim3(nt), dim3(kEigThreads), 0, s, c, t0, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_forces(const ClassDev& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_eig_query, dim3(c.n_traj), dim3(kEigThreads), 0, s, c, 0, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_thermal(const ClassDev& c, double kT, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_thermal, dim3(c.n_traj), dim3(kEigThreads), 0, s, c, kT, seed);
+  return hipGetLastError();
+}
+
+}  // namespace iesh

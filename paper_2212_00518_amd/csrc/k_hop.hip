@@ -1,0 +1,505 @@
+// Hop probabilities from determinant ratios, hop selection, rescaling,
+// occupation update and observables (Sec. II.B, Eqs. hopping_probability and
+// hopping_rate; the Slater-determinant overlaps <k|psi> = det S).
+//
+// For the occupied set s (sorted) the overlap matrix is S = C[s, :].  Moving
+// one electron from orbital a (row r of S) to orbital b replaces row r of S
+// by row b of C, and by the matrix determinant lemma
+//     <j|psi> / <k|psi> = (C S^-1)[b][r] = W[b][r],
+// so every hop probability follows from one inverse of S:
+//     g(a -> b) = max(-2 dt v D[b][a] Re W[b][r], 0).
+// W is formed by Gauss-Jordan elimination with column pivoting applied to
+// the whole n x N orbital matrix: column operations that turn the rows of S
+// into a permutation turn the remaining rows into W (columns permuted).
+//
+// One work-group of 512 threads per trajectory.  Thread (ti, tj), tid =
+// ti + 16 tj, owns rows ti + 16 ri and columns tj + 32 cj of the n x N
+// matrix in registers (the slot counts RS, CS are template parameters sized
+// to the problem); a row of S and the pivot column are exchanged through
+// LDS, and every wave chooses the pivot redundantly from the same LDS data.
+
+#include "iesh_internal.hpp"
+
+namespace iesh {
+namespace {
+
+constexpr int kHopThreads = 512;
+constexpr int kRowLanes = 16;  // threads along the rows (states)
+constexpr int kColLanes = 32;  // threads along the columns (orbitals)
+
+struct HopLds {
+  double2 rowbuf[2][kMaxElec];
+  double2 colbuf[2][kMaxStates];
+  double lam[kMaxStates];
+  double q0[kMaxStates];
+  double rowsum[kMaxElec];
+  double grow[kMaxStates];
+  double zz[kMaxElec];
+  int occflag[kMaxStates];
+  int perm[kMaxElec];
+  int invperm[kMaxElec];
+  int occ[kMaxElec];
+  int singular;
+  int sc_occ_changed;
+  double sc_xi;
+  double sc_v;
+};
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <bool kF32, int kRS, int kCS>
+__global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint64_t seed,
+                                                     Counters* cnt, iesh_event* events,
+                                                     int query_mode, int t0, int record,
+                                                     int exit_enabled, double exit_x,
+                                                     int64_t max_steps) {
+  __shared__ HopLds L;
+  const int t = t0 + blockIdx.x;
+  const int tid = threadIdx.x;
+  const int ti = tid & 15, tj = tid >> 4;
+  const int lane = tid & 63;
+  const ModelDev& md = c.md;
+  const int n = md.n, n_pad = md.n_pad, N = md.N;
+  if (!query_mode && (c.status[t] & kFreezeMask)) return;
+
+  for (int k = tid; k < n_pad; k += kHopThreads) {
+    L.lam[k] = c.lam[(size_t)t * n_pad + k];
+    L.q0[k] = c.q0[(size_t)t * n_pad + k];
+    L.occflag[k] = 0;
+  }
+  if (tid == 0) L.singular = 0;
+  __syncthreads();
+  for (int r = tid; r < N; r += kHopThreads) {
+    const int a = c.occ[(size_t)t * N + r];
+    L.occ[r] = a;
+    L.occflag[a] = 1;
+  }
+
+  // ---- orbitals into registers
+  double2 w[kRS][kCS];
+#pragma unroll
+  for (int ri = 0; ri < kRS; ++ri) {
+#pragma unroll
+    for (int cj = 0; cj < kCS; ++cj) {
+      const int i = ti + 16 * ri, j = tj + 32 * cj;
+      double2 val = make_double2(0.0, 0.0);
+      if (i < n_pad && j < N) {
+        const size_t off = ((size_t)t * N + j) * n_pad + i;
+        if (kF32) {
+          const float2 f = reinterpret_cast<const float2*>(c.C32)[off];
+          val = make_double2((double)f.x, (double)f.y);
+        } else {
+          val = reinterpret_cast<const double2*>(c.C64)[off];
+        }
+      }
+      w[ri][cj] = val;
+    }
+  }
+  __syncthreads();
+
+  // ---- impurity amplitude of every orbital, sum_i q0_i C[i][j] (observable)
+  if (record && !query_mode) {
+#pragma unroll
+    for (int cj = 0; cj < kCS; ++cj) {
+      double zr = 0.0, zi = 0.0;
+#pragma unroll
+      for (int ri = 0; ri < kRS; ++ri) {
+        const int i = ti + 16 * ri;
+        const double q = (i < n_pad) ? L.q0[i] : 0.0;
+        zr += q * w[ri][cj].x;
+        zi += q * w[ri][cj].y;
+      }
+      for (int m = kRowLanes / 2; m > 0; m >>= 1) {
+        zr += __shfl_xor(zr, m, kRowLanes);
+        zi += __shfl_xor(zi, m, kRowLanes);
+      }
+      const int j = tj + 32 * cj;
+      if (ti == 0 && j < N) L.zz[j] = zr * zr + zi * zi;
+    }
+  }
+
+  // ---- Gauss-Jordan elimination with column pivoting on the rows of S
+  static_assert(kMaxElec <= 128, "used-column mask holds 128 bits");
+  uint64_t used_lo = 0, used_hi = 0;
+  for (int r = 0; r < N; ++r) {
+    const int buf = r & 1;
+    const int i = L.occ[r];
+    if (ti == (i & 15)) {
+      const int ri0 = i >> 4;
+#pragma unroll
+      for (int cj = 0; cj < kCS; ++cj) {
+        const int j = tj + 32 * cj;
+        if (j < N) {
+          double2 val = w[0][cj];
+#pragma unroll
+          for (int ri = 1; ri < kRS; ++ri)
+            if (ri == ri0) val = w[ri][cj];
+          L.rowbuf[buf][j] = val;
+        }
+      }
+    }
+    __syncthreads();
+    // pivot: largest |S[r][j]| over unused columns, ties to the smallest j
+    double best = -1.0;
+    int bidx = 0x7fffffff;
+#pragma unroll
+    for (int h = 0; h < (kMaxElec + 63) / 64; ++h) {
+      const int j = lane + 64 * h;
+      const bool used_j = (j < 64) ? ((used_lo >> j) & 1ull) : ((used_hi >> (j - 64)) & 1ull);
+      if (j < N && !used_j) {
+        const double2 z = L.rowbuf[buf][j];
+        const double m = z.x * z.x + z.y * z.y;
+        if (m > best || (m == best && j < bidx)) {
+          best = m;
+          bidx = j;
+        }
+      }
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+      const double ob = __shfl_xor(best, m);
+      const int oi = __shfl_xor(bidx, m);
+      if (ob > best || (ob == best && oi < bidx)) {
+        best = ob;
+        bidx = oi;
+      }
+    }
+    // A zero pivot (singular S) turns the remaining steps into no-ops; every
+    // wave sees the same data, so the decision is uniform.
+    const bool bad = !(best > 0.0) || bidx >= N;
+    if (bad && tid == 0) L.singular = 1;
+    const int p = bad ? 0 : bidx;
+    if (!bad) {
+      if (p < 64)
+        used_lo |= 1ull << p;
+      else
+        used_hi |= 1ull << (p - 64);
+    }
+    const double2 piv = L.rowbuf[buf][p];
+    const double inv_m = bad ? 0.0 : 1.0 / best;
+    const double2 pinv = make_double2(piv.x * inv_m, -piv.y * inv_m);
+    if (tid == 0) L.perm[r] = p;
+    // owners of column p publish the scaled pivot column (read-only here)
+    if (!bad && tj == (p & 31)) {
+      const int cj0 = p >> 5;
+#pragma unroll
+      for (int cj = 0; cj < kCS; ++cj) {
+        if (cj == cj0) {
+#pragma unroll
+          for (int ri = 0; ri < kRS; ++ri) {
+            const int ii = ti + 16 * ri;
+            if (ii < n_pad) L.colbuf[buf][ii] = cmul(w[ri][cj], pinv);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // every element: column p becomes the scaled pivot column, the others
+    // lose their component along it (branch-free on the register matrix)
+    double2 rb[kCS];
+    bool isp[kCS];
+#pragma unroll
+    for (int cj = 0; cj < kCS; ++cj) {
+      const int j = tj + 32 * cj;
+      isp[cj] = !bad && (j == p);
+      rb[cj] = (!bad && j < N) ? L.rowbuf[buf][j] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int ri = 0; ri < kRS; ++ri) {
+      const int ii = ti + 16 * ri;
+      const double2 cbv = (!bad && ii < n_pad) ? L.colbuf[buf][ii] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int cj = 0; cj < kCS; ++cj) {
+        const double2 pr = cmul(rb[cj], cbv);
+        const double2 upd = make_double2(w[ri][cj].x - pr.x, w[ri][cj].y - pr.y);
+        w[ri][cj] = isp[cj] ? cbv : upd;
+      }
+    }
+  }
+  __syncthreads();
+  const bool singular = L.singular != 0;
+  if (!singular) {
+    for (int r = tid; r < N; r += kHopThreads) L.invperm[L.perm[r]] = r;
+  }
+  __syncthreads();
+
+  const double* geo = c.geo + (size_t)t * kGeoStride;
+  const double h = geo[GEO_H], dh = geo[GEO_DH], rho = geo[GEO_RHO];
+  const double v = c.v[t];
+
+  // ---- hop probabilities, formed on the fly from the owned elements
+  auto gval = [&](int ri, int cj) -> double {
+    const int bb = ti + 16 * ri, j = tj + 32 * cj;
+    if (singular || bb >= n || j >= N || L.occflag[bb]) return 0.0;
+    const int a = L.occ[L.invperm[j]];
+    const double gab = L.q0[bb] * L.q0[a] * (dh + rho * ((L.lam[bb] - h) + (L.lam[a] - h)));
+    const double vD = v * gab / (L.lam[a] - L.lam[bb]);  // v <b|d/dx a>
+    return fmax(-2.0 * dt * vD * w[ri][cj].x, 0.0);
+  };
+
+  if (query_mode) {
+    double* go = c.gbuf + (size_t)t * N * n_pad;
+#pragma unroll
+    for (int ri = 0; ri < kRS; ++ri) {
+#pragma unroll
+      for (int cj = 0; cj < kCS; ++cj) {
+        const int bb = ti + 16 * ri, j = tj + 32 * cj;
+        if (bb < n_pad && j < N) go[(size_t)(singular ? j : L.invperm[j]) * n_pad + bb] = gval(ri, cj);
+      }
+    }
+    if (singular && tid == 0) c.status[t] |= IESH_TRAJ_SINGULAR_S;
+    return;
+  }
+
+  // ---- row totals (fixed-order reduction over the owned rows)
+#pragma unroll
+  for (int cj = 0; cj < kCS; ++cj) {
+    double s = 0.0;
+#pragma unroll
+    for (int ri = 0; ri < kRS; ++ri) s += gval(ri, cj);
+    for (int m = kRowLanes / 2; m > 0; m >>= 1) s += __shfl_xor(s, m, kRowLanes);
+    const int j = tj + 32 * cj;
+    if (ti == 0 && j < N && !singular) L.rowsum[L.invperm[j]] = s;
+  }
+  __syncthreads();
+
+  const int64_t step = cnt->step;
+  __shared__ int sel_r, sel_cidx;
+  __shared__ double sel_prev, sel_margin, sel_total;
+  if (tid == 0) {
+    sel_r = -1;
+    sel_margin = 1e300;
+    sel_total = 0.0;
+    if (!singular) {
+      const double xi = philox_uniform(seed, (uint32_t)c.gtraj[t], (uint64_t)step, 0u);
+      double cum = 0.0, margin = 1e300;
+      for (int r = 0; r < N; ++r) {
+        const double prev = cum;
+        cum = cum + L.rowsum[r];
+        margin = fmin(margin, fabs(cum - xi));
+        if (sel_r < 0 && cum > xi) {
+          sel_r = r;
+          sel_prev = prev;
+          break;
+        }
+      }
+      double tot = 0.0;
+      for (int r = 0; r < N; ++r) tot += L.rowsum[r];
+      sel_total = tot;
+      sel_margin = margin;
+      L.sc_xi = xi;
+    }
+  }
+  __syncthreads();
+  const int rsel = sel_r;
+  if (rsel >= 0) {
+    const int csel = L.perm[rsel];
+    if (tj == (csel & 31)) {
+      const int cj0 = csel >> 5;
+#pragma unroll
+      for (int cj = 0; cj < kCS; ++cj)
+        if (cj == cj0)
+#pragma unroll
+          for (int ri = 0; ri < kRS; ++ri) {
+            const int bb = ti + 16 * ri;
+            if (bb < n_pad) L.grow[bb] = gval(ri, cj);
+          }
+    }
+  }
+  __syncthreads();
+
+  if (tid == 0) {
+    double vnew = v;
+    int32_t st = c.status[t];
+    if (singular) st |= IESH_TRAJ_SINGULAR_S;
+    int occ_changed = 0;
+    if (rsel >= 0) {
+      const double xi = L.sc_xi;
+      double acc = sel_prev, margin = sel_margin;
+      int bsel = -1;
+      for (int bb = 0; bb < n; ++bb) {
+        const double g = L.grow[bb];
+        if (g == 0.0) continue;
+        acc = acc + g;
+        margin = fmin(margin, fabs(acc - xi));
+        if (acc > xi) {
+          bsel = bb;
+          break;
+        }
+      }
+      if (bsel < 0) {
+        for (int bb = n - 1; bb >= 0; --bb)
+          if (L.grow[bb] > 0.0) {
+            bsel = bb;
+            break;
+          }
+        margin = 0.0;
+      }
+      const int a = L.occ[rsel];
+      // rescale along d = <b|d/dx a>
+      const double gba = L.q0[bsel] * L.q0[a] * (dh + rho * ((L.lam[bsel] - h) + (L.lam[a] - h)));
+      const double d = gba / (L.lam[a] - L.lam[bsel]);
+      const double dE = L.lam[bsel] - L.lam[a];
+      const double A2 = d * d / (2.0 * md.mass);
+      const double B1 = v * d;
+      const double disc = B1 * B1 - 4.0 * A2 * dE;
+      int accepted = 0;
+      if (A2 != 0.0 && disc >= 0.0) {
+        const double root = sqrt(disc);
+        const double q = B1 + (B1 >= 0.0 ? root : -root);
+        const double gamma = (q != 0.0) ? 2.0 * dE / q : 0.0;
+        vnew = v - gamma * d / md.mass;
+        accepted = 1;
+        // occupation update, keep sorted
+        int* o = L.occ;
+        o[rsel] = bsel;
+        int r = rsel;
+        while (r > 0 && o[r - 1] > o[r]) {
+          const int tmp = o[r - 1];
+          o[r - 1] = o[r];
+          o[r] = tmp;
+          --r;
+        }
+        while (r < N - 1 && o[r + 1] < o[r]) {
+          const int tmp = o[r + 1];
+          o[r + 1] = o[r];
+          o[r] = tmp;
+          ++r;
+        }
+        occ_changed = 1;
+      }
+      const int64_t slot = atomicAdd((unsigned long long*)&cnt->n_events, 1ull);
+      if (slot < IESH_EVENT_CAP) {
+        iesh_event* ev = events + slot;
+        ev->step = step;
+        ev->traj = c.gtraj[t];
+        ev->a = a;
+        ev->b = bsel;
+        ev->accepted = accepted;
+        ev->margin = margin;
+        ev->g_total = sel_total;
+      }
+    }
+    // force refresh for the (possibly new) occupations
+    if (occ_changed) {
+      double s = 0.0;
+      for (int r = 0; r < N; ++r) {
+        const int a = L.occ[r];
+        s += L.q0[a] * L.q0[a] * (dh + 2.0 * rho * (L.lam[a] - h));
+      }
+      c.F[t] = -geo[GEO_DU0] - s;
+      c.v[t] = vnew;
+    }
+    const int64_t ns = c.nsteps[t] + 1;
+    c.nsteps[t] = ns;
+    const double x = c.x[t];
+    if (exit_enabled && x > exit_x) st |= IESH_TRAJ_EXITED;
+    if (max_steps > 0 && ns >= max_steps) st |= IESH_TRAJ_STEPCAP;
+    if (!isfinite(vnew)) st |= IESH_TRAJ_NONFINITE;
+    c.status[t] = st;
+    L.sc_occ_changed = occ_changed;
+    L.sc_v = vnew;
+  }
+  __syncthreads();
+  if (L.sc_occ_changed) {
+    for (int r = tid; r < N; r += kHopThreads) c.occ[(size_t)t * N + r] = L.occ[r];
+  }
+  if (record && tid == 0) {
+    const int64_t rel = step - cnt->run_step0 + 1;
+    if (cnt->record_every > 0 && rel % cnt->record_every == 0) {
+      const int64_t rec = rel / cnt->record_every - 1;
+      double pds = 0.0, elam = 0.0, pdw = 0.0;
+      for (int r = 0; r < N; ++r) {
+        const int a = L.occ[r];
+        pds += L.q0[a] * L.q0[a];
+        elam += L.lam[a];
+        pdw += L.zz[r];
+      }
+      const double vv = L.sc_v;
+      const double ekin = 0.5 * md.mass * vv * vv;
+      const double epot = geo[GEO_U0] + elam;
+      double* o = c.obs + ((size_t)rec * c.n_traj + t) * IESH_N_OBS;
+      o[IESH_OBS_PD_SURF] = pds;
+      o[IESH_OBS_PD_WF] = pdw;
+      o[IESH_OBS_EKIN] = ekin;
+      o[IESH_OBS_EPOT] = epot;
+      o[IESH_OBS_ETOT] = ekin + epot;
+    }
+  }
+}
+
+__global__ void k_advance(Counters* cnt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) cnt->step = cnt->step + 1;
+}
+
+}  // namespace
+
+template <bool F32, int RS, int CS>
+static void launch_hop_t(const ClassDev& c, dim3 grid, double dt, uint64_t seed, Counters* cnt,
+                         iesh_event* events, int query_mode, int t0, int record,
+                         int exit_enabled, double exit_x, int64_t max_steps, hipStream_t s) {
+  hipLaunchKernelGGL((k_hop<F32, RS, CS>), grid, dim3(kHopThreads), 0, s, c, dt, seed, cnt,
+                     events, query_mode, t0, record, exit_enabled, exit_x, max_steps);
+}
+
+template <bool F32, int RS>
+static void launch_hop_rs(const ClassDev& c, dim3 grid, double dt, uint64_t seed,
+                          Counters* cnt, iesh_event* events, int query_mode, int t0,
+                          int record, int exit_enabled, double exit_x, int64_t max_steps,
+                          hipStream_t s) {
+  const int N = c.md.N;
+  if (N <= 32)
+    launch_hop_t<F32, RS, 1>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
+                             exit_enabled, exit_x, max_steps, s);
+  else if (N <= 64)
+    launch_hop_t<F32, RS, 2>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
+                             exit_enabled, exit_x, max_steps, s);
+  else
+    launch_hop_t<F32, RS, 4>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
+                             exit_enabled, exit_x, max_steps, s);
+}
+
+template <bool F32>
+static void launch_hop_p(const ClassDev& c, dim3 grid, double dt, uint64_t seed, Counters* cnt,
+                         iesh_event* events, int query_mode, int t0, int record,
+                         int exit_enabled, double exit_x, int64_t max_steps, hipStream_t s) {
+  const int rs = c.md.n_pad / kRowLanes;
+  if (rs <= 2)
+    launch_hop_rs<F32, 2>(c, grid, dt, seed, cnt, events, query_mode, t0, record, exit_enabled,
+                          exit_x, max_steps, s);
+  else if (rs <= 4)
+    launch_hop_rs<F32, 4>(c, grid, dt, seed, cnt, events, query_mode, t0, record, exit_enabled,
+                          exit_x, max_steps, s);
+  else if (rs <= 8)
+    launch_hop_rs<F32, 8>(c, grid, dt, seed, cnt, events, query_mode, t0, record, exit_enabled,
+                          exit_x, max_steps, s);
+  else if (rs <= 13)
+    launch_hop_rs<F32, 13>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
+                           exit_enabled, exit_x, max_steps, s);
+  else
+    launch_hop_rs<F32, 14>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
+                           exit_enabled, exit_x, max_steps, s);
+}
+
+hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt,
+                      iesh_event* events, int query_mode, int t0, int nt, int record,
+                      int exit_enabled, double exit_x, int64_t max_steps, int precision,
+                      hipStream_t s) {
+  const dim3 grid(query_mode ? nt : c.n_traj);
+  const int t0e = query_mode ? t0 : 0;
+  if (precision == IESH_FP64)
+    launch_hop_p<false>(c, grid, dt, seed, cnt, events, query_mode, t0e, record, exit_enabled,
+                        exit_x, max_steps, s);
+  else
+    launch_hop_p<true>(c, grid, dt, seed, cnt, events, query_mode, t0e, record, exit_enabled,
+                       exit_x, max_steps, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(Counters* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, cnt);
+  return hipGetLastError();
+}
+
+}  // namespace iesh

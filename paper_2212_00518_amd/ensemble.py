@@ -1,0 +1,45 @@
+"""Ensembles from workload descriptions, and state packing helpers."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib
+
+
+def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M: int | None = None,
+                n_elec: int | None = None, lowdin_every: int = 100, record_every: int = 0,
+                stream=None):
+    """One-class ensemble for a workload description of ``workloads.configs``
+    (bath discretised by the library)."""
+    b = cfg["bath"]
+    M = M if M is not None else b["M"]
+    N = n_elec if n_elec is not None else cfg.get("n_elec", M // 2)
+    eps, w = _lib.discretize(b["kind"], M, b["W"])
+    desc = _lib.model_desc(cfg["model"], eps, w, N)
+    run = dict(n_traj=n_traj if n_traj is not None else cfg["n_traj"], precision=precision,
+               dt=cfg["dt"], kT=cfg.get("kT", 0.0), seed=cfg.get("seed", 0),
+               lowdin_every=lowdin_every if precision == "mixed" else 0,
+               record_every=record_every)
+    return _lib.Ensemble([desc], run, stream=stream)
+
+
+def pack_states(states, n_max: int, N_max: int):
+    """states: list of (x, v, C (n x N complex), s (N,)) -> ABI arrays."""
+    T = len(states)
+    x = np.zeros(T)
+    v = np.zeros(T)
+    Cc = np.zeros((T, n_max * N_max), dtype=np.complex128)
+    occ = np.zeros((T, N_max), dtype=np.int32)
+    for t, (xx, vv, CC, ss) in enumerate(states):
+        n, N = CC.shape
+        x[t] = float(np.atleast_1d(xx)[0])
+        v[t] = float(np.atleast_1d(vv)[0])
+        Cc[t, : n * N] = np.ascontiguousarray(CC.T).reshape(-1)
+        occ[t, :N] = np.asarray(ss, dtype=np.int32)
+    return x, v, Cc, occ
+
+
+def unpack_C(Cflat, t: int, n: int, N: int, n_max: int, N_max: int):
+    """Orbital matrix (n x N) of trajectory t from the ABI layout."""
+    blk = np.asarray(Cflat).reshape(-1)[t * n_max * N_max: t * n_max * N_max + n * N]
+    return blk.reshape(N, n).T.copy()

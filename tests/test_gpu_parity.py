@@ -1,0 +1,308 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (FP64 path): energies and impurity amplitudes 1e-10 relative;
+hop probabilities 1e-10 relative to the largest probability of the
+trajectory; positions and velocities 1e-10 relative; orbital coefficients
+1e-10 absolute (orbitals have unit norm); occupations and hop events
+bit-exact except at near-ties (|cumulative sum - xi| within the tolerance).
+Mixed path: the same at 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import models, dynamics as dyn, electronic as el, rng
+from workloads import get_config, boltzmann_harmonic
+from workloads.sampling import random_orbitals, uniforms
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_00518_amd import _lib
+    _lib.lib()  # fails loudly when the library is missing
+
+
+def make_cfg(name, M=None, N=None, **model_over):
+    cfg = get_config(name)
+    if M is not None:
+        cfg["bath"]["M"] = M
+    if N is not None:
+        cfg["n_elec"] = N
+    elif M is not None:
+        cfg["n_elec"] = max(1, M // 2)
+    cfg["model"].update(model_over)
+    if name == "c3":
+        cfg.setdefault("n_elec", cfg["bath"]["M"] // 2)
+        cfg["dt"] = 5.0
+    return cfg
+
+
+def ensemble(cfg, T, precision="fp64", **kw):
+    from paper_2212_00518_amd import from_config
+    return from_config(cfg, n_traj=T, precision=precision, **kw)
+
+
+def random_states(m, N, T, seed, xs, v_scale):
+    rs = np.random.default_rng(seed)
+    out = []
+    for t in range(T):
+        C = random_orbitals(m.n, N, seed=seed * 1000 + t)
+        s = np.sort(rs.choice(m.n, N, replace=False))
+        out.append(dyn.State([xs[t]], [v_scale * rs.normal()], C, s))
+    return out
+
+
+def upload(ens, states):
+    from paper_2212_00518_amd import pack_states
+    ens.set_state(*pack_states([(s.x, s.v, s.C, s.s) for s in states], ens.n_max, ens.N_max))
+
+
+# --------------------------------------------------------------------- eigen
+@pytest.mark.parametrize("name,M,xs", [
+    ("c1", 20, np.linspace(-12, 30, 8)),
+    ("c2", 200, np.linspace(-10, 25, 6)),
+    ("c2gl", 200, np.linspace(-10, 25, 6)),
+    ("c1", 1, np.linspace(-5, 25, 4)),
+    ("c1", 5, np.linspace(-5, 25, 4)),
+    ("c3", 40, np.linspace(2.0, 14.0, 6)),
+    ("c3", 160, np.linspace(2.0, 14.0, 6)),
+    ("c2", 222, np.linspace(-10, 25, 3)),
+])
+def test_adiabatic_energies_and_amplitudes(name, M, xs):
+    cfg = make_cfg(name, M=M)
+    m = models.from_config(cfg, M=M)
+    N = cfg["n_elec"]
+    T = len(xs)
+    states = [dyn.State([x], [0.0], np.eye(m.n, N, dtype=complex), np.arange(N)) for x in xs]
+    ens = ensemble(cfg, T)
+    upload(ens, states)
+    lam, q0 = ens.adiabatic()
+    assert np.all(ens.status() == 0)
+    for t, x in enumerate(xs):
+        lr, Q = el.eig(m.H(np.array([x])))
+        scale = np.max(np.abs(lr))
+        assert np.max(np.abs(lam[t, : m.n] - lr)) <= 1e-10 * scale
+        assert np.max(np.abs(q0[t, : m.n] - Q[0]) / np.abs(Q[0])) <= 1e-10
+    ens.close()
+
+
+# --------------------------------------------------------------- hop probabilities
+@pytest.mark.parametrize("name,M,N", [
+    ("c1", 20, 10), ("c1", 1, 1), ("c1", 6, 1), ("c1", 37, 13), ("c1", 63, 31),
+    ("c2", 200, 100), ("c2gl", 200, 100), ("c3", 80, 40), ("c2", 222, 111), ("c1", 127, 127),
+])
+def test_hop_probabilities(name, M, N):
+    cfg = make_cfg(name, M=M, N=N)
+    m = models.from_config(cfg, M=M)
+    T = 4
+    xs = np.linspace(2.0, 12.0, T) if name == "c3" else np.linspace(-6, 16, T)
+    vs = 0.01 if name == "c3" else 0.002
+    states = random_states(m, N, T, seed=M + N, xs=xs, v_scale=vs)
+    ens = ensemble(cfg, T)
+    upload(ens, states)
+    g = ens.hop_probs()
+    for t in range(T):
+        ref = dyn.hop_probs(m, states[t], cfg["dt"])
+        gt = g[t, : N * m.n].reshape(N, m.n)
+        gmax = np.max(ref)
+        assert gmax > 0
+        assert np.max(np.abs(gt - ref)) <= 1e-10 * gmax, (t, np.max(np.abs(gt - ref)) / gmax)
+    ens.close()
+
+
+# ---------------------------------------------------------------------- one step
+def _compare_step(cfg, m, states, precision="fp64", tol=1e-10, step0=0):
+    T = len(states)
+    N = len(states[0].s)
+    ens = ensemble(cfg, T, precision=precision)
+    upload(ens, states)
+    if step0:
+        ens.set_step(step0)
+    ens.step()
+    x, v, Cf, occ = ens.get_state()
+    from paper_2212_00518_amd import unpack_C
+    evs, _ = ens.events()
+    n_checked = 0
+    for t in range(T):
+        xi = rng.uniform(cfg["seed"], t, step0)
+        ref, ev, _ = dyn.step(m, states[t], cfg["dt"], xi)
+        near_tie = ev["attempted"] and ev["margin"] < 1e3 * tol * max(ev["g_total"], 1e-300)
+        assert abs(x[t] - ref.x[0]) <= tol * max(1.0, abs(ref.x[0]))
+        Cg = unpack_C(Cf, t, m.n, N, ens.n_max, ens.N_max)
+        assert np.max(np.abs(Cg - ref.C)) <= tol * 10
+        if near_tie:
+            continue
+        assert list(occ[t, :N]) == list(ref.s), t
+        assert abs(v[t] - ref.v[0]) <= tol * max(1e-3, abs(ref.v[0])), (t, v[t], ref.v[0])
+        mine = [e for e in evs if e["traj"] == t]
+        if ev["attempted"]:
+            assert len(mine) == 1 and (mine[0]["a"], mine[0]["b"]) == (ev["a"], ev["b"])
+            assert mine[0]["accepted"] == ev["accepted"]
+        else:
+            assert not mine
+        n_checked += 1
+    ens.close()
+    return n_checked
+
+
+@pytest.mark.parametrize("name,M,N,vscale", [
+    ("c1", 20, 10, 0.002), ("c1", 37, 13, 0.004), ("c2", 200, 100, 0.002),
+    ("c2gl", 200, 100, 0.002), ("c3", 40, 20, 0.01), ("c1", 1, 1, 0.003),
+])
+def test_single_step_random_orbitals(name, M, N, vscale):
+    """Random orthonormal orbitals make hops likely within one step."""
+    cfg = make_cfg(name, M=M, N=N)
+    m = models.from_config(cfg, M=M)
+    T = 6
+    xs = np.linspace(2.5, 10.0, T) if name == "c3" else np.linspace(-5, 15, T)
+    states = random_states(m, N, T, seed=7 + M, xs=xs, v_scale=vscale)
+    assert _compare_step(cfg, m, states) >= T - 1
+
+
+def test_step_counter_drives_the_hop_uniform():
+    cfg = make_cfg("c1", M=20, N=10)
+    m = models.from_config(cfg)
+    states = random_states(m, 10, 5, seed=3, xs=np.linspace(-4, 8, 5), v_scale=0.003)
+    assert _compare_step(cfg, m, states, step0=123456789) >= 4
+
+
+# ------------------------------------------------------------------ trajectories
+def _hot_c1(T, Gamma=0.001, fac=200.0):
+    cfg = make_cfg("c1", Gamma=Gamma)
+    m = models.from_config(cfg)
+    x0, v0 = boltzmann_harmonic(T, 2000.0, 2e-4, cfg["kT"], seed=11, kT_factor=fac)
+    states = [dyn.initial_state(m, x0[t], v0[t], cfg["n_elec"], cfg["kT"], cfg["seed"], t)
+              for t in range(T)]
+    return cfg, m, states
+
+
+def test_trajectory_parity_with_hops():
+    """32 trajectories x 300 steps through iesh_run (graph replay): identical
+    hop events and final states, trajectories cut at their first near-tie."""
+    T, steps = 32, 300
+    cfg, m, states = _hot_c1(T)
+    ens = ensemble(cfg, T)
+    upload(ens, states)
+    ens.run(steps)
+    x, v, Cf, occ = ens.get_state()
+    evs, n_ev = ens.events()
+    from paper_2212_00518_amd import unpack_C
+    hops = 0
+    compared = 0
+    for t in range(T):
+        ref, ref_ev, _ = dyn.run(m, states[t], cfg["dt"], steps, cfg["seed"], t)
+        mine = [e for e in evs if e["traj"] == t]
+        tie = any(e["margin"] < 1e-7 * max(e["g_total"], 1e-300) for e in ref_ev)
+        if tie:
+            continue
+        assert [(e["step"], e["a"], e["b"], e["accepted"]) for e in mine] == \
+               [(e["step"], e["a"], e["b"], e["accepted"]) for e in ref_ev], t
+        hops += sum(e["accepted"] for e in ref_ev)
+        assert list(occ[t, : cfg["n_elec"]]) == list(ref.s)
+        assert abs(x[t] - ref.x[0]) <= 1e-8 * max(1.0, abs(ref.x[0]))
+        assert abs(v[t] - ref.v[0]) <= 1e-8 * max(1e-3, abs(ref.v[0]))
+        Cg = unpack_C(Cf, t, m.n, cfg["n_elec"], ens.n_max, ens.N_max)
+        assert np.max(np.abs(Cg - ref.C)) <= 1e-8
+        compared += 1
+    assert compared >= T - 2
+    assert hops >= 5
+    ens.close()
+
+
+def test_observables_records():
+    T, steps, rec = 8, 60, 20
+    cfg, m, states = _hot_c1(T)
+    from paper_2212_00518_amd import from_config
+    ens = from_config(cfg, n_traj=T, record_every=rec)
+    upload(ens, states)
+    obs = ens.run(steps, record=True)
+    assert obs.shape == (steps // rec, T, 5)
+    for t in range(T):
+        _, _, records = dyn.run(m, states[t], cfg["dt"], steps, cfg["seed"], t, record_every=rec)
+        for q, r in enumerate(records):
+            for i, key in enumerate(("Pd_surf", "Pd_wf", "Ekin", "Epot", "Etot")):
+                assert abs(obs[q, t, i] - r[key]) <= 1e-9 * max(1e-6, abs(r[key])), (q, t, key)
+    ens.close()
+
+
+def test_run_is_bitwise_deterministic():
+    T = 16
+    cfg, m, states = _hot_c1(T)
+    outs = []
+    for _ in range(2):
+        ens = ensemble(cfg, T)
+        upload(ens, states)
+        ens.run(100)
+        outs.append(ens.get_state())
+        ens.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_thermal_initialisation_matches_oracle():
+    cfg = make_cfg("c1")
+    T = 64
+    m = models.from_config(cfg)
+    x0, v0 = boltzmann_harmonic(T, 2000.0, 2e-4, cfg["kT"], seed=0)
+    ens = ensemble(cfg, T)
+    ens.init_thermal(x0, v0)
+    x, v, Cf, occ = ens.get_state()
+    from paper_2212_00518_amd import unpack_C
+    for t in range(T):
+        ref = dyn.initial_state(m, x0[t], v0[t], cfg["n_elec"], cfg["kT"], cfg["seed"], t)
+        assert list(occ[t, : cfg["n_elec"]]) == list(ref.s)
+        assert np.array_equal(unpack_C(Cf, t, m.n, cfg["n_elec"], ens.n_max, ens.N_max), ref.C)
+    ens.close()
+
+
+# ---------------------------------------------------------------------- edge cases
+def test_zero_velocity_is_a_pure_phase_and_never_hops():
+    cfg = make_cfg("c1", M=20, N=10)
+    m = models.from_config(cfg)
+    T = 4
+    states = random_states(m, 10, T, seed=5, xs=np.zeros(T), v_scale=0.0)
+    for s in states:
+        s.x[:] = 0.0  # force zero at the origin of the harmonic well
+    ens = ensemble(cfg, T)
+    upload(ens, states)
+    ens.step()
+    x, v, Cf, occ = ens.get_state()
+    from paper_2212_00518_amd import unpack_C
+    lam, _ = el.eig(m.H(np.array([0.0])))
+    for t in range(T):
+        Cg = unpack_C(Cf, t, m.n, 10, ens.n_max, ens.N_max)
+        ref = np.exp(-1j * lam * cfg["dt"])[:, None] * states[t].C
+        assert np.max(np.abs(Cg - ref)) <= 1e-12
+    assert ens.events()[1] == 0
+    ens.close()
+
+
+def test_singular_overlap_sets_status_and_skips_hop():
+    cfg = make_cfg("c1", M=20, N=10)
+    m = models.from_config(cfg)
+    states = random_states(m, 10, 2, seed=9, xs=np.array([1.0, 2.0]), v_scale=0.003)
+    a = states[0].s[3]
+    states[0].C[a, :] = 0.0  # an occupied row of S vanishes: det S = 0
+    ens = ensemble(cfg, 2)
+    upload(ens, states)
+    g = ens.hop_probs(0, 1)
+    assert np.all(g == 0.0)
+    from paper_2212_00518_amd import _lib
+    assert ens.status()[0] & _lib.TRAJ_SINGULAR_S
+    ens.close()
+
+
+# ----------------------------------------------------------------------- mixed
+@pytest.mark.parametrize("name,M,N", [("c1", 20, 10), ("c2", 200, 100)])
+def test_mixed_precision_single_step(name, M, N):
+    cfg = make_cfg(name, M=M, N=N)
+    m = models.from_config(cfg, M=M)
+    T = 4
+    states = random_states(m, N, T, seed=17, xs=np.linspace(-4, 10, T), v_scale=0.002)
+    _compare_step(cfg, m, states, precision="mixed", tol=1e-5)
