@@ -19,6 +19,8 @@
 // carries 8 orbitals as [Re of 8 | Im of 8], so the real and imaginary part
 // of an orbital sit in lanes l and l^8 of the same MFMA tile and meet through
 // one lane swap.  b_{k+1} of the slab lives in LDS (B operand).  The
+// accumulator row held by a lane differs between the FP64 (row lk + 4 r) and
+// FP32 (row 4 lk + r) 16x16x4 matrix instructions.  The
 // coupling matrix B is streamed from memory through a double-buffered LDS
 // stage of two 4-column blocks (A operand), so every wave reads it from LDS.
 // The output tiles (row tile, column tile) of the slab are dealt to the
@@ -53,6 +55,8 @@ struct PropCfg<double> {
   __device__ static inline acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  // row of accumulator element r held by lane group lk (measured on gfx950)
+  __device__ static constexpr int out_row(int lk, int r) { return lk + 4 * r; }
   __device__ static inline double* C(const ClassDev& c) { return c.C64; }
   __device__ static inline const double* B(const ClassDev& c) { return c.Bt; }
 };
@@ -65,6 +69,7 @@ struct PropCfg<float> {
   __device__ static inline acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static constexpr int out_row(int lk, int r) { return 4 * lk + r; }
   __device__ static inline float* C(const ClassDev& c) { return c.C32; }
   __device__ static inline const float* B(const ClassDev& c) { return c.Bt32; }
 };
@@ -112,7 +117,7 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int wave, int tid) {
     if (o < s.N) {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        Xq[q][r] = s.Cg[((size_t)o * s.n_pad + prow[q] * 16 + lk * 4 + r) * 2 + (is_re ? 0 : 1)];
+        Xq[q][r] = s.Cg[((size_t)o * s.n_pad + prow[q] * 16 + Cfg::out_row(lk, r)) * 2 + (is_re ? 0 : 1)];
     }
   }
 
@@ -166,7 +171,7 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int wave, int tid) {
     for (int q = 0; q < NQ; ++q) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = prow[q] * 16 + lk * 4 + r;
+        const int row = prow[q] * 16 + Cfg::out_row(lk, r);
         const T x = Xq[q][r];
         const T xp = __shfl_xor(x, 8);
         const T cx = is_re ? (cr * x - ci * xp) : (cr * x + ci * xp);
@@ -182,7 +187,7 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int wave, int tid) {
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        s.X[(prow[q] * 16 + lk * 4 + r) * s.ldx + pcol[q] * 16 + lrow] = Y[q][r];
+        s.X[(prow[q] * 16 + Cfg::out_row(lk, r)) * s.ldx + pcol[q] * 16 + lrow] = Y[q][r];
     __syncthreads();
   }
 }
