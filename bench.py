@@ -1,0 +1,250 @@
+#!/usr/bin/env python
+"""Throughput of the IESH ensemble step on one MI355X.
+
+Workload: plain IESH on the double-well Newns-Anderson model with M = 200
+bath levels (n = 201 one-electron states) and N = 100 electrons, 4096
+trajectories, dt = 20 a.u., Boltzmann-sampled positions and velocities and
+Fermi-sampled occupations (synthetic inputs, seed 0).  One step is the
+whole per-timestep update of every trajectory.
+
+Both precisions are timed: the mixed path (FP32 MFMA propagation, FP64
+eigen-solve / overlap inverse / rescaling, FP64 Loewdin every 100 steps)
+gives the headline value; the FP64 path is reported beside it with the
+deviation of the mixed path from it.  The JSON line also carries the
+roofline of the dominant kernel (the orbital propagation) and the CPU
+oracle timed on the host cores on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # MI355X dense MFMA FP64 / FP32
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_prop_flops(n, N, sum_terms):
+    # K applications of the real n x n coupling matrix to [Re C | Im C]
+    # (n x 2N) per trajectory-step: 2 * n * n * 2N flops each.
+    return 4.0 * n * n * N * sum_terms
+
+
+def traffic_from_profile(path_md, kernel_src):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel source."""
+    if not os.path.exists(path_md):
+        return None
+    text = open(path_md).read()
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if d.get("kernel_source_sha256") != sha:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_path(cfg, precision, T, steps, warmup, x0, v0):
+    import torch
+    from paper_2212_00518_amd import from_config
+
+    ens = from_config(cfg, n_traj=T, precision=precision, lowdin_every=100)
+    ens.init_thermal(x0, v0)
+    ens.run(warmup)
+    ens.sync()
+    ens.timing(True)  # per-kernel HIP events; clears the work counters
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.run(steps)
+    ens.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = ens.timing_read()
+    sum_terms, traj_steps = ens.work()
+    status = ens.status()
+    ens.timing(False)
+    ens.close()
+    n, N = cfg["bath"]["M"] + 1, cfg["n_elec"]
+    flops = algorithmic_prop_flops(n, N, sum_terms)
+    prop_ms, prop_launches = tm["prop"]
+    return dict(
+        wall_s=wall, traj_steps=traj_steps, value=traj_steps / wall, ms_per_step=1e3 * wall / steps,
+        kernels_ms={k: round(v[0] / max(v[1], 1), 4) for k, v in tm.items() if v[1]},
+        kernels_share={k: round(v[0] / (1e3 * wall), 4) for k, v in tm.items() if v[1]},
+        prop_flops_per_launch=flops / max(prop_launches, 1),
+        prop_ms_per_launch=prop_ms / max(prop_launches, 1),
+        prop_tflops=flops / (prop_ms * 1e-3) / 1e12 if prop_ms > 0 else 0.0,
+        mean_cheb_terms=sum_terms / max(traj_steps, 1),
+        frozen=int((status != 0).sum()),
+    )
+
+
+def mixed_vs_fp64(cfg, T=64, steps=500):
+    """Deviation of the mixed path from the FP64 path on the same inputs."""
+    import numpy as np
+    from paper_2212_00518_amd import from_config
+    from workloads import boltzmann_harmonic
+
+    x0, v0 = boltzmann_harmonic(T, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"],
+                                seed=cfg["seed"] + 1)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        ens = from_config(cfg, n_traj=T, precision=prec, lowdin_every=100, record_every=steps // 10)
+        ens.init_thermal(x0, v0)
+        obs = ens.run(steps, record=True)
+        evs, _ = ens.events(cap=1 << 18)
+        out[prec] = (obs, evs)
+        ens.close()
+    o64, om = out["fp64"][0], out["mixed"][0]
+    ev64 = {}
+    for e in out["fp64"][1]:
+        ev64.setdefault(e["traj"], []).append((e["step"], e["a"], e["b"], e["accepted"]))
+    evm = {}
+    for e in out["mixed"][1]:
+        evm.setdefault(e["traj"], []).append((e["step"], e["a"], e["b"], e["accepted"]))
+    same = sum(1 for t in range(T) if ev64.get(t, []) == evm.get(t, []))
+    e0 = o64[0, :, 4]
+    return dict(
+        trajectories=T, steps=steps,
+        max_abs_dPd_wf=float(np.max(np.abs(om[:, :, 1] - o64[:, :, 1]))),
+        max_abs_dPd_surf=float(np.max(np.abs(om[:, :, 0] - o64[:, :, 0]))),
+        max_rel_dEtot=float(np.max(np.abs(om[:, :, 4] - o64[:, :, 4]) / np.abs(o64[:, :, 4]))),
+        fp64_Etot_drift_rel=float(np.max(np.abs(o64[-1, :, 4] - e0) / np.abs(e0))),
+        mixed_Etot_drift_rel=float(np.max(np.abs(om[-1, :, 4] - om[0, :, 4]) / np.abs(om[0, :, 4]))),
+        identical_event_sequences=same,
+        ensemble_mean_dPd_wf=float(abs(om[-1, :, 1].mean() - o64[-1, :, 1].mean())),
+    )
+
+
+def _cpu_worker(args):
+    cfg_name, t, steps = args
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        from oracle import models, dynamics as dyn, rng
+        from workloads import get_config, boltzmann_harmonic
+        cfg = get_config(cfg_name)
+        m = models.from_config(cfg)
+        x0, v0 = boltzmann_harmonic(t + 1, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"],
+                                    seed=cfg["seed"])
+        st = dyn.initial_state(m, x0[t], v0[t], cfg["n_elec"], cfg["kT"], cfg["seed"], t)
+        F = None
+        t0 = time.perf_counter()
+        for k in range(steps):
+            st, _, F = dyn.step(m, st, cfg["dt"], rng.uniform(cfg["seed"], t, k), F)
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(cfg_name, steps_per_worker):
+    import multiprocessing as mp
+    workers = min(16, os.cpu_count() or 1)
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    os.environ["MKL_NUM_THREADS"] = "1"
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        per = pool.map(_cpu_worker, [(cfg_name, t, steps_per_worker) for t in range(workers)])
+    wall = time.perf_counter() - t0
+    total = workers * steps_per_worker
+    return dict(value=total / wall, unit="trajectory-steps/s", cores=workers, kind="oracle",
+                sample=f"{workers} trajectories x {steps_per_worker} steps of the same workload, "
+                       f"one process per trajectory, one BLAS thread each",
+                one_core_s_per_traj_step=sum(per) / total, wall_s=wall)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--n-traj", type=int, default=None)
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=300)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {a.gpus} is not supported (trajectories are "
+              f"independent; sharding across GPUs is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    from workloads import get_config, boltzmann_harmonic
+
+    cfg = get_config(a.config)
+    T = a.n_traj or cfg["n_traj"]
+    x0, v0 = boltzmann_harmonic(T, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"],
+                                seed=cfg["seed"], kT_factor=cfg.get("sample_kT_factor", 1.0))
+    precs = ["fp64", "mixed"] if a.precision == "both" else [a.precision]
+    res = {}
+    for p in precs:
+        res[p] = time_path(cfg, p, T, a.steps, a.warmup, x0, v0)
+        print(f"# {p}: {res[p]['value']:.1f} trajectory-steps/s, {res[p]['ms_per_step']:.2f} ms/step, "
+              f"kernels {res[p]['kernels_ms']} ms, propagation {res[p]['prop_tflops']:.2f} TFLOP/s",
+              file=sys.stderr, flush=True)
+    head = "mixed" if "mixed" in res else "fp64"
+    r = res[head]
+    src = os.path.join(ROOT, "paper_2212_00518_amd", "csrc", "k_prop.hip")
+    traffic = traffic_from_profile(os.path.join(ROOT, "profiles", f"k_prop_{head}_{a.config}_traffic.md"), src)
+    achieved = r["prop_tflops"]
+    line = {
+        "metric": "trajectory-steps/s (M=200,N=100) mixed vs FP64 at stated error; adjoint ms/step",
+        "value": round(r["value"], 2),
+        "unit": "trajectory-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(r["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "M": cfg["bath"]["M"], "N": cfg["n_elec"],
+                   "n_traj": T, "dt": cfg["dt"], "bath": cfg["bath"]["kind"], "path": head},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[head],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[head], 4),
+                     "traffic": traffic, "kernel": "k_prop",
+                     "flops_per_launch": r["prop_flops_per_launch"],
+                     "ms_per_launch": round(r["prop_ms_per_launch"], 4),
+                     "mean_chebyshev_terms": round(r["mean_cheb_terms"], 3)},
+        "kernels_ms_per_launch": r["kernels_ms"],
+        "kernels_time_share": r["kernels_share"],
+    }
+    if "fp64" in res and head != "fp64":
+        f = res["fp64"]
+        line["fp64"] = {"value": round(f["value"], 2), "ms_per_step": round(f["ms_per_step"], 3),
+                        "roofline": {"bound": "mfma", "achieved": round(f["prop_tflops"], 3),
+                                     "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                                     "frac": round(f["prop_tflops"] / PEAK_TFLOPS["fp64"], 4),
+                                     "ms_per_launch": round(f["prop_ms_per_launch"], 4),
+                                     "mean_chebyshev_terms": round(f["mean_cheb_terms"], 3)},
+                        "kernels_ms_per_launch": f["kernels_ms"]}
+        line["mixed_over_fp64"] = round(r["value"] / f["value"], 3)
+    if not a.no_error and "mixed" in res and "fp64" in res:
+        line["mixed_error"] = mixed_vs_fp64(cfg)
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(a.config, a.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -240,6 +240,27 @@ typedef struct iesh_sizes {
 } iesh_sizes;
 int iesh_query_sizes(const iesh_ctx* ctx, iesh_sizes* out);
 
+/* ---- measurement ------------------------------------------------------------
+   Per-kernel timing: while enabled, every kernel launched by iesh_step and
+   iesh_run is bracketed by HIP events on the context stream (iesh_run then
+   launches eagerly instead of replaying its graph).  Enabling or disabling
+   clears the accumulated times and the work counters. */
+#define IESH_TIMER_EIG 0     /* eigen-solves, couplings, Chebyshev set-up, Verlet */
+#define IESH_TIMER_PROP 1    /* orbital propagation                              */
+#define IESH_TIMER_HOP 2     /* hop probabilities, hop, rescaling, observables   */
+#define IESH_TIMER_LOWDIN 3  /* Loewdin re-orthonormalisation (mixed path)       */
+#define IESH_TIMER_FILTER 4  /* exact no-hop bound that skips the ratio kernel    */
+#define IESH_N_TIMERS 5
+int iesh_timing(iesh_ctx* ctx, int32_t enable);
+/* Milliseconds and launch counts per timer (host arrays of IESH_N_TIMERS)
+   since the last read; synchronises. */
+int iesh_timing_read(iesh_ctx* ctx, double* ms, int64_t* launches);
+/* Algorithmic work since iesh_timing was last called: the number of
+   Chebyshev terms summed over all propagated trajectory-steps (one
+   propagation of a trajectory costs 4 K n^2 N real flops for K terms) and
+   the number of trajectory-steps. */
+int iesh_work(iesh_ctx* ctx, int64_t* sum_cheb_terms, int64_t* traj_steps);
+
 /* Wait for all work on the context stream; reports asynchronous errors. */
 int iesh_sync(iesh_ctx* ctx);
 

@@ -38,7 +38,9 @@ SYMBOLS = (
     "iesh_init_thermal", "iesh_set_step", "iesh_get_step", "iesh_step", "iesh_run",
     "iesh_hop_probs", "iesh_adiabatic", "iesh_traj_status", "iesh_events",
     "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
+    "iesh_timing", "iesh_timing_read", "iesh_work",
 )
+TIMERS = ("eig", "prop", "hop", "lowdin", "filter")
 
 
 class ModelDesc(C.Structure):
@@ -100,6 +102,9 @@ def lib():
         L.iesh_last_error.argtypes = [vp]
         L.iesh_last_error.restype = C.c_char_p
         L.iesh_version.argtypes = [ip, ip, ip]
+        L.iesh_timing.argtypes = [vp, C.c_int32]
+        L.iesh_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
+        L.iesh_work.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -285,6 +290,22 @@ class Ensemble:
         return [dict(step=buf[i].step, traj=buf[i].traj, a=buf[i].a, b=buf[i].b,
                      accepted=bool(buf[i].accepted), margin=buf[i].margin,
                      g_total=buf[i].g_total) for i in range(m)], n.value
+
+    def timing(self, enable: bool):
+        self._check(lib().iesh_timing(self.ctx, 1 if enable else 0), "iesh_timing")
+
+    def timing_read(self):
+        ms = np.zeros(len(TIMERS))
+        n = np.zeros(len(TIMERS), dtype=np.int64)
+        self._check(lib().iesh_timing_read(self.ctx, ms.ctypes.data_as(C.POINTER(C.c_double)),
+                                           n.ctypes.data_as(C.POINTER(C.c_int64))),
+                    "iesh_timing_read")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(TIMERS)}
+
+    def work(self):
+        a, b = C.c_int64(), C.c_int64()
+        self._check(lib().iesh_work(self.ctx, C.byref(a), C.byref(b)), "iesh_work")
+        return a.value, b.value
 
     def clear_events(self):
         self._check(lib().iesh_clear_events(self.ctx), "iesh_clear_events")

@@ -32,6 +32,11 @@ struct iesh_ctx {
   hipGraph_t graph = nullptr;
   int graph_record = -1;
   int64_t obs_records = 0;  // capacity of the class observable buffers
+  // per-kernel timing with HIP events (diagnostic)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (timer, index of the start event)
 };
 
 namespace {
@@ -197,18 +202,40 @@ int reset_traj_words(iesh_ctx* ctx) {
 }
 
 int set_counters(iesh_ctx* ctx, int64_t run_step0, int64_t record_every) {
-  Counters h{};
-  h.step = ctx->step;
-  h.run_step0 = run_step0;
-  h.record_every = record_every;
-  // keep n_events: copy it back first
-  int64_t nev = 0;
-  HIPTRY(ctx, hipMemcpyAsync(&nev, &ctx->cnt->n_events, sizeof(int64_t), hipMemcpyDeviceToHost,
-                             ctx->stream));
+  // step, run_step0 are the first two fields; record_every the fourth
+  const int64_t head[2] = {ctx->step, run_step0};
+  HIPTRY(ctx, hipMemcpyAsync(ctx->cnt, head, sizeof(head), hipMemcpyHostToDevice, ctx->stream));
+  HIPTRY(ctx, hipMemcpyAsync(&ctx->cnt->record_every, &record_every, sizeof(int64_t),
+                             hipMemcpyHostToDevice, ctx->stream));
   HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
-  h.n_events = nev;
-  HIPTRY(ctx, hipMemcpyAsync(ctx->cnt, &h, sizeof(Counters), hipMemcpyHostToDevice, ctx->stream));
   return IESH_OK;
+}
+
+hipEvent_t next_event(iesh_ctx* ctx) {
+  if (ctx->ev_used == ctx->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->ev_pool.push_back(e);
+  }
+  return ctx->ev_pool[ctx->ev_used++];
+}
+
+// Launch `fn` bracketed by timing events when timing is on.
+template <typename F>
+hipError_t timed(iesh_ctx* ctx, int timer, F fn) {
+  if (!ctx->timing) return fn();
+  const size_t i0 = ctx->ev_used;
+  hipEvent_t a = next_event(ctx);
+  if (!a) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, ctx->stream);
+  if (e != hipSuccess) return e;
+  e = fn();
+  if (e != hipSuccess) return e;
+  hipEvent_t b = next_event(ctx);
+  if (!b) return hipErrorOutOfMemory;
+  e = hipEventRecord(b, ctx->stream);
+  ctx->ev_marks.push_back({timer, i0});
+  return e;
 }
 
 // Kernel sequence of one step for every class.
@@ -216,12 +243,21 @@ int enqueue_step(iesh_ctx* ctx, int record) {
   const iesh_run_desc& r = ctx->run;
   for (auto& c : ctx->cls) {
     if (c.n_traj == 0) continue;
-    HIPTRY(ctx, launch_eig_step(c, r.dt, ctx->stream));
-    HIPTRY(ctx, launch_prop(c, r.precision, ctx->stream));
-    HIPTRY(ctx, launch_hop(c, r.dt, r.seed, ctx->cnt, ctx->events, 0, 0, c.n_traj, record,
-                           r.exit_enabled, r.exit_x, r.max_steps, r.precision, ctx->stream));
+    hipStream_t s = ctx->stream;
+    Counters* cnt = ctx->cnt;
+    HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return launch_eig_step(c, r.dt, cnt, s); }));
+    HIPTRY(ctx, timed(ctx, IESH_TIMER_PROP, [&] { return launch_prop(c, r.precision, s); }));
+    HIPTRY(ctx, timed(ctx, IESH_TIMER_FILTER, [&] {
+             return launch_hop_filter(c, r.dt, r.seed, cnt, record, r.exit_enabled, r.exit_x,
+                                      r.max_steps, r.precision, s);
+           }));
+    HIPTRY(ctx, timed(ctx, IESH_TIMER_HOP, [&] {
+             return launch_hop(c, r.dt, r.seed, cnt, ctx->events, 0, 0, c.n_traj, record,
+                               r.exit_enabled, r.exit_x, r.max_steps, r.precision, s);
+           }));
     if (r.precision == IESH_MIXED && r.lowdin_every > 0)
-      HIPTRY(ctx, launch_lowdin(c, ctx->cnt, r.lowdin_every, c.low, ctx->stream));
+      HIPTRY(ctx, timed(ctx, IESH_TIMER_LOWDIN,
+                        [&] { return launch_lowdin(c, cnt, r.lowdin_every, c.low, s); }));
   }
   HIPTRY(ctx, launch_advance(ctx->cnt, ctx->stream));
   return IESH_OK;
@@ -250,6 +286,7 @@ int iesh_destroy(iesh_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   free_graph(ctx);
   for (void* p : ctx->allocations) (void)hipFree(p);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return IESH_OK;
@@ -332,7 +369,8 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
         (rc = dalloc(ctx, &c.lam_mid, (size_t)T * n_pad)) ||
         (rc = dalloc(ctx, &c.geo, (size_t)T * kGeoStride)) ||
         (rc = dalloc(ctx, &c.cheb, (size_t)T * kChebStride)) ||
-        (rc = dalloc(ctx, &c.gbuf, (size_t)T * N * n_pad)))
+        (rc = dalloc(ctx, &c.gbuf, (size_t)T * N * n_pad)) ||
+        (rc = dalloc(ctx, &c.hopneed, T)))
       return bail(rc);
     if (r.precision == IESH_FP64) {
       if ((rc = dalloc(ctx, &c.C64, (size_t)T * N * n_pad * 2)) ||
@@ -536,7 +574,16 @@ int iesh_run(iesh_ctx* ctx, int64_t n_steps, double* obs_out) {
   int rc = set_counters(ctx, ctx->step, record ? r.record_every : 0);
   if (rc) return rc;
   if (n_steps == 0) return IESH_OK;
-  if (ctx->graph_record != record) {
+  if (ctx->timing) {
+    // eager launches so that every kernel is bracketed by its own events
+    for (int64_t k = 0; k < n_steps; ++k) {
+      rc = enqueue_step(ctx, record);
+      if (rc) return rc;
+      ctx->step += 1;
+    }
+    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+    n_steps = 0;
+  } else if (ctx->graph_record != record) {
     free_graph(ctx);
     HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
     HIPTRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
@@ -665,6 +712,45 @@ int iesh_clear_events(iesh_ctx* ctx) {
   if (!ctx) return IESH_EINVAL;
   HIPTRY(ctx, hipMemsetAsync(&ctx->cnt->n_events, 0, sizeof(int64_t), ctx->stream));
   HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  return IESH_OK;
+}
+
+int iesh_timing(iesh_ctx* ctx, int32_t enable) {
+  if (!ctx) return IESH_EINVAL;
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->timing = enable != 0;
+  ctx->ev_used = 0;
+  ctx->ev_marks.clear();
+  const int64_t zero[2] = {0, 0};
+  HIPTRY(ctx, hipMemcpy(&ctx->cnt->sum_cheb, zero, sizeof(zero), hipMemcpyHostToDevice));
+  return IESH_OK;
+}
+
+int iesh_timing_read(iesh_ctx* ctx, double* ms, int64_t* launches) {
+  if (!ctx || !ms || !launches) return IESH_EINVAL;
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < IESH_N_TIMERS; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (const auto& m : ctx->ev_marks) {
+    float t = 0.0f;
+    HIPTRY(ctx, hipEventElapsedTime(&t, ctx->ev_pool[m.second], ctx->ev_pool[m.second + 1]));
+    ms[m.first] += t;
+    launches[m.first] += 1;
+  }
+  ctx->ev_used = 0;
+  ctx->ev_marks.clear();
+  return IESH_OK;
+}
+
+int iesh_work(iesh_ctx* ctx, int64_t* sum_cheb_terms, int64_t* traj_steps) {
+  if (!ctx || !sum_cheb_terms || !traj_steps) return IESH_EINVAL;
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  int64_t w[2];
+  HIPTRY(ctx, hipMemcpy(w, &ctx->cnt->sum_cheb, sizeof(w), hipMemcpyDeviceToHost));
+  *sum_cheb_terms = w[0];
+  *traj_steps = w[1];
   return IESH_OK;
 }
 

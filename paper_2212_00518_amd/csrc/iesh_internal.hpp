@@ -71,13 +71,16 @@ struct ClassDev {
   double* gbuf = nullptr;   // [T][N][n_pad] hop probabilities (query mode)
   double* obs = nullptr;    // [records][T][IESH_N_OBS] (class-local records)
   double2* low = nullptr;   // Loewdin scratch (mixed path)
+  int32_t* hopneed = nullptr;  // [T] 1: the determinant-ratio kernel must run
 };
 
 struct Counters {
-  int64_t step;       // global step counter (hop uniform counter)
-  int64_t run_step0;  // first step of the current iesh_run call
-  int64_t n_events;   // events recorded
+  int64_t step;          // global step counter (hop uniform counter)
+  int64_t run_step0;     // first step of the current iesh_run call
+  int64_t n_events;      // events recorded
   int64_t record_every;
+  int64_t sum_cheb;      // Chebyshev terms summed over propagated trajectory-steps
+  int64_t traj_steps;    // trajectory-steps taken
 };
 
 // -------------------------------------------------------------------------
@@ -165,7 +168,7 @@ __host__ __device__ inline ModelAt model_at(const ModelDev& md, double x) {
 
 // -------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).
-hipError_t launch_eig_step(const ClassDev& c, double dt, hipStream_t s);
+hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s);
 hipError_t launch_eig_query(const ClassDev& c, int t0, int nt, hipStream_t s);
 hipError_t launch_init_thermal(const ClassDev& c, double kT, uint64_t seed, hipStream_t s);
 hipError_t launch_forces(const ClassDev& c, hipStream_t s);
@@ -177,6 +180,9 @@ hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt
                       iesh_event* events, int query_mode, int t0, int nt, int record,
                       int exit_enabled, double exit_x, int64_t max_steps, int precision,
                       hipStream_t s);
+hipError_t launch_hop_filter(const ClassDev& c, double dt, uint64_t seed, Counters* cnt, int record,
+                             int exit_enabled, double exit_x, int64_t max_steps, int precision,
+                             hipStream_t s);
 hipError_t launch_lowdin(const ClassDev& c, const Counters* cnt, int every, double2* scratch,
                          hipStream_t s);
 size_t lowdin_scratch_elems(const ClassDev& c);

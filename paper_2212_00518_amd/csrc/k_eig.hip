@@ -337,7 +337,8 @@ __device__ void load_bath(const ClassDev& c, EigLds& L) {
 }
 
 // One step for one trajectory up to (not including) the propagation.
-__global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt, int precision) {
+__global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt, int precision,
+                                                           Counters* cnt) {
   __shared__ EigLds L;
   const int t = blockIdx.x;
   const int tid = threadIdx.x;
@@ -421,6 +422,9 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt,
       cb[CHEB_INVR] = 1.0 / rr;
       cb[CHEB_K] = (double)K;
       cb[CHEB_RHO] = rho;
+      // work counters (integer sums: independent of the order of the adds)
+      atomicAdd((unsigned long long*)&cnt->sum_cheb, (unsigned long long)K);
+      atomicAdd((unsigned long long*)&cnt->traj_steps, 1ull);
     }
   }
   __syncthreads();
@@ -559,9 +563,9 @@ __global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double
 
 }  // namespace
 
-hipError_t launch_eig_step(const ClassDev& c, double dt, hipStream_t s) {
+hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s) {
   const int precision = c.C64 ? IESH_FP64 : IESH_MIXED;
-  hipLaunchKernelGGL(k_eig_step, dim3(c.n_traj), dim3(kEigThreads), 0, s, c, dt, precision);
+  hipLaunchKernelGGL(k_eig_step, dim3(c.n_traj), dim3(kEigThreads), 0, s, c, dt, precision, cnt);
   return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
                                                      Counters* cnt, iesh_event* events,
                                                      int query_mode, int t0, int record,
                                                      int exit_enabled, double exit_x,
-                                                     int64_t max_steps) {
+                                                     int64_t max_steps, const int32_t* need) {
   __shared__ HopLds L;
   const int t = t0 + blockIdx.x;
   const int tid = threadIdx.x;
@@ -63,6 +63,7 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
   const ModelDev& md = c.md;
   const int n = md.n, n_pad = md.n_pad, N = md.N;
   if (!query_mode && (c.status[t] & kFreezeMask)) return;
+  if (need && !need[t]) return;  // the bound proved that no hop can occur
 
   for (int k = tid; k < n_pad; k += kHopThreads) {
     L.lam[k] = c.lam[(size_t)t * n_pad + k];
@@ -429,6 +430,172 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Exact hop filter.  For orbitals with orthonormal columns, S^H S =
+// I - C_U^H C_U, so sigma_min(S)^2 >= 1 - ||C_U||_F^2 - delta (delta covers the
+// orthonormality defect of the stored orbitals), and by Cauchy-Schwarz
+//   |W[b][r]| = |C_U[b, :] S^-1 e_r| <= ||C_U[b, :]|| / sigma_min(S).
+// Hence the total hop probability of the step is bounded by
+//   sum_{r, b} g <= 2 dt sum_b ||C_U[b, :]|| sum_r |v D[b][s_r]| / sigma_min(S).
+// When that bound does not exceed the step's uniform xi, no pair can be
+// selected and the step ends without a hop: the filter completes such
+// trajectories (counters, exit checks, observables) and the determinant-ratio
+// kernel runs only for the others.  No factorisation is needed for the bound:
+// it costs one pass over C and one coupling per (occupied, unoccupied) pair.
+constexpr int kFltThreads = 256;
+
+struct FltLds {
+  double lam[kMaxStates];
+  double q0[kMaxStates];
+  double rn[kMaxStates];  // ||C[b, :]||
+  double red[kFltThreads];
+  double red2[kFltThreads];
+  double zz[kMaxElec];
+  int occflag[kMaxStates];
+  int occ[kMaxElec];
+};
+
+template <bool kF32>
+__global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double dt, uint64_t seed,
+                                                            Counters* cnt, int record,
+                                                            int exit_enabled, double exit_x,
+                                                            int64_t max_steps, double delta) {
+  __shared__ FltLds L;
+  const int t = blockIdx.x;
+  const int tid = threadIdx.x;
+  const ModelDev& md = c.md;
+  const int n = md.n, n_pad = md.n_pad, N = md.N;
+  if (c.status[t] & kFreezeMask) return;
+  for (int k = tid; k < n_pad; k += kFltThreads) {
+    L.lam[k] = c.lam[(size_t)t * n_pad + k];
+    L.q0[k] = c.q0[(size_t)t * n_pad + k];
+    L.occflag[k] = 0;
+  }
+  __syncthreads();
+  for (int r = tid; r < N; r += kFltThreads) {
+    const int a = c.occ[(size_t)t * N + r];
+    L.occ[r] = a;
+    L.occflag[a] = 1;
+  }
+  __syncthreads();
+  // row norms of C (state b over all orbitals); ||C_U||_F^2 over unoccupied b
+  const size_t base = (size_t)t * N * n_pad;
+  double fro_part = 0.0;
+  for (int b = tid; b < n_pad; b += kFltThreads) {
+    double s2 = 0.0;
+    for (int j = 0; j < N; ++j) {
+      double re, im;
+      if (kF32) {
+        const float2 z = reinterpret_cast<const float2*>(c.C32)[base + (size_t)j * n_pad + b];
+        re = z.x;
+        im = z.y;
+      } else {
+        const double2 z = reinterpret_cast<const double2*>(c.C64)[base + (size_t)j * n_pad + b];
+        re = z.x;
+        im = z.y;
+      }
+      s2 += re * re + im * im;
+    }
+    L.rn[b] = sqrt(s2);
+    if (b < n && !L.occflag[b]) fro_part += s2;
+  }
+  __syncthreads();
+  // sum_b ||C_U[b]|| sum_r |v D[b][s_r]|
+  const double* geo = c.geo + (size_t)t * kGeoStride;
+  const double h = geo[GEO_H], dh = geo[GEO_DH], rho = geo[GEO_RHO];
+  const double v = c.v[t];
+  double bnd_part = 0.0;
+  for (int b = tid; b < n; b += kFltThreads) {
+    if (L.occflag[b]) continue;
+    double s = 0.0;
+    for (int r = 0; r < N; ++r) {
+      const int a = L.occ[r];
+      const double gab = L.q0[b] * L.q0[a] * (dh + rho * ((L.lam[b] - h) + (L.lam[a] - h)));
+      s += fabs(v * gab / (L.lam[a] - L.lam[b]));
+    }
+    bnd_part += L.rn[b] * s;
+  }
+  L.red[tid] = fro_part;
+  L.red2[tid] = bnd_part;
+  __syncthreads();
+  for (int st = kFltThreads / 2; st > 0; st >>= 1) {
+    if (tid < st) {
+      L.red[tid] += L.red[tid + st];
+      L.red2[tid] += L.red2[tid + st];
+    }
+    __syncthreads();
+  }
+  const double fro2 = L.red[0], S1 = L.red2[0];
+  const int64_t step = cnt->step;
+  const double xi = philox_uniform(seed, (uint32_t)c.gtraj[t], (uint64_t)step, 0u);
+  const double smin2 = 1.0 - fro2 - delta;
+  const bool no_hop = smin2 > 0.0 && (1.0 + 1e-10) * 2.0 * dt * S1 / sqrt(smin2) <= xi;
+  __syncthreads();
+  if (!no_hop) {
+    if (tid == 0) c.hopneed[t] = 1;
+    return;
+  }
+  // impurity amplitude of every orbital (observable), one wave per orbital
+  if (record) {
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int j = wv; j < N; j += kFltThreads / 64) {
+      double zr = 0.0, zi = 0.0;
+      for (int i = lane; i < n_pad; i += 64) {
+        double re, im;
+        if (kF32) {
+          const float2 z = reinterpret_cast<const float2*>(c.C32)[base + (size_t)j * n_pad + i];
+          re = z.x;
+          im = z.y;
+        } else {
+          const double2 z = reinterpret_cast<const double2*>(c.C64)[base + (size_t)j * n_pad + i];
+          re = z.x;
+          im = z.y;
+        }
+        zr += L.q0[i] * re;
+        zi += L.q0[i] * im;
+      }
+      for (int m = 32; m > 0; m >>= 1) {
+        zr += __shfl_xor(zr, m);
+        zi += __shfl_xor(zi, m);
+      }
+      if (lane == 0) L.zz[j] = zr * zr + zi * zi;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    c.hopneed[t] = 0;
+    int32_t st = c.status[t];
+    const int64_t ns = c.nsteps[t] + 1;
+    c.nsteps[t] = ns;
+    if (exit_enabled && c.x[t] > exit_x) st |= IESH_TRAJ_EXITED;
+    if (max_steps > 0 && ns >= max_steps) st |= IESH_TRAJ_STEPCAP;
+    if (!isfinite(v)) st |= IESH_TRAJ_NONFINITE;
+    c.status[t] = st;
+    if (record) {
+      const int64_t rel = step - cnt->run_step0 + 1;
+      if (cnt->record_every > 0 && rel % cnt->record_every == 0) {
+        const int64_t rec = rel / cnt->record_every - 1;
+        double pds = 0.0, elam = 0.0, pdw = 0.0;
+        for (int r = 0; r < N; ++r) {
+          const int a = L.occ[r];
+          pds += L.q0[a] * L.q0[a];
+          elam += L.lam[a];
+          pdw += L.zz[r];
+        }
+        const double ekin = 0.5 * md.mass * v * v;
+        const double epot = geo[GEO_U0] + elam;
+        double* o = c.obs + ((size_t)rec * c.n_traj + t) * IESH_N_OBS;
+        o[IESH_OBS_PD_SURF] = pds;
+        o[IESH_OBS_PD_WF] = pdw;
+        o[IESH_OBS_EKIN] = ekin;
+        o[IESH_OBS_EPOT] = epot;
+        o[IESH_OBS_ETOT] = ekin + epot;
+      }
+    }
+  }
+}
+
 __global__ void k_advance(Counters* cnt) {
   if (threadIdx.x == 0 && blockIdx.x == 0) cnt->step = cnt->step + 1;
 }
@@ -440,7 +607,8 @@ static void launch_hop_t(const ClassDev& c, dim3 grid, double dt, uint64_t seed,
                          iesh_event* events, int query_mode, int t0, int record,
                          int exit_enabled, double exit_x, int64_t max_steps, hipStream_t s) {
   hipLaunchKernelGGL((k_hop<F32, RS, CS>), grid, dim3(kHopThreads), 0, s, c, dt, seed, cnt,
-                     events, query_mode, t0, record, exit_enabled, exit_x, max_steps);
+                     events, query_mode, t0, record, exit_enabled, exit_x, max_steps,
+                     query_mode ? (const int32_t*)nullptr : (const int32_t*)c.hopneed);
 }
 
 template <bool F32, int RS>
@@ -494,6 +662,20 @@ hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt
   else
     launch_hop_p<true>(c, grid, dt, seed, cnt, events, query_mode, t0e, record, exit_enabled,
                        exit_x, max_steps, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_hop_filter(const ClassDev& c, double dt, uint64_t seed, Counters* cnt, int record,
+                             int exit_enabled, double exit_x, int64_t max_steps, int precision,
+                             hipStream_t s) {
+  // orthonormality defect allowed for the stored orbitals
+  const double delta = (precision == IESH_FP64) ? 1e-8 : 1e-3;
+  if (precision == IESH_FP64)
+    hipLaunchKernelGGL(k_hop_filter<false>, dim3(c.n_traj), dim3(kFltThreads), 0, s, c, dt, seed,
+                       cnt, record, exit_enabled, exit_x, max_steps, delta);
+  else
+    hipLaunchKernelGGL(k_hop_filter<true>, dim3(c.n_traj), dim3(kFltThreads), 0, s, c, dt, seed,
+                       cnt, record, exit_enabled, exit_x, max_steps, delta);
   return hipGetLastError();
 }
 
