@@ -260,6 +260,10 @@ int iesh_timing_read(iesh_ctx* ctx, double* ms, int64_t* launches);
    propagation of a trajectory costs 4 K n^2 N real flops for K terms) and
    the number of trajectory-steps. */
 int iesh_work(iesh_ctx* ctx, int64_t* sum_cheb_terms, int64_t* traj_steps);
+/* Trajectory-steps since iesh_timing was last called whose hop
+   probabilities had to be evaluated from the determinant ratios (the others
+   were completed by the exact no-hop bound); synchronises. */
+int iesh_hop_evals(iesh_ctx* ctx, int64_t* full_evals);
 
 /* Wait for all work on the context stream; reports asynchronous errors. */
 int iesh_sync(iesh_ctx* ctx);

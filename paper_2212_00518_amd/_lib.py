@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libiesh.so")
+# IESH_LIBRARY may point at another build of the same library (e.g. a tuning
+# variant); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("IESH_LIBRARY", os.path.join(HERE, "libiesh.so"))
 
 IESH_OK = 0
 IESH_MODEL_HARMONIC = 0
@@ -38,7 +40,7 @@ SYMBOLS = (
     "iesh_init_thermal", "iesh_set_step", "iesh_get_step", "iesh_step", "iesh_run",
     "iesh_hop_probs", "iesh_adiabatic", "iesh_traj_status", "iesh_events",
     "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
-    "iesh_timing", "iesh_timing_read", "iesh_work",
+    "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals",
 )
 TIMERS = ("eig", "prop", "hop", "lowdin", "filter")
 
@@ -105,6 +107,7 @@ def lib():
         L.iesh_timing.argtypes = [vp, C.c_int32]
         L.iesh_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
         L.iesh_work.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.iesh_hop_evals.argtypes = [vp, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -306,6 +309,11 @@ class Ensemble:
         a, b = C.c_int64(), C.c_int64()
         self._check(lib().iesh_work(self.ctx, C.byref(a), C.byref(b)), "iesh_work")
         return a.value, b.value
+
+    def hop_evals(self):
+        n = C.c_int64()
+        self._check(lib().iesh_hop_evals(self.ctx, C.byref(n)), "iesh_hop_evals")
+        return n.value
 
     def clear_events(self):
         self._check(lib().iesh_clear_events(self.ctx), "iesh_clear_events")

@@ -721,7 +721,7 @@ int iesh_timing(iesh_ctx* ctx, int32_t enable) {
   ctx->timing = enable != 0;
   ctx->ev_used = 0;
   ctx->ev_marks.clear();
-  const int64_t zero[2] = {0, 0};
+  const int64_t zero[3] = {0, 0, 0};
   HIPTRY(ctx, hipMemcpy(&ctx->cnt->sum_cheb, zero, sizeof(zero), hipMemcpyHostToDevice));
   return IESH_OK;
 }
@@ -751,6 +751,13 @@ int iesh_work(iesh_ctx* ctx, int64_t* sum_cheb_terms, int64_t* traj_steps) {
   HIPTRY(ctx, hipMemcpy(w, &ctx->cnt->sum_cheb, sizeof(w), hipMemcpyDeviceToHost));
   *sum_cheb_terms = w[0];
   *traj_steps = w[1];
+  return IESH_OK;
+}
+
+int iesh_hop_evals(iesh_ctx* ctx, int64_t* full_evals) {
+  if (!ctx || !full_evals) return IESH_EINVAL;
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  HIPTRY(ctx, hipMemcpy(full_evals, &ctx->cnt->hop_evals, sizeof(int64_t), hipMemcpyDeviceToHost));
   return IESH_OK;
 }
 

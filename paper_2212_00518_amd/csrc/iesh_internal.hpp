@@ -81,6 +81,7 @@ struct Counters {
   int64_t record_every;
   int64_t sum_cheb;      // Chebyshev terms summed over propagated trajectory-steps
   int64_t traj_steps;    // trajectory-steps taken
+  int64_t hop_evals;     // trajectory-steps that needed the determinant ratios
 };
 
 // -------------------------------------------------------------------------

@@ -42,6 +42,7 @@ struct EigLds {
   int fail;
   int count;
   double sc[16];             // scalars
+  double J[kMaxCheb];        // Bessel values J_0..J_K of the propagator
 };
 
 // f and its split derivative at tau (origin eo); terms with k < j are left
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt,
     if (K < 0) {
       atomicOr(&L.fail, 2);
     } else {
-      double J[kMaxCheb];
+      double* J = L.J;
       bessel_j(K, rho, J);
       double sn, cs;
       sincos(cc * dt, &sn, &cs);

@@ -8,15 +8,21 @@
 //     <j|psi> / <k|psi> = (C S^-1)[b][r] = W[b][r],
 // so every hop probability follows from one inverse of S:
 //     g(a -> b) = max(-2 dt v D[b][a] Re W[b][r], 0).
-// W is formed by Gauss-Jordan elimination with column pivoting applied to
-// the whole n x N orbital matrix: column operations that turn the rows of S
-// into a permutation turn the remaining rows into W (columns permuted).
+// The inverse comes from Gauss-Jordan elimination with column pivoting on S
+// alone, done in place: processing row r of S picks the unused column p of
+// largest modulus; afterwards the array X satisfies
+//     X[q][c] = (S^-1)[perm[q]][perm^-1[c]],   perm[r] = pivot column of row r,
+// so with Y = C_U[:, perm] X the ratios are W[b][r] = Y[b][perm[r]].  Only
+// Re W enters g, so Y is accumulated as a real product over the 2N real and
+// imaginary parts.
 //
 // One work-group of 512 threads per trajectory.  Thread (ti, tj), tid =
-// ti + 16 tj, owns rows ti + 16 ri and columns tj + 32 cj of the n x N
-// matrix in registers (the slot counts RS, CS are template parameters sized
-// to the problem); a row of S and the pivot column are exchanged through
-// LDS, and every wave chooses the pivot redundantly from the same LDS data.
+// ti + 16 tj, owns rows ti + 16 ri and columns tj + 32 cj of X and rows
+// ti + 16 rb (positions in the unoccupied list) and columns tj + 32 cj of Y in
+// registers (the slot counts are template parameters sized to the problem).
+// A row of X and the pivot column are exchanged through LDS, and every wave
+// chooses the pivot redundantly from the same LDS data.  Y is accumulated
+// over chunks of 16 rows of X staged in LDS with the matching orbitals of C_U.
 
 #include "iesh_internal.hpp"
 
@@ -24,21 +30,24 @@ namespace iesh {
 namespace {
 
 constexpr int kHopThreads = 512;
-constexpr int kRowLanes = 16;  // threads along the rows (states)
-constexpr int kColLanes = 32;  // threads along the columns (orbitals)
+constexpr int kRowLanes = 16;  // threads along the rows
 
 struct HopLds {
-  double2 rowbuf[2][kMaxElec];
-  double2 colbuf[2][kMaxStates];
+  double2 rowbuf[2][kMaxElec];   // row r of X (pivot search and elimination factors)
+  double2 colbuf[2][kMaxElec];   // scaled pivot column of X
+  double2 xs[16][kMaxElec];      // chunk of 16 rows of X
+  double2 cu[16][kMaxStates];    // C[u_bi][perm[q]] for the chunk's rows q
   double lam[kMaxStates];
   double q0[kMaxStates];
   double rowsum[kMaxElec];
-  double grow[kMaxStates];
+  double grow[kMaxStates];       // g of the selected row, by unoccupied position
   double zz[kMaxElec];
   int occflag[kMaxStates];
+  int uocc[kMaxStates];          // unoccupied states, ascending
   int perm[kMaxElec];
   int invperm[kMaxElec];
   int occ[kMaxElec];
+  unsigned long long wkey[2][kHopThreads / 64];  // per-wave pivot keys, by row parity
   int singular;
   int sc_occ_changed;
   double sc_xi;
@@ -49,21 +58,34 @@ __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-template <bool kF32, int kRS, int kCS>
+// Element i of orbital j of trajectory t, widened to FP64.
+template <bool kF32>
+__device__ inline double2 orb(const ClassDev& c, size_t base, int n_pad, int j, int i) {
+  if (kF32) {
+    const float2 f = reinterpret_cast<const float2*>(c.C32)[base + (size_t)j * n_pad + i];
+    return make_double2((double)f.x, (double)f.y);
+  }
+  return reinterpret_cast<const double2*>(c.C64)[base + (size_t)j * n_pad + i];
+}
+
+template <bool kF32, int kRS, int kRB>
 __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint64_t seed,
                                                      Counters* cnt, iesh_event* events,
                                                      int query_mode, int t0, int record,
                                                      int exit_enabled, double exit_x,
                                                      int64_t max_steps, const int32_t* need) {
+  constexpr int kCS = (kRS + 1) / 2;  // 32-column slots covering 16 kRS columns
   __shared__ HopLds L;
   const int t = t0 + blockIdx.x;
   const int tid = threadIdx.x;
   const int ti = tid & 15, tj = tid >> 4;
   const int lane = tid & 63;
   const ModelDev& md = c.md;
-  const int n = md.n, n_pad = md.n_pad, N = md.N;
+  const int n = md.n, n_pad = md.n_pad, N = md.N, nU = n - N;
   if (!query_mode && (c.status[t] & kFreezeMask)) return;
   if (need && !need[t]) return;  // the bound proved that no hop can occur
+  const size_t base = (size_t)t * N * n_pad;
+  if (!query_mode && tid == 0) atomicAdd((unsigned long long*)&cnt->hop_evals, 1ull);
 
   for (int k = tid; k < n_pad; k += kHopThreads) {
     L.lam[k] = c.lam[(size_t)t * n_pad + k];
@@ -77,111 +99,127 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
     L.occ[r] = a;
     L.occflag[a] = 1;
   }
+  __syncthreads();
+  // unoccupied list: b sits at position b - #{occupied < b}
+  for (int b = tid; b < n; b += kHopThreads) {
+    if (L.occflag[b]) continue;
+    int lo = 0, hi = N;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (L.occ[mid] < b)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    L.uocc[b - lo] = b;
+  }
 
-  // ---- orbitals into registers
-  double2 w[kRS][kCS];
+  // ---- impurity amplitude of every orbital, sum_i q0_i C[i][j] (observable)
+  if (record && !query_mode) {
+    const int wv = tid >> 6;
+    for (int j = wv; j < N; j += kHopThreads / 64) {
+      double zr = 0.0, zi = 0.0;
+      for (int i = lane; i < n_pad; i += 64) {
+        const double2 z = orb<kF32>(c, base, n_pad, j, i);
+        zr += L.q0[i] * z.x;
+        zi += L.q0[i] * z.y;
+      }
+      for (int m = 32; m > 0; m >>= 1) {
+        zr += __shfl_xor(zr, m);
+        zi += __shfl_xor(zi, m);
+      }
+      if (lane == 0) L.zz[j] = zr * zr + zi * zi;
+    }
+  }
+
+  // ---- S = C[s, :] into registers: x[ri][cj] = S[ti + 16 ri][tj + 32 cj]
+  double2 x[kRS][kCS];
 #pragma unroll
   for (int ri = 0; ri < kRS; ++ri) {
 #pragma unroll
     for (int cj = 0; cj < kCS; ++cj) {
       const int i = ti + 16 * ri, j = tj + 32 * cj;
-      double2 val = make_double2(0.0, 0.0);
-      if (i < n_pad && j < N) {
-        const size_t off = ((size_t)t * N + j) * n_pad + i;
-        if (kF32) {
-          const float2 f = reinterpret_cast<const float2*>(c.C32)[off];
-          val = make_double2((double)f.x, (double)f.y);
-        } else {
-          val = reinterpret_cast<const double2*>(c.C64)[off];
-        }
-      }
-      w[ri][cj] = val;
+      x[ri][cj] = (i < N && j < N) ? orb<kF32>(c, base, n_pad, j, L.occ[i]) : make_double2(0.0, 0.0);
     }
   }
   __syncthreads();
 
-  // ---- impurity amplitude of every orbital, sum_i q0_i C[i][j] (observable)
-  if (record && !query_mode) {
-#pragma unroll
-    for (int cj = 0; cj < kCS; ++cj) {
-      double zr = 0.0, zi = 0.0;
+  // ---- in-place Gauss-Jordan inversion with column pivoting
+  // The pivot of row r is the largest of keys that hold |X[r][j]|^2 in their
+  // high bits (the bit pattern of a non-negative double orders like the
+  // value) and 127 - j in the low 7 bits, so equal moduli go to the smallest
+  // column; moduli within a relative 2^-45 of each other count as equal.
+  // When the owners of row r publish it (right after their update of the
+  // previous step) each wave reduces its owners' keys to one slot.
+  static_assert(kMaxElec <= 128, "pivot keys hold 128 columns");
+  constexpr int kWaves = kHopThreads / 64;
+  unsigned used = 0u;  // bit cj: this thread's column tj + 32 cj has been a pivot
+  auto publish_row = [&](int r) {
+    const int ri0 = r >> 4, buf = r & 1;
+    unsigned long long k = 0ull;
+    if (ti == (r & 15)) {
+      // one uniform branch per register row; the empty asm keeps the stores
+      // in their branches (merged, they would need a run-time register index)
 #pragma unroll
       for (int ri = 0; ri < kRS; ++ri) {
-        const int i = ti + 16 * ri;
-        const double q = (i < n_pad) ? L.q0[i] : 0.0;
-        zr += q * w[ri][cj].x;
-        zi += q * w[ri][cj].y;
+        if (ri == ri0) {
+#pragma unroll
+          for (int cj = 0; cj < kCS; ++cj) {
+            const int j = tj + 32 * cj;
+            if (j < N) {
+              const double2 z = x[ri][cj];
+              L.rowbuf[buf][j] = z;
+              const double m = z.x * z.x + z.y * z.y;
+              if (!((used >> cj) & 1u) && m > 0.0 && m < INFINITY) {
+                const unsigned long long kj =
+                    ((unsigned long long)__double_as_longlong(m) & ~0x7Full) | (unsigned long long)(127 - j);
+                k = kj > k ? kj : k;
+              }
+            }
+          }
+          asm volatile("" ::: "memory");
+        }
       }
-      for (int m = kRowLanes / 2; m > 0; m >>= 1) {
-        zr += __shfl_xor(zr, m, kRowLanes);
-        zi += __shfl_xor(zi, m, kRowLanes);
-      }
-      const int j = tj + 32 * cj;
-      if (ti == 0 && j < N) L.zz[j] = zr * zr + zi * zi;
     }
+    // the owners of a wave are lanes l, l ^ 16, l ^ 32, l ^ 48
+    unsigned long long o = __shfl_xor(k, 16);
+    k = o > k ? o : k;
+    o = __shfl_xor(k, 32);
+    k = o > k ? o : k;
+    if (lane == (r & 15)) L.wkey[buf][tid >> 6] = k;
+  };
+  // entries of the row and column buffers past N stay zero, so the update
+  // needs no bounds selects
+  for (int e = tid; e < 2 * kMaxElec; e += kHopThreads) {
+    L.rowbuf[e / kMaxElec][e % kMaxElec] = make_double2(0.0, 0.0);
+    L.colbuf[e / kMaxElec][e % kMaxElec] = make_double2(0.0, 0.0);
   }
-
-  // ---- Gauss-Jordan elimination with column pivoting on the rows of S
-  static_assert(kMaxElec <= 128, "used-column mask holds 128 bits");
-  uint64_t used_lo = 0, used_hi = 0;
+  __syncthreads();
+  publish_row(0);
+  __syncthreads();
   for (int r = 0; r < N; ++r) {
     const int buf = r & 1;
-    const int i = L.occ[r];
-    if (ti == (i & 15)) {
-      const int ri0 = i >> 4;
+    unsigned long long kr = 0ull;
 #pragma unroll
-      for (int cj = 0; cj < kCS; ++cj) {
-        const int j = tj + 32 * cj;
-        if (j < N) {
-          double2 val = w[0][cj];
-#pragma unroll
-          for (int ri = 1; ri < kRS; ++ri)
-            if (ri == ri0) val = w[ri][cj];
-          L.rowbuf[buf][j] = val;
-        }
-      }
+    for (int w = 0; w < kWaves; ++w) {
+      const unsigned long long kw = L.wkey[buf][w];
+      kr = kw > kr ? kw : kr;
     }
-    __syncthreads();
-    // pivot: largest |S[r][j]| over unused columns, ties to the smallest j
-    double best = -1.0;
-    int bidx = 0x7fffffff;
-#pragma unroll
-    for (int h = 0; h < (kMaxElec + 63) / 64; ++h) {
-      const int j = lane + 64 * h;
-      const bool used_j = (j < 64) ? ((used_lo >> j) & 1ull) : ((used_hi >> (j - 64)) & 1ull);
-      if (j < N && !used_j) {
-        const double2 z = L.rowbuf[buf][j];
-        const double m = z.x * z.x + z.y * z.y;
-        if (m > best || (m == best && j < bidx)) {
-          best = m;
-          bidx = j;
-        }
-      }
-    }
-    for (int m = 32; m > 0; m >>= 1) {
-      const double ob = __shfl_xor(best, m);
-      const int oi = __shfl_xor(bidx, m);
-      if (ob > best || (ob == best && oi < bidx)) {
-        best = ob;
-        bidx = oi;
-      }
-    }
-    // A zero pivot (singular S) turns the remaining steps into no-ops; every
-    // wave sees the same data, so the decision is uniform.
-    const bool bad = !(best > 0.0) || bidx >= N;
-    if (bad && tid == 0) L.singular = 1;
-    const int p = bad ? 0 : bidx;
-    if (!bad) {
-      if (p < 64)
-        used_lo |= 1ull << p;
-      else
-        used_hi |= 1ull << (p - 64);
-    }
+    // no finite nonzero candidate (singular S): the remaining steps are
+    // no-ops; the decision is uniform
+    const bool bad = (kr == 0ull);
+    const int p = bad ? 0 : 127 - (int)(kr & 0x7Full);
+    if (!bad && tj == (p & 31)) used |= 1u << (p >> 5);
     const double2 piv = L.rowbuf[buf][p];
+    const double best = piv.x * piv.x + piv.y * piv.y;
     const double inv_m = bad ? 0.0 : 1.0 / best;
-    const double2 pinv = make_double2(piv.x * inv_m, -piv.y * inv_m);
-    if (tid == 0) L.perm[r] = p;
-    // owners of column p publish the scaled pivot column (read-only here)
+    const double2 pinv = make_double2(piv.x * inv_m, -piv.y * inv_m);  // 1 / piv
+    if (tid == 0) {
+      L.perm[r] = p;
+      if (bad) L.singular = 1;
+    }
+    // owners of column p publish it scaled by 1/piv, with 1/piv in row r
+    // (before row r is cleared below)
     if (!bad && tj == (p & 31)) {
       const int cj0 = p >> 5;
 #pragma unroll
@@ -190,38 +228,97 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
 #pragma unroll
           for (int ri = 0; ri < kRS; ++ri) {
             const int ii = ti + 16 * ri;
-            if (ii < n_pad) L.colbuf[buf][ii] = cmul(w[ri][cj], pinv);
+            if (ii < N) L.colbuf[buf][ii] = (ii == r) ? pinv : cmul(x[ri][cj], pinv);
+          }
+          asm volatile("" ::: "memory");
+        }
+      }
+    }
+    // row r is cleared by its owners (the update then leaves -X[r][j] / piv
+    // in it)
+    if (!bad && ti == (r & 15)) {
+      const int ri0 = r >> 4;
+#pragma unroll
+      for (int ri = 0; ri < kRS; ++ri)
+        if (ri == ri0)
+#pragma unroll
+          for (int cj = 0; cj < kCS; ++cj) x[ri][cj] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    // every column j: X[:, j] -= X[r][j] * (published column); column p is
+    // then replaced by the published column itself
+    if (!bad) {  // uniform
+      double2 rb[kCS];
+#pragma unroll
+      for (int cj = 0; cj < kCS; ++cj) rb[cj] = L.rowbuf[buf][tj + 32 * cj];
+#pragma unroll
+      for (int ri = 0; ri < kRS; ++ri) {
+        const double2 cbv = L.colbuf[buf][ti + 16 * ri];
+#pragma unroll
+        for (int cj = 0; cj < kCS; ++cj) {
+          x[ri][cj].x = fma(-rb[cj].x, cbv.x, x[ri][cj].x);
+          x[ri][cj].x = fma(rb[cj].y, cbv.y, x[ri][cj].x);
+          x[ri][cj].y = fma(-rb[cj].x, cbv.y, x[ri][cj].y);
+          x[ri][cj].y = fma(-rb[cj].y, cbv.x, x[ri][cj].y);
+        }
+      }
+    }
+    if (!bad && tj == (p & 31)) {
+      const int cj0 = p >> 5;
+#pragma unroll
+      for (int cj = 0; cj < kCS; ++cj) {
+        if (cj == cj0) {
+#pragma unroll
+          for (int ri = 0; ri < kRS; ++ri) {
+            const int ii = ti + 16 * ri;
+            if (ii < N) x[ri][cj] = L.colbuf[buf][ii];
           }
         }
       }
     }
+    if (r + 1 < N) publish_row(r + 1);
     __syncthreads();
-    // every element: column p becomes the scaled pivot column, the others
-    // lose their component along it (branch-free on the register matrix)
-    double2 rb[kCS];
-    bool isp[kCS];
-#pragma unroll
-    for (int cj = 0; cj < kCS; ++cj) {
-      const int j = tj + 32 * cj;
-      isp[cj] = !bad && (j == p);
-      rb[cj] = (!bad && j < N) ? L.rowbuf[buf][j] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int ri = 0; ri < kRS; ++ri) {
-      const int ii = ti + 16 * ri;
-      const double2 cbv = (!bad && ii < n_pad) ? L.colbuf[buf][ii] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int cj = 0; cj < kCS; ++cj) {
-        const double2 pr = cmul(rb[cj], cbv);
-        const double2 upd = make_double2(w[ri][cj].x - pr.x, w[ri][cj].y - pr.y);
-        w[ri][cj] = isp[cj] ? cbv : upd;
-      }
-    }
   }
   __syncthreads();
   const bool singular = L.singular != 0;
   if (!singular) {
     for (int r = tid; r < N; r += kHopThreads) L.invperm[L.perm[r]] = r;
+  }
+
+  // ---- Y[bi][c] = Re sum_q C[u_bi][perm[q]] X[q][c], chunks of 16 rows q
+  double y[kRB][kCS];
+#pragma unroll
+  for (int rb = 0; rb < kRB; ++rb)
+#pragma unroll
+    for (int cj = 0; cj < kCS; ++cj) y[rb][cj] = 0.0;
+#pragma unroll
+  for (int ri = 0; ri < kRS; ++ri) {
+    if (16 * ri < N) {  // uniform
+      __syncthreads();  // the previous chunk has been consumed
+#pragma unroll
+      for (int cj = 0; cj < kCS; ++cj) {
+        const int j = tj + 32 * cj;
+        if (j < N) L.xs[ti][j] = x[ri][cj];
+      }
+      const int nq = min(16, N - 16 * ri);
+      for (int e = tid; e < nq * nU; e += kHopThreads) {
+        const int qq = e / nU, bi = e - qq * nU;
+        L.cu[qq][bi] = orb<kF32>(c, base, n_pad, L.perm[16 * ri + qq], L.uocc[bi]);
+      }
+      __syncthreads();
+      for (int qq = 0; qq < nq; ++qq) {
+        double2 xv[kCS];
+#pragma unroll
+        for (int cj = 0; cj < kCS; ++cj) xv[cj] = L.xs[qq][tj + 32 * cj];
+#pragma unroll
+        for (int rb = 0; rb < kRB; ++rb) {
+          const int bi = ti + 16 * rb;
+          const double2 cv = (bi < nU) ? L.cu[qq][bi] : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int cj = 0; cj < kCS; ++cj) y[rb][cj] += cv.x * xv[cj].x - cv.y * xv[cj].y;
+        }
+      }
+    }
   }
   __syncthreads();
 
@@ -229,24 +326,29 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
   const double h = geo[GEO_H], dh = geo[GEO_DH], rho = geo[GEO_RHO];
   const double v = c.v[t];
 
-  // ---- hop probabilities, formed on the fly from the owned elements
-  auto gval = [&](int ri, int cj) -> double {
-    const int bb = ti + 16 * ri, j = tj + 32 * cj;
-    if (singular || bb >= n || j >= N || L.occflag[bb]) return 0.0;
+  // ---- hop probabilities, formed on the fly from the owned elements of Y
+  auto gval = [&](int rb, int cj) -> double {
+    const int bi = ti + 16 * rb, j = tj + 32 * cj;
+    if (singular || bi >= nU || j >= N) return 0.0;
+    const int bb = L.uocc[bi];
     const int a = L.occ[L.invperm[j]];
     const double gab = L.q0[bb] * L.q0[a] * (dh + rho * ((L.lam[bb] - h) + (L.lam[a] - h)));
     const double vD = v * gab / (L.lam[a] - L.lam[bb]);  // v <b|d/dx a>
-    return fmax(-2.0 * dt * vD * w[ri][cj].x, 0.0);
+    return fmax(-2.0 * dt * vD * y[rb][cj], 0.0);
   };
 
   if (query_mode) {
     double* go = c.gbuf + (size_t)t * N * n_pad;
+    for (int e = tid; e < N * n_pad; e += kHopThreads) go[e] = 0.0;
+    __syncthreads();
+    if (!singular) {
 #pragma unroll
-    for (int ri = 0; ri < kRS; ++ri) {
+      for (int rb = 0; rb < kRB; ++rb) {
 #pragma unroll
-      for (int cj = 0; cj < kCS; ++cj) {
-        const int bb = ti + 16 * ri, j = tj + 32 * cj;
-        if (bb < n_pad && j < N) go[(size_t)(singular ? j : L.invperm[j]) * n_pad + bb] = gval(ri, cj);
+        for (int cj = 0; cj < kCS; ++cj) {
+          const int bi = ti + 16 * rb, j = tj + 32 * cj;
+          if (bi < nU && j < N) go[(size_t)L.invperm[j] * n_pad + L.uocc[bi]] = gval(rb, cj);
+        }
       }
     }
     if (singular && tid == 0) c.status[t] |= IESH_TRAJ_SINGULAR_S;
@@ -258,7 +360,7 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
   for (int cj = 0; cj < kCS; ++cj) {
     double s = 0.0;
 #pragma unroll
-    for (int ri = 0; ri < kRS; ++ri) s += gval(ri, cj);
+    for (int rb = 0; rb < kRB; ++rb) s += gval(rb, cj);
     for (int m = kRowLanes / 2; m > 0; m >>= 1) s += __shfl_xor(s, m, kRowLanes);
     const int j = tj + 32 * cj;
     if (ti == 0 && j < N && !singular) L.rowsum[L.invperm[j]] = s;
@@ -266,7 +368,7 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
   __syncthreads();
 
   const int64_t step = cnt->step;
-  __shared__ int sel_r, sel_cidx;
+  __shared__ int sel_r;
   __shared__ double sel_prev, sel_margin, sel_total;
   if (tid == 0) {
     sel_r = -1;
@@ -299,13 +401,16 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
     if (tj == (csel & 31)) {
       const int cj0 = csel >> 5;
 #pragma unroll
-      for (int cj = 0; cj < kCS; ++cj)
-        if (cj == cj0)
+      for (int cj = 0; cj < kCS; ++cj) {
+        if (cj == cj0) {
 #pragma unroll
-          for (int ri = 0; ri < kRS; ++ri) {
-            const int bb = ti + 16 * ri;
-            if (bb < n_pad) L.grow[bb] = gval(ri, cj);
+          for (int rb = 0; rb < kRB; ++rb) {
+            const int bi = ti + 16 * rb;
+            if (bi < nU) L.grow[bi] = gval(rb, cj);
           }
+          asm volatile("" ::: "memory");
+        }
+      }
     }
   }
   __syncthreads();
@@ -319,20 +424,20 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
       const double xi = L.sc_xi;
       double acc = sel_prev, margin = sel_margin;
       int bsel = -1;
-      for (int bb = 0; bb < n; ++bb) {
-        const double g = L.grow[bb];
+      for (int bi = 0; bi < nU; ++bi) {  // b ascending over the unoccupied states
+        const double g = L.grow[bi];
         if (g == 0.0) continue;
         acc = acc + g;
         margin = fmin(margin, fabs(acc - xi));
         if (acc > xi) {
-          bsel = bb;
+          bsel = L.uocc[bi];
           break;
         }
       }
       if (bsel < 0) {
-        for (int bb = n - 1; bb >= 0; --bb)
-          if (L.grow[bb] > 0.0) {
-            bsel = bb;
+        for (int bi = nU - 1; bi >= 0; --bi)
+          if (L.grow[bi] > 0.0) {
+            bsel = L.uocc[bi];
             break;
           }
         margin = 0.0;
@@ -602,52 +707,57 @@ __global__ void k_advance(Counters* cnt) {
 
 }  // namespace
 
-template <bool F32, int RS, int CS>
+template <bool F32, int RS, int RB>
 static void launch_hop_t(const ClassDev& c, dim3 grid, double dt, uint64_t seed, Counters* cnt,
                          iesh_event* events, int query_mode, int t0, int record,
                          int exit_enabled, double exit_x, int64_t max_steps, hipStream_t s) {
-  hipLaunchKernelGGL((k_hop<F32, RS, CS>), grid, dim3(kHopThreads), 0, s, c, dt, seed, cnt,
+  hipLaunchKernelGGL((k_hop<F32, RS, RB>), grid, dim3(kHopThreads), 0, s, c, dt, seed, cnt,
                      events, query_mode, t0, record, exit_enabled, exit_x, max_steps,
                      query_mode ? (const int32_t*)nullptr : (const int32_t*)c.hopneed);
 }
 
+// Register slots: RS rows of 16 for the N x N inverse, RB rows of 16 for the
+// n - N unoccupied states.
 template <bool F32, int RS>
 static void launch_hop_rs(const ClassDev& c, dim3 grid, double dt, uint64_t seed,
                           Counters* cnt, iesh_event* events, int query_mode, int t0,
                           int record, int exit_enabled, double exit_x, int64_t max_steps,
                           hipStream_t s) {
-  const int N = c.md.N;
-  if (N <= 32)
-    launch_hop_t<F32, RS, 1>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
-                             exit_enabled, exit_x, max_steps, s);
-  else if (N <= 64)
+  const int rb = (c.md.n - c.md.N + 15) / 16;
+  if (rb <= 2)
     launch_hop_t<F32, RS, 2>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
                              exit_enabled, exit_x, max_steps, s);
-  else
+  else if (rb <= 4)
     launch_hop_t<F32, RS, 4>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
                              exit_enabled, exit_x, max_steps, s);
+  else if (rb <= 7)
+    launch_hop_t<F32, RS, 7>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
+                             exit_enabled, exit_x, max_steps, s);
+  else if (rb <= 10)
+    launch_hop_t<F32, RS, 10>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
+                              exit_enabled, exit_x, max_steps, s);
+  else
+    launch_hop_t<F32, RS, 14>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
+                              exit_enabled, exit_x, max_steps, s);
 }
 
 template <bool F32>
 static void launch_hop_p(const ClassDev& c, dim3 grid, double dt, uint64_t seed, Counters* cnt,
                          iesh_event* events, int query_mode, int t0, int record,
                          int exit_enabled, double exit_x, int64_t max_steps, hipStream_t s) {
-  const int rs = c.md.n_pad / kRowLanes;
+  const int rs = (c.md.N + 15) / 16;
   if (rs <= 2)
     launch_hop_rs<F32, 2>(c, grid, dt, seed, cnt, events, query_mode, t0, record, exit_enabled,
                           exit_x, max_steps, s);
   else if (rs <= 4)
     launch_hop_rs<F32, 4>(c, grid, dt, seed, cnt, events, query_mode, t0, record, exit_enabled,
                           exit_x, max_steps, s);
-  else if (rs <= 8)
+  else if (rs <= 7)
+    launch_hop_rs<F32, 7>(c, grid, dt, seed, cnt, events, query_mode, t0, record, exit_enabled,
+                          exit_x, max_steps, s);
+  else
     launch_hop_rs<F32, 8>(c, grid, dt, seed, cnt, events, query_mode, t0, record, exit_enabled,
                           exit_x, max_steps, s);
-  else if (rs <= 13)
-    launch_hop_rs<F32, 13>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
-                           exit_enabled, exit_x, max_steps, s);
-  else
-    launch_hop_rs<F32, 14>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
-                           exit_enabled, exit_x, max_steps, s);
 }
 
 hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt,

@@ -38,8 +38,7 @@ namespace {
 
 constexpr int kPropWaves = 8;
 constexpr int kPropThreads = kPropWaves * 64;
-constexpr int kStageKB = 2;  // k-blocks (of 4 columns of B) per LDS stage
-constexpr int kPre = (kStageKB * (kMaxStates / 16) * 64 + kPropThreads - 1) / kPropThreads;
+constexpr int kDepth = 2;  // k-blocks of A operands in flight per wave (divides n_pad / 4)
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -74,22 +73,45 @@ struct PropCfg<float> {
   __device__ static inline const float* B(const ClassDev& c) { return c.Bt32; }
 };
 
+// One element per lane of an A-operand fragment through a buffer resource.
+template <typename T>
+__device__ inline T load_frag(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ inline double load_frag<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ inline float load_frag<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// Row stride (elements) of the LDS slab: 16 nct, plus 16 when nct is even, so
+// the stride is 16 mod 32 elements.  The rows of one 16x16x4 B operand then
+// start 32 (FP64) or 16 (FP32) four-byte words apart modulo 64 and a read
+// serves its lanes from disjoint banks.
+__host__ __device__ constexpr int slab_ld(int nct) { return 16 * nct + ((nct & 1) ? 0 : 16); }
+
 // Geometry of one work-group's slab, shared by all waves.
 template <typename T>
 struct Slab {
-  T* X;         // LDS [n_pad][ldx]: b_{k+1}, finally the result
+  T* X0;        // LDS [n_pad][ldx]: b_j for even j, finally the result
+  T* X1;        // LDS [n_pad][ldx]: b_j for odd j
   T* lam;       // LDS [n_pad]: lambda - c
-  T* stage;     // LDS 2 x [kStageKB][RT][64]
   const T* Bt;  // memory [KB][RT][64]
   const T* Cg;  // memory [N][n_pad] complex: the input orbitals
   const double* cb;
-  int n_pad, N, RT, KB, ldx, tile0, nct, stage_elems, n_stages, K;
+  int n_pad, N, RT, KB, ldx, tile0, nct, K;
   T invr;
 };
 
-// The Clenshaw loop for a wave that owns NQ output tiles.
+// The Clenshaw loop for a wave that owns NQ output tiles: the contiguous
+// range [t0, t0 + NQ) of the slab's tiles in row-major order, so
+// consecutive tiles mostly share their row tile of B (repeated fragment
+// loads of a wave hit the L1 cache).  Each wave streams its A operands
+// (fragments of B) from memory itself, kDepth k-blocks ahead.  The k-block
+// loop has no barriers; b_{k+1} is read from LDS.
 template <typename T, int NQ>
-__device__ void clenshaw_tiles(const Slab<T>& s, int wave, int tid) {
+__device__ void clenshaw_tiles(const Slab<T>& s, int t0, int tid) {
   typedef PropCfg<T> Cfg;
   typedef typename Cfg::acc_t acc_t;
   constexpr int NQ1 = NQ > 0 ? NQ : 1;
@@ -99,18 +121,14 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int wave, int tid) {
   const bool is_re = lrow < 8;
   int prow[NQ1], pcol[NQ1];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int p = wave + kPropWaves * q;
+  for (int q = 0; q < NQ1; ++q) {
+    const int p = t0 + q;
     prow[q] = p / s.nct;
     pcol[q] = p - prow[q] * s.nct;
   }
-  acc_t Bq[NQ1];  // b_{k+2}
   acc_t Xq[NQ1];  // this lane's component of the input X
 #pragma unroll
-  for (int q = 0; q < NQ1; ++q) {
-    Bq[q] = acc_t{0, 0, 0, 0};
-    Xq[q] = acc_t{0, 0, 0, 0};
-  }
+  for (int q = 0; q < NQ1; ++q) Xq[q] = acc_t{0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int o = s.tile0 * 8 + pcol[q] * 8 + (lrow & 7);
@@ -120,47 +138,54 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int wave, int tid) {
         Xq[q][r] = s.Cg[((size_t)o * s.n_pad + prow[q] * 16 + Cfg::out_row(lk, r)) * 2 + (is_re ? 0 : 1)];
     }
   }
+  // A operands through a buffer resource over this trajectory's B: the lane
+  // offset is the only per-lane address, the block offset is scalar.
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)s.Bt, (short)0, (int)(sizeof(T) * s.n_pad * s.n_pad), 0x00020000);
+  const unsigned voff = lane * sizeof(T);
+  const unsigned kb_bytes = s.RT * 64 * sizeof(T);
+  unsigned roff[NQ1];
+#pragma unroll
+  for (int q = 0; q < NQ1; ++q) roff[q] = __builtin_amdgcn_readfirstlane(prow[q] * 64 * (int)sizeof(T));
 
   for (int k = s.K - 1; k >= 0; --k) {
     acc_t Y[NQ1];
 #pragma unroll
     for (int q = 0; q < NQ1; ++q) Y[q] = acc_t{0, 0, 0, 0};
 
-    // Y = B b_{k+1}, B streamed through two LDS stages
-    for (int e = tid; e < s.stage_elems; e += kPropThreads)
-      s.stage[e] = (e / (s.RT * 64) < s.KB) ? s.Bt[e] : (T)0;
-    __syncthreads();
-    for (int st = 0; st < s.n_stages; ++st) {
-      T pre[kPre];
-      const bool more = st + 1 < s.n_stages;
+    const T* b1buf = (k & 1) ? s.X0 : s.X1;
+    T* b2buf = (k & 1) ? s.X1 : s.X0;  // holds b_{k+2}, receives b_k
+
+    // Y = B b_{k+1}: A fragments from memory through a ring of kDepth
+    // k-blocks in registers, B operands from LDS one k-block ahead.  Indices
+    // past the last k-block are clamped (harmless reloads), so the loop body
+    // has no branches.
+    T a[kDepth][NQ1];
+    T xv[2][NQ1];
+    // issue order = order of use, so the waits at the loop head stay partial
 #pragma unroll
-      for (int u = 0; u < kPre; ++u) {
-        const int e = tid + u * kPropThreads;
-        const int kb_abs = (st + 1) * kStageKB + e / (s.RT * 64);
-        pre[u] = (more && e < s.stage_elems && kb_abs < s.KB)
-                     ? s.Bt[(size_t)(st + 1) * s.stage_elems + e]
-                     : (T)0;
+    for (int d = 0; d < kDepth; ++d)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        a[d][q] = load_frag<T>(rsrc, voff, d * kb_bytes + roff[q]);
+        __builtin_amdgcn_sched_barrier(0);
       }
-      const T* sb = s.stage + (st & 1) * s.stage_elems;
 #pragma unroll
-      for (int kk = 0; kk < kStageKB; ++kk) {
-        const int kb = st * kStageKB + kk;
-        if (kb < s.KB) {  // uniform
-          const T* xrow = s.X + (kb * 4 + lk) * s.ldx + lrow;
-          const T* arow = sb + kk * s.RT * 64 + lane;
+    for (int q = 0; q < NQ; ++q) xv[0][q] = b1buf[lk * s.ldx + pcol[q] * 16 + lrow];
+    for (int kb0 = 0; kb0 < s.KB; kb0 += kDepth) {
 #pragma unroll
-          for (int q = 0; q < NQ; ++q) Y[q] = Cfg::mma(arow[prow[q] << 6], xrow[pcol[q] * 16], Y[q]);
-        }
+      for (int d = 0; d < kDepth; ++d) {
+        const int kb = kb0 + d;
+        const int kx = min(kb + 1, s.KB - 1);
+        const T* xrow = b1buf + (kx * 4 + lk) * s.ldx + lrow;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) xv[(d + 1) & 1][q] = xrow[pcol[q] * 16];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) Y[q] = Cfg::mma(a[d][q], xv[d & 1][q], Y[q]);
+        const unsigned kn = (unsigned)min(kb + kDepth, s.KB - 1) * kb_bytes;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a[d][q] = load_frag<T>(rsrc, voff, kn + roff[q]);
       }
-      if (more) {
-        T* nb = s.stage + ((st + 1) & 1) * s.stage_elems;
-#pragma unroll
-        for (int u = 0; u < kPre; ++u) {
-          const int e = tid + u * kPropThreads;
-          if (e < s.stage_elems) nb[e] = pre[u];
-        }
-      }
-      __syncthreads();
     }
 
     // b_k = c_k X + 2 At b_{k+1} - b_{k+2}   (k >= 1)
@@ -175,19 +200,15 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int wave, int tid) {
         const T x = Xq[q][r];
         const T xp = __shfl_xor(x, 8);
         const T cx = is_re ? (cr * x - ci * xp) : (cr * x + ci * xp);
-        const T b1 = s.X[row * s.ldx + pcol[q] * 16 + lrow];
+        const int e = row * s.ldx + pcol[q] * 16 + lrow;
+        const T b1 = b1buf[e];
         const T yp = __shfl_xor(Y[q][r], 8);
         const T atb = s.lam[row] * b1 + (is_re ? yp : -yp);
-        Y[q][r] = cx + scale * atb - Bq[q][r];  // b_k, stored after the barrier
-        Bq[q][r] = b1;
+        // b_k replaces b_{k+2}: the element belongs to this lane alone
+        b2buf[e] = cx + scale * atb - b2buf[e];
       }
     }
-    __syncthreads();  // every wave has read b_{k+1}
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        s.X[(prow[q] * 16 + Cfg::out_row(lk, r)) * s.ldx + pcol[q] * 16 + lrow] = Y[q][r];
+    // b_k complete before anyone reads it; b_{k+1} free to be overwritten
     __syncthreads();
   }
 }
@@ -216,12 +237,10 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c) {
   const int base = tiles_total / c.n_slabs, rem = tiles_total % c.n_slabs;
   s.tile0 = slab * base + (slab < rem ? slab : rem);
   s.nct = base + (slab < rem ? 1 : 0);
-  s.ldx = 16 * s.nct + 2;
-  s.X = reinterpret_cast<T*>(smem_raw);
-  s.lam = s.X + (size_t)s.n_pad * s.ldx;
-  s.stage = s.lam + s.n_pad;
-  s.stage_elems = kStageKB * s.RT * 64;
-  s.n_stages = (s.KB + kStageKB - 1) / kStageKB;
+  s.ldx = slab_ld(s.nct);
+  s.X0 = reinterpret_cast<T*>(smem_raw);
+  s.X1 = s.X0 + (size_t)s.n_pad * s.ldx;
+  s.lam = s.X1 + (size_t)s.n_pad * s.ldx;
   s.Bt = Cfg::B(c) + (size_t)t * s.n_pad * s.n_pad;
   T* Cg = Cfg::C(c) + (size_t)t * s.N * s.n_pad * 2;
   s.Cg = Cg;
@@ -234,9 +253,13 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c) {
   for (int i = tid; i < s.n_pad; i += kPropThreads)
     s.lam[i] = (T)c.lam_mid[(size_t)t * s.n_pad + i] - cc;
 
-  // b_K = c_K X into LDS: X[i][lt*16 + (o&7)] = Re, X[i][lt*16 + 8 + (o&7)] = Im
+  // b_K = c_K X into the buffer of its parity: row i, column
+  // lt*16 + (o&7) = Re, lt*16 + 8 + (o&7) = Im; b_{K+1} = 0 into the other
   const int n_orb = s.nct * 8;
   {
+    T* bk = (s.K & 1) ? s.X1 : s.X0;
+    T* bk1 = (s.K & 1) ? s.X0 : s.X1;
+    for (int idx = tid; idx < s.n_pad * s.ldx; idx += kPropThreads) bk1[idx] = (T)0;
     const T cr = (T)s.cb[CHEB_COEF + 2 * s.K], ci = (T)s.cb[CHEB_COEF + 2 * s.K + 1];
     for (int idx = tid; idx < n_orb * s.n_pad; idx += kPropThreads) {
       const int ol = idx / s.n_pad, i = idx - ol * s.n_pad;
@@ -247,27 +270,30 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c) {
         im = Cg[((size_t)o * s.n_pad + i) * 2 + 1];
       }
       const int col = (ol >> 3) * 16 + (ol & 7);
-      s.X[i * s.ldx + col] = cr * re - ci * im;
-      s.X[i * s.ldx + col + 8] = cr * im + ci * re;
+      bk[i * s.ldx + col] = cr * re - ci * im;
+      bk[i * s.ldx + col + 8] = cr * im + ci * re;
     }
   }
   __syncthreads();
 
-  // tiles p = wave + 8 q, q < nq; dispatch on the (wave-uniform) count
+  // tiles [t0, t0 + nq) of the P row-major tiles; dispatch on the
+  // (wave-uniform) count
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int P = s.RT * s.nct;
-  const int nq = (P > wave) ? (P - wave + kPropWaves - 1) / kPropWaves : 0;
+  const int base_q = P / kPropWaves, rem_q = P % kPropWaves;
+  const int nq = base_q + (wave < rem_q ? 1 : 0);
+  const int t0 = wave * base_q + (wave < rem_q ? wave : rem_q);
   switch (nq) {
-    case 0: clenshaw_tiles<T, 0>(s, wave, tid); break;
-    case 1: clenshaw_tiles<T, 1>(s, wave, tid); break;
-    case 2: clenshaw_tiles<T, 2>(s, wave, tid); break;
-    case 3: clenshaw_tiles<T, 3>(s, wave, tid); break;
-    case 4: clenshaw_tiles<T, 4>(s, wave, tid); break;
-    case 5: clenshaw_tiles<T, 5>(s, wave, tid); break;
-    case 6: clenshaw_tiles<T, 6>(s, wave, tid); break;
-    case 7: if constexpr (Cfg::kMaxPairs >= 7) clenshaw_tiles<T, 7>(s, wave, tid); break;
-    case 8: if constexpr (Cfg::kMaxPairs >= 8) clenshaw_tiles<T, 8>(s, wave, tid); break;
-    default: if constexpr (Cfg::kMaxPairs >= 9) clenshaw_tiles<T, 9>(s, wave, tid); break;
+    case 0: clenshaw_tiles<T, 0>(s, t0, tid); break;
+    case 1: clenshaw_tiles<T, 1>(s, t0, tid); break;
+    case 2: clenshaw_tiles<T, 2>(s, t0, tid); break;
+    case 3: clenshaw_tiles<T, 3>(s, t0, tid); break;
+    case 4: clenshaw_tiles<T, 4>(s, t0, tid); break;
+    case 5: clenshaw_tiles<T, 5>(s, t0, tid); break;
+    case 6: clenshaw_tiles<T, 6>(s, t0, tid); break;
+    case 7: if constexpr (Cfg::kMaxPairs >= 7) clenshaw_tiles<T, 7>(s, t0, tid); break;
+    case 8: if constexpr (Cfg::kMaxPairs >= 8) clenshaw_tiles<T, 8>(s, t0, tid); break;
+    default: if constexpr (Cfg::kMaxPairs >= 9) clenshaw_tiles<T, 9>(s, t0, tid); break;
   }
 
   // result (in LDS) to memory, coalesced
@@ -276,16 +302,18 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c) {
     const int o = s.tile0 * 8 + ol;
     if (o < s.N) {
       const int col = (ol >> 3) * 16 + (ol & 7);
-      Cg[((size_t)o * s.n_pad + i) * 2] = s.X[i * s.ldx + col];
-      Cg[((size_t)o * s.n_pad + i) * 2 + 1] = s.X[i * s.ldx + col + 8];
+      Cg[((size_t)o * s.n_pad + i) * 2] = s.X0[i * s.ldx + col];
+      Cg[((size_t)o * s.n_pad + i) * 2 + 1] = s.X0[i * s.ldx + col + 8];
     }
   }
 }
 
 template <typename T>
 size_t lds_bytes_t(const ClassDev& c) {
-  const size_t n_pad = c.md.n_pad, RT = n_pad / 16;
-  return sizeof(T) * (n_pad * (16 * c.nct_max + 2) + n_pad + 2 * kStageKB * RT * 64);
+  const size_t n_pad = c.md.n_pad;
+  int ld = 0;
+  for (int nct = 1; nct <= c.nct_max; ++nct) ld = ld > slab_ld(nct) ? ld : slab_ld(nct);
+  return sizeof(T) * (2 * n_pad * ld + n_pad);
 }
 
 template <typename T>
