@@ -9,7 +9,8 @@ whole per-timestep update of every trajectory.  The timed steps follow a
 warm-up of 1000 steps by default: from a thermal start the orbitals are
 still unit vectors and the exact no-hop bound skips nearly every
 determinant-ratio evaluation, so early steps are cheaper than the steady
-state.
+state.  The 100 timed steps span one period of the Loewdin correction of
+the mixed path.
 
 Both precisions are timed: the mixed path (FP32 MFMA propagation, FP64
 eigen-solve / overlap inverse / rescaling, FP64 Loewdin every 100 steps)
@@ -174,7 +175,7 @@ def cpu_baseline(cfg_name, steps_per_worker):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--n-traj", type=int, default=None)

@@ -99,6 +99,15 @@ def propagate(C, A, dt):
     return P @ (np.exp(-1j * mu * dt)[:, None] * (P.conj().T @ C))
 
 
+def lowdin(C):
+    """Symmetric (Loewdin) orthonormalisation C (C^H C)^{-1/2}, the FP64
+    correction that the mixed-precision pattern applies to its FP32 orbitals
+    every L steps; the inverse square root is taken from the eigenpairs of the
+    Hermitian overlap matrix."""
+    w, V = np.linalg.eigh(C.conj().T @ C)
+    return C @ (V @ np.diag(1.0 / np.sqrt(w)) @ V.conj().T)
+
+
 # ------------------------------------------------------------------------- hopping
 def vdot_D(Ds, v):
     return sum(vn * D for vn, D in zip(np.atleast_1d(v), Ds))

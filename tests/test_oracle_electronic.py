@@ -311,3 +311,19 @@ def test_digamma_closed_form_limits():
         t0 = closed_forms.impurity_occupation(h, 0.01, 0.0, 0.0)
         tsmall = closed_forms.impurity_occupation(h, 0.01, 0.0, 1e-7)
         assert abs(t0 - tsmall) < 1e-7
+
+
+def test_lowdin_is_the_polar_factor():
+    """C (C^H C)^{-1/2} equals the unitary polar factor U V^H of the SVD
+    C = U S V^H (an independent closed form), is orthonormal, commutes with a
+    unitary acting from the left, and leaves orthonormal orbitals unchanged."""
+    rs = np.random.default_rng(5)
+    n, N = 17, 6
+    C = rs.normal(size=(n, N)) + 1j * rs.normal(size=(n, N))
+    L = el.lowdin(C)
+    U, _, Vh = np.linalg.svd(C, full_matrices=False)
+    assert np.allclose(L, U @ Vh, atol=1e-12)
+    assert np.allclose(L.conj().T @ L, np.eye(N), atol=1e-12)
+    Q, _ = np.linalg.qr(rs.normal(size=(n, n)) + 1j * rs.normal(size=(n, n)))
+    assert np.allclose(el.lowdin(Q @ C), Q @ L, atol=1e-12)
+    assert np.allclose(el.lowdin(L), L, atol=1e-12)
