@@ -125,8 +125,8 @@ typedef struct iesh_run_desc {
   int64_t max_steps;     /* freeze a trajectory after this many steps (0: no cap) */
 } iesh_run_desc;
 
-#define IESH_MAX_STATES 224   /* n = M + 1 limit of this build                */
-#define IESH_MAX_ELEC 128     /* N limit of this build                        */
+#define IESH_MAX_STATES 336   /* n = M + 1 limit of this build                */
+#define IESH_MAX_ELEC 168     /* N limit of this build                        */
 
 /* Observables written per record and trajectory by iesh_run, in this order. */
 #define IESH_OBS_PD_SURF 0   /* sum_{a in s} Q[0][a]^2                         */

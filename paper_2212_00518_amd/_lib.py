@@ -26,8 +26,8 @@ IESH_BATH_TRAPEZOID = 0
 IESH_BATH_TRAPEZOID_MIDPOINT = 1
 IESH_BATH_GAUSS_LEGENDRE = 2
 IESH_N_OBS = 5
-IESH_MAX_STATES = 224
-IESH_MAX_ELEC = 128
+IESH_MAX_STATES = 336
+IESH_MAX_ELEC = 168
 IESH_EVENT_CAP = 1 << 20
 
 TRAJ_EXITED, TRAJ_NONCONV, TRAJ_SINGULAR_S, TRAJ_NONFINITE, TRAJ_STEPCAP = 1, 2, 4, 8, 16

@@ -23,6 +23,7 @@ struct iesh_ctx {
   Counters* cnt = nullptr;
   iesh_event* events = nullptr;
   int n_max = 0, N_max = 0;
+  int n_cu = 256;  // compute units of the device
   int64_t step = 0;
   size_t device_bytes = 0;
   std::string err;
@@ -316,6 +317,10 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     ctx->own_stream = true;
   }
   (void)hipGetDevice(&ctx->device);
+  if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+          hipSuccess ||
+      ctx->n_cu < 1)
+    ctx->n_cu = 256;
   const iesh_run_desc& r = ctx->run;
   if (r.n_traj < 1) return (fail(ctx, IESH_EINVAL, "n_traj must be >= 1"), bail(IESH_EINVAL));
   if (!(r.dt > 0.0)) return (fail(ctx, IESH_EINVAL, "dt must be > 0"), bail(IESH_EINVAL));
@@ -370,7 +375,9 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
         (rc = dalloc(ctx, &c.geo, (size_t)T * kGeoStride)) ||
         (rc = dalloc(ctx, &c.cheb, (size_t)T * kChebStride)) ||
         (rc = dalloc(ctx, &c.gbuf, (size_t)T * N * n_pad)) ||
-        (rc = dalloc(ctx, &c.hopneed, T)))
+        (rc = dalloc(ctx, &c.hopq, (size_t)3 + T)))
+      return bail(rc);
+    if (hop_needs_scratch(c) && (rc = dalloc(ctx, &c.hopx, (size_t)T * N * N)))
       return bail(rc);
     if (r.precision == IESH_FP64) {
       if ((rc = dalloc(ctx, &c.C64, (size_t)T * N * n_pad * 2)) ||

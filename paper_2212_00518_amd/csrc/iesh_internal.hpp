@@ -71,7 +71,8 @@ struct ClassDev {
   double* gbuf = nullptr;   // [T][N][n_pad] hop probabilities (query mode)
   double* obs = nullptr;    // [records][T][IESH_N_OBS] (class-local records)
   double2* low = nullptr;   // Loewdin scratch (mixed path)
-  int32_t* hopneed = nullptr;  // [T] 1: the determinant-ratio kernel must run
+  int32_t* hopq = nullptr;  // [3 + T] queue for the determinant-ratio kernel: count, -, done, list
+  double2* hopx = nullptr;  // [T][N][N] inverse of S (shapes whose registers cannot hold it)
 };
 
 struct Counters {
@@ -181,6 +182,7 @@ hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt
                       iesh_event* events, int query_mode, int t0, int nt, int record,
                       int exit_enabled, double exit_x, int64_t max_steps, int precision,
                       hipStream_t s);
+bool hop_needs_scratch(const ClassDev& c);
 hipError_t launch_hop_filter(const ClassDev& c, double dt, uint64_t seed, Counters* cnt, int record,
                              int exit_enabled, double exit_x, int64_t max_steps, int precision,
                              hipStream_t s);

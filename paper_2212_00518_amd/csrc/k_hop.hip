@@ -16,13 +16,17 @@
 // Re W enters g, so Y is accumulated as a real product over the 2N real and
 // imaginary parts.
 //
-// One work-group of 512 threads per trajectory.  Thread (ti, tj), tid =
+// One 512-thread work-group per trajectory that the exact no-hop bound could
+// not settle, taken in order from a per-class queue filled by the bound
+// kernel.  Thread (ti, tj), tid =
 // ti + 16 tj, owns rows ti + 16 ri and columns tj + 32 cj of X and rows
 // ti + 16 rb (positions in the unoccupied list) and columns tj + 32 cj of Y in
 // registers (the slot counts are template parameters sized to the problem).
 // A row of X and the pivot column are exchanged through LDS, and every wave
 // chooses the pivot redundantly from the same LDS data.  Y is accumulated
-// over chunks of 16 rows of X staged in LDS with the matching orbitals of C_U.
+// over chunks of 8 rows of X staged in LDS with the matching orbitals of C_U;
+// when X and Y together would not fit in registers, X goes to the
+// trajectory's scratch after the inversion and the chunks are read from there.
 
 #include "iesh_internal.hpp"
 
@@ -32,11 +36,13 @@ namespace {
 constexpr int kHopThreads = 512;
 constexpr int kRowLanes = 16;  // threads along the rows
 
+constexpr int kElecPad = (kMaxElec + 31) / 32 * 32;  // columns covered by the 32-wide slots
+
 struct HopLds {
-  double2 rowbuf[2][kMaxElec];   // row r of X (pivot search and elimination factors)
-  double2 colbuf[2][kMaxElec];   // scaled pivot column of X
-  double2 xs[16][kMaxElec];      // chunk of 16 rows of X
-  double2 cu[16][kMaxStates];    // C[u_bi][perm[q]] for the chunk's rows q
+  double2 rowbuf[2][kElecPad];   // row r of X (pivot search and elimination factors)
+  double2 colbuf[2][kElecPad];   // scaled pivot column of X
+  double2 xs[8][kElecPad];       // chunk of 8 rows of X
+  double2 cu[8][kMaxStates];     // C[u_bi][perm[q]] for the chunk's rows q
   double lam[kMaxStates];
   double q0[kMaxStates];
   double rowsum[kMaxElec];
@@ -68,24 +74,28 @@ __device__ inline double2 orb(const ClassDev& c, size_t base, int n_pad, int j, 
   return reinterpret_cast<const double2*>(c.C64)[base + (size_t)j * n_pad + i];
 }
 
+// X and Y in registers together, or X through scratch for the product.
+template <int kRS, int kRB>
+constexpr bool x_via_scratch() {
+  return 4 * kRS * ((kRS + 1) / 2) + 2 * kRB * ((kRS + 1) / 2) > 170;
+}
+
+// Everything the step needs for trajectory t (all threads of the work-group).
 template <bool kF32, int kRS, int kRB>
-__global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint64_t seed,
-                                                     Counters* cnt, iesh_event* events,
-                                                     int query_mode, int t0, int record,
-                                                     int exit_enabled, double exit_x,
-                                                     int64_t max_steps, const int32_t* need) {
+__device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Counters* cnt,
+                        iesh_event* events, int query_mode, int record, int exit_enabled,
+                        double exit_x, int64_t max_steps, HopLds& L, double2* xscr) {
   constexpr int kCS = (kRS + 1) / 2;  // 32-column slots covering 16 kRS columns
-  __shared__ HopLds L;
-  const int t = t0 + blockIdx.x;
+  constexpr bool kXS = x_via_scratch<kRS, kRB>();
   const int tid = threadIdx.x;
   const int ti = tid & 15, tj = tid >> 4;
   const int lane = tid & 63;
   const ModelDev& md = c.md;
   const int n = md.n, n_pad = md.n_pad, N = md.N, nU = n - N;
-  if (!query_mode && (c.status[t] & kFreezeMask)) return;
-  if (need && !need[t]) return;  // the bound proved that no hop can occur
+  if (!query_mode && (c.status[t] & kFreezeMask)) return;  // uniform
   const size_t base = (size_t)t * N * n_pad;
   if (!query_mode && tid == 0) atomicAdd((unsigned long long*)&cnt->hop_evals, 1ull);
+  __syncthreads();  // the previous trajectory of this work-group is done with L
 
   for (int k = tid; k < n_pad; k += kHopThreads) {
     L.lam[k] = c.lam[(size_t)t * n_pad + k];
@@ -147,11 +157,11 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
   // ---- in-place Gauss-Jordan inversion with column pivoting
   // The pivot of row r is the largest of keys that hold |X[r][j]|^2 in their
   // high bits (the bit pattern of a non-negative double orders like the
-  // value) and 127 - j in the low 7 bits, so equal moduli go to the smallest
-  // column; moduli within a relative 2^-45 of each other count as equal.
+  // value) and 255 - j in the low 8 bits, so equal moduli go to the smallest
+  // column; moduli within a relative 2^-44 of each other count as equal.
   // When the owners of row r publish it (right after their update of the
   // previous step) each wave reduces its owners' keys to one slot.
-  static_assert(kMaxElec <= 128, "pivot keys hold 128 columns");
+  static_assert(kMaxElec <= 256, "pivot keys hold 256 columns");
   constexpr int kWaves = kHopThreads / 64;
   unsigned used = 0u;  // bit cj: this thread's column tj + 32 cj has been a pivot
   auto publish_row = [&](int r) {
@@ -172,7 +182,7 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
               const double m = z.x * z.x + z.y * z.y;
               if (!((used >> cj) & 1u) && m > 0.0 && m < INFINITY) {
                 const unsigned long long kj =
-                    ((unsigned long long)__double_as_longlong(m) & ~0x7Full) | (unsigned long long)(127 - j);
+                    ((unsigned long long)__double_as_longlong(m) & ~0xFFull) | (unsigned long long)(255 - j);
                 k = kj > k ? kj : k;
               }
             }
@@ -190,9 +200,9 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
   };
   // entries of the row and column buffers past N stay zero, so the update
   // needs no bounds selects
-  for (int e = tid; e < 2 * kMaxElec; e += kHopThreads) {
-    L.rowbuf[e / kMaxElec][e % kMaxElec] = make_double2(0.0, 0.0);
-    L.colbuf[e / kMaxElec][e % kMaxElec] = make_double2(0.0, 0.0);
+  for (int e = tid; e < 2 * kElecPad; e += kHopThreads) {
+    L.rowbuf[e / kElecPad][e % kElecPad] = make_double2(0.0, 0.0);
+    L.colbuf[e / kElecPad][e % kElecPad] = make_double2(0.0, 0.0);
   }
   __syncthreads();
   publish_row(0);
@@ -208,7 +218,7 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
     // no finite nonzero candidate (singular S): the remaining steps are
     // no-ops; the decision is uniform
     const bool bad = (kr == 0ull);
-    const int p = bad ? 0 : 127 - (int)(kr & 0x7Full);
+    const int p = bad ? 0 : 255 - (int)(kr & 0xFFull);
     if (!bad && tj == (p & 31)) used |= 1u << (p >> 5);
     const double2 piv = L.rowbuf[buf][p];
     const double best = piv.x * piv.x + piv.y * piv.y;
@@ -285,7 +295,16 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
     for (int r = tid; r < N; r += kHopThreads) L.invperm[L.perm[r]] = r;
   }
 
-  // ---- Y[bi][c] = Re sum_q C[u_bi][perm[q]] X[q][c], chunks of 16 rows q
+  // ---- Y[bi][c] = Re sum_q C[u_bi][perm[q]] X[q][c], chunks of 8 rows q
+  if (kXS) {
+#pragma unroll
+    for (int ri = 0; ri < kRS; ++ri)
+#pragma unroll
+      for (int cj = 0; cj < kCS; ++cj) {
+        const int i = ti + 16 * ri, j = tj + 32 * cj;
+        if (i < N && j < N) xscr[(size_t)i * N + j] = x[ri][cj];
+      }
+  }
   double y[kRB][kCS];
 #pragma unroll
   for (int rb = 0; rb < kRB; ++rb)
@@ -293,29 +312,40 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
     for (int cj = 0; cj < kCS; ++cj) y[rb][cj] = 0.0;
 #pragma unroll
   for (int ri = 0; ri < kRS; ++ri) {
-    if (16 * ri < N) {  // uniform
-      __syncthreads();  // the previous chunk has been consumed
 #pragma unroll
-      for (int cj = 0; cj < kCS; ++cj) {
-        const int j = tj + 32 * cj;
-        if (j < N) L.xs[ti][j] = x[ri][cj];
-      }
-      const int nq = min(16, N - 16 * ri);
-      for (int e = tid; e < nq * nU; e += kHopThreads) {
-        const int qq = e / nU, bi = e - qq * nU;
-        L.cu[qq][bi] = orb<kF32>(c, base, n_pad, L.perm[16 * ri + qq], L.uocc[bi]);
-      }
-      __syncthreads();
-      for (int qq = 0; qq < nq; ++qq) {
-        double2 xv[kCS];
+    for (int hh = 0; hh < 2; ++hh) {
+      const int q0 = 16 * ri + 8 * hh;
+      if (q0 < N) {  // uniform
+        __syncthreads();  // the previous chunk has been consumed (X in scratch is complete)
+        if (kXS) {
+          for (int e = tid; e < 8 * N; e += kHopThreads) {
+            const int qq = e / N, j = e - qq * N;
+            L.xs[qq][j] = (q0 + qq < N) ? xscr[(size_t)(q0 + qq) * N + j] : make_double2(0.0, 0.0);
+          }
+        } else if ((ti >> 3) == hh) {
 #pragma unroll
-        for (int cj = 0; cj < kCS; ++cj) xv[cj] = L.xs[qq][tj + 32 * cj];
+          for (int cj = 0; cj < kCS; ++cj) {
+            const int j = tj + 32 * cj;
+            if (j < N) L.xs[ti & 7][j] = x[ri][cj];
+          }
+        }
+        const int nq = min(8, N - q0);
+        for (int e = tid; e < nq * nU; e += kHopThreads) {
+          const int qq = e / nU, bi = e - qq * nU;
+          L.cu[qq][bi] = orb<kF32>(c, base, n_pad, L.perm[q0 + qq], L.uocc[bi]);
+        }
+        __syncthreads();
+        for (int qq = 0; qq < nq; ++qq) {
+          double2 xv[kCS];
 #pragma unroll
-        for (int rb = 0; rb < kRB; ++rb) {
-          const int bi = ti + 16 * rb;
-          const double2 cv = (bi < nU) ? L.cu[qq][bi] : make_double2(0.0, 0.0);
+          for (int cj = 0; cj < kCS; ++cj) xv[cj] = L.xs[qq][tj + 32 * cj];
 #pragma unroll
-          for (int cj = 0; cj < kCS; ++cj) y[rb][cj] += cv.x * xv[cj].x - cv.y * xv[cj].y;
+          for (int rb = 0; rb < kRB; ++rb) {
+            const int bi = ti + 16 * rb;
+            const double2 cv = (bi < nU) ? L.cu[qq][bi] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int cj = 0; cj < kCS; ++cj) y[rb][cj] += cv.x * xv[cj].x - cv.y * xv[cj].y;
+          }
         }
       }
     }
@@ -536,6 +566,36 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
 }
 
 
+// Work-group b takes entry b of the class queue hopq = [count, unused, done,
+// list...] that the bound kernel fills (work-groups past the count exit at
+// once; the dispatcher hands out work-groups in order, so the busy ones fill
+// the compute units first).  The last work-group to finish resets the queue
+// for the next step.  In query mode work-group b handles trajectory t0 + b.
+template <bool kF32, int kRS, int kRB>
+__global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint64_t seed,
+                                                     Counters* cnt, iesh_event* events,
+                                                     int query_mode, int t0, int record,
+                                                     int exit_enabled, double exit_x,
+                                                     int64_t max_steps) {
+  __shared__ HopLds L;
+  int32_t* q = c.hopq;
+  const int b = blockIdx.x;
+  int t = t0 + b;
+  if (!query_mode) t = (b < q[0]) ? q[3 + b] : -1;
+  if (t >= 0) {
+    double2* xscr = x_via_scratch<kRS, kRB>() ? c.hopx + (size_t)t * c.md.N * c.md.N : nullptr;
+    hop_one<kF32, kRS, kRB>(c, t, dt, seed, cnt, events, query_mode, record, exit_enabled, exit_x,
+                            max_steps, L, xscr);
+  }
+  if (!query_mode && threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&q[2], 1) == (int)gridDim.x - 1) {
+      q[0] = 0;
+      q[2] = 0;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Exact hop filter.  For orbitals with orthonormal columns, S^H S =
 // I - C_U^H C_U, so sigma_min(S)^2 >= 1 - ||C_U||_F^2 - delta (delta covers the
@@ -638,7 +698,7 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
   const bool no_hop = smin2 > 0.0 && (1.0 + 1e-10) * 2.0 * dt * S1 / sqrt(smin2) <= xi;
   __syncthreads();
   if (!no_hop) {
-    if (tid == 0) c.hopneed[t] = 1;
+    if (tid == 0) c.hopq[3 + atomicAdd(&c.hopq[0], 1)] = t;
     return;
   }
   // impurity amplitude of every orbital (observable), one wave per orbital
@@ -669,7 +729,6 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
     __syncthreads();
   }
   if (tid == 0) {
-    c.hopneed[t] = 0;
     int32_t st = c.status[t];
     const int64_t ns = c.nsteps[t] + 1;
     c.nsteps[t] = ns;
@@ -707,38 +766,49 @@ __global__ void k_advance(Counters* cnt) {
 
 }  // namespace
 
+// Register slots: RS rows of 16 for the N x N inverse (N <= 16 RS), RB rows
+// of 16 for the n - N unoccupied states.  Buckets that cannot occur with
+// n <= IESH_MAX_STATES are not instantiated.
+constexpr int rs_floor(int rs) { return rs == 2 ? 0 : rs == 4 ? 2 : rs == 7 ? 4 : rs == 10 ? 7 : 10; }
+constexpr int rb_floor(int rb) {
+  return rb == 2 ? 0 : rb == 4 ? 2 : rb == 7 ? 4 : rb == 11 ? 7 : rb == 14 ? 11 : 14;
+}
+template <int RS, int RB>
+constexpr bool bucket_possible() {
+  return 16 * rs_floor(RS) + 1 + 16 * rb_floor(RB) + 1 <= kMaxStates;
+}
+
 template <bool F32, int RS, int RB>
 static void launch_hop_t(const ClassDev& c, dim3 grid, double dt, uint64_t seed, Counters* cnt,
                          iesh_event* events, int query_mode, int t0, int record,
                          int exit_enabled, double exit_x, int64_t max_steps, hipStream_t s) {
-  hipLaunchKernelGGL((k_hop<F32, RS, RB>), grid, dim3(kHopThreads), 0, s, c, dt, seed, cnt,
-                     events, query_mode, t0, record, exit_enabled, exit_x, max_steps,
-                     query_mode ? (const int32_t*)nullptr : (const int32_t*)c.hopneed);
+  if constexpr (bucket_possible<RS, RB>())
+    hipLaunchKernelGGL((k_hop<F32, RS, RB>), grid, dim3(kHopThreads), 0, s, c, dt, seed, cnt,
+                       events, query_mode, t0, record, exit_enabled, exit_x, max_steps);
 }
 
-// Register slots: RS rows of 16 for the N x N inverse, RB rows of 16 for the
-// n - N unoccupied states.
 template <bool F32, int RS>
 static void launch_hop_rs(const ClassDev& c, dim3 grid, double dt, uint64_t seed,
                           Counters* cnt, iesh_event* events, int query_mode, int t0,
                           int record, int exit_enabled, double exit_x, int64_t max_steps,
                           hipStream_t s) {
   const int rb = (c.md.n - c.md.N + 15) / 16;
+#define IESH_HOP_RB(RBV)                                                                      \
+  launch_hop_t<F32, RS, RBV>(c, grid, dt, seed, cnt, events, query_mode, t0, record,          \
+                             exit_enabled, exit_x, max_steps, s)
   if (rb <= 2)
-    launch_hop_t<F32, RS, 2>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
-                             exit_enabled, exit_x, max_steps, s);
+    IESH_HOP_RB(2);
   else if (rb <= 4)
-    launch_hop_t<F32, RS, 4>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
-                             exit_enabled, exit_x, max_steps, s);
+    IESH_HOP_RB(4);
   else if (rb <= 7)
-    launch_hop_t<F32, RS, 7>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
-                             exit_enabled, exit_x, max_steps, s);
-  else if (rb <= 10)
-    launch_hop_t<F32, RS, 10>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
-                              exit_enabled, exit_x, max_steps, s);
+    IESH_HOP_RB(7);
+  else if (rb <= 11)
+    IESH_HOP_RB(11);
+  else if (rb <= 14)
+    IESH_HOP_RB(14);
   else
-    launch_hop_t<F32, RS, 14>(c, grid, dt, seed, cnt, events, query_mode, t0, record,
-                              exit_enabled, exit_x, max_steps, s);
+    IESH_HOP_RB(21);
+#undef IESH_HOP_RB
 }
 
 template <bool F32>
@@ -746,18 +816,28 @@ static void launch_hop_p(const ClassDev& c, dim3 grid, double dt, uint64_t seed,
                          iesh_event* events, int query_mode, int t0, int record,
                          int exit_enabled, double exit_x, int64_t max_steps, hipStream_t s) {
   const int rs = (c.md.N + 15) / 16;
+#define IESH_HOP_RS(RSV)                                                                      \
+  launch_hop_rs<F32, RSV>(c, grid, dt, seed, cnt, events, query_mode, t0, record,             \
+                          exit_enabled, exit_x, max_steps, s)
   if (rs <= 2)
-    launch_hop_rs<F32, 2>(c, grid, dt, seed, cnt, events, query_mode, t0, record, exit_enabled,
-                          exit_x, max_steps, s);
+    IESH_HOP_RS(2);
   else if (rs <= 4)
-    launch_hop_rs<F32, 4>(c, grid, dt, seed, cnt, events, query_mode, t0, record, exit_enabled,
-                          exit_x, max_steps, s);
+    IESH_HOP_RS(4);
   else if (rs <= 7)
-    launch_hop_rs<F32, 7>(c, grid, dt, seed, cnt, events, query_mode, t0, record, exit_enabled,
-                          exit_x, max_steps, s);
+    IESH_HOP_RS(7);
+  else if (rs <= 10)
+    IESH_HOP_RS(10);
   else
-    launch_hop_rs<F32, 8>(c, grid, dt, seed, cnt, events, query_mode, t0, record, exit_enabled,
-                          exit_x, max_steps, s);
+    IESH_HOP_RS(11);
+#undef IESH_HOP_RS
+}
+
+bool hop_needs_scratch(const ClassDev& c) {
+  const int rs = (c.md.N + 15) / 16, rb = (c.md.n - c.md.N + 15) / 16;
+  const int RS = rs <= 2 ? 2 : rs <= 4 ? 4 : rs <= 7 ? 7 : rs <= 10 ? 10 : 11;
+  const int RB = rb <= 2 ? 2 : rb <= 4 ? 4 : rb <= 7 ? 7 : rb <= 11 ? 11 : rb <= 14 ? 14 : 21;
+  const int CS = (RS + 1) / 2;
+  return 4 * RS * CS + 2 * RB * CS > 170;
 }
 
 hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt,

@@ -236,8 +236,12 @@ hipError_t launch_lowdin(const ClassDev& c, const Counters* cnt, int every, doub
     hipLaunchKernelGGL(k_lowdin<2>, dim3(nb), dim3(kLowThreads), 0, s, c, cnt, every, scratch);
   else if (ri <= 3)
     hipLaunchKernelGGL(k_lowdin<3>, dim3(nb), dim3(kLowThreads), 0, s, c, cnt, every, scratch);
-  else
+  else if (ri <= 4)
     hipLaunchKernelGGL(k_lowdin<4>, dim3(nb), dim3(kLowThreads), 0, s, c, cnt, every, scratch);
+  else if (ri <= 5)
+    hipLaunchKernelGGL(k_lowdin<5>, dim3(nb), dim3(kLowThreads), 0, s, c, cnt, every, scratch);
+  else
+    hipLaunchKernelGGL(k_lowdin<6>, dim3(nb), dim3(kLowThreads), 0, s, c, cnt, every, scratch);
   return hipGetLastError();
 }
 

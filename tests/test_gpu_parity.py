@@ -73,6 +73,8 @@ def upload(ens, states):
     ("c3", 40, np.linspace(2.0, 14.0, 6)),
     ("c3", 160, np.linspace(2.0, 14.0, 6)),
     ("c2", 222, np.linspace(-10, 25, 3)),
+    ("c3", 320, np.linspace(2.0, 14.0, 4)),
+    ("c1", 335, np.linspace(-10, 25, 3)),
 ])
 def test_adiabatic_energies_and_amplitudes(name, M, xs):
     cfg = make_cfg(name, M=M)
@@ -96,6 +98,7 @@ def test_adiabatic_energies_and_amplitudes(name, M, xs):
 @pytest.mark.parametrize("name,M,N", [
     ("c1", 20, 10), ("c1", 1, 1), ("c1", 6, 1), ("c1", 37, 13), ("c1", 63, 31),
     ("c2", 200, 100), ("c2gl", 200, 100), ("c3", 80, 40), ("c2", 222, 111), ("c1", 127, 127),
+    ("c3", 160, 80), ("c3", 320, 160), ("c1", 300, 40), ("c1", 335, 168), ("c1", 250, 120),
 ])
 def test_hop_probabilities(name, M, N):
     cfg = make_cfg(name, M=M, N=N)
@@ -156,6 +159,7 @@ def _compare_step(cfg, m, states, precision="fp64", tol=1e-10, step0=0):
 @pytest.mark.parametrize("name,M,N,vscale", [
     ("c1", 20, 10, 0.002), ("c1", 37, 13, 0.004), ("c2", 200, 100, 0.002),
     ("c2gl", 200, 100, 0.002), ("c3", 40, 20, 0.01), ("c1", 1, 1, 0.003),
+    ("c3", 320, 160, 0.01), ("c1", 300, 40, 0.003),
 ])
 def test_single_step_random_orbitals(name, M, N, vscale):
     """Random orthonormal orbitals make hops likely within one step."""
