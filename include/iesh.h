@@ -120,7 +120,9 @@ typedef struct iesh_run_desc {
   int32_t lowdin_every;  /* IESH_MIXED: re-orthonormalise every L steps (0: never) */
   int32_t record_every;  /* observables every R steps in iesh_run (0: none)    */
   int32_t exit_enabled;  /* freeze trajectories once x > exit_x                */
-  int32_t reserved0;
+  int32_t compact_every; /* iesh_run: every this many steps, move frozen trajectories
+                            behind the active ones so that the step kernels visit
+                            only active slots (0: never)                         */
   double exit_x;
   int64_t max_steps;     /* freeze a trajectory after this many steps (0: no cap) */
 } iesh_run_desc;
@@ -233,6 +235,14 @@ int iesh_traj_status(iesh_ctx* ctx, int32_t* status_out);
 #define IESH_EVENT_CAP (1 << 20)
 int iesh_events(iesh_ctx* ctx, iesh_event* out, int64_t cap, int64_t* count);
 int iesh_clear_events(iesh_ctx* ctx);
+
+/* Per bath-size class (model index cls), 8 int32 values: number of
+   trajectories, live slots (the step kernels visit slots [0, live); the
+   others hold frozen trajectories after compaction), n, N, orbital tiles of
+   16 columns per propagation work-group (chosen by timing at creation),
+   propagation work-groups per trajectory, n rounded up to 16, 0.  Does not
+   synchronise. */
+int iesh_class_info(const iesh_ctx* ctx, int32_t cls, int32_t* info);
 
 typedef struct iesh_sizes {
   int32_t n_traj, n_models, n_max, N_max;

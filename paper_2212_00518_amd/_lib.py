@@ -40,7 +40,7 @@ SYMBOLS = (
     "iesh_init_thermal", "iesh_set_step", "iesh_get_step", "iesh_step", "iesh_run",
     "iesh_hop_probs", "iesh_adiabatic", "iesh_traj_status", "iesh_events",
     "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
-    "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals",
+    "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals", "iesh_class_info",
 )
 TIMERS = ("eig", "prop", "hop", "lowdin", "filter")
 
@@ -56,7 +56,7 @@ class RunDesc(C.Structure):
     _fields_ = [("n_traj", C.c_int32), ("precision", C.c_int32), ("dt", C.c_double),
                 ("kT", C.c_double), ("seed", C.c_uint64), ("lowdin_every", C.c_int32),
                 ("record_every", C.c_int32), ("exit_enabled", C.c_int32),
-                ("reserved0", C.c_int32), ("exit_x", C.c_double), ("max_steps", C.c_int64)]
+                ("compact_every", C.c_int32), ("exit_x", C.c_double), ("max_steps", C.c_int64)]
 
 
 class Event(C.Structure):
@@ -108,6 +108,7 @@ def lib():
         L.iesh_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
         L.iesh_work.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.iesh_hop_evals.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.iesh_class_info.argtypes = [vp, C.c_int32, ip]
         _lib = L
     return _lib
 
@@ -180,6 +181,7 @@ class Ensemble:
         r.exit_enabled = int(run.get("exit_enabled", 0))
         r.exit_x = float(run.get("exit_x", 0.0))
         r.max_steps = int(run.get("max_steps", 0))
+        r.compact_every = int(run.get("compact_every", 0))
         self.run_desc = r
         tm = None
         if traj_model is not None:
@@ -309,6 +311,15 @@ class Ensemble:
         a, b = C.c_int64(), C.c_int64()
         self._check(lib().iesh_work(self.ctx, C.byref(a), C.byref(b)), "iesh_work")
         return a.value, b.value
+
+    def class_info(self, cls: int = 0):
+        """(n_traj, live slots, n, N, tiles per propagation work-group,
+        work-groups per trajectory, n_pad) of one bath-size class."""
+        info = np.zeros(8, dtype=np.int32)
+        self._check(lib().iesh_class_info(self.ctx, int(cls), info.ctypes.data_as(C.POINTER(C.c_int32))),
+                    "iesh_class_info")
+        keys = ("n_traj", "live", "n", "N", "tiles_per_group", "groups_per_traj", "n_pad")
+        return dict(zip(keys, (int(v) for v in info[:7])))
 
     def hop_evals(self):
         n = C.c_int64()

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libiesh.so")
 
-SOURCES = ["api.cpp", "bath.cpp", "k_eig.hip", "k_prop.hip", "k_hop.hip", "k_lowdin.hip"]
+SOURCES = ["api.cpp", "bath.cpp", "k_eig.hip", "k_prop.hip", "k_hop.hip", "k_lowdin.hip",
+           "k_compact.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.

@@ -15,7 +15,11 @@ using namespace iesh;
 struct iesh_ctx {
   std::vector<ClassDev> cls;
   std::vector<int32_t> traj_class;  // global trajectory -> class
-  std::vector<int32_t> traj_local;  // global trajectory -> index inside its class
+  std::vector<int32_t> traj_local;  // global trajectory -> home index inside its class
+  std::vector<std::vector<int32_t>> members;    // per class: home index -> global trajectory
+  std::vector<std::vector<int32_t>> slot_home;  // per class: slot -> home index
+  std::vector<std::vector<int32_t>> home_slot;  // per class: home index -> slot
+  std::vector<CompactBufs> spare;               // per class, when compaction is enabled
   iesh_run_desc run{};
   hipStream_t stream = nullptr;
   bool own_stream = false;  // created here when the caller passes none
@@ -82,16 +86,82 @@ int round16(int v) { return (v + 15) / 16 * 16; }
 
 // Propagation work split: column tiles of 8 orbitals, up to
 // prop_max_col_tiles per work-group, limited by the LDS footprint.
-void choose_slabs(ClassDev& c, int precision) {
+hipEvent_t next_event(iesh_ctx* ctx);
+
+// Largest slab width (16-column tiles per propagation work-group) whose LDS
+// fits, not above `limit`.
+int widest_slab(ClassDev& c, int precision, int limit) {
   const size_t lds_budget = 160 * 1024;
   const int tiles = (c.md.N + 7) / 8;
-  int nct = std::min(prop_max_col_tiles(precision), tiles);
+  int nct = std::min(std::min(prop_max_col_tiles(precision), tiles), limit);
   for (; nct > 1; --nct) {
     c.nct_max = nct;
     if (prop_lds_bytes(c, precision) <= lds_budget) break;
   }
+  return std::max(nct, 1);
+}
+
+// Split the orbital tiles into slabs of at most nct tiles, balanced.
+void set_slabs(ClassDev& c, int nct) {
+  const int tiles = (c.md.N + 7) / 8;
   c.n_slabs = (tiles + nct - 1) / nct;
   c.nct_max = (tiles + c.n_slabs - 1) / c.n_slabs;
+}
+
+void choose_slabs(ClassDev& c, int precision) { set_slabs(c, widest_slab(c, precision, 1 << 20)); }
+
+// Time the propagation kernel for every slab width on a sample of slots
+// (K = 12 terms, zero data: the time depends on the shapes only) and keep the
+// fastest per trajectory.  Results do not depend on the choice: every output
+// tile accumulates its k-blocks in the same order.
+int autotune_slabs(iesh_ctx* ctx, ClassDev& c) {
+  const int prec = ctx->run.precision;
+  const int widest = widest_slab(c, prec, 1 << 20);
+  if (widest <= 1 || c.n_traj < 64) {
+    set_slabs(c, widest);
+    return IESH_OK;
+  }
+  const int sample = std::min(c.n_traj, 4 * ctx->n_cu);
+  std::vector<double> cb(kChebStride, 0.0);
+  cb[CHEB_K] = 12.0;
+  cb[CHEB_INVR] = 1.0;
+  for (int t = 0; t < sample; ++t)
+    HIPTRY(ctx, hipMemcpyAsync(c.cheb + (size_t)t * kChebStride, cb.data(), cb.size() * sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream));
+  hipEvent_t e0 = next_event(ctx), e1 = next_event(ctx);
+  if (!e0 || !e1) return fail(ctx, IESH_EDEVICE, "event creation failed");
+  const int saved_live = c.n_live;
+  c.n_live = sample;
+  int best = widest;
+  float best_ms = 1e30f;
+  std::vector<int> seen;
+  for (int nct = 1; nct <= widest; ++nct) {
+    set_slabs(c, nct);
+    if (std::find(seen.begin(), seen.end(), c.nct_max) != seen.end()) continue;
+    seen.push_back(c.nct_max);
+    HIPTRY(ctx, prop_prepare(c, prec));
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIPTRY(ctx, hipEventRecord(e0, ctx->stream));
+      HIPTRY(ctx, launch_prop(c, prec, ctx->stream));
+      HIPTRY(ctx, hipEventRecord(e1, ctx->stream));
+      HIPTRY(ctx, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPTRY(ctx, hipEventElapsedTime(&ms, e0, e1));
+      ms_min = std::min(ms_min, ms);
+    }
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best = c.nct_max;
+    }
+  }
+  ctx->ev_used = 0;
+  c.n_live = saved_live;
+  set_slabs(c, best);
+  HIPTRY(ctx, prop_prepare(c, prec));
+  HIPTRY(ctx, hipMemsetAsync(c.cheb, 0, (size_t)sample * kChebStride * sizeof(double), ctx->stream));
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  return IESH_OK;
 }
 
 int validate_model(const iesh_model_desc& m, std::string& why) {
@@ -199,6 +269,63 @@ int reset_traj_words(iesh_ctx* ctx) {
     HIPTRY(ctx, hipMemsetAsync(c.nsteps, 0, c.n_traj * sizeof(int64_t), ctx->stream));
   }
   HIPTRY(ctx, hipMemsetAsync(&ctx->cnt->n_events, 0, sizeof(int64_t), ctx->stream));
+  return IESH_OK;
+}
+
+// Slots back in upload order (slot = home index), every slot live.
+int reset_perm(iesh_ctx* ctx) {
+  for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+    ClassDev& c = ctx->cls[ci];
+    auto& sh = ctx->slot_home[ci];
+    auto& hs = ctx->home_slot[ci];
+    for (int s = 0; s < c.n_traj; ++s) sh[s] = hs[s] = s;
+    if (c.n_traj)
+      HIPTRY(ctx, hipMemcpyAsync(c.home, sh.data(), c.n_traj * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, ctx->stream));
+    if (c.n_live != c.n_traj) free_graph(ctx);
+    c.n_live = c.n_traj;
+  }
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  return IESH_OK;
+}
+
+// Move the frozen trajectories of every class behind its active ones and
+// shrink the slots the step kernels visit.
+int compact(iesh_ctx* ctx) {
+  for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+    ClassDev& c = ctx->cls[ci];
+    CompactBufs& b = ctx->spare[ci];
+    if (c.n_live < 1 || !b.dst) continue;
+    HIPTRY(ctx, launch_compact_rank(c, b.dst, b.n_active, ctx->stream));
+    int32_t n_active = 0;
+    HIPTRY(ctx, hipMemcpyAsync(&n_active, b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (n_active == c.n_live) continue;
+    const int nl = c.n_live, N = c.md.N;
+    HIPTRY(ctx, launch_compact_move(c, b.dst, b, ctx->run.precision, ctx->stream));
+    const size_t esz = ctx->run.precision == IESH_FP64 ? sizeof(double) : sizeof(float);
+    void* Cdst = ctx->run.precision == IESH_FP64 ? (void*)c.C64 : (void*)c.C32;
+    auto cp = [&](void* dst, const void* src, size_t bytes) {
+      return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream);
+    };
+    HIPTRY(ctx, cp(c.x, b.x, nl * sizeof(double)));
+    HIPTRY(ctx, cp(c.v, b.v, nl * sizeof(double)));
+    HIPTRY(ctx, cp(c.F, b.F, nl * sizeof(double)));
+    HIPTRY(ctx, cp(c.status, b.status, nl * sizeof(int32_t)));
+    HIPTRY(ctx, cp(c.gtraj, b.gtraj, nl * sizeof(int32_t)));
+    HIPTRY(ctx, cp(c.home, b.home, nl * sizeof(int32_t)));
+    HIPTRY(ctx, cp(c.nsteps, b.nsteps, nl * sizeof(int64_t)));
+    HIPTRY(ctx, cp(c.occ, b.occ, (size_t)nl * N * sizeof(int32_t)));
+    HIPTRY(ctx, cp(Cdst, b.C, (size_t)nl * N * c.md.n_pad * 2 * esz));
+    auto& sh = ctx->slot_home[ci];
+    HIPTRY(ctx, hipMemcpyAsync(sh.data(), c.home, nl * sizeof(int32_t), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int s = 0; s < nl; ++s) ctx->home_slot[ci][sh[s]] = s;
+    c.n_live = n_active;
+    free_graph(ctx);  // launch sizes changed
+  }
   return IESH_OK;
 }
 
@@ -334,6 +461,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     if (!validate_model(models[m], why))
       return (fail(ctx, IESH_EINVAL, "model " + std::to_string(m) + ": " + why), bail(IESH_EINVAL));
   }
+  if (r.compact_every < 0) return (fail(ctx, IESH_EINVAL, "negative cadence"), bail(IESH_EINVAL));
   ctx->traj_class.assign(r.n_traj, 0);
   ctx->traj_local.assign(r.n_traj, 0);
   std::vector<int> count(n_models, 0);
@@ -349,6 +477,11 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
   rc = dalloc(ctx, &ctx->events, (size_t)IESH_EVENT_CAP);
   if (rc) return bail(rc);
   ctx->cls.resize(n_models);
+  ctx->members.assign(n_models, {});
+  ctx->slot_home.assign(n_models, {});
+  ctx->home_slot.assign(n_models, {});
+  ctx->spare.assign(n_models, CompactBufs{});
+  for (int t = 0; t < r.n_traj; ++t) ctx->members[ctx->traj_class[t]].push_back(t);
   for (int m = 0; m < n_models; ++m) {
     const iesh_model_desc& d = models[m];
     ClassDev& c = ctx->cls[m];
@@ -361,6 +494,9 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     c.md.Gamma = d.Gamma;
     for (int q = 0; q < 16; ++q) c.md.p[q] = d.params[q];
     c.n_traj = count[m];
+    c.n_live = count[m];
+    ctx->slot_home[m].assign(count[m], 0);
+    ctx->home_slot[m].assign(count[m], 0);
     ctx->n_max = std::max(ctx->n_max, c.md.n);
     ctx->N_max = std::max(ctx->N_max, c.md.N);
     choose_slabs(c, r.precision);
@@ -370,6 +506,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
         (rc = dalloc(ctx, &c.x, T)) || (rc = dalloc(ctx, &c.v, T)) || (rc = dalloc(ctx, &c.F, T)) ||
         (rc = dalloc(ctx, &c.occ, (size_t)T * N)) || (rc = dalloc(ctx, &c.status, T)) ||
         (rc = dalloc(ctx, &c.gtraj, T)) || (rc = dalloc(ctx, &c.nsteps, T)) ||
+        (rc = dalloc(ctx, &c.home, T)) ||
         (rc = dalloc(ctx, &c.lam, (size_t)T * n_pad)) || (rc = dalloc(ctx, &c.q0, (size_t)T * n_pad)) ||
         (rc = dalloc(ctx, &c.lam_mid, (size_t)T * n_pad)) ||
         (rc = dalloc(ctx, &c.geo, (size_t)T * kGeoStride)) ||
@@ -379,6 +516,25 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
       return bail(rc);
     if (hop_needs_scratch(c) && (rc = dalloc(ctx, &c.hopx, (size_t)T * N * N)))
       return bail(rc);
+    if (r.compact_every > 0) {
+      CompactBufs& b = ctx->spare[m];
+      const size_t csz = (size_t)T * N * n_pad * 2;
+      if ((rc = dalloc(ctx, &b.x, T)) || (rc = dalloc(ctx, &b.v, T)) || (rc = dalloc(ctx, &b.F, T)) ||
+          (rc = dalloc(ctx, &b.status, T)) || (rc = dalloc(ctx, &b.gtraj, T)) ||
+          (rc = dalloc(ctx, &b.home, T)) || (rc = dalloc(ctx, &b.nsteps, T)) ||
+          (rc = dalloc(ctx, &b.occ, (size_t)T * N)) || (rc = dalloc(ctx, &b.dst, T)) ||
+          (rc = dalloc(ctx, &b.n_active, 1)))
+        return bail(rc);
+      if (r.precision == IESH_FP64) {
+        double* p = nullptr;
+        if ((rc = dalloc(ctx, &p, csz))) return bail(rc);
+        b.C = p;
+      } else {
+        float* p = nullptr;
+        if ((rc = dalloc(ctx, &p, csz))) return bail(rc);
+        b.C = p;
+      }
+    }
     if (r.precision == IESH_FP64) {
       if ((rc = dalloc(ctx, &c.C64, (size_t)T * N * n_pad * 2)) ||
           (rc = dalloc(ctx, &c.Bt, (size_t)T * n_pad * n_pad)))
@@ -406,8 +562,25 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
   }
   if (hipStreamSynchronize(ctx->stream) != hipSuccess)
     return (fail(ctx, IESH_EDEVICE, "device synchronisation failed"), bail(IESH_EDEVICE));
+  for (auto& c : ctx->cls)
+    if (c.n_traj && autotune_slabs(ctx, c)) return bail(IESH_EDEVICE);
   if (set_counters(ctx, 0, 0)) return bail(IESH_EDEVICE);
+  if (reset_perm(ctx)) return bail(IESH_EDEVICE);
   *out = ctx;
+  return IESH_OK;
+}
+
+int iesh_class_info(const iesh_ctx* ctx, int32_t cls, int32_t* info) {
+  if (!ctx || !info || cls < 0 || cls >= (int)ctx->cls.size()) return IESH_EINVAL;
+  const ClassDev& c = ctx->cls[cls];
+  info[0] = c.n_traj;
+  info[1] = c.n_live;
+  info[2] = c.md.n;
+  info[3] = c.md.N;
+  info[4] = c.nct_max;
+  info[5] = c.n_slabs;
+  info[6] = c.md.n_pad;
+  info[7] = 0;
   return IESH_OK;
 }
 
@@ -464,8 +637,9 @@ int iesh_set_state(iesh_ctx* ctx, const double* x, const double* v, const double
     C = hC.data();
     occ = hocc.data();
   }
-  int rc = upload_state(ctx, x, v, C, occ);
+  int rc = reset_perm(ctx);
   if (rc) return rc;
+  if ((rc = upload_state(ctx, x, v, C, occ))) return rc;
   if ((rc = reset_traj_words(ctx))) return rc;
   for (auto& c : ctx->cls)
     if (c.n_traj) HIPTRY(ctx, launch_forces(c, ctx->stream));
@@ -475,8 +649,9 @@ int iesh_set_state(iesh_ctx* ctx, const double* x, const double* v, const double
 
 int iesh_init_thermal(iesh_ctx* ctx, const double* x, const double* v) {
   if (!ctx || !x || !v) return fail(ctx, IESH_EINVAL, "null pointer");
-  int rc = upload_state(ctx, x, v, nullptr, nullptr);
+  int rc = reset_perm(ctx);
   if (rc) return rc;
+  if ((rc = upload_state(ctx, x, v, nullptr, nullptr))) return rc;
   if ((rc = reset_traj_words(ctx))) return rc;
   for (auto& c : ctx->cls)
     if (c.n_traj) HIPTRY(ctx, launch_init_thermal(c, ctx->run.kT, ctx->run.seed, ctx->stream));
@@ -514,9 +689,9 @@ int iesh_get_state(iesh_ctx* ctx, double* x, double* v, double* C, int32_t* occ,
         for (size_t q = 0; q < f.size(); ++q) cC[q] = f[q];
       }
     }
-    int tl = 0;
-    for (int t = 0; t < T; ++t) {
-      if (ctx->traj_class[t] != (int)ci) continue;
+    for (int sl = 0; sl < Tc; ++sl) {
+      const int t = ctx->members[ci][ctx->slot_home[ci][sl]];
+      const int tl = sl;
       hx[t] = cx[tl];
       hv[t] = cv[tl];
       if (occ)
@@ -530,7 +705,6 @@ int iesh_get_state(iesh_ctx* ctx, double* x, double* v, double* C, int32_t* occ,
             dst[((size_t)j * n + i) * 2 + 1] = cC[s + 1];
           }
       }
-      ++tl;
     }
   }
   auto put = [&](void* dst, const void* src, size_t bytes) -> int {
@@ -581,33 +755,44 @@ int iesh_run(iesh_ctx* ctx, int64_t n_steps, double* obs_out) {
   int rc = set_counters(ctx, ctx->step, record ? r.record_every : 0);
   if (rc) return rc;
   if (n_steps == 0) return IESH_OK;
-  if (ctx->timing) {
-    // eager launches so that every kernel is bracketed by its own events
-    for (int64_t k = 0; k < n_steps; ++k) {
-      rc = enqueue_step(ctx, record);
-      if (rc) return rc;
-      ctx->step += 1;
+  // chunks end where compaction is due
+  int64_t left = n_steps;
+  while (left > 0) {
+    const int64_t chunk = r.compact_every > 0 ? std::min<int64_t>(left, r.compact_every) : left;
+    if (ctx->timing) {
+      // eager launches so that every kernel is bracketed by its own events
+      for (int64_t k = 0; k < chunk; ++k) {
+        rc = enqueue_step(ctx, record);
+        if (rc) return rc;
+        ctx->step += 1;
+      }
+    } else {
+      if (ctx->graph_record != record) {
+        free_graph(ctx);
+        HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIPTRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_step(ctx, record);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+        if (rc) {
+          if (g) (void)hipGraphDestroy(g);
+          return rc;
+        }
+        if (e != hipSuccess)
+          return fail(ctx, IESH_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        ctx->graph = g;
+        HIPTRY(ctx, hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+        ctx->graph_record = record;
+      }
+      for (int64_t k = 0; k < chunk; ++k) HIPTRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+      ctx->step += chunk;
     }
-    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
-    n_steps = 0;
-  } else if (ctx->graph_record != record) {
-    free_graph(ctx);
-    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
-    HIPTRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_step(ctx, record);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
-    if (rc) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
+    left -= chunk;
+    if (r.compact_every > 0) {
+      HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+      if ((rc = compact(ctx))) return rc;
     }
-    if (e != hipSuccess) return fail(ctx, IESH_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    ctx->graph = g;
-    HIPTRY(ctx, hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
-    ctx->graph_record = record;
   }
-  for (int64_t k = 0; k < n_steps; ++k) HIPTRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
-  ctx->step += n_steps;
   HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
   if (record) {
     const int T = r.n_traj;
@@ -638,7 +823,7 @@ int iesh_hop_probs(iesh_ctx* ctx, int32_t traj0, int32_t ntraj, double* g_out, i
   for (int q = 0; q < ntraj; ++q) {
     const int t = traj0 + q;
     ClassDev& c = ctx->cls[ctx->traj_class[t]];
-    const int tl = ctx->traj_local[t];
+    const int tl = ctx->home_slot[ctx->traj_class[t]][ctx->traj_local[t]];
     HIPTRY(ctx, launch_eig_query(c, tl, 1, ctx->stream));
     HIPTRY(ctx, launch_hop(c, ctx->run.dt, ctx->run.seed, ctx->cnt, ctx->events, 1, tl, 1, 0, 0,
                            0.0, 0, ctx->run.precision, ctx->stream));
@@ -664,7 +849,7 @@ int iesh_adiabatic(iesh_ctx* ctx, int32_t traj0, int32_t ntraj, double* lam_out,
   for (int q = 0; q < ntraj; ++q) {
     const int t = traj0 + q;
     ClassDev& c = ctx->cls[ctx->traj_class[t]];
-    const int tl = ctx->traj_local[t];
+    const int tl = ctx->home_slot[ctx->traj_class[t]][ctx->traj_local[t]];
     HIPTRY(ctx, launch_eig_query(c, tl, 1, ctx->stream));
     const int n = c.md.n, n_pad = c.md.n_pad;
     std::vector<double> l(n_pad), qq(n_pad);
@@ -689,9 +874,7 @@ int iesh_traj_status(iesh_ctx* ctx, int32_t* status_out) {
     if (!c.n_traj) continue;
     std::vector<int32_t> s(c.n_traj);
     HIPTRY(ctx, hipMemcpy(s.data(), c.status, s.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-    int tl = 0;
-    for (int t = 0; t < ctx->run.n_traj; ++t)
-      if (ctx->traj_class[t] == (int)ci) status_out[t] = s[tl++];
+    for (int sl = 0; sl < c.n_traj; ++sl) status_out[ctx->members[ci][ctx->slot_home[ci][sl]]] = s[sl];
   }
   return IESH_OK;
 }

@@ -45,7 +45,8 @@ struct ModelDev {
 // Device state of one bath-size class.
 struct ClassDev {
   ModelDev md;
-  int n_traj;           // trajectories in this class
+  int n_traj;           // trajectories in this class (allocated slots)
+  int n_live;           // leading slots the step kernels visit (the others are frozen)
   int traj_offset;      // first global trajectory index of this class
   int nct_max;          // column tiles per propagation work-group
   int n_slabs;          // propagation work-groups per trajectory
@@ -58,6 +59,7 @@ struct ClassDev {
   int32_t* occ = nullptr;   // [T][N]
   int32_t* status = nullptr;  // [T]
   int32_t* gtraj = nullptr;   // [T] global trajectory index
+  int32_t* home = nullptr;    // [T] class-local index of the trajectory held in this slot
   int64_t* nsteps = nullptr;  // [T] steps taken
   double* C64 = nullptr;    // [T][N][n_pad] complex (re, im)
   float* C32 = nullptr;     // [T][N][n_pad] complex (re, im), mixed path
@@ -168,6 +170,21 @@ __host__ __device__ inline ModelAt model_at(const ModelDev& md, double x) {
   return r;
 }
 
+// Spare copies of the state that moves with a trajectory (compaction).
+struct CompactBufs {
+  double* x = nullptr;
+  double* v = nullptr;
+  double* F = nullptr;
+  int32_t* status = nullptr;
+  int32_t* gtraj = nullptr;
+  int32_t* home = nullptr;
+  int64_t* nsteps = nullptr;
+  int32_t* occ = nullptr;  // [T][N]
+  void* C = nullptr;       // [T][N][n_pad] complex, element type of the orbitals
+  int32_t* dst = nullptr;  // [T] destination slot of each live slot
+  int32_t* n_active = nullptr;  // [1]
+};
+
 // -------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s);
@@ -190,6 +207,9 @@ hipError_t launch_lowdin(const ClassDev& c, const Counters* cnt, int every, doub
                          hipStream_t s);
 size_t lowdin_scratch_elems(const ClassDev& c);
 hipError_t launch_advance(Counters* cnt, hipStream_t s);
+hipError_t launch_compact_rank(const ClassDev& c, int32_t* dst, int32_t* n_active, hipStream_t s);
+hipError_t launch_compact_move(const ClassDev& c, const int32_t* dst, const CompactBufs& b,
+                               int precision, hipStream_t s);
 
 // Host-side bath discretisation (bath.cpp).
 int discretize(int kind, int M, double a, double b, double eps_f, double* eps, double* w);

@@ -1,0 +1,93 @@
+// Compaction of frozen trajectories (exited, at the step cap, non-finite).
+//
+// Trajectories stop at different times (a scattering trajectory leaves once
+// it has rebounded past the exit distance).  Every few hundred steps the live
+// slots [0, n_live) of a class are permuted stably so that the active
+// trajectories come first; the step kernels then visit only the leading
+// active slots.  Per-trajectory state that outlives a step moves with the
+// trajectory: position, velocity, force, status, global index, step count,
+// home index (the slot it was uploaded to, which keys its observable
+// records), occupations and orbitals.  Everything else is recomputed at the
+// start of the next step.  The hop uniforms are keyed by the global index, so
+// a trajectory's dynamics do not depend on where it sits.
+
+#include "iesh_internal.hpp"
+
+namespace iesh {
+namespace {
+
+constexpr int kRankThreads = 1024;
+constexpr int kMoveThreads = 256;
+
+// dst[t] for t < n_live: active slots keep their order at the front, frozen
+// ones follow in order.  n_active_out[0] = number of active slots.
+__global__ __launch_bounds__(kRankThreads) void k_compact_rank(ClassDev c, int32_t* dst,
+                                                                int32_t* n_active_out) {
+  __shared__ int part[kRankThreads];
+  const int tid = threadIdx.x, nl = c.n_live;
+  const int per = (nl + kRankThreads - 1) / kRankThreads;
+  const int lo = min(nl, tid * per), hi = min(nl, lo + per);
+  int mine = 0;
+  for (int t = lo; t < hi; ++t) mine += (c.status[t] & kFreezeMask) ? 0 : 1;
+  part[tid] = mine;
+  __syncthreads();
+  // inclusive scan of the per-thread counts (Hillis-Steele)
+  for (int off = 1; off < kRankThreads; off <<= 1) {
+    const int add = (tid >= off) ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  const int total = part[kRankThreads - 1];
+  int before = part[tid] - mine;  // active slots before lo
+  for (int t = lo; t < hi; ++t) {
+    const bool active = !(c.status[t] & kFreezeMask);
+    dst[t] = active ? before : total + (t - before);
+    before += active ? 1 : 0;
+  }
+  if (tid == 0) n_active_out[0] = total;
+}
+
+template <typename CT>
+__global__ __launch_bounds__(kMoveThreads) void k_compact_move(ClassDev c, const int32_t* dst,
+                                                                CompactBufs b, const CT* C,
+                                                                CT* Cs) {
+  const int t = blockIdx.x;
+  const int d = dst[t];
+  const int N = c.md.N, n_pad = c.md.n_pad;
+  if (threadIdx.x == 0) {
+    b.x[d] = c.x[t];
+    b.v[d] = c.v[t];
+    b.F[d] = c.F[t];
+    b.status[d] = c.status[t];
+    b.gtraj[d] = c.gtraj[t];
+    b.home[d] = c.home[t];
+    b.nsteps[d] = c.nsteps[t];
+  }
+  for (int r = threadIdx.x; r < N; r += kMoveThreads) b.occ[(size_t)d * N + r] = c.occ[(size_t)t * N + r];
+  const size_t len = (size_t)N * n_pad * 2;
+  const CT* src = C + (size_t)t * len;
+  CT* out = Cs + (size_t)d * len;
+  for (size_t e = threadIdx.x; e < len; e += kMoveThreads) out[e] = src[e];
+}
+
+}  // namespace
+
+hipError_t launch_compact_rank(const ClassDev& c, int32_t* dst, int32_t* n_active, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_rank, dim3(1), dim3(kRankThreads), 0, s, c, dst, n_active);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_move(const ClassDev& c, const int32_t* dst, const CompactBufs& b,
+                               int precision, hipStream_t s) {
+  if (c.n_live < 1) return hipSuccess;
+  if (precision == IESH_FP64)
+    hipLaunchKernelGGL(k_compact_move<double>, dim3(c.n_live), dim3(kMoveThreads), 0, s, c, dst, b,
+                       (const double*)c.C64, (double*)b.C);
+  else
+    hipLaunchKernelGGL(k_compact_move<float>, dim3(c.n_live), dim3(kMoveThreads), 0, s, c, dst, b,
+                       (const float*)c.C32, (float*)b.C);
+  return hipGetLastError();
+}
+
+}  // namespace iesh

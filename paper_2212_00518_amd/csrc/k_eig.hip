@@ -566,7 +566,8 @@ __global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double
 
 hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s) {
   const int precision = c.C64 ? IESH_FP64 : IESH_MIXED;
-  hipLaunchKernelGGL(k_eig_step, dim3(c.n_traj), dim3(kEigThreads), 0, s, c, dt, precision, cnt);
+  if (c.n_live < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_eig_step, dim3(c.n_live), dim3(kEigThreads), 0, s, c, dt, precision, cnt);
   return hipGetLastError();
 }
 

@@ -555,7 +555,7 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
       const double vv = L.sc_v;
       const double ekin = 0.5 * md.mass * vv * vv;
       const double epot = geo[GEO_U0] + elam;
-      double* o = c.obs + ((size_t)rec * c.n_traj + t) * IESH_N_OBS;
+      double* o = c.obs + ((size_t)rec * c.n_traj + c.home[t]) * IESH_N_OBS;
       o[IESH_OBS_PD_SURF] = pds;
       o[IESH_OBS_PD_WF] = pdw;
       o[IESH_OBS_EKIN] = ekin;
@@ -749,7 +749,7 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
         }
         const double ekin = 0.5 * md.mass * v * v;
         const double epot = geo[GEO_U0] + elam;
-        double* o = c.obs + ((size_t)rec * c.n_traj + t) * IESH_N_OBS;
+        double* o = c.obs + ((size_t)rec * c.n_traj + c.home[t]) * IESH_N_OBS;
         o[IESH_OBS_PD_SURF] = pds;
         o[IESH_OBS_PD_WF] = pdw;
         o[IESH_OBS_EKIN] = ekin;
@@ -844,7 +844,8 @@ hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt
                       iesh_event* events, int query_mode, int t0, int nt, int record,
                       int exit_enabled, double exit_x, int64_t max_steps, int precision,
                       hipStream_t s) {
-  const dim3 grid(query_mode ? nt : c.n_traj);
+  if (!query_mode && c.n_live < 1) return hipSuccess;
+  const dim3 grid(query_mode ? nt : c.n_live);
   const int t0e = query_mode ? t0 : 0;
   if (precision == IESH_FP64)
     launch_hop_p<false>(c, grid, dt, seed, cnt, events, query_mode, t0e, record, exit_enabled,
@@ -860,11 +861,12 @@ hipError_t launch_hop_filter(const ClassDev& c, double dt, uint64_t seed, Counte
                              hipStream_t s) {
   // orthonormality defect allowed for the stored orbitals
   const double delta = (precision == IESH_FP64) ? 1e-8 : 1e-3;
+  if (c.n_live < 1) return hipSuccess;
   if (precision == IESH_FP64)
-    hipLaunchKernelGGL(k_hop_filter<false>, dim3(c.n_traj), dim3(kFltThreads), 0, s, c, dt, seed,
+    hipLaunchKernelGGL(k_hop_filter<false>, dim3(c.n_live), dim3(kFltThreads), 0, s, c, dt, seed,
                        cnt, record, exit_enabled, exit_x, max_steps, delta);
   else
-    hipLaunchKernelGGL(k_hop_filter<true>, dim3(c.n_traj), dim3(kFltThreads), 0, s, c, dt, seed,
+    hipLaunchKernelGGL(k_hop_filter<true>, dim3(c.n_live), dim3(kFltThreads), 0, s, c, dt, seed,
                        cnt, record, exit_enabled, exit_x, max_steps, delta);
   return hipGetLastError();
 }

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c) {
   const int local = b >> 3;
   const int slab = local % c.n_slabs;
   const int t = (local / c.n_slabs) * 8 + xcd;
-  if (t >= c.n_traj) return;
+  if (t >= c.n_live) return;
   if (c.status[t] & kFreezeMask) return;
 
   const ModelDev& md = c.md;
@@ -341,7 +341,8 @@ hipError_t prop_prepare(const ClassDev& c, int precision) {
 }
 
 hipError_t launch_prop(const ClassDev& c, int precision, hipStream_t s) {
-  const int n_traj_pad = (c.n_traj + 7) / 8 * 8;
+  if (c.n_live < 1) return hipSuccess;
+  const int n_traj_pad = (c.n_live + 7) / 8 * 8;
   const dim3 grid(n_traj_pad * c.n_slabs);
   const size_t lds = prop_lds_bytes(c, precision);
   if (precision == IESH_FP64) return launch_prop_t<double>(c, grid, lds, s);

@@ -346,3 +346,47 @@ def test_lowdin_step_restores_orthonormality(name, M, N):
         if not near_tie:
             assert list(occ[t, :N]) == list(ref.s), t
     ens.close()
+
+
+# ------------------------------------------------------------------ compaction
+def _two_class_run(compact_every, steps=200, T=96):
+    from paper_2212_00518_amd import _lib
+    cfg = get_config("c1")
+    descs = []
+    for M in (20, 30):
+        eps, w = _lib.discretize(cfg["bath"]["kind"], M, cfg["bath"]["W"])
+        descs.append(_lib.model_desc(cfg["model"], eps, w, M // 2))
+    tm = np.arange(T) % 2
+    run = dict(n_traj=T, precision="fp64", dt=cfg["dt"], kT=cfg["kT"], seed=11,
+               record_every=10, exit_enabled=1, exit_x=2.0, compact_every=compact_every)
+    ens = _lib.Ensemble(descs, run, traj_model=tm)
+    x0, v0 = boltzmann_harmonic(T, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"], seed=5)
+    x0 = x0 - 2.0  # start below the exit distance; trajectories cross it at scattered times
+    ens.init_thermal(x0, v0)
+    obs = ens.run(steps, record=True)
+    state = ens.get_state()
+    status = ens.status()
+    evs, _ = ens.events(cap=1 << 16)
+    info = [ens.class_info(k) for k in (0, 1)]
+    ens.close()
+    return obs, state, status, evs, info
+
+
+def test_compaction_is_invisible_in_the_results():
+    """Moving exited trajectories behind the active ones (every 10 steps) and
+    visiting only the active slots changes nothing a caller can see: states,
+    statuses, observable records and hop events are bitwise those of the same
+    run without compaction, for two bath-size classes in one context."""
+    ref = _two_class_run(0)
+    got = _two_class_run(10)
+    exited = int(np.sum(ref[2] & 1))
+    assert 10 <= exited <= 90, exited  # the test exercises partial exits
+    for a, b in zip(ref[1], got[1]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(ref[2], got[2])
+    assert np.array_equal(ref[0], got[0])
+    key = lambda e: (e["step"], e["traj"], e["a"], e["b"], e["accepted"])
+    assert sorted(map(key, ref[3])) == sorted(map(key, got[3]))
+    live = sum(i["live"] for i in got[4])
+    assert live < 96 and live >= 96 - exited
+    assert all(i["live"] == i["n_traj"] for i in ref[4])
