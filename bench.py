@@ -172,6 +172,84 @@ def cpu_baseline(cfg_name, steps_per_worker):
                 one_core_s_per_traj_step=sum(per) / total, wall_s=wall)
 
 
+def scattering_bench(a):
+    """Uneven batched scattering workload: useful (active) trajectory-steps/s
+    with compaction every 100 steps."""
+    import numpy as np
+    import torch
+    from paper_2212_00518_amd import _lib
+    from workloads import get_config
+    from workloads.sampling import bath_classes, scattering_initial
+
+    cfg = get_config("c3")
+    T = a.n_traj or cfg["n_traj"]
+    classes = cfg["bath"]["M_classes"]
+    cls = bath_classes(T, classes, seed=cfg["seed"])
+    descs = []
+    for M in classes:
+        eps, w = _lib.discretize(cfg["bath"]["kind"], M, cfg["bath"]["W"])
+        descs.append(_lib.model_desc(cfg["model"], eps, w, M // 2))
+    x0, v0, _ = scattering_initial(T, cfg["model"]["mass"], cfg["x_start"], cfg["E_inc"],
+                                   seed=cfg["seed"] + 1)
+    chunk = 100
+    run = dict(n_traj=T, precision="mixed", dt=cfg["dt"], kT=0.0, seed=cfg["seed"],
+               lowdin_every=100, exit_enabled=1, exit_x=cfg["exit_x"],
+               max_steps=cfg["max_steps"], compact_every=chunk)
+    t_create = time.perf_counter()
+    ens = _lib.Ensemble(descs, run, traj_model=cls)
+    t_create = time.perf_counter() - t_create
+    ens.init_thermal(x0, v0)
+    if a.forced_lifetimes:
+        rng = np.random.default_rng(cfg["seed"] + 2)
+        caps = np.exp(rng.uniform(np.log(200.0), np.log(20000.0), size=T)).astype(np.int64)
+        ens.set_step_caps(caps)
+    info0 = [ens.class_info(k) for k in range(len(classes))]
+    ens.timing(True)  # clears the work counters; the steps below replay graphs
+    ens.timing(False)
+    visited = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < a.steps:
+        k = min(chunk, a.steps - done)
+        live = sum(ens.class_info(c)["live"] for c in range(len(classes)))
+        visited += live * k
+        ens.run(k)
+        done += k
+        print(f"# step {done}: live slots {live}", file=sys.stderr, flush=True)
+    ens.sync()
+    wall = time.perf_counter() - t0
+    _, traj_steps = ens.work()
+    status = ens.status()
+    info1 = [ens.class_info(k) for k in range(len(classes))]
+    ens.close()
+    line = {
+        "metric": "useful trajectory-steps/s (scattering, uneven M, compaction every 100 steps)",
+        "value": round(traj_steps / wall, 2),
+        "unit": "trajectory-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": 0,
+        "ms_per_step": round(1e3 * wall / a.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "M_classes": classes, "n_traj": T, "dt": cfg["dt"],
+                   "forced_lifetimes": bool(a.forced_lifetimes), "path": "mixed"},
+        "active_trajectory_steps": int(traj_steps),
+        "visited_slot_steps": int(visited),
+        "compaction_efficiency": round(traj_steps / max(visited, 1), 4),
+        "frozen_at_end": int((status != 0).sum()),
+        "tiles_per_group": {str(M): i["tiles_per_group"] for M, i in zip(classes, info0)},
+        "live_slots_at_end": {str(M): i["live"] for M, i in zip(classes, info1)},
+        "trajectories_per_class": {str(M): i["n_traj"] for M, i in zip(classes, info0)},
+        "context_creation_s": round(t_create, 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +261,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--forced-lifetimes", action="store_true",
+                    help="c3: per-trajectory step caps log-uniform in [200, 20000]")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference dispatch for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -204,6 +284,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_dispatch": x.numel() * 4, "dispatches": 3}))
+        return
+    if a.config == "c3":
+        scattering_bench(a)
         return
     from workloads import get_config, boltzmann_harmonic
 

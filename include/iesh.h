@@ -236,6 +236,12 @@ int iesh_traj_status(iesh_ctx* ctx, int32_t* status_out);
 int iesh_events(iesh_ctx* ctx, iesh_event* out, int64_t cap, int64_t* count);
 int iesh_clear_events(iesh_ctx* ctx);
 
+/* Per-trajectory step caps (host array of n_traj, global order; 0: none):
+   a trajectory freezes with IESH_TRAJ_STEPCAP once it has taken that many
+   steps, in addition to run->max_steps.  Kept until changed; state uploads
+   do not reset them. */
+int iesh_set_step_caps(iesh_ctx* ctx, const int64_t* caps);
+
 /* Per bath-size class (model index cls), 8 int32 values: number of
    trajectories, live slots (the step kernels visit slots [0, live); the
    others hold frozen trajectories after compaction), n, N, orbital tiles of

@@ -41,6 +41,7 @@ SYMBOLS = (
     "iesh_hop_probs", "iesh_adiabatic", "iesh_traj_status", "iesh_events",
     "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
     "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals", "iesh_class_info",
+    "iesh_set_step_caps",
 )
 TIMERS = ("eig", "prop", "hop", "lowdin", "filter")
 
@@ -109,6 +110,7 @@ def lib():
         L.iesh_work.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.iesh_hop_evals.argtypes = [vp, C.POINTER(C.c_int64)]
         L.iesh_class_info.argtypes = [vp, C.c_int32, ip]
+        L.iesh_set_step_caps.argtypes = [vp, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -311,6 +313,13 @@ class Ensemble:
         a, b = C.c_int64(), C.c_int64()
         self._check(lib().iesh_work(self.ctx, C.byref(a), C.byref(b)), "iesh_work")
         return a.value, b.value
+
+    def set_step_caps(self, caps):
+        caps = np.ascontiguousarray(caps, dtype=np.int64)
+        if caps.shape != (self.n_traj,):
+            raise ValueError("one cap per trajectory")
+        self._check(lib().iesh_set_step_caps(self.ctx, caps.ctypes.data_as(C.POINTER(C.c_int64))),
+                    "iesh_set_step_caps")
 
     def class_info(self, cls: int = 0):
         """(n_traj, live slots, n, N, tiles per propagation work-group,

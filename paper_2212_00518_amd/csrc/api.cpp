@@ -20,6 +20,7 @@ struct iesh_ctx {
   std::vector<std::vector<int32_t>> slot_home;  // per class: slot -> home index
   std::vector<std::vector<int32_t>> home_slot;  // per class: home index -> slot
   std::vector<CompactBufs> spare;               // per class, when compaction is enabled
+  std::vector<std::vector<int64_t>> caps_home;  // per class: step cap by home index
   iesh_run_desc run{};
   hipStream_t stream = nullptr;
   bool own_stream = false;  // created here when the caller passes none
@@ -279,9 +280,12 @@ int reset_perm(iesh_ctx* ctx) {
     auto& sh = ctx->slot_home[ci];
     auto& hs = ctx->home_slot[ci];
     for (int s = 0; s < c.n_traj; ++s) sh[s] = hs[s] = s;
-    if (c.n_traj)
+    if (c.n_traj) {
       HIPTRY(ctx, hipMemcpyAsync(c.home, sh.data(), c.n_traj * sizeof(int32_t),
                                  hipMemcpyHostToDevice, ctx->stream));
+      HIPTRY(ctx, hipMemcpyAsync(c.stepcap, ctx->caps_home[ci].data(), c.n_traj * sizeof(int64_t),
+                                 hipMemcpyHostToDevice, ctx->stream));
+    }
     if (c.n_live != c.n_traj) free_graph(ctx);
     c.n_live = c.n_traj;
   }
@@ -316,6 +320,7 @@ int compact(iesh_ctx* ctx) {
     HIPTRY(ctx, cp(c.gtraj, b.gtraj, nl * sizeof(int32_t)));
     HIPTRY(ctx, cp(c.home, b.home, nl * sizeof(int32_t)));
     HIPTRY(ctx, cp(c.nsteps, b.nsteps, nl * sizeof(int64_t)));
+    HIPTRY(ctx, cp(c.stepcap, b.stepcap, nl * sizeof(int64_t)));
     HIPTRY(ctx, cp(c.occ, b.occ, (size_t)nl * N * sizeof(int32_t)));
     HIPTRY(ctx, cp(Cdst, b.C, (size_t)nl * N * c.md.n_pad * 2 * esz));
     auto& sh = ctx->slot_home[ci];
@@ -481,6 +486,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
   ctx->slot_home.assign(n_models, {});
   ctx->home_slot.assign(n_models, {});
   ctx->spare.assign(n_models, CompactBufs{});
+  ctx->caps_home.assign(n_models, {});
   for (int t = 0; t < r.n_traj; ++t) ctx->members[ctx->traj_class[t]].push_back(t);
   for (int m = 0; m < n_models; ++m) {
     const iesh_model_desc& d = models[m];
@@ -497,6 +503,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     c.n_live = count[m];
     ctx->slot_home[m].assign(count[m], 0);
     ctx->home_slot[m].assign(count[m], 0);
+    ctx->caps_home[m].assign(count[m], 0);
     ctx->n_max = std::max(ctx->n_max, c.md.n);
     ctx->N_max = std::max(ctx->N_max, c.md.N);
     choose_slabs(c, r.precision);
@@ -506,7 +513,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
         (rc = dalloc(ctx, &c.x, T)) || (rc = dalloc(ctx, &c.v, T)) || (rc = dalloc(ctx, &c.F, T)) ||
         (rc = dalloc(ctx, &c.occ, (size_t)T * N)) || (rc = dalloc(ctx, &c.status, T)) ||
         (rc = dalloc(ctx, &c.gtraj, T)) || (rc = dalloc(ctx, &c.nsteps, T)) ||
-        (rc = dalloc(ctx, &c.home, T)) ||
+        (rc = dalloc(ctx, &c.home, T)) || (rc = dalloc(ctx, &c.stepcap, T)) ||
         (rc = dalloc(ctx, &c.lam, (size_t)T * n_pad)) || (rc = dalloc(ctx, &c.q0, (size_t)T * n_pad)) ||
         (rc = dalloc(ctx, &c.lam_mid, (size_t)T * n_pad)) ||
         (rc = dalloc(ctx, &c.geo, (size_t)T * kGeoStride)) ||
@@ -522,6 +529,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
       if ((rc = dalloc(ctx, &b.x, T)) || (rc = dalloc(ctx, &b.v, T)) || (rc = dalloc(ctx, &b.F, T)) ||
           (rc = dalloc(ctx, &b.status, T)) || (rc = dalloc(ctx, &b.gtraj, T)) ||
           (rc = dalloc(ctx, &b.home, T)) || (rc = dalloc(ctx, &b.nsteps, T)) ||
+          (rc = dalloc(ctx, &b.stepcap, T)) ||
           (rc = dalloc(ctx, &b.occ, (size_t)T * N)) || (rc = dalloc(ctx, &b.dst, T)) ||
           (rc = dalloc(ctx, &b.n_active, 1)))
         return bail(rc);
@@ -567,6 +575,25 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
   if (set_counters(ctx, 0, 0)) return bail(IESH_EDEVICE);
   if (reset_perm(ctx)) return bail(IESH_EDEVICE);
   *out = ctx;
+  return IESH_OK;
+}
+
+int iesh_set_step_caps(iesh_ctx* ctx, const int64_t* caps) {
+  if (!ctx || !caps) return IESH_EINVAL;
+  for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+    ClassDev& c = ctx->cls[ci];
+    if (!c.n_traj) continue;
+    std::vector<int64_t> h(c.n_traj);
+    for (int hm = 0; hm < c.n_traj; ++hm) {
+      const int64_t v = caps[ctx->members[ci][hm]];
+      if (v < 0) return fail(ctx, IESH_EINVAL, "negative step cap");
+      h[ctx->home_slot[ci][hm]] = v;
+      ctx->caps_home[ci][hm] = v;
+    }
+    HIPTRY(ctx, hipMemcpyAsync(c.stepcap, h.data(), h.size() * sizeof(int64_t),
+                               hipMemcpyHostToDevice, ctx->stream));
+  }
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
   return IESH_OK;
 }
 

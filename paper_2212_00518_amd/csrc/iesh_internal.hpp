@@ -61,6 +61,7 @@ struct ClassDev {
   int32_t* gtraj = nullptr;   // [T] global trajectory index
   int32_t* home = nullptr;    // [T] class-local index of the trajectory held in this slot
   int64_t* nsteps = nullptr;  // [T] steps taken
+  int64_t* stepcap = nullptr;  // [T] freeze after this many steps (0: no own cap)
   double* C64 = nullptr;    // [T][N][n_pad] complex (re, im)
   float* C32 = nullptr;     // [T][N][n_pad] complex (re, im), mixed path
   double* lam = nullptr;    // [T][n_pad] energies at the current geometry
@@ -179,6 +180,7 @@ struct CompactBufs {
   int32_t* gtraj = nullptr;
   int32_t* home = nullptr;
   int64_t* nsteps = nullptr;
+  int64_t* stepcap = nullptr;
   int32_t* occ = nullptr;  // [T][N]
   void* C = nullptr;       // [T][N][n_pad] complex, element type of the orbitals
   int32_t* dst = nullptr;  // [T] destination slot of each live slot

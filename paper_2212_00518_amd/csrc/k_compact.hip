@@ -6,9 +6,9 @@
 // trajectories come first; the step kernels then visit only the leading
 // active slots.  Per-trajectory state that outlives a step moves with the
 // trajectory: position, velocity, force, status, global index, step count,
-// home index (the slot it was uploaded to, which keys its observable
-// records), occupations and orbitals.  Everything else is recomputed at the
-// start of the next step.  The hop uniforms are keyed by the global index, so
+// step cap, home index (the slot it was uploaded to, which keys its
+// observable records), occupations and orbitals.  Everything else is
+// recomputed at the start of the next step.  The hop uniforms are keyed by the global index, so
 // a trajectory's dynamics do not depend on where it sits.
 
 #include "iesh_internal.hpp"
@@ -63,6 +63,7 @@ __global__ __launch_bounds__(kMoveThreads) void k_compact_move(ClassDev c, const
     b.gtraj[d] = c.gtraj[t];
     b.home[d] = c.home[t];
     b.nsteps[d] = c.nsteps[t];
+    b.stepcap[d] = c.stepcap[t];
   }
   for (int r = threadIdx.x; r < N; r += kMoveThreads) b.occ[(size_t)d * N + r] = c.occ[(size_t)t * N + r];
   const size_t len = (size_t)N * n_pad * 2;

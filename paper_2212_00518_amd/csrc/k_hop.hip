@@ -531,7 +531,8 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
     c.nsteps[t] = ns;
     const double x = c.x[t];
     if (exit_enabled && x > exit_x) st |= IESH_TRAJ_EXITED;
-    if (max_steps > 0 && ns >= max_steps) st |= IESH_TRAJ_STEPCAP;
+    if ((max_steps > 0 && ns >= max_steps) || (c.stepcap[t] > 0 && ns >= c.stepcap[t]))
+      st |= IESH_TRAJ_STEPCAP;
     if (!isfinite(vnew)) st |= IESH_TRAJ_NONFINITE;
     c.status[t] = st;
     L.sc_occ_changed = occ_changed;
@@ -733,7 +734,8 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
     const int64_t ns = c.nsteps[t] + 1;
     c.nsteps[t] = ns;
     if (exit_enabled && c.x[t] > exit_x) st |= IESH_TRAJ_EXITED;
-    if (max_steps > 0 && ns >= max_steps) st |= IESH_TRAJ_STEPCAP;
+    if ((max_steps > 0 && ns >= max_steps) || (c.stepcap[t] > 0 && ns >= c.stepcap[t]))
+      st |= IESH_TRAJ_STEPCAP;
     if (!isfinite(v)) st |= IESH_TRAJ_NONFINITE;
     c.status[t] = st;
     if (record) {
