@@ -1,0 +1,64 @@
+"""Pins of the oracle's tangent-linear gradient of the path loss (CPU)."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as adj
+from oracle import bath
+from workloads import get_config
+from workloads.sampling import fixed_paths
+
+
+def _case(M=8, N=4, T=12, seed=3):
+    cfg = get_config("c4")
+    m = cfg["model"]
+    eps, w = bath.discretise(cfg["bath"]["kind"], M, cfg["bath"]["W"])
+    p = adj.Params(0.0, m["Gamma"], eps, m["omega"], m["g"], m["dG"], w, m["mass"])
+    x, _ = fixed_paths(2, T, cfg["dt"], m["omega"], seed=seed)
+    return p, x[1], N, cfg["dt"]
+
+
+def test_tangent_matches_central_differences():
+    p, path, N, dt = _case()
+    theta = adj.pack(p)
+    scale = np.abs(theta).copy()
+    scale[scale == 0] = 1e-3
+    for i in range(len(theta)):
+        e = np.zeros_like(theta)
+        e[i] = 1.0
+        _, dl = adj.tangent(p, adj.unpack(e, p.w, p.mass), path, N, dt)
+        h = 1e-6 * scale[i]
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (adj.loss(adj.unpack(tp, p.w, p.mass), path, N, dt)
+              - adj.loss(adj.unpack(tm, p.w, p.mass), path, N, dt)) / (2 * h)
+        assert abs(dl - fd) <= 1e-5 * max(abs(fd), 1e-8 / scale[i]) + 1e-9, (i, dl, fd)
+
+
+def test_eps_d_and_dG_enter_alike():
+    """Along prescribed paths eps_d and dG both only shift h."""
+    p, path, N, dt = _case(T=8)
+    g = adj.gradient(p, path, N, dt)
+    M = len(p.eps)
+    assert abs(g[0] - g[4 + M]) <= 1e-10 * max(abs(g[0]), 1e-12)
+
+
+def test_tangent_is_linear_in_the_direction():
+    p, path, N, dt = _case(T=6)
+    rs = np.random.default_rng(0)
+    d1 = rs.normal(size=adj.n_params(len(p.eps))) * 1e-3
+    d2 = rs.normal(size=adj.n_params(len(p.eps))) * 1e-3
+    f = lambda d: adj.tangent(p, adj.unpack(d, p.w, p.mass), path, N, dt)[1]
+    assert np.isclose(f(d1 + 2 * d2), f(d1) + 2 * f(d2), rtol=1e-9, atol=1e-15)
+
+
+def test_loss_with_no_coupling_motion_is_the_initial_population():
+    """A path at rest: v = 0 makes A diagonal; the orbitals only pick up
+    phases, so P(t) stays the initial impurity population and E_exc = 0."""
+    p, _, N, dt = _case(T=5)
+    path = np.full(6, 1.3)
+    H, _ = adj.hamiltonian(p, 1.3)
+    from oracle.electronic import eig
+    lam, Q = eig(H)
+    P0 = np.sum(Q[0, :N] ** 2)
+    assert np.isclose(adj.loss(p, path, N, dt), P0, rtol=1e-12, atol=1e-15)
