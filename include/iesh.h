@@ -281,6 +281,40 @@ int iesh_work(iesh_ctx* ctx, int64_t* sum_cheb_terms, int64_t* traj_steps);
    were completed by the exact no-hop bound); synchronises. */
 int iesh_hop_evals(iesh_ctx* ctx, int64_t* full_evals);
 
+/* ---- adjoint along prescribed nuclear paths -------------------------------
+   Reverse-mode gradient of an electronic loss with respect to the model
+   parameters, for trajectories whose nuclear path x_0 .. x_T is given.  The
+   orbitals start as the N lowest adiabatic states at x_0 and follow the
+   orbital equation of motion above (Sec. II.C, Eq. exponential_integrator),
+   with the propagator frozen at the midpoint (x_n + x_{n+1}) / 2 and the
+   velocity (x_{n+1} - x_n) / dt over step n; no hops.  Loss of trajectory t:
+     L_t = (1/T) sum_{s=1..T} P(s) + E_exc(T),
+     P(s) = sum_o |sum_a q0_a(x_s) C_ao(s)|^2   (impurity population, Sec. III.B),
+     E_exc = sum_a lambda_a(x_T) (rho_a - n0_a), rho_a = sum_o |C_ao(T)|^2,
+   n0 the initial occupations.  Gradients are exact for the discrete
+   propagation (Chebyshev series, Sec. II.C) with the series centre and
+   radius held fixed.  Supported: IESH_FP64 contexts whose models are all
+   IESH_MODEL_HARMONIC.  Parameter layout of one gradient row (model of the
+   trajectory, M bath levels): [eps_d, Gamma, eps_1 .. eps_M, omega, g, dG];
+   the bath weights w and the mass are constants.
+
+   iesh_adjoint_forward: path (host) [n_traj][n_steps + 1] positions;
+   n_steps >= 1; the orbitals are stored every ckpt_every steps (>= 1) and
+   recomputed inside each segment by the backward pass (device memory of the
+   segment buffer: (ckpt_every + 1) copies of the orbitals).  loss_out (host,
+   n_traj, may be NULL) receives L_t.  Replaces the ensemble state (positions
+   follow the path, v is set from it, occupations n0) and releases the
+   buffers of any earlier forward pass.  IESH_ENOTSUP for unsupported
+   contexts, IESH_EINVAL for a non-finite path.
+
+   iesh_adjoint_backward: dloss (host, n_traj) weights w_t; grad_out (host)
+   [n_traj][n_max + 4] receives w_t dL_t/dtheta in the first M_t + 5 entries
+   of row t (the rest zero).  May be called again with other weights;
+   IESH_ESTATE before a forward pass.  Both calls synchronise. */
+int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int32_t ckpt_every,
+                         double* loss_out);
+int iesh_adjoint_backward(iesh_ctx* ctx, const double* dloss, double* grad_out);
+
 /* Wait for all work on the context stream; reports asynchronous errors. */
 int iesh_sync(iesh_ctx* ctx);
 

@@ -41,7 +41,7 @@ SYMBOLS = (
     "iesh_hop_probs", "iesh_adiabatic", "iesh_traj_status", "iesh_events",
     "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
     "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals", "iesh_class_info",
-    "iesh_set_step_caps",
+    "iesh_set_step_caps", "iesh_adjoint_forward", "iesh_adjoint_backward",
 )
 TIMERS = ("eig", "prop", "hop", "lowdin", "filter")
 
@@ -111,6 +111,8 @@ def lib():
         L.iesh_hop_evals.argtypes = [vp, C.POINTER(C.c_int64)]
         L.iesh_class_info.argtypes = [vp, C.c_int32, ip]
         L.iesh_set_step_caps.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.iesh_adjoint_forward.argtypes = [vp, dp, C.c_int32, C.c_int32, dp]
+        L.iesh_adjoint_backward.argtypes = [vp, dp, dp]
         _lib = L
     return _lib
 
@@ -329,6 +331,31 @@ class Ensemble:
                     "iesh_class_info")
         keys = ("n_traj", "live", "n", "N", "tiles_per_group", "groups_per_traj", "n_pad")
         return dict(zip(keys, (int(v) for v in info[:7])))
+
+    def adjoint_forward(self, path, ckpt_every: int = 100):
+        """Losses of the prescribed paths (n_traj, n_steps + 1); keeps what
+        the backward pass needs."""
+        path = np.ascontiguousarray(path, dtype=np.float64)
+        if path.ndim != 2 or path.shape[0] != self.n_traj or path.shape[1] < 2:
+            raise ValueError("path must be (n_traj, n_steps + 1) with n_steps >= 1")
+        loss = np.zeros(self.n_traj)
+        self._check(lib().iesh_adjoint_forward(self.ctx, path.ctypes.data_as(C.POINTER(C.c_double)),
+                                               path.shape[1] - 1, int(ckpt_every),
+                                               loss.ctypes.data_as(C.POINTER(C.c_double))),
+                    "iesh_adjoint_forward")
+        return loss
+
+    def adjoint_backward(self, dloss):
+        """Rows w_t dL_t/dtheta, (n_traj, n_max + 4), layout
+        [eps_d, Gamma, eps_1 .. eps_M, omega, g, dG] per row."""
+        w = np.ascontiguousarray(dloss, dtype=np.float64)
+        if w.shape != (self.n_traj,):
+            raise ValueError("one weight per trajectory")
+        g = np.zeros((self.n_traj, self.n_max + 4))
+        self._check(lib().iesh_adjoint_backward(self.ctx, w.ctypes.data_as(C.POINTER(C.c_double)),
+                                                g.ctypes.data_as(C.POINTER(C.c_double))),
+                    "iesh_adjoint_backward")
+        return g
 
     def hop_evals(self):
         n = C.c_int64()

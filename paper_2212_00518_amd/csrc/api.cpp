@@ -43,6 +43,25 @@ struct iesh_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;  // (timer, index of the start event)
+  // adjoint along prescribed paths: buffers of the last forward pass
+  struct AdjClass {
+    double* ckpt = nullptr;    // [n_ckpt][T][N][n_pad] complex: C at the segment starts
+    double* snap = nullptr;    // [seg + 1][T][N][n_pad] complex: C inside one segment
+    double* Gh = nullptr;      // [T][N][n_pad] complex: cotangent of C (Wirtinger, dL/d conj C)
+    double* taps_s = nullptr;  // [T][tap_k][N][n_pad] complex: adjoint Clenshaw vectors
+    double* taps_t = nullptr;  // [T][tap_k][N][n_pad] complex: Chebyshev vectors
+    double* imphi = nullptr;   // [T][n_pad][n_pad]
+    double* rediag = nullptr;  // [T][n_pad]
+    double* chebc = nullptr;   // [T][kChebStride] conjugated series
+  };
+  std::vector<AdjClass> adj;
+  std::vector<void*> adj_allocs;
+  double* adj_path = nullptr;  // [n_traj][n_steps + 1]
+  double* adj_loss = nullptr;  // [n_traj]
+  double* adj_w = nullptr;     // [n_traj]
+  double* adj_grad = nullptr;  // [n_traj][n_max + 4]
+  int adj_steps = 0, adj_ckpt = 0, adj_tap_k = 0;
+  bool adj_forward_done = false, adj_backward_bufs = false;
 };
 
 namespace {
@@ -396,6 +415,47 @@ int enqueue_step(iesh_ctx* ctx, int record) {
   return IESH_OK;
 }
 
+// ---- adjoint along prescribed paths ----------------------------------------
+template <typename T>
+int adj_alloc(iesh_ctx* ctx, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return IESH_OK;
+  void* q = nullptr;
+  const size_t bytes = count * sizeof(T);
+  if (hipMalloc(&q, bytes) != hipSuccess)
+    return fail(ctx, IESH_ENOMEM, "hipMalloc failed (adjoint): " + std::to_string(bytes) + " bytes");
+  ctx->adj_allocs.push_back(q);
+  if (hipMemsetAsync(q, 0, bytes, ctx->stream) != hipSuccess)
+    return fail(ctx, IESH_EDEVICE, "hipMemsetAsync failed");
+  *p = reinterpret_cast<T*>(q);
+  return IESH_OK;
+}
+
+void adj_release(iesh_ctx* ctx) {
+  (void)hipStreamSynchronize(ctx->stream);
+  for (void* p : ctx->adj_allocs) (void)hipFree(p);
+  ctx->adj_allocs.clear();
+  ctx->adj.assign(ctx->cls.size(), iesh_ctx::AdjClass{});
+  ctx->adj_path = ctx->adj_loss = ctx->adj_w = ctx->adj_grad = nullptr;
+  ctx->adj_forward_done = ctx->adj_backward_bufs = false;
+}
+
+// The class with the prescribed path attached, at step n.
+ClassDev on_path(const iesh_ctx* ctx, const ClassDev& c, int n) {
+  ClassDev cc = c;
+  cc.path = ctx->adj_path;
+  cc.path_len = ctx->adj_steps + 1;
+  cc.path_n = n;
+  return cc;
+}
+
+// One forward step along the path: eigen-solves, propagation of cc.C64.
+int adj_step(iesh_ctx* ctx, const ClassDev& cc) {
+  HIPTRY(ctx, launch_eig_step(cc, ctx->run.dt, ctx->cnt, ctx->stream));
+  HIPTRY(ctx, launch_prop(cc, IESH_FP64, ctx->stream));
+  return IESH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -419,6 +479,7 @@ int iesh_destroy(iesh_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   free_graph(ctx);
   for (void* p : ctx->allocations) (void)hipFree(p);
+  for (void* p : ctx->adj_allocs) (void)hipFree(p);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -975,6 +1036,157 @@ int iesh_hop_evals(iesh_ctx* ctx, int64_t* full_evals) {
   if (!ctx || !full_evals) return IESH_EINVAL;
   HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
   HIPTRY(ctx, hipMemcpy(full_evals, &ctx->cnt->hop_evals, sizeof(int64_t), hipMemcpyDeviceToHost));
+  return IESH_OK;
+}
+
+
+int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int32_t ckpt_every,
+                         double* loss_out) {
+  if (!ctx || !path || n_steps < 1 || ckpt_every < 1)
+    return fail(ctx, IESH_EINVAL, "adjoint: path, n_steps >= 1 and ckpt_every >= 1 required");
+  if (ctx->run.precision != IESH_FP64)
+    return fail(ctx, IESH_ENOTSUP, "adjoint: FP64 contexts only");
+  for (const auto& c : ctx->cls)
+    if (c.n_traj && c.md.kind != IESH_MODEL_HARMONIC)
+      return fail(ctx, IESH_ENOTSUP, "adjoint: harmonic (double-well) models only");
+  const int T = ctx->run.n_traj;
+  for (size_t q = 0; q < (size_t)T * (n_steps + 1); ++q)
+    if (!std::isfinite(path[q])) return fail(ctx, IESH_EINVAL, "adjoint: non-finite path");
+  adj_release(ctx);
+  ctx->adj_steps = n_steps;
+  ctx->adj_ckpt = std::min(ckpt_every, n_steps);
+  const int n_ckpt = (n_steps + ctx->adj_ckpt - 1) / ctx->adj_ckpt;
+  int rc;
+  if ((rc = adj_alloc(ctx, &ctx->adj_path, (size_t)T * (n_steps + 1))) ||
+      (rc = adj_alloc(ctx, &ctx->adj_loss, (size_t)T)))
+    return rc;
+  HIPTRY(ctx, hipMemcpyAsync(ctx->adj_path, path, (size_t)T * (n_steps + 1) * sizeof(double),
+                             hipMemcpyHostToDevice, ctx->stream));
+  for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+    const ClassDev& c = ctx->cls[ci];
+    if (!c.n_traj) continue;
+    if ((rc = adj_alloc(ctx, &ctx->adj[ci].ckpt, (size_t)n_ckpt * c.n_traj * c.md.N * c.md.n_pad * 2)))
+      return rc;
+  }
+  // start: x = path[.][0], v = 0, the N lowest adiabatic orbitals occupied
+  std::vector<double> x0(T), v0(T, 0.0);
+  for (int t = 0; t < T; ++t) x0[t] = path[(size_t)t * (n_steps + 1)];
+  if ((rc = reset_perm(ctx)) || (rc = upload_state(ctx, x0.data(), v0.data(), nullptr, nullptr)) ||
+      (rc = reset_traj_words(ctx)))
+    return rc;
+  const int64_t zero = 0;
+  HIPTRY(ctx, hipMemcpyAsync(&ctx->cnt->max_cheb, &zero, sizeof(zero), hipMemcpyHostToDevice,
+                             ctx->stream));
+  for (auto& c : ctx->cls)
+    if (c.n_traj) HIPTRY(ctx, launch_init_thermal(c, 0.0, ctx->run.seed, ctx->stream));
+  for (int n = 0; n < n_steps; ++n) {
+    for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+      const ClassDev& c = ctx->cls[ci];
+      if (!c.n_traj) continue;
+      const size_t csz = (size_t)c.n_traj * c.md.N * c.md.n_pad * 2;
+      if (n % ctx->adj_ckpt == 0)
+        HIPTRY(ctx, hipMemcpyAsync(ctx->adj[ci].ckpt + (size_t)(n / ctx->adj_ckpt) * csz, c.C64,
+                                   csz * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+      const ClassDev cc = on_path(ctx, c, n);
+      if ((rc = adj_step(ctx, cc))) return rc;
+      HIPTRY(ctx, launch_adj_loss(cc, ctx->adj_loss, n, n_steps, ctx->stream));
+    }
+  }
+  int64_t kmax = 0;
+  HIPTRY(ctx, hipMemcpyAsync(&kmax, &ctx->cnt->max_cheb, sizeof(int64_t), hipMemcpyDeviceToHost,
+                             ctx->stream));
+  if (loss_out)
+    HIPTRY(ctx, hipMemcpyAsync(loss_out, ctx->adj_loss, T * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->adj_tap_k = (int)std::max<int64_t>(kmax, 1);
+  ctx->step += n_steps;
+  ctx->adj_forward_done = true;
+  return IESH_OK;
+}
+
+int iesh_adjoint_backward(iesh_ctx* ctx, const double* dloss, double* grad_out) {
+  if (!ctx || !dloss || !grad_out) return fail(ctx, IESH_EINVAL, "adjoint: null pointer");
+  if (!ctx->adj_forward_done)
+    return fail(ctx, IESH_ESTATE, "adjoint: iesh_adjoint_forward must come first");
+  const int T = ctx->run.n_traj, nst = ctx->adj_steps, seg = ctx->adj_ckpt;
+  const int gstride = ctx->n_max + 4;
+  int rc;
+  if (!ctx->adj_backward_bufs) {
+    if ((rc = adj_alloc(ctx, &ctx->adj_w, (size_t)T)) ||
+        (rc = adj_alloc(ctx, &ctx->adj_grad, (size_t)T * gstride)))
+      return rc;
+    for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+      const ClassDev& c = ctx->cls[ci];
+      if (!c.n_traj) continue;
+      auto& a = ctx->adj[ci];
+      const size_t csz = (size_t)c.n_traj * c.md.N * c.md.n_pad * 2;
+      if ((rc = adj_alloc(ctx, &a.snap, (size_t)(seg + 1) * csz)) ||
+          (rc = adj_alloc(ctx, &a.Gh, csz)) ||
+          (rc = adj_alloc(ctx, &a.taps_s, (size_t)ctx->adj_tap_k * csz)) ||
+          (rc = adj_alloc(ctx, &a.taps_t, (size_t)ctx->adj_tap_k * csz)) ||
+          (rc = adj_alloc(ctx, &a.imphi, (size_t)c.n_traj * c.md.n_pad * c.md.n_pad)) ||
+          (rc = adj_alloc(ctx, &a.rediag, (size_t)c.n_traj * c.md.n_pad)) ||
+          (rc = adj_alloc(ctx, &a.chebc, (size_t)c.n_traj * kChebStride)))
+        return rc;
+    }
+    ctx->adj_backward_bufs = true;
+  }
+  HIPTRY(ctx, hipMemcpyAsync(ctx->adj_w, dloss, T * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPTRY(ctx, hipMemsetAsync(ctx->adj_grad, 0, (size_t)T * gstride * sizeof(double), ctx->stream));
+  for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+    const ClassDev& c = ctx->cls[ci];
+    if (!c.n_traj) continue;
+    const size_t csz = (size_t)c.n_traj * c.md.N * c.md.n_pad * 2;
+    HIPTRY(ctx, hipMemsetAsync(ctx->adj[ci].Gh, 0, csz * sizeof(double), ctx->stream));
+  }
+  const int n_ckpt = (nst + seg - 1) / seg;
+  for (int sg = n_ckpt - 1; sg >= 0; --sg) {
+    const int a0 = sg * seg, b0 = std::min(a0 + seg, nst);
+    for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+      const ClassDev& c = ctx->cls[ci];
+      if (!c.n_traj) continue;
+      auto& a = ctx->adj[ci];
+      const size_t csz = (size_t)c.n_traj * c.md.N * c.md.n_pad * 2;
+      auto snap = [&](int j) { return a.snap + (size_t)j * csz; };
+      // orbitals C_{a0} .. C_{b0} of the segment, recomputed from its checkpoint
+      HIPTRY(ctx, hipMemcpyAsync(snap(0), a.ckpt + (size_t)sg * csz, csz * sizeof(double),
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+      for (int n = a0; n < b0; ++n) {
+        HIPTRY(ctx, hipMemcpyAsync(snap(n - a0 + 1), snap(n - a0), csz * sizeof(double),
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+        ClassDev cc = on_path(ctx, c, n);
+        cc.C64 = snap(n - a0 + 1);
+        if ((rc = adj_step(ctx, cc))) return rc;
+      }
+      // reverse sweep over the segment
+      for (int n = b0 - 1; n >= a0; --n) {
+        ClassDev cc = on_path(ctx, c, n);
+        HIPTRY(ctx, launch_eig_step(cc, ctx->run.dt, ctx->cnt, ctx->stream));
+        // explicit loss terms at x_{n+1}: cotangent of C_{n+1}
+        HIPTRY(ctx, launch_adj_explicit(cc, snap(n - a0 + 1), a.Gh, ctx->adj_w, ctx->adj_grad,
+                                        gstride, n + 1, nst, ctx->stream));
+        // Chebyshev vectors of C_n under this step's propagator
+        ClassDev cf = cc;
+        cf.C64 = snap(n - a0);
+        HIPTRY(ctx, launch_prop_taps(cf, 2, a.taps_t, ctx->adj_tap_k, ctx->stream));
+        // cotangent of C_n = U^H (cotangent of C_{n+1}), keeping the adjoint vectors
+        HIPTRY(ctx, launch_conj_cheb(cc, a.chebc, ctx->stream));
+        ClassDev cg = cc;
+        cg.C64 = a.Gh;
+        cg.cheb = a.chebc;
+        HIPTRY(ctx, launch_prop_taps(cg, 1, a.taps_s, ctx->adj_tap_k, ctx->stream));
+        // through the propagator matrix into the midpoint eigen-solve
+        HIPTRY(ctx, launch_adj_phi(cc, a.taps_s, a.taps_t, ctx->adj_tap_k, a.imphi, a.rediag,
+                                   ctx->stream));
+        HIPTRY(ctx, launch_adj_mid(cc, a.imphi, a.rediag, ctx->adj_grad, gstride, n, ctx->run.dt,
+                                   ctx->stream));
+      }
+    }
+  }
+  HIPTRY(ctx, hipMemcpyAsync(grad_out, ctx->adj_grad, (size_t)T * gstride * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
   return IESH_OK;
 }
 

@@ -76,6 +76,11 @@ struct ClassDev {
   double2* low = nullptr;   // Loewdin scratch (mixed path)
   int32_t* hopq = nullptr;  // [3 + T] queue for the determinant-ratio kernel: count, -, done, list
   double2* hopx = nullptr;  // [T][N][N] inverse of S (shapes whose registers cannot hold it)
+  // prescribed nuclear path (adjoint): x of trajectory g at step n is
+  // path[g * path_len + n]; the step kernels follow it when path != nullptr
+  const double* path = nullptr;
+  int path_len = 0;
+  int path_n = 0;
 };
 
 struct Counters {
@@ -86,6 +91,7 @@ struct Counters {
   int64_t sum_cheb;      // Chebyshev terms summed over propagated trajectory-steps
   int64_t traj_steps;    // trajectory-steps taken
   int64_t hop_evals;     // trajectory-steps that needed the determinant ratios
+  int64_t max_cheb;      // largest number of Chebyshev terms used
 };
 
 // -------------------------------------------------------------------------
@@ -194,6 +200,7 @@ hipError_t launch_eig_query(const ClassDev& c, int t0, int nt, hipStream_t s);
 hipError_t launch_init_thermal(const ClassDev& c, double kT, uint64_t seed, hipStream_t s);
 hipError_t launch_forces(const ClassDev& c, hipStream_t s);
 hipError_t launch_prop(const ClassDev& c, int precision, hipStream_t s);
+hipError_t launch_prop_taps(const ClassDev& c, int mode, double* taps, int tap_k, hipStream_t s);
 int prop_max_col_tiles(int precision);
 hipError_t prop_prepare(const ClassDev& c, int precision);
 size_t prop_lds_bytes(const ClassDev& c, int precision);
@@ -209,6 +216,15 @@ hipError_t launch_lowdin(const ClassDev& c, const Counters* cnt, int every, doub
                          hipStream_t s);
 size_t lowdin_scratch_elems(const ClassDev& c);
 hipError_t launch_advance(Counters* cnt, hipStream_t s);
+// Adjoint along prescribed paths (k_eig.hip, k_adjoint.hip).
+hipError_t launch_adj_loss(const ClassDev& c, double* loss, int s, int T, hipStream_t st);
+hipError_t launch_adj_explicit(const ClassDev& c, const double* Cs, double* Gh, const double* weights,
+                               double* grads, int gstride, int s, int T, hipStream_t st);
+hipError_t launch_adj_mid(const ClassDev& c, const double* imphi, const double* rediag, double* grads,
+                          int gstride, int s, double dt, hipStream_t st);
+hipError_t launch_conj_cheb(const ClassDev& c, double* out, hipStream_t st);
+hipError_t launch_adj_phi(const ClassDev& c, const double* taps_s, const double* taps_t, int tap_k,
+                          double* imphi, double* rediag, hipStream_t st);
 hipError_t launch_compact_rank(const ClassDev& c, int32_t* dst, int32_t* n_active, hipStream_t s);
 hipError_t launch_compact_move(const ClassDev& c, const int32_t* dst, const CompactBufs& b,
                                int precision, hipStream_t s);

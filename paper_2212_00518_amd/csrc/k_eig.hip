@@ -347,9 +347,19 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt,
   const ModelDev& md = c.md;
   load_bath(c, L);
   if (tid == 0) {
-    const double x = c.x[t], v = c.v[t], F = c.F[t];
-    const double vh = v + 0.5 * dt * F / md.mass;
-    const double xn = x + dt * vh;
+    double vh, xn, x;
+    if (c.path) {
+      // prescribed path: v over the step from the two end points
+      const double* pp = c.path + (size_t)c.gtraj[t] * c.path_len + c.path_n;
+      x = pp[0];
+      xn = pp[1];
+      vh = (xn - x) / dt;
+    } else {
+      x = c.x[t];
+      const double v = c.v[t], F = c.F[t];
+      vh = v + 0.5 * dt * F / md.mass;
+      xn = x + dt * vh;
+    }
     L.sc[0] = vh;
     L.sc[1] = xn;
     L.sc[2] = 0.5 * (x + xn);
@@ -426,6 +436,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt,
       // work counters (integer sums: independent of the order of the adds)
       atomicAdd((unsigned long long*)&cnt->sum_cheb, (unsigned long long)K);
       atomicAdd((unsigned long long*)&cnt->traj_steps, 1ull);
+      atomicMax((unsigned long long*)&cnt->max_cheb, (unsigned long long)K);
     }
   }
   __syncthreads();
@@ -562,6 +573,211 @@ __global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double
   }
 }
 
+// ---------------------------------------------------------------------------
+// Reverse mode through the eigen-solve (adjoint along prescribed paths;
+// harmonic model: V_k constant, rho = 0).  With the gauge q0_j > 0 the
+// impurity amplitude is a function of the root alone, q0_j = f'(lambda_j)^{-1/2}
+// with f'(l) = 1 + sum_k V_k^2 / (l - eps_k)^2, and the roots follow from
+// f(lambda_j) = 0 by the implicit function theorem:
+//   d lambda_j / dh = q0_j^2,  d lambda_j / dV_k = 2 V_k q0_j^2 / (lambda_j - eps_k),
+//   d lambda_j / d eps_k = V_k^2 q0_j^2 / (lambda_j - eps_k)^2.
+// So cotangents (lbar, qbar) of (lambda, q0) map to (h, V, eps) in O(n M).
+// Gradient layout per trajectory: [eps_d, Gamma, eps_1 .. eps_M, omega, g, dG].
+
+struct AdjLds {
+  EigLds L;
+  double lbar[kMaxStates];
+  double qbar[kMaxStates];
+  double fb[kMaxStates];  // cotangent of f'(lambda_j)
+  double red3[kEigThreads];
+};
+
+// lambda_j - eps_k from the pole-relative representation.
+__device__ inline double lam_minus_eps(const EigLds& L, int j, int k) {
+  return -((L.e[k] - L.e[L.org[j]]) - L.tau[j]);
+}
+
+__device__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int s = kEigThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Accumulate into grad the parameter cotangents of one eigen-solve at x whose
+// (lambda, q0) cotangents are in A.lbar, A.qbar, plus hpbar for h' = dh/dx.
+__device__ void eig_backprop(const ModelDev& md, const ModelAt& ma, double x, AdjLds& A,
+                             double hpbar, double* grad) {
+  const EigLds& L = A.L;
+  const int n = md.n, M = md.M, tid = threadIdx.x;
+  // f' cotangent and the total lambda cotangent
+  for (int j = tid; j < n; j += kEigThreads) {
+    double s3 = 0.0;
+    for (int k = 0; k < M; ++k) {
+      const double d = lam_minus_eps(L, j, k);
+      s3 += L.V2[k] / (d * d * d);
+    }
+    const double q = L.q0[j];
+    const double fb = -0.5 * A.qbar[j] * q * q * q;
+    A.fb[j] = fb;
+    A.lbar[j] += fb * (-2.0 * s3);
+  }
+  __syncthreads();
+  double hpart = 0.0;
+  for (int j = tid; j < n; j += kEigThreads) hpart += A.lbar[j] * L.q0[j] * L.q0[j];
+  const double hbar = block_sum(hpart, A.red3);
+  double gpart = 0.0;
+  for (int k = tid; k < M; k += kEigThreads) {
+    const double V = sqrt(L.V2[k]);
+    double vb = 0.0, eb = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double d = lam_minus_eps(L, j, k);
+      const double q2 = L.q0[j] * L.q0[j];
+      const double lb = A.lbar[j], fb = A.fb[j];
+      vb += lb * 2.0 * V * q2 / d + fb * 2.0 * V / (d * d);
+      eb += lb * L.V2[k] * q2 / (d * d) + fb * 2.0 * L.V2[k] / (d * d * d);
+    }
+    grad[2 + k] += eb;
+    gpart += vb * V / (2.0 * md.Gamma);
+  }
+  const double Gbar = block_sum(gpart, A.red3);
+  if (tid == 0) {
+    const double omega = md.p[0], g = md.p[1], m = md.mass;
+    grad[0] += hbar;
+    grad[1] += Gbar;
+    grad[2 + M] += hbar * m * omega * (g * g - 2.0 * g * x) + hpbar * (-2.0 * m * omega * g);
+    grad[3 + M] += hbar * m * omega * omega * (g - x) + hpbar * (-m * omega * omega);
+    grad[4 + M] += hbar;
+  }
+  __syncthreads();
+}
+
+// Explicit terms of the loss at x_s (end of step s - 1, s = 1 .. T) for one
+// trajectory: Gh += w q0 z^T / T (z = C^T q0) and, at s = T, w diag(lambda) C;
+// the cotangents of q0 and lambda go through the eigen-solve into grad.
+__global__ __launch_bounds__(kEigThreads) void k_adj_explicit(ClassDev c, const double* Cs,
+                                                              double* Gh, const double* weights,
+                                                              double* grads, int gstride, int s,
+                                                              int T) {
+  __shared__ AdjLds A;
+  __shared__ double zr[kMaxElec], zi[kMaxElec];
+  EigLds& L = A.L;
+  const int t = blockIdx.x, tid = threadIdx.x;
+  const ModelDev& md = c.md;
+  const int n = md.n, n_pad = md.n_pad, N = md.N;
+  const double w = weights[c.gtraj[t]];
+  const double x = c.path[(size_t)c.gtraj[t] * c.path_len + s];
+  load_bath(c, L);
+  const ModelAt ma = solve_arrowhead(md, c.vbar, x, L);
+  const double* C = Cs + (size_t)t * N * n_pad * 2;
+  double* G = Gh + (size_t)t * N * n_pad * 2;
+  // z_o = sum_a q0_a C[o][a], one wave per orbital
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int o = wv; o < N; o += kEigThreads / 64) {
+    double ar = 0.0, ai = 0.0;
+    for (int a = lane; a < n; a += 64) {
+      ar += L.q0[a] * C[((size_t)o * n_pad + a) * 2];
+      ai += L.q0[a] * C[((size_t)o * n_pad + a) * 2 + 1];
+    }
+    for (int m = 32; m > 0; m >>= 1) {
+      ar += __shfl_xor(ar, m);
+      ai += __shfl_xor(ai, m);
+    }
+    if (lane == 0) {
+      zr[o] = ar;
+      zi[o] = ai;
+    }
+  }
+  __syncthreads();
+  const bool last = (s == T);
+  const double invT = 1.0 / T;
+  // Gh update; qbar_a = (2/T) sum_o Re(C[o][a] conj(z_o)); at T, lbar_a = rho_a - n0_a
+  for (int a = tid; a < n; a += kEigThreads) {
+    double qb = 0.0, rho = 0.0;
+    for (int o = 0; o < N; ++o) {
+      const size_t e = ((size_t)o * n_pad + a) * 2;
+      const double cr = C[e], ci = C[e + 1];
+      qb += cr * zr[o] + ci * zi[o];
+      rho += cr * cr + ci * ci;
+      double gr = invT * L.q0[a] * zr[o], gi = invT * L.q0[a] * zi[o];
+      if (last) {
+        gr += L.lam[a] * cr;
+        gi += L.lam[a] * ci;
+      }
+      G[e] += w * gr;
+      G[e + 1] += w * gi;
+    }
+    A.qbar[a] = w * 2.0 * invT * qb;
+    double lb = 0.0;
+    if (last) {
+      bool occ = false;
+      for (int r = 0; r < N; ++r) occ |= (c.occ[(size_t)t * N + r] == a);
+      lb = rho - (occ ? 1.0 : 0.0);
+    }
+    A.lbar[a] = w * lb;
+  }
+  __syncthreads();
+  eig_backprop(md, ma, x, A, 0.0, grads + (size_t)c.gtraj[t] * gstride);
+}
+
+// Midpoint of step s: from Phi = dL/dAt (ImPhi [n_pad][n_pad], ReD = Re diag)
+// with At = (A - c)/r, A = diag(lambda) - i v D, D_jk = h' q0_j q0_k /
+// (lambda_k - lambda_j): lbar_j = (2/r) Re Phi_jj, Dbar = (2 v / r) Im Phi,
+// then through D to (lambda, q0, h') and through the eigen-solve.
+__global__ __launch_bounds__(kEigThreads) void k_adj_mid(ClassDev c, const double* imphi,
+                                                         const double* rediag, double* grads,
+                                                         int gstride, int s, double dt) {
+  __shared__ AdjLds A;
+  EigLds& L = A.L;
+  const int t = blockIdx.x, tid = threadIdx.x;
+  const ModelDev& md = c.md;
+  const int n = md.n, n_pad = md.n_pad;
+  const double* pp = c.path + (size_t)c.gtraj[t] * c.path_len + s;
+  const double x0 = pp[0], x1 = pp[1];
+  const double xm = 0.5 * (x0 + x1), v = (x1 - x0) / dt;
+  const double r = 1.0 / c.cheb[(size_t)t * kChebStride + CHEB_INVR];
+  load_bath(c, L);
+  const ModelAt ma = solve_arrowhead(md, c.vbar, xm, L);
+  const double hp = ma.dh;
+  const double* P = imphi + (size_t)t * n_pad * n_pad;
+  const double sc = 2.0 * v / r;  // Dbar = sc * Im Phi
+  double hpart = 0.0;
+  for (int m = tid; m < n; m += kEigThreads) {
+    double qb = 0.0, lb = 0.0;
+    for (int k = 0; k < n; ++k) {
+      if (k == m) continue;
+      const double dkm = lam_diff(L, k, m);  // lambda_k - lambda_m
+      const double Dmk = hp * L.q0[m] * L.q0[k] / dkm;
+      const double Dkm = -Dmk;
+      const double bmk = sc * P[(size_t)m * n_pad + k], bkm = sc * P[(size_t)k * n_pad + m];
+      qb += hp * L.q0[k] * (bmk - bkm) / dkm;
+      lb += (bmk * Dmk + bkm * Dkm) / dkm;
+      hpart += bmk * L.q0[m] * L.q0[k] / dkm;
+    }
+    A.qbar[m] = qb;
+    A.lbar[m] = lb + 2.0 / r * rediag[(size_t)t * n_pad + m];
+  }
+  const double hpbar = block_sum(hpart, A.red3);
+  eig_backprop(md, ma, xm, A, hpbar, grads + (size_t)c.gtraj[t] * gstride);
+}
+
+// Chebyshev block with conjugated coefficients (the adjoint series).
+__global__ void k_conj_cheb(ClassDev c, double* out) {
+  const int t = blockIdx.x;
+  const double* in = c.cheb + (size_t)t * kChebStride;
+  double* o = out + (size_t)t * kChebStride;
+  for (int e = threadIdx.x; e < kChebStride; e += blockDim.x) {
+    const bool imag = e >= CHEB_COEF && ((e - CHEB_COEF) & 1);
+    o[e] = imag ? -in[e] : in[e];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s) {
@@ -583,6 +799,25 @@ hipError_t launch_forces(const ClassDev& c, hipStream_t s) {
 
 hipError_t launch_init_thermal(const ClassDev& c, double kT, uint64_t seed, hipStream_t s) {
   hipLaunchKernelGGL(k_init_thermal, dim3(c.n_traj), dim3(kEigThreads), 0, s, c, kT, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_explicit(const ClassDev& c, const double* Cs, double* Gh, const double* weights,
+                               double* grads, int gstride, int s, int T, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_explicit, dim3(c.n_traj), dim3(kEigThreads), 0, st, c, Cs, Gh, weights,
+                     grads, gstride, s, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_mid(const ClassDev& c, const double* imphi, const double* rediag, double* grads,
+                          int gstride, int s, double dt, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_mid, dim3(c.n_traj), dim3(kEigThreads), 0, st, c, imphi, rediag, grads,
+                     gstride, s, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_conj_cheb(const ClassDev& c, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_conj_cheb, dim3(c.n_traj), dim3(64), 0, st, c, out);
   return hipGetLastError();
 }
 

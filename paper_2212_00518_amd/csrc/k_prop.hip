@@ -100,9 +100,23 @@ struct Slab {
   const T* Bt;  // memory [KB][RT][64]
   const T* Cg;  // memory [N][n_pad] complex: the input orbitals
   const double* cb;
+  T* tap;       // memory [K][N][n_pad] complex (tap modes), this trajectory
   int n_pad, N, RT, KB, ldx, tile0, nct, K;
   T invr;
 };
+
+// Kernel modes.  kPropagate: C <- sum_k c_k T_k(At) C (Clenshaw).  kClenshawTaps:
+// the same, and b_k for k = K .. 1 is stored at tap[k - 1] (run on a cotangent
+// with conjugated coefficients it gives the adjoint vectors of the series).
+// kForwardTaps: the Chebyshev vectors t_k = T_k(At) C for k = 0 .. K-1 are
+// stored at tap[k] and C is left unchanged.
+enum PropMode { kPropagate = 0, kClenshawTaps = 1, kForwardTaps = 2 };
+
+// Store the element of a lane's accumulator tile (orbital o, row) at tap[k].
+template <typename T>
+__device__ inline void tap_store(const Slab<T>& s, int k, int o, int row, bool is_re, T val) {
+  if (o < s.N) s.tap[(((size_t)k * s.N + o) * s.n_pad + row) * 2 + (is_re ? 0 : 1)] = val;
+}
 
 // The Clenshaw loop for a wave that owns NQ output tiles: the contiguous
 // range [t0, t0 + NQ) of the slab's tiles in row-major order, so
@@ -110,7 +124,7 @@ struct Slab {
 // loads of a wave hit the L1 cache).  Each wave streams its A operands
 // (fragments of B) from memory itself, kDepth k-blocks ahead.  The k-block
 // loop has no barriers; b_{k+1} is read from LDS.
-template <typename T, int NQ>
+template <typename T, int NQ, int kMode>
 __device__ void clenshaw_tiles(const Slab<T>& s, int t0, int tid) {
   typedef PropCfg<T> Cfg;
   typedef typename Cfg::acc_t acc_t;
@@ -148,7 +162,10 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int t0, int tid) {
 #pragma unroll
   for (int q = 0; q < NQ1; ++q) roff[q] = __builtin_amdgcn_readfirstlane(prow[q] * 64 * (int)sizeof(T));
 
-  for (int k = s.K - 1; k >= 0; --k) {
+  // Clenshaw: k = K-1 .. 0 produces b_k.  Forward recurrence: k = K-1 .. 1
+  // produces t_{K-k} (the loop index only sets the buffer parity).
+  const int k_end = (kMode == kForwardTaps) ? 1 : 0;
+  for (int k = s.K - 1; k >= k_end; --k) {
     acc_t Y[NQ1];
 #pragma unroll
     for (int q = 0; q < NQ1; ++q) Y[q] = acc_t{0, 0, 0, 0};
@@ -204,8 +221,19 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int t0, int tid) {
         const T b1 = b1buf[e];
         const T yp = __shfl_xor(Y[q][r], 8);
         const T atb = s.lam[row] * b1 + (is_re ? yp : -yp);
-        // b_k replaces b_{k+2}: the element belongs to this lane alone
-        b2buf[e] = cx + scale * atb - b2buf[e];
+        if (kMode == kForwardTaps) {
+          // t_{j+1} = 2 At t_j - t_{j-1} (t_1 = At t_0) replaces t_{j-1}
+          const int j = s.K - 1 - k;
+          const T tn = ((j == 0) ? s.invr : (T)2 * s.invr) * atb - b2buf[e];
+          b2buf[e] = tn;
+          tap_store(s, j + 1, s.tile0 * 8 + pcol[q] * 8 + (lrow & 7), row, is_re, tn);
+        } else {
+          // b_k replaces b_{k+2}: the element belongs to this lane alone
+          const T bk = cx + scale * atb - b2buf[e];
+          b2buf[e] = bk;
+          if (kMode == kClenshawTaps && k >= 1)
+            tap_store(s, k - 1, s.tile0 * 8 + pcol[q] * 8 + (lrow & 7), row, is_re, bk);
+        }
       }
     }
     // b_k complete before anyone reads it; b_{k+1} free to be overwritten
@@ -213,8 +241,8 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int t0, int tid) {
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c) {
+template <typename T, int kMode>
+__global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c, T* taps, int tap_k) {
   typedef PropCfg<T> Cfg;
   extern __shared__ unsigned char smem_raw[];
 
@@ -247,6 +275,7 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c) {
   s.cb = c.cheb + (size_t)t * kChebStride;
   s.K = (int)s.cb[CHEB_K];
   s.invr = (T)s.cb[CHEB_INVR];
+  s.tap = taps ? taps + (size_t)t * tap_k * s.N * s.n_pad * 2 : nullptr;
   const T cc = (T)s.cb[CHEB_C];
 
   const int tid = threadIdx.x;
@@ -260,7 +289,9 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c) {
     T* bk = (s.K & 1) ? s.X1 : s.X0;
     T* bk1 = (s.K & 1) ? s.X0 : s.X1;
     for (int idx = tid; idx < s.n_pad * s.ldx; idx += kPropThreads) bk1[idx] = (T)0;
-    const T cr = (T)s.cb[CHEB_COEF + 2 * s.K], ci = (T)s.cb[CHEB_COEF + 2 * s.K + 1];
+    // the forward recurrence starts from t_0 = X
+    const T cr = (kMode == kForwardTaps) ? (T)1 : (T)s.cb[CHEB_COEF + 2 * s.K];
+    const T ci = (kMode == kForwardTaps) ? (T)0 : (T)s.cb[CHEB_COEF + 2 * s.K + 1];
     for (int idx = tid; idx < n_orb * s.n_pad; idx += kPropThreads) {
       const int ol = idx / s.n_pad, i = idx - ol * s.n_pad;
       const int o = s.tile0 * 8 + ol;
@@ -270,8 +301,14 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c) {
         im = Cg[((size_t)o * s.n_pad + i) * 2 + 1];
       }
       const int col = (ol >> 3) * 16 + (ol & 7);
-      bk[i * s.ldx + col] = cr * re - ci * im;
-      bk[i * s.ldx + col + 8] = cr * im + ci * re;
+      const T vre = cr * re - ci * im, vim = cr * im + ci * re;
+      bk[i * s.ldx + col] = vre;
+      bk[i * s.ldx + col + 8] = vim;
+      if (kMode != kPropagate) {
+        const int kt = (kMode == kForwardTaps) ? 0 : s.K - 1;
+        tap_store(s, kt, o, i, true, vre);
+        tap_store(s, kt, o, i, false, vim);
+      }
     }
   }
   __syncthreads();
@@ -284,19 +321,20 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c) {
   const int nq = base_q + (wave < rem_q ? 1 : 0);
   const int t0 = wave * base_q + (wave < rem_q ? wave : rem_q);
   switch (nq) {
-    case 0: clenshaw_tiles<T, 0>(s, t0, tid); break;
-    case 1: clenshaw_tiles<T, 1>(s, t0, tid); break;
-    case 2: clenshaw_tiles<T, 2>(s, t0, tid); break;
-    case 3: clenshaw_tiles<T, 3>(s, t0, tid); break;
-    case 4: clenshaw_tiles<T, 4>(s, t0, tid); break;
-    case 5: clenshaw_tiles<T, 5>(s, t0, tid); break;
-    case 6: clenshaw_tiles<T, 6>(s, t0, tid); break;
-    case 7: if constexpr (Cfg::kMaxPairs >= 7) clenshaw_tiles<T, 7>(s, t0, tid); break;
-    case 8: if constexpr (Cfg::kMaxPairs >= 8) clenshaw_tiles<T, 8>(s, t0, tid); break;
-    default: if constexpr (Cfg::kMaxPairs >= 9) clenshaw_tiles<T, 9>(s, t0, tid); break;
+    case 0: clenshaw_tiles<T, 0, kMode>(s, t0, tid); break;
+    case 1: clenshaw_tiles<T, 1, kMode>(s, t0, tid); break;
+    case 2: clenshaw_tiles<T, 2, kMode>(s, t0, tid); break;
+    case 3: clenshaw_tiles<T, 3, kMode>(s, t0, tid); break;
+    case 4: clenshaw_tiles<T, 4, kMode>(s, t0, tid); break;
+    case 5: clenshaw_tiles<T, 5, kMode>(s, t0, tid); break;
+    case 6: clenshaw_tiles<T, 6, kMode>(s, t0, tid); break;
+    case 7: if constexpr (Cfg::kMaxPairs >= 7) clenshaw_tiles<T, 7, kMode>(s, t0, tid); break;
+    case 8: if constexpr (Cfg::kMaxPairs >= 8) clenshaw_tiles<T, 8, kMode>(s, t0, tid); break;
+    default: if constexpr (Cfg::kMaxPairs >= 9) clenshaw_tiles<T, 9, kMode>(s, t0, tid); break;
   }
 
   // result (in LDS) to memory, coalesced
+  if (kMode == kForwardTaps) return;
   for (int idx = tid; idx < n_orb * s.n_pad; idx += kPropThreads) {
     const int ol = idx / s.n_pad, i = idx - ol * s.n_pad;
     const int o = s.tile0 * 8 + ol;
@@ -316,9 +354,10 @@ size_t lds_bytes_t(const ClassDev& c) {
   return sizeof(T) * (2 * n_pad * ld + n_pad);
 }
 
-template <typename T>
-hipError_t launch_prop_t(const ClassDev& c, dim3 grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_prop<T>, grid, dim3(kPropThreads), lds, s, c);
+template <typename T, int kMode>
+hipError_t launch_prop_t(const ClassDev& c, dim3 grid, size_t lds, hipStream_t s, T* taps,
+                         int tap_k) {
+  hipLaunchKernelGGL((k_prop<T, kMode>), grid, dim3(kPropThreads), lds, s, c, taps, tap_k);
   return hipGetLastError();
 }
 
@@ -336,8 +375,16 @@ size_t prop_lds_bytes(const ClassDev& c, int precision) {
 hipError_t prop_prepare(const ClassDev& c, int precision) {
   const size_t lds = prop_lds_bytes(c, precision);
   if (lds <= 64 * 1024) return hipSuccess;
-  const void* fn = (precision == IESH_FP64) ? (const void*)k_prop<double> : (const void*)k_prop<float>;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (precision == IESH_FP64) {
+    for (const void* fn : {(const void*)k_prop<double, kPropagate>, (const void*)k_prop<double, kClenshawTaps>,
+                           (const void*)k_prop<double, kForwardTaps>}) {
+      const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  return hipFuncSetAttribute((const void*)k_prop<float, kPropagate>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 hipError_t launch_prop(const ClassDev& c, int precision, hipStream_t s) {
@@ -345,8 +392,20 @@ hipError_t launch_prop(const ClassDev& c, int precision, hipStream_t s) {
   const int n_traj_pad = (c.n_live + 7) / 8 * 8;
   const dim3 grid(n_traj_pad * c.n_slabs);
   const size_t lds = prop_lds_bytes(c, precision);
-  if (precision == IESH_FP64) return launch_prop_t<double>(c, grid, lds, s);
-  return launch_prop_t<float>(c, grid, lds, s);
+  if (precision == IESH_FP64) return launch_prop_t<double, kPropagate>(c, grid, lds, s, nullptr, 0);
+  return launch_prop_t<float, kPropagate>(c, grid, lds, s, nullptr, 0);
+}
+
+// FP64 tap modes for the adjoint: mode 1 stores the Clenshaw vectors b_K .. b_1
+// of the series applied to c.C64, mode 2 the Chebyshev vectors t_0 .. t_{K-1}
+// of c.C64 (left unchanged); taps: [trajectory][tap_k][N][n_pad] complex.
+hipError_t launch_prop_taps(const ClassDev& c, int mode, double* taps, int tap_k, hipStream_t s) {
+  if (c.n_live < 1) return hipSuccess;
+  const int n_traj_pad = (c.n_live + 7) / 8 * 8;
+  const dim3 grid(n_traj_pad * c.n_slabs);
+  const size_t lds = prop_lds_bytes(c, IESH_FP64);
+  if (mode == kClenshawTaps) return launch_prop_t<double, kClenshawTaps>(c, grid, lds, s, taps, tap_k);
+  return launch_prop_t<double, kForwardTaps>(c, grid, lds, s, taps, tap_k);
 }
 
 }  // namespace iesh

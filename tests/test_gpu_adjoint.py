@@ -1,0 +1,161 @@
+"""Parity of the GPU adjoint (iesh_adjoint_forward / iesh_adjoint_backward)
+with the oracle's path loss and its tangent-linear gradient.
+
+Tolerances (FP64): loss 1e-10 relative; gradient 1e-8 relative to the
+largest gradient entry of the path (the GPU differentiates the truncated
+Chebyshev series with its centre and radius held fixed, the oracle the
+exact exponential; both errors are far below this).
+"""
+import numpy as np
+import pytest
+
+from oracle import adjoint as adj
+from workloads import get_config
+from workloads.sampling import fixed_paths
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_00518_amd import _lib
+    _lib.lib()  # fails loudly when the library is missing
+
+
+def _model(M, eps_d=0.0):
+    """The double-well model of the adjoint workload on an evenly spaced
+    band of width W (plain input data: cell centres, equal weights)."""
+    cfg = get_config("c4")
+    m = cfg["model"]
+    W = cfg["bath"]["W"]
+    eps = -0.5 * W + (np.arange(M) + 0.5) * (W / M)
+    w = np.full(M, W / M)
+    p = adj.Params(eps_d, m["Gamma"], eps, m["omega"], m["g"], m["dG"], w, m["mass"])
+    return p, cfg["dt"]
+
+
+def _ensemble(p, N, T, dt):
+    from paper_2212_00518_amd.adjoint import ensemble_for
+    return ensemble_for(adj.pack(p), p.w, p.mass, N, T, dt)
+
+
+def _paths(p, T, n_steps, dt, seed):
+    x, _ = fixed_paths(T, n_steps, dt, p.omega, seed=seed)
+    return x
+
+
+def _check_grad(g_gpu, g_ref, what):
+    scale = np.max(np.abs(g_ref))
+    err = np.max(np.abs(g_gpu - g_ref))
+    assert err <= 1e-8 * scale, (what, err, scale, np.argmax(np.abs(g_gpu - g_ref)))
+
+
+@pytest.mark.parametrize("M,N,n_steps,ckpt", [
+    (8, 4, 12, 5),     # ragged last segment
+    (20, 10, 30, 7),
+    (35, 17, 16, 16),  # one segment, n not a multiple of 16
+    (1, 1, 6, 2),      # one bath level
+])
+def test_loss_and_gradient_match_the_oracle(M, N, n_steps, ckpt):
+    p, dt = _model(M)
+    T = 3
+    x = _paths(p, T, n_steps, dt, seed=M)
+    ens = _ensemble(p, N, T, dt)
+    loss = ens.adjoint_forward(x, ckpt)
+    w = np.array([1.0, -0.5, 2.0])
+    rows = ens.adjoint_backward(w)
+    npar = adj.n_params(M)
+    assert np.all(rows[:, npar:] == 0.0)
+    for t in range(T):
+        ref = adj.loss(p, x[t], N, dt)
+        assert abs(loss[t] - ref) <= 1e-10 * abs(ref), (t, loss[t], ref)
+        g = adj.gradient(p, x[t], N, dt)
+        print(f"M={M} N={N} steps={n_steps} path {t}: loss {loss[t]:.12g}", flush=True)
+        _check_grad(rows[t, :npar], w[t] * g, f"path {t}")
+
+
+def test_full_size_model_on_short_paths():
+    """The workload's model size (M = 100, N = 50) on two short paths."""
+    p, dt = _model(100)
+    N, T, n_steps = 50, 2, 4
+    x = _paths(p, T, n_steps, dt, seed=11)
+    ens = _ensemble(p, N, T, dt)
+    loss = ens.adjoint_forward(x, 3)
+    rows = ens.adjoint_backward(np.ones(T))
+    for t in range(T):
+        ref = adj.loss(p, x[t], N, dt)
+        assert abs(loss[t] - ref) <= 1e-10 * abs(ref)
+        _check_grad(rows[t, :adj.n_params(100)], adj.gradient(p, x[t], N, dt), f"path {t}")
+
+
+def test_checkpoint_spacing_does_not_change_the_result():
+    p, dt = _model(12)
+    N, T, n_steps = 6, 4, 40
+    x = _paths(p, T, n_steps, dt, seed=5)
+    ens = _ensemble(p, N, T, dt)
+    out = []
+    for ckpt in (1, 9, 40):
+        loss = ens.adjoint_forward(x, ckpt)
+        rows = ens.adjoint_backward(np.ones(T))
+        out.append((loss, rows))
+    for loss, rows in out[1:]:
+        assert np.array_equal(loss, out[0][0])
+        assert np.array_equal(rows, out[0][1])
+
+
+def test_backward_is_linear_in_the_weights_and_repeatable():
+    p, dt = _model(10)
+    N, T, n_steps = 5, 3, 10
+    x = _paths(p, T, n_steps, dt, seed=8)
+    ens = _ensemble(p, N, T, dt)
+    ens.adjoint_forward(x, 4)
+    g1 = ens.adjoint_backward(np.ones(T))
+    g2 = ens.adjoint_backward(np.array([2.0, 0.0, -1.0]))
+    g1b = ens.adjoint_backward(np.ones(T))
+    assert np.array_equal(g1, g1b)
+    np.testing.assert_allclose(g2, g1 * np.array([2.0, 0.0, -1.0])[:, None], rtol=1e-14, atol=0)
+
+
+def test_autograd_function_sums_the_rows():
+    import torch
+    from paper_2212_00518_amd.adjoint import path_loss
+    p, dt = _model(8)
+    N, T, n_steps = 4, 3, 8
+    x = _paths(p, T, n_steps, dt, seed=2)
+    theta = torch.tensor(adj.pack(p), dtype=torch.float64, requires_grad=True)
+    L = path_loss(theta, x, p.w, p.mass, N, dt, ckpt_every=3)
+    (L * torch.tensor([1.0, 2.0, 3.0], dtype=torch.float64)).sum().backward()
+    ref = sum(c * adj.gradient(p, x[t], N, dt) for t, c in enumerate((1.0, 2.0, 3.0)))
+    _check_grad(theta.grad.numpy(), ref, "autograd")
+    for t in range(T):
+        assert abs(L[t].item() - adj.loss(p, x[t], N, dt)) <= 1e-10 * abs(L[t].item())
+
+
+def test_error_paths():
+    from paper_2212_00518_amd import _lib, from_config
+    p, dt = _model(6)
+    ens = _ensemble(p, 3, 2, dt)
+    with pytest.raises(_lib.IeshError, match="forward must come first"):
+        ens.adjoint_backward(np.ones(2))
+    x = _paths(p, 2, 4, dt, seed=1)
+    bad = x.copy()
+    bad[1, 2] = np.nan
+    with pytest.raises(_lib.IeshError, match="non-finite"):
+        ens.adjoint_forward(bad, 2)
+    with pytest.raises(_lib.IeshError, match="ckpt_every"):
+        ens.adjoint_forward(x, 0)
+    cfg = get_config("c4")
+    cfg["bath"]["M"] = 6
+    cfg["n_elec"] = 3
+    mixed = from_config(cfg, n_traj=2, precision="mixed")
+    with pytest.raises(_lib.IeshError, match="FP64"):
+        mixed.adjoint_forward(x, 2)
+    c3 = get_config("c3")
+    c3["bath"]["M"] = 6
+    c3["n_elec"] = 3
+    morse = from_config(c3, n_traj=2, precision="fp64")
+    with pytest.raises(_lib.IeshError, match="harmonic"):
+        morse.adjoint_forward(x, 2)
