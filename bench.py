@@ -250,6 +250,93 @@ def scattering_bench(a):
     print(json.dumps(line), flush=True)
 
 
+def adjoint_flops(n, N, sum_terms):
+    """Algorithmic flops of one forward + backward adjoint pass: per
+    propagated trajectory-step with K terms, the forward propagation, its
+    recomputation, the Chebyshev vectors, the adjoint Clenshaw vectors (each
+    4 n^2 N K) and the contraction Im sum_k conj(s_k) t_{k-1}^T (4 n^2 N K)."""
+    return 5.0 * algorithmic_prop_flops(n, N, sum_terms)
+
+
+def adjoint_bench(a, cfg=None, n_steps=None, report=True):
+    """Adjoint along 1024 prescribed paths (M = 100, N = 50): forward pass
+    with checkpoints every 100 steps, then the checkpointed backward pass."""
+    import numpy as np
+    import torch
+    from paper_2212_00518_amd.adjoint import ensemble_for
+    from paper_2212_00518_amd import _lib
+    from workloads import get_config
+    from workloads.sampling import fixed_paths
+
+    cfg = cfg or get_config("c4")
+    T = a.n_traj or cfg["n_traj"]
+    n_steps = n_steps or cfg["n_steps"]
+    m, b = cfg["model"], cfg["bath"]
+    M, N = b["M"], cfg["n_elec"]
+    eps, w = _lib.discretize(b["kind"], M, b["W"])
+    theta = np.concatenate([[m.get("eps_d", 0.0), m["Gamma"]], eps, [m["omega"], m["g"], m["dG"]]])
+    x, _ = fixed_paths(T, n_steps, cfg["dt"], m["omega"], seed=cfg["seed"])
+    ens = ensemble_for(theta, w, m["mass"], N, T, cfg["dt"])
+    # untimed warm-up pass on a short prefix (allocations, code objects)
+    ens.adjoint_forward(x[:, :11], 5)
+    ens.adjoint_backward(np.ones(T))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.adjoint_forward(x, cfg["ckpt_every"])
+    ens.sync()
+    t1 = time.perf_counter()
+    g = ens.adjoint_backward(np.full(T, 1.0 / T))
+    t2 = time.perf_counter()
+    fwd, bwd = t1 - t0, t2 - t1
+    # per-kernel breakdown on a shorter prefix with HIP events around every launch
+    k_steps = min(n_steps, 200)
+    ens.timing(True)
+    ens.adjoint_forward(x[:, :k_steps + 1], min(cfg["ckpt_every"], k_steps))
+    ens.adjoint_backward(np.full(T, 1.0 / T))
+    tm = ens.timing_read()
+    sum_terms, traj_steps = ens.work()
+    ens.timing(False)
+    ens.close()
+    n = M + 1
+    # every propagated trajectory-step is counted three times by the work
+    # counter (forward, recompute, reverse sweep): K per pass is sum / 3
+    sum_k = sum_terms / 3.0
+    flops = adjoint_flops(n, N, sum_k)
+    prop_ms = tm["adj_prop"][0] + tm["adj_phi"][0]
+    achieved = 0.8 * flops / (tm["adj_prop"][0] * 1e-3) / 1e12 if tm["adj_prop"][0] > 0 else 0.0
+    out = {
+        "metric": "adjoint ms/step (forward + backward, all paths)",
+        "value": round(1e3 * (fwd + bwd) / n_steps, 4),
+        "unit": "ms/step",
+        "n_gpus": 1,
+        "steps": n_steps,
+        "warmup": 10,
+        "ms_per_step": round(1e3 * (fwd + bwd) / n_steps, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "M": M, "N": N, "n_paths": T, "dt": cfg["dt"],
+                   "ckpt_every": cfg["ckpt_every"]},
+        "forward_ms_per_step": round(1e3 * fwd / n_steps, 4),
+        "backward_ms_per_step": round(1e3 * bwd / n_steps, 4),
+        "backward_over_forward": round(bwd / fwd, 3),
+        "path_steps_per_s": round(T * n_steps / (fwd + bwd), 1),
+        "roofline": {"bound": "mfma", "kernel": "k_prop (forward, recompute, tap modes)",
+                     "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TFLOPS["fp64"], 4), "traffic": None,
+                     "mean_chebyshev_terms": round(sum_k / max(traj_steps / 3.0, 1), 3)},
+        "kernels_ms_per_step": {k: round(v[0] / k_steps, 4) for k, v in tm.items() if v[1]},
+        "contraction_tflops": round(0.2 * flops / (tm["adj_phi"][0] * 1e-3) / 1e12, 3)
+        if tm["adj_phi"][0] > 0 else None,
+        "grad_norm": float(np.linalg.norm(g.sum(axis=0))),
+    }
+    if report:
+        print(json.dumps(out), flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,6 +374,9 @@ def main():
         return
     if a.config == "c3":
         scattering_bench(a)
+        return
+    if a.config == "c4":
+        adjoint_bench(a)
         return
     from workloads import get_config, boltzmann_harmonic
 

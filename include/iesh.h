@@ -257,8 +257,8 @@ typedef struct iesh_sizes {
 int iesh_query_sizes(const iesh_ctx* ctx, iesh_sizes* out);
 
 /* ---- measurement ------------------------------------------------------------
-   Per-kernel timing: while enabled, every kernel launched by iesh_step and
-   iesh_run is bracketed by HIP events on the context stream (iesh_run then
+   Per-kernel timing: while enabled, every kernel launched by iesh_step,
+   iesh_run and the adjoint calls is bracketed by HIP events on the context stream (iesh_run then
    launches eagerly instead of replaying its graph).  Enabling or disabling
    clears the accumulated times and the work counters. */
 #define IESH_TIMER_EIG 0     /* eigen-solves, couplings, Chebyshev set-up, Verlet */
@@ -266,7 +266,12 @@ int iesh_query_sizes(const iesh_ctx* ctx, iesh_sizes* out);
 #define IESH_TIMER_HOP 2     /* hop probabilities, hop, rescaling, observables   */
 #define IESH_TIMER_LOWDIN 3  /* Loewdin re-orthonormalisation (mixed path)       */
 #define IESH_TIMER_FILTER 4  /* exact no-hop bound that skips the ratio kernel    */
-#define IESH_N_TIMERS 5
+/* adjoint calls (iesh_adjoint_forward / _backward):                          */
+#define IESH_TIMER_ADJ_PROP 5  /* propagations: forward, recompute, Chebyshev and
+                                  adjoint Clenshaw vectors                     */
+#define IESH_TIMER_ADJ_PHI 6   /* contraction of the adjoint and Chebyshev vectors */
+#define IESH_TIMER_ADJ_EIG 7   /* eigen-solves and their reverse, loss terms    */
+#define IESH_N_TIMERS 8
 int iesh_timing(iesh_ctx* ctx, int32_t enable);
 /* Milliseconds and launch counts per timer (host arrays of IESH_N_TIMERS)
    since the last read; synchronises. */

@@ -43,7 +43,7 @@ SYMBOLS = (
     "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals", "iesh_class_info",
     "iesh_set_step_caps", "iesh_adjoint_forward", "iesh_adjoint_backward",
 )
-TIMERS = ("eig", "prop", "hop", "lowdin", "filter")
+TIMERS = ("eig", "prop", "hop", "lowdin", "filter", "adj_prop", "adj_phi", "adj_eig")
 
 
 class ModelDesc(C.Structure):

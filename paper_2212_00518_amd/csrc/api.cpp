@@ -451,8 +451,9 @@ ClassDev on_path(const iesh_ctx* ctx, const ClassDev& c, int n) {
 
 // One forward step along the path: eigen-solves, propagation of cc.C64.
 int adj_step(iesh_ctx* ctx, const ClassDev& cc) {
-  HIPTRY(ctx, launch_eig_step(cc, ctx->run.dt, ctx->cnt, ctx->stream));
-  HIPTRY(ctx, launch_prop(cc, IESH_FP64, ctx->stream));
+  HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_EIG,
+                    [&] { return launch_eig_step(cc, ctx->run.dt, ctx->cnt, ctx->stream); }));
+  HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_PROP, [&] { return launch_prop(cc, IESH_FP64, ctx->stream); }));
   return IESH_OK;
 }
 
@@ -1089,7 +1090,8 @@ int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int
                                    csz * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
       const ClassDev cc = on_path(ctx, c, n);
       if ((rc = adj_step(ctx, cc))) return rc;
-      HIPTRY(ctx, launch_adj_loss(cc, ctx->adj_loss, n, n_steps, ctx->stream));
+      HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_EIG,
+                        [&] { return launch_adj_loss(cc, ctx->adj_loss, n, n_steps, ctx->stream); }));
     }
   }
   int64_t kmax = 0;
@@ -1162,25 +1164,34 @@ int iesh_adjoint_backward(iesh_ctx* ctx, const double* dloss, double* grad_out) 
       // reverse sweep over the segment
       for (int n = b0 - 1; n >= a0; --n) {
         ClassDev cc = on_path(ctx, c, n);
-        HIPTRY(ctx, launch_eig_step(cc, ctx->run.dt, ctx->cnt, ctx->stream));
+        const hipStream_t st = ctx->stream;
+        HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_EIG,
+                          [&] { return launch_eig_step(cc, ctx->run.dt, ctx->cnt, st); }));
         // explicit loss terms at x_{n+1}: cotangent of C_{n+1}
-        HIPTRY(ctx, launch_adj_explicit(cc, snap(n - a0 + 1), a.Gh, ctx->adj_w, ctx->adj_grad,
-                                        gstride, n + 1, nst, ctx->stream));
+        HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_EIG, [&] {
+                 return launch_adj_explicit(cc, snap(n - a0 + 1), a.Gh, ctx->adj_w, ctx->adj_grad,
+                                            gstride, n + 1, nst, st);
+               }));
         // Chebyshev vectors of C_n under this step's propagator
         ClassDev cf = cc;
         cf.C64 = snap(n - a0);
-        HIPTRY(ctx, launch_prop_taps(cf, 2, a.taps_t, ctx->adj_tap_k, ctx->stream));
+        HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_PROP,
+                          [&] { return launch_prop_taps(cf, 2, a.taps_t, ctx->adj_tap_k, st); }));
         // cotangent of C_n = U^H (cotangent of C_{n+1}), keeping the adjoint vectors
-        HIPTRY(ctx, launch_conj_cheb(cc, a.chebc, ctx->stream));
+        HIPTRY(ctx, launch_conj_cheb(cc, a.chebc, st));
         ClassDev cg = cc;
         cg.C64 = a.Gh;
         cg.cheb = a.chebc;
-        HIPTRY(ctx, launch_prop_taps(cg, 1, a.taps_s, ctx->adj_tap_k, ctx->stream));
+        HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_PROP,
+                          [&] { return launch_prop_taps(cg, 1, a.taps_s, ctx->adj_tap_k, st); }));
         // through the propagator matrix into the midpoint eigen-solve
-        HIPTRY(ctx, launch_adj_phi(cc, a.taps_s, a.taps_t, ctx->adj_tap_k, a.imphi, a.rediag,
-                                   ctx->stream));
-        HIPTRY(ctx, launch_adj_mid(cc, a.imphi, a.rediag, ctx->adj_grad, gstride, n, ctx->run.dt,
-                                   ctx->stream));
+        HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_PHI, [&] {
+                 return launch_adj_phi(cc, a.taps_s, a.taps_t, ctx->adj_tap_k, a.imphi, a.rediag, st);
+               }));
+        HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_EIG, [&] {
+                 return launch_adj_mid(cc, a.imphi, a.rediag, ctx->adj_grad, gstride, n,
+                                       ctx->run.dt, st);
+               }));
       }
     }
   }
