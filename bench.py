@@ -348,6 +348,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint ms/step entry of the default line")
     ap.add_argument("--forced-lifetimes", action="store_true",
                     help="c3: per-trajectory step caps log-uniform in [200, 20000]")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -434,6 +436,12 @@ def main():
         line["mixed_over_fp64"] = round(r["value"] / f["value"], 3)
     if not a.no_error and "mixed" in res and "fp64" in res:
         line["mixed_error"] = mixed_vs_fp64(cfg)
+    if not a.no_adjoint:
+        # the adjoint workload's ms/step on a 200-step prefix of its paths
+        adj = adjoint_bench(argparse.Namespace(n_traj=None), n_steps=200, report=False)
+        line["adjoint"] = {k: adj[k] for k in ("metric", "value", "unit", "steps", "config",
+                                               "forward_ms_per_step", "backward_ms_per_step",
+                                               "kernels_ms_per_step", "roofline")}
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(a.config, a.cpu_steps)
     print(json.dumps(line), flush=True)

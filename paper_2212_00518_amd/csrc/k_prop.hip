@@ -20,16 +20,15 @@
 // of an orbital sit in lanes l and l^8 of the same MFMA tile and meet through
 // one lane swap.  b_{k+1} of the slab lives in LDS (B operand).  The
 // accumulator row held by a lane differs between the FP64 (row lk + 4 r) and
-// FP32 (row 4 lk + r) 16x16x4 matrix instructions.  The
-// coupling matrix B is streamed from memory through a double-buffered LDS
-// stage of two 4-column blocks (A operand), so every wave reads it from LDS.
-// The output tiles (row tile, column tile) of the slab are dealt to the
-// waves round-robin, which balances the four SIMDs for any tile count; each
-// wave keeps b_{k+2}, its component of the input X and the product of its
-// tiles in registers.  The number
-// of tiles of a wave is a template parameter (wave-uniform dispatch), so the
-// matrix-core chains carry no predication.  Work-group ids are mapped so
-// that the slabs of one trajectory land on the same XCD and share B in L2.
+// FP32 (row 4 lk + r) 16x16x4 matrix instructions.  The output tiles (row
+// tile, column tile) of the slab are split into contiguous row-major ranges,
+// one per wave; each wave streams its own A-operand fragments of the
+// coupling matrix B from memory through a buffer resource, kDepth k-blocks
+// ahead in registers, and keeps its component of the input X and the product
+// of its tiles in registers.  The number of tiles of a wave is a template
+// parameter (wave-uniform dispatch), so the matrix-core chains carry no
+// predication.  Work-group ids are mapped so that the slabs of one
+// trajectory land on the same XCD and share B in L2.
 
 #include "iesh_internal.hpp"
 

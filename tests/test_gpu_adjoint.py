@@ -159,3 +159,31 @@ def test_error_paths():
     morse = from_config(c3, n_traj=2, precision="fp64")
     with pytest.raises(_lib.IeshError, match="harmonic"):
         morse.adjoint_forward(x, 2)
+
+
+def test_gradient_matches_central_differences_of_the_gpu_loss():
+    """Central differences (h = 1e-6 relative) of the GPU's own loss agree
+    with its adjoint gradient to 1e-6 of the largest entry."""
+    p, dt = _model(8)
+    N, T, n_steps = 4, 2, 12
+    x = _paths(p, T, n_steps, dt, seed=21)
+    theta = adj.pack(p)
+    ens = _ensemble(p, N, T, dt)
+    ens.adjoint_forward(x, 5)
+    g = ens.adjoint_backward(np.ones(T))[:, :len(theta)]
+    fd = np.zeros_like(g)
+    from paper_2212_00518_amd.adjoint import ensemble_for
+    for i in range(len(theta)):
+        h = 1e-6 * max(abs(theta[i]), 1e-3)
+        vals = []
+        for sgn in (1.0, -1.0):
+            th = theta.copy()
+            th[i] += sgn * h
+            e = ensemble_for(th, p.w, p.mass, N, T, dt)
+            vals.append(e.adjoint_forward(x, 5))
+            e.close()
+        fd[:, i] = (vals[0] - vals[1]) / (2 * h)
+    for t in range(T):
+        scale = np.max(np.abs(g[t]))
+        err = np.abs(g[t] - fd[t])
+        assert np.all(err <= 1e-6 * scale + 1e-6 * np.abs(fd[t])), (t, np.max(err), scale)
