@@ -17,18 +17,26 @@ the matrix A = diag(lambda) - i v D is frozen at the midpoint
 exp(-i A dt) C_n.  The initial orbitals are the unit vectors of the N lowest
 adiabatic states at x_0 (occupations n0).
 
-Loss of one path:
-    L = (1/T) sum_{t=1..T} P(t) + E_exc(T),
+Loss of one path, with term weights (c_P, c_E, c_G, c_F) (default 1, 1, 0, 0):
+    L = c_P (1/T) sum_{t=1..T} P(t) + c_E E_exc(T) + c_G (1/T) sum_t G(t) + c_F (1/T) sum_t F(t),
     P(t)    = sum_n |sum_a Q0_a(x_t) C_an(t)|^2          (impurity population),
-    E_exc   = sum_a lambda_a(x_T) (rho_aa - n0_a),  rho_aa = sum_n |C_an(T)|^2.
+    E_exc   = sum_a lambda_a(x_T) (rho_aa - n0_a),  rho_aa = sum_n |C_an(T)|^2,
+    G(t)    = sum_{a occupied, b not} g_ab(t)          (accumulated hop probability),
+    g_ab    = max(-2 dt v_t D_ba(x_t) Re W_b,r(a), 0),  W = C_U S^-1 (Eqs.
+              hopping_probability and hopping_rate, determinant-ratio form),
+    F(t)    = -dU0/dx(x_t) - h'(x_t) sum_{a occupied} Q0_a(x_t)^2
+              (Hellmann-Feynman force, Eq. classical_hamiltonian),
+with the occupations n0 held along the path (no hops), v_t = (x_t - x_{t-1})/dt
+and D_jk = h' Q0_j Q0_k / (lambda_k - lambda_j) at x_t.
 
 ``loss`` evaluates it plainly; ``tangent`` propagates one directional
 derivative alongside (forward mode): eigenvalue and eigenvector perturbation
 of the dense H, the derivative of the couplings, and the Frechet derivative
 of the matrix exponential from the eigendecomposition of A,
     L(X, E) = P (Phi o (P^H E P)) P^H,  Phi_jk = (e^{x_j} - e^{x_k}) / (x_j - x_k).
-Pins: central finite differences of ``loss``; d L / d eps_d = d L / d dG
-(both only shift h).
+Pins: central finite differences of ``loss`` for every term; d L / d eps_d =
+d L / d dG (both only shift h, in every term); G(t) against the oracle's determinant-ratio hop probabilities and F(t)
+against its Hellmann-Feynman force, both computed from the dense model.
 """
 from __future__ import annotations
 
@@ -117,8 +125,22 @@ def _initial(p, x0, N):
     return C, n0
 
 
-def loss(p: Params, path, N, dt):
+def _hop_sum(C, N, D, v, dt):
+    """G = sum of the hop probabilities out of the occupied orbitals 0 .. N-1
+    (the N lowest, so r(a) = a) into every other orbital."""
+    S, CU = C[:N, :], C[N:, :]
+    W = CU @ np.linalg.inv(S)
+    y = -2.0 * dt * v * D[N:, :N] * W.real
+    return np.sum(np.maximum(y, 0.0))
+
+
+def _force(p: Params, x, q0, N, hp):
+    return -p.mass * p.omega ** 2 * x - hp * np.sum(q0[:N] ** 2)
+
+
+def loss(p: Params, path, N, dt, terms=(1.0, 1.0, 0.0, 0.0)):
     """Loss of one prescribed path x_0 .. x_T (array of T + 1 positions)."""
+    cP, cE, cG, cF = terms
     T = len(path) - 1
     C, n0 = _initial(p, path[0], N)
     total = 0.0
@@ -131,13 +153,17 @@ def loss(p: Params, path, N, dt):
         A = np.diag(lam).astype(np.complex128) - 1j * v * D
         mu, P = np.linalg.eigh(A)
         C = P @ (np.exp(-1j * mu * dt)[:, None] * (P.conj().T @ C))
-        H1, _ = hamiltonian(p, path[s + 1])
+        H1, hp1 = hamiltonian(p, path[s + 1])
         lam1, Q1 = eig(H1)
         z = C.T @ Q1[0, :]
-        total += np.sum(np.abs(z) ** 2) / T
+        total += cP * np.sum(np.abs(z) ** 2) / T
+        if cG:
+            total += cG * _hop_sum(C, N, _couplings(lam1, Q1, hp1), v, dt) / T
+        if cF:
+            total += cF * _force(p, path[s + 1], Q1[0, :], N, hp1) / T
         if s == T - 1:
             rho = np.sum(np.abs(C) ** 2, axis=1)
-            total += np.sum(lam1 * (rho - n0))
+            total += cE * np.sum(lam1 * (rho - n0))
     return total
 
 
@@ -169,8 +195,24 @@ def _frechet_exp(mu, P, E, dt):
     return P @ (Phi * (P.conj().T @ E @ P)) @ P.conj().T
 
 
-def tangent(p: Params, d: Params, path, N, dt):
+def _coupling_dir(lam, q0, hp, dlam, dq0, dhp):
+    """D and its directional derivative from (lambda, q0, h') and theirs."""
+    n = len(lam)
+    diff = lam[None, :] - lam[:, None]
+    ddiff = dlam[None, :] - dlam[:, None]
+    off = ~np.eye(n, dtype=bool)
+    G = hp * np.outer(q0, q0)
+    dG = dhp * np.outer(q0, q0) + hp * (np.outer(dq0, q0) + np.outer(q0, dq0))
+    D = np.zeros((n, n))
+    dD = np.zeros((n, n))
+    D[off] = G[off] / diff[off]
+    dD[off] = (dG[off] - D[off] * ddiff[off]) / diff[off]
+    return D, dD
+
+
+def tangent(p: Params, d: Params, path, N, dt, terms=(1.0, 1.0, 0.0, 0.0)):
     """(loss, directional derivative of the loss along d), forward mode."""
+    cP, cE, cG, cF = terms
     T = len(path) - 1
     C, n0 = _initial(p, path[0], N)
     dC = np.zeros_like(C)
@@ -201,23 +243,38 @@ def tangent(p: Params, d: Params, path, N, dt):
         dU = _frechet_exp(mu, P, -1j * dt * dA, dt)
         dC = U @ dC + dU @ C
         C = U @ C
-        H1, _ = hamiltonian(p, path[s + 1])
-        dH1, _ = hamiltonian_dir(p, d, path[s + 1])
+        H1, hp1 = hamiltonian(p, path[s + 1])
+        dH1, dhp1 = hamiltonian_dir(p, d, path[s + 1])
         lam1, Q1 = eig(H1)
         dlam1, dQ1 = _eig_dir(lam1, Q1, dH1)
         z = C.T @ Q1[0, :]
         dz = dC.T @ Q1[0, :] + C.T @ dQ1[0, :]
-        total += np.sum(np.abs(z) ** 2) / T
-        dtotal += 2.0 * np.sum((z.conj() * dz).real) / T
+        total += cP * np.sum(np.abs(z) ** 2) / T
+        dtotal += cP * 2.0 * np.sum((z.conj() * dz).real) / T
+        if cG:
+            D1, dD1 = _coupling_dir(lam1, Q1[0, :], hp1, dlam1, dQ1[0, :], dhp1)
+            X = np.linalg.inv(C[:N, :])
+            W = C[N:, :] @ X
+            dW = (dC[N:, :] - W @ dC[:N, :]) @ X
+            y = -2.0 * dt * v * D1[N:, :N] * W.real
+            dy = -2.0 * dt * v * (dD1[N:, :N] * W.real + D1[N:, :N] * dW.real)
+            total += cG * np.sum(np.maximum(y, 0.0)) / T
+            dtotal += cG * np.sum(np.where(y > 0.0, dy, 0.0)) / T
+        if cF:
+            q0 = Q1[0, :N]
+            total += cF * _force(p, path[s + 1], Q1[0, :], N, hp1) / T
+            dF = (-p.mass * 2.0 * p.omega * d.omega * path[s + 1] - dhp1 * np.sum(q0 ** 2)
+                  - hp1 * 2.0 * np.sum(q0 * dQ1[0, :N]))
+            dtotal += cF * dF / T
         if s == T - 1:
             rho = np.sum(np.abs(C) ** 2, axis=1)
             drho = 2.0 * np.sum((C.conj() * dC).real, axis=1)
-            total += np.sum(lam1 * (rho - n0))
-            dtotal += np.sum(dlam1 * (rho - n0) + lam1 * drho)
+            total += cE * np.sum(lam1 * (rho - n0))
+            dtotal += cE * np.sum(dlam1 * (rho - n0) + lam1 * drho)
     return total, dtotal
 
 
-def gradient(p: Params, path, N, dt):
+def gradient(p: Params, path, N, dt, terms=(1.0, 1.0, 0.0, 0.0)):
     """Full gradient by one tangent sweep per parameter (test sizes only)."""
     M = len(p.eps)
     g = np.zeros(n_params(M))
@@ -225,5 +282,5 @@ def gradient(p: Params, path, N, dt):
         e = np.zeros(n_params(M))
         e[i] = 1.0
         d = unpack(e, p.w, p.mass)
-        g[i] = tangent(p, d, path, N, dt)[1]
+        g[i] = tangent(p, d, path, N, dt, terms)[1]
     return g

@@ -62,3 +62,65 @@ def test_loss_with_no_coupling_motion_is_the_initial_population():
     lam, Q = eig(H)
     P0 = np.sum(Q[0, :N] ** 2)
     assert np.isclose(adj.loss(p, path, N, dt), P0, rtol=1e-12, atol=1e-15)
+
+
+TERMS = (0.7, 0.3, 1.5, 2.0)
+
+
+def test_every_loss_term_matches_central_differences():
+    p, path, N, dt = _case(T=10, seed=4)
+    theta = adj.pack(p)
+    scale = np.abs(theta).copy()
+    scale[scale == 0] = 1e-3
+    g = adj.gradient(p, path, N, dt, TERMS)
+    for i in range(len(theta)):
+        h = 1e-6 * scale[i]
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (adj.loss(adj.unpack(tp, p.w, p.mass), path, N, dt, TERMS)
+              - adj.loss(adj.unpack(tm, p.w, p.mass), path, N, dt, TERMS)) / (2 * h)
+        assert abs(g[i] - fd) <= 1e-5 * max(abs(fd), 1e-8 / scale[i]) + 1e-9, (i, g[i], fd)
+
+
+def test_eps_d_and_dG_enter_alike_in_every_term():
+    p, path, N, dt = _case(T=6, seed=9)
+    g = adj.gradient(p, path, N, dt, TERMS)
+    M = len(p.eps)
+    assert abs(g[0] - g[4 + M]) <= 1e-10 * max(abs(g[0]), 1e-12)
+
+
+def _dense_model(p):
+    from oracle.models import Harmonic
+    return Harmonic(p.eps, p.w, p.Gamma, p.mass, p.omega, p.g, p.dG, eps_d=p.eps_d)
+
+
+def test_hop_term_is_the_sum_of_the_determinant_ratio_probabilities():
+    """G(t) equals the total of the hop probabilities of the dynamics'
+    determinant-ratio evaluation on the dense model (itself pinned by brute
+    force determinants), for random orbitals and both signs of v."""
+    from oracle import electronic as el
+    from workloads.sampling import random_orbitals
+    p, _, N, dt = _case(M=10, N=5)
+    m = _dense_model(p)
+    for seed, x, v in ((1, 2.5, 3e-4), (2, -4.0, -5e-4), (3, 0.7, 1e-3)):
+        lam, Q = el.eig(m.H(np.array([x])))
+        _, Ds = el.coupling_matrices(lam, Q, m.dH(np.array([x])))
+        C = random_orbitals(len(lam), N, seed=seed)
+        ref = el.hop_probabilities(C, np.arange(N), v * Ds[0], dt)[0].sum()
+        H, hp = adj.hamiltonian(p, x)
+        lam2, Q2 = el.eig(H)
+        got = adj._hop_sum(C, N, adj._couplings(lam2, Q2, hp), v, dt)
+        assert ref > 0
+        assert abs(got - ref) <= 1e-12 * ref
+
+
+def test_force_term_is_the_hellmann_feynman_force():
+    from oracle import electronic as el
+    p, _, N, dt = _case(M=12, N=6)
+    m = _dense_model(p)
+    for x in (-3.0, 0.5, 6.0):
+        ref = el.forces(m, np.array([x]), np.arange(N))[0]
+        H, hp = adj.hamiltonian(p, x)
+        lam, Q = el.eig(H)
+        assert abs(adj._force(p, x, Q[0, :], N, hp) - ref) <= 1e-12 * abs(ref)
