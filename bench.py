@@ -260,7 +260,9 @@ def adjoint_flops(n, N, sum_terms):
 
 def adjoint_bench(a, cfg=None, n_steps=None, report=True):
     """Adjoint along 1024 prescribed paths (M = 100, N = 50): forward pass
-    with checkpoints every 100 steps, then the checkpointed backward pass."""
+    with checkpoints every 100 steps, then the checkpointed backward pass.
+    The loss carries all four terms (population, excitation energy,
+    accumulated hop probability, Hellmann-Feynman force), weights 1."""
     import numpy as np
     import torch
     from paper_2212_00518_amd.adjoint import ensemble_for
@@ -278,11 +280,12 @@ def adjoint_bench(a, cfg=None, n_steps=None, report=True):
     x, _ = fixed_paths(T, n_steps, cfg["dt"], m["omega"], seed=cfg["seed"])
     ens = ensemble_for(theta, w, m["mass"], N, T, cfg["dt"])
     # untimed warm-up pass on a short prefix (allocations, code objects)
-    ens.adjoint_forward(x[:, :11], 5)
+    terms = (1.0, 1.0, 1.0, 1.0)
+    ens.adjoint_forward(x[:, :11], 5, terms)
     ens.adjoint_backward(np.ones(T))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ens.adjoint_forward(x, cfg["ckpt_every"])
+    ens.adjoint_forward(x, cfg["ckpt_every"], terms)
     ens.sync()
     t1 = time.perf_counter()
     g = ens.adjoint_backward(np.full(T, 1.0 / T))
@@ -291,7 +294,7 @@ def adjoint_bench(a, cfg=None, n_steps=None, report=True):
     # per-kernel breakdown on a shorter prefix with HIP events around every launch
     k_steps = min(n_steps, 200)
     ens.timing(True)
-    ens.adjoint_forward(x[:, :k_steps + 1], min(cfg["ckpt_every"], k_steps))
+    ens.adjoint_forward(x[:, :k_steps + 1], min(cfg["ckpt_every"], k_steps), terms)
     ens.adjoint_backward(np.full(T, 1.0 / T))
     tm = ens.timing_read()
     sum_terms, traj_steps = ens.work()
@@ -318,7 +321,7 @@ def adjoint_bench(a, cfg=None, n_steps=None, report=True):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "M": M, "N": N, "n_paths": T, "dt": cfg["dt"],
-                   "ckpt_every": cfg["ckpt_every"]},
+                   "ckpt_every": cfg["ckpt_every"], "loss_terms": list(terms)},
         "forward_ms_per_step": round(1e3 * fwd / n_steps, 4),
         "backward_ms_per_step": round(1e3 * bwd / n_steps, 4),
         "backward_over_forward": round(bwd / fwd, 3),

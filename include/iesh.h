@@ -271,7 +271,8 @@ int iesh_query_sizes(const iesh_ctx* ctx, iesh_sizes* out);
                                   adjoint Clenshaw vectors                     */
 #define IESH_TIMER_ADJ_PHI 6   /* contraction of the adjoint and Chebyshev vectors */
 #define IESH_TIMER_ADJ_EIG 7   /* eigen-solves and their reverse, loss terms    */
-#define IESH_N_TIMERS 8
+#define IESH_TIMER_ADJ_HOP 8   /* hop-probability term and its reverse          */
+#define IESH_N_TIMERS 9
 int iesh_timing(iesh_ctx* ctx, int32_t enable);
 /* Milliseconds and launch counts per timer (host arrays of IESH_N_TIMERS)
    since the last read; synchronises. */
@@ -292,11 +293,18 @@ int iesh_hop_evals(iesh_ctx* ctx, int64_t* full_evals);
    orbitals start as the N lowest adiabatic states at x_0 and follow the
    orbital equation of motion above (Sec. II.C, Eq. exponential_integrator),
    with the propagator frozen at the midpoint (x_n + x_{n+1}) / 2 and the
-   velocity (x_{n+1} - x_n) / dt over step n; no hops.  Loss of trajectory t:
-     L_t = (1/T) sum_{s=1..T} P(s) + E_exc(T),
+   velocity (x_{n+1} - x_n) / dt over step n; no hops (the occupations stay
+   n0).  Loss of trajectory t with term weights terms = (c_P, c_E, c_G, c_F):
+     L_t = c_P (1/T) sum_{s=1..T} P(s) + c_E E_exc(T) + c_G (1/T) sum_s G(s)
+           + c_F (1/T) sum_s F(s),
      P(s) = sum_o |sum_a q0_a(x_s) C_ao(s)|^2   (impurity population, Sec. III.B),
      E_exc = sum_a lambda_a(x_T) (rho_a - n0_a), rho_a = sum_o |C_ao(T)|^2,
-   n0 the initial occupations.  Gradients are exact for the discrete
+     G(s) = sum over occupied a, unoccupied b of the hop probabilities
+            g_ab = max(-2 dt v_s D_ba Re W_b,r(a), 0) (Eqs. hopping_probability
+            and hopping_rate, W = C_U S^-1), v_s = (x_s - x_{s-1}) / dt,
+     F(s) = -dU0/dx(x_s) - h' sum_{a in n0} q0_a(x_s)^2 (Hellmann-Feynman
+            force, Eq. classical_hamiltonian).
+   A singular S at some step drops that step's G term (value and gradient).  Gradients are exact for the discrete
    propagation (Chebyshev series, Sec. II.C) with the series centre and
    radius held fixed.  Supported: IESH_FP64 contexts whose models are all
    IESH_MODEL_HARMONIC.  Parameter layout of one gradient row (model of the
@@ -306,8 +314,9 @@ int iesh_hop_evals(iesh_ctx* ctx, int64_t* full_evals);
    iesh_adjoint_forward: path (host) [n_traj][n_steps + 1] positions;
    n_steps >= 1; the orbitals are stored every ckpt_every steps (>= 1) and
    recomputed inside each segment by the backward pass (device memory of the
-   segment buffer: (ckpt_every + 1) copies of the orbitals).  loss_out (host,
-   n_traj, may be NULL) receives L_t.  Replaces the ensemble state (positions
+   segment buffer: (ckpt_every + 1) copies of the orbitals).  terms (host, 4
+   doubles) or NULL for (1, 1, 0, 0).  loss_out (host, n_traj, may be NULL)
+   receives L_t.  Replaces the ensemble state (positions
    follow the path, v is set from it, occupations n0) and releases the
    buffers of any earlier forward pass.  IESH_ENOTSUP for unsupported
    contexts, IESH_EINVAL for a non-finite path.
@@ -317,7 +326,7 @@ int iesh_hop_evals(iesh_ctx* ctx, int64_t* full_evals);
    of row t (the rest zero).  May be called again with other weights;
    IESH_ESTATE before a forward pass.  Both calls synchronise. */
 int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int32_t ckpt_every,
-                         double* loss_out);
+                         const double* terms, double* loss_out);
 int iesh_adjoint_backward(iesh_ctx* ctx, const double* dloss, double* grad_out);
 
 /* Wait for all work on the context stream; reports asynchronous errors. */

@@ -43,7 +43,7 @@ SYMBOLS = (
     "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals", "iesh_class_info",
     "iesh_set_step_caps", "iesh_adjoint_forward", "iesh_adjoint_backward",
 )
-TIMERS = ("eig", "prop", "hop", "lowdin", "filter", "adj_prop", "adj_phi", "adj_eig")
+TIMERS = ("eig", "prop", "hop", "lowdin", "filter", "adj_prop", "adj_phi", "adj_eig", "adj_hop")
 
 
 class ModelDesc(C.Structure):
@@ -111,7 +111,7 @@ def lib():
         L.iesh_hop_evals.argtypes = [vp, C.POINTER(C.c_int64)]
         L.iesh_class_info.argtypes = [vp, C.c_int32, ip]
         L.iesh_set_step_caps.argtypes = [vp, C.POINTER(C.c_int64)]
-        L.iesh_adjoint_forward.argtypes = [vp, dp, C.c_int32, C.c_int32, dp]
+        L.iesh_adjoint_forward.argtypes = [vp, dp, C.c_int32, C.c_int32, dp, dp]
         L.iesh_adjoint_backward.argtypes = [vp, dp, dp]
         _lib = L
     return _lib
@@ -332,15 +332,19 @@ class Ensemble:
         keys = ("n_traj", "live", "n", "N", "tiles_per_group", "groups_per_traj", "n_pad")
         return dict(zip(keys, (int(v) for v in info[:7])))
 
-    def adjoint_forward(self, path, ckpt_every: int = 100):
-        """Losses of the prescribed paths (n_traj, n_steps + 1); keeps what
-        the backward pass needs."""
+    def adjoint_forward(self, path, ckpt_every: int = 100, terms=(1.0, 1.0, 0.0, 0.0)):
+        """Losses of the prescribed paths (n_traj, n_steps + 1) with term
+        weights (c_P, c_E, c_G, c_F); keeps what the backward pass needs."""
         path = np.ascontiguousarray(path, dtype=np.float64)
         if path.ndim != 2 or path.shape[0] != self.n_traj or path.shape[1] < 2:
             raise ValueError("path must be (n_traj, n_steps + 1) with n_steps >= 1")
+        tw = np.ascontiguousarray(terms, dtype=np.float64)
+        if tw.shape != (4,):
+            raise ValueError("terms: four weights (c_P, c_E, c_G, c_F)")
         loss = np.zeros(self.n_traj)
         self._check(lib().iesh_adjoint_forward(self.ctx, path.ctypes.data_as(C.POINTER(C.c_double)),
                                                path.shape[1] - 1, int(ckpt_every),
+                                               tw.ctypes.data_as(C.POINTER(C.c_double)),
                                                loss.ctypes.data_as(C.POINTER(C.c_double))),
                     "iesh_adjoint_forward")
         return loss

@@ -34,11 +34,11 @@ class PathLoss(torch.autograd.Function):
     """losses (n_traj,) = L(theta; paths); d/dtheta through the GPU adjoint."""
 
     @staticmethod
-    def forward(ctx, theta, paths, bath_w, mass, n_elec, dt, ckpt_every):
+    def forward(ctx, theta, paths, bath_w, mass, n_elec, dt, ckpt_every, terms):
         p = np.ascontiguousarray(paths.detach().cpu().numpy() if torch.is_tensor(paths) else paths,
                                  dtype=np.float64)
         ens = ensemble_for(theta.detach().cpu().numpy(), bath_w, mass, n_elec, p.shape[0], dt)
-        loss = ens.adjoint_forward(p, ckpt_every)
+        loss = ens.adjoint_forward(p, ckpt_every, terms)
         ctx.ens = ens
         ctx.n_par = theta.shape[0]
         ctx.theta_dtype, ctx.theta_device = theta.dtype, theta.device
@@ -50,9 +50,10 @@ class PathLoss(torch.autograd.Function):
         rows = ctx.ens.adjoint_backward(w)
         g = rows[:, :ctx.n_par].sum(axis=0)
         gt = torch.from_numpy(g).to(dtype=ctx.theta_dtype, device=ctx.theta_device)
-        return gt, None, None, None, None, None, None
+        return gt, None, None, None, None, None, None, None
 
 
-def path_loss(theta, paths, bath_w, mass, n_elec, dt, ckpt_every=100):
-    """Per-path losses, differentiable in theta (a float64 tensor of M + 5)."""
-    return PathLoss.apply(theta, paths, bath_w, mass, n_elec, dt, ckpt_every)
+def path_loss(theta, paths, bath_w, mass, n_elec, dt, ckpt_every=100, terms=(1.0, 1.0, 0.0, 0.0)):
+    """Per-path losses, differentiable in theta (a float64 tensor of M + 5);
+    terms = weights of the population, excitation, hop and force terms."""
+    return PathLoss.apply(theta, paths, bath_w, mass, n_elec, dt, ckpt_every, tuple(terms))

@@ -53,6 +53,8 @@ struct iesh_ctx {
     double* imphi = nullptr;   // [T][n_pad][n_pad]
     double* rediag = nullptr;  // [T][n_pad]
     double* chebc = nullptr;   // [T][kChebStride] conjugated series
+    double* hopscr = nullptr;  // hop-term scratch (S | I, W, Gbar_U, R, Dbar per trajectory)
+    double* hopbar = nullptr;  // [T][2 n_pad + 1] hop-term cotangents of (q0, lambda, h')
   };
   std::vector<AdjClass> adj;
   std::vector<void*> adj_allocs;
@@ -61,6 +63,7 @@ struct iesh_ctx {
   double* adj_w = nullptr;     // [n_traj]
   double* adj_grad = nullptr;  // [n_traj][n_max + 4]
   int adj_steps = 0, adj_ckpt = 0, adj_tap_k = 0;
+  AdjTerms adj_terms{1.0, 1.0, 0.0, 0.0};
   bool adj_forward_done = false, adj_backward_bufs = false;
 };
 
@@ -1042,9 +1045,16 @@ int iesh_hop_evals(iesh_ctx* ctx, int64_t* full_evals) {
 
 
 int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int32_t ckpt_every,
-                         double* loss_out) {
+                         const double* terms, double* loss_out) {
   if (!ctx || !path || n_steps < 1 || ckpt_every < 1)
     return fail(ctx, IESH_EINVAL, "adjoint: path, n_steps >= 1 and ckpt_every >= 1 required");
+  AdjTerms tw{1.0, 1.0, 0.0, 0.0};
+  if (terms) {
+    tw = AdjTerms{terms[0], terms[1], terms[2], terms[3]};
+    if (!std::isfinite(tw.cP) || !std::isfinite(tw.cE) || !std::isfinite(tw.cG) ||
+        !std::isfinite(tw.cF))
+      return fail(ctx, IESH_EINVAL, "adjoint: non-finite loss term weight");
+  }
   if (ctx->run.precision != IESH_FP64)
     return fail(ctx, IESH_ENOTSUP, "adjoint: FP64 contexts only");
   for (const auto& c : ctx->cls)
@@ -1054,6 +1064,7 @@ int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int
   for (size_t q = 0; q < (size_t)T * (n_steps + 1); ++q)
     if (!std::isfinite(path[q])) return fail(ctx, IESH_EINVAL, "adjoint: non-finite path");
   adj_release(ctx);
+  ctx->adj_terms = tw;
   ctx->adj_steps = n_steps;
   ctx->adj_ckpt = std::min(ckpt_every, n_steps);
   const int n_ckpt = (n_steps + ctx->adj_ckpt - 1) / ctx->adj_ckpt;
@@ -1067,6 +1078,8 @@ int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int
     const ClassDev& c = ctx->cls[ci];
     if (!c.n_traj) continue;
     if ((rc = adj_alloc(ctx, &ctx->adj[ci].ckpt, (size_t)n_ckpt * c.n_traj * c.md.N * c.md.n_pad * 2)))
+      return rc;
+    if (tw.cG != 0.0 && (rc = adj_alloc(ctx, &ctx->adj[ci].hopscr, adj_hop_scratch_elems(c))))
       return rc;
   }
   // start: x = path[.][0], v = 0, the N lowest adiabatic orbitals occupied
@@ -1091,7 +1104,12 @@ int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int
       const ClassDev cc = on_path(ctx, c, n);
       if ((rc = adj_step(ctx, cc))) return rc;
       HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_EIG,
-                        [&] { return launch_adj_loss(cc, ctx->adj_loss, n, n_steps, ctx->stream); }));
+                        [&] { return launch_adj_loss(cc, ctx->adj_loss, n, n_steps, tw, ctx->stream); }));
+      if (tw.cG != 0.0)
+        HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_HOP, [&] {
+                 return launch_adj_hop(cc, c.C64, nullptr, ctx->adj[ci].hopscr, nullptr, ctx->adj_loss,
+                                       nullptr, n + 1, n_steps, ctx->run.dt, tw.cG, 0, ctx->stream);
+               }));
     }
   }
   int64_t kmax = 0;
@@ -1131,6 +1149,9 @@ int iesh_adjoint_backward(iesh_ctx* ctx, const double* dloss, double* grad_out) 
           (rc = adj_alloc(ctx, &a.rediag, (size_t)c.n_traj * c.md.n_pad)) ||
           (rc = adj_alloc(ctx, &a.chebc, (size_t)c.n_traj * kChebStride)))
         return rc;
+      if (ctx->adj_terms.cG != 0.0 &&
+          (rc = adj_alloc(ctx, &a.hopbar, (size_t)c.n_traj * (2 * c.md.n_pad + 1))))
+        return rc;
     }
     ctx->adj_backward_bufs = true;
   }
@@ -1168,8 +1189,15 @@ int iesh_adjoint_backward(iesh_ctx* ctx, const double* dloss, double* grad_out) 
         HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_EIG,
                           [&] { return launch_eig_step(cc, ctx->run.dt, ctx->cnt, st); }));
         // explicit loss terms at x_{n+1}: cotangent of C_{n+1}
+        const AdjTerms& tw = ctx->adj_terms;
+        if (tw.cG != 0.0)
+          HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_HOP, [&] {
+                   return launch_adj_hop(cc, snap(n - a0 + 1), a.Gh, a.hopscr, ctx->adj_w, nullptr,
+                                         a.hopbar, n + 1, nst, ctx->run.dt, tw.cG, 1, st);
+                 }));
         HIPTRY(ctx, timed(ctx, IESH_TIMER_ADJ_EIG, [&] {
-                 return launch_adj_explicit(cc, snap(n - a0 + 1), a.Gh, ctx->adj_w, ctx->adj_grad,
+                 return launch_adj_explicit(cc, snap(n - a0 + 1), a.Gh, ctx->adj_w,
+                                            tw.cG != 0.0 ? a.hopbar : nullptr, tw, ctx->adj_grad,
                                             gstride, n + 1, nst, st);
                }));
         // Chebyshev vectors of C_n under this step's propagator

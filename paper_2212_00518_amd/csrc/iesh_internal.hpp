@@ -217,9 +217,18 @@ hipError_t launch_lowdin(const ClassDev& c, const Counters* cnt, int every, doub
 size_t lowdin_scratch_elems(const ClassDev& c);
 hipError_t launch_advance(Counters* cnt, hipStream_t s);
 // Adjoint along prescribed paths (k_eig.hip, k_adjoint.hip).
-hipError_t launch_adj_loss(const ClassDev& c, double* loss, int s, int T, hipStream_t st);
+struct AdjTerms {
+  double cP, cE, cG, cF;  // weights of the population, excitation, hop and force terms
+};
+hipError_t launch_adj_loss(const ClassDev& c, double* loss, int s, int T, const AdjTerms& w,
+                          hipStream_t st);
+size_t adj_hop_scratch_elems(const ClassDev& c);
+hipError_t launch_adj_hop(const ClassDev& c, const double* Cs, double* Gh, double* scr,
+                          const double* weights, double* loss, double* hopbar, int s, int T,
+                          double dt, double cG, int reverse, hipStream_t st);
 hipError_t launch_adj_explicit(const ClassDev& c, const double* Cs, double* Gh, const double* weights,
-                               double* grads, int gstride, int s, int T, hipStream_t st);
+                               const double* hopbar, const AdjTerms& w, double* grads, int gstride,
+                               int s, int T, hipStream_t st);
 hipError_t launch_adj_mid(const ClassDev& c, const double* imphi, const double* rediag, double* grads,
                           int gstride, int s, double dt, hipStream_t st);
 hipError_t launch_conj_cheb(const ClassDev& c, double* out, hipStream_t st);

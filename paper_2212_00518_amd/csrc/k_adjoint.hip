@@ -1,10 +1,14 @@
-// Path loss and the contraction of the adjoint Chebyshev vectors (adjoint
-// pattern along prescribed nuclear paths).
+// Path loss, its hop-probability term, and the contraction of the adjoint
+// Chebyshev vectors (adjoint pattern along prescribed nuclear paths).
 //
-// Loss of one path (impurity population and electronic excitation energy of
-// the Newns-Anderson model, Sec. II.B and III.B):
-//   L = (1/T) sum_{s=1..T} P(s) + E_exc(T),  P(s) = sum_o |sum_a q0_a(x_s) C_ao(s)|^2,
-//   E_exc = sum_a lambda_a(x_T) (rho_a - n0_a),  rho_a = sum_o |C_ao(T)|^2.
+// Loss of one path with term weights (c_P, c_E, c_G, c_F), at x_s (s = 1..T):
+//   L = c_P (1/T) sum_s P(s) + c_E E_exc(T) + c_G (1/T) sum_s G(s) + c_F (1/T) sum_s F(s),
+//   P(s) = sum_o |sum_a q0_a C_ao(s)|^2            (impurity population, Sec. III.B),
+//   E_exc = sum_a lambda_a(x_T) (rho_a - n0_a),     rho_a = sum_o |C_ao(T)|^2,
+//   G(s) = sum_{a occupied, b not} g_ab,  g_ab = max(-2 dt v D_ba Re W_b,r(a), 0),
+//          W = C_U S^-1 (Eqs. hopping_probability and hopping_rate),
+//   F(s) = -dU0/dx - h' sum_{a occupied} q0_a^2     (Eq. classical_hamiltonian),
+// occupations held at their initial values, v = (x_s - x_{s-1}) / dt.
 //
 // Reverse mode through one propagation y = sum_k c_k T_k(At) x with output
 // cotangent g: the cotangent of x is the same series with conjugated
@@ -20,16 +24,19 @@ namespace iesh {
 namespace {
 
 constexpr int kLossThreads = 256;
+constexpr int kHopAdjThreads = 256;
 
-// loss[g] += P(s+1) / T (and E_exc at the last step), with lambda, q0 at the
-// end point of step s and the propagated orbitals.
-__global__ __launch_bounds__(kLossThreads) void k_adj_loss(ClassDev c, double* loss, int s, int T) {
+// loss[g] += the P, F terms at x_{s+1} (and E_exc at the last step), with
+// lambda, q0 at the end point of step s and the propagated orbitals.
+__global__ __launch_bounds__(kLossThreads) void k_adj_loss(ClassDev c, double* loss, int s, int T,
+                                                           AdjTerms w) {
   __shared__ double red[kLossThreads];
   const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = c.md.n, n_pad = c.md.n_pad, N = c.md.N;
   const double* C = c.C64 + (size_t)t * N * n_pad * 2;
   const double* q0 = c.q0 + (size_t)t * n_pad;
   const double* lam = c.lam + (size_t)t * n_pad;
+  const int32_t* occ = c.occ + (size_t)t * N;
   double part = 0.0;
   for (int o = wv; o < N; o += kLossThreads / 64) {
     double zr = 0.0, zi = 0.0;
@@ -41,7 +48,18 @@ __global__ __launch_bounds__(kLossThreads) void k_adj_loss(ClassDev c, double* l
       zr += __shfl_xor(zr, m);
       zi += __shfl_xor(zi, m);
     }
-    if (lane == 0) part += (zr * zr + zi * zi) / T;
+    if (lane == 0) part += w.cP * (zr * zr + zi * zi) / T;
+  }
+  if (w.cF != 0.0) {
+    // Hellmann-Feynman force on the held occupations (harmonic model)
+    const double omega = c.md.p[0], g = c.md.p[1], m = c.md.mass;
+    const double x = c.path[(size_t)c.gtraj[t] * c.path_len + s + 1];
+    const double hp = -m * omega * omega * g;
+    for (int r = tid; r < N; r += kLossThreads) {
+      const double q = q0[occ[r]];
+      part -= w.cF * hp * q * q / T;
+    }
+    if (tid == 0) part -= w.cF * m * omega * omega * x / T;
   }
   if (s == T - 1) {
     for (int a = tid; a < n; a += kLossThreads) {
@@ -50,9 +68,9 @@ __global__ __launch_bounds__(kLossThreads) void k_adj_loss(ClassDev c, double* l
         const double cr = C[((size_t)o * n_pad + a) * 2], ci = C[((size_t)o * n_pad + a) * 2 + 1];
         rho += cr * cr + ci * ci;
       }
-      bool occ = false;
-      for (int r = 0; r < N; ++r) occ |= (c.occ[(size_t)t * N + r] == a);
-      part += lam[a] * (rho - (occ ? 1.0 : 0.0));
+      bool oc = false;
+      for (int r = 0; r < N; ++r) oc |= (occ[r] == a);
+      part += w.cE * lam[a] * (rho - (oc ? 1.0 : 0.0));
     }
   }
   red[tid] = part;
@@ -62,6 +80,257 @@ __global__ __launch_bounds__(kLossThreads) void k_adj_loss(ClassDev c, double* l
     __syncthreads();
   }
   if (tid == 0) loss[c.gtraj[t]] += red[0];
+}
+
+// Hop-probability term at x_s for one trajectory (one work-group).
+// S = C[occupied rows] is inverted by Gauss-Jordan elimination with partial
+// pivoting on [S | I] in the trajectory's scratch block; W = C_U X, the pair
+// probabilities g_ab and (forward) their sum into the loss.  Reverse: with
+// R_br = dL/dRe W_br = c [g_ab > 0] (-2 dt v D_ba) and Dbar_ba = c [g_ab > 0]
+// (-2 dt v Re W_br) (c = weight c_G / T), the orbital cotangents are
+//   Gbar_U = R X^H,  Gbar_S = -W^H Gbar_U   (added as halves to the Wirtinger
+// cotangent Gh), and D_ba = h' q0_b q0_a / (lambda_a - lambda_b) passes Dbar
+// to (q0, lambda, h'), written to hopbar = [qbar (n_pad) | lbar (n_pad) | hpbar]
+// for the reverse of the end-point eigen-solve.  Sums run in a fixed order.
+// Scratch per trajectory (doubles): [S | I] 4 N^2, W and Gbar_U 2 n_pad N
+// each, R and Dbar n_pad N each.
+__host__ __device__ inline size_t hop_adj_scratch(int n_pad, int N) {
+  return (size_t)4 * N * N + (size_t)6 * n_pad * N;
+}
+
+__global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const double* Cs, double* Gh,
+                                                            double* scr, const double* weights,
+                                                            double* loss, double* hopbar, int s,
+                                                            int T, double dt, double cG, int reverse) {
+  __shared__ int mark[kMaxStates];
+  __shared__ int uidx[kMaxStates];
+  __shared__ double2 fcol[kMaxElec];
+  __shared__ double red[kHopAdjThreads];
+  __shared__ int redi[kHopAdjThreads];
+  __shared__ double qb[kMaxStates], lb[kMaxStates];
+  __shared__ int sing;
+  const int t = blockIdx.x, tid = threadIdx.x;
+  if (t >= c.n_live) return;
+  const int n = c.md.n, n_pad = c.md.n_pad, N = c.md.N, nU = n - N, N2 = 2 * N;
+  const double* C = Cs + (size_t)t * N * n_pad * 2;
+  const double* lam = c.lam + (size_t)t * n_pad;
+  const double* q0 = c.q0 + (size_t)t * n_pad;
+  const int32_t* occ = c.occ + (size_t)t * N;
+  const int g = c.gtraj[t];
+  const double* pp = c.path + (size_t)g * c.path_len + s;
+  const double v = (pp[0] - pp[-1]) / dt;
+  const double omega = c.md.p[0], gg = c.md.p[1];
+  const double hp = -c.md.mass * omega * omega * gg;
+  double* base = scr + (size_t)t * hop_adj_scratch(n_pad, N);
+  double2* Mg = reinterpret_cast<double2*>(base);              // [N][2N]
+  double2* Wg = reinterpret_cast<double2*>(base + 4 * N * N);  // [nU][N]
+  double2* Gu = Wg + (size_t)n_pad * N;                        // [nU][N]
+  double* Rg = reinterpret_cast<double*>(Gu + (size_t)n_pad * N);  // [nU][N]
+  double* Db = Rg + (size_t)n_pad * N;                         // [nU][N]
+
+  for (int a = tid; a < n; a += kHopAdjThreads) mark[a] = 0;
+  if (tid == 0) sing = 0;
+  __syncthreads();
+  for (int r = tid; r < N; r += kHopAdjThreads) mark[occ[r]] = 1;
+  __syncthreads();
+  if (tid == 0) {
+    int j = 0;
+    for (int a = 0; a < n; ++a)
+      if (!mark[a]) uidx[j++] = a;
+  }
+  // [S | I], S[r][o] = C[o][occ[r]]
+  for (int e = tid; e < N * N2; e += kHopAdjThreads) {
+    const int r = e / N2, col = e - r * N2;
+    double2 val = make_double2(0.0, 0.0);
+    if (col < N) {
+      const size_t off = ((size_t)col * n_pad + occ[r]) * 2;
+      val = make_double2(C[off], C[off + 1]);
+    } else if (col - N == r) {
+      val.x = 1.0;
+    }
+    Mg[e] = val;
+  }
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    // pivot: largest |M[r][k]|, r >= k, smallest r among equals
+    double best = -1.0;
+    int bi = N;
+    for (int r = k + tid; r < N; r += kHopAdjThreads) {
+      const double2 m = Mg[(size_t)r * N2 + k];
+      const double mag = m.x * m.x + m.y * m.y;
+      if (mag > best) {
+        best = mag;
+        bi = r;
+      }
+    }
+    red[tid] = best;
+    redi[tid] = bi;
+    __syncthreads();
+    for (int st = kHopAdjThreads / 2; st > 0; st >>= 1) {
+      if (tid < st) {
+        const double o = red[tid + st];
+        const int oi = redi[tid + st];
+        if (o > red[tid] || (o == red[tid] && oi < redi[tid])) {
+          red[tid] = o;
+          redi[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = redi[0];
+    if (!(red[0] > 0.0)) {
+      if (tid == 0) sing = 1;
+      break;  // uniform: every thread read the same reduction result
+    }
+    if (p != k) {
+      for (int col = tid; col < N2; col += kHopAdjThreads) {
+        const double2 a = Mg[(size_t)k * N2 + col], b = Mg[(size_t)p * N2 + col];
+        Mg[(size_t)k * N2 + col] = b;
+        Mg[(size_t)p * N2 + col] = a;
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < N; r += kHopAdjThreads) fcol[r] = Mg[(size_t)r * N2 + k];
+    __syncthreads();
+    const double2 pv = fcol[k];
+    const double den = pv.x * pv.x + pv.y * pv.y;
+    const double ir = pv.x / den, ii = -pv.y / den;  // 1 / pivot
+    for (int col = k + tid; col < N2; col += kHopAdjThreads) {
+      const double2 a = Mg[(size_t)k * N2 + col];
+      Mg[(size_t)k * N2 + col] = make_double2(a.x * ir - a.y * ii, a.x * ii + a.y * ir);
+    }
+    __syncthreads();
+    const int w = N2 - k;
+    for (int e = tid; e < N * w; e += kHopAdjThreads) {
+      const int r = e / w, col = k + (e - r * w);
+      if (r == k) continue;
+      const double2 f = fcol[r], a = Mg[(size_t)k * N2 + col];
+      double2 m = Mg[(size_t)r * N2 + col];
+      m.x -= f.x * a.x - f.y * a.y;
+      m.y -= f.x * a.y + f.y * a.x;
+      Mg[(size_t)r * N2 + col] = m;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const bool singular = sing != 0;
+  const double wt = reverse ? weights[g] : 1.0;
+  const double sc = wt * cG / T;
+  // W = C_U X (X[o][r] = M[o][N + r]), pair probabilities
+  double gsum = 0.0;
+  if (!singular) {
+    for (int e = tid; e < nU * N; e += kHopAdjThreads) {
+      const int j = e / N, r = e - j * N;
+      const int b = uidx[j], a = occ[r];
+      double wr = 0.0, wi = 0.0;
+      for (int o = 0; o < N; ++o) {
+        const size_t off = ((size_t)o * n_pad + b) * 2;
+        const double cr = C[off], ci = C[off + 1];
+        const double2 x = Mg[(size_t)o * N2 + N + r];
+        wr += cr * x.x - ci * x.y;
+        wi += cr * x.y + ci * x.x;
+      }
+      const double D = hp * q0[b] * q0[a] / (lam[a] - lam[b]);
+      const double y = -2.0 * dt * v * D * wr;
+      if (reverse) {
+        const bool on = y > 0.0;
+        Wg[e] = make_double2(wr, wi);
+        Rg[e] = on ? sc * (-2.0 * dt * v * D) : 0.0;
+        Db[e] = on ? sc * (-2.0 * dt * v * wr) : 0.0;
+      } else {
+        gsum += fmax(y, 0.0);
+      }
+    }
+  }
+  if (!reverse) {
+    red[tid] = gsum;
+    __syncthreads();
+    for (int st = kHopAdjThreads / 2; st > 0; st >>= 1) {
+      if (tid < st) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    if (tid == 0) loss[g] += sc * red[0];
+    return;
+  }
+  double* hb = hopbar + (size_t)t * (2 * n_pad + 1);
+  if (singular) {
+    for (int a = tid; a < 2 * n_pad + 1; a += kHopAdjThreads) hb[a] = 0.0;
+    return;
+  }
+  __syncthreads();
+  // (q0, lambda, h') cotangents of the couplings D_ba, b unoccupied, a occupied
+  double hpart = 0.0;
+  for (int j = tid; j < nU; j += kHopAdjThreads) {
+    const int b = uidx[j];
+    double qs = 0.0, ls = 0.0;
+    for (int r = 0; r < N; ++r) {
+      const int a = occ[r];
+      const double d = lam[a] - lam[b];
+      const double db = Db[(size_t)j * N + r];
+      qs += db * hp * q0[a] / d;
+      ls += db * hp * q0[b] * q0[a] / (d * d);  // dD_ba/dlambda_b = D_ba / d
+      hpart += db * q0[b] * q0[a] / d;
+    }
+    qb[b] = qs;
+    lb[b] = ls;
+  }
+  for (int r = tid; r < N; r += kHopAdjThreads) {
+    const int a = occ[r];
+    double qs = 0.0, ls = 0.0;
+    for (int j = 0; j < nU; ++j) {
+      const int b = uidx[j];
+      const double d = lam[a] - lam[b];
+      const double db = Db[(size_t)j * N + r];
+      qs += db * hp * q0[b] / d;
+      ls -= db * hp * q0[b] * q0[a] / (d * d);  // dD_ba/dlambda_a = -D_ba / d
+    }
+    qb[a] = qs;
+    lb[a] = ls;
+  }
+  red[tid] = hpart;
+  __syncthreads();
+  for (int st = kHopAdjThreads / 2; st > 0; st >>= 1) {
+    if (tid < st) red[tid] += red[tid + st];
+    __syncthreads();
+  }
+  for (int a = tid; a < n_pad; a += kHopAdjThreads) {
+    hb[a] = a < n ? qb[a] : 0.0;
+    hb[n_pad + a] = a < n ? lb[a] : 0.0;
+  }
+  if (tid == 0) hb[2 * n_pad] = red[0];
+  // Gbar_U[j][o] = sum_r R[j][r] conj(X[o][r])
+  for (int e = tid; e < nU * N; e += kHopAdjThreads) {
+    const int j = e / N, o = e - j * N;
+    double gr = 0.0, gi = 0.0;
+    for (int r = 0; r < N; ++r) {
+      const double rv = Rg[(size_t)j * N + r];
+      const double2 x = Mg[(size_t)o * N2 + N + r];
+      gr += rv * x.x;
+      gi -= rv * x.y;
+    }
+    Gu[e] = make_double2(gr, gi);
+  }
+  __syncthreads();
+  double* G = Gh + (size_t)t * N * n_pad * 2;
+  for (int e = tid; e < nU * N; e += kHopAdjThreads) {
+    const int j = e / N, o = e - j * N;
+    const size_t off = ((size_t)o * n_pad + uidx[j]) * 2;
+    G[off] += 0.5 * Gu[e].x;
+    G[off + 1] += 0.5 * Gu[e].y;
+  }
+  // Gbar_S[r][o] = -sum_j conj(W[j][r]) Gbar_U[j][o]
+  for (int e = tid; e < N * N; e += kHopAdjThreads) {
+    const int r = e / N, o = e - r * N;
+    double gr = 0.0, gi = 0.0;
+    for (int j = 0; j < nU; ++j) {
+      const double2 wv = Wg[(size_t)j * N + r], gu = Gu[(size_t)j * N + o];
+      gr -= wv.x * gu.x + wv.y * gu.y;
+      gi -= wv.x * gu.y - wv.y * gu.x;
+    }
+    const size_t off = ((size_t)o * n_pad + occ[r]) * 2;
+    G[off] += 0.5 * gr;
+    G[off + 1] += 0.5 * gi;
+  }
 }
 
 // Im Phi and Re diag(Phi) as one real product per trajectory on the matrix
@@ -250,8 +519,22 @@ __global__ __launch_bounds__(kPhiThreads) void k_adj_phi(ClassDev c, const doubl
 
 }  // namespace
 
-hipError_t launch_adj_loss(const ClassDev& c, double* loss, int s, int T, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_loss, dim3(c.n_traj), dim3(kLossThreads), 0, st, c, loss, s, T);
+hipError_t launch_adj_loss(const ClassDev& c, double* loss, int s, int T, const AdjTerms& w,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_loss, dim3(c.n_traj), dim3(kLossThreads), 0, st, c, loss, s, T, w);
+  return hipGetLastError();
+}
+
+size_t adj_hop_scratch_elems(const ClassDev& c) {
+  return (size_t)c.n_traj * hop_adj_scratch(c.md.n_pad, c.md.N);
+}
+
+hipError_t launch_adj_hop(const ClassDev& c, const double* Cs, double* Gh, double* scr,
+                          const double* weights, double* loss, double* hopbar, int s, int T,
+                          double dt, double cG, int reverse, hipStream_t st) {
+  if (c.n_live < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_hop, dim3(c.n_live), dim3(kHopAdjThreads), 0, st, c, Cs, Gh, scr, weights,
+                     loss, hopbar, s, T, dt, cG, reverse);
   return hipGetLastError();
 }
 

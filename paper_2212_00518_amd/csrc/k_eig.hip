@@ -659,10 +659,13 @@ __device__ void eig_backprop(const ModelDev& md, const ModelAt& ma, double x, Ad
 }
 
 // Explicit terms of the loss at x_s (end of step s - 1, s = 1 .. T) for one
-// trajectory: Gh += w q0 z^T / T (z = C^T q0) and, at s = T, w diag(lambda) C;
-// the cotangents of q0 and lambda go through the eigen-solve into grad.
+// trajectory: Gh += w c_P q0 z^T / T (z = C^T q0) and, at s = T,
+// w c_E diag(lambda) C; the force term adds to the q0 and h' cotangents, the
+// hop term's (q0, lambda, h') cotangents come in through hopbar (may be
+// null); all of them go through the eigen-solve into grad.
 __global__ __launch_bounds__(kEigThreads) void k_adj_explicit(ClassDev c, const double* Cs,
                                                               double* Gh, const double* weights,
+                                                              const double* hopbar, AdjTerms wt,
                                                               double* grads, int gstride, int s,
                                                               int T) {
   __shared__ AdjLds A;
@@ -697,6 +700,9 @@ __global__ __launch_bounds__(kEigThreads) void k_adj_explicit(ClassDev c, const 
   __syncthreads();
   const bool last = (s == T);
   const double invT = 1.0 / T;
+  const double omega = md.p[0], gg = md.p[1], m = md.mass;
+  const double hp = -m * omega * omega * gg;
+  const double* hb = hopbar ? hopbar + (size_t)t * (2 * n_pad + 1) : nullptr;
   // Gh update; qbar_a = (2/T) sum_o Re(C[o][a] conj(z_o)); at T, lbar_a = rho_a - n0_a
   for (int a = tid; a < n; a += kEigThreads) {
     double qb = 0.0, rho = 0.0;
@@ -705,25 +711,34 @@ __global__ __launch_bounds__(kEigThreads) void k_adj_explicit(ClassDev c, const 
       const double cr = C[e], ci = C[e + 1];
       qb += cr * zr[o] + ci * zi[o];
       rho += cr * cr + ci * ci;
-      double gr = invT * L.q0[a] * zr[o], gi = invT * L.q0[a] * zi[o];
+      double gr = wt.cP * invT * L.q0[a] * zr[o], gi = wt.cP * invT * L.q0[a] * zi[o];
       if (last) {
-        gr += L.lam[a] * cr;
-        gi += L.lam[a] * ci;
+        gr += wt.cE * L.lam[a] * cr;
+        gi += wt.cE * L.lam[a] * ci;
       }
       G[e] += w * gr;
       G[e + 1] += w * gi;
     }
-    A.qbar[a] = w * 2.0 * invT * qb;
-    double lb = 0.0;
-    if (last) {
-      bool occ = false;
-      for (int r = 0; r < N; ++r) occ |= (c.occ[(size_t)t * N + r] == a);
-      lb = rho - (occ ? 1.0 : 0.0);
-    }
-    A.lbar[a] = w * lb;
+    bool occ = false;
+    for (int r = 0; r < N; ++r) occ |= (c.occ[(size_t)t * N + r] == a);
+    double qbar = wt.cP * 2.0 * invT * qb;
+    // force term: F = -m omega^2 x - h' sum_occ q0^2
+    if (occ) qbar -= wt.cF * invT * hp * 2.0 * L.q0[a];
+    double lb = last ? wt.cE * (rho - (occ ? 1.0 : 0.0)) : 0.0;
+    A.qbar[a] = w * qbar + (hb ? hb[a] : 0.0);
+    A.lbar[a] = w * lb + (hb ? hb[n_pad + a] : 0.0);
   }
+  // h' cotangent: force term and hop term
+  double hpart = 0.0;
+  for (int r = tid; r < N; r += kEigThreads) {
+    const double q = L.q0[c.occ[(size_t)t * N + r]];
+    hpart -= wt.cF * invT * q * q;
+  }
+  const double hpbar = w * block_sum(hpart, A.red3) + (hb ? hb[2 * n_pad] : 0.0);
+  double* gr = grads + (size_t)c.gtraj[t] * gstride;
+  if (tid == 0 && wt.cF != 0.0) gr[2 + md.M] += -w * wt.cF * invT * 2.0 * m * omega * x;
   __syncthreads();
-  eig_backprop(md, ma, x, A, 0.0, grads + (size_t)c.gtraj[t] * gstride);
+  eig_backprop(md, ma, x, A, hpbar, gr);
 }
 
 // Midpoint of step s: from Phi = dL/dAt (ImPhi [n_pad][n_pad], ReD = Re diag)
@@ -803,9 +818,10 @@ hipError_t launch_init_thermal(const ClassDev& c, double kT, uint64_t seed, hipS
 }
 
 hipError_t launch_adj_explicit(const ClassDev& c, const double* Cs, double* Gh, const double* weights,
-                               double* grads, int gstride, int s, int T, hipStream_t st) {
+                               const double* hopbar, const AdjTerms& w, double* grads, int gstride,
+                               int s, int T, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_explicit, dim3(c.n_traj), dim3(kEigThreads), 0, st, c, Cs, Gh, weights,
-                     grads, gstride, s, T);
+                     hopbar, w, grads, gstride, s, T);
   return hipGetLastError();
 }
 
