@@ -83,8 +83,10 @@ __global__ __launch_bounds__(kLossThreads) void k_adj_loss(ClassDev c, double* l
 }
 
 // Hop-probability term at x_s for one trajectory (one work-group).
-// S = C[occupied rows] is inverted by Gauss-Jordan elimination with partial
-// pivoting on [S | I] in the trajectory's scratch block; W = C_U X, the pair
+// S = C[occupied rows] is inverted in place by Gauss-Jordan elimination with
+// partial (row) pivoting, the row interchanges undone as column interchanges
+// at the end; the N x N matrix lives in LDS when it fits the work-group's
+// dynamic LDS, else in the trajectory's scratch block.  W = C_U X, the pair
 // probabilities g_ab and (forward) their sum into the loss.  Reverse: with
 // R_br = dL/dRe W_br = c [g_ab > 0] (-2 dt v D_ba) and Dbar_ba = c [g_ab > 0]
 // (-2 dt v Re W_br) (c = weight c_G / T), the orbital cotangents are
@@ -92,16 +94,24 @@ __global__ __launch_bounds__(kLossThreads) void k_adj_loss(ClassDev c, double* l
 // cotangent Gh), and D_ba = h' q0_b q0_a / (lambda_a - lambda_b) passes Dbar
 // to (q0, lambda, h'), written to hopbar = [qbar (n_pad) | lbar (n_pad) | hpbar]
 // for the reverse of the end-point eigen-solve.  Sums run in a fixed order.
-// Scratch per trajectory (doubles): [S | I] 4 N^2, W and Gbar_U 2 n_pad N
-// each, R and Dbar n_pad N each.
+// Scratch per trajectory (doubles): S 2 N^2, W and Gbar_U 2 n_pad N each,
+// R and Dbar n_pad N each.
 __host__ __device__ inline size_t hop_adj_scratch(int n_pad, int N) {
-  return (size_t)4 * N * N + (size_t)6 * n_pad * N;
+  return (size_t)2 * N * N + (size_t)6 * n_pad * N;
+}
+
+// Dynamic LDS of the hop-term kernel: the N x N inverse when it fits.
+constexpr size_t kHopAdjLdsMax = 128 * 1024;
+inline size_t hop_adj_lds(int N) {
+  const size_t b = (size_t)N * N * sizeof(double2);
+  return b <= kHopAdjLdsMax ? b : 0;
 }
 
 __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const double* Cs, double* Gh,
                                                             double* scr, const double* weights,
                                                             double* loss, double* hopbar, int s,
-                                                            int T, double dt, double cG, int reverse) {
+                                                            int T, double dt, double cG, int reverse,
+                                                            int in_lds) {
   __shared__ int mark[kMaxStates];
   __shared__ int uidx[kMaxStates];
   __shared__ double2 fcol[kMaxElec];
@@ -109,9 +119,11 @@ __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const do
   __shared__ int redi[kHopAdjThreads];
   __shared__ double qb[kMaxStates], lb[kMaxStates];
   __shared__ int sing;
+  __shared__ int piv[kMaxElec];
+  extern __shared__ double2 hop_smem[];
   const int t = blockIdx.x, tid = threadIdx.x;
   if (t >= c.n_live) return;
-  const int n = c.md.n, n_pad = c.md.n_pad, N = c.md.N, nU = n - N, N2 = 2 * N;
+  const int n = c.md.n, n_pad = c.md.n_pad, N = c.md.N, nU = n - N;
   const double* C = Cs + (size_t)t * N * n_pad * 2;
   const double* lam = c.lam + (size_t)t * n_pad;
   const double* q0 = c.q0 + (size_t)t * n_pad;
@@ -122,8 +134,9 @@ __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const do
   const double omega = c.md.p[0], gg = c.md.p[1];
   const double hp = -c.md.mass * omega * omega * gg;
   double* base = scr + (size_t)t * hop_adj_scratch(n_pad, N);
-  double2* Mg = reinterpret_cast<double2*>(base);              // [N][2N]
-  double2* Wg = reinterpret_cast<double2*>(base + 4 * N * N);  // [nU][N]
+  // X: [N][N] (S in, S^-1 out), in LDS when the launch gave it room
+  double2* Mg = in_lds ? hop_smem : reinterpret_cast<double2*>(base);
+  double2* Wg = reinterpret_cast<double2*>(base + 2 * N * N);  // [nU][N]
   double2* Gu = Wg + (size_t)n_pad * N;                        // [nU][N]
   double* Rg = reinterpret_cast<double*>(Gu + (size_t)n_pad * N);  // [nU][N]
   double* Db = Rg + (size_t)n_pad * N;                         // [nU][N]
@@ -138,17 +151,11 @@ __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const do
     for (int a = 0; a < n; ++a)
       if (!mark[a]) uidx[j++] = a;
   }
-  // [S | I], S[r][o] = C[o][occ[r]]
-  for (int e = tid; e < N * N2; e += kHopAdjThreads) {
-    const int r = e / N2, col = e - r * N2;
-    double2 val = make_double2(0.0, 0.0);
-    if (col < N) {
-      const size_t off = ((size_t)col * n_pad + occ[r]) * 2;
-      val = make_double2(C[off], C[off + 1]);
-    } else if (col - N == r) {
-      val.x = 1.0;
-    }
-    Mg[e] = val;
+  // S[r][o] = C[o][occ[r]]
+  for (int e = tid; e < N * N; e += kHopAdjThreads) {
+    const int r = e / N, col = e - r * N;
+    const size_t off = ((size_t)col * n_pad + occ[r]) * 2;
+    Mg[e] = make_double2(C[off], C[off + 1]);
   }
   __syncthreads();
   for (int k = 0; k < N; ++k) {
@@ -156,77 +163,100 @@ __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const do
     double best = -1.0;
     int bi = N;
     for (int r = k + tid; r < N; r += kHopAdjThreads) {
-      const double2 m = Mg[(size_t)r * N2 + k];
+      const double2 m = Mg[(size_t)r * N + k];
       const double mag = m.x * m.x + m.y * m.y;
       if (mag > best) {
         best = mag;
         bi = r;
       }
     }
-    red[tid] = best;
-    redi[tid] = bi;
-    __syncthreads();
-    for (int st = kHopAdjThreads / 2; st > 0; st >>= 1) {
-      if (tid < st) {
-        const double o = red[tid + st];
-        const int oi = redi[tid + st];
-        if (o > red[tid] || (o == red[tid] && oi < redi[tid])) {
-          red[tid] = o;
-          redi[tid] = oi;
-        }
+    // wave reduction by lane swaps, then the four wave results in a fixed order
+    for (int m = 32; m > 0; m >>= 1) {
+      const double o = __shfl_xor(best, m);
+      const int oi = __shfl_xor(bi, m);
+      if (o > best || (o == best && oi < bi)) {
+        best = o;
+        bi = oi;
       }
-      __syncthreads();
     }
-    const int p = redi[0];
-    if (!(red[0] > 0.0)) {
+    if ((tid & 63) == 0) {
+      red[tid >> 6] = best;
+      redi[tid >> 6] = bi;
+    }
+    __syncthreads();
+    best = red[0];
+    bi = redi[0];
+    for (int q = 1; q < kHopAdjThreads / 64; ++q)
+      if (red[q] > best || (red[q] == best && redi[q] < bi)) {
+        best = red[q];
+        bi = redi[q];
+      }
+    const int p = bi;
+    if (!(best > 0.0)) {
       if (tid == 0) sing = 1;
       break;  // uniform: every thread read the same reduction result
     }
+    if (tid == 0) piv[k] = p;
     if (p != k) {
-      for (int col = tid; col < N2; col += kHopAdjThreads) {
-        const double2 a = Mg[(size_t)k * N2 + col], b = Mg[(size_t)p * N2 + col];
-        Mg[(size_t)k * N2 + col] = b;
-        Mg[(size_t)p * N2 + col] = a;
+      for (int col = tid; col < N; col += kHopAdjThreads) {
+        const double2 a = Mg[(size_t)k * N + col], b = Mg[(size_t)p * N + col];
+        Mg[(size_t)k * N + col] = b;
+        Mg[(size_t)p * N + col] = a;
       }
     }
     __syncthreads();
-    for (int r = tid; r < N; r += kHopAdjThreads) fcol[r] = Mg[(size_t)r * N2 + k];
+    for (int r = tid; r < N; r += kHopAdjThreads) fcol[r] = Mg[(size_t)r * N + k];
     __syncthreads();
     const double2 pv = fcol[k];
     const double den = pv.x * pv.x + pv.y * pv.y;
     const double ir = pv.x / den, ii = -pv.y / den;  // 1 / pivot
-    for (int col = k + tid; col < N2; col += kHopAdjThreads) {
-      const double2 a = Mg[(size_t)k * N2 + col];
-      Mg[(size_t)k * N2 + col] = make_double2(a.x * ir - a.y * ii, a.x * ii + a.y * ir);
+    // row k: M[k][j] / pivot for j != k, 1 / pivot at j = k
+    for (int col = tid; col < N; col += kHopAdjThreads) {
+      const double2 a = (col == k) ? make_double2(1.0, 0.0) : Mg[(size_t)k * N + col];
+      Mg[(size_t)k * N + col] = make_double2(a.x * ir - a.y * ii, a.x * ii + a.y * ir);
     }
     __syncthreads();
-    const int w = N2 - k;
-    for (int e = tid; e < N * w; e += kHopAdjThreads) {
-      const int r = e / w, col = k + (e - r * w);
+    // other rows: M[r][j] -= f_r M[k][j] (j != k), M[r][k] = -f_r M[k][k]
+    for (int e = tid; e < N * N; e += kHopAdjThreads) {
+      const int r = e / N, col = e - r * N;
       if (r == k) continue;
-      const double2 f = fcol[r], a = Mg[(size_t)k * N2 + col];
-      double2 m = Mg[(size_t)r * N2 + col];
+      const double2 f = fcol[r], a = Mg[(size_t)k * N + col];
+      double2 m = (col == k) ? make_double2(0.0, 0.0) : Mg[e];
       m.x -= f.x * a.x - f.y * a.y;
       m.y -= f.x * a.y + f.y * a.x;
-      Mg[(size_t)r * N2 + col] = m;
+      Mg[e] = m;
     }
     __syncthreads();
   }
   __syncthreads();
+  // undo the row interchanges as column interchanges, last first
+  if (!sing) {
+    for (int k = N - 1; k >= 0; --k) {
+      const int p = piv[k];
+      if (p != k) {
+        for (int r = tid; r < N; r += kHopAdjThreads) {
+          const double2 a = Mg[(size_t)r * N + k], b = Mg[(size_t)r * N + p];
+          Mg[(size_t)r * N + k] = b;
+          Mg[(size_t)r * N + p] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
   const bool singular = sing != 0;
   const double wt = reverse ? weights[g] : 1.0;
   const double sc = wt * cG / T;
-  // W = C_U X (X[o][r] = M[o][N + r]), pair probabilities
+  // W = C_U X (X[o][r] = M[o][r]), pair probabilities
   double gsum = 0.0;
   if (!singular) {
     for (int e = tid; e < nU * N; e += kHopAdjThreads) {
-      const int j = e / N, r = e - j * N;
+      const int r = e / nU, j = e - r * nU;  // element [r][j]: consecutive threads, consecutive b
       const int b = uidx[j], a = occ[r];
       double wr = 0.0, wi = 0.0;
       for (int o = 0; o < N; ++o) {
         const size_t off = ((size_t)o * n_pad + b) * 2;
         const double cr = C[off], ci = C[off + 1];
-        const double2 x = Mg[(size_t)o * N2 + N + r];
+        const double2 x = Mg[(size_t)o * N + r];
         wr += cr * x.x - ci * x.y;
         wi += cr * x.y + ci * x.x;
       }
@@ -266,7 +296,7 @@ __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const do
     for (int r = 0; r < N; ++r) {
       const int a = occ[r];
       const double d = lam[a] - lam[b];
-      const double db = Db[(size_t)j * N + r];
+      const double db = Db[(size_t)r * nU + j];
       qs += db * hp * q0[a] / d;
       ls += db * hp * q0[b] * q0[a] / (d * d);  // dD_ba/dlambda_b = D_ba / d
       hpart += db * q0[b] * q0[a] / d;
@@ -280,7 +310,7 @@ __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const do
     for (int j = 0; j < nU; ++j) {
       const int b = uidx[j];
       const double d = lam[a] - lam[b];
-      const double db = Db[(size_t)j * N + r];
+      const double db = Db[(size_t)r * nU + j];
       qs += db * hp * q0[b] / d;
       ls -= db * hp * q0[b] * q0[a] / (d * d);  // dD_ba/dlambda_a = -D_ba / d
     }
@@ -298,13 +328,13 @@ __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const do
     hb[n_pad + a] = a < n ? lb[a] : 0.0;
   }
   if (tid == 0) hb[2 * n_pad] = red[0];
-  // Gbar_U[j][o] = sum_r R[j][r] conj(X[o][r])
+  // Gbar_U[j][o] = sum_r R[j][r] conj(X[o][r]), stored [o][j]
   for (int e = tid; e < nU * N; e += kHopAdjThreads) {
-    const int j = e / N, o = e - j * N;
+    const int o = e / nU, j = e - o * nU;
     double gr = 0.0, gi = 0.0;
     for (int r = 0; r < N; ++r) {
-      const double rv = Rg[(size_t)j * N + r];
-      const double2 x = Mg[(size_t)o * N2 + N + r];
+      const double rv = Rg[(size_t)r * nU + j];
+      const double2 x = Mg[(size_t)o * N + r];
       gr += rv * x.x;
       gi -= rv * x.y;
     }
@@ -313,7 +343,7 @@ __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const do
   __syncthreads();
   double* G = Gh + (size_t)t * N * n_pad * 2;
   for (int e = tid; e < nU * N; e += kHopAdjThreads) {
-    const int j = e / N, o = e - j * N;
+    const int o = e / nU, j = e - o * nU;
     const size_t off = ((size_t)o * n_pad + uidx[j]) * 2;
     G[off] += 0.5 * Gu[e].x;
     G[off + 1] += 0.5 * Gu[e].y;
@@ -323,7 +353,7 @@ __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const do
     const int r = e / N, o = e - r * N;
     double gr = 0.0, gi = 0.0;
     for (int j = 0; j < nU; ++j) {
-      const double2 wv = Wg[(size_t)j * N + r], gu = Gu[(size_t)j * N + o];
+      const double2 wv = Wg[(size_t)r * nU + j], gu = Gu[(size_t)o * nU + j];
       gr -= wv.x * gu.x + wv.y * gu.y;
       gi -= wv.x * gu.y - wv.y * gu.x;
     }
@@ -533,8 +563,14 @@ hipError_t launch_adj_hop(const ClassDev& c, const double* Cs, double* Gh, doubl
                           const double* weights, double* loss, double* hopbar, int s, int T,
                           double dt, double cG, int reverse, hipStream_t st) {
   if (c.n_live < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_adj_hop, dim3(c.n_live), dim3(kHopAdjThreads), 0, st, c, Cs, Gh, scr, weights,
-                     loss, hopbar, s, T, dt, cG, reverse);
+  const size_t lds = hop_adj_lds(c.md.N);
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_adj_hop,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_adj_hop, dim3(c.n_live), dim3(kHopAdjThreads), lds, st, c, Cs, Gh, scr, weights,
+                     loss, hopbar, s, T, dt, cG, reverse, lds > 0 ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -129,6 +129,22 @@ def test_hop_term_alone_is_nonzero_and_matches():
         _check_grad(rows[t, :adj.n_params(12)], adj.gradient(p, x[t], N, dt, only), f"path {t}")
 
 
+def test_hop_term_with_the_inverse_outside_lds():
+    """N = 95 electrons: the N x N inverse of the hop term does not fit the
+    work-group's LDS and is kept in the trajectory's scratch block."""
+    p, dt = _model(191)
+    N, T, n_steps = 95, 1, 3
+    x = _paths(p, T, n_steps, dt, seed=5)
+    ens = _ensemble(p, N, T, dt)
+    only = (0.0, 0.0, 1.0, 0.0)
+    loss = ens.adjoint_forward(x, 2, only)
+    rows = ens.adjoint_backward(np.ones(T))
+    ref = adj.loss(p, x[0], N, dt, only)
+    assert ref > 0.0
+    assert abs(loss[0] - ref) <= 1e-10 * ref
+    _check_grad(rows[0, :adj.n_params(191)], adj.gradient(p, x[0], N, dt, only), "N = 95")
+
+
 def test_full_size_model_on_short_paths():
     """The workload's model size (M = 100, N = 50) on two short paths."""
     p, dt = _model(100)
