@@ -45,6 +45,18 @@ struct EigLds {
   double J[kMaxCheb];        // Bessel values J_0..J_K of the propagator
 };
 
+// 1/d from the hardware reciprocal estimate and two Newton steps
+// r <- r + r (1 - d r) (each squares the relative error), within a few ulp;
+// d != 0 at every call (poles are excluded from the root brackets, the bath
+// energies are distinct and the roots interlace them strictly).
+__device__ inline double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
 // f and its split derivative at tau (origin eo); terms with k < j are left
 // of the root.
 __device__ inline void secular_eval(int j, int M, const double* e, const double* V2, double eo,
@@ -53,7 +65,7 @@ __device__ inline void secular_eval(int j, int M, const double* e, const double*
   double psi = 0.0, l = 0.0, r = 0.0, abssum = 0.0;
   for (int k = 0; k < M; ++k) {
     const double d = (e[k] - eo) - tau;  // eps_k - lambda
-    const double inv = 1.0 / d;
+    const double inv = rcp_nr(d);
     const double t = V2[k] * inv;
     psi += t;
     abssum += fabs(t);
@@ -217,9 +229,9 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
     double prod = dk * (-dk1);
     for (int l = 0; l < M; ++l) {
       if (l < k) {
-        prod *= ((ek - L.e[L.org[l]]) - L.tau[l]) / (ek - L.e[l]);
+        prod *= ((ek - L.e[L.org[l]]) - L.tau[l]) * rcp_nr(ek - L.e[l]);
       } else if (l > k) {
-        prod *= ((L.e[L.org[l + 1]] - ek) + L.tau[l + 1]) / (L.e[l] - ek);
+        prod *= ((L.e[L.org[l + 1]] - ek) + L.tau[l + 1]) * rcp_nr(L.e[l] - ek);
       }
     }
     L.Vh2[k] = prod;
@@ -231,7 +243,8 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
       double s = 1.0;
       for (int k = 0; k < M; ++k) {
         const double d = (L.e[k] - eo) - tj;
-        s += L.Vh2[k] / (d * d);
+        const double id = rcp_nr(d);
+        s += L.Vh2[k] * (id * id);
       }
       L.q0[j] = 1.0 / sqrt(s);
     } else {
@@ -251,7 +264,7 @@ __device__ inline double lam_diff(const EigLds& L, int k, int j) {
 // v * D[j][k] for j != k < n.
 __device__ inline double vD_elem(const EigLds& L, const ModelAt& ma, double v, int j, int k) {
   const double g = L.q0[j] * L.q0[k] * (ma.dh + ma.rho * ((L.lam[j] - ma.h) + (L.lam[k] - ma.h)));
-  return v * g / lam_diff(L, k, j);
+  return v * g * rcp_nr(lam_diff(L, k, j));
 }
 
 // Bessel J_k(rho), k = 0..K, by Miller's downward recurrence normalised with
