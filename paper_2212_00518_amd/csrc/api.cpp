@@ -112,14 +112,17 @@ int round16(int v) { return (v + 15) / 16 * 16; }
 hipEvent_t next_event(iesh_ctx* ctx);
 
 // Largest slab width (16-column tiles per propagation work-group) whose LDS
-// fits, not above `limit`.
+// fits and whose output tiles (row tiles x slab width, dealt to 8 waves) stay
+// within the per-wave tile count the kernel is compiled for, not above `limit`.
 int widest_slab(ClassDev& c, int precision, int limit) {
   const size_t lds_budget = 160 * 1024;
   const int tiles = (c.md.N + 7) / 8;
+  const int RT = c.md.n_pad / 16;
   int nct = std::min(std::min(prop_max_col_tiles(precision), tiles), limit);
   for (; nct > 1; --nct) {
     c.nct_max = nct;
-    if (prop_lds_bytes(c, precision) <= lds_budget) break;
+    const bool fits_waves = (RT * nct + 7) / 8 <= prop_max_tiles_per_wave(precision);
+    if (fits_waves && prop_lds_bytes(c, precision) <= lds_budget) break;
   }
   return std::max(nct, 1);
 }

@@ -202,6 +202,7 @@ hipError_t launch_forces(const ClassDev& c, hipStream_t s);
 hipError_t launch_prop(const ClassDev& c, int precision, hipStream_t s);
 hipError_t launch_prop_taps(const ClassDev& c, int mode, double* taps, int tap_k, hipStream_t s);
 int prop_max_col_tiles(int precision);
+int prop_max_tiles_per_wave(int precision);
 hipError_t prop_prepare(const ClassDev& c, int precision);
 size_t prop_lds_bytes(const ClassDev& c, int precision);
 hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt,

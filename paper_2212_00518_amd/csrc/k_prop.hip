@@ -49,7 +49,7 @@ template <>
 struct PropCfg<double> {
   typedef v4d acc_t;
   static constexpr int kMaxColTiles = 3;
-  static constexpr int kMaxPairs = 6;  // ceil(14 * 3 / 8)
+  static constexpr int kMaxPairs = 6;  // output tiles per wave (the slab width is capped to fit)
   __device__ static inline acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -63,7 +63,7 @@ template <>
 struct PropCfg<float> {
   typedef v4f acc_t;
   static constexpr int kMaxColTiles = 5;
-  static constexpr int kMaxPairs = 9;  // ceil(14 * 5 / 8)
+  static constexpr int kMaxPairs = 9;  // output tiles per wave (the slab width is capped to fit)
   __device__ static inline acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -364,6 +364,10 @@ hipError_t launch_prop_t(const ClassDev& c, dim3 grid, size_t lds, hipStream_t s
 
 int prop_max_col_tiles(int precision) {
   return precision == IESH_FP64 ? PropCfg<double>::kMaxColTiles : PropCfg<float>::kMaxColTiles;
+}
+
+int prop_max_tiles_per_wave(int precision) {
+  return precision == IESH_FP64 ? PropCfg<double>::kMaxPairs : PropCfg<float>::kMaxPairs;
 }
 
 size_t prop_lds_bytes(const ClassDev& c, int precision) {

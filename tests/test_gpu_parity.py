@@ -251,6 +251,38 @@ def test_run_is_bitwise_deterministic():
         assert np.array_equal(a, b)
 
 
+def test_resume_from_a_saved_state_is_bitwise():
+    """Checkpoint / resume: the state saved after 60 steps and uploaded into a
+    new context with the step counter restored continues bit for bit like the
+    uninterrupted run (states and hop events), FP64 and mixed."""
+    T = 16
+    cfg, m, states = _hot_c1(T)
+    for prec in ("fp64", "mixed"):
+        full = ensemble(cfg, T, precision=prec)
+        upload(full, states)
+        full.run(120)
+        ref = full.get_state()
+        ref_ev = [e for e in full.events(cap=1 << 16)[0] if e["step"] >= 60]
+        full.close()
+        first = ensemble(cfg, T, precision=prec)
+        upload(first, states)
+        first.run(60)
+        saved = first.get_state()
+        first.close()
+        second = ensemble(cfg, T, precision=prec)
+        second.set_state(*saved)
+        second.set_step(60)
+        second.run(60)
+        got = second.get_state()
+        got_ev = second.events(cap=1 << 16)[0]
+        second.close()
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), prec
+        key = lambda e: (e["step"], e["traj"], e["a"], e["b"], e["accepted"])
+        assert sorted(map(key, ref_ev)) == sorted(map(key, got_ev)), prec
+        assert len(ref_ev) > 0
+
+
 def test_thermal_initialisation_matches_oracle():
     cfg = make_cfg("c1")
     T = 64
@@ -306,12 +338,15 @@ def test_singular_overlap_sets_status_and_skips_hop():
 
 
 # ----------------------------------------------------------------------- mixed
-@pytest.mark.parametrize("name,M,N", [("c1", 20, 10), ("c2", 200, 100)])
+@pytest.mark.parametrize("name,M,N", [("c1", 20, 10), ("c2", 200, 100),
+                                      ("c2", 230, 115),   # 15 row tiles: slab width capped by tiles per wave
+                                      ("c3", 320, 160)])
 def test_mixed_precision_single_step(name, M, N):
     cfg = make_cfg(name, M=M, N=N)
     m = models.from_config(cfg, M=M)
     T = 4
-    states = random_states(m, N, T, seed=17, xs=np.linspace(-4, 10, T), v_scale=0.002)
+    xs = np.linspace(2.5, 10.0, T) if name == "c3" else np.linspace(-4, 10, T)
+    states = random_states(m, N, T, seed=17, xs=xs, v_scale=0.01 if name == "c3" else 0.002)
     _compare_step(cfg, m, states, precision="mixed", tol=1e-5)
 
 
