@@ -240,7 +240,10 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int t0, int tid) {
   }
 }
 
-template <typename T, int kMode>
+// kQ: the most output tiles any wave of the launch owns.  Instantiated for a
+// few tiers so that narrow slabs get a kernel with fewer registers (more
+// work-groups per CU).
+template <typename T, int kMode, int kQ>
 __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c, T* taps, int tap_k) {
   typedef PropCfg<T> Cfg;
   extern __shared__ unsigned char smem_raw[];
@@ -323,13 +326,13 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c, T* taps, int 
     case 0: clenshaw_tiles<T, 0, kMode>(s, t0, tid); break;
     case 1: clenshaw_tiles<T, 1, kMode>(s, t0, tid); break;
     case 2: clenshaw_tiles<T, 2, kMode>(s, t0, tid); break;
-    case 3: clenshaw_tiles<T, 3, kMode>(s, t0, tid); break;
-    case 4: clenshaw_tiles<T, 4, kMode>(s, t0, tid); break;
-    case 5: clenshaw_tiles<T, 5, kMode>(s, t0, tid); break;
-    case 6: clenshaw_tiles<T, 6, kMode>(s, t0, tid); break;
-    case 7: if constexpr (Cfg::kMaxPairs >= 7) clenshaw_tiles<T, 7, kMode>(s, t0, tid); break;
-    case 8: if constexpr (Cfg::kMaxPairs >= 8) clenshaw_tiles<T, 8, kMode>(s, t0, tid); break;
-    default: if constexpr (Cfg::kMaxPairs >= 9) clenshaw_tiles<T, 9, kMode>(s, t0, tid); break;
+    case 3: if constexpr (kQ >= 3) clenshaw_tiles<T, 3, kMode>(s, t0, tid); break;
+    case 4: if constexpr (kQ >= 4) clenshaw_tiles<T, 4, kMode>(s, t0, tid); break;
+    case 5: if constexpr (kQ >= 5) clenshaw_tiles<T, 5, kMode>(s, t0, tid); break;
+    case 6: if constexpr (kQ >= 6) clenshaw_tiles<T, 6, kMode>(s, t0, tid); break;
+    case 7: if constexpr (kQ >= 7) clenshaw_tiles<T, 7, kMode>(s, t0, tid); break;
+    case 8: if constexpr (kQ >= 8) clenshaw_tiles<T, 8, kMode>(s, t0, tid); break;
+    default: if constexpr (kQ >= 9) clenshaw_tiles<T, 9, kMode>(s, t0, tid); break;
   }
 
   // result (in LDS) to memory, coalesced
@@ -353,10 +356,53 @@ size_t lds_bytes_t(const ClassDev& c) {
   return sizeof(T) * (2 * n_pad * ld + n_pad);
 }
 
+// Register tiers of the kernel: the smallest tier that holds the launch's
+// largest per-wave tile count is used.
+template <typename T>
+struct Tiers;
+template <>
+struct Tiers<double> {
+  static constexpr int q[3] = {2, 4, 6};
+};
+template <>
+struct Tiers<float> {
+  static constexpr int q[3] = {3, 6, 9};
+};
+
+template <typename T, int kMode>
+const void* prop_fn(int tier) {
+  switch (tier) {
+    case 0: return (const void*)k_prop<T, kMode, Tiers<T>::q[0]>;
+    case 1: return (const void*)k_prop<T, kMode, Tiers<T>::q[1]>;
+    default: return (const void*)k_prop<T, kMode, Tiers<T>::q[2]>;
+  }
+}
+
+template <typename T>
+int prop_tier(const ClassDev& c) {
+  const int q = ((c.md.n_pad / 16) * c.nct_max + kPropWaves - 1) / kPropWaves;
+  int tier = 0;
+  while (tier < 2 && Tiers<T>::q[tier] < q) ++tier;
+  return tier;
+}
+
 template <typename T, int kMode>
 hipError_t launch_prop_t(const ClassDev& c, dim3 grid, size_t lds, hipStream_t s, T* taps,
                          int tap_k) {
-  hipLaunchKernelGGL((k_prop<T, kMode>), grid, dim3(kPropThreads), lds, s, c, taps, tap_k);
+  switch (prop_tier<T>(c)) {
+    case 0:
+      hipLaunchKernelGGL((k_prop<T, kMode, Tiers<T>::q[0]>), grid, dim3(kPropThreads), lds, s, c, taps,
+                         tap_k);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_prop<T, kMode, Tiers<T>::q[1]>), grid, dim3(kPropThreads), lds, s, c, taps,
+                         tap_k);
+      break;
+    default:
+      hipLaunchKernelGGL((k_prop<T, kMode, Tiers<T>::q[2]>), grid, dim3(kPropThreads), lds, s, c, taps,
+                         tap_k);
+      break;
+  }
   return hipGetLastError();
 }
 
@@ -378,16 +424,22 @@ size_t prop_lds_bytes(const ClassDev& c, int precision) {
 hipError_t prop_prepare(const ClassDev& c, int precision) {
   const size_t lds = prop_lds_bytes(c, precision);
   if (lds <= 64 * 1024) return hipSuccess;
-  if (precision == IESH_FP64) {
-    for (const void* fn : {(const void*)k_prop<double, kPropagate>, (const void*)k_prop<double, kClenshawTaps>,
-                           (const void*)k_prop<double, kForwardTaps>}) {
+  for (int tier = 0; tier < 3; ++tier) {
+    const void* fns[3] = {nullptr, nullptr, nullptr};
+    if (precision == IESH_FP64) {
+      fns[0] = prop_fn<double, kPropagate>(tier);
+      fns[1] = prop_fn<double, kClenshawTaps>(tier);
+      fns[2] = prop_fn<double, kForwardTaps>(tier);
+    } else {
+      fns[0] = prop_fn<float, kPropagate>(tier);
+    }
+    for (const void* fn : fns) {
+      if (!fn) continue;
       const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    return hipSuccess;
   }
-  return hipFuncSetAttribute((const void*)k_prop<float, kPropagate>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return hipSuccess;
 }
 
 hipError_t launch_prop(const ClassDev& c, int precision, hipStream_t s) {
