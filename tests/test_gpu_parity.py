@@ -425,3 +425,61 @@ def test_compaction_is_invisible_in_the_results():
     live = sum(i["live"] for i in got[4])
     assert live < 96 and live >= 96 - exited
     assert all(i["live"] == i["n_traj"] for i in ref[4])
+
+
+# ------------------------------------------------------------------ desorption
+def test_desorption_exit_and_total_probability_match_the_oracle():
+    """Desorption workload (Table et-parameters, Gauss-Legendre bath, 300 K
+    Fermi occupations) with the 5 Angstrom threshold: trajectories started
+    just inside it, half moving out; the GPU freezes each at the end of the
+    step that takes it past the threshold.  P_total(t) after every 100 steps
+    and the frozen states equal the oracle's step-by-step run (trajectories
+    with a near-tie hop decision are left out)."""
+    from paper_2212_00518_amd import _lib
+    cfg = make_cfg("desorption", M=20, N=10)
+    m = models.from_config(cfg, M=20)
+    T, steps, chunk = 12, 400, 100
+    xth = cfg["x_threshold"]
+    rs = np.random.default_rng(4)
+    x0 = xth - rs.uniform(0.5, 1.2, size=T)
+    e_kin = rs.uniform(ev_to_ha(0.1), ev_to_ha(0.5), size=T)
+    v0 = np.sqrt(2.0 * e_kin / m.mass[0]) * np.where(np.arange(T) % 2 == 0, 1.0, -1.0)
+    states = [dyn.initial_state(m, x0[t], v0[t], 10, cfg["kT"], cfg["seed"], t) for t in range(T)]
+    eps, w = _lib.discretize(cfg["bath"]["kind"], 20, cfg["bath"]["W"])
+    desc = _lib.model_desc(cfg["model"], eps, w, 10)
+    ens = _lib.Ensemble([desc], dict(n_traj=T, precision="fp64", dt=cfg["dt"], kT=cfg["kT"],
+                                     seed=cfg["seed"], exit_enabled=1, exit_x=xth))
+    upload(ens, states)
+    p_gpu = []
+    for _ in range(steps // chunk):
+        ens.run(chunk)
+        p_gpu.append(int(np.sum(ens.status() & _lib.TRAJ_EXITED)))
+    x, v, Cf, occ = ens.get_state()
+    ens.close()
+    exit_step = np.full(T, steps + 1)
+    compared = 0
+    for t in range(T):
+        st = states[t]
+        F = None
+        tie = False
+        for k in range(steps):
+            st, ev, F = dyn.step(m, st, cfg["dt"], rng.uniform(cfg["seed"], t, k), F)
+            tie |= ev["attempted"] and ev["margin"] < 1e-7 * max(ev["g_total"], 1e-300)
+            if st.x[0] > xth:
+                exit_step[t] = k + 1
+                break
+        if tie:
+            continue
+        assert abs(x[t] - st.x[0]) <= 1e-8 * abs(st.x[0]), t
+        assert abs(v[t] - st.v[0]) <= 1e-8 * max(1e-4, abs(st.v[0])), t
+        assert list(occ[t, :10]) == list(st.s), t
+        compared += 1
+    p_ref = [int(np.sum(exit_step <= (q + 1) * chunk)) for q in range(steps // chunk)]
+    print("P_total counts", p_gpu, p_ref, "compared", compared, flush=True)
+    assert p_gpu == p_ref
+    assert compared >= T - 2
+    assert 0 < p_ref[-1] < T
+
+
+def ev_to_ha(e):
+    return e / 27.211386245988

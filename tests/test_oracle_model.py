@@ -184,3 +184,29 @@ def test_eig_arrowhead_identities(cfg_name, M):
             u = np.concatenate([[1.0], V / (lam[j] - eps)])
             u /= np.linalg.norm(u)
             assert np.max(np.abs(u - Q[:, j])) < 1e-9
+
+
+def test_wigner_sample_has_the_quantum_corrected_widths():
+    """The desorption workload's harmonic Wigner sample (Eq. wigner): variances
+    Q kT / (m w^2) and Q kT / m with Q from the closed form, w the harmonic
+    frequency of U0 at its minimum (second derivative from the oracle model by
+    central differences), Q = 1.9 at 300 K as printed."""
+    from workloads import get_config
+    from workloads.sampling import wigner_harmonic
+    cfg = get_config("desorption")
+    m = models.from_config(cfg, M=4)
+    x0 = cfg["model"]["x0"]
+    h = 1e-4
+    k2 = (m.U0(np.array([x0 + h])) - 2 * m.U0(np.array([x0])) + m.U0(np.array([x0 - h]))) / h ** 2
+    omega = float(np.sqrt(k2 / m.mass[0]))
+    kT = cfg["kT"]
+    Q = closed_forms.harmonic_wigner_factor(1.0 / kT, omega)
+    assert abs(Q - _paper()["wigner_Q_10p54u_300K"]["value"]) <= 0.05
+    n = 400000
+    x, v = wigner_harmonic(n, m.mass[0], omega, x0, kT, seed=3)
+    var_x = Q * kT / (m.mass[0] * omega ** 2)
+    var_v = Q * kT / m.mass[0]
+    # sample variance: relative standard error sqrt(2/n) = 0.22%
+    assert abs(np.var(x) / var_x - 1.0) < 0.01
+    assert abs(np.var(v) / var_v - 1.0) < 0.01
+    assert abs(np.mean(x) - x0) < 4.0 * np.sqrt(var_x / n)

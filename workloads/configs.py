@@ -83,6 +83,18 @@ CONFIGS = {
         exit_x=15.0, max_steps=20000,
         n_traj=16384, dt=5.0, seed=0,
     ),
+    # Desorption (Sec. III.C): the vibronic model of Table et-parameters,
+    # Gauss-Legendre bath of 100 states over 64 eV, half filling, 300 K Fermi
+    # occupations and a harmonic Wigner sample of the Morse well; a trajectory
+    # counts as desorbed once x exceeds 5 Angstrom.
+    "desorption": dict(
+        name="desorption, Table et-parameters, GL M=100 W=64 eV, N=50, 300 K, 8192 trajectories, dt=5",
+        model=dict(kind="morse_tanh", **{k: v for k, v in DESORPTION_TABLE.items()},
+                   Gamma=ev(1.0), eps_d=0.0),
+        bath=dict(kind="gauss_legendre", M=100, W=ev(64.0)),
+        n_elec=50, kT=300.0 * KB_HARTREE_PER_K, x_threshold=angstrom(5.0),
+        n_traj=8192, n_steps=2000, dt=5.0, seed=0,
+    ),
     # Adjoint workload: fixed nuclear paths.
     "c4": dict(
         name="adjoint, harmonic M=100 N=50, 1024 fixed paths, 2000 steps, dt=20",

@@ -27,6 +27,22 @@ def boltzmann_harmonic(n_traj: int, mass: float, omega: float, kT: float,
     return x, v
 
 
+def wigner_harmonic(n_traj: int, mass: float, omega: float, x_centre: float, kT: float,
+                    seed: int):
+    """Harmonic Wigner sample about x_centre (Sec. III.C, Eq. wigner): the
+    classical Boltzmann Gaussians with kT replaced by Q kT, where
+    Q = (beta omega / 2) / tanh(beta omega / 2) (hbar = 1).  x has variance
+    Q kT / (m w^2) and v has variance Q kT / m."""
+    rng = np.random.default_rng(seed)
+    half = 0.5 * omega / kT
+    q = half / np.tanh(half)
+    sx = np.sqrt(q * kT / (mass * omega * omega))
+    sv = np.sqrt(q * kT / mass)
+    x = x_centre + rng.normal(0.0, sx, size=n_traj)
+    v = rng.normal(0.0, sv, size=n_traj)
+    return x, v
+
+
 def scattering_initial(n_traj: int, mass: float, x_start: float,
                        e_range: tuple, seed: int):
     """Incoming scattering trajectories: x = x_start, moving toward the
