@@ -250,24 +250,19 @@ def scattering_bench(a):
     print(json.dumps(line), flush=True)
 
 
-def desorption_bench(a):
-    """Desorption workload (Sec. III.C): Table et-parameters, Gauss-Legendre
-    bath of 100 states over 64 eV, half filling, 300 K Fermi occupations, a
-    harmonic Wigner sample of the Morse well; P_total(t) is the fraction of
-    trajectories past 5 Angstrom (frozen on crossing, compaction every 100
-    steps)."""
+def desorption_run(cfg, T, steps):
+    """One desorption ensemble: (trajectory-steps, wall s, P_total every 100
+    steps, tiles per propagation work-group)."""
     import numpy as np
     import torch
-    from paper_2212_00518_amd import _lib
-    from workloads import get_config
+    from paper_2212_00518_amd import _lib, bath_grid, electrons_below
     from workloads.sampling import wigner_harmonic
 
-    cfg = get_config("desorption")
     m, b = cfg["model"], cfg["bath"]
-    T = a.n_traj or cfg["n_traj"]
-    steps = a.steps if a.steps != 100 else cfg["n_steps"]
-    eps, w = _lib.discretize(b["kind"], b["M"], b["W"])
-    desc = _lib.model_desc(m, eps, w, cfg["n_elec"])
+    eps, w = bath_grid(b, b["M"])
+    # fill the bath states below mu (half of them when the band follows mu)
+    n_elec = electrons_below(eps, b.get("mu", 0.0))
+    desc = _lib.model_desc(m, eps, w, n_elec)
     omega = m["a"] * np.sqrt(2.0 * m["De"] / m["mass"])  # harmonic frequency of the Morse U0
     x0, v0 = wigner_harmonic(T, m["mass"], omega, m["x0"], cfg["kT"], seed=cfg["seed"] + 1)
     chunk = 100
@@ -286,29 +281,60 @@ def desorption_bench(a):
         ens.run(k)
         done += k
         p_total.append(round(float(np.mean((ens.status() & _lib.TRAJ_EXITED) > 0)), 6))
-        print(f"# step {done}: P_total {p_total[-1]}", file=sys.stderr, flush=True)
+        print(f"# mu {b.get('mu', 0.0):+.5f} step {done}: P_total {p_total[-1]}", file=sys.stderr,
+              flush=True)
     ens.sync()
     wall = time.perf_counter() - t0
     _, traj_steps = ens.work()
     info = ens.class_info(0)
     ens.close()
+    return traj_steps, wall, p_total, info["tiles_per_group"], n_elec
+
+
+def desorption_bench(a):
+    """Desorption workload (Sec. III.C): Table et-parameters, Gauss-Legendre
+    bath of 100 states over 64 eV, 300 K Fermi occupations, a harmonic Wigner
+    sample of the Morse well; P_total(t) is the fraction of trajectories past
+    5 Angstrom (frozen on crossing, compaction every 100 steps).  The band
+    follows the chemical potential mu (its centre and the Gauss-Legendre split
+    sit at mu) and the electrons fill the bath states below it; --mu-sweep
+    runs mu = -0.5, 0, +0.5 eV."""
+    from workloads import get_config
+    from workloads.configs import ev
+
+    cfg = get_config("desorption")
+    T = a.n_traj or cfg["n_traj"]
+    steps = a.steps if a.steps != 100 else cfg["n_steps"]
+    mus = (-0.5, 0.0, 0.5) if a.mu_sweep else (a.mu,)
+    total_steps, total_wall, sweep = 0, 0.0, {}
+    for mu in mus:
+        c = get_config("desorption")
+        c["bath"]["mu"] = ev(mu)
+        ts, wall, p_total, tiles, n_elec = desorption_run(c, T, steps)
+        total_steps += ts
+        total_wall += wall
+        sweep[f"{mu:+.2f} eV"] = {"p_total_every_100_steps": p_total, "n_elec": n_elec,
+                                  "trajectory_steps_per_s": round(ts / wall, 1)}
+    b = cfg["bath"]
+    m = cfg["model"]
     line = {
         "metric": "trajectory-steps/s (desorption, P_total(t) with x_threshold = 5 Angstrom)",
-        "value": round(traj_steps / wall, 2),
+        "value": round(total_steps / total_wall, 2),
         "unit": "trajectory-steps/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": 0,
-        "ms_per_step": round(1e3 * wall / steps, 3),
+        "ms_per_step": round(1e3 * total_wall / (steps * len(mus)), 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "M": b["M"], "N": cfg["n_elec"], "n_traj": T,
-                   "dt": cfg["dt"], "kT": cfg["kT"], "path": "mixed"},
-        "p_total_every_100_steps": p_total,
-        "tiles_per_group": info["tiles_per_group"],
+        "config": {"workload": cfg["name"], "M": b["M"], "n_traj": T, "dt": cfg["dt"],
+                   "kT": cfg["kT"], "Gamma": m["Gamma"], "path": "mixed",
+                   "mu_eV": list(mus), "band": "centred on mu, Gauss-Legendre split at mu"},
+        "by_mu": sweep,
+        "tiles_per_group": tiles,
     }
     print(json.dumps(line), flush=True)
 
@@ -414,6 +440,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--mu", type=float, default=0.0,
+                    help="desorption: chemical potential in eV (the band follows it)")
+    ap.add_argument("--mu-sweep", action="store_true",
+                    help="desorption: mu = -0.5, 0, +0.5 eV")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint ms/step entry of the default line")
     ap.add_argument("--forced-lifetimes", action="store_true",

@@ -51,8 +51,9 @@ def gauss_legendre(M: int, a: float, b: float, eps_f: float = 0.0):
     return np.concatenate([lo_e, hi_e]), np.concatenate([lo_w, hi_w])
 
 
-def discretise(kind: str, M: int, W: float, eps_f: float = 0.0):
-    a, b = -0.5 * W, 0.5 * W
+def discretise(kind: str, M: int, W: float, eps_f: float = 0.0, centre: float = 0.0):
+    """Bath on [centre - W/2, centre + W/2]; Gauss-Legendre halves split at eps_f."""
+    a, b = centre - 0.5 * W, centre + 0.5 * W
     if kind == "trapezoid":
         return trapezoid(M, a, b)
     if kind == "trapezoid_midpoint":

@@ -165,7 +165,11 @@ def from_config(cfg: dict, M: int | None = None):
     """Build a model from a workload description (``workloads.configs``)."""
     mcfg, bcfg = cfg["model"], cfg["bath"]
     M = M if M is not None else bcfg["M"]
-    eps, w = _bath.discretise(bcfg["kind"], M, bcfg["W"])
+    # chemical potential mu: the band moves with mu ("shift", wide-band limit)
+    # or only the Gauss-Legendre split does ("split")
+    mu = bcfg.get("mu", 0.0)
+    centre = mu if bcfg.get("placement", "shift") == "shift" else 0.0
+    eps, w = _bath.discretise(bcfg["kind"], M, bcfg["W"], eps_f=mu, centre=centre)
     if mcfg["kind"] == "harmonic":
         return Harmonic(eps, w, mcfg["Gamma"], mcfg["mass"], mcfg["omega"], mcfg["g"],
                         mcfg["dG"], mcfg.get("eps_d", 0.0))

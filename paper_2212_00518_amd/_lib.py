@@ -125,13 +125,14 @@ def _ptr(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
 
 
-def discretize(kind: str, M: int, W: float, eps_f: float = 0.0):
-    """Bath energies and weights on [-W/2, W/2] from the library (Appendix A)."""
+def discretize(kind: str, M: int, W: float, eps_f: float = 0.0, centre: float = 0.0):
+    """Bath energies and weights on [centre - W/2, centre + W/2] from the
+    library (Appendix A); the Gauss-Legendre halves split at eps_f."""
     k = {"trapezoid": IESH_BATH_TRAPEZOID, "trapezoid_midpoint": IESH_BATH_TRAPEZOID_MIDPOINT,
          "gauss_legendre": IESH_BATH_GAUSS_LEGENDRE}[kind]
     eps = np.zeros(M)
     w = np.zeros(M)
-    rc = lib().iesh_discretize(k, M, -0.5 * W, 0.5 * W, eps_f,
+    rc = lib().iesh_discretize(k, M, centre - 0.5 * W, centre + 0.5 * W, eps_f,
                                eps.ctypes.data_as(C.POINTER(C.c_double)),
                                w.ctypes.data_as(C.POINTER(C.c_double)))
     if rc != IESH_OK:

@@ -6,6 +6,24 @@ import numpy as np
 from . import _lib
 
 
+def bath_grid(b: dict, M: int):
+    """Bath of a workload description, placed for its chemical potential mu
+    (default 0).  Placement "shift" moves the whole band so that its centre
+    and the Gauss-Legendre split sit at mu (wide-band limit); "split" keeps
+    the band [-W/2, W/2] and splits the Gauss-Legendre halves at mu
+    (Sec. II.B, chemical potential; App. A)."""
+    mu = b.get("mu", 0.0)
+    if b.get("placement", "shift") == "shift":
+        return _lib.discretize(b["kind"], M, b["W"], eps_f=mu, centre=mu)
+    return _lib.discretize(b["kind"], M, b["W"], eps_f=mu)
+
+
+def electrons_below(eps, mu: float) -> int:
+    """Electron count that fills the bath states below mu in the lowest
+    configuration (Sec. II.B, chemical potential)."""
+    return int(np.sum(np.asarray(eps) < mu))
+
+
 def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M: int | None = None,
                 n_elec: int | None = None, lowdin_every: int = 100, record_every: int = 0,
                 stream=None):
@@ -14,7 +32,7 @@ def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M
     b = cfg["bath"]
     M = M if M is not None else b["M"]
     N = n_elec if n_elec is not None else cfg.get("n_elec", M // 2)
-    eps, w = _lib.discretize(b["kind"], M, b["W"])
+    eps, w = bath_grid(b, M)
     desc = _lib.model_desc(cfg["model"], eps, w, N)
     run = dict(n_traj=n_traj if n_traj is not None else cfg["n_traj"], precision=precision,
                dt=cfg["dt"], kT=cfg.get("kT", 0.0), seed=cfg.get("seed", 0),

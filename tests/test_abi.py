@@ -60,6 +60,27 @@ def test_library_discretisation_matches_oracle(kind, M):
     assert np.max(np.abs(w - w_ref)) < 1e-15
 
 
+@pytest.mark.parametrize("kind,M,mu,placement", [("gauss_legendre", 40, 0.01, "shift"),
+                                                 ("gauss_legendre", 100, -0.02, "split"),
+                                                 ("trapezoid", 20, 0.03, "shift")])
+def test_band_placement_for_a_chemical_potential(kind, M, mu, placement):
+    """The library's grid for a chemical potential mu equals the oracle's, and
+    the states below mu are half of the bath when the band or the
+    Gauss-Legendre split follows mu."""
+    from paper_2212_00518_amd import bath_grid, electrons_below
+    from oracle import models
+    from workloads import get_config
+    b = dict(kind=kind, M=M, W=0.1, mu=mu, placement=placement)
+    eps, w = bath_grid(b, M)
+    cfg = get_config("c1")
+    cfg["bath"] = b
+    m = models.from_config(cfg, M=M)
+    e_ref = np.diag(m.H(np.array([0.0])))[1:]
+    assert np.max(np.abs(eps - e_ref)) < 1e-15
+    assert abs(np.sum(w) - 0.1) < 1e-14
+    assert electrons_below(eps, mu) == M // 2
+
+
 def test_discretisation_rejects_bad_arguments(libiesh):
     from paper_2212_00518_amd import _lib
     e = np.zeros(3)

@@ -483,3 +483,22 @@ def test_desorption_exit_and_total_probability_match_the_oracle():
 
 def ev_to_ha(e):
     return e / 27.211386245988
+
+
+@pytest.mark.parametrize("mu_ev,placement", [(0.5, "shift"), (-0.5, "split")])
+def test_single_step_with_the_band_placed_for_a_chemical_potential(mu_ev, placement):
+    """Desorption model with the chemical potential moved off the band centre
+    (the band or only its Gauss-Legendre split follows mu; the electrons fill
+    the bath states below mu): one step from random orbitals matches."""
+    from paper_2212_00518_amd import bath_grid, electrons_below
+    cfg = make_cfg("desorption", M=20)
+    cfg["bath"]["mu"] = ev_to_ha(mu_ev)
+    cfg["bath"]["placement"] = placement
+    eps, _ = bath_grid(cfg["bath"], 20)
+    N = electrons_below(eps, cfg["bath"]["mu"])
+    assert N == 10
+    cfg["n_elec"] = N
+    m = models.from_config(cfg, M=20)
+    T = 6
+    states = random_states(m, N, T, seed=31, xs=np.linspace(3.4, 6.0, T), v_scale=0.002)
+    assert _compare_step(cfg, m, states) >= T - 1
