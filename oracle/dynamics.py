@@ -19,6 +19,13 @@ the step.  Reading used here: the midpoint.  With F_n the force at (x_n, s_n):
      changes (no velocity reversal).
 
 The energy change of a hop is lambda_b(x_new) - lambda_a(x_new).
+
+Electronic sub-steps (Sec. II.C, the paragraph after Eq.
+fast_exponential_integrator): with S > 1 the orbital propagation of step 4
+is split into S sub-steps of dt/S; sub-step j freezes A at the geometry
+x_n + (j + 1/2)/S (x_new - x_n) along the drift, with the same velocity
+v_half, solving the eigenproblem there rather than interpolating lambda and D
+between the nuclear steps.  S = 1 is the midpoint rule above.
 """
 from __future__ import annotations
 
@@ -39,7 +46,7 @@ class State:
         return State(self.x, self.v, self.C, self.s)
 
 
-def step(model, st: State, dt: float, xi: float, F=None):
+def step(model, st: State, dt: float, xi: float, F=None, substeps: int = 1):
     """Advance one step; returns (new_state, event, F_new).
 
     event: dict(hop=bool, attempted=bool, r, a, b, accepted, margin, g_total).
@@ -52,10 +59,18 @@ def step(model, st: State, dt: float, xi: float, F=None):
     x_new = x + dt * v_half
     x_mid = 0.5 * (x + x_new)
 
-    lam_m, Q_m = el.eig(model.H(x_mid))
-    _, Ds_m = el.coupling_matrices(lam_m, Q_m, model.dH(x_mid))
-    A = el.propagator_matrix(lam_m, Ds_m, v_half)
-    C_new = el.propagate(C, A, dt)
+    if substeps == 1:
+        lam_m, Q_m = el.eig(model.H(x_mid))
+        _, Ds_m = el.coupling_matrices(lam_m, Q_m, model.dH(x_mid))
+        A = el.propagator_matrix(lam_m, Ds_m, v_half)
+        C_new = el.propagate(C, A, dt)
+    else:
+        C_new = C
+        for j in range(substeps):
+            x_j = x + ((j + 0.5) / substeps) * (x_new - x)
+            lam_j, Q_j = el.eig(model.H(x_j))
+            _, Ds_j = el.coupling_matrices(lam_j, Q_j, model.dH(x_j))
+            C_new = el.propagate(C_new, el.propagator_matrix(lam_j, Ds_j, v_half), dt / substeps)
 
     lam, Q = el.eig(model.H(x_new))
     Gs, Ds = el.coupling_matrices(lam, Q, model.dH(x_new))
@@ -175,14 +190,14 @@ def initial_state(model, x0, v0, n_elec, kT, seed, traj):
 
 
 def run(model, st: State, dt: float, n_steps: int, seed: int, traj: int, step0: int = 0,
-        record_every: int = 0):
+        record_every: int = 0, substeps: int = 1):
     """Run n_steps; the hop uniform of step k (0-based, counted from step0) is
     rng.uniform(seed, traj, step0 + k).  Returns (state, events, records)."""
     F = el.forces(model, st.x, st.s)
     events, records = [], []
     for k in range(n_steps):
         xi = _rng.uniform(seed, traj, step0 + k)
-        st, ev, F = step(model, st, dt, xi, F)
+        st, ev, F = step(model, st, dt, xi, F, substeps)
         ev["step"] = step0 + k
         if ev["attempted"]:
             events.append(ev)
