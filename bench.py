@@ -62,11 +62,11 @@ def traffic_from_profile(path_md, kernel_src):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_path(cfg, precision, T, steps, warmup, x0, v0):
+def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1):
     import torch
     from paper_2212_00518_amd import from_config
 
-    ens = from_config(cfg, n_traj=T, precision=precision, lowdin_every=100)
+    ens = from_config(cfg, n_traj=T, precision=precision, lowdin_every=100, elec_substeps=substeps)
     ens.init_thermal(x0, v0)
     ens.run(warmup)
     ens.sync()
@@ -444,6 +444,8 @@ def main():
                     help="desorption: chemical potential in eV (the band follows it)")
     ap.add_argument("--mu-sweep", action="store_true",
                     help="desorption: mu = -0.5, 0, +0.5 eV")
+    ap.add_argument("--substeps", type=int, default=1,
+                    help="electronic sub-steps per nuclear step (default 1)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint ms/step entry of the default line")
     ap.add_argument("--forced-lifetimes", action="store_true",
@@ -488,7 +490,7 @@ def main():
     precs = ["fp64", "mixed"] if a.precision == "both" else [a.precision]
     res = {}
     for p in precs:
-        res[p] = time_path(cfg, p, T, a.steps, a.warmup, x0, v0)
+        res[p] = time_path(cfg, p, T, a.steps, a.warmup, x0, v0, a.substeps)
         print(f"# {p}: {res[p]['value']:.1f} trajectory-steps/s, {res[p]['ms_per_step']:.2f} ms/step, "
               f"kernels {res[p]['kernels_ms']} ms, propagation {res[p]['prop_tflops']:.2f} TFLOP/s",
               file=sys.stderr, flush=True)
@@ -511,7 +513,8 @@ def main():
         "dtype": "f32+f64" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "M": cfg["bath"]["M"], "N": cfg["n_elec"],
-                   "n_traj": T, "dt": cfg["dt"], "bath": cfg["bath"]["kind"], "path": head},
+                   "n_traj": T, "dt": cfg["dt"], "bath": cfg["bath"]["kind"], "path": head,
+                   "elec_substeps": a.substeps},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[head],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[head], 4),
                      "traffic": traffic, "kernel": "k_prop",

@@ -125,6 +125,12 @@ typedef struct iesh_run_desc {
                             only active slots (0: never)                         */
   double exit_x;
   int64_t max_steps;     /* freeze a trajectory after this many steps (0: no cap) */
+  int32_t elec_substeps; /* electronic sub-steps per nuclear step, 1..64 (0 = 1):
+                            sub-step j of S propagates dt/S with the propagator
+                            frozen at x_n + (j + 1/2)/S (x_{n+1} - x_n) (Sec. II.C,
+                            sub-stepping of the electronic integrator); hop
+                            probabilities stay once per nuclear step            */
+  int32_t reserved1;
 } iesh_run_desc;
 
 #define IESH_MAX_STATES 336   /* n = M + 1 limit of this build                */

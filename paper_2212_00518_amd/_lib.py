@@ -57,7 +57,8 @@ class RunDesc(C.Structure):
     _fields_ = [("n_traj", C.c_int32), ("precision", C.c_int32), ("dt", C.c_double),
                 ("kT", C.c_double), ("seed", C.c_uint64), ("lowdin_every", C.c_int32),
                 ("record_every", C.c_int32), ("exit_enabled", C.c_int32),
-                ("compact_every", C.c_int32), ("exit_x", C.c_double), ("max_steps", C.c_int64)]
+                ("compact_every", C.c_int32), ("exit_x", C.c_double), ("max_steps", C.c_int64),
+                ("elec_substeps", C.c_int32), ("reserved1", C.c_int32)]
 
 
 class Event(C.Structure):
@@ -187,6 +188,7 @@ class Ensemble:
         r.exit_x = float(run.get("exit_x", 0.0))
         r.max_steps = int(run.get("max_steps", 0))
         r.compact_every = int(run.get("compact_every", 0))
+        r.elec_substeps = int(run.get("elec_substeps", 1))
         self.run_desc = r
         tm = None
         if traj_model is not None:

@@ -403,8 +403,18 @@ int enqueue_step(iesh_ctx* ctx, int record) {
     if (c.n_traj == 0) continue;
     hipStream_t s = ctx->stream;
     Counters* cnt = ctx->cnt;
-    HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return launch_eig_step(c, r.dt, cnt, s); }));
-    HIPTRY(ctx, timed(ctx, IESH_TIMER_PROP, [&] { return launch_prop(c, r.precision, s); }));
+    const int S = r.elec_substeps;
+    if (S <= 1) {
+      HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return launch_eig_step(c, r.dt, cnt, s); }));
+      HIPTRY(ctx, timed(ctx, IESH_TIMER_PROP, [&] { return launch_prop(c, r.precision, s); }));
+    } else {
+      // electronic sub-steps: a propagator and a propagation each, then the end point
+      for (int j = 0; j < S; ++j) {
+        HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return launch_eig_step(c, r.dt, cnt, s, j, S); }));
+        HIPTRY(ctx, timed(ctx, IESH_TIMER_PROP, [&] { return launch_prop(c, r.precision, s); }));
+      }
+      HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return launch_eig_step(c, r.dt, cnt, s, -2, S); }));
+    }
     HIPTRY(ctx, timed(ctx, IESH_TIMER_FILTER, [&] {
              return launch_hop_filter(c, r.dt, r.seed, cnt, record, r.exit_enabled, r.exit_x,
                                       r.max_steps, r.precision, s);
@@ -535,6 +545,9 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
       return (fail(ctx, IESH_EINVAL, "model " + std::to_string(m) + ": " + why), bail(IESH_EINVAL));
   }
   if (r.compact_every < 0) return (fail(ctx, IESH_EINVAL, "negative cadence"), bail(IESH_EINVAL));
+  if (r.elec_substeps < 0 || r.elec_substeps > 64)
+    return (fail(ctx, IESH_EINVAL, "elec_substeps out of range [0, 64]"), bail(IESH_EINVAL));
+  if (ctx->run.elec_substeps == 0) ctx->run.elec_substeps = 1;
   ctx->traj_class.assign(r.n_traj, 0);
   ctx->traj_local.assign(r.n_traj, 0);
   std::vector<int> count(n_models, 0);
@@ -1060,6 +1073,8 @@ int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int
   }
   if (ctx->run.precision != IESH_FP64)
     return fail(ctx, IESH_ENOTSUP, "adjoint: FP64 contexts only");
+  if (ctx->run.elec_substeps > 1)
+    return fail(ctx, IESH_ENOTSUP, "adjoint: one electronic step per nuclear step only");
   for (const auto& c : ctx->cls)
     if (c.n_traj && c.md.kind != IESH_MODEL_HARMONIC)
       return fail(ctx, IESH_ENOTSUP, "adjoint: harmonic (double-well) models only");

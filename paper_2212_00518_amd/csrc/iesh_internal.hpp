@@ -195,7 +195,9 @@ struct CompactBufs {
 
 // -------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files).
-hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s);
+// sub: -1 whole step, j >= 0 propagator of electronic sub-step j of nsub, -2 end point only.
+hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s, int sub = -1,
+                           int nsub = 1);
 hipError_t launch_eig_query(const ClassDev& c, int t0, int nt, hipStream_t s);
 hipError_t launch_init_thermal(const ClassDev& c, double kT, uint64_t seed, hipStream_t s);
 hipError_t launch_forces(const ClassDev& c, hipStream_t s);

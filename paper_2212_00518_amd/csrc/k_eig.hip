@@ -351,8 +351,12 @@ __device__ void load_bath(const ClassDev& c, EigLds& L) {
 }
 
 // One step for one trajectory up to (not including) the propagation.
+// sub = -1: the whole step (midpoint geometry for the propagator, then the
+// end point); sub = j in [0, nsub): only the propagator of electronic
+// sub-step j, frozen at x_n + (j + 1/2)/nsub (x_{n+1} - x_n) for dt/nsub;
+// sub = -2: only the end point (after the sub-steps).
 __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt, int precision,
-                                                           Counters* cnt) {
+                                                           Counters* cnt, int sub, int nsub) {
   __shared__ EigLds L;
   const int t = blockIdx.x;
   const int tid = threadIdx.x;
@@ -375,14 +379,16 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt,
     }
     L.sc[0] = vh;
     L.sc[1] = xn;
-    L.sc[2] = 0.5 * (x + xn);
+    L.sc[2] = (sub >= 0) ? x + ((sub + 0.5) / nsub) * (xn - x) : 0.5 * (x + xn);
   }
   __syncthreads();
   const double vh = L.sc[0], xn = L.sc[1], xm = L.sc[2];
+  const double dte = (sub >= 0) ? dt / nsub : dt;  // electronic step of this propagator
 
+  const int n = md.n, n_pad = md.n_pad, RT = n_pad / 16;
+  if (sub != -2) {
   // ---- midpoint geometry: couplings for the propagator
   const ModelAt mm = solve_arrowhead(md, c.vbar, xm, L);
-  const int n = md.n, n_pad = md.n_pad, RT = n_pad / 16;
   double* Bt = c.Bt + (size_t)t * n_pad * n_pad;
   float* Bt32 = c.Bt32 ? c.Bt32 + (size_t)t * n_pad * n_pad : nullptr;
   double lo_part = 1e300, hi_part = -1e300;
@@ -420,7 +426,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt,
     const double lo = L.red[0], hi = L.red2[0];
     const double cc = 0.5 * (lo + hi);
     const double rr = fmax(0.5 * (hi - lo), 1e-300);
-    const double rho = rr * dt;
+    const double rho = rr * dte;
     const int K = cheb_terms(rho, precision == IESH_FP64 ? 2e-16 : 1e-8);
     if (K < 0) {
       atomicOr(&L.fail, 2);
@@ -428,7 +434,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt,
       double* J = L.J;
       bessel_j(K, rho, J);
       double sn, cs;
-      sincos(cc * dt, &sn, &cs);
+      sincos(cc * dte, &sn, &cs);
       // e^{-i c dt} * (2 - delta_k0) * (-i)^k * J_k
       for (int k = 0; k <= K; ++k) {
         const double a = (k ? 2.0 : 1.0) * J[k];
@@ -448,11 +454,17 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt,
       cb[CHEB_RHO] = rho;
       // work counters (integer sums: independent of the order of the adds)
       atomicAdd((unsigned long long*)&cnt->sum_cheb, (unsigned long long)K);
-      atomicAdd((unsigned long long*)&cnt->traj_steps, 1ull);
+      if (sub <= 0) atomicAdd((unsigned long long*)&cnt->traj_steps, 1ull);
       atomicMax((unsigned long long*)&cnt->max_cheb, (unsigned long long)K);
     }
   }
   __syncthreads();
+  }
+  if (sub >= 0) {
+    // a sub-step's failure freezes the trajectory before its propagation
+    if (tid == 0 && L.fail) c.status[t] |= IESH_TRAJ_NONCONV;
+    return;
+  }
 
   // ---- end-point geometry: energies, amplitudes, forces
   const ModelAt mn = solve_arrowhead(md, c.vbar, xn, L);
@@ -808,10 +820,12 @@ __global__ void k_conj_cheb(ClassDev c, double* out) {
 
 }  // namespace
 
-hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s) {
+hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s, int sub,
+                           int nsub) {
   const int precision = c.C64 ? IESH_FP64 : IESH_MIXED;
   if (c.n_live < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_eig_step, dim3(c.n_live), dim3(kEigThreads), 0, s, c, dt, precision, cnt);
+  hipLaunchKernelGGL(k_eig_step, dim3(c.n_live), dim3(kEigThreads), 0, s, c, dt, precision, cnt, sub,
+                     nsub);
   return hipGetLastError();
 }
 

@@ -26,7 +26,7 @@ def electrons_below(eps, mu: float) -> int:
 
 def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M: int | None = None,
                 n_elec: int | None = None, lowdin_every: int = 100, record_every: int = 0,
-                stream=None):
+                stream=None, elec_substeps: int = 1):
     """One-class ensemble for a workload description of ``workloads.configs``
     (bath discretised by the library)."""
     b = cfg["bath"]
@@ -37,7 +37,7 @@ def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M
     run = dict(n_traj=n_traj if n_traj is not None else cfg["n_traj"], precision=precision,
                dt=cfg["dt"], kT=cfg.get("kT", 0.0), seed=cfg.get("seed", 0),
                lowdin_every=lowdin_every if precision == "mixed" else 0,
-               record_every=record_every)
+               record_every=record_every, elec_substeps=elec_substeps)
     return _lib.Ensemble([desc], run, stream=stream)
 
 

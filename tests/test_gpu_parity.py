@@ -502,3 +502,61 @@ def test_single_step_with_the_band_placed_for_a_chemical_potential(mu_ev, placem
     T = 6
     states = random_states(m, N, T, seed=31, xs=np.linspace(3.4, 6.0, T), v_scale=0.002)
     assert _compare_step(cfg, m, states) >= T - 1
+
+
+# ------------------------------------------------------ electronic sub-steps
+def _substep_ensemble(cfg, T, S, precision="fp64"):
+    from paper_2212_00518_amd import _lib, bath_grid
+    eps, w = bath_grid(cfg["bath"], cfg["bath"]["M"])
+    desc = _lib.model_desc(cfg["model"], eps, w, cfg["n_elec"])
+    return _lib.Ensemble([desc], dict(n_traj=T, precision=precision, dt=cfg["dt"], kT=cfg["kT"],
+                                      seed=cfg["seed"], elec_substeps=S,
+                                      lowdin_every=100 if precision == "mixed" else 0))
+
+
+@pytest.mark.parametrize("S,precision,tol", [(4, "fp64", 1e-10), (3, "fp64", 1e-10), (2, "mixed", 1e-5)])
+def test_electronic_substeps_match_the_oracle(S, precision, tol):
+    """Sub-stepped propagation (S propagators along the drift per nuclear
+    step) over 30 steps of the graph-replayed run: states and hop events
+    equal the oracle's step(substeps=S) run, trajectories with a near-tie
+    hop decision left out."""
+    from paper_2212_00518_amd import unpack_C
+    T, steps = 8, 30
+    cfg, m, states = _hot_c1(T)
+    ens = _substep_ensemble(cfg, T, S, precision)
+    upload(ens, states)
+    ens.run(steps)
+    x, v, Cf, occ = ens.get_state()
+    evs, _ = ens.events()
+    n_max, N_max = ens.n_max, ens.N_max
+    ens.close()
+    compared = 0
+    for t in range(T):
+        ref, ref_ev, _ = dyn.run(m, states[t], cfg["dt"], steps, cfg["seed"], t, substeps=S)
+        if any(e["margin"] < 1e3 * tol * max(e["g_total"], 1e-300) for e in ref_ev):
+            continue
+        mine = [e for e in evs if e["traj"] == t]
+        assert [(e["step"], e["a"], e["b"], e["accepted"]) for e in mine] == \
+               [(e["step"], e["a"], e["b"], e["accepted"]) for e in ref_ev], t
+        assert abs(x[t] - ref.x[0]) <= tol * max(1.0, abs(ref.x[0])), t
+        assert abs(v[t] - ref.v[0]) <= tol * max(1e-3, abs(ref.v[0])), t
+        Cg = unpack_C(Cf, t, m.n, cfg["n_elec"], n_max, N_max)
+        assert np.max(np.abs(Cg - ref.C)) <= 10 * tol, t
+        assert list(occ[t, :cfg["n_elec"]]) == list(ref.s), t
+        compared += 1
+    assert compared >= T - 2
+
+
+def test_one_substep_is_the_plain_step():
+    """elec_substeps = 1 and the default give bitwise the same run."""
+    T = 8
+    cfg, m, states = _hot_c1(T)
+    out = []
+    for S in (0, 1):
+        ens = _substep_ensemble(cfg, T, S)
+        upload(ens, states)
+        ens.run(40)
+        out.append(ens.get_state())
+        ens.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
