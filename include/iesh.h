@@ -79,7 +79,16 @@ enum iesh_model_kind {
      V_k(x) = Vbar_k [(1-q)/2 (1 - tanh((x - xt)/at)) + q].
      params: [0] De, [1] x0, [2] a, [3] D1, [4] D2, [5] a', [6] Vinf, [7] q,
              [8] at, [9] xt, [10] c, [11] eps_d.                            */
-  IESH_MODEL_MORSE_TANH = 1
+  IESH_MODEL_MORSE_TANH = 1,
+  /* Several nuclear coordinates R_1 .. R_D (D = n_dof <= IESH_MAX_DOF), for a
+     molecule with internal and surface-normal modes; the functional forms are
+     this library's choice (the paper's models are one-dimensional):
+       U0(R) = sum_nu D_nu (1 - exp(-a_nu (R_nu - r_nu)))^2,
+       h(R)  = U1 - U0 + eps_d = Delta + eps_d + sum_nu g_nu (R_nu - r_nu),
+       V_k(R) = Vbar_k f(R),  f(R) = exp(-sum_nu (R_nu - c_nu)^2 / (4 s_nu^2))
+     (so Gamma(R) = Gamma f^2 is a Gaussian in R).  params: [0] Delta,
+     [1] eps_d; dof: n_dof rows of (mass, D, a, r, g, c, s).               */
+  IESH_MODEL_MULTI_DOF = 2
 };
 
 enum iesh_precision {
@@ -103,12 +112,16 @@ typedef struct iesh_model_desc {
   int32_t kind;        /* enum iesh_model_kind                                */
   int32_t n_bath;      /* M >= 1; n = M + 1 <= IESH_MAX_STATES                */
   int32_t n_elec;      /* N electrons, 1 <= N <= min(n - 1, IESH_MAX_ELEC)     */
-  int32_t reserved0;
+  int32_t n_dof;       /* nuclear coordinates: 1 (0 means 1) except for
+                          IESH_MODEL_MULTI_DOF (1 .. IESH_MAX_DOF); all models
+                          of a context have the same count                     */
   const double* eps;   /* host, M bath energies, strictly ascending           */
   const double* w;     /* host, M quadrature weights > 0 (V_k = sqrt(Gamma w_k / 2 pi)) */
-  double mass;         /* nuclear mass > 0                                    */
+  double mass;         /* nuclear mass > 0 (one coordinate)                   */
   double Gamma;        /* hybridisation Gamma > 0 (Eq. hybridization)          */
   double params[16];   /* model constants, layout per iesh_model_kind         */
+  const double* dof;   /* host, IESH_MODEL_MULTI_DOF: n_dof rows of 7 doubles
+                          (mass > 0, D, a, r, g, c, s > 0); else unused       */
 } iesh_model_desc;
 
 typedef struct iesh_run_desc {
@@ -119,7 +132,7 @@ typedef struct iesh_run_desc {
   uint64_t seed;         /* key of the hop uniforms                             */
   int32_t lowdin_every;  /* IESH_MIXED: re-orthonormalise every L steps (0: never) */
   int32_t record_every;  /* observables every R steps in iesh_run (0: none)    */
-  int32_t exit_enabled;  /* freeze trajectories once x > exit_x                */
+  int32_t exit_enabled;  /* freeze trajectories once x > exit_x (coordinate 0)  */
   int32_t compact_every; /* iesh_run: every this many steps, move frozen trajectories
                             behind the active ones so that the step kernels visit
                             only active slots (0: never)                         */
@@ -135,6 +148,7 @@ typedef struct iesh_run_desc {
 
 #define IESH_MAX_STATES 336   /* n = M + 1 limit of this build                */
 #define IESH_MAX_ELEC 168     /* N limit of this build                        */
+#define IESH_MAX_DOF 6        /* nuclear coordinates per trajectory            */
 
 /* Observables written per record and trajectory by iesh_run, in this order. */
 #define IESH_OBS_PD_SURF 0   /* sum_{a in s} Q[0][a]^2                         */
@@ -179,7 +193,7 @@ int iesh_discretize(int32_t kind, int32_t M, double a, double b, double eps_f, d
 
 /* ---- state ----------------------------------------------------------------
    Layouts (both for host and device buffers):
-     x, v   : n_traj doubles
+     x, v   : n_traj blocks of n_dof doubles (the context's coordinate count)
      C      : n_traj blocks; block t holds N_t * n_t complex doubles,
               orbital-major (C[t][j][i] = coefficient of adiabatic state i in
               orbital j), interleaved (re, im); blocks are packed with the
@@ -259,6 +273,8 @@ int iesh_class_info(const iesh_ctx* ctx, int32_t cls, int32_t* info);
 typedef struct iesh_sizes {
   int32_t n_traj, n_models, n_max, N_max;
   int64_t device_bytes;
+  int32_t n_dof;  /* nuclear coordinates per trajectory */
+  int32_t reserved;
 } iesh_sizes;
 int iesh_query_sizes(const iesh_ctx* ctx, iesh_sizes* out);
 

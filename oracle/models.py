@@ -10,7 +10,7 @@ electronic_hamiltonian) in the diabatic basis {|d>, |1>, ..., |M>} is the
 
 and the nuclear potential of a configuration s is U0(x) + sum_{k in s}
 lambda_k(x) (Eq. classical_hamiltonian).  Positions are arrays of n_dof
-coordinates; every model here has n_dof = 1.
+coordinates; the models of the paper have n_dof = 1, MultiDof has several.
 """
 from __future__ import annotations
 
@@ -161,6 +161,46 @@ class MorseTanh(Model):
         return (self.Vbar * df)[:, None]
 
 
+class MultiDof(Model):
+    """Several coordinates R_1 .. R_D (the library's multi-coordinate model;
+    the paper's models are one-dimensional):
+        U0(R) = sum_nu D_nu (1 - exp(-a_nu (R_nu - r_nu)))^2
+        h(R)  = Delta + eps_d + sum_nu g_nu (R_nu - r_nu)
+        V_k(R) = Vbar_k exp(-sum_nu (R_nu - c_nu)^2 / (4 s_nu^2)).
+    dof rows: (mass, D, a, r, g, c, s)."""
+
+    def __init__(self, eps, w, Gamma, dof, Delta, eps_d=0.0):
+        dof = np.asarray(dof, dtype=np.float64)
+        super().__init__(eps, w, Gamma, dof[:, 0])
+        self.n_dof = dof.shape[0]
+        self.D, self.a, self.r, self.g, self.c, self.s = (dof[:, k] for k in range(1, 7))
+        self.Delta, self.eps_d = float(Delta), float(eps_d)
+
+    def U0(self, x):
+        e = np.exp(-self.a * (x - self.r))
+        return float(np.sum(self.D * (1.0 - e) ** 2))
+
+    def dU0(self, x):
+        e = np.exp(-self.a * (x - self.r))
+        return 2.0 * self.D * self.a * e * (1.0 - e)
+
+    def h(self, x):
+        return self.Delta + self.eps_d + float(np.sum(self.g * (x - self.r)))
+
+    def dh(self, x):
+        return self.g.copy()
+
+    def _f(self, x):
+        return float(np.exp(-np.sum((x - self.c) ** 2 / (4.0 * self.s ** 2))))
+
+    def V(self, x):
+        return self.Vbar * self._f(x)
+
+    def dV(self, x):
+        df = -self._f(x) * (x - self.c) / (2.0 * self.s ** 2)  # (n_dof,)
+        return self.Vbar[:, None] * df[None, :]
+
+
 def from_config(cfg: dict, M: int | None = None):
     """Build a model from a workload description (``workloads.configs``)."""
     mcfg, bcfg = cfg["model"], cfg["bath"]
@@ -173,6 +213,8 @@ def from_config(cfg: dict, M: int | None = None):
     if mcfg["kind"] == "harmonic":
         return Harmonic(eps, w, mcfg["Gamma"], mcfg["mass"], mcfg["omega"], mcfg["g"],
                         mcfg["dG"], mcfg.get("eps_d", 0.0))
+    if mcfg["kind"] == "multi_dof":
+        return MultiDof(eps, w, mcfg["Gamma"], mcfg["dof"], mcfg["Delta"], mcfg.get("eps_d", 0.0))
     if mcfg["kind"] == "morse_tanh":
         return MorseTanh(eps, w, mcfg["Gamma"], mcfg["mass"], mcfg["De"], mcfg["x0"],
                          mcfg["a"], mcfg["D1"], mcfg["D2"], mcfg["ap"], mcfg["Vinf"],

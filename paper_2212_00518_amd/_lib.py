@@ -18,6 +18,8 @@ LIB_PATH = os.environ.get("IESH_LIBRARY", os.path.join(HERE, "libiesh.so"))
 IESH_OK = 0
 IESH_MODEL_HARMONIC = 0
 IESH_MODEL_MORSE_TANH = 1
+IESH_MODEL_MULTI_DOF = 2
+IESH_MAX_DOF = 6
 IESH_FP64 = 0
 IESH_MIXED = 1
 IESH_MEM_HOST = 0
@@ -48,9 +50,9 @@ TIMERS = ("eig", "prop", "hop", "lowdin", "filter", "adj_prop", "adj_phi", "adj_
 
 class ModelDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_bath", C.c_int32), ("n_elec", C.c_int32),
-                ("reserved0", C.c_int32), ("eps", C.POINTER(C.c_double)),
+                ("n_dof", C.c_int32), ("eps", C.POINTER(C.c_double)),
                 ("w", C.POINTER(C.c_double)), ("mass", C.c_double), ("Gamma", C.c_double),
-                ("params", C.c_double * 16)]
+                ("params", C.c_double * 16), ("dof", C.POINTER(C.c_double))]
 
 
 class RunDesc(C.Structure):
@@ -68,7 +70,8 @@ class Event(C.Structure):
 
 class Sizes(C.Structure):
     _fields_ = [("n_traj", C.c_int32), ("n_models", C.c_int32), ("n_max", C.c_int32),
-                ("N_max", C.c_int32), ("device_bytes", C.c_int64)]
+                ("N_max", C.c_int32), ("device_bytes", C.c_int64), ("n_dof", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -150,10 +153,21 @@ def model_desc(model: dict, eps, w, n_elec: int):
     d.n_elec = int(n_elec)
     d.eps = eps.ctypes.data_as(C.POINTER(C.c_double))
     d.w = w.ctypes.data_as(C.POINTER(C.c_double))
-    d.mass = float(model["mass"])
+    d.mass = float(model.get("mass", 0.0))
     d.Gamma = float(model["Gamma"])
     p = [0.0] * 16
-    if model["kind"] == "harmonic":
+    dof = None
+    d.n_dof = 1
+    if model["kind"] == "multi_dof":
+        d.kind = IESH_MODEL_MULTI_DOF
+        p[:2] = [model["Delta"], model.get("eps_d", 0.0)]
+        dof = np.ascontiguousarray(model["dof"], dtype=np.float64)
+        if dof.ndim != 2 or dof.shape[1] != 7:
+            raise ValueError("dof: rows of (mass, D, a, r, g, c, s)")
+        d.n_dof = dof.shape[0]
+        d.dof = dof.ctypes.data_as(C.POINTER(C.c_double))
+        d.mass = float(dof[0, 0])
+    elif model["kind"] == "harmonic":
         d.kind = IESH_MODEL_HARMONIC
         p[:4] = [model["omega"], model["g"], model["dG"], model.get("eps_d", 0.0)]
     elif model["kind"] == "morse_tanh":
@@ -164,7 +178,7 @@ def model_desc(model: dict, eps, w, n_elec: int):
         raise ValueError(model["kind"])
     d.params[:] = p
     # keep arrays alive with the descriptor
-    d._keep = (eps, w)
+    d._keep = (eps, w, dof)
     return d
 
 
@@ -203,6 +217,7 @@ class Ensemble:
         s = Sizes()
         L.iesh_query_sizes(ctx, C.byref(s))
         self.n_traj, self.n_max, self.N_max = s.n_traj, s.n_max, s.N_max
+        self.n_dof = max(1, s.n_dof)
         self.device_bytes = s.device_bytes
 
     def _check(self, rc, what):
@@ -222,12 +237,19 @@ class Ensemble:
             pass
 
     # ---------------------------------------------------------------- state
+    def _nuc(self, a):
+        """Positions or velocities as the (T * n_dof) block layout of iesh.h."""
+        return np.ascontiguousarray(a, dtype=np.float64).reshape(self.n_traj * self.n_dof)
+
+    def _nuc_out(self, a):
+        return a if self.n_dof == 1 else a.reshape(self.n_traj, self.n_dof)
+
     def set_state(self, x, v, Cmat, occ):
-        """x, v: (T,), Cmat: (T, N_max, n_max) complex (orbital-major, blocks
-        packed as documented in iesh.h), occ: (T, N_max) int32."""
-        T = self.n_traj
-        x = np.ascontiguousarray(x, dtype=np.float64).reshape(T)
-        v = np.ascontiguousarray(v, dtype=np.float64).reshape(T)
+        """x, v: (T,) or (T, n_dof), Cmat: (T, N_max, n_max) complex
+        (orbital-major, blocks packed as documented in iesh.h), occ:
+        (T, N_max) int32."""
+        x = self._nuc(x)
+        v = self._nuc(v)
         Cc = np.ascontiguousarray(Cmat, dtype=np.complex128)
         occ = np.ascontiguousarray(occ, dtype=np.int32)
         self._check(lib().iesh_set_state(self.ctx, _ptr(x), _ptr(v), _ptr(Cc), _ptr(occ),
@@ -235,17 +257,17 @@ class Ensemble:
 
     def get_state(self):
         T = self.n_traj
-        x = np.zeros(T)
-        v = np.zeros(T)
+        x = np.zeros(T * self.n_dof)
+        v = np.zeros(T * self.n_dof)
         Cc = np.zeros(T * self.n_max * self.N_max, dtype=np.complex128)
         occ = np.zeros((T, self.N_max), dtype=np.int32)
         self._check(lib().iesh_get_state(self.ctx, _ptr(x), _ptr(v), _ptr(Cc), _ptr(occ),
                                          IESH_MEM_HOST), "iesh_get_state")
-        return x, v, Cc, occ
+        return self._nuc_out(x), self._nuc_out(v), Cc, occ
 
     def init_thermal(self, x, v):
-        x = np.ascontiguousarray(x, dtype=np.float64)
-        v = np.ascontiguousarray(v, dtype=np.float64)
+        x = self._nuc(x)
+        v = self._nuc(v)
         self._check(lib().iesh_init_thermal(self.ctx, x.ctypes.data_as(C.POINTER(C.c_double)),
                                             v.ctypes.data_as(C.POINTER(C.c_double))),
                     "iesh_init_thermal")

@@ -28,6 +28,7 @@ struct iesh_ctx {
   Counters* cnt = nullptr;
   iesh_event* events = nullptr;
   int n_max = 0, N_max = 0;
+  int ndof = 1;  // nuclear coordinates per trajectory (all models)
   int n_cu = 256;  // compute units of the device
   int64_t step = 0;
   size_t device_bytes = 0;
@@ -190,10 +191,35 @@ int autotune_slabs(iesh_ctx* ctx, ClassDev& c) {
   return IESH_OK;
 }
 
+int model_ndof(const iesh_model_desc& m) { return m.n_dof < 1 ? 1 : m.n_dof; }
+
 int validate_model(const iesh_model_desc& m, std::string& why) {
-  if (m.kind != IESH_MODEL_HARMONIC && m.kind != IESH_MODEL_MORSE_TANH) {
+  if (m.kind != IESH_MODEL_HARMONIC && m.kind != IESH_MODEL_MORSE_TANH &&
+      m.kind != IESH_MODEL_MULTI_DOF) {
     why = "unknown model kind";
     return 0;
+  }
+  if (m.kind != IESH_MODEL_MULTI_DOF && model_ndof(m) != 1) {
+    why = "only IESH_MODEL_MULTI_DOF has several coordinates";
+    return 0;
+  }
+  if (m.kind == IESH_MODEL_MULTI_DOF) {
+    if (m.n_dof < 1 || m.n_dof > IESH_MAX_DOF || !m.dof) {
+      why = "n_dof out of range [1, IESH_MAX_DOF] or dof missing";
+      return 0;
+    }
+    for (int nu = 0; nu < m.n_dof; ++nu) {
+      const double* r = m.dof + 7 * nu;
+      for (int q = 0; q < 7; ++q)
+        if (!std::isfinite(r[q])) {
+          why = "non-finite coordinate constant";
+          return 0;
+        }
+      if (!(r[0] > 0.0) || !(r[6] > 0.0)) {
+        why = "coordinate mass and Gaussian width must be > 0";
+        return 0;
+      }
+    }
   }
   if (m.n_bath < 1 || m.n_bath + 1 > IESH_MAX_STATES) {
     why = "n_bath out of range [1, IESH_MAX_STATES-1]";
@@ -217,7 +243,7 @@ int validate_model(const iesh_model_desc& m, std::string& why) {
       return 0;
     }
   }
-  if (!(m.mass > 0.0) || !(m.Gamma > 0.0)) {
+  if ((m.kind != IESH_MODEL_MULTI_DOF && !(m.mass > 0.0)) || !(m.Gamma > 0.0)) {
     why = "mass and Gamma must be > 0";
     return 0;
   }
@@ -229,8 +255,8 @@ int upload_state(iesh_ctx* ctx, const double* x, const double* v, const double* 
   const int T = ctx->run.n_traj;
   for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
     ClassDev& c = ctx->cls[ci];
-    const int Tc = c.n_traj, N = c.md.N, n = c.md.n, n_pad = c.md.n_pad;
-    std::vector<double> hx(Tc), hv(Tc);
+    const int Tc = c.n_traj, N = c.md.N, n = c.md.n, n_pad = c.md.n_pad, nd = ctx->ndof;
+    std::vector<double> hx((size_t)Tc * nd), hv((size_t)Tc * nd);
     std::vector<int32_t> hocc((size_t)Tc * N);
     std::vector<double> hC;
     std::vector<float> hC32;
@@ -244,8 +270,10 @@ int upload_state(iesh_ctx* ctx, const double* x, const double* v, const double* 
     int tl = 0;
     for (int t = 0; t < T; ++t) {
       if (ctx->traj_class[t] != (int)ci) continue;
-      hx[tl] = x[t];
-      hv[tl] = v[t];
+      for (int nu = 0; nu < nd; ++nu) {
+        hx[(size_t)tl * nd + nu] = x[(size_t)t * nd + nu];
+        hv[(size_t)tl * nd + nu] = v[(size_t)t * nd + nu];
+      }
       if (occ) {
         for (int r = 0; r < N; ++r) {
           const int a = occ[(size_t)t * ctx->N_max + r];
@@ -271,8 +299,10 @@ int upload_state(iesh_ctx* ctx, const double* x, const double* v, const double* 
       }
       ++tl;
     }
-    HIPTRY(ctx, hipMemcpyAsync(c.x, hx.data(), Tc * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HIPTRY(ctx, hipMemcpyAsync(c.v, hv.data(), Tc * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPTRY(ctx, hipMemcpyAsync(c.x, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice,
+                               ctx->stream));
+    HIPTRY(ctx, hipMemcpyAsync(c.v, hv.data(), hv.size() * sizeof(double), hipMemcpyHostToDevice,
+                               ctx->stream));
     if (occ)
       HIPTRY(ctx, hipMemcpyAsync(c.occ, hocc.data(), hocc.size() * sizeof(int32_t),
                                  hipMemcpyHostToDevice, ctx->stream));
@@ -338,9 +368,10 @@ int compact(iesh_ctx* ctx) {
     auto cp = [&](void* dst, const void* src, size_t bytes) {
       return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream);
     };
-    HIPTRY(ctx, cp(c.x, b.x, nl * sizeof(double)));
-    HIPTRY(ctx, cp(c.v, b.v, nl * sizeof(double)));
-    HIPTRY(ctx, cp(c.F, b.F, nl * sizeof(double)));
+    const size_t nds = (size_t)nl * c.md.ndof * sizeof(double);
+    HIPTRY(ctx, cp(c.x, b.x, nds));
+    HIPTRY(ctx, cp(c.v, b.v, nds));
+    HIPTRY(ctx, cp(c.F, b.F, nds));
     HIPTRY(ctx, cp(c.status, b.status, nl * sizeof(int32_t)));
     HIPTRY(ctx, cp(c.gtraj, b.gtraj, nl * sizeof(int32_t)));
     HIPTRY(ctx, cp(c.home, b.home, nl * sizeof(int32_t)));
@@ -580,6 +611,23 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     c.md.mass = d.mass;
     c.md.Gamma = d.Gamma;
     for (int q = 0; q < 16; ++q) c.md.p[q] = d.params[q];
+    c.md.ndof = model_ndof(d);
+    if (m == 0) ctx->ndof = c.md.ndof;
+    if (c.md.ndof != ctx->ndof)
+      return (fail(ctx, IESH_EINVAL, "all models of a context need the same n_dof"), bail(IESH_EINVAL));
+    for (int nu = 0; nu < kMaxDof; ++nu) {
+      c.md.mass_dof[nu] = 0.0;
+      for (int q = 0; q < 6; ++q) c.md.dofp[nu][q] = 0.0;
+    }
+    if (d.kind == IESH_MODEL_MULTI_DOF) {
+      c.md.mass = d.dof[0];
+      for (int nu = 0; nu < c.md.ndof; ++nu) {
+        c.md.mass_dof[nu] = d.dof[7 * nu];
+        for (int q = 0; q < 6; ++q) c.md.dofp[nu][q] = d.dof[7 * nu + 1 + q];
+      }
+    } else {
+      c.md.mass_dof[0] = d.mass;
+    }
     c.n_traj = count[m];
     c.n_live = count[m];
     ctx->slot_home[m].assign(count[m], 0);
@@ -590,8 +638,10 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     choose_slabs(c, r.precision);
     const int T = c.n_traj, n_pad = c.md.n_pad, N = c.md.N, M = c.md.M;
     if (T == 0) continue;
+    const int nd = c.md.ndof;
     if ((rc = dalloc(ctx, &c.eps, M)) || (rc = dalloc(ctx, &c.vbar, M)) ||
-        (rc = dalloc(ctx, &c.x, T)) || (rc = dalloc(ctx, &c.v, T)) || (rc = dalloc(ctx, &c.F, T)) ||
+        (rc = dalloc(ctx, &c.x, (size_t)T * nd)) || (rc = dalloc(ctx, &c.v, (size_t)T * nd)) ||
+        (rc = dalloc(ctx, &c.F, (size_t)T * nd)) ||
         (rc = dalloc(ctx, &c.occ, (size_t)T * N)) || (rc = dalloc(ctx, &c.status, T)) ||
         (rc = dalloc(ctx, &c.gtraj, T)) || (rc = dalloc(ctx, &c.nsteps, T)) ||
         (rc = dalloc(ctx, &c.home, T)) || (rc = dalloc(ctx, &c.stepcap, T)) ||
@@ -607,7 +657,8 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     if (r.compact_every > 0) {
       CompactBufs& b = ctx->spare[m];
       const size_t csz = (size_t)T * N * n_pad * 2;
-      if ((rc = dalloc(ctx, &b.x, T)) || (rc = dalloc(ctx, &b.v, T)) || (rc = dalloc(ctx, &b.F, T)) ||
+      if ((rc = dalloc(ctx, &b.x, (size_t)T * nd)) || (rc = dalloc(ctx, &b.v, (size_t)T * nd)) ||
+          (rc = dalloc(ctx, &b.F, (size_t)T * nd)) ||
           (rc = dalloc(ctx, &b.status, T)) || (rc = dalloc(ctx, &b.gtraj, T)) ||
           (rc = dalloc(ctx, &b.home, T)) || (rc = dalloc(ctx, &b.nsteps, T)) ||
           (rc = dalloc(ctx, &b.stepcap, T)) ||
@@ -698,6 +749,8 @@ int iesh_query_sizes(const iesh_ctx* ctx, iesh_sizes* out) {
   out->n_models = (int32_t)ctx->cls.size();
   out->n_max = ctx->n_max;
   out->N_max = ctx->N_max;
+  out->n_dof = ctx->ndof;
+  out->reserved = 0;
   out->device_bytes = (int64_t)ctx->device_bytes;
   return IESH_OK;
 }
@@ -735,8 +788,8 @@ int iesh_set_state(iesh_ctx* ctx, const double* x, const double* v, const double
   std::vector<int32_t> hocc;
   const size_t csize = (size_t)T * ctx->n_max * ctx->N_max * 2;
   if (mem_kind == IESH_MEM_DEVICE) {
-    hx = host_copy_d(ctx, x, T, mem_kind);
-    hv = host_copy_d(ctx, v, T, mem_kind);
+    hx = host_copy_d(ctx, x, (size_t)T * ctx->ndof, mem_kind);
+    hv = host_copy_d(ctx, v, (size_t)T * ctx->ndof, mem_kind);
     hC = host_copy_d(ctx, C, csize, mem_kind);
     hocc.resize((size_t)T * ctx->N_max);
     HIPTRY(ctx, hipMemcpy(hocc.data(), occ, hocc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -775,16 +828,17 @@ int iesh_get_state(iesh_ctx* ctx, double* x, double* v, double* C, int32_t* occ,
   HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
   const int T = ctx->run.n_traj;
   const size_t csize = (size_t)T * ctx->n_max * ctx->N_max * 2;
-  std::vector<double> hx(T), hv(T), hC(C ? csize : 0, 0.0);
+  const int nd = ctx->ndof;
+  std::vector<double> hx((size_t)T * nd), hv((size_t)T * nd), hC(C ? csize : 0, 0.0);
   std::vector<int32_t> hocc(occ ? (size_t)T * ctx->N_max : 0, -1);
   for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
     ClassDev& c = ctx->cls[ci];
     const int Tc = c.n_traj, N = c.md.N, n = c.md.n, n_pad = c.md.n_pad;
     if (!Tc) continue;
-    std::vector<double> cx(Tc), cv(Tc);
+    std::vector<double> cx((size_t)Tc * nd), cv((size_t)Tc * nd);
     std::vector<int32_t> cocc((size_t)Tc * N);
-    HIPTRY(ctx, hipMemcpy(cx.data(), c.x, Tc * sizeof(double), hipMemcpyDeviceToHost));
-    HIPTRY(ctx, hipMemcpy(cv.data(), c.v, Tc * sizeof(double), hipMemcpyDeviceToHost));
+    HIPTRY(ctx, hipMemcpy(cx.data(), c.x, cx.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPTRY(ctx, hipMemcpy(cv.data(), c.v, cv.size() * sizeof(double), hipMemcpyDeviceToHost));
     HIPTRY(ctx, hipMemcpy(cocc.data(), c.occ, cocc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     std::vector<double> cC;
     if (C) {
@@ -800,8 +854,10 @@ int iesh_get_state(iesh_ctx* ctx, double* x, double* v, double* C, int32_t* occ,
     for (int sl = 0; sl < Tc; ++sl) {
       const int t = ctx->members[ci][ctx->slot_home[ci][sl]];
       const int tl = sl;
-      hx[t] = cx[tl];
-      hv[t] = cv[tl];
+      for (int nu = 0; nu < nd; ++nu) {
+        hx[(size_t)t * nd + nu] = cx[(size_t)tl * nd + nu];
+        hv[(size_t)t * nd + nu] = cv[(size_t)tl * nd + nu];
+      }
       if (occ)
         for (int r = 0; r < N; ++r) hocc[(size_t)t * ctx->N_max + r] = cocc[(size_t)tl * N + r];
       if (C) {
@@ -825,8 +881,8 @@ int iesh_get_state(iesh_ctx* ctx, double* x, double* v, double* C, int32_t* occ,
     return IESH_OK;
   };
   int rc;
-  if ((rc = put(x, hx.data(), T * sizeof(double)))) return rc;
-  if ((rc = put(v, hv.data(), T * sizeof(double)))) return rc;
+  if ((rc = put(x, hx.data(), hx.size() * sizeof(double)))) return rc;
+  if ((rc = put(v, hv.data(), hv.size() * sizeof(double)))) return rc;
   if ((rc = put(C, hC.data(), hC.size() * sizeof(double)))) return rc;
   if ((rc = put(occ, hocc.data(), hocc.size() * sizeof(int32_t)))) return rc;
   return IESH_OK;

@@ -13,16 +13,24 @@ namespace iesh {
 
 constexpr int kMaxStates = IESH_MAX_STATES;  // n = M + 1
 constexpr int kMaxElec = IESH_MAX_ELEC;      // N
+constexpr int kMaxDof = IESH_MAX_DOF;        // nuclear coordinates
 constexpr int kMaxCheb = 64;                 // Chebyshev terms per step
 constexpr int kChebStride = 2 * kMaxCheb + 8;
-constexpr int kGeoStride = 8;
+constexpr int kGeoStride = 32;
 
 // Status bits that stop a trajectory.
 constexpr int kFreezeMask = IESH_TRAJ_EXITED | IESH_TRAJ_NONCONV | IESH_TRAJ_NONFINITE |
                             IESH_TRAJ_STEPCAP;
 
-// Per-trajectory scalars at the most recent geometry (layout of geo[]).
-enum GeoSlot { GEO_H = 0, GEO_DH = 1, GEO_RHO = 2, GEO_U0 = 3, GEO_DU0 = 4 };
+// Per-trajectory scalars at the most recent geometry (layout of geo[]):
+// h, dh/dx, rho = f'/f, U0, dU0/dx of coordinate 0; v.grad h and
+// v.grad f / f with the current velocity (several coordinates); then the
+// gradients of every coordinate (dh/dR_nu, rho_nu, dU0/dR_nu) at GEO_DHV,
+// GEO_RHOV, GEO_DU0V.
+enum GeoSlot {
+  GEO_H = 0, GEO_DH = 1, GEO_RHO = 2, GEO_U0 = 3, GEO_DU0 = 4, GEO_VDH = 5, GEO_VRHO = 6,
+  GEO_DHV = 8, GEO_RHOV = 8 + kMaxDof, GEO_DU0V = 8 + 2 * kMaxDof
+};
 
 // Chebyshev parameter block (layout of cheb[]): [0] centre c, [1] 1/radius,
 // [2] number of terms K (as double), [3] radius*dt, then K complex
@@ -36,10 +44,12 @@ struct ModelDev {
   int n;       // M + 1
   int n_pad;   // n rounded up to 16
   int N;       // electrons
-  int pad0;
+  int ndof;    // nuclear coordinates
   double mass;
   double Gamma;
   double p[16];
+  double mass_dof[kMaxDof];  // mass of each coordinate (mass_dof[0] = mass for one coordinate)
+  double dofp[kMaxDof][6];   // IESH_MODEL_MULTI_DOF: D, a, r, g, c, s per coordinate
 };
 
 // Device state of one bath-size class.
@@ -53,9 +63,9 @@ struct ClassDev {
   // device arrays (class-local trajectory index t)
   double* eps = nullptr;    // [M]
   double* vbar = nullptr;   // [M]  sqrt(Gamma w / 2 pi)
-  double* x = nullptr;      // [T]
-  double* v = nullptr;      // [T]
-  double* F = nullptr;      // [T]
+  double* x = nullptr;      // [T][ndof]
+  double* v = nullptr;      // [T][ndof]
+  double* F = nullptr;      // [T][ndof]
   int32_t* occ = nullptr;   // [T][N]
   int32_t* status = nullptr;  // [T]
   int32_t* gtraj = nullptr;   // [T] global trajectory index
@@ -140,14 +150,42 @@ __host__ __device__ inline double philox_uniform(uint64_t seed, uint32_t traj, u
 }
 
 // -------------------------------------------------------------------------
-// Model scalars at x.  Couplings factor as V_k(x) = Vbar_k f(x); rho = f'/f.
+// Model scalars at the geometry x[0 .. ndof).  Couplings factor as
+// V_k(x) = Vbar_k f(x); rho = f'/f.  dU0, dh and rho are those of coordinate
+// 0; model_grad gives them for any coordinate.
 struct ModelAt {
   double U0, dU0, h, dh, f, rho;
 };
 
-__host__ __device__ inline ModelAt model_at(const ModelDev& md, double x) {
+// dh/dR_nu, rho_nu = (df/dR_nu)/f and dU0/dR_nu of the multi-coordinate model.
+__host__ __device__ inline void multi_dof_grad(const ModelDev& md, const double* x, int nu,
+                                               double& dh, double& rho, double& dU0) {
+  const double D = md.dofp[nu][0], a = md.dofp[nu][1], r = md.dofp[nu][2];
+  const double g = md.dofp[nu][3], cc = md.dofp[nu][4], s = md.dofp[nu][5];
+  const double e = exp(-a * (x[nu] - r));
+  dU0 = 2.0 * D * a * e * (1.0 - e);
+  dh = g;
+  rho = -(x[nu] - cc) / (2.0 * s * s);
+}
+
+__host__ __device__ inline ModelAt model_at(const ModelDev& md, const double* xv) {
   ModelAt r;
-  if (md.kind == IESH_MODEL_HARMONIC) {
+  const double x = xv[0];
+  if (md.kind == IESH_MODEL_MULTI_DOF) {
+    double U0 = 0.0, hs = md.p[0] + md.p[1], lf = 0.0;
+    for (int nu = 0; nu < md.ndof; ++nu) {
+      const double D = md.dofp[nu][0], a = md.dofp[nu][1], rr = md.dofp[nu][2];
+      const double g = md.dofp[nu][3], cc = md.dofp[nu][4], s = md.dofp[nu][5];
+      const double e = exp(-a * (xv[nu] - rr));
+      U0 += D * (1.0 - e) * (1.0 - e);
+      hs += g * (xv[nu] - rr);
+      lf -= (xv[nu] - cc) * (xv[nu] - cc) / (4.0 * s * s);
+    }
+    r.U0 = U0;
+    r.h = hs;
+    r.f = exp(lf);
+    multi_dof_grad(md, xv, 0, r.dh, r.rho, r.dU0);
+  } else if (md.kind == IESH_MODEL_HARMONIC) {
     const double omega = md.p[0], g = md.p[1], dG = md.p[2], eps_d = md.p[3];
     const double k = md.mass * omega * omega;
     r.U0 = 0.5 * k * x * x;

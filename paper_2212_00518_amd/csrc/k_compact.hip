@@ -54,11 +54,14 @@ __global__ __launch_bounds__(kMoveThreads) void k_compact_move(ClassDev c, const
                                                                 CT* Cs) {
   const int t = blockIdx.x;
   const int d = dst[t];
-  const int N = c.md.N, n_pad = c.md.n_pad;
+  const int N = c.md.N, n_pad = c.md.n_pad, nd = c.md.ndof;
+  if (threadIdx.x < nd) {
+    const int nu = threadIdx.x;
+    b.x[(size_t)d * nd + nu] = c.x[(size_t)t * nd + nu];
+    b.v[(size_t)d * nd + nu] = c.v[(size_t)t * nd + nu];
+    b.F[(size_t)d * nd + nu] = c.F[(size_t)t * nd + nu];
+  }
   if (threadIdx.x == 0) {
-    b.x[d] = c.x[t];
-    b.v[d] = c.v[t];
-    b.F[d] = c.F[t];
     b.status[d] = c.status[t];
     b.gtraj[d] = c.gtraj[t];
     b.home[d] = c.home[t];

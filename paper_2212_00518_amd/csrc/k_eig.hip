@@ -43,6 +43,7 @@ struct EigLds {
   int count;
   double sc[16];             // scalars
   double J[kMaxCheb];        // Bessel values J_0..J_K of the propagator
+  double nuc[4][kMaxDof];    // half-step velocity, new, frozen-propagator geometry, force
 };
 
 // 1/d from the hardware reciprocal estimate and two Newton steps
@@ -190,8 +191,8 @@ __device__ int secular_root(int j, int M, const double* e, const double* V2, dou
 
 // Solve the arrowhead problem of geometry x; fills lam, tau, org, q0 in LDS
 // (entries n..n_pad-1 of lam/q0 set to 0).  Returns model scalars.
-__device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict__ vbar, double x,
-                                   EigLds& L) {
+__device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict__ vbar,
+                                   const double* x, EigLds& L) {
   const int M = md.M, n = md.n, tid = threadIdx.x;
   const ModelAt ma = model_at(md, x);
   for (int k = tid; k < M; k += kEigThreads) {
@@ -341,6 +342,58 @@ __device__ double hf_force(const ModelDev& md, const ModelAt& ma, const int32_t*
   return F;
 }
 
+// Hellmann-Feynman force on every coordinate of the multi-coordinate model at
+// geometry x (held in L): F_nu = -dU0/dR_nu - sum_occ q0^2 (dh_nu + 2 rho_nu (lambda - h)),
+// into F[0 .. ndof) (every thread gets the same values).
+__device__ void hf_force_multi(const ModelDev& md, const ModelAt& ma, const double* x,
+                               const int32_t* occ, EigLds& L, double* F) {
+  const int tid = threadIdx.x;
+  double p1 = 0.0, p2 = 0.0;
+  if (tid < md.N) {
+    const int a = occ[tid];
+    const double q2 = L.q0[a] * L.q0[a];
+    p1 = q2;
+    p2 = q2 * (L.lam[a] - ma.h);
+  }
+  L.red[tid] = p1;
+  L.red2[tid] = p2;
+  __syncthreads();
+  for (int s = kEigThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      L.red[tid] += L.red[tid + s];
+      L.red2[tid] += L.red2[tid + s];
+    }
+    __syncthreads();
+  }
+  const double s1 = L.red[0], s2 = L.red2[0];
+  __syncthreads();
+  for (int nu = 0; nu < md.ndof; ++nu) {
+    double dh, rho, dU0;
+    multi_dof_grad(md, x, nu, dh, rho, dU0);
+    F[nu] = -dU0 - dh * s1 - 2.0 * rho * s2;
+  }
+}
+
+// Per-coordinate gradients into geo (coordinate 0 also in the scalar slots)
+// and, with several coordinates, v.grad h and v.grad f / f for the velocity v.
+__device__ void write_geo_grads(double* geo, const ModelDev& md, const ModelAt& ma, const double* x,
+                                const double* v) {
+  if (md.kind == IESH_MODEL_MULTI_DOF) {
+    double vdh = 0.0, vrho = 0.0;
+    for (int nu = 0; nu < md.ndof; ++nu) {
+      multi_dof_grad(md, x, nu, geo[GEO_DHV + nu], geo[GEO_RHOV + nu], geo[GEO_DU0V + nu]);
+      vdh += v[nu] * geo[GEO_DHV + nu];
+      vrho += v[nu] * geo[GEO_RHOV + nu];
+    }
+    geo[GEO_VDH] = vdh;
+    geo[GEO_VRHO] = vrho;
+  } else {
+    geo[GEO_DHV] = ma.dh;
+    geo[GEO_RHOV] = ma.rho;
+    geo[GEO_DU0V] = ma.dU0;
+  }
+}
+
 __device__ void load_bath(const ClassDev& c, EigLds& L) {
   for (int k = threadIdx.x; k < c.md.M; k += kEigThreads) L.e[k] = c.eps[k];
   if (threadIdx.x == 0) {
@@ -363,32 +416,48 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt,
   if (c.status[t] & kFreezeMask) return;
   const ModelDev& md = c.md;
   load_bath(c, L);
-  if (tid == 0) {
+  const int nd = md.ndof;
+  if (tid < nd) {
+    const int nu = tid;
     double vh, xn, x;
     if (c.path) {
-      // prescribed path: v over the step from the two end points
+      // prescribed path (one coordinate): v over the step from the two end points
       const double* pp = c.path + (size_t)c.gtraj[t] * c.path_len + c.path_n;
       x = pp[0];
       xn = pp[1];
       vh = (xn - x) / dt;
     } else {
-      x = c.x[t];
-      const double v = c.v[t], F = c.F[t];
-      vh = v + 0.5 * dt * F / md.mass;
+      x = c.x[(size_t)t * nd + nu];
+      const double v = c.v[(size_t)t * nd + nu], F = c.F[(size_t)t * nd + nu];
+      vh = v + 0.5 * dt * F / md.mass_dof[nu];
       xn = x + dt * vh;
     }
-    L.sc[0] = vh;
-    L.sc[1] = xn;
-    L.sc[2] = (sub >= 0) ? x + ((sub + 0.5) / nsub) * (xn - x) : 0.5 * (x + xn);
+    L.nuc[0][nu] = vh;
+    L.nuc[1][nu] = xn;
+    L.nuc[2][nu] = (sub >= 0) ? x + ((sub + 0.5) / nsub) * (xn - x) : 0.5 * (x + xn);
   }
   __syncthreads();
-  const double vh = L.sc[0], xn = L.sc[1], xm = L.sc[2];
+  const double vh = L.nuc[0][0];
   const double dte = (sub >= 0) ? dt / nsub : dt;  // electronic step of this propagator
 
   const int n = md.n, n_pad = md.n_pad, RT = n_pad / 16;
   if (sub != -2) {
   // ---- midpoint geometry: couplings for the propagator
-  const ModelAt mm = solve_arrowhead(md, c.vbar, xm, L);
+  ModelAt mm = solve_arrowhead(md, c.vbar, L.nuc[2], L);
+  double vfac = vh;
+  if (nd > 1) {
+    // v . D over the coordinates: the gradients enter through v.grad h and v.grad f / f
+    double dhe = 0.0, rhoe = 0.0;
+    for (int nu = 0; nu < nd; ++nu) {
+      double dh, rho, dU0;
+      multi_dof_grad(md, L.nuc[2], nu, dh, rho, dU0);
+      dhe += L.nuc[0][nu] * dh;
+      rhoe += L.nuc[0][nu] * rho;
+    }
+    mm.dh = dhe;
+    mm.rho = rhoe;
+    vfac = 1.0;
+  }
   double* Bt = c.Bt + (size_t)t * n_pad * n_pad;
   float* Bt32 = c.Bt32 ? c.Bt32 + (size_t)t * n_pad * n_pad : nullptr;
   double lo_part = 1e300, hi_part = -1e300;
@@ -397,7 +466,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt,
     double rsum = 0.0;
     for (int k = 0; k < n_pad; ++k) {
       double val = 0.0;
-      if (j < n && k < n && j != k) val = vD_elem(L, mm, vh, j, k);
+      if (j < n && k < n && j != k) val = vD_elem(L, mm, vfac, j, k);
       rsum += fabs(val);
       const size_t off = ((size_t)((k >> 2) * RT + rt) << 6) + lane_lo + ((k & 3) << 4);
       if (precision == IESH_FP64)
@@ -467,22 +536,33 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt,
   }
 
   // ---- end-point geometry: energies, amplitudes, forces
-  const ModelAt mn = solve_arrowhead(md, c.vbar, xn, L);
+  const ModelAt mn = solve_arrowhead(md, c.vbar, L.nuc[1], L);
   for (int j = tid; j < n_pad; j += kEigThreads) {
     c.lam[(size_t)t * n_pad + j] = L.lam[j];
     c.q0[(size_t)t * n_pad + j] = L.q0[j];
   }
-  const double Fn = hf_force(md, mn, c.occ + (size_t)t * md.N, L);
+  double Fv[kMaxDof];
+  if (nd == 1)
+    Fv[0] = hf_force(md, mn, c.occ + (size_t)t * md.N, L);
+  else
+    hf_force_multi(md, mn, L.nuc[1], c.occ + (size_t)t * md.N, L, Fv);
   if (tid == 0) {
-    write_model_geo(c.geo + (size_t)t * kGeoStride, mn);
-    const double vn = vh + 0.5 * dt * Fn / md.mass;
-    c.x[t] = xn;
-    c.v[t] = vn;
-    c.F[t] = Fn;
+    double* geo = c.geo + (size_t)t * kGeoStride;
+    write_model_geo(geo, mn);
     int st = c.status[t];
+    double vnv[kMaxDof];
+    for (int nu = 0; nu < nd; ++nu) {
+      const double xn = L.nuc[1][nu];
+      const double vn = L.nuc[0][nu] + 0.5 * dt * Fv[nu] / md.mass_dof[nu];
+      vnv[nu] = vn;
+      c.x[(size_t)t * nd + nu] = xn;
+      c.v[(size_t)t * nd + nu] = vn;
+      c.F[(size_t)t * nd + nu] = Fv[nu];
+      if (!isfinite(xn) || !isfinite(vn)) st |= IESH_TRAJ_NONFINITE;
+    }
+    write_geo_grads(geo, md, mn, L.nuc[1], vnv);
     if (L.fail & 1) st |= IESH_TRAJ_NONCONV;
     if (L.fail & 2) st |= IESH_TRAJ_NONCONV;
-    if (!isfinite(xn) || !isfinite(vn)) st |= IESH_TRAJ_NONFINITE;
     c.status[t] = st;
   }
 }
@@ -495,17 +575,26 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_query(ClassDev c, int t0, i
   const int tid = threadIdx.x;
   const ModelDev& md = c.md;
   load_bath(c, L);
-  const double x = c.x[t];
-  const ModelAt ma = solve_arrowhead(md, c.vbar, x, L);
+  const int nd = md.ndof;
+  if (tid < nd) L.nuc[1][tid] = c.x[(size_t)t * nd + tid];
+  __syncthreads();
+  const ModelAt ma = solve_arrowhead(md, c.vbar, L.nuc[1], L);
   for (int j = tid; j < md.n_pad; j += kEigThreads) {
     c.lam[(size_t)t * md.n_pad + j] = L.lam[j];
     c.q0[(size_t)t * md.n_pad + j] = L.q0[j];
   }
-  if (tid == 0) write_model_geo(c.geo + (size_t)t * kGeoStride, ma);
+  if (tid == 0) {
+    write_model_geo(c.geo + (size_t)t * kGeoStride, ma);
+    write_geo_grads(c.geo + (size_t)t * kGeoStride, md, ma, L.nuc[1], c.v + (size_t)t * nd);
+  }
   if (mode == 1) {
-    const double F = hf_force(md, ma, c.occ + (size_t)t * md.N, L);
+    double Fv[kMaxDof];
+    if (nd == 1)
+      Fv[0] = hf_force(md, ma, c.occ + (size_t)t * md.N, L);
+    else
+      hf_force_multi(md, ma, L.nuc[1], c.occ + (size_t)t * md.N, L, Fv);
     if (tid == 0) {
-      c.F[t] = F;
+      for (int nu = 0; nu < nd; ++nu) c.F[(size_t)t * nd + nu] = Fv[nu];
       if (L.fail) c.status[t] |= IESH_TRAJ_NONCONV;
     }
   }
@@ -519,7 +608,9 @@ __global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double
   const ModelDev& md = c.md;
   const int n = md.n, N = md.N;
   load_bath(c, L);
-  const ModelAt ma = solve_arrowhead(md, c.vbar, c.x[t], L);
+  if (tid < md.ndof) L.nuc[1][tid] = c.x[(size_t)t * md.ndof + tid];
+  __syncthreads();
+  const ModelAt ma = solve_arrowhead(md, c.vbar, L.nuc[1], L);
   int32_t* occ = c.occ + (size_t)t * N;
   __shared__ int chosen[kMaxStates];
   bool done = false;
@@ -590,10 +681,16 @@ __global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double
     c.lam[(size_t)t * md.n_pad + j] = L.lam[j];
     c.q0[(size_t)t * md.n_pad + j] = L.q0[j];
   }
-  const double F = hf_force(md, ma, occ, L);
+  const int nd = md.ndof;
+  double Fv[kMaxDof];
+  if (nd == 1)
+    Fv[0] = hf_force(md, ma, occ, L);
+  else
+    hf_force_multi(md, ma, L.nuc[1], occ, L, Fv);
   if (tid == 0) {
     write_model_geo(c.geo + (size_t)t * kGeoStride, ma);
-    c.F[t] = F;
+    write_geo_grads(c.geo + (size_t)t * kGeoStride, md, ma, L.nuc[1], c.v + (size_t)t * nd);
+    for (int nu = 0; nu < nd; ++nu) c.F[(size_t)t * nd + nu] = Fv[nu];
     c.status[t] = L.fail ? IESH_TRAJ_NONCONV : 0;
   }
 }
@@ -702,7 +799,7 @@ __global__ __launch_bounds__(kEigThreads) void k_adj_explicit(ClassDev c, const 
   const double w = weights[c.gtraj[t]];
   const double x = c.path[(size_t)c.gtraj[t] * c.path_len + s];
   load_bath(c, L);
-  const ModelAt ma = solve_arrowhead(md, c.vbar, x, L);
+  const ModelAt ma = solve_arrowhead(md, c.vbar, &x, L);
   const double* C = Cs + (size_t)t * N * n_pad * 2;
   double* G = Gh + (size_t)t * N * n_pad * 2;
   // z_o = sum_a q0_a C[o][a], one wave per orbital
@@ -783,7 +880,7 @@ __global__ __launch_bounds__(kEigThreads) void k_adj_mid(ClassDev c, const doubl
   const double xm = 0.5 * (x0 + x1), v = (x1 - x0) / dt;
   const double r = 1.0 / c.cheb[(size_t)t * kChebStride + CHEB_INVR];
   load_bath(c, L);
-  const ModelAt ma = solve_arrowhead(md, c.vbar, xm, L);
+  const ModelAt ma = solve_arrowhead(md, c.vbar, &xm, L);
   const double hp = ma.dh;
   const double* P = imphi + (size_t)t * n_pad * n_pad;
   const double sc = 2.0 * v / r;  // Dbar = sc * Im Phi

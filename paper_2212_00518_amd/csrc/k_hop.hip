@@ -58,6 +58,9 @@ struct HopLds {
   int sc_occ_changed;
   double sc_xi;
   double sc_v;
+  double sc_ekin;
+  double dofv[kMaxDof];  // velocity per coordinate (thread 0 of the hop)
+  double dofd[kMaxDof];  // rescaling direction per coordinate
 };
 
 __device__ inline double2 cmul(double2 a, double2 b) {
@@ -353,8 +356,14 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
   __syncthreads();
 
   const double* geo = c.geo + (size_t)t * kGeoStride;
-  const double h = geo[GEO_H], dh = geo[GEO_DH], rho = geo[GEO_RHO];
-  const double v = c.v[t];
+  const int nd = md.ndof;
+  const double h = geo[GEO_H];
+  // v.D from the coordinate gradients: with several coordinates the sums
+  // v.grad h and v.grad f / f replace (dh, rho) and the velocity factor is 1
+  const bool multi = nd > 1;
+  const double dh = multi ? geo[GEO_VDH] : geo[GEO_DH];
+  const double rho = multi ? geo[GEO_VRHO] : geo[GEO_RHO];
+  const double v = multi ? 1.0 : c.v[(size_t)t * nd];
 
   // ---- hop probabilities, formed on the fly from the owned elements of Y
   auto gval = [&](int rb, int cj) -> double {
@@ -446,7 +455,8 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
   __syncthreads();
 
   if (tid == 0) {
-    double vnew = v;
+    double* vv = L.dofv;
+    for (int nu = 0; nu < nd; ++nu) vv[nu] = c.v[(size_t)t * nd + nu];
     int32_t st = c.status[t];
     if (singular) st |= IESH_TRAJ_SINGULAR_S;
     int occ_changed = 0;
@@ -473,19 +483,27 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
         margin = 0.0;
       }
       const int a = L.occ[rsel];
-      // rescale along d = <b|d/dx a>
-      const double gba = L.q0[bsel] * L.q0[a] * (dh + rho * ((L.lam[bsel] - h) + (L.lam[a] - h)));
-      const double d = gba / (L.lam[a] - L.lam[bsel]);
+      // rescale along d_nu = <b|d/dR_nu a> (momentum change gamma d)
+      double* dv = L.dofd;
+      for (int nu = 0; nu < nd; ++nu) {
+        const double dhn = geo[GEO_DHV + nu], rhon = geo[GEO_RHOV + nu];
+        const double gba = L.q0[bsel] * L.q0[a] * (dhn + rhon * ((L.lam[bsel] - h) + (L.lam[a] - h)));
+        dv[nu] = gba / (L.lam[a] - L.lam[bsel]);
+      }
       const double dE = L.lam[bsel] - L.lam[a];
-      const double A2 = d * d / (2.0 * md.mass);
-      const double B1 = v * d;
+      double A2 = dv[0] * dv[0] / (2.0 * md.mass_dof[0]);
+      double B1 = vv[0] * dv[0];
+      for (int nu = 1; nu < nd; ++nu) {
+        A2 += dv[nu] * dv[nu] / (2.0 * md.mass_dof[nu]);
+        B1 += vv[nu] * dv[nu];
+      }
       const double disc = B1 * B1 - 4.0 * A2 * dE;
       int accepted = 0;
       if (A2 != 0.0 && disc >= 0.0) {
         const double root = sqrt(disc);
         const double q = B1 + (B1 >= 0.0 ? root : -root);
         const double gamma = (q != 0.0) ? 2.0 * dE / q : 0.0;
-        vnew = v - gamma * d / md.mass;
+        for (int nu = 0; nu < nd; ++nu) vv[nu] = vv[nu] - gamma * dv[nu] / md.mass_dof[nu];
         accepted = 1;
         // occupation update, keep sorted
         int* o = L.occ;
@@ -519,24 +537,31 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
     }
     // force refresh for the (possibly new) occupations
     if (occ_changed) {
-      double s = 0.0;
-      for (int r = 0; r < N; ++r) {
-        const int a = L.occ[r];
-        s += L.q0[a] * L.q0[a] * (dh + 2.0 * rho * (L.lam[a] - h));
+      for (int nu = 0; nu < nd; ++nu) {
+        const double dhn = geo[GEO_DHV + nu], rhon = geo[GEO_RHOV + nu];
+        double s = 0.0;
+        for (int r = 0; r < N; ++r) {
+          const int a = L.occ[r];
+          s += L.q0[a] * L.q0[a] * (dhn + 2.0 * rhon * (L.lam[a] - h));
+        }
+        c.F[(size_t)t * nd + nu] = -geo[GEO_DU0V + nu] - s;
+        c.v[(size_t)t * nd + nu] = vv[nu];
       }
-      c.F[t] = -geo[GEO_DU0] - s;
-      c.v[t] = vnew;
     }
     const int64_t ns = c.nsteps[t] + 1;
     c.nsteps[t] = ns;
-    const double x = c.x[t];
+    const double x = c.x[(size_t)t * nd];
     if (exit_enabled && x > exit_x) st |= IESH_TRAJ_EXITED;
     if ((max_steps > 0 && ns >= max_steps) || (c.stepcap[t] > 0 && ns >= c.stepcap[t]))
       st |= IESH_TRAJ_STEPCAP;
-    if (!isfinite(vnew)) st |= IESH_TRAJ_NONFINITE;
+    double ekin = 0.0;
+    for (int nu = 0; nu < nd; ++nu) {
+      if (!isfinite(vv[nu])) st |= IESH_TRAJ_NONFINITE;
+      ekin += 0.5 * md.mass_dof[nu] * vv[nu] * vv[nu];
+    }
     c.status[t] = st;
     L.sc_occ_changed = occ_changed;
-    L.sc_v = vnew;
+    L.sc_ekin = ekin;
   }
   __syncthreads();
   if (L.sc_occ_changed) {
@@ -553,8 +578,7 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
         elam += L.lam[a];
         pdw += L.zz[r];
       }
-      const double vv = L.sc_v;
-      const double ekin = 0.5 * md.mass * vv * vv;
+      const double ekin = L.sc_ekin;
       const double epot = geo[GEO_U0] + elam;
       double* o = c.obs + ((size_t)rec * c.n_traj + c.home[t]) * IESH_N_OBS;
       o[IESH_OBS_PD_SURF] = pds;
@@ -669,8 +693,12 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
   __syncthreads();
   // sum_b ||C_U[b]|| sum_r |v D[b][s_r]|
   const double* geo = c.geo + (size_t)t * kGeoStride;
-  const double h = geo[GEO_H], dh = geo[GEO_DH], rho = geo[GEO_RHO];
-  const double v = c.v[t];
+  const int nd = md.ndof;
+  const double h = geo[GEO_H];
+  const bool multi = nd > 1;
+  const double dh = multi ? geo[GEO_VDH] : geo[GEO_DH];
+  const double rho = multi ? geo[GEO_VRHO] : geo[GEO_RHO];
+  const double v = multi ? 1.0 : c.v[(size_t)t * nd];
   double bnd_part = 0.0;
   for (int b = tid; b < n; b += kFltThreads) {
     if (L.occflag[b]) continue;
@@ -733,10 +761,15 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
     int32_t st = c.status[t];
     const int64_t ns = c.nsteps[t] + 1;
     c.nsteps[t] = ns;
-    if (exit_enabled && c.x[t] > exit_x) st |= IESH_TRAJ_EXITED;
+    if (exit_enabled && c.x[(size_t)t * nd] > exit_x) st |= IESH_TRAJ_EXITED;
     if ((max_steps > 0 && ns >= max_steps) || (c.stepcap[t] > 0 && ns >= c.stepcap[t]))
       st |= IESH_TRAJ_STEPCAP;
-    if (!isfinite(v)) st |= IESH_TRAJ_NONFINITE;
+    double ekin = 0.0;
+    for (int nu = 0; nu < nd; ++nu) {
+      const double vn = c.v[(size_t)t * nd + nu];
+      if (!isfinite(vn)) st |= IESH_TRAJ_NONFINITE;
+      ekin += 0.5 * md.mass_dof[nu] * vn * vn;
+    }
     c.status[t] = st;
     if (record) {
       const int64_t rel = step - cnt->run_step0 + 1;
@@ -749,7 +782,6 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
           elam += L.lam[a];
           pdw += L.zz[r];
         }
-        const double ekin = 0.5 * md.mass * v * v;
         const double epot = geo[GEO_U0] + elam;
         double* o = c.obs + ((size_t)rec * c.n_traj + c.home[t]) * IESH_N_OBS;
         o[IESH_OBS_PD_SURF] = pds;

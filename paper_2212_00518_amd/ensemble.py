@@ -42,18 +42,22 @@ def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M
 
 
 def pack_states(states, n_max: int, N_max: int):
-    """states: list of (x, v, C (n x N complex), s (N,)) -> ABI arrays."""
+    """states: list of (x, v, C (n x N complex), s (N,)) -> ABI arrays; x and
+    v hold one value per coordinate (shape (T,) for one, (T, n_dof) else)."""
     T = len(states)
-    x = np.zeros(T)
-    v = np.zeros(T)
+    nd = np.atleast_1d(states[0][0]).size
+    x = np.zeros((T, nd))
+    v = np.zeros((T, nd))
     Cc = np.zeros((T, n_max * N_max), dtype=np.complex128)
     occ = np.zeros((T, N_max), dtype=np.int32)
     for t, (xx, vv, CC, ss) in enumerate(states):
         n, N = CC.shape
-        x[t] = float(np.atleast_1d(xx)[0])
-        v[t] = float(np.atleast_1d(vv)[0])
+        x[t] = np.atleast_1d(xx).astype(np.float64)
+        v[t] = np.atleast_1d(vv).astype(np.float64)
         Cc[t, : n * N] = np.ascontiguousarray(CC.T).reshape(-1)
         occ[t, :N] = np.asarray(ss, dtype=np.int32)
+    if nd == 1:
+        x, v = x[:, 0], v[:, 0]
     return x, v, Cc, occ
 
 

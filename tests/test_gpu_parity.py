@@ -560,3 +560,79 @@ def test_one_substep_is_the_plain_step():
         ens.close()
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------ several coordinates
+def _multi_states(m, N, T, seed, v_scale=2e-3):
+    rs = np.random.default_rng(seed)
+    R0 = m.r
+    out = []
+    for t in range(T):
+        C = random_orbitals(m.n, N, seed=seed * 100 + t)
+        s = np.sort(rs.choice(m.n, N, replace=False))
+        out.append(dyn.State(R0 + rs.normal(0.0, 0.2, size=m.n_dof),
+                             rs.normal(0.0, v_scale, size=m.n_dof) * np.sqrt(2000.0 / m.mass), C, s))
+    return out
+
+
+def test_multi_coordinate_energies_and_hop_probabilities():
+    cfg = make_cfg("c5", M=30, N=15)
+    m = models.from_config(cfg, M=30)
+    T = 6
+    states = _multi_states(m, 15, T, seed=3)
+    ens = ensemble(cfg, T)
+    assert ens.n_dof == 6
+    upload(ens, states)
+    lam, q0 = ens.adiabatic()
+    g = ens.hop_probs()
+    x, v, _, _ = ens.get_state()
+    for t in range(T):
+        assert np.array_equal(x[t], states[t].x) and np.array_equal(v[t], states[t].v)
+        lr, Q = el.eig(m.H(states[t].x))
+        assert np.max(np.abs(lam[t, :m.n] - lr)) <= 1e-10 * np.max(np.abs(lr))
+        assert np.max(np.abs(q0[t, :m.n] - Q[0])) <= 1e-10
+        gr = dyn.hop_probs(m, states[t], cfg["dt"])
+        gg = g[t].reshape(ens.N_max, ens.n_max)[:15, :m.n]
+        assert np.max(np.abs(gg - gr)) <= 1e-10 * max(np.max(gr), 1e-300), t
+    ens.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_multi_coordinate_steps_match_the_oracle(precision, tol):
+    """Six coordinates, 40 graph-replayed steps from random orbitals (hops
+    likely): per-coordinate positions and velocities, orbitals, occupations
+    and hop events equal the oracle's, trajectories with a near-tie left out."""
+    from paper_2212_00518_amd import unpack_C
+    cfg = make_cfg("c5", M=24, N=12)
+    m = models.from_config(cfg, M=24)
+    T = 8
+    # mixed: fewer, slower steps (hop attempts whose margin is within the FP32
+    # tolerance of a boundary are left out, and random orbitals give many)
+    steps, vs = (40, 4e-3) if precision == "fp64" else (10, 1e-3)
+    states = _multi_states(m, 12, T, seed=9, v_scale=vs)
+    ens = ensemble(cfg, T, precision=precision)
+    upload(ens, states)
+    ens.run(steps)
+    x, v, Cf, occ = ens.get_state()
+    evs, _ = ens.events()
+    n_max, N_max = ens.n_max, ens.N_max
+    ens.close()
+    compared, hops = 0, 0
+    for t in range(T):
+        ref, ref_ev, _ = dyn.run(m, states[t], cfg["dt"], steps, cfg["seed"], t)
+        if any(e["margin"] < 1e3 * tol * max(e["g_total"], 1e-300) for e in ref_ev):
+            continue
+        mine = [e for e in evs if e["traj"] == t]
+        assert [(e["step"], e["a"], e["b"], e["accepted"]) for e in mine] == \
+               [(e["step"], e["a"], e["b"], e["accepted"]) for e in ref_ev], t
+        hops += sum(e["accepted"] for e in ref_ev)
+        assert np.max(np.abs(x[t] - ref.x)) <= tol * max(1.0, np.max(np.abs(ref.x))), t
+        assert np.max(np.abs(v[t] - ref.v)) <= tol * max(1e-3, np.max(np.abs(ref.v))), t
+        Cg = unpack_C(Cf, t, m.n, 12, n_max, N_max)
+        assert np.max(np.abs(Cg - ref.C)) <= 10 * tol, t
+        assert list(occ[t, :12]) == list(ref.s), t
+        compared += 1
+    print("compared", compared, "accepted hops", hops, flush=True)
+    assert compared >= (T - 2 if precision == "fp64" else T // 2)
+    if precision == "fp64":
+        assert hops >= 2

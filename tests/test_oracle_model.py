@@ -210,3 +210,51 @@ def test_wigner_sample_has_the_quantum_corrected_widths():
     assert abs(np.var(x) / var_x - 1.0) < 0.01
     assert abs(np.var(v) / var_v - 1.0) < 0.01
     assert abs(np.mean(x) - x0) < 4.0 * np.sqrt(var_x / n)
+
+
+def test_multi_coordinate_model_derivatives_and_forces():
+    """The six-coordinate model: dU0, dh and dV against central differences
+    of U0, h and V in every coordinate, and the Hellmann-Feynman force of an
+    occupied set against central differences of E_pot."""
+    from workloads import get_config
+    cfg = get_config("c5")
+    m = models.from_config(cfg, M=12)
+    assert m.n_dof == 6
+    rs = np.random.default_rng(3)
+    for _ in range(3):
+        R = np.array(cfg["model"]["dof"])[:, 3] + rs.normal(0.0, 0.3, size=6)
+        hs = 1e-5
+        s = np.arange(6)
+        F = el.forces(m, R, s)
+        for nu in range(6):
+            e = np.zeros(6)
+            e[nu] = hs
+            fd_u0 = (m.U0(R + e) - m.U0(R - e)) / (2 * hs)
+            fd_h = (m.h(R + e) - m.h(R - e)) / (2 * hs)
+            fd_v = (m.V(R + e) - m.V(R - e)) / (2 * hs)
+            assert abs(m.dU0(R)[nu] - fd_u0) < 1e-8 * max(1.0, abs(fd_u0))
+            assert abs(m.dh(R)[nu] - fd_h) < 1e-9
+            assert np.max(np.abs(m.dV(R)[:, nu] - fd_v)) < 1e-9
+            fd_e = (el.potential_energy(m, R + e, s) - el.potential_energy(m, R - e, s)) / (2 * hs)
+            assert abs(F[nu] + fd_e) < 1e-7 * max(1.0, abs(fd_e)), (nu, F[nu], fd_e)
+
+
+def test_vector_rescaling_conserves_energy_along_the_coupling():
+    """Several coordinates: the rescaled velocity changes the momentum along
+    d only (p' - p parallel to d) and lowers the kinetic energy by exactly dE;
+    an unaffordable dE is frustrated (v unchanged)."""
+    rs = np.random.default_rng(6)
+    m = np.array([2000.0, 2000.0, 4000.0, 4000.0, 8000.0, 8000.0])
+    for _ in range(20):
+        v = rs.normal(0.0, 2e-3, size=6)
+        d = rs.normal(0.0, 1.0, size=6)
+        ke = 0.5 * np.sum(m * v * v)
+        dE = rs.uniform(-0.5, 0.9) * ke
+        v2, ok = el.rescale(v, m, d, dE)
+        dp = m * (v2 - v)
+        if ok:
+            assert abs(0.5 * np.sum(m * v2 * v2) - (ke - dE)) < 1e-12 * ke
+            cross = dp - d * (dp @ d) / (d @ d)
+            assert np.max(np.abs(cross)) < 1e-12 * max(np.max(np.abs(dp)), 1e-30)
+        else:
+            assert np.array_equal(v2, v)

@@ -95,6 +95,22 @@ CONFIGS = {
         n_elec=50, kT=300.0 * KB_HARTREE_PER_K, x_threshold=angstrom(5.0),
         n_traj=8192, n_steps=2000, dt=5.0, seed=0,
     ),
+    # Several nuclear coordinates (six: one surface-normal Morse mode and
+    # five internal modes), the library's multi-coordinate model: Morse U0 per
+    # coordinate, impurity level linear in the displacements, Gaussian
+    # hybridisation Gamma(R); one band of 256 states, half filling, mixed path.
+    "c5": dict(
+        name="six coordinates, Morse U0, Gaussian Gamma(R), M=256 N=128, 8192 trajectories, dt=20",
+        model=dict(kind="multi_dof", Gamma=0.01, Delta=0.005, eps_d=0.0,
+                   dof=[[2000.0, 0.10, 1.0, 3.0, -0.004, 3.0, 1.5],
+                        [2000.0, 0.15, 1.2, 2.0, 0.002, 2.0, 2.0],
+                        [4000.0, 0.08, 0.8, 0.0, 0.001, 0.0, 2.5],
+                        [4000.0, 0.08, 0.8, 0.0, -0.001, 0.0, 2.5],
+                        [8000.0, 0.05, 0.6, 0.0, 0.0005, 0.0, 3.0],
+                        [8000.0, 0.05, 0.6, 0.0, -0.0005, 0.0, 3.0]]),
+        bath=dict(kind="trapezoid", M=256, W=0.1),
+        n_elec=128, kT=9.5e-4, n_traj=8192, n_steps=1000, dt=20.0, seed=0,
+    ),
     # Adjoint workload: fixed nuclear paths.
     "c4": dict(
         name="adjoint, harmonic M=100 N=50, 1024 fixed paths, 2000 steps, dt=20",

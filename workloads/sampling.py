@@ -43,6 +43,20 @@ def wigner_harmonic(n_traj: int, mass: float, omega: float, x_centre: float, kT:
     return x, v
 
 
+def boltzmann_coordinates(n_traj: int, masses, omegas, centres, kT: float, seed: int):
+    """Classical Boltzmann sample of independent harmonic coordinates (one
+    per column): R_nu ~ N(c_nu, kT / (m_nu w_nu^2)), v_nu ~ N(0, kT / m_nu).
+    Positions are drawn first (all trajectories, coordinate-major per
+    trajectory), then velocities."""
+    rng = np.random.default_rng(seed)
+    m = np.asarray(masses, dtype=np.float64)
+    w = np.asarray(omegas, dtype=np.float64)
+    c = np.asarray(centres, dtype=np.float64)
+    x = c[None, :] + rng.normal(size=(n_traj, len(m))) * np.sqrt(kT / (m * w * w))[None, :]
+    v = rng.normal(size=(n_traj, len(m))) * np.sqrt(kT / m)[None, :]
+    return x, v
+
+
 def scattering_initial(n_traj: int, mass: float, x_start: float,
                        e_range: tuple, seed: int):
     """Incoming scattering trajectories: x = x_start, moving toward the
