@@ -63,6 +63,23 @@ def discretise(kind: str, M: int, W: float, eps_f: float = 0.0, centre: float = 
     raise ValueError(kind)
 
 
+def two_leads(eps, w):
+    """Two leads on one grid, each coupled with half the hybridisation
+    (Gamma/2 each, so the total width stays Gamma): every level appears once
+    per lead with half its weight.  Levels are listed in ascending energy,
+    lead 0 before lead 1 at equal energy.  Returns (eps, w, lead)."""
+    eps = np.asarray(eps, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    M = len(eps)
+    e2, w2, lead = [], [], []
+    for k in range(M):
+        for l in (0, 1):
+            e2.append(eps[k])
+            w2.append(0.5 * w[k])
+            lead.append(l)
+    return np.array(e2), np.array(w2), np.array(lead, dtype=np.int32)
+
+
 def couplings(Gamma: float, w):
     """V_k = sqrt(Gamma w_k / (2 pi)) (Eq. hybridization with Appendix A)."""
     return np.sqrt(Gamma * np.asarray(w) / (2.0 * np.pi))

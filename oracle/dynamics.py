@@ -134,7 +134,33 @@ def observables(model, st: State):
     )
 
 
-def fermi_occupations(lam, n_elec, kT, seed, traj, max_attempts=4096):
+def occupation_probabilities(lam, mu, kT, q0=None, w0=None, bias=0.0):
+    """Occupation probability of each orbital at chemical potential mu.
+
+    Without a bias, the Fermi function f(lambda - mu).  With a bias V between
+    two leads (Sec. III.C models a bias as a shift of the chemical
+    potential; the paper does not say how two leads at different chemical
+    potentials fill the orbitals).  Reading: lead 0 sits at mu + V/2, lead 1
+    at mu - V/2 and the impurity at mu, and an orbital's probability is the
+    mix of the three Fermi functions weighted by its squared components on
+    the impurity (q0^2), on lead 0 (w0) and on lead 1 (1 - q0^2 - w0)."""
+    if bias == 0.0:
+        return fermi(lam, mu, kT)
+    q2 = np.asarray(q0) ** 2
+    w0 = np.asarray(w0)
+    w1 = 1.0 - q2 - w0
+    return (q2 * fermi(lam, mu, kT) + w0 * fermi(lam, mu + 0.5 * bias, kT)
+            + w1 * fermi(lam, mu - 0.5 * bias, kT))
+
+
+def lead_weights(Q, lead):
+    """Squared weight of every orbital (column of Q) on the levels of lead 0."""
+    rows = 1 + np.flatnonzero(np.asarray(lead) == 0)
+    return np.sum(Q[rows, :] ** 2, axis=0)
+
+
+def fermi_occupations(lam, n_elec, kT, seed, traj, max_attempts=4096, q0=None, w0=None,
+                      bias=0.0):
     """Occupied set s for the initial state: N electrons at temperature kT
     (Sec. III.C initialises electrons from a Fermi-Dirac distribution; the
     paper does not fix the electron-number constraint).  Reading: the
@@ -142,23 +168,27 @@ def fermi_occupations(lam, n_elec, kT, seed, traj, max_attempts=4096):
     f_a = 1/(1 + exp((lambda_a - mu)/kT)); attempt t draws one uniform per
     level from stream 1 at counter t*n + a, occupies level a when u_a < f_a,
     and is accepted when exactly N levels are occupied.  kT = 0, or no
-    acceptance within max_attempts, gives the lowest N levels.
+    acceptance within max_attempts, gives the lowest N levels.  With a bias
+    (two leads) f_a is occupation_probabilities(...) with the orbitals'
+    impurity amplitudes q0 and lead-0 weights w0, and the bisection bracket
+    is widened by |bias|.
 
     Returns (s, attempts_used); attempts_used = 0 means the lowest-N rule.
     """
     n = len(lam)
     if kT <= 0.0:
         return np.arange(n_elec), 0
-    lo, hi = lam[0] - 50.0 * kT - 1.0, lam[-1] + 50.0 * kT + 1.0
+    lo = lam[0] - 50.0 * kT - 1.0 - abs(bias)
+    hi = lam[-1] + 50.0 * kT + 1.0 + abs(bias)
     for _ in range(200):
         mu = 0.5 * (lo + hi)
-        f = fermi(lam, mu, kT)
+        f = occupation_probabilities(lam, mu, kT, q0, w0, bias)
         if f.sum() > n_elec:
             hi = mu
         else:
             lo = mu
     mu = 0.5 * (lo + hi)
-    f = fermi(lam, mu, kT)
+    f = occupation_probabilities(lam, mu, kT, q0, w0, bias)
     for t in range(max_attempts):
         u = np.array([_rng.uniform(seed, traj, t * n + a, stream=1) for a in range(n)])
         occ = u < f
@@ -177,12 +207,17 @@ def fermi(e, mu, kT):
     return out
 
 
-def initial_state(model, x0, v0, n_elec, kT, seed, traj):
+def initial_state(model, x0, v0, n_elec, kT, seed, traj, bias=0.0):
     """Initial state: occupations from fermi_occupations at x0 and orbitals
     that are the occupied adiabatic unit vectors (Sec. III.C: the
-    coefficients match the discrete populations)."""
-    lam, _ = el.eig(model.H(np.atleast_1d(x0)))
-    s, _ = fermi_occupations(lam, n_elec, kT, seed, traj)
+    coefficients match the discrete populations).  A bias needs a two-lead
+    model (model.lead)."""
+    lam, Q = el.eig(model.H(np.atleast_1d(x0)))
+    if bias != 0.0:
+        s, _ = fermi_occupations(lam, n_elec, kT, seed, traj, q0=Q[0], w0=lead_weights(Q, model.lead),
+                                 bias=bias)
+    else:
+        s, _ = fermi_occupations(lam, n_elec, kT, seed, traj)
     C = np.zeros((model.n, n_elec), dtype=np.complex128)
     for i, a in enumerate(s):
         C[a, i] = 1.0

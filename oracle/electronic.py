@@ -50,11 +50,17 @@ def eig(H):
 
 
 def coupling_matrices(lam, Q, dH_list):
-    """G^(nu) = Q^T dH^(nu) Q and D^(nu)[j, k] = G[j, k] / (lambda_k - lambda_j)."""
+    """G^(nu) = Q^T dH^(nu) Q and D^(nu)[j, k] = G[j, k] / (lambda_k - lambda_j).
+
+    Reading: two states of equal energy (to rounding, 1e-12 of the largest
+    |lambda|) get D = 0.  The paper's couplings assume distinct energies;
+    equal energies arise only for repeated bath levels (two leads on one
+    grid), whose extra eigenstates have no impurity part and a fixed
+    direction, so that their coupling to every state vanishes."""
     Gs, Ds = [], []
     n = len(lam)
     diff = lam[None, :] - lam[:, None]          # [j, k] -> lambda_k - lambda_j
-    off = ~np.eye(n, dtype=bool)
+    off = ~np.eye(n, dtype=bool) & (np.abs(diff) > 1e-12 * np.max(np.abs(lam)))
     for dH in dH_list:
         G = Q.T @ dH @ Q
         D = np.zeros_like(G)

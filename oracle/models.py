@@ -21,6 +21,7 @@ from . import bath as _bath
 
 class Model:
     n_dof = 1
+    lead = None  # per bath level 0 or 1 for two leads (else None)
 
     def __init__(self, eps, w, Gamma, mass):
         self.eps = np.asarray(eps, dtype=np.float64)
@@ -209,15 +210,25 @@ def from_config(cfg: dict, M: int | None = None):
     # or only the Gauss-Legendre split does ("split")
     mu = bcfg.get("mu", 0.0)
     centre = mu if bcfg.get("placement", "shift") == "shift" else 0.0
-    eps, w = _bath.discretise(bcfg["kind"], M, bcfg["W"], eps_f=mu, centre=centre)
+    leads = bcfg.get("leads", 1)
+    if leads == 2:
+        # M levels in all: one grid of M/2 levels shared by the two leads
+        eps, w = _bath.discretise(bcfg["kind"], M // 2, bcfg["W"], eps_f=mu, centre=centre)
+        eps, w, lead = _bath.two_leads(eps, w)
+    else:
+        eps, w = _bath.discretise(bcfg["kind"], M, bcfg["W"], eps_f=mu, centre=centre)
+        lead = None
     if mcfg["kind"] == "harmonic":
-        return Harmonic(eps, w, mcfg["Gamma"], mcfg["mass"], mcfg["omega"], mcfg["g"],
-                        mcfg["dG"], mcfg.get("eps_d", 0.0))
-    if mcfg["kind"] == "multi_dof":
-        return MultiDof(eps, w, mcfg["Gamma"], mcfg["dof"], mcfg["Delta"], mcfg.get("eps_d", 0.0))
-    if mcfg["kind"] == "morse_tanh":
-        return MorseTanh(eps, w, mcfg["Gamma"], mcfg["mass"], mcfg["De"], mcfg["x0"],
-                         mcfg["a"], mcfg["D1"], mcfg["D2"], mcfg["ap"], mcfg["Vinf"],
-                         mcfg["q"], mcfg["atil"], mcfg["xtil"], mcfg["c"],
-                         mcfg.get("eps_d", 0.0))
-    raise ValueError(mcfg["kind"])
+        m = Harmonic(eps, w, mcfg["Gamma"], mcfg["mass"], mcfg["omega"], mcfg["g"],
+                     mcfg["dG"], mcfg.get("eps_d", 0.0))
+    elif mcfg["kind"] == "multi_dof":
+        m = MultiDof(eps, w, mcfg["Gamma"], mcfg["dof"], mcfg["Delta"], mcfg.get("eps_d", 0.0))
+    elif mcfg["kind"] == "morse_tanh":
+        m = MorseTanh(eps, w, mcfg["Gamma"], mcfg["mass"], mcfg["De"], mcfg["x0"],
+                      mcfg["a"], mcfg["D1"], mcfg["D2"], mcfg["ap"], mcfg["Vinf"],
+                      mcfg["q"], mcfg["atil"], mcfg["xtil"], mcfg["c"],
+                      mcfg.get("eps_d", 0.0))
+    else:
+        raise ValueError(mcfg["kind"])
+    m.lead = lead
+    return m
