@@ -115,13 +115,20 @@ typedef struct iesh_model_desc {
   int32_t n_dof;       /* nuclear coordinates: 1 (0 means 1) except for
                           IESH_MODEL_MULTI_DOF (1 .. IESH_MAX_DOF); all models
                           of a context have the same count                     */
-  const double* eps;   /* host, M bath energies, strictly ascending           */
+  const double* eps;   /* host, M bath energies, ascending; equal energies are
+                          allowed (two leads on one grid): a group of g equal
+                          levels has g - 1 eigenstates at that energy with no
+                          impurity component and no coupling to any other
+                          state, found by deflation (the secular function keeps
+                          one pole per distinct energy, with the summed weight) */
   const double* w;     /* host, M quadrature weights > 0 (V_k = sqrt(Gamma w_k / 2 pi)) */
   double mass;         /* nuclear mass > 0 (one coordinate)                   */
   double Gamma;        /* hybridisation Gamma > 0 (Eq. hybridization)          */
   double params[16];   /* model constants, layout per iesh_model_kind         */
   const double* dof;   /* host, IESH_MODEL_MULTI_DOF: n_dof rows of 7 doubles
                           (mass > 0, D, a, r, g, c, s > 0); else unused       */
+  const int32_t* lead; /* host, M labels 0 or 1 (two leads), or NULL (one lead).
+                          Only iesh_init_thermal with run.bias != 0 reads them */
 } iesh_model_desc;
 
 typedef struct iesh_run_desc {
@@ -144,6 +151,10 @@ typedef struct iesh_run_desc {
                             sub-stepping of the electronic integrator); hop
                             probabilities stay once per nuclear step            */
   int32_t reserved1;
+  double bias;           /* V: lead 0 at chemical potential mu + V/2, lead 1 at
+                            mu - V/2 for the initial occupations (Sec. III.C, an
+                            external bias as a shift of the chemical potential);
+                            != 0 needs kT > 0 and lead labels in every model    */
 } iesh_run_desc;
 
 #define IESH_MAX_STATES 336   /* n = M + 1 limit of this build                */
@@ -215,7 +226,11 @@ int iesh_get_state(iesh_ctx* ctx, double* x, double* v, double* C, int32_t* occ,
    potential by bisection, one uniform per level from Philox stream 1 at
    counter attempt*n + level, accept when exactly N levels are occupied;
    kT = 0 or 4096 failed attempts give the lowest N), orbitals = occupied
-   adiabatic unit vectors (Sec. III.C). */
+   adiabatic unit vectors (Sec. III.C).  With run.bias = V != 0 the
+   occupation probability of orbital j is
+     q0_j^2 f(lambda_j - mu) + w0_j f(lambda_j - mu - V/2) + w1_j f(lambda_j - mu + V/2),
+   w_l = the orbital's weight on the levels of lead l, and mu is found by the
+   same bisection. */
 int iesh_init_thermal(iesh_ctx* ctx, const double* x, const double* v);
 
 /* Global step counter (the hop-uniform counter of the next step). */

@@ -7,4 +7,5 @@ arguments (``_lib``) and builds ensembles from workload descriptions
 (``ensemble``).
 """
 from ._lib import Ensemble, IeshError, discretize, model_desc, lib  # noqa: F401
-from .ensemble import bath_grid, electrons_below, from_config, pack_states, unpack_C  # noqa: F401
+from .ensemble import (bath_grid, bath_levels, electrons_below, from_config, pack_states,  # noqa: F401
+                       unpack_C)

@@ -52,7 +52,8 @@ class ModelDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_bath", C.c_int32), ("n_elec", C.c_int32),
                 ("n_dof", C.c_int32), ("eps", C.POINTER(C.c_double)),
                 ("w", C.POINTER(C.c_double)), ("mass", C.c_double), ("Gamma", C.c_double),
-                ("params", C.c_double * 16), ("dof", C.POINTER(C.c_double))]
+                ("params", C.c_double * 16), ("dof", C.POINTER(C.c_double)),
+                ("lead", C.POINTER(C.c_int32))]
 
 
 class RunDesc(C.Structure):
@@ -60,7 +61,7 @@ class RunDesc(C.Structure):
                 ("kT", C.c_double), ("seed", C.c_uint64), ("lowdin_every", C.c_int32),
                 ("record_every", C.c_int32), ("exit_enabled", C.c_int32),
                 ("compact_every", C.c_int32), ("exit_x", C.c_double), ("max_steps", C.c_int64),
-                ("elec_substeps", C.c_int32), ("reserved1", C.c_int32)]
+                ("elec_substeps", C.c_int32), ("reserved1", C.c_int32), ("bias", C.c_double)]
 
 
 class Event(C.Structure):
@@ -144,11 +145,18 @@ def discretize(kind: str, M: int, W: float, eps_f: float = 0.0, centre: float = 
     return eps, w
 
 
-def model_desc(model: dict, eps, w, n_elec: int):
-    """Fill an iesh_model_desc; `model` follows workloads.configs."""
+def model_desc(model: dict, eps, w, n_elec: int, lead=None):
+    """Fill an iesh_model_desc; `model` follows workloads.configs; `lead`
+    (optional) labels each bath level 0 or 1 (two leads)."""
     eps = np.ascontiguousarray(eps, dtype=np.float64)
     w = np.ascontiguousarray(w, dtype=np.float64)
     d = ModelDesc()
+    lead_arr = None
+    if lead is not None:
+        lead_arr = np.ascontiguousarray(lead, dtype=np.int32)
+        if lead_arr.shape != eps.shape:
+            raise ValueError("lead: one label per bath level")
+        d.lead = lead_arr.ctypes.data_as(C.POINTER(C.c_int32))
     d.n_bath = len(eps)
     d.n_elec = int(n_elec)
     d.eps = eps.ctypes.data_as(C.POINTER(C.c_double))
@@ -178,7 +186,7 @@ def model_desc(model: dict, eps, w, n_elec: int):
         raise ValueError(model["kind"])
     d.params[:] = p
     # keep arrays alive with the descriptor
-    d._keep = (eps, w, dof)
+    d._keep = (eps, w, dof, lead_arr)
     return d
 
 
@@ -203,6 +211,7 @@ class Ensemble:
         r.max_steps = int(run.get("max_steps", 0))
         r.compact_every = int(run.get("compact_every", 0))
         r.elec_substeps = int(run.get("elec_substeps", 1))
+        r.bias = float(run.get("bias", 0.0))
         self.run_desc = r
         tm = None
         if traj_model is not None:

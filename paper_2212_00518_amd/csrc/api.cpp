@@ -193,6 +193,55 @@ int autotune_slabs(iesh_ctx* ctx, ClassDev& c) {
 
 int model_ndof(const iesh_model_desc& m) { return m.n_dof < 1 ? 1 : m.n_dof; }
 
+// Distinct bath energies of a model with their summed weights, the map from
+// adiabatic index to secular root or deflated state (ModelDev::expand), and
+// the lead-0 shares of two-lead models (ModelDev::lead0).
+struct BathPoles {
+  std::vector<double> eps, w, lead0;
+  std::vector<int32_t> expand;
+};
+
+BathPoles bath_poles(const iesh_model_desc& d) {
+  BathPoles b;
+  std::vector<int> size;        // levels per pole
+  std::vector<double> w0;       // lead-0 weight per pole
+  std::vector<int> n0;          // lead-0 levels per pole
+  for (int k = 0; k < d.n_bath; ++k) {
+    const bool l0 = d.lead && d.lead[k] == 0;
+    if (k == 0 || d.eps[k] != d.eps[k - 1]) {
+      b.eps.push_back(d.eps[k]);
+      b.w.push_back(0.0);
+      size.push_back(0);
+      w0.push_back(0.0);
+      n0.push_back(0);
+    }
+    b.w.back() += d.w[k];
+    size.back() += 1;
+    if (l0) {
+      w0.back() += d.w[k];
+      n0.back() += 1;
+    }
+  }
+  const int Mr = (int)b.eps.size();
+  // root 0, then per pole m its g_m - 1 deflated states and root m + 1
+  b.expand.push_back(0);
+  for (int m = 0; m < Mr; ++m) {
+    for (int q = 1; q < size[m]; ++q) b.expand.push_back(-(m + 1));
+    b.expand.push_back(m + 1);
+  }
+  if (d.lead) {
+    b.lead0.assign(2 * Mr, 0.0);
+    for (int m = 0; m < Mr; ++m) {
+      const double phi = w0[m] / b.w[m];
+      b.lead0[m] = phi;
+      // the deflated states of a pole carry the pole's levels minus the
+      // coupled combination; each gets the mean over them
+      b.lead0[Mr + m] = size[m] > 1 ? (n0[m] - phi) / (size[m] - 1) : 0.0;
+    }
+  }
+  return b;
+}
+
 int validate_model(const iesh_model_desc& m, std::string& why) {
   if (m.kind != IESH_MODEL_HARMONIC && m.kind != IESH_MODEL_MORSE_TANH &&
       m.kind != IESH_MODEL_MULTI_DOF) {
@@ -238,8 +287,12 @@ int validate_model(const iesh_model_desc& m, std::string& why) {
       why = "bath weights must be > 0 and energies finite";
       return 0;
     }
-    if (k && !(m.eps[k] > m.eps[k - 1])) {
-      why = "bath energies must be strictly ascending";
+    if (k && !(m.eps[k] >= m.eps[k - 1])) {
+      why = "bath energies must be ascending";
+      return 0;
+    }
+    if (m.lead && m.lead[k] != 0 && m.lead[k] != 1) {
+      why = "lead labels must be 0 or 1";
       return 0;
     }
   }
@@ -579,6 +632,15 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
   if (r.elec_substeps < 0 || r.elec_substeps > 64)
     return (fail(ctx, IESH_EINVAL, "elec_substeps out of range [0, 64]"), bail(IESH_EINVAL));
   if (ctx->run.elec_substeps == 0) ctx->run.elec_substeps = 1;
+  if (!std::isfinite(r.bias))
+    return (fail(ctx, IESH_EINVAL, "bias must be finite"), bail(IESH_EINVAL));
+  if (r.bias != 0.0) {
+    if (!(r.kT > 0.0))
+      return (fail(ctx, IESH_EINVAL, "a bias needs kT > 0"), bail(IESH_EINVAL));
+    for (int m = 0; m < n_models; ++m)
+      if (!models[m].lead)
+        return (fail(ctx, IESH_EINVAL, "a bias needs lead labels in every model"), bail(IESH_EINVAL));
+  }
   ctx->traj_class.assign(r.n_traj, 0);
   ctx->traj_local.assign(r.n_traj, 0);
   std::vector<int> count(n_models, 0);
@@ -605,6 +667,9 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     ClassDev& c = ctx->cls[m];
     c.md.kind = d.kind;
     c.md.M = d.n_bath;
+    c.md.M_red = d.n_bath;
+    c.md.expand = nullptr;
+    c.md.lead0 = nullptr;
     c.md.n = d.n_bath + 1;
     c.md.n_pad = round16(c.md.n);
     c.md.N = d.n_elec;
@@ -689,16 +754,31 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
       return (fail(ctx, IESH_EDEVICE, std::string("propagation LDS attribute: ") +
                                          hipGetErrorString(e)),
               bail(IESH_EDEVICE));
-    std::vector<double> vb(M);
-    for (int k = 0; k < M; ++k) vb[k] = std::sqrt(d.Gamma * d.w[k] / (2.0 * M_PI));
+    // poles of the secular function: groups of equal bath energies, each
+    // with the summed weight (V^2 of the coupled combination)
+    const BathPoles bp = bath_poles(d);
+    const int Mr = (int)bp.eps.size();
+    std::vector<double> vb(Mr);
+    for (int q = 0; q < Mr; ++q) vb[q] = std::sqrt(d.Gamma * bp.w[q] / (2.0 * M_PI));
     std::vector<int32_t> gt;
     for (int t = 0; t < r.n_traj; ++t)
       if (ctx->traj_class[t] == m) gt.push_back(t);
-    if (hipMemcpyAsync(c.eps, d.eps, M * sizeof(double), hipMemcpyHostToDevice, ctx->stream) ||
-        hipMemcpyAsync(c.vbar, vb.data(), M * sizeof(double), hipMemcpyHostToDevice, ctx->stream) ||
+    int32_t* expand = nullptr;
+    double* lead0 = nullptr;
+    if (Mr < M && (rc = dalloc(ctx, &expand, (size_t)c.md.n))) return bail(rc);
+    if (d.lead && (rc = dalloc(ctx, &lead0, (size_t)2 * Mr))) return bail(rc);
+    if (hipMemcpyAsync(c.eps, bp.eps.data(), Mr * sizeof(double), hipMemcpyHostToDevice, ctx->stream) ||
+        hipMemcpyAsync(c.vbar, vb.data(), Mr * sizeof(double), hipMemcpyHostToDevice, ctx->stream) ||
         hipMemcpyAsync(c.gtraj, gt.data(), T * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream) ||
+        (expand && hipMemcpyAsync(expand, bp.expand.data(), c.md.n * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, ctx->stream)) ||
+        (lead0 && hipMemcpyAsync(lead0, bp.lead0.data(), 2 * Mr * sizeof(double),
+                                 hipMemcpyHostToDevice, ctx->stream)) ||
         hipStreamSynchronize(ctx->stream))
       return (fail(ctx, IESH_EDEVICE, "upload of model data failed"), bail(IESH_EDEVICE));
+    c.md.M_red = Mr;
+    c.md.expand = expand;
+    c.md.lead0 = lead0;
   }
   if (hipStreamSynchronize(ctx->stream) != hipSuccess)
     return (fail(ctx, IESH_EDEVICE, "device synchronisation failed"), bail(IESH_EDEVICE));
@@ -815,7 +895,7 @@ int iesh_init_thermal(iesh_ctx* ctx, const double* x, const double* v) {
   if ((rc = upload_state(ctx, x, v, nullptr, nullptr))) return rc;
   if ((rc = reset_traj_words(ctx))) return rc;
   for (auto& c : ctx->cls)
-    if (c.n_traj) HIPTRY(ctx, launch_init_thermal(c, ctx->run.kT, ctx->run.seed, ctx->stream));
+    if (c.n_traj) HIPTRY(ctx, launch_init_thermal(c, ctx->run.kT, ctx->run.bias, ctx->run.seed, ctx->stream));
   HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
   return IESH_OK;
 }
@@ -1134,6 +1214,9 @@ int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int
   for (const auto& c : ctx->cls)
     if (c.n_traj && c.md.kind != IESH_MODEL_HARMONIC)
       return fail(ctx, IESH_ENOTSUP, "adjoint: harmonic (double-well) models only");
+  for (const auto& c : ctx->cls)
+    if (c.n_traj && c.md.M_red != c.md.M)
+      return fail(ctx, IESH_ENOTSUP, "adjoint: distinct bath energies only");
   const int T = ctx->run.n_traj;
   for (size_t q = 0; q < (size_t)T * (n_steps + 1); ++q)
     if (!std::isfinite(path[q])) return fail(ctx, IESH_EINVAL, "adjoint: non-finite path");
@@ -1166,7 +1249,7 @@ int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int
   HIPTRY(ctx, hipMemcpyAsync(&ctx->cnt->max_cheb, &zero, sizeof(zero), hipMemcpyHostToDevice,
                              ctx->stream));
   for (auto& c : ctx->cls)
-    if (c.n_traj) HIPTRY(ctx, launch_init_thermal(c, 0.0, ctx->run.seed, ctx->stream));
+    if (c.n_traj) HIPTRY(ctx, launch_init_thermal(c, 0.0, 0.0, ctx->run.seed, ctx->stream));
   for (int n = 0; n < n_steps; ++n) {
     for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
       const ClassDev& c = ctx->cls[ci];

@@ -41,6 +41,7 @@ enum ChebSlot { CHEB_C = 0, CHEB_INVR = 1, CHEB_K = 2, CHEB_RHO = 3, CHEB_COEF =
 struct ModelDev {
   int kind;
   int M;       // bath levels
+  int M_red;   // distinct bath energies (poles of the secular function); M without repeats
   int n;       // M + 1
   int n_pad;   // n rounded up to 16
   int N;       // electrons
@@ -50,6 +51,19 @@ struct ModelDev {
   double p[16];
   double mass_dof[kMaxDof];  // mass of each coordinate (mass_dof[0] = mass for one coordinate)
   double dofp[kMaxDof][6];   // IESH_MODEL_MULTI_DOF: D, a, r, g, c, s per coordinate
+  // Repeated bath energies (deflation): the levels of a group of g equal
+  // energies couple to the impurity only through one combination, which
+  // keeps a pole of the secular function with the summed weight; the g - 1
+  // orthogonal combinations are eigenstates at that energy with no impurity
+  // component.  expand[j] (j < n, nullptr without repeats) names adiabatic
+  // state j: r >= 0 is root r of the secular function over the M_red
+  // distinct poles, -(m + 1) a deflated state at pole m.  Deflated states lie
+  // between roots m and m + 1, so the energies stay ascending.
+  const int32_t* expand;
+  // Two leads (nullptr for one): lead0[m] is the share of pole m's squared
+  // coupling that belongs to lead 0, lead0[M_red + m] the lead-0 weight of
+  // each deflated state at pole m (their mean over the degenerate subspace).
+  const double* lead0;
 };
 
 // Device state of one bath-size class.
@@ -237,7 +251,8 @@ struct CompactBufs {
 hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s, int sub = -1,
                            int nsub = 1);
 hipError_t launch_eig_query(const ClassDev& c, int t0, int nt, hipStream_t s);
-hipError_t launch_init_thermal(const ClassDev& c, double kT, uint64_t seed, hipStream_t s);
+hipError_t launch_init_thermal(const ClassDev& c, double kT, double bias, uint64_t seed,
+                               hipStream_t s);
 hipError_t launch_forces(const ClassDev& c, hipStream_t s);
 hipError_t launch_prop(const ClassDev& c, int precision, hipStream_t s);
 hipError_t launch_prop_taps(const ClassDev& c, int mode, double* taps, int tap_k, hipStream_t s);

@@ -6,7 +6,8 @@
 // the roots of the secular function
 //     f(lambda) = lambda - h + sum_k V_k^2 / (eps_k - lambda),
 // one below eps_0, one between each pair of neighbouring bath levels and one
-// above eps_{M-1} (strict interlacing when every V_k != 0).  Each root is
+// above eps_{M-1} (strict interlacing when every V_k != 0 and the levels are
+// distinct; equal levels are deflated first, see ModelDev).  Each root is
 // found relative to its nearest pole, tau = lambda - eps_o, so that the
 // differences lambda_j - eps_k stay accurate for closely spaced levels; the
 // iteration fits a two-pole rational model to f and f' at the current point
@@ -48,8 +49,8 @@ struct EigLds {
 
 // 1/d from the hardware reciprocal estimate and two Newton steps
 // r <- r + r (1 - d r) (each squares the relative error), within a few ulp;
-// d != 0 at every call (poles are excluded from the root brackets, the bath
-// energies are distinct and the roots interlace them strictly).
+// d != 0 at every call (poles are excluded from the root brackets, the
+// secular poles are distinct and the roots interlace them strictly).
 __device__ inline double rcp_nr(double d) {
   double r = __builtin_amdgcn_rcp(d);
   double e = fma(-d, r, 1.0);
@@ -193,7 +194,9 @@ __device__ int secular_root(int j, int M, const double* e, const double* V2, dou
 // (entries n..n_pad-1 of lam/q0 set to 0).  Returns model scalars.
 __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict__ vbar,
                                    const double* x, EigLds& L) {
-  const int M = md.M, n = md.n, tid = threadIdx.x;
+  // the secular problem over the distinct bath energies (M = M_red poles,
+  // M + 1 roots); repeated energies are expanded into deflated states below
+  const int M = md.M_red, n = M + 1, tid = threadIdx.x;
   const ModelAt ma = model_at(md, x);
   for (int k = tid; k < M; k += kEigThreads) {
     const double V = vbar[k] * ma.f;
@@ -248,12 +251,48 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
         s += L.Vh2[k] * (id * id);
       }
       L.q0[j] = 1.0 / sqrt(s);
-    } else {
+    } else if (j >= md.n) {
       L.q0[j] = 0.0;
       L.lam[j] = 0.0;
     }
   }
   __syncthreads();
+  if (md.expand) {
+    // deflation: adiabatic state j is secular root r = expand[j] or, for
+    // expand[j] = -(m + 1), the eigenstate at pole m with no impurity part
+    constexpr int kPer = (kMaxStates + kEigThreads - 1) / kEigThreads;
+    double tq[kPer], tt[kPer];
+    int to[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int j = tid + i * kEigThreads;
+      tq[i] = 0.0;
+      tt[i] = 0.0;
+      to[i] = 0;
+      if (j < md.n) {
+        const int r = md.expand[j];
+        if (r >= 0) {
+          tq[i] = L.q0[r];
+          tt[i] = L.tau[r];
+          to[i] = L.org[r];
+        } else {
+          to[i] = -r - 1;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int j = tid + i * kEigThreads;
+      if (j < md.n) {
+        L.q0[j] = tq[i];
+        L.tau[j] = tt[i];
+        L.org[j] = to[i];
+        L.lam[j] = L.e[to[i]] + tt[i];
+      }
+    }
+    __syncthreads();
+  }
   return ma;
 }
 
@@ -262,10 +301,11 @@ __device__ inline double lam_diff(const EigLds& L, int k, int j) {
   return (L.e[L.org[k]] - L.e[L.org[j]]) + (L.tau[k] - L.tau[j]);
 }
 
-// v * D[j][k] for j != k < n.
+// v * D[j][k] for j != k < n (zero when either state has no impurity part:
+// deflated states of equal bath energies, possibly degenerate with each other).
 __device__ inline double vD_elem(const EigLds& L, const ModelAt& ma, double v, int j, int k) {
   const double g = L.q0[j] * L.q0[k] * (ma.dh + ma.rho * ((L.lam[j] - ma.h) + (L.lam[k] - ma.h)));
-  return v * g * rcp_nr(lam_diff(L, k, j));
+  return g == 0.0 ? 0.0 : v * g * rcp_nr(lam_diff(L, k, j));
 }
 
 // Bessel J_k(rho), k = 0..K, by Miller's downward recurrence normalised with
@@ -395,7 +435,7 @@ __device__ void write_geo_grads(double* geo, const ModelDev& md, const ModelAt& 
 }
 
 __device__ void load_bath(const ClassDev& c, EigLds& L) {
-  for (int k = threadIdx.x; k < c.md.M; k += kEigThreads) L.e[k] = c.eps[k];
+  for (int k = threadIdx.x; k < c.md.M_red; k += kEigThreads) L.e[k] = c.eps[k];
   if (threadIdx.x == 0) {
     L.fail = 0;
     L.count = 0;
@@ -600,8 +640,49 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_query(ClassDev c, int t0, i
   }
 }
 
+__device__ inline double fermi_fn(double e, double mu, double kT) {
+  const double z = (e - mu) / kT;
+  return (z > 0.0) ? exp(-z) / (1.0 + exp(-z)) : 1.0 / (1.0 + exp(z));
+}
+
+// Occupation probability of orbital a at chemical potential mu: one Fermi
+// function, or with a bias V the weighted mix of the impurity (mu) and the
+// two leads (mu +- V/2); w0 = lead-0 weight of the orbital.
+__device__ inline double occ_prob(const EigLds& L, int a, double mu, double kT, double bias) {
+  if (bias == 0.0) return fermi_fn(L.lam[a], mu, kT);
+  const double q2 = L.q0[a] * L.q0[a], w0 = L.V2[a], w1 = 1.0 - q2 - w0;
+  return q2 * fermi_fn(L.lam[a], mu, kT) + w0 * fermi_fn(L.lam[a], mu + 0.5 * bias, kT) +
+         w1 * fermi_fn(L.lam[a], mu - 0.5 * bias, kT);
+}
+
+// Lead-0 weight of every adiabatic state into L.V2 (free after the solve):
+// a secular root j has bath components Vh_m q0_j / (lambda_j - e_m) on the
+// coupled combination of pole m, of which the share lead0[m] lies on lead 0;
+// a deflated state at pole m takes lead0[M_red + m].
+__device__ void lead_weights(const ModelDev& md, EigLds& L) {
+  const int Mr = md.M_red;
+  for (int j = threadIdx.x; j < md.n; j += kEigThreads) {
+    const int r = md.expand ? md.expand[j] : j;
+    double w0;
+    if (r < 0) {
+      w0 = md.lead0[Mr - r - 1];
+    } else {
+      const double eo = L.e[L.org[j]], tj = L.tau[j];
+      double s = 0.0;
+      for (int m = 0; m < Mr; ++m) {
+        const double id = rcp_nr((L.e[m] - eo) - tj);
+        s += md.lead0[m] * L.Vh2[m] * (id * id);
+      }
+      w0 = L.q0[j] * L.q0[j] * s;
+    }
+    L.V2[j] = w0;
+  }
+  __syncthreads();
+}
+
 // Initial occupations at kT (fixed N) and unit-vector orbitals.
-__global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double kT, uint64_t seed) {
+__global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double kT, double bias,
+                                                              uint64_t seed) {
   __shared__ EigLds L;
   const int t = blockIdx.x;
   const int tid = threadIdx.x;
@@ -615,15 +696,14 @@ __global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double
   __shared__ int chosen[kMaxStates];
   bool done = false;
   if (kT > 0.0) {
+    if (bias != 0.0) lead_weights(md, L);
     // chemical potential by bisection on sum_a f_a = N
-    double lo = L.lam[0] - 50.0 * kT - 1.0, hi = L.lam[n - 1] + 50.0 * kT + 1.0;
+    double lo = L.lam[0] - 50.0 * kT - 1.0 - fabs(bias);
+    double hi = L.lam[n - 1] + 50.0 * kT + 1.0 + fabs(bias);
     for (int it = 0; it < 200; ++it) {
       const double mu = 0.5 * (lo + hi);
       double part = 0.0;
-      for (int a = tid; a < n; a += kEigThreads) {
-        const double z = (L.lam[a] - mu) / kT;
-        part += (z > 0.0) ? exp(-z) / (1.0 + exp(-z)) : 1.0 / (1.0 + exp(z));
-      }
+      for (int a = tid; a < n; a += kEigThreads) part += occ_prob(L, a, mu, kT, bias);
       L.red[tid] = part;
       __syncthreads();
       for (int s = kEigThreads / 2; s > 0; s >>= 1) {
@@ -641,8 +721,7 @@ __global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double
     for (int attempt = 0; attempt < 4096 && !done; ++attempt) {
       int cnt = 0;
       for (int a = tid; a < n; a += kEigThreads) {
-        const double z = (L.lam[a] - mu) / kT;
-        const double fa = (z > 0.0) ? exp(-z) / (1.0 + exp(-z)) : 1.0 / (1.0 + exp(z));
+        const double fa = occ_prob(L, a, mu, kT, bias);
         const double u = philox_uniform(seed, gt, (uint64_t)attempt * n + a, 1u);
         chosen[a] = (u < fa) ? 1 : 0;
         cnt += chosen[a];
@@ -936,8 +1015,9 @@ hipError_t launch_forces(const ClassDev& c, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_init_thermal(const ClassDev& c, double kT, uint64_t seed, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_thermal, dim3(c.n_traj), dim3(kEigThreads), 0, s, c, kT, seed);
+hipError_t launch_init_thermal(const ClassDev& c, double kT, double bias, uint64_t seed,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_init_thermal, dim3(c.n_traj), dim3(kEigThreads), 0, s, c, kT, bias, seed);
   return hipGetLastError();
 }
 

@@ -372,7 +372,9 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
     const int bb = L.uocc[bi];
     const int a = L.occ[L.invperm[j]];
     const double gab = L.q0[bb] * L.q0[a] * (dh + rho * ((L.lam[bb] - h) + (L.lam[a] - h)));
-    const double vD = v * gab / (L.lam[a] - L.lam[bb]);  // v <b|d/dx a>
+    // v <b|d/dx a>; zero for deflated states (no impurity part), which may
+    // share their energy with another deflated state
+    const double vD = gab == 0.0 ? 0.0 : v * gab / (L.lam[a] - L.lam[bb]);
     return fmax(-2.0 * dt * vD * y[rb][cj], 0.0);
   };
 
@@ -488,7 +490,7 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
       for (int nu = 0; nu < nd; ++nu) {
         const double dhn = geo[GEO_DHV + nu], rhon = geo[GEO_RHOV + nu];
         const double gba = L.q0[bsel] * L.q0[a] * (dhn + rhon * ((L.lam[bsel] - h) + (L.lam[a] - h)));
-        dv[nu] = gba / (L.lam[a] - L.lam[bsel]);
+        dv[nu] = gba == 0.0 ? 0.0 : gba / (L.lam[a] - L.lam[bsel]);
       }
       const double dE = L.lam[bsel] - L.lam[a];
       double A2 = dv[0] * dv[0] / (2.0 * md.mass_dof[0]);
@@ -706,7 +708,7 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
     for (int r = 0; r < N; ++r) {
       const int a = L.occ[r];
       const double gab = L.q0[b] * L.q0[a] * (dh + rho * ((L.lam[b] - h) + (L.lam[a] - h)));
-      s += fabs(v * gab / (L.lam[a] - L.lam[b]));
+      if (gab != 0.0) s += fabs(v * gab / (L.lam[a] - L.lam[b]));
     }
     bnd_part += L.rn[b] * s;
   }

@@ -18,6 +18,24 @@ def bath_grid(b: dict, M: int):
     return _lib.discretize(b["kind"], M, b["W"], eps_f=mu)
 
 
+def bath_levels(b: dict, M: int):
+    """Bath levels of a workload description: (eps, w, lead).  With
+    ``leads: 2`` the M levels are one grid of M/2 levels shared by two leads,
+    each coupled with half the hybridisation (half of every weight), listed
+    in ascending energy with lead 0 first at equal energy; lead is None for
+    one lead."""
+    if b.get("leads", 1) != 2:
+        eps, w = bath_grid(b, M)
+        return eps, w, None
+    if M % 2:
+        raise ValueError("two leads need an even number of bath levels")
+    e1, w1 = bath_grid(b, M // 2)
+    eps = np.repeat(e1, 2)
+    w = np.repeat(0.5 * w1, 2)
+    lead = np.tile(np.array([0, 1], dtype=np.int32), M // 2)
+    return eps, w, lead
+
+
 def electrons_below(eps, mu: float) -> int:
     """Electron count that fills the bath states below mu in the lowest
     configuration (Sec. II.B, chemical potential)."""
@@ -32,10 +50,11 @@ def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M
     b = cfg["bath"]
     M = M if M is not None else b["M"]
     N = n_elec if n_elec is not None else cfg.get("n_elec", M // 2)
-    eps, w = bath_grid(b, M)
-    desc = _lib.model_desc(cfg["model"], eps, w, N)
+    eps, w, lead = bath_levels(b, M)
+    desc = _lib.model_desc(cfg["model"], eps, w, N, lead)
     run = dict(n_traj=n_traj if n_traj is not None else cfg["n_traj"], precision=precision,
                dt=cfg["dt"], kT=cfg.get("kT", 0.0), seed=cfg.get("seed", 0),
+               bias=b.get("bias", 0.0),
                lowdin_every=lowdin_every if precision == "mixed" else 0,
                record_every=record_every, elec_substeps=elec_substeps)
     return _lib.Ensemble([desc], run, stream=stream)

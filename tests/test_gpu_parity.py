@@ -575,8 +575,10 @@ def _multi_states(m, N, T, seed, v_scale=2e-3):
     return out
 
 
-def test_multi_coordinate_energies_and_hop_probabilities():
+@pytest.mark.parametrize("leads", [1, 2])
+def test_multi_coordinate_energies_and_hop_probabilities(leads):
     cfg = make_cfg("c5", M=30, N=15)
+    cfg["bath"]["leads"] = leads
     m = models.from_config(cfg, M=30)
     T = 6
     states = _multi_states(m, 15, T, seed=3)
@@ -597,13 +599,16 @@ def test_multi_coordinate_energies_and_hop_probabilities():
     ens.close()
 
 
+@pytest.mark.parametrize("leads", [1, 2])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
-def test_multi_coordinate_steps_match_the_oracle(precision, tol):
+def test_multi_coordinate_steps_match_the_oracle(precision, tol, leads):
     """Six coordinates, 40 graph-replayed steps from random orbitals (hops
     likely): per-coordinate positions and velocities, orbitals, occupations
-    and hop events equal the oracle's, trajectories with a near-tie left out."""
+    and hop events equal the oracle's, trajectories with a near-tie left out.
+    Two leads: every bath energy appears twice (deflated eigen-solve)."""
     from paper_2212_00518_amd import unpack_C
     cfg = make_cfg("c5", M=24, N=12)
+    cfg["bath"]["leads"] = leads
     m = models.from_config(cfg, M=24)
     T = 8
     # mixed: fewer, slower steps (hop attempts whose margin is within the FP32
@@ -636,3 +641,146 @@ def test_multi_coordinate_steps_match_the_oracle(precision, tol):
     assert compared >= (T - 2 if precision == "fp64" else T // 2)
     if precision == "fp64":
         assert hops >= 2
+
+
+# ------------------------------------------------------- repeated bath energies
+def _repeated_bath(M_grid, g, W=0.1):
+    """g levels at each energy of a trapezoid grid of M_grid levels, each with
+    1/g of the weight (plain input data)."""
+    e = -0.5 * W + np.arange(M_grid) * (W / (M_grid - 1))
+    w = np.full(M_grid, W / M_grid)
+    return np.repeat(e, g), np.repeat(w / g, g)
+
+
+def _steps_vs_oracle(m, ens, states, steps, dt, seed, tol, N):
+    from paper_2212_00518_amd import unpack_C
+    upload(ens, states)
+    ens.run(steps)
+    x, v, Cf, occ = ens.get_state()
+    evs, _ = ens.events()
+    n_max, N_max = ens.n_max, ens.N_max
+    compared, hops = 0, 0
+    for t in range(len(states)):
+        ref, ref_ev, _ = dyn.run(m, states[t], dt, steps, seed, t)
+        if any(e["margin"] < 1e3 * tol * max(e["g_total"], 1e-300) for e in ref_ev):
+            continue
+        mine = [e for e in evs if e["traj"] == t]
+        assert [(e["step"], e["a"], e["b"], e["accepted"]) for e in mine] == \
+               [(e["step"], e["a"], e["b"], e["accepted"]) for e in ref_ev], t
+        hops += sum(e["accepted"] for e in ref_ev)
+        xt, vt = np.atleast_1d(x[t]), np.atleast_1d(v[t])
+        assert np.max(np.abs(xt - ref.x)) <= tol * max(1.0, np.max(np.abs(ref.x))), t
+        assert np.max(np.abs(vt - ref.v)) <= tol * max(1e-3, np.max(np.abs(ref.v))), t
+        Cg = unpack_C(Cf, t, m.n, N, n_max, N_max)
+        assert np.all(np.isfinite(Cg))
+        assert np.max(np.abs(Cg - ref.C)) <= 10 * tol, t
+        assert list(occ[t, :N]) == list(ref.s), t
+        compared += 1
+    return compared, hops
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_two_lead_double_well_steps_match_the_oracle(precision, tol):
+    """The double-well model on two leads of 20 levels (every energy twice):
+    graph-replayed steps from random orbitals against the oracle's dense
+    eigen-decomposition."""
+    cfg = make_cfg("c2", M=40, N=20)
+    cfg["bath"]["leads"] = 2
+    m = models.from_config(cfg, M=40)
+    T = 8
+    xs = np.linspace(-8.0, 24.0, T)
+    states = random_states(m, 20, T, seed=31, xs=xs, v_scale=1e-2)
+    ens = ensemble(cfg, T, precision=precision)
+    steps = 30 if precision == "fp64" else 8
+    compared, hops = _steps_vs_oracle(m, ens, states, steps, cfg["dt"], cfg["seed"], tol, 20)
+    ens.close()
+    print("compared", compared, "accepted hops", hops, flush=True)
+    assert compared >= (T - 2 if precision == "fp64" else T // 2)
+    if precision == "fp64":
+        assert hops >= 2
+
+
+@pytest.mark.parametrize("g", [2, 3])
+def test_repeated_levels_energies_amplitudes_and_hops(g):
+    """g equal levels per energy: the deflated eigen-solve gives every
+    eigenvalue of the dense matrix (g - 1 of them exactly at each bath
+    energy, with impurity amplitude 0), the hop probabilities of the oracle,
+    and steps equal to the oracle's (FP64)."""
+    from paper_2212_00518_amd import _lib
+    c1 = get_config("c1")
+    eps, w = _repeated_bath(12, g)
+    N = len(eps) // 2
+    mc = c1["model"]
+    m = models.Harmonic(eps, w, mc["Gamma"], mc["mass"], mc["omega"], mc["g"], mc["dG"],
+                        mc.get("eps_d", 0.0))
+    T = 6
+    desc = _lib.model_desc(mc, eps, w, N)
+    run = dict(n_traj=T, precision="fp64", dt=c1["dt"], kT=0.0, seed=3)
+    ens = _lib.Ensemble([desc], run)
+    states = random_states(m, N, T, seed=17, xs=np.linspace(-6.0, 26.0, T), v_scale=4e-3)
+    upload(ens, states)
+    lam, q0 = ens.adiabatic()
+    gp = ens.hop_probs()
+    for t in range(T):
+        lr, Q = el.eig(m.H(states[t].x))
+        assert np.max(np.abs(lam[t, :m.n] - lr)) <= 1e-10 * np.max(np.abs(lr))
+        assert np.max(np.abs(np.abs(q0[t, :m.n]) - np.abs(Q[0]))) <= 1e-10
+        at_grid = np.isin(lam[t, :m.n], eps)
+        assert at_grid.sum() == 12 * (g - 1)
+        assert np.all(q0[t, :m.n][at_grid] == 0.0)
+        gr = dyn.hop_probs(m, states[t], c1["dt"])
+        gg = gp[t].reshape(ens.N_max, ens.n_max)[:N, :m.n]
+        assert np.all(np.isfinite(gg))
+        assert np.max(np.abs(gg - gr)) <= 1e-10 * max(np.max(gr), 1e-300), t
+    compared, hops = _steps_vs_oracle(m, ens, states, 20, c1["dt"], 3, 1e-10, N)
+    ens.close()
+    print("g", g, "compared", compared, "accepted hops", hops, flush=True)
+    assert compared >= T - 2
+
+
+@pytest.mark.parametrize("bias", [0.0, 0.01, 0.02])
+def test_biased_initial_occupations_match_the_oracle(bias):
+    """Two leads at mu +- V/2: the occupations drawn by iesh_init_thermal equal
+    the oracle's (same Philox uniforms, FP64 probabilities)."""
+    from workloads.sampling import boltzmann_coordinates
+    cfg = make_cfg("c5", M=40, N=20)
+    cfg["bath"]["bias"] = bias
+    m = models.from_config(cfg, M=40)
+    T = 16
+    dof = np.array(cfg["model"]["dof"])
+    om = dof[:, 2] * np.sqrt(2.0 * dof[:, 1] / dof[:, 0])
+    x0, v0 = boltzmann_coordinates(T, dof[:, 0], om, dof[:, 3], cfg["kT"], seed=4)
+    ens = ensemble(cfg, T)
+    ens.init_thermal(x0, v0)
+    _, _, _, occ = ens.get_state()
+    ens.close()
+    for t in range(T):
+        ref = dyn.initial_state(m, x0[t], v0[t], 20, cfg["kT"], cfg["seed"], t, bias=bias)
+        assert list(occ[t, :20]) == list(ref.s), t
+
+
+def test_two_lead_error_paths():
+    from paper_2212_00518_amd import _lib
+    cfg = make_cfg("c2", M=20, N=10)
+    cfg["bath"]["bias"] = 0.01     # one lead: a bias has no leads to act on
+    with pytest.raises(_lib.IeshError):
+        ensemble(cfg, 2)
+    cfg = make_cfg("c5", M=20, N=10)
+    cfg["bath"]["bias"] = 0.01
+    cfg["kT"] = 0.0                # a bias needs a temperature
+    with pytest.raises(_lib.IeshError):
+        ensemble(cfg, 2)
+    c1 = get_config("c1")
+    eps, w = _repeated_bath(6, 2)
+    bad = np.tile(np.array([0, 2], dtype=np.int32), 6)
+    with pytest.raises(_lib.IeshError):
+        _lib.Ensemble([_lib.model_desc(c1["model"], eps, w, 6, bad)],
+                      dict(n_traj=2, precision="fp64", dt=c1["dt"]))
+    with pytest.raises(_lib.IeshError):  # not ascending
+        _lib.Ensemble([_lib.model_desc(c1["model"], eps[::-1].copy(), w, 6)],
+                      dict(n_traj=2, precision="fp64", dt=c1["dt"]))
+    ens = _lib.Ensemble([_lib.model_desc(c1["model"], eps, w, 6)],
+                        dict(n_traj=2, precision="fp64", dt=c1["dt"]))
+    with pytest.raises(_lib.IeshError, match="distinct"):
+        ens.adjoint_forward(np.zeros((2, 4)), 2)
+    ens.close()

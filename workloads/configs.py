@@ -99,8 +99,12 @@ CONFIGS = {
     # five internal modes), the library's multi-coordinate model: Morse U0 per
     # coordinate, impurity level linear in the displacements, Gaussian
     # hybridisation Gamma(R); one band of 256 states, half filling, mixed path.
+    # Biased two-lead junction: two leads of 128 levels on one trapezoid grid
+    # (each coupled with Gamma/2; equal energies, deflated), bias V between
+    # the leads' chemical potentials (V in {0, 0.01, 0.02}).
     "c5": dict(
-        name="six coordinates, Morse U0, Gaussian Gamma(R), M=256 N=128, 8192 trajectories, dt=20",
+        name="two leads 2x128 (n=257), bias V, six coordinates, Morse U0, Gaussian Gamma(R), "
+             "N=128, 8192 trajectories, dt=20",
         model=dict(kind="multi_dof", Gamma=0.01, Delta=0.005, eps_d=0.0,
                    dof=[[2000.0, 0.10, 1.0, 3.0, -0.004, 3.0, 1.5],
                         [2000.0, 0.15, 1.2, 2.0, 0.002, 2.0, 2.0],
@@ -108,8 +112,9 @@ CONFIGS = {
                         [4000.0, 0.08, 0.8, 0.0, -0.001, 0.0, 2.5],
                         [8000.0, 0.05, 0.6, 0.0, 0.0005, 0.0, 3.0],
                         [8000.0, 0.05, 0.6, 0.0, -0.0005, 0.0, 3.0]]),
-        bath=dict(kind="trapezoid", M=256, W=0.1),
-        n_elec=128, kT=9.5e-4, n_traj=8192, n_steps=1000, dt=20.0, seed=0,
+        bath=dict(kind="trapezoid", M=256, W=0.1, leads=2, bias=0.0),
+        n_elec=128, kT=9.5e-4, n_traj=8192, n_steps=10000, dt=20.0, seed=0,
+        biases=[0.0, 0.01, 0.02],
     ),
     # Adjoint workload: fixed nuclear paths.
     "c4": dict(
