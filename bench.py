@@ -136,17 +136,34 @@ def mixed_vs_fp64(cfg, T=64, steps=500):
     )
 
 
+def initial_sample(cfg, T, seed):
+    """Boltzmann positions and velocities of a workload: the harmonic U0 of
+    the double-well models, or every coordinate of the multi-coordinate model
+    about its Morse minimum r with the well's harmonic frequency
+    a sqrt(2 D / m)."""
+    import numpy as np
+    from workloads import boltzmann_harmonic
+    from workloads.sampling import boltzmann_coordinates
+    m = cfg["model"]
+    if m["kind"] == "multi_dof":
+        dof = np.array(m["dof"])
+        om = dof[:, 2] * np.sqrt(2.0 * dof[:, 1] / dof[:, 0])
+        return boltzmann_coordinates(T, dof[:, 0], om, dof[:, 3], cfg["kT"], seed=seed)
+    return boltzmann_harmonic(T, m["mass"], m["omega"], cfg["kT"], seed=seed,
+                              kT_factor=cfg.get("sample_kT_factor", 1.0))
+
+
 def _cpu_worker(args):
     cfg_name, t, steps = args
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
         from oracle import models, dynamics as dyn, rng
-        from workloads import get_config, boltzmann_harmonic
+        from workloads import get_config
         cfg = get_config(cfg_name)
         m = models.from_config(cfg)
-        x0, v0 = boltzmann_harmonic(t + 1, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"],
-                                    seed=cfg["seed"])
-        st = dyn.initial_state(m, x0[t], v0[t], cfg["n_elec"], cfg["kT"], cfg["seed"], t)
+        x0, v0 = initial_sample(cfg, t + 1, cfg["seed"])
+        st = dyn.initial_state(m, x0[t], v0[t], cfg["n_elec"], cfg["kT"], cfg["seed"], t,
+                               bias=cfg["bath"].get("bias", 0.0))
         F = None
         t0 = time.perf_counter()
         for k in range(steps):
@@ -339,6 +356,66 @@ def desorption_bench(a):
     print(json.dumps(line), flush=True)
 
 
+def two_lead_bench(a):
+    """Biased two-lead junction with six nuclear coordinates (two leads of 128
+    levels on one grid, n = 257, N = 128, 8192 trajectories, mixed path):
+    trajectory-steps/s at each bias V, with the roofline of the propagation
+    and the share of the eigen-solve kernel, which carries the six-coordinate
+    projection."""
+    from workloads import get_config
+
+    cfg = get_config("c5")
+    T = a.n_traj or cfg["n_traj"]
+    warmup = a.warmup if a.warmup != 1000 else 300
+    biases = cfg["biases"] if a.bias is None else [a.bias]
+    x0, v0 = initial_sample(cfg, T, cfg["seed"])
+    by_bias, total_steps, total_wall, flops, prop_ms = {}, 0, 0.0, 0.0, 0.0
+    for V in biases:
+        c = get_config("c5")
+        c["bath"]["bias"] = V
+        r = time_path(c, "mixed", T, a.steps, warmup, x0, v0, a.substeps)
+        print(f"# bias {V}: {r['value']:.1f} trajectory-steps/s, {r['ms_per_step']:.2f} ms/step, "
+              f"kernels {r['kernels_ms']} ms, propagation {r['prop_tflops']:.2f} TFLOP/s",
+              file=sys.stderr, flush=True)
+        total_steps += r["traj_steps"]
+        total_wall += r["wall_s"]
+        flops += r["prop_flops_per_launch"]
+        prop_ms += r["prop_ms_per_launch"]
+        by_bias[f"{V:g}"] = {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 3),
+                             "kernels_ms_per_launch": r["kernels_ms"],
+                             "kernels_time_share": r["kernels_share"],
+                             "mean_chebyshev_terms": round(r["mean_cheb_terms"], 3),
+                             "exact_hop_fraction": round(r["exact_hop_fraction"], 4),
+                             "frozen": r["frozen"]}
+    achieved = flops / (prop_ms * 1e-3) / 1e12 if prop_ms > 0 else 0.0
+    n, N = cfg["bath"]["M"] + 1, cfg["n_elec"]
+    line = {
+        "metric": "trajectory-steps/s (two leads 2x128, six coordinates, bias sweep)",
+        "value": round(total_steps / total_wall, 2),
+        "unit": "trajectory-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": warmup,
+        "ms_per_step": round(1e3 * total_wall / (a.steps * len(biases)), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "n": n, "N": N, "n_traj": T, "dt": cfg["dt"],
+                   "n_dof": len(cfg["model"]["dof"]), "bias": biases, "path": "mixed",
+                   "elec_substeps": a.substeps},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["mixed"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["mixed"], 4),
+                     "traffic": None, "kernel": "k_prop",
+                     "ms_per_launch": round(prop_ms / len(biases), 4)},
+        "by_bias": by_bias,
+    }
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline("c5", a.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
 def adjoint_flops(n, N, sum_terms):
     """Algorithmic flops of one forward + backward adjoint pass: per
     propagated trajectory-step with K terms, the forward propagation, its
@@ -444,6 +521,8 @@ def main():
                     help="desorption: chemical potential in eV (the band follows it)")
     ap.add_argument("--mu-sweep", action="store_true",
                     help="desorption: mu = -0.5, 0, +0.5 eV")
+    ap.add_argument("--bias", type=float, default=None,
+                    help="c5: one bias V (default: the sweep 0, 0.01, 0.02)")
     ap.add_argument("--substeps", type=int, default=1,
                     help="electronic sub-steps per nuclear step (default 1)")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -481,12 +560,14 @@ def main():
     if a.config == "desorption":
         desorption_bench(a)
         return
-    from workloads import get_config, boltzmann_harmonic
+    if a.config == "c5":
+        two_lead_bench(a)
+        return
+    from workloads import get_config
 
     cfg = get_config(a.config)
     T = a.n_traj or cfg["n_traj"]
-    x0, v0 = boltzmann_harmonic(T, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"],
-                                seed=cfg["seed"], kT_factor=cfg.get("sample_kT_factor", 1.0))
+    x0, v0 = initial_sample(cfg, T, cfg["seed"])
     precs = ["fp64", "mixed"] if a.precision == "both" else [a.precision]
     res = {}
     for p in precs:
