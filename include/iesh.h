@@ -139,7 +139,7 @@ typedef struct iesh_run_desc {
   uint64_t seed;         /* key of the hop uniforms                             */
   int32_t lowdin_every;  /* IESH_MIXED: re-orthonormalise every L steps (0: never) */
   int32_t record_every;  /* observables every R steps in iesh_run (0: none)    */
-  int32_t exit_enabled;  /* freeze trajectories once x > exit_x (coordinate 0)  */
+  int32_t exit_enabled;  /* freeze trajectories once x > exit_x (coordinate exit_dof) */
   int32_t compact_every; /* iesh_run: every this many steps, move frozen trajectories
                             behind the active ones so that the step kernels visit
                             only active slots (0: never)                         */
@@ -150,11 +150,15 @@ typedef struct iesh_run_desc {
                             frozen at x_n + (j + 1/2)/S (x_{n+1} - x_n) (Sec. II.C,
                             sub-stepping of the electronic integrator); hop
                             probabilities stay once per nuclear step            */
-  int32_t reserved1;
+  int32_t hop_filter_off; /* 1: evaluate the determinant ratios at every step
+                            instead of skipping steps whose exact no-hop bound
+                            lies below the uniform (same results, slower)     */
   double bias;           /* V: lead 0 at chemical potential mu + V/2, lead 1 at
                             mu - V/2 for the initial occupations (Sec. III.C, an
                             external bias as a shift of the chemical potential);
                             != 0 needs kT > 0 and lead labels in every model    */
+  int32_t exit_dof;      /* coordinate compared with exit_x (0 .. n_dof - 1)     */
+  int32_t reserved2;
 } iesh_run_desc;
 
 #define IESH_MAX_STATES 336   /* n = M + 1 limit of this build                */

@@ -61,7 +61,8 @@ class RunDesc(C.Structure):
                 ("kT", C.c_double), ("seed", C.c_uint64), ("lowdin_every", C.c_int32),
                 ("record_every", C.c_int32), ("exit_enabled", C.c_int32),
                 ("compact_every", C.c_int32), ("exit_x", C.c_double), ("max_steps", C.c_int64),
-                ("elec_substeps", C.c_int32), ("reserved1", C.c_int32), ("bias", C.c_double)]
+                ("elec_substeps", C.c_int32), ("hop_filter_off", C.c_int32), ("bias", C.c_double),
+                ("exit_dof", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class Event(C.Structure):
@@ -212,6 +213,8 @@ class Ensemble:
         r.compact_every = int(run.get("compact_every", 0))
         r.elec_substeps = int(run.get("elec_substeps", 1))
         r.bias = float(run.get("bias", 0.0))
+        r.hop_filter_off = int(run.get("hop_filter_off", 0))
+        r.exit_dof = int(run.get("exit_dof", 0))
         self.run_desc = r
         tm = None
         if traj_model is not None:

@@ -693,6 +693,12 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     } else {
       c.md.mass_dof[0] = d.mass;
     }
+    if (r.exit_dof < 0 || r.exit_dof >= c.md.ndof)
+      return (fail(ctx, IESH_EINVAL, "exit_dof out of range [0, n_dof)"), bail(IESH_EINVAL));
+    if (r.hop_filter_off != 0 && r.hop_filter_off != 1)
+      return (fail(ctx, IESH_EINVAL, "hop_filter_off must be 0 or 1"), bail(IESH_EINVAL));
+    c.exit_dof = r.exit_dof;
+    c.exact_hops = r.hop_filter_off;
     c.n_traj = count[m];
     c.n_live = count[m];
     ctx->slot_home[m].assign(count[m], 0);

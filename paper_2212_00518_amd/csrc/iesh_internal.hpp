@@ -74,6 +74,8 @@ struct ClassDev {
   int traj_offset;      // first global trajectory index of this class
   int nct_max;          // column tiles per propagation work-group
   int n_slabs;          // propagation work-groups per trajectory
+  int exit_dof = 0;     // coordinate compared with the exit distance
+  int exact_hops = 0;   // 1: determinant ratios at every step (no-hop bound unused)
   // device arrays (class-local trajectory index t)
   double* eps = nullptr;    // [M]
   double* vbar = nullptr;   // [M]  sqrt(Gamma w / 2 pi)

@@ -552,7 +552,7 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
     }
     const int64_t ns = c.nsteps[t] + 1;
     c.nsteps[t] = ns;
-    const double x = c.x[(size_t)t * nd];
+    const double x = c.x[(size_t)t * nd + c.exit_dof];
     if (exit_enabled && x > exit_x) st |= IESH_TRAJ_EXITED;
     if ((max_steps > 0 && ns >= max_steps) || (c.stepcap[t] > 0 && ns >= c.stepcap[t]))
       st |= IESH_TRAJ_STEPCAP;
@@ -726,7 +726,8 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
   const int64_t step = cnt->step;
   const double xi = philox_uniform(seed, (uint32_t)c.gtraj[t], (uint64_t)step, 0u);
   const double smin2 = 1.0 - fro2 - delta;
-  const bool no_hop = smin2 > 0.0 && (1.0 + 1e-10) * 2.0 * dt * S1 / sqrt(smin2) <= xi;
+  const bool no_hop =
+      !c.exact_hops && smin2 > 0.0 && (1.0 + 1e-10) * 2.0 * dt * S1 / sqrt(smin2) <= xi;
   __syncthreads();
   if (!no_hop) {
     if (tid == 0) c.hopq[3 + atomicAdd(&c.hopq[0], 1)] = t;
@@ -763,7 +764,7 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
     int32_t st = c.status[t];
     const int64_t ns = c.nsteps[t] + 1;
     c.nsteps[t] = ns;
-    if (exit_enabled && c.x[(size_t)t * nd] > exit_x) st |= IESH_TRAJ_EXITED;
+    if (exit_enabled && c.x[(size_t)t * nd + c.exit_dof] > exit_x) st |= IESH_TRAJ_EXITED;
     if ((max_steps > 0 && ns >= max_steps) || (c.stepcap[t] > 0 && ns >= c.stepcap[t]))
       st |= IESH_TRAJ_STEPCAP;
     double ekin = 0.0;

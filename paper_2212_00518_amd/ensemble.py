@@ -44,9 +44,10 @@ def electrons_below(eps, mu: float) -> int:
 
 def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M: int | None = None,
                 n_elec: int | None = None, lowdin_every: int = 100, record_every: int = 0,
-                stream=None, elec_substeps: int = 1):
+                stream=None, elec_substeps: int = 1, **run_options):
     """One-class ensemble for a workload description of ``workloads.configs``
-    (bath discretised by the library)."""
+    (bath discretised by the library); run_options add iesh_run_desc fields
+    (exit_enabled, exit_x, exit_dof, hop_filter_off, ...)."""
     b = cfg["bath"]
     M = M if M is not None else b["M"]
     N = n_elec if n_elec is not None else cfg.get("n_elec", M // 2)
@@ -57,6 +58,7 @@ def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M
                bias=b.get("bias", 0.0),
                lowdin_every=lowdin_every if precision == "mixed" else 0,
                record_every=record_every, elec_substeps=elec_substeps)
+    run.update(run_options)
     return _lib.Ensemble([desc], run, stream=stream)
 
 

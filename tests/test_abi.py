@@ -100,3 +100,32 @@ def test_product_path_does_not_use_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Size and field offsets of every descriptor struct, as the C compiler
+    lays them out from include/iesh.h, equal the ctypes binding's."""
+    import shutil
+    import subprocess
+    from paper_2212_00518_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"iesh_model_desc": _lib.ModelDesc, "iesh_run_desc": _lib.RunDesc,
+               "iesh_event": _lib.Event, "iesh_sizes": _lib.Sizes}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "iesh.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])

@@ -784,3 +784,62 @@ def test_two_lead_error_paths():
     with pytest.raises(_lib.IeshError, match="distinct"):
         ens.adjoint_forward(np.zeros((2, 4)), 2)
     ens.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_exact_hop_filter_does_not_change_the_dynamics(precision):
+    """hop_filter_off = 1 evaluates the determinant ratios at every step; the
+    no-hop bound is exact, so positions, velocities, orbitals, occupations and
+    hop events are bit-identical with and without it."""
+    cfg = make_cfg("c2", M=40, N=20)
+    m = models.from_config(cfg, M=40)
+    T = 24
+    # even trajectories: random orbitals (hops happen; the bound never rules a
+    # step out); odd ones: the lowest orbitals as unit vectors (the bound rules
+    # out most steps)
+    states = random_states(m, 20, T, seed=41, xs=np.linspace(-8.0, 24.0, T), v_scale=1e-2)
+    for t in range(1, T, 2):
+        states[t] = dyn.State(states[t].x, states[t].v, np.eye(m.n, 20, dtype=np.complex128),
+                              np.arange(20))
+    out = []
+    for off in (0, 1):
+        ens = ensemble(cfg, T, precision=precision, hop_filter_off=off)
+        upload(ens, states)
+        ens.run(200)
+        st = ens.get_state()
+        evs, _ = ens.events()
+        hop_evals = ens.hop_evals()
+        ens.close()
+        out.append((st, [(e["step"], e["traj"], e["a"], e["b"], e["accepted"]) for e in evs], hop_evals))
+    (s0, e0, h0), (s1, e1, h1) = out
+    for a, b in zip(s0, s1):
+        assert np.array_equal(a, b)
+    assert e0 == e1
+    print("events", len(e0), "exact evaluations", h0, "->", h1, flush=True)
+    assert len(e0) > 0
+    assert h1 == T * 200 and 0 < h0 < h1
+
+
+def test_exit_on_a_chosen_coordinate():
+    """exit_dof = 2: a trajectory is frozen as soon as coordinate 2 passes
+    exit_x, and never otherwise."""
+    from paper_2212_00518_amd import _lib
+    cfg = make_cfg("c5", M=12, N=6)
+    cfg["bath"]["leads"] = 1
+    m = models.from_config(cfg, M=12)
+    T = 32
+    rs = np.random.default_rng(12)
+    states = [dyn.State(m.r + rs.normal(0.0, 0.05, size=6), rs.normal(0.0, 2e-3, size=6),
+                        np.eye(m.n, 6, dtype=np.complex128), np.arange(6)) for _ in range(T)]
+    exit_x = 0.2  # about 19 of 32 pass it within 60 steps (oracle run)
+    ens = ensemble(cfg, T, exit_enabled=1, exit_x=exit_x, exit_dof=2)
+    upload(ens, states)
+    ens.run(60)
+    x, _, _, _ = ens.get_state()
+    status = ens.status()
+    ens.close()
+    gone = (status & _lib.TRAJ_EXITED) > 0
+    print("exited", int(gone.sum()), "of", T, flush=True)
+    assert 0 < gone.sum() < T
+    assert np.all(x[gone, 2] > exit_x)
+    assert np.all(x[~gone, 2] <= exit_x)
