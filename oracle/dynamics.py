@@ -224,18 +224,46 @@ def initial_state(model, x0, v0, n_elec, kT, seed, traj, bias=0.0):
     return State(x0, v0, C, s)
 
 
+def next_dt(g_total, dt_cur, dt0, g_max, levels):
+    """Time step of the next step from the hop probabilities of this one.
+
+    Sec. II.C (the paragraph after Eq. fast_exponential_integrator) limits
+    the nuclear step by the size of the hopping probabilities, and the
+    outlook proposes adapting it to them; the paper gives no rule.  Reading:
+    the probabilities are proportional to the step, so the next step is the
+    largest dt0 / 2^k (k = 0 .. levels) for which this step's total,
+    rescaled to it, stays at or below g_max: g_total * (dt0 / 2^k) / dt_cur
+    <= g_max; the smallest step when none does."""
+    dtn = dt0
+    k = 0
+    while k < levels and g_total * (dtn / dt_cur) > g_max:
+        dtn = 0.5 * dtn
+        k += 1
+    return dtn
+
+
 def run(model, st: State, dt: float, n_steps: int, seed: int, traj: int, step0: int = 0,
-        record_every: int = 0, substeps: int = 1):
+        record_every: int = 0, substeps: int = 1, adapt=None):
     """Run n_steps; the hop uniform of step k (0-based, counted from step0) is
-    rng.uniform(seed, traj, step0 + k).  Returns (state, events, records)."""
+    rng.uniform(seed, traj, step0 + k).  Returns (state, events, records).
+
+    adapt = (g_max, levels) makes the step adaptive (next_dt, starting from
+    dt); every event records the step's dt, and the returned state carries
+    the elapsed time and the next step's dt (attributes time, dt)."""
     F = el.forces(model, st.x, st.s)
     events, records = [], []
+    dt_cur, time = dt, 0.0
     for k in range(n_steps):
         xi = _rng.uniform(seed, traj, step0 + k)
-        st, ev, F = step(model, st, dt, xi, F, substeps)
+        st, ev, F = step(model, st, dt_cur, xi, F, substeps)
         ev["step"] = step0 + k
+        ev["dt"] = dt_cur
+        time += dt_cur
+        if adapt is not None:
+            dt_cur = next_dt(ev["g_total"], dt_cur, dt, adapt[0], adapt[1])
         if ev["attempted"]:
             events.append(ev)
         if record_every and (k + 1) % record_every == 0:
             records.append(observables(model, st))
+    st.time, st.dt = time, dt_cur
     return st, events, records

@@ -142,3 +142,68 @@ def test_substeps_converge_at_second_order():
     assert err[0] > 1e-9
     for a, b in zip(err, err[1:]):
         assert 3.2 < a / b < 4.8, err
+
+
+def test_hop_probabilities_are_proportional_to_the_step():
+    """The premise of the adaptive step: for fixed orbitals, occupations,
+    couplings and velocity the hop probabilities scale with dt."""
+    from workloads.sampling import random_orbitals
+    cfg, m = _c1_like(M=12, N=6)
+    rs = np.random.default_rng(2)
+    st = dyn.State([3.0], [4e-3], random_orbitals(m.n, 6, seed=5), np.sort(rs.choice(m.n, 6, replace=False)))
+    g1 = dyn.hop_probs(m, st, 1.0)
+    assert g1.sum() > 0
+    for dt in (0.25, 7.0, 50.0):
+        assert np.allclose(dyn.hop_probs(m, st, dt), dt * g1, rtol=1e-14, atol=0)
+
+
+def test_next_dt_rule():
+    dt0 = 40.0
+    assert dyn.next_dt(0.0, dt0, dt0, 0.05, 3) == dt0
+    # the largest dt0 / 2^k whose rescaled total fits
+    assert dyn.next_dt(0.08, dt0, dt0, 0.05, 3) == dt0 / 2
+    assert dyn.next_dt(0.3, dt0, dt0, 0.05, 3) == dt0 / 8
+    assert dyn.next_dt(0.3, dt0, dt0, 0.05, 2) == dt0 / 4     # floor at levels
+    # from a reduced step the rule can grow back in one step
+    assert dyn.next_dt(0.02, dt0 / 4, dt0, 0.05, 3) == dt0 / 2   # 0.08 at dt0, 0.04 at dt0/2
+    assert dyn.next_dt(0.001, dt0 / 4, dt0, 0.05, 3) == dt0
+    # monotone in the total
+    got = [dyn.next_dt(g, dt0, dt0, 0.05, 5) for g in np.linspace(0.0, 2.0, 41)]
+    assert all(a >= b for a, b in zip(got, got[1:]))
+
+
+def test_adaptive_run_reduces_to_the_fixed_step():
+    """A threshold no step reaches keeps dt fixed: the run is the fixed-step
+    run bit for bit, and the clock reads n_steps * dt."""
+    from workloads.sampling import random_orbitals
+    cfg, m = _c1_like(M=12, N=6)
+    st0 = dyn.State([2.0], [6e-3], random_orbitals(m.n, 6, seed=9), np.arange(6))
+    a, ea, _ = dyn.run(m, st0, cfg["dt"], 25, 0, 3)
+    b, eb, _ = dyn.run(m, st0, cfg["dt"], 25, 0, 3, adapt=(1e300, 4))
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.v, b.v) and np.array_equal(a.C, b.C)
+    assert np.array_equal(a.s, b.s)
+    assert [e["b"] for e in ea] == [e["b"] for e in eb]
+    assert b.time == 25 * cfg["dt"] and b.dt == cfg["dt"]
+
+
+def test_adaptive_run_keeps_the_per_step_total_near_the_threshold():
+    """With strong mixing the adapted steps are smaller, the clock is the sum
+    of the steps taken, and no step after the first exceeds the threshold by
+    more than the one-step change of the probabilities (here a factor 3)."""
+    from workloads.sampling import random_orbitals
+    cfg, m = _c1_like(M=12, N=6)
+    st0 = dyn.State([4.0], [1.5e-2], random_orbitals(m.n, 6, seed=11), np.arange(6))
+    g_max, levels = 0.02, 4
+    steps = []
+    F = el.forces(m, st0.x, st0.s)
+    st, dt_cur, time = st0, cfg["dt"], 0.0
+    for k in range(40):
+        st, ev, F = dyn.step(m, st, dt_cur, rng.uniform(0, 1, k), F)
+        steps.append((dt_cur, ev["g_total"]))
+        time += dt_cur
+        dt_cur = dyn.next_dt(ev["g_total"], dt_cur, cfg["dt"], g_max, levels)
+    fin, _, _ = dyn.run(m, st0, cfg["dt"], 40, 0, 1, adapt=(g_max, levels))
+    assert fin.time == time and np.array_equal(fin.x, st.x)
+    assert min(d for d, _ in steps) < cfg["dt"]
+    for d, g in steps[1:]:
+        assert g <= 3.0 * g_max or d == cfg["dt"] / 2 ** levels
