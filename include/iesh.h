@@ -158,7 +158,15 @@ typedef struct iesh_run_desc {
                             external bias as a shift of the chemical potential);
                             != 0 needs kT > 0 and lead labels in every model    */
   int32_t exit_dof;      /* coordinate compared with exit_x (0 .. n_dof - 1)     */
-  int32_t reserved2;
+  int32_t dt_levels;     /* 0: fixed step dt.  K in 1..30: adaptive step (Sec. II.C
+                            bounds the step by the hopping probabilities): after
+                            each step a trajectory's next step is the largest
+                            dt / 2^k, k = 0..K, for which the step's hop-probability
+                            total, rescaled to it (g is proportional to the step),
+                            stays <= hop_gmax; dt / 2^K when none does.  Each
+                            trajectory keeps its own clock (iesh_traj_clock); the
+                            hop uniforms still follow the step count           */
+  double hop_gmax;       /* threshold of the adaptive step (> 0 when dt_levels > 0) */
 } iesh_run_desc;
 
 #define IESH_MAX_STATES 336   /* n = M + 1 limit of this build                */
@@ -267,6 +275,11 @@ int iesh_adiabatic(iesh_ctx* ctx, int32_t traj0, int32_t ntraj, double* lam_out,
 
 /* Status words (n_traj int32, host). */
 int iesh_traj_status(iesh_ctx* ctx, int32_t* status_out);
+
+/* Step clock of every trajectory (host arrays of n_traj, global trajectory
+   order; either may be NULL): elapsed time and the step its next step will
+   take.  Without an adaptive step, time = steps taken * dt.  Synchronises. */
+int iesh_traj_clock(iesh_ctx* ctx, double* time_out, double* dt_out);
 
 /* Copy up to cap hop events (sorted by step, then trajectory) recorded
    since the last set_state / clear into out (host); *count receives the

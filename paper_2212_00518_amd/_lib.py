@@ -40,7 +40,7 @@ OBS_NAMES = ("Pd_surf", "Pd_wf", "Ekin", "Epot", "Etot")
 SYMBOLS = (
     "iesh_create", "iesh_destroy", "iesh_discretize", "iesh_set_state", "iesh_get_state",
     "iesh_init_thermal", "iesh_set_step", "iesh_get_step", "iesh_step", "iesh_run",
-    "iesh_hop_probs", "iesh_adiabatic", "iesh_traj_status", "iesh_events",
+    "iesh_hop_probs", "iesh_adiabatic", "iesh_traj_status", "iesh_traj_clock", "iesh_events",
     "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
     "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals", "iesh_class_info",
     "iesh_set_step_caps", "iesh_adjoint_forward", "iesh_adjoint_backward",
@@ -62,7 +62,7 @@ class RunDesc(C.Structure):
                 ("record_every", C.c_int32), ("exit_enabled", C.c_int32),
                 ("compact_every", C.c_int32), ("exit_x", C.c_double), ("max_steps", C.c_int64),
                 ("elec_substeps", C.c_int32), ("hop_filter_off", C.c_int32), ("bias", C.c_double),
-                ("exit_dof", C.c_int32), ("reserved2", C.c_int32)]
+                ("exit_dof", C.c_int32), ("dt_levels", C.c_int32), ("hop_gmax", C.c_double)]
 
 
 class Event(C.Structure):
@@ -104,6 +104,7 @@ def lib():
         L.iesh_hop_probs.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int32]
         L.iesh_adiabatic.argtypes = [vp, C.c_int32, C.c_int32, dp, dp]
         L.iesh_traj_status.argtypes = [vp, ip]
+        L.iesh_traj_clock.argtypes = [vp, dp, dp]
         L.iesh_events.argtypes = [vp, C.POINTER(Event), C.c_int64, C.POINTER(C.c_int64)]
         L.iesh_clear_events.argtypes = [vp]
         L.iesh_query_sizes.argtypes = [vp, C.POINTER(Sizes)]
@@ -215,6 +216,8 @@ class Ensemble:
         r.bias = float(run.get("bias", 0.0))
         r.hop_filter_off = int(run.get("hop_filter_off", 0))
         r.exit_dof = int(run.get("exit_dof", 0))
+        r.dt_levels = int(run.get("dt_levels", 0))
+        r.hop_gmax = float(run.get("hop_gmax", 0.0))
         self.run_desc = r
         tm = None
         if traj_model is not None:
@@ -327,6 +330,15 @@ class Ensemble:
         self._check(lib().iesh_traj_status(self.ctx, s.ctypes.data_as(C.POINTER(C.c_int32))),
                     "iesh_traj_status")
         return s
+
+    def clock(self):
+        """(elapsed time, next step) per trajectory."""
+        t = np.zeros(self.n_traj)
+        d = np.zeros(self.n_traj)
+        dpt = C.POINTER(C.c_double)
+        self._check(lib().iesh_traj_clock(self.ctx, t.ctypes.data_as(dpt), d.ctypes.data_as(dpt)),
+                    "iesh_traj_clock")
+        return t, d
 
     def events(self, cap: int = 1 << 16):
         buf = (Event * cap)()

@@ -393,6 +393,15 @@ int reset_perm(iesh_ctx* ctx) {
                                  hipMemcpyHostToDevice, ctx->stream));
       HIPTRY(ctx, hipMemcpyAsync(c.stepcap, ctx->caps_home[ci].data(), c.n_traj * sizeof(int64_t),
                                  hipMemcpyHostToDevice, ctx->stream));
+      // every trajectory restarts its clock at the largest step
+      std::vector<double> ck(2 * (size_t)c.n_traj);
+      for (int s = 0; s < c.n_traj; ++s) {
+        ck[2 * (size_t)s] = c.dt0;
+        ck[2 * (size_t)s + 1] = 0.0;
+      }
+      HIPTRY(ctx, hipMemcpyAsync(c.clock, ck.data(), ck.size() * sizeof(double), hipMemcpyHostToDevice,
+                                 ctx->stream));
+      HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
     }
     if (c.n_live != c.n_traj) free_graph(ctx);
     c.n_live = c.n_traj;
@@ -431,6 +440,7 @@ int compact(iesh_ctx* ctx) {
     HIPTRY(ctx, cp(c.nsteps, b.nsteps, nl * sizeof(int64_t)));
     HIPTRY(ctx, cp(c.stepcap, b.stepcap, nl * sizeof(int64_t)));
     HIPTRY(ctx, cp(c.occ, b.occ, (size_t)nl * N * sizeof(int32_t)));
+    HIPTRY(ctx, cp(c.clock, b.clock, (size_t)nl * 2 * sizeof(double)));
     HIPTRY(ctx, cp(Cdst, b.C, (size_t)nl * N * c.md.n_pad * 2 * esz));
     auto& sh = ctx->slot_home[ci];
     HIPTRY(ctx, hipMemcpyAsync(sh.data(), c.home, nl * sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -632,6 +642,10 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
   if (r.elec_substeps < 0 || r.elec_substeps > 64)
     return (fail(ctx, IESH_EINVAL, "elec_substeps out of range [0, 64]"), bail(IESH_EINVAL));
   if (ctx->run.elec_substeps == 0) ctx->run.elec_substeps = 1;
+  if (r.dt_levels < 0 || r.dt_levels > 30)
+    return (fail(ctx, IESH_EINVAL, "dt_levels out of range [0, 30]"), bail(IESH_EINVAL));
+  if (r.dt_levels > 0 && !(r.hop_gmax > 0.0 && std::isfinite(r.hop_gmax)))
+    return (fail(ctx, IESH_EINVAL, "an adaptive step needs hop_gmax > 0"), bail(IESH_EINVAL));
   if (!std::isfinite(r.bias))
     return (fail(ctx, IESH_EINVAL, "bias must be finite"), bail(IESH_EINVAL));
   if (r.bias != 0.0) {
@@ -699,6 +713,9 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
       return (fail(ctx, IESH_EINVAL, "hop_filter_off must be 0 or 1"), bail(IESH_EINVAL));
     c.exit_dof = r.exit_dof;
     c.exact_hops = r.hop_filter_off;
+    c.dt0 = r.dt;
+    c.gmax = r.hop_gmax;
+    c.dt_levels = r.dt_levels;
     c.n_traj = count[m];
     c.n_live = count[m];
     ctx->slot_home[m].assign(count[m], 0);
@@ -721,6 +738,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
         (rc = dalloc(ctx, &c.geo, (size_t)T * kGeoStride)) ||
         (rc = dalloc(ctx, &c.cheb, (size_t)T * kChebStride)) ||
         (rc = dalloc(ctx, &c.gbuf, (size_t)T * N * n_pad)) ||
+        (rc = dalloc(ctx, &c.clock, (size_t)2 * T)) ||
         (rc = dalloc(ctx, &c.hopq, (size_t)3 + T)))
       return bail(rc);
     if (hop_needs_scratch(c) && (rc = dalloc(ctx, &c.hopx, (size_t)T * N * N)))
@@ -734,6 +752,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
           (rc = dalloc(ctx, &b.home, T)) || (rc = dalloc(ctx, &b.nsteps, T)) ||
           (rc = dalloc(ctx, &b.stepcap, T)) ||
           (rc = dalloc(ctx, &b.occ, (size_t)T * N)) || (rc = dalloc(ctx, &b.dst, T)) ||
+          (rc = dalloc(ctx, &b.clock, (size_t)2 * T)) ||
           (rc = dalloc(ctx, &b.n_active, 1)))
         return bail(rc);
       if (r.precision == IESH_FP64) {
@@ -1129,6 +1148,23 @@ int iesh_traj_status(iesh_ctx* ctx, int32_t* status_out) {
   return IESH_OK;
 }
 
+int iesh_traj_clock(iesh_ctx* ctx, double* time_out, double* dt_out) {
+  if (!ctx || (!time_out && !dt_out)) return IESH_EINVAL;
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+    ClassDev& c = ctx->cls[ci];
+    if (!c.n_traj) continue;
+    std::vector<double> ck(2 * (size_t)c.n_traj);
+    HIPTRY(ctx, hipMemcpy(ck.data(), c.clock, ck.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int sl = 0; sl < c.n_traj; ++sl) {
+      const int g = ctx->members[ci][ctx->slot_home[ci][sl]];
+      if (dt_out) dt_out[g] = ck[2 * (size_t)sl];
+      if (time_out) time_out[g] = ck[2 * (size_t)sl + 1];
+    }
+  }
+  return IESH_OK;
+}
+
 int iesh_events(iesh_ctx* ctx, iesh_event* out, int64_t cap, int64_t* count) {
   if (!ctx || !count || cap < 0) return IESH_EINVAL;
   HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -1223,6 +1259,7 @@ int iesh_adjoint_forward(iesh_ctx* ctx, const double* path, int32_t n_steps, int
   for (const auto& c : ctx->cls)
     if (c.n_traj && c.md.M_red != c.md.M)
       return fail(ctx, IESH_ENOTSUP, "adjoint: distinct bath energies only");
+  if (ctx->run.dt_levels > 0) return fail(ctx, IESH_ENOTSUP, "adjoint: fixed time step only");
   const int T = ctx->run.n_traj;
   for (size_t q = 0; q < (size_t)T * (n_steps + 1); ++q)
     if (!std::isfinite(path[q])) return fail(ctx, IESH_EINVAL, "adjoint: non-finite path");

@@ -76,6 +76,12 @@ struct ClassDev {
   int n_slabs;          // propagation work-groups per trajectory
   int exit_dof = 0;     // coordinate compared with the exit distance
   int exact_hops = 0;   // 1: determinant ratios at every step (no-hop bound unused)
+  // step clock: [T][2] = (dt of the next step, elapsed time); the step kernels
+  // take dt from it.  dt_levels > 0 adapts dt to the hop probabilities.
+  double* clock = nullptr;
+  double dt0 = 0.0;     // largest step (the run's dt)
+  double gmax = 0.0;    // bound on the rescaled hop-probability total per step
+  int dt_levels = 0;    // halvings allowed (0: fixed step)
   // device arrays (class-local trajectory index t)
   double* eps = nullptr;    // [M]
   double* vbar = nullptr;   // [M]  sqrt(Gamma w / 2 pi)
@@ -232,6 +238,19 @@ __host__ __device__ inline ModelAt model_at(const ModelDev& md, const double* xv
 }
 
 // Spare copies of the state that moves with a trajectory (compaction).
+// Step clock after a step whose hop probabilities total g_total: the next
+// step is the largest dt0 / 2^k (k <= dt_levels) for which g_total rescaled
+// from the current step to it stays at or below gmax (Sec. II.C bounds the
+// step by the hopping probabilities; they are proportional to the step).
+__device__ inline void advance_clock(const ClassDev& c, int t, double g_total) {
+  double* ck = c.clock + 2 * (size_t)t;
+  const double dtc = ck[0];
+  double dtn = c.dt0;
+  for (int k = 0; k < c.dt_levels && g_total * (dtn / dtc) > c.gmax; ++k) dtn = 0.5 * dtn;
+  ck[0] = dtn;
+  ck[1] += dtc;
+}
+
 struct CompactBufs {
   double* x = nullptr;
   double* v = nullptr;
@@ -242,6 +261,7 @@ struct CompactBufs {
   int64_t* nsteps = nullptr;
   int64_t* stepcap = nullptr;
   int32_t* occ = nullptr;  // [T][N]
+  double* clock = nullptr;  // [T][2]
   void* C = nullptr;       // [T][N][n_pad] complex, element type of the orbitals
   int32_t* dst = nullptr;  // [T] destination slot of each live slot
   int32_t* n_active = nullptr;  // [1]

@@ -68,6 +68,7 @@ __global__ __launch_bounds__(kMoveThreads) void k_compact_move(ClassDev c, const
     b.nsteps[d] = c.nsteps[t];
     b.stepcap[d] = c.stepcap[t];
   }
+  if (c.clock && threadIdx.x < 2) b.clock[2 * (size_t)d + threadIdx.x] = c.clock[2 * (size_t)t + threadIdx.x];
   for (int r = threadIdx.x; r < N; r += kMoveThreads) b.occ[(size_t)d * N + r] = c.occ[(size_t)t * N + r];
   const size_t len = (size_t)N * n_pad * 2;
   const CT* src = C + (size_t)t * len;

@@ -448,12 +448,13 @@ __device__ void load_bath(const ClassDev& c, EigLds& L) {
 // end point); sub = j in [0, nsub): only the propagator of electronic
 // sub-step j, frozen at x_n + (j + 1/2)/nsub (x_{n+1} - x_n) for dt/nsub;
 // sub = -2: only the end point (after the sub-steps).
-__global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt, int precision,
+__global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt_run, int precision,
                                                            Counters* cnt, int sub, int nsub) {
   __shared__ EigLds L;
   const int t = blockIdx.x;
   const int tid = threadIdx.x;
   if (c.status[t] & kFreezeMask) return;
+  const double dt = c.clock ? c.clock[2 * (size_t)t] : dt_run;  // this trajectory's step
   const ModelDev& md = c.md;
   load_bath(c, L);
   const int nd = md.ndof;

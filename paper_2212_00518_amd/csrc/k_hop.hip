@@ -85,9 +85,10 @@ constexpr bool x_via_scratch() {
 
 // Everything the step needs for trajectory t (all threads of the work-group).
 template <bool kF32, int kRS, int kRB>
-__device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Counters* cnt,
+__device__ void hop_one(const ClassDev& c, int t, double dt_run, uint64_t seed, Counters* cnt,
                         iesh_event* events, int query_mode, int record, int exit_enabled,
                         double exit_x, int64_t max_steps, HopLds& L, double2* xscr) {
+  const double dt = c.clock ? c.clock[2 * (size_t)t] : dt_run;  // this trajectory's step
   constexpr int kCS = (kRS + 1) / 2;  // 32-column slots covering 16 kRS columns
   constexpr bool kXS = x_via_scratch<kRS, kRB>();
   const int tid = threadIdx.x;
@@ -372,9 +373,11 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
     const int bb = L.uocc[bi];
     const int a = L.occ[L.invperm[j]];
     const double gab = L.q0[bb] * L.q0[a] * (dh + rho * ((L.lam[bb] - h) + (L.lam[a] - h)));
-    // v <b|d/dx a>; zero for deflated states (no impurity part), which may
-    // share their energy with another deflated state
-    const double vD = gab == 0.0 ? 0.0 : v * gab / (L.lam[a] - L.lam[bb]);
+    // v <b|d/dx a>.  A deflated state (no impurity part) gives gab = 0: an
+    // exact 0 unless two deflated states share their energy (three or more
+    // equal bath levels), where 0/0 is NaN and the fmax below (maxNum: the
+    // non-NaN operand) returns 0.  No branch here: it costs registers.
+    const double vD = v * gab / (L.lam[a] - L.lam[bb]);
     return fmax(-2.0 * dt * vD * y[rb][cj], 0.0);
   };
 
@@ -562,6 +565,7 @@ __device__ void hop_one(const ClassDev& c, int t, double dt, uint64_t seed, Coun
       ekin += 0.5 * md.mass_dof[nu] * vv[nu] * vv[nu];
     }
     c.status[t] = st;
+    if (c.clock) advance_clock(c, t, sel_total);
     L.sc_occ_changed = occ_changed;
     L.sc_ekin = ekin;
   }
@@ -649,7 +653,7 @@ struct FltLds {
 };
 
 template <bool kF32>
-__global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double dt, uint64_t seed,
+__global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double dt_run, uint64_t seed,
                                                             Counters* cnt, int record,
                                                             int exit_enabled, double exit_x,
                                                             int64_t max_steps, double delta) {
@@ -659,6 +663,7 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
   const ModelDev& md = c.md;
   const int n = md.n, n_pad = md.n_pad, N = md.N;
   if (c.status[t] & kFreezeMask) return;
+  const double dt = c.clock ? c.clock[2 * (size_t)t] : dt_run;  // this trajectory's step
   for (int k = tid; k < n_pad; k += kFltThreads) {
     L.lam[k] = c.lam[(size_t)t * n_pad + k];
     L.q0[k] = c.q0[(size_t)t * n_pad + k];
@@ -726,8 +731,12 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
   const int64_t step = cnt->step;
   const double xi = philox_uniform(seed, (uint32_t)c.gtraj[t], (uint64_t)step, 0u);
   const double smin2 = 1.0 - fro2 - delta;
-  const bool no_hop =
-      !c.exact_hops && smin2 > 0.0 && (1.0 + 1e-10) * 2.0 * dt * S1 / sqrt(smin2) <= xi;
+  // no hop when the bound on the total lies below the uniform; an adaptive
+  // step also needs the bound to keep the next step at its largest (the
+  // total, at most the bound, then selects dt0 exactly)
+  const double bound = smin2 > 0.0 ? (1.0 + 1e-10) * 2.0 * dt * S1 / sqrt(smin2) : 0.0;
+  const bool no_hop = !c.exact_hops && smin2 > 0.0 && bound <= xi &&
+                      (c.dt_levels == 0 || bound * (c.dt0 / dt) <= c.gmax);
   __syncthreads();
   if (!no_hop) {
     if (tid == 0) c.hopq[3 + atomicAdd(&c.hopq[0], 1)] = t;
@@ -774,6 +783,7 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
       ekin += 0.5 * md.mass_dof[nu] * vn * vn;
     }
     c.status[t] = st;
+    if (c.clock) advance_clock(c, t, 0.0);  // the bound kept the step at dt0
     if (record) {
       const int64_t rel = step - cnt->run_step0 + 1;
       if (cnt->record_every > 0 && rel % cnt->record_every == 0) {

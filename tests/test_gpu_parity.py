@@ -384,7 +384,7 @@ def test_lowdin_step_restores_orthonormality(name, M, N):
 
 
 # ------------------------------------------------------------------ compaction
-def _two_class_run(compact_every, steps=200, T=96):
+def _two_class_run(compact_every, steps=200, T=96, **extra):
     from paper_2212_00518_amd import _lib
     cfg = get_config("c1")
     descs = []
@@ -394,6 +394,7 @@ def _two_class_run(compact_every, steps=200, T=96):
     tm = np.arange(T) % 2
     run = dict(n_traj=T, precision="fp64", dt=cfg["dt"], kT=cfg["kT"], seed=11,
                record_every=10, exit_enabled=1, exit_x=2.0, compact_every=compact_every)
+    run.update(extra)
     ens = _lib.Ensemble(descs, run, traj_model=tm)
     x0, v0 = boltzmann_harmonic(T, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"], seed=5)
     x0 = x0 - 2.0  # start below the exit distance; trajectories cross it at scattered times
@@ -403,8 +404,9 @@ def _two_class_run(compact_every, steps=200, T=96):
     status = ens.status()
     evs, _ = ens.events(cap=1 << 16)
     info = [ens.class_info(k) for k in (0, 1)]
+    clock = ens.clock()
     ens.close()
-    return obs, state, status, evs, info
+    return obs, state, status, evs, info, clock
 
 
 def test_compaction_is_invisible_in_the_results():
@@ -843,3 +845,98 @@ def test_exit_on_a_chosen_coordinate():
     assert 0 < gone.sum() < T
     assert np.all(x[gone, 2] > exit_x)
     assert np.all(x[~gone, 2] <= exit_x)
+
+
+
+# ------------------------------------------------------------ adaptive step
+def _oracle_adaptive(m, st, dt0, steps, seed, traj, g_max, levels):
+    """The oracle's adaptive run, step by step, keeping every step's total and
+    the margin of each step-size decision."""
+    F = el.forces(m, st.x, st.s)
+    dt, time, evs, dmargin = dt0, 0.0, [], 1e300
+    for k in range(steps):
+        st, ev, F = dyn.step(m, st, dt, rng.uniform(seed, traj, k), F)
+        ev["step"] = k
+        if ev["attempted"]:
+            evs.append(ev)
+        time += dt
+        for q in range(levels + 1):
+            dmargin = min(dmargin, abs(ev["g_total"] * (dt0 / 2 ** q) / dt - g_max) / g_max)
+        dt = dyn.next_dt(ev["g_total"], dt, dt0, g_max, levels)
+    return st, evs, time, dt, dmargin
+
+
+@pytest.mark.parametrize("filter_off", [0, 1])
+def test_adaptive_step_matches_the_oracle(filter_off):
+    """dt_levels = 4, hop_gmax = 0.02 on random orbitals (large hop
+    probabilities): per-trajectory steps, clocks, states and hop events equal
+    the oracle's adaptive run (decisions within 1e-9 of a threshold left out)."""
+    from paper_2212_00518_amd import unpack_C
+    cfg = make_cfg("c1", M=12, N=6)
+    m = models.from_config(cfg, M=12)
+    T, steps, g_max, levels = 10, 40, 0.02, 4
+    states = random_states(m, 6, T, seed=23, xs=np.linspace(-4.0, 20.0, T), v_scale=1.5e-2)
+    ens = ensemble(cfg, T, dt_levels=levels, hop_gmax=g_max, hop_filter_off=filter_off)
+    upload(ens, states)
+    ens.run(steps)
+    x, v, Cf, occ = ens.get_state()
+    evs, _ = ens.events()
+    time, dtn = ens.clock()
+    n_max, N_max = ens.n_max, ens.N_max
+    ens.close()
+    compared, reduced = 0, 0
+    for t in range(T):
+        ref, ref_ev, rtime, rdt, dmargin = _oracle_adaptive(m, states[t], cfg["dt"], steps,
+                                                            cfg["seed"], t, g_max, levels)
+        if dmargin < 1e-9 or any(e["margin"] < 1e-7 * max(e["g_total"], 1e-300) for e in ref_ev):
+            continue
+        mine = [e for e in evs if e["traj"] == t]
+        assert [(e["step"], e["a"], e["b"], e["accepted"]) for e in mine] == \
+               [(e["step"], e["a"], e["b"], e["accepted"]) for e in ref_ev], t
+        assert time[t] == rtime and dtn[t] == rdt, (t, time[t], rtime, dtn[t], rdt)
+        assert abs(x[t] - ref.x[0]) <= 1e-10 * max(1.0, abs(ref.x[0])), t
+        assert abs(v[t] - ref.v[0]) <= 1e-10 * max(1e-3, abs(ref.v[0])), t
+        assert np.max(np.abs(unpack_C(Cf, t, m.n, 6, n_max, N_max) - ref.C)) <= 1e-9, t
+        assert list(occ[t, :6]) == list(ref.s), t
+        compared += 1
+        reduced += rtime < steps * cfg["dt"]
+    print("compared", compared, "with reduced steps", reduced, flush=True)
+    assert compared >= T - 2 and reduced >= 3
+
+
+def test_fixed_step_clock_counts_steps():
+    cfg = make_cfg("c1", M=12, N=6)
+    T = 4
+    x0, v0 = boltzmann_harmonic(T, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"], seed=1)
+    ens = ensemble(cfg, T)
+    ens.init_thermal(x0, v0)
+    ens.run(17)
+    time, dtn = ens.clock()
+    ens.close()
+    assert np.all(time == 17 * cfg["dt"]) and np.all(dtn == cfg["dt"])
+
+
+def test_adaptive_step_with_compaction_is_invisible_in_the_results():
+    """The step clocks move with their trajectories: an adaptive run (a tiny
+    threshold, so steps shrink near the crossing) with compaction every 10
+    steps equals the same run without it, clocks included."""
+    extra = dict(dt_levels=3, hop_gmax=1e-7)
+    ref = _two_class_run(0, **extra)
+    got = _two_class_run(10, **extra)
+    for a, b in zip(ref[1], got[1]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(ref[2], got[2])
+    assert np.array_equal(ref[5][0], got[5][0]) and np.array_equal(ref[5][1], got[5][1])
+    steps_taken = ref[5][0] / get_config("c1")["dt"]
+    print("exited", int(np.sum(ref[2] & 1)), "min time in steps", steps_taken.min(), flush=True)
+    assert np.any(ref[5][1] < get_config("c1")["dt"])  # some next steps are reduced
+    assert int(np.sum(ref[2] & 1)) >= 10
+
+
+def test_adaptive_step_error_paths():
+    from paper_2212_00518_amd import _lib
+    cfg = make_cfg("c1", M=12, N=6)
+    with pytest.raises(_lib.IeshError):
+        ensemble(cfg, 2, dt_levels=2)            # no threshold
+    with pytest.raises(_lib.IeshError):
+        ensemble(cfg, 2, dt_levels=31, hop_gmax=0.1)
