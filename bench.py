@@ -62,11 +62,12 @@ def traffic_from_profile(path_md, kernel_src):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1):
+def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1, **run_options):
     import torch
     from paper_2212_00518_amd import from_config
 
-    ens = from_config(cfg, n_traj=T, precision=precision, lowdin_every=100, elec_substeps=substeps)
+    ens = from_config(cfg, n_traj=T, precision=precision, lowdin_every=100, elec_substeps=substeps,
+                      **run_options)
     ens.init_thermal(x0, v0)
     ens.run(warmup)
     ens.sync()
@@ -81,6 +82,7 @@ def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1):
     sum_terms, traj_steps = ens.work()
     hop_evals = ens.hop_evals()
     status = ens.status()
+    clock_time, _ = ens.clock()
     ens.timing(False)
     ens.close()
     n, N = cfg["bath"]["M"] + 1, cfg["n_elec"]
@@ -96,6 +98,7 @@ def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1):
         mean_cheb_terms=sum_terms / max(traj_steps, 1),
         exact_hop_fraction=hop_evals / max(traj_steps, 1),
         frozen=int((status != 0).sum()),
+        mean_dt=float(clock_time.sum()) / max(warmup + steps, 1) / T,
     )
 
 
@@ -525,6 +528,10 @@ def main():
                     help="c5: one bias V (default: the sweep 0, 0.01, 0.02)")
     ap.add_argument("--substeps", type=int, default=1,
                     help="electronic sub-steps per nuclear step (default 1)")
+    ap.add_argument("--dt-levels", type=int, default=0,
+                    help="adaptive step: halvings allowed (0: fixed step)")
+    ap.add_argument("--hop-gmax", type=float, default=0.0,
+                    help="adaptive step: bound on the rescaled hop-probability total per step")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint ms/step entry of the default line")
     ap.add_argument("--forced-lifetimes", action="store_true",
@@ -571,7 +578,8 @@ def main():
     precs = ["fp64", "mixed"] if a.precision == "both" else [a.precision]
     res = {}
     for p in precs:
-        res[p] = time_path(cfg, p, T, a.steps, a.warmup, x0, v0, a.substeps)
+        adapt = dict(dt_levels=a.dt_levels, hop_gmax=a.hop_gmax) if a.dt_levels else {}
+        res[p] = time_path(cfg, p, T, a.steps, a.warmup, x0, v0, a.substeps, **adapt)
         print(f"# {p}: {res[p]['value']:.1f} trajectory-steps/s, {res[p]['ms_per_step']:.2f} ms/step, "
               f"kernels {res[p]['kernels_ms']} ms, propagation {res[p]['prop_tflops']:.2f} TFLOP/s",
               file=sys.stderr, flush=True)
@@ -595,7 +603,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "M": cfg["bath"]["M"], "N": cfg["n_elec"],
                    "n_traj": T, "dt": cfg["dt"], "bath": cfg["bath"]["kind"], "path": head,
-                   "elec_substeps": a.substeps},
+                   "elec_substeps": a.substeps, "dt_levels": a.dt_levels, "hop_gmax": a.hop_gmax},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[head],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[head], 4),
                      "traffic": traffic, "kernel": "k_prop",
@@ -605,6 +613,7 @@ def main():
         "kernels_ms_per_launch": r["kernels_ms"],
         "kernels_time_share": r["kernels_share"],
         "exact_hop_fraction": round(r["exact_hop_fraction"], 4),
+        "mean_dt": round(r["mean_dt"], 4),
     }
     if "fp64" in res and head != "fp64":
         f = res["fp64"]
