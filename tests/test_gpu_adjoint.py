@@ -255,3 +255,22 @@ def test_gradient_matches_central_differences_of_the_gpu_loss():
         scale = np.max(np.abs(g[t]))
         err = np.abs(g[t] - fd[t])
         assert np.all(err <= 1e-6 * scale + 1e-6 * np.abs(fd[t])), (t, np.max(err), scale)
+
+
+def test_full_ensemble_of_1024_paths_sampled():
+    """The adjoint workload's ensemble size (1024 paths, M = 100, N = 50, all
+    four loss terms) on a short prefix; two sampled paths against the oracle,
+    every path's loss finite."""
+    p, dt = _model(100)
+    N, T, n_steps = 50, 1024, 4
+    x = _paths(p, T, n_steps, dt, seed=3)
+    ens = _ensemble(p, N, T, dt)
+    loss = ens.adjoint_forward(x, 3, TERMS)
+    w = np.linspace(0.5, 1.5, T)
+    rows = ens.adjoint_backward(w)
+    assert np.all(np.isfinite(loss)) and np.all(np.isfinite(rows))
+    npar = adj.n_params(100)
+    for t in (0, 1023):
+        ref = adj.loss(p, x[t], N, dt, TERMS)
+        assert abs(loss[t] - ref) <= 1e-10 * abs(ref), (t, loss[t], ref)
+        _check_grad(rows[t, :npar], w[t] * adj.gradient(p, x[t], N, dt, TERMS), f"path {t}")
