@@ -940,3 +940,72 @@ def test_adaptive_step_error_paths():
         ensemble(cfg, 2, dt_levels=2)            # no threshold
     with pytest.raises(_lib.IeshError):
         ensemble(cfg, 2, dt_levels=31, hop_gmax=0.1)
+
+
+def test_hop_total_above_one_is_not_clipped():
+    """Large velocities: several trajectories have a hop-probability total
+    above one.  The probabilities are the oracle's (no clipping), and one step
+    selects the same hop as the oracle (with a total above one a uniform
+    below one always finds a pair)."""
+    cfg = make_cfg("c1", M=20, N=10)
+    m = models.from_config(cfg, M=20)
+    T = 8
+    states = random_states(m, 10, T, seed=71, xs=np.linspace(8.0, 14.0, T), v_scale=0.1)
+    ens = ensemble(cfg, T)
+    upload(ens, states)
+    g = ens.hop_probs()
+    above = 0
+    for t in range(T):
+        gr = dyn.hop_probs(m, states[t], cfg["dt"])
+        gg = g[t].reshape(ens.N_max, ens.n_max)[:10, :m.n]
+        assert np.max(np.abs(gg - gr)) <= 1e-10 * np.max(gr), t
+        above += gr.sum() > 1.0
+    assert above >= 3
+    ens.set_step(7)
+    ens.step()
+    evs, _ = ens.events()
+    _, _, _, occ = ens.get_state()
+    ens.close()
+    for t in range(T):
+        st, ev, _ = dyn.step(m, states[t], cfg["dt"], rng.uniform(cfg["seed"], t, 7))
+        if ev["margin"] < 1e-7 * ev["g_total"]:
+            continue
+        mine = [e for e in evs if e["traj"] == t]
+        if ev["g_total"] > 1.0:
+            assert ev["attempted"]
+        assert [(e["a"], e["b"], e["accepted"]) for e in mine] == \
+               ([(ev["a"], ev["b"], ev["accepted"])] if ev["attempted"] else []), t
+        assert list(occ[t, :10]) == list(st.s), t
+
+
+def test_a_model_without_trajectories_changes_nothing():
+    """Two models in one context with every trajectory on the second: the
+    empty class is skipped and the run equals the one-model context bit for
+    bit; zero steps are a no-op."""
+    from paper_2212_00518_amd import _lib
+    cfg = get_config("c1")
+    T = 12
+    descs = []
+    for M in (30, 20):
+        eps, w = _lib.discretize(cfg["bath"]["kind"], M, cfg["bath"]["W"])
+        descs.append(_lib.model_desc(cfg["model"], eps, w, M // 2))
+    run = dict(n_traj=T, precision="fp64", dt=cfg["dt"], kT=cfg["kT"], seed=2)
+    x0, v0 = boltzmann_harmonic(T, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"], seed=9)
+    out = []
+    for models_, tm in ((descs, np.ones(T, dtype=np.int32)), (descs[1:], None)):
+        ens = _lib.Ensemble(models_, run, traj_model=tm)
+        ens.init_thermal(x0, v0)
+        before = ens.get_state()
+        ens.run(0)
+        after = ens.get_state()
+        for a, b in zip(before, after):
+            assert np.array_equal(a, b)
+        ens.run(40)
+        out.append((ens.get_state(), ens.n_max, ens.N_max))
+        ens.close()
+    from paper_2212_00518_amd import unpack_C
+    (s0, n0, N0), (s1, n1, N1) = out
+    assert np.array_equal(s0[0], s1[0]) and np.array_equal(s0[1], s1[1])
+    assert np.array_equal(s0[3][:, :10], s1[3][:, :10])
+    for t in range(T):
+        assert np.array_equal(unpack_C(s0[2], t, 21, 10, n0, N0), unpack_C(s1[2], t, 21, 10, n1, N1))
