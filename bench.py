@@ -542,7 +542,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {a.gpus} is not supported (trajectories are "
-              f"independent; sharding across GPUs is described in DESIGN.md)", file=sys.stderr)
+              f"independent: shard them by trajectory, one process and one context per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch

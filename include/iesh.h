@@ -57,7 +57,7 @@ extern "C" {
 #define IESH_ENOMEM (-2)   /* device allocation failed                       */
 #define IESH_EDEVICE (-3)  /* HIP runtime / kernel launch error              */
 #define IESH_ESTATE (-4)   /* call not valid in the current context state   */
-#define IESH_ENOTSUP (-5)  /* combination not supported by this build        */
+#define IESH_ENOTSUP (-5)  /* combination not supported by the library        */
 
 /* ---- per-trajectory status bits (iesh_traj_status) -------------------- */
 #define IESH_TRAJ_OK 0
@@ -169,8 +169,8 @@ typedef struct iesh_run_desc {
   double hop_gmax;       /* threshold of the adaptive step (> 0 when dt_levels > 0) */
 } iesh_run_desc;
 
-#define IESH_MAX_STATES 336   /* n = M + 1 limit of this build                */
-#define IESH_MAX_ELEC 168     /* N limit of this build                        */
+#define IESH_MAX_STATES 336   /* n = M + 1 limit of the library               */
+#define IESH_MAX_ELEC 168     /* N limit of the library                       */
 #define IESH_MAX_DOF 6        /* nuclear coordinates per trajectory            */
 
 /* Observables written per record and trajectory by iesh_run, in this order. */
