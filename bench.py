@@ -419,6 +419,86 @@ def two_lead_bench(a):
     print(json.dumps(line), flush=True)
 
 
+def _cpu_adj_worker(args):
+    t, steps = args
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        from oracle import adjoint as adj, bath
+        from workloads import get_config
+        from workloads.sampling import fixed_paths
+        cfg = get_config("c4")
+        m, b = cfg["model"], cfg["bath"]
+        eps, w = bath.discretise(b["kind"], b["M"], b["W"])
+        p = adj.Params(m.get("eps_d", 0.0), m["Gamma"], eps, m["omega"], m["g"], m["dG"], w, m["mass"])
+        x, _ = fixed_paths(t + 1, steps, cfg["dt"], m["omega"], seed=cfg["seed"])
+        t0 = time.perf_counter()
+        adj.gradient(p, x[t], cfg["n_elec"], cfg["dt"], (1.0, 1.0, 1.0, 1.0))
+        return time.perf_counter() - t0
+
+
+def adjoint_cpu_baseline(steps_per_worker, n_paths):
+    """The oracle's loss and tangent-linear gradient (every parameter
+    direction) timed on the host cores: one path per process."""
+    import multiprocessing as mp
+    workers = min(16, os.cpu_count() or 1)
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        per = pool.map(_cpu_adj_worker, [(t, steps_per_worker) for t in range(workers)])
+    wall = time.perf_counter() - t0
+    path_steps = workers * steps_per_worker
+    return dict(value=round(1e3 * n_paths * wall / path_steps, 1), unit="ms/step", cores=workers,
+                kind="oracle",
+                sample=f"{workers} paths x {steps_per_worker} steps, one process per path, one BLAS "
+                       f"thread each; scaled to {n_paths} paths",
+                path_steps_per_s=round(path_steps / wall, 3),
+                one_core_s_per_path_step=sum(per) / path_steps)
+
+
+def peak_probe():
+    """Library GEMMs (torch.matmul: hipBLASLt / rocBLAS) on square matrices:
+    the FP32 and FP64 matrix-core rates this device reaches in practice."""
+    import torch
+    out = {}
+    for dt, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+        n = 8192
+        a = torch.randn(n, n, device="cuda", dtype=dt)
+        b = torch.randn(n, n, device="cuda", dtype=dt)
+        for _ in range(3):
+            torch.matmul(a, b)
+        torch.cuda.synchronize()
+        reps = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            torch.matmul(a, b)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"n": n, "ms": round(ms, 3), "tflops": round(2.0 * n ** 3 / (ms * 1e-3) / 1e12, 2)}
+        del a, b
+        # the propagation's product: per trajectory B (n_pad x n_pad) times the
+        # real orbital block (n_pad x 2N), 4096 trajectories at n = 201, N = 100
+        bt, npad, cols = 4096, 208, 200
+        a = torch.randn(bt, npad, npad, device="cuda", dtype=dt)
+        b = torch.randn(bt, npad, cols, device="cuda", dtype=dt)
+        for _ in range(3):
+            torch.bmm(a, b)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            torch.bmm(a, b)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name + "_batched_208x208x200_x4096"] = {
+            "ms": round(ms, 3), "tflops": round(2.0 * bt * npad * npad * cols / (ms * 1e-3) / 1e12, 2)}
+        del a, b
+    print(json.dumps({"gemm_peak_probe": out, "published_peak_tflops": PEAK_TFLOPS}), flush=True)
+
+
 def adjoint_flops(n, N, sum_terms):
     """Algorithmic flops of one forward + backward adjoint pass: per
     propagated trajectory-step with K terms, the forward propagation, its
@@ -505,6 +585,8 @@ def adjoint_bench(a, cfg=None, n_steps=None, report=True):
         "grad_norm": float(np.linalg.norm(g.sum(axis=0))),
     }
     if report:
+        if not getattr(a, "no_cpu", True):
+            out["cpu_baseline"] = adjoint_cpu_baseline(10, T)
         print(json.dumps(out), flush=True)
     return out
 
@@ -536,6 +618,8 @@ def main():
                     help="skip the adjoint ms/step entry of the default line")
     ap.add_argument("--forced-lifetimes", action="store_true",
                     help="c3: per-trajectory step caps log-uniform in [200, 20000]")
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="only time library FP32 / FP64 GEMMs (8192^3) for the achievable MFMA rate")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference dispatch for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -550,6 +634,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if a.peak_probe:
+        peak_probe()
+        return
     if a.copy_calibration:
         x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
