@@ -262,7 +262,9 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c, T* taps, int 
   s.n_pad = md.n_pad;
   s.N = md.N;
   s.RT = s.n_pad >> 4;
-  s.KB = s.n_pad >> 2;
+  // k-blocks of the product: rows past n of B and of the slab are zero, so
+  // the sum stops at ceil(n / 4) blocks, rounded up to the prefetch ring
+  s.KB = ((((md.n + 3) >> 2) + kDepth - 1) / kDepth) * kDepth;
   const int tiles_total = (s.N + 7) >> 3;
   const int base = tiles_total / c.n_slabs, rem = tiles_total % c.n_slabs;
   s.tile0 = slab * base + (slab < rem ? slab : rem);
