@@ -1009,3 +1009,37 @@ def test_a_model_without_trajectories_changes_nothing():
     assert np.array_equal(s0[3][:, :10], s1[3][:, :10])
     for t in range(T):
         assert np.array_equal(unpack_C(s0[2], t, 21, 10, n0, N0), unpack_C(s1[2], t, 21, 10, n1, N1))
+
+
+@pytest.mark.parametrize("bias", [0.01, 0.02])
+def test_biased_occupations_with_offset_lead_grids(bias):
+    """Two leads on grids offset by half a spacing (no equal energies, no
+    deflation): the lead weights of every orbital come from the coupling
+    formula alone; the sampled occupations equal the oracle's."""
+    from paper_2212_00518_amd import _lib
+    from workloads.sampling import boltzmann_coordinates
+    cfg = make_cfg("c5", M=40, N=20)
+    W, M1 = 0.1, 20
+    e1 = -0.5 * W + np.arange(M1) * (W / (M1 - 1))
+    w1 = np.full(M1, W / M1)
+    eps = np.concatenate([e1, e1 + 0.5 * W / (M1 - 1)])
+    w = np.concatenate([0.5 * w1, 0.5 * w1])
+    lead = np.repeat(np.array([0, 1], dtype=np.int32), M1)
+    order = np.argsort(eps, kind="stable")
+    eps, w, lead = eps[order], w[order], lead[order]
+    mc = cfg["model"]
+    m = models.MultiDof(eps, w, mc["Gamma"], mc["dof"], mc["Delta"], mc.get("eps_d", 0.0))
+    m.lead = lead
+    T = 12
+    dof = np.array(mc["dof"])
+    om = dof[:, 2] * np.sqrt(2.0 * dof[:, 1] / dof[:, 0])
+    x0, v0 = boltzmann_coordinates(T, dof[:, 0], om, dof[:, 3], cfg["kT"], seed=8)
+    ens = _lib.Ensemble([_lib.model_desc(mc, eps, w, 20, lead)],
+                        dict(n_traj=T, precision="fp64", dt=cfg["dt"], kT=cfg["kT"], seed=cfg["seed"],
+                             bias=bias))
+    ens.init_thermal(x0, v0)
+    _, _, _, occ = ens.get_state()
+    ens.close()
+    for t in range(T):
+        ref = dyn.initial_state(m, x0[t], v0[t], 20, cfg["kT"], cfg["seed"], t, bias=bias)
+        assert list(occ[t, :20]) == list(ref.s), t
