@@ -209,8 +209,8 @@ def scattering_bench(a):
     for M in classes:
         eps, w = _lib.discretize(cfg["bath"]["kind"], M, cfg["bath"]["W"])
         descs.append(_lib.model_desc(cfg["model"], eps, w, M // 2))
-    x0, v0, _ = scattering_initial(T, cfg["model"]["mass"], cfg["x_start"], cfg["E_inc"],
-                                   seed=cfg["seed"] + 1)
+    x0, v0, e_inc = scattering_initial(T, cfg["model"]["mass"], cfg["x_start"], cfg["E_inc"],
+                                       seed=cfg["seed"] + 1)
     chunk = 100
     run = dict(n_traj=T, precision="mixed", dt=cfg["dt"], kT=0.0, seed=cfg["seed"],
                lowdin_every=100, exit_enabled=1, exit_x=cfg["exit_x"],
@@ -242,7 +242,19 @@ def scattering_bench(a):
     _, traj_steps = ens.work()
     status = ens.status()
     info1 = [ens.class_info(k) for k in range(len(classes))]
+    _, v_end, _, _ = ens.get_state()
     ens.close()
+    # kinetic-energy loss of the trajectories that rebounded past the exit
+    # distance: 1 - E_kin(final) / E_inc, by incidence energy (Sec. III.D)
+    out = (status & _lib.TRAJ_EXITED) > 0
+    loss = 1.0 - 0.5 * cfg["model"]["mass"] * v_end ** 2 / e_inc
+    edges = np.linspace(cfg["E_inc"][0], cfg["E_inc"][1], 6)
+    ke_loss = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        sel = out & (e_inc >= lo) & (e_inc < hi)
+        ke_loss.append({"E_inc_eV": [round(lo * 27.211386, 3), round(hi * 27.211386, 3)],
+                        "rebounded": int(sel.sum()),
+                        "mean_ke_loss": round(float(loss[sel].mean()), 4) if sel.any() else None})
     line = {
         "metric": "useful trajectory-steps/s (scattering, uneven M, compaction every 100 steps)",
         "value": round(traj_steps / wall, 2),
@@ -266,6 +278,7 @@ def scattering_bench(a):
         "live_slots_at_end": {str(M): i["live"] for M, i in zip(classes, info1)},
         "trajectories_per_class": {str(M): i["n_traj"] for M, i in zip(classes, info0)},
         "context_creation_s": round(t_create, 2),
+        "kinetic_energy_loss": ke_loss,
     }
     print(json.dumps(line), flush=True)
 
