@@ -37,7 +37,7 @@ namespace {
 
 constexpr int kPropWaves = 8;
 constexpr int kPropThreads = kPropWaves * 64;
-constexpr int kDepth = 2;  // k-blocks of A operands in flight per wave (divides n_pad / 4)
+constexpr int kDepth = 2;  // k-blocks of A operands in flight per wave (the k-block count is a multiple)
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -96,7 +96,7 @@ struct Slab {
   T* X0;        // LDS [n_pad][ldx]: b_j for even j, finally the result
   T* X1;        // LDS [n_pad][ldx]: b_j for odd j
   T* lam;       // LDS [n_pad]: lambda - c
-  const T* Bt;  // memory [KB][RT][64]
+  const T* Bt;  // memory [n_pad / 4][RT][64]; the first KB k-blocks enter the product
   const T* Cg;  // memory [N][n_pad] complex: the input orbitals
   const double* cb;
   T* tap;       // memory [K][N][n_pad] complex (tap modes), this trajectory
