@@ -386,6 +386,10 @@ int iesh_adjoint_backward(iesh_ctx* ctx, const double* dloss, double* grad_out);
 /* Wait for all work on the context stream; reports asynchronous errors. */
 int iesh_sync(iesh_ctx* ctx);
 
+/* Description of the last failure on ctx; with ctx = NULL, the reason the
+   last iesh_create on the calling thread failed.  iesh_create checks every
+   argument before its first device call, so argument errors (IESH_EINVAL)
+   are reported without touching a GPU. */
 const char* iesh_last_error(const iesh_ctx* ctx);
 int iesh_version(int* major, int* minor, int* patch);
 

@@ -227,7 +227,8 @@ class Ensemble:
         st = C.c_void_p(stream) if stream is not None else None
         rc = L.iesh_create(arr, len(self._descs), tm, C.byref(r), st, C.byref(ctx))
         if rc != IESH_OK:
-            raise IeshError(f"iesh_create failed ({rc})")
+            why = L.iesh_last_error(None)
+            raise IeshError(f"iesh_create failed ({rc}): {why.decode() if why else ''}")
         self.ctx = ctx
         s = Sizes()
         L.iesh_query_sizes(ctx, C.byref(s))

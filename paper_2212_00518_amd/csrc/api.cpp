@@ -578,7 +578,13 @@ int iesh_version(int* major, int* minor, int* patch) {
   return IESH_OK;
 }
 
-const char* iesh_last_error(const iesh_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+// reason of the last failed iesh_create on this thread (no context exists then)
+thread_local std::string g_create_err;
+
+const char* iesh_last_error(const iesh_ctx* ctx) {
+  if (ctx) return ctx->err.c_str();
+  return g_create_err.empty() ? "null context" : g_create_err.c_str();
+}
 
 int iesh_discretize(int32_t kind, int32_t M, double a, double b, double eps_f, double* eps,
                     double* w) {
@@ -587,7 +593,7 @@ int iesh_discretize(int32_t kind, int32_t M, double a, double b, double eps_f, d
 
 int iesh_destroy(iesh_ctx* ctx) {
   if (!ctx) return IESH_OK;
-  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   free_graph(ctx);
   for (void* p : ctx->allocations) (void)hipFree(p);
   for (void* p : ctx->adj_allocs) (void)hipFree(p);
@@ -604,28 +610,17 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
   if (!models || n_models < 1 || !run) return IESH_EINVAL;
   iesh_ctx* ctx = new (std::nothrow) iesh_ctx();
   if (!ctx) return IESH_ENOMEM;
+  g_create_err.clear();
   auto bail = [&](int code) {
-    // keep the message for the caller through a static buffer
-    static thread_local std::string last;
-    last = ctx->err;
+    // keep the message for iesh_last_error(NULL)
+    g_create_err = ctx->err;
     iesh_destroy(ctx);
-    std::fprintf(stderr, "iesh_create: %s\n", last.c_str());
+    std::fprintf(stderr, "iesh_create: %s\n", g_create_err.c_str());
     return code;
   };
   ctx->run = *run;
-  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  if (!ctx->stream) {
-    // the step loop is captured into a graph, which needs a non-null stream
-    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
-      return (fail(ctx, IESH_EDEVICE, "stream creation failed"), bail(IESH_EDEVICE));
-    ctx->own_stream = true;
-  }
-  (void)hipGetDevice(&ctx->device);
-  if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
-          hipSuccess ||
-      ctx->n_cu < 1)
-    ctx->n_cu = 256;
   const iesh_run_desc& r = ctx->run;
+  // every argument check comes before the first device call
   if (r.n_traj < 1) return (fail(ctx, IESH_EINVAL, "n_traj must be >= 1"), bail(IESH_EINVAL));
   if (!(r.dt > 0.0)) return (fail(ctx, IESH_EINVAL, "dt must be > 0"), bail(IESH_EINVAL));
   if (!(r.kT >= 0.0)) return (fail(ctx, IESH_EINVAL, "kT must be >= 0"), bail(IESH_EINVAL));
@@ -665,6 +660,27 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     ctx->traj_class[t] = m;
     ctx->traj_local[t] = count[m]++;
   }
+  const int ndof0 = model_ndof(models[0]);
+  for (int m = 1; m < n_models; ++m)
+    if (model_ndof(models[m]) != ndof0)
+      return (fail(ctx, IESH_EINVAL, "all models of a context need the same n_dof"), bail(IESH_EINVAL));
+  if (r.exit_dof < 0 || r.exit_dof >= ndof0)
+    return (fail(ctx, IESH_EINVAL, "exit_dof out of range [0, n_dof)"), bail(IESH_EINVAL));
+  if (r.hop_filter_off != 0 && r.hop_filter_off != 1)
+    return (fail(ctx, IESH_EINVAL, "hop_filter_off must be 0 or 1"), bail(IESH_EINVAL));
+
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (!ctx->stream) {
+    // the step loop is captured into a graph, which needs a non-null stream
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
+      return (fail(ctx, IESH_EDEVICE, "stream creation failed"), bail(IESH_EDEVICE));
+    ctx->own_stream = true;
+  }
+  (void)hipGetDevice(&ctx->device);
+  if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+          hipSuccess ||
+      ctx->n_cu < 1)
+    ctx->n_cu = 256;
   int rc = dalloc(ctx, &ctx->cnt, 1);
   if (rc) return bail(rc);
   rc = dalloc(ctx, &ctx->events, (size_t)IESH_EVENT_CAP);
@@ -707,10 +723,6 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     } else {
       c.md.mass_dof[0] = d.mass;
     }
-    if (r.exit_dof < 0 || r.exit_dof >= c.md.ndof)
-      return (fail(ctx, IESH_EINVAL, "exit_dof out of range [0, n_dof)"), bail(IESH_EINVAL));
-    if (r.hop_filter_off != 0 && r.hop_filter_off != 1)
-      return (fail(ctx, IESH_EINVAL, "hop_filter_off must be 0 or 1"), bail(IESH_EINVAL));
     c.exit_dof = r.exit_dof;
     c.exact_hops = r.hop_filter_off;
     c.dt0 = r.dt;

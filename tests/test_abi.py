@@ -129,3 +129,60 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for f in cls._fields_:
             assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
+
+
+def _valid_case():
+    """A valid two-lead multi-coordinate descriptor set (plain dicts)."""
+    from workloads import get_config
+    cfg = get_config("c5")
+    e = np.repeat(np.linspace(-0.05, 0.05, 6), 2)
+    w = np.full(12, 0.1 / 12)
+    lead = np.tile(np.array([0, 1], dtype=np.int32), 6)
+    run = dict(n_traj=4, precision="fp64", dt=20.0, kT=1e-3, seed=0)
+    return cfg["model"], e, w, lead, run
+
+
+@pytest.mark.parametrize("change,message", [
+    (lambda m, e, w, l, r, n: r.update(dt=0.0), "dt must be > 0"),
+    (lambda m, e, w, l, r, n: r.update(kT=-1.0), "kT must be >= 0"),
+    (lambda m, e, w, l, r, n: r.update(n_traj=0), "n_traj"),
+    (lambda m, e, w, l, r, n: r.update(elec_substeps=65), "elec_substeps"),
+    (lambda m, e, w, l, r, n: r.update(dt_levels=3), "hop_gmax"),
+    (lambda m, e, w, l, r, n: r.update(dt_levels=31, hop_gmax=0.1), "dt_levels"),
+    (lambda m, e, w, l, r, n: r.update(bias=0.01, kT=0.0), "kT > 0"),
+    (lambda m, e, w, l, r, n: r.update(exit_dof=6), "exit_dof"),
+    (lambda m, e, w, l, r, n: r.update(hop_filter_off=2), "hop_filter_off"),
+    (lambda m, e, w, l, r, n: e.__setitem__(3, 0.2), "ascending"),
+    (lambda m, e, w, l, r, n: w.__setitem__(0, 0.0), "weights"),
+    (lambda m, e, w, l, r, n: l.__setitem__(0, 2), "lead labels"),
+    (lambda m, e, w, l, r, n: n.__setitem__(0, 13), "n_elec"),
+])
+def test_create_rejects_bad_arguments_before_any_device_call(change, message):
+    """Argument errors come back as IESH_EINVAL with their reason, on a host
+    without a GPU (iesh_create checks everything before its first device
+    call)."""
+    from paper_2212_00518_amd import _lib
+    model, e, w, lead, run = _valid_case()
+    n_elec = [6]
+    change(model, e, w, lead, run, n_elec)
+    with pytest.raises(_lib.IeshError, match=message):
+        _lib.Ensemble([_lib.model_desc(model, e, w, n_elec[0], lead)], run)
+
+
+def test_bias_needs_lead_labels_in_every_model():
+    from paper_2212_00518_amd import _lib
+    model, e, w, lead, run = _valid_case()
+    run.update(bias=0.01)
+    with pytest.raises(_lib.IeshError, match="lead labels in every model"):
+        _lib.Ensemble([_lib.model_desc(model, e, w, 6, lead), _lib.model_desc(model, e, w, 6)], run,
+                      traj_model=np.array([0, 1, 0, 1], dtype=np.int32))
+
+
+def test_models_of_a_context_need_the_same_coordinate_count():
+    from paper_2212_00518_amd import _lib
+    from workloads import get_config
+    model, e, w, lead, run = _valid_case()
+    c1 = get_config("c1")["model"]
+    with pytest.raises(_lib.IeshError, match="same n_dof"):
+        _lib.Ensemble([_lib.model_desc(model, e, w, 6, lead), _lib.model_desc(c1, e, w, 6)], run,
+                      traj_model=np.array([0, 1, 0, 1], dtype=np.int32))
