@@ -1,5 +1,7 @@
 """Discretisation of the metallic band (Appendix A).
 
+Test infrastructure only (see the package docstring).
+
 The continuum coupling integral is replaced by a sum over M states with
 energies eps_k and weights w_k; the couplings are V_k = V(eps_k) sqrt(w_k)
 (Appendix A), and with an energy-independent hybridisation Gamma the

@@ -1,5 +1,7 @@
 """Closed forms used to pin the oracle.
 
+Test infrastructure only (see the package docstring).
+
 Impurity occupation in equilibrium.  For an energy-independent
 hybridisation Gamma (Eq. hybridization) in the wide-band limit, the impurity
 spectral function is the Lorentzian A(e) = (Gamma/2pi) / ((e - h)^2 +

@@ -1,5 +1,7 @@
 """One IESH time step, trajectories and observables (Sec. II.B, II.C).
 
+Test infrastructure only (see the package docstring).
+
 Step order.  The paper integrates the nuclei with velocity Verlet and the
 orbitals with the exponential integrator of Eq. exponential_integrator but
 does not say at which nuclear geometry the propagator matrix is frozen over

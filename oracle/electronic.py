@@ -1,5 +1,7 @@
 """Electronic structure and surface hopping pieces of IESH (Sec. II.B, II.C).
 
+Test infrastructure only (see the package docstring).
+
 Conventions (ħ = 1, atomic units):
 
 * Adiabatic orbitals: columns of Q from a dense ``eigh`` of the one-electron

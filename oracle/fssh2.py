@@ -1,6 +1,8 @@
 """Independent two-state fewest-switches surface hopping (one impurity level,
 one bath level, one electron).
 
+Test infrastructure only (see the package docstring).
+
 With M = 1 and N = 1 IESH reduces to Tully's original two-state
 fewest-switches algorithm (Sec. II.B states the IESH rates are the
 fewest-switches ones).  This module implements that limit from closed forms

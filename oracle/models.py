@@ -1,5 +1,7 @@
 """Newns-Anderson models (Sec. II.A, Sec. III.B, Sec. III.C).
 
+Test infrastructure only (see the package docstring).
+
 The discrete one-electron Hamiltonian (Eq. single_electron_discrete_
 electronic_hamiltonian) in the diabatic basis {|d>, |1>, ..., |M>} is the
 (M+1) x (M+1) matrix

@@ -1,5 +1,7 @@
 """Counter-based uniform random numbers: Philox4x32-10.
 
+Test infrastructure only (see the package docstring).
+
 The generator is the one published by Salmon, Moraes, Dror and Shaw
 ("Parallel random numbers: as easy as 1, 2, 3", SC'11): a 128-bit counter
 and a 64-bit key, ten rounds of two 32x32->64 multiplications with the
