@@ -172,6 +172,7 @@ typedef struct iesh_run_desc {
 #define IESH_MAX_STATES 336   /* n = M + 1 limit of the library               */
 #define IESH_MAX_ELEC 168     /* N limit of the library                       */
 #define IESH_MAX_DOF 6        /* nuclear coordinates per trajectory            */
+#define IESH_JACOBI_MAX_N 96  /* order limit of iesh_eigh_batched              */
 
 /* Observables written per record and trajectory by iesh_run, in this order. */
 #define IESH_OBS_PD_SURF 0   /* sum_{a in s} Q[0][a]^2                         */
@@ -386,8 +387,27 @@ int iesh_adjoint_backward(iesh_ctx* ctx, const double* dloss, double* grad_out);
 /* Wait for all work on the context stream; reports asynchronous errors. */
 int iesh_sync(iesh_ctx* ctx);
 
+/* ---- dense eigen-solver ------------------------------------------------------
+   Eigen-decomposition of `batch` general dense symmetric matrices of order n
+   (1 <= n <= IESH_JACOBI_MAX_N): the fallback for a one-electron Hamiltonian
+   that is not an arrowhead (Eq. single_electron_discrete_electronic_hamiltonian
+   for H of any structure).  Cyclic two-sided Jacobi rotations, FP64, one
+   work-group per matrix with the matrix in LDS.
+     H      : batch x n x n row-major (only symmetric input is meaningful)
+     lam    : batch x n eigenvalues, ascending
+     Q      : batch x n x n row-major, column j = eigenvector of lam[j]; the
+              first component above 1e-12 of the column's largest is positive
+     sweeps : batch int32 sweeps used (-1: not converged in 60 sweeps), or NULL
+   mem_kind: IESH_MEM_HOST (the call copies, runs and synchronises) or
+   IESH_MEM_DEVICE (pointers on the current device; asynchronous on
+   hip_stream, NULL = the null stream).  Argument errors return IESH_EINVAL
+   before any device call; iesh_last_error(NULL) gives the reason. */
+int iesh_eigh_batched(const double* H, int32_t n, int32_t batch, double* lam, double* Q,
+                      int32_t* sweeps, int32_t mem_kind, void* hip_stream);
+
 /* Description of the last failure on ctx; with ctx = NULL, the reason the
-   last iesh_create on the calling thread failed.  iesh_create checks every
+   last context-free call (iesh_create, iesh_eigh_batched) on the calling
+   thread failed.  iesh_create checks every
    argument before its first device call, so argument errors (IESH_EINVAL)
    are reported without touching a GPU. */
 const char* iesh_last_error(const iesh_ctx* ctx);

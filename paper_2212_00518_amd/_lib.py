@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("IESH_LIBRARY", os.path.join(HERE, "libiesh.so"))
 
 IESH_OK = 0
+IESH_EINVAL, IESH_ENOMEM, IESH_EDEVICE, IESH_ESTATE, IESH_ENOTSUP = -1, -2, -3, -4, -5
 IESH_MODEL_HARMONIC = 0
 IESH_MODEL_MORSE_TANH = 1
 IESH_MODEL_MULTI_DOF = 2
@@ -43,7 +44,7 @@ SYMBOLS = (
     "iesh_hop_probs", "iesh_adiabatic", "iesh_traj_status", "iesh_traj_clock", "iesh_events",
     "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
     "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals", "iesh_class_info",
-    "iesh_set_step_caps", "iesh_adjoint_forward", "iesh_adjoint_backward",
+    "iesh_set_step_caps", "iesh_adjoint_forward", "iesh_adjoint_backward", "iesh_eigh_batched",
 )
 TIMERS = ("eig", "prop", "hop", "lowdin", "filter", "adj_prop", "adj_phi", "adj_eig", "adj_hop")
 
@@ -105,6 +106,7 @@ def lib():
         L.iesh_adiabatic.argtypes = [vp, C.c_int32, C.c_int32, dp, dp]
         L.iesh_traj_status.argtypes = [vp, ip]
         L.iesh_traj_clock.argtypes = [vp, dp, dp]
+        L.iesh_eigh_batched.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, vp]
         L.iesh_events.argtypes = [vp, C.POINTER(Event), C.c_int64, C.POINTER(C.c_int64)]
         L.iesh_clear_events.argtypes = [vp]
         L.iesh_query_sizes.argtypes = [vp, C.POINTER(Sizes)]
@@ -130,6 +132,28 @@ class IeshError(RuntimeError):
 
 def _ptr(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def eigh_batched(H):
+    """Eigen-decomposition of a batch of dense symmetric matrices (host
+    arrays, shape (batch, n, n) or (n, n)) on the GPU: (lam, Q, sweeps), lam
+    ascending, Q[..., :, j] the eigenvector of lam[..., j]."""
+    L = lib()
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    single = H.ndim == 2
+    if single:
+        H = H[None]
+    if H.ndim != 3 or H.shape[1] != H.shape[2]:
+        raise ValueError("H: (batch, n, n)")
+    b, n = H.shape[0], H.shape[1]
+    lam = np.zeros((b, n))
+    Q = np.zeros((b, n, n))
+    sw = np.zeros(b, dtype=np.int32)
+    rc = L.iesh_eigh_batched(_ptr(H), n, b, _ptr(lam), _ptr(Q), _ptr(sw), IESH_MEM_HOST, None)
+    if rc != IESH_OK:
+        why = L.iesh_last_error(None)
+        raise IeshError(f"iesh_eigh_batched failed ({rc}): {why.decode() if why else ''}")
+    return (lam[0], Q[0], sw[0]) if single else (lam, Q, sw)
 
 
 def discretize(kind: str, M: int, W: float, eps_f: float = 0.0, centre: float = 0.0):

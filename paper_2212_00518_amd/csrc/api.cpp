@@ -586,6 +586,58 @@ const char* iesh_last_error(const iesh_ctx* ctx) {
   return g_create_err.empty() ? "null context" : g_create_err.c_str();
 }
 
+int iesh_eigh_batched(const double* H, int32_t n, int32_t batch, double* lam, double* Q,
+                      int32_t* sweeps, int32_t mem_kind, void* hip_stream) {
+  g_create_err.clear();
+  auto bad = [](const char* why) {
+    g_create_err = why;
+    return IESH_EINVAL;
+  };
+  if (n < 1 || n > IESH_JACOBI_MAX_N) return bad("eigh: n out of range [1, IESH_JACOBI_MAX_N]");
+  if (batch < 0) return bad("eigh: batch must be >= 0");
+  if (mem_kind != IESH_MEM_HOST && mem_kind != IESH_MEM_DEVICE) return bad("eigh: unknown mem_kind");
+  if (batch == 0) return IESH_OK;
+  if (!H || !lam || !Q) return bad("eigh: H, lam and Q must be given");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  auto dev_err = [](const std::string& why) {
+    g_create_err = "eigh: " + why;
+    return IESH_EDEVICE;
+  };
+  if (mem_kind == IESH_MEM_DEVICE) {
+    if (hipError_t e = launch_jacobi(H, n, batch, lam, Q, sweeps, st); e != hipSuccess)
+      return dev_err(hipGetErrorString(e));
+    return IESH_OK;
+  }
+  // host arrays: device copies for the call
+  const size_t nm = (size_t)batch * n * n, nl = (size_t)batch * n;
+  double *dH = nullptr, *dlam = nullptr, *dQ = nullptr;
+  int32_t* dsw = nullptr;
+  auto release = [&] {
+    (void)hipFree(dH);
+    (void)hipFree(dlam);
+    (void)hipFree(dQ);
+    (void)hipFree(dsw);
+  };
+  if (hipMalloc(&dH, nm * sizeof(double)) != hipSuccess ||
+      hipMalloc(&dlam, nl * sizeof(double)) != hipSuccess ||
+      hipMalloc(&dQ, nm * sizeof(double)) != hipSuccess ||
+      (sweeps && hipMalloc(&dsw, batch * sizeof(int32_t)) != hipSuccess)) {
+    release();
+    g_create_err = "eigh: device allocation failed";
+    return IESH_ENOMEM;
+  }
+  hipError_t e = hipMemcpyAsync(dH, H, nm * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_jacobi(dH, n, batch, dlam, dQ, dsw, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(lam, dlam, nl * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(Q, dQ, nm * sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && sweeps)
+    e = hipMemcpyAsync(sweeps, dsw, batch * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  release();
+  if (e != hipSuccess) return dev_err(hipGetErrorString(e));
+  return IESH_OK;
+}
+
 int iesh_discretize(int32_t kind, int32_t M, double a, double b, double eps_f, double* eps,
                     double* w) {
   return discretize(kind, M, a, b, eps_f, eps, w);

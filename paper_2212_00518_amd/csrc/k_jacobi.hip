@@ -1,0 +1,184 @@
+// Batched eigen-decomposition of general dense symmetric matrices by cyclic
+// two-sided Jacobi rotations: the fallback for a one-electron Hamiltonian
+// that is not an arrowhead (the arrowhead case has its own secular solver).
+//
+// One work-group per matrix; the matrix A and the accumulated rotations V
+// live in LDS (order n <= IESH_JACOBI_MAX_N).  A sweep visits every index
+// pair once in m - 1 rounds of m/2 disjoint pairs (round-robin schedule over
+// m = n rounded up to even; pairs with the padding index are skipped), so
+// the rotations of a round are independent: one pass rotates the rows of
+// every pair, a second the columns of A and V.  The rotation of pair (p, q)
+// annihilates a_pq (Golub and Van Loan, symmetric Schur decomposition):
+//   tau = (a_qq - a_pp) / (2 a_pq),  t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+//   c = 1 / sqrt(1 + t^2),  s = t c,  A <- J^T A J,  V <- V J,
+// with J the identity except J_pp = J_qq = c, J_pq = s, J_qp = -s.  A pair is
+// skipped once |a_pq| <= eps sqrt(|a_pp a_qq|) (eps the FP64 unit roundoff
+// times 2; the relative-accuracy stopping rule of Demmel and Veselic) or
+// a_pq = 0; the iteration ends after a sweep without rotations (or reports
+// non-convergence after max_sweeps).
+
+#include "iesh_internal.hpp"
+
+namespace iesh {
+namespace {
+
+constexpr int kJacThreads = 256;
+
+size_t jacobi_lds(int n) {
+  const int m = n + (n & 1);
+  return sizeof(double) * (2 * (size_t)m * m + m) + sizeof(int) * (m + 4);
+}
+
+__global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict__ H, int n,
+                                                       double* __restrict__ lam,
+                                                       double* __restrict__ Q, int32_t* sweeps_out,
+                                                       int max_sweeps) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int m = n + (n & 1), half = m / 2;
+  double* A = sm;                   // [m][m]
+  double* V = A + (size_t)m * m;    // [m][m]
+  double* cs = V + (size_t)m * m;   // [half] cosines of the round
+  double* sn = cs + half;           // [half] sines
+  int* pq = reinterpret_cast<int*>(sn + half);  // [m]: p, q of each pair
+  int* flag = pq + m;               // [1]: a rotation happened in this sweep
+
+  const double* Hb = H + (size_t)b * n * n;
+  for (int idx = tid; idx < m * m; idx += kJacThreads) {
+    const int i = idx / m, j = idx - i * m;
+    A[idx] = (i < n && j < n) ? Hb[(size_t)i * n + j] : 0.0;
+    V[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+
+  int sweep = 0;
+  bool converged = false;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) flag[0] = 0;
+    __syncthreads();
+    for (int r = 0; r < m - 1; ++r) {
+      // the pairs of round r and their rotations
+      for (int k = tid; k < half; k += kJacThreads) {
+        int p, q;
+        if (k == 0) {
+          p = r;
+          q = m - 1;
+        } else {
+          p = (r + k) % (m - 1);
+          q = (r - k + (m - 1)) % (m - 1);
+        }
+        if (p > q) {
+          const int x = p;
+          p = q;
+          q = x;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[(size_t)p * m + q];
+          const double app = A[(size_t)p * m + p], aqq = A[(size_t)q * m + q];
+          if (apq != 0.0 && fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq))) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            flag[0] = 1;
+          }
+        }
+        pq[2 * k] = p;
+        pq[2 * k + 1] = q;
+        cs[k] = c;
+        sn[k] = s;
+      }
+      __syncthreads();
+      // rows p, q of every pair: rows <- J^T rows
+      for (int idx = tid; idx < half * m; idx += kJacThreads) {
+        const int k = idx / m, j = idx - k * m;
+        const double s = sn[k];
+        if (s == 0.0) continue;
+        const double c = cs[k];
+        const int p = pq[2 * k], q = pq[2 * k + 1];
+        const double ap = A[(size_t)p * m + j], aq = A[(size_t)q * m + j];
+        A[(size_t)p * m + j] = c * ap - s * aq;
+        A[(size_t)q * m + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns p, q of A and V: columns <- columns J
+      for (int idx = tid; idx < half * m; idx += kJacThreads) {
+        const int k = idx / m, j = idx - k * m;
+        const double s = sn[k];
+        if (s == 0.0) continue;
+        const double c = cs[k];
+        const int p = pq[2 * k], q = pq[2 * k + 1];
+        const double ap = A[(size_t)j * m + p], aq = A[(size_t)j * m + q];
+        A[(size_t)j * m + p] = c * ap - s * aq;
+        A[(size_t)j * m + q] = s * ap + c * aq;
+        const double vp = V[(size_t)j * m + p], vq = V[(size_t)j * m + q];
+        V[(size_t)j * m + p] = c * vp - s * vq;
+        V[(size_t)j * m + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+      // the annihilated pair is exactly zero
+      for (int k = tid; k < half; k += kJacThreads) {
+        if (sn[k] != 0.0) {
+          const int p = pq[2 * k], q = pq[2 * k + 1];
+          A[(size_t)p * m + q] = 0.0;
+          A[(size_t)q * m + p] = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = flag[0];
+    __syncthreads();
+    if (!any) {
+      converged = true;
+      break;
+    }
+  }
+
+  // ascending order (ties by index) and the phase: the first component of
+  // each eigenvector above 1e-12 of its largest is made positive
+  int* rank = pq;  // reuse: [m]
+  for (int j = tid; j < n; j += kJacThreads) {
+    const double dj = A[(size_t)j * m + j];
+    int rk = 0;
+    for (int i = 0; i < n; ++i) {
+      const double di = A[(size_t)i * m + i];
+      rk += (di < dj || (di == dj && i < j)) ? 1 : 0;
+    }
+    rank[j] = rk;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += kJacThreads) {
+    double vmax = 0.0;
+    for (int i = 0; i < n; ++i) vmax = fmax(vmax, fabs(V[(size_t)i * m + j]));
+    double sgn = 1.0;
+    for (int i = 0; i < n; ++i) {
+      const double v = V[(size_t)i * m + j];
+      if (fabs(v) > 1e-12 * vmax) {
+        sgn = v < 0.0 ? -1.0 : 1.0;
+        break;
+      }
+    }
+    const int rk = rank[j];
+    lam[(size_t)b * n + rk] = A[(size_t)j * m + j];
+    double* Qb = Q + (size_t)b * n * n;
+    for (int i = 0; i < n; ++i) Qb[(size_t)i * n + rk] = sgn * V[(size_t)i * m + j];
+  }
+  if (tid == 0 && sweeps_out) sweeps_out[b] = converged ? sweep + 1 : -1;
+}
+
+}  // namespace
+
+size_t jacobi_lds_bytes(int n) { return jacobi_lds(n); }
+
+hipError_t launch_jacobi(const double* H, int n, int batch, double* lam, double* Q, int32_t* sweeps,
+                         hipStream_t s) {
+  const size_t lds = jacobi_lds(n);
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(kJacThreads), lds, s, H, n, lam, Q, sweeps, 60);
+  return hipGetLastError();
+}
+
+}  // namespace iesh

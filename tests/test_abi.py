@@ -186,3 +186,22 @@ def test_models_of_a_context_need_the_same_coordinate_count():
     with pytest.raises(_lib.IeshError, match="same n_dof"):
         _lib.Ensemble([_lib.model_desc(model, e, w, 6, lead), _lib.model_desc(c1, e, w, 6)], run,
                       traj_model=np.array([0, 1, 0, 1], dtype=np.int32))
+
+
+@pytest.mark.parametrize("n,batch,kind,message", [
+    (0, 1, 0, "n out of range"), (97, 1, 0, "n out of range"), (4, -1, 0, "batch"),
+    (4, 1, 7, "mem_kind"),
+])
+def test_dense_eigensolver_rejects_bad_arguments_without_a_gpu(libiesh, n, batch, kind, message):
+    from paper_2212_00518_amd import _lib
+    L = _lib.lib()
+    H = np.eye(max(n, 1))
+    lam = np.zeros(max(n, 1))
+    Q = np.zeros_like(H)
+    rc = L.iesh_eigh_batched(H.ctypes.data_as(ctypes.c_void_p), n, batch,
+                             lam.ctypes.data_as(ctypes.c_void_p), Q.ctypes.data_as(ctypes.c_void_p),
+                             None, kind, None)
+    assert rc == _lib.IESH_EINVAL
+    assert message in L.iesh_last_error(None).decode()
+    # an empty batch is a no-op
+    assert L.iesh_eigh_batched(None, 4, 0, None, None, None, 0, None) == _lib.IESH_OK
