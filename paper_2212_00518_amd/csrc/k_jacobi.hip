@@ -26,7 +26,7 @@ constexpr int kJacThreads = 256;
 
 size_t jacobi_lds(int n) {
   const int m = n + (n & 1);
-  return sizeof(double) * (2 * (size_t)m * m + m) + sizeof(int) * (m + 4);
+  return sizeof(double) * (2 * (size_t)m * (m + 1) + m) + sizeof(int) * (m + 4);
 }
 
 __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict__ H, int n,
@@ -36,9 +36,10 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   extern __shared__ double sm[];
   const int b = blockIdx.x, tid = threadIdx.x;
   const int m = n + (n & 1), half = m / 2;
-  double* A = sm;                   // [m][m]
-  double* V = A + (size_t)m * m;    // [m][m]
-  double* cs = V + (size_t)m * m;   // [half] cosines of the round
+  const int ld = m + 1;             // row stride: a column walk spreads over the LDS banks
+  double* A = sm;                   // [m][ld]
+  double* V = A + (size_t)m * ld;   // [m][ld]
+  double* cs = V + (size_t)m * ld;  // [half] cosines of the round
   double* sn = cs + half;           // [half] sines
   int* pq = reinterpret_cast<int*>(sn + half);  // [m]: p, q of each pair
   int* flag = pq + m;               // [1]: a rotation happened in this sweep
@@ -46,8 +47,8 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   const double* Hb = H + (size_t)b * n * n;
   for (int idx = tid; idx < m * m; idx += kJacThreads) {
     const int i = idx / m, j = idx - i * m;
-    A[idx] = (i < n && j < n) ? Hb[(size_t)i * n + j] : 0.0;
-    V[idx] = (i == j) ? 1.0 : 0.0;
+    A[(size_t)i * ld + j] = (i < n && j < n) ? Hb[(size_t)i * n + j] : 0.0;
+    V[(size_t)i * ld + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
 
@@ -74,8 +75,8 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
         }
         double c = 1.0, s = 0.0;
         if (q < n) {
-          const double apq = A[(size_t)p * m + q];
-          const double app = A[(size_t)p * m + p], aqq = A[(size_t)q * m + q];
+          const double apq = A[(size_t)p * ld + q];
+          const double app = A[(size_t)p * ld + p], aqq = A[(size_t)q * ld + q];
           if (apq != 0.0 && fabs(apq) > 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq))) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double t = copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
@@ -97,9 +98,9 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
         if (s == 0.0) continue;
         const double c = cs[k];
         const int p = pq[2 * k], q = pq[2 * k + 1];
-        const double ap = A[(size_t)p * m + j], aq = A[(size_t)q * m + j];
-        A[(size_t)p * m + j] = c * ap - s * aq;
-        A[(size_t)q * m + j] = s * ap + c * aq;
+        const double ap = A[(size_t)p * ld + j], aq = A[(size_t)q * ld + j];
+        A[(size_t)p * ld + j] = c * ap - s * aq;
+        A[(size_t)q * ld + j] = s * ap + c * aq;
       }
       __syncthreads();
       // columns p, q of A and V: columns <- columns J
@@ -109,21 +110,13 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
         if (s == 0.0) continue;
         const double c = cs[k];
         const int p = pq[2 * k], q = pq[2 * k + 1];
-        const double ap = A[(size_t)j * m + p], aq = A[(size_t)j * m + q];
-        A[(size_t)j * m + p] = c * ap - s * aq;
-        A[(size_t)j * m + q] = s * ap + c * aq;
-        const double vp = V[(size_t)j * m + p], vq = V[(size_t)j * m + q];
-        V[(size_t)j * m + p] = c * vp - s * vq;
-        V[(size_t)j * m + q] = s * vp + c * vq;
-      }
-      __syncthreads();
-      // the annihilated pair is exactly zero
-      for (int k = tid; k < half; k += kJacThreads) {
-        if (sn[k] != 0.0) {
-          const int p = pq[2 * k], q = pq[2 * k + 1];
-          A[(size_t)p * m + q] = 0.0;
-          A[(size_t)q * m + p] = 0.0;
-        }
+        const double ap = A[(size_t)j * ld + p], aq = A[(size_t)j * ld + q];
+        // the annihilated pair (rows p and q of columns q and p) is set to zero
+        A[(size_t)j * ld + p] = (j == q) ? 0.0 : c * ap - s * aq;
+        A[(size_t)j * ld + q] = (j == p) ? 0.0 : s * ap + c * aq;
+        const double vp = V[(size_t)j * ld + p], vq = V[(size_t)j * ld + q];
+        V[(size_t)j * ld + p] = c * vp - s * vq;
+        V[(size_t)j * ld + q] = s * vp + c * vq;
       }
       __syncthreads();
     }
@@ -139,10 +132,10 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   // each eigenvector above 1e-12 of its largest is made positive
   int* rank = pq;  // reuse: [m]
   for (int j = tid; j < n; j += kJacThreads) {
-    const double dj = A[(size_t)j * m + j];
+    const double dj = A[(size_t)j * ld + j];
     int rk = 0;
     for (int i = 0; i < n; ++i) {
-      const double di = A[(size_t)i * m + i];
+      const double di = A[(size_t)i * ld + i];
       rk += (di < dj || (di == dj && i < j)) ? 1 : 0;
     }
     rank[j] = rk;
@@ -150,19 +143,19 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   __syncthreads();
   for (int j = tid; j < n; j += kJacThreads) {
     double vmax = 0.0;
-    for (int i = 0; i < n; ++i) vmax = fmax(vmax, fabs(V[(size_t)i * m + j]));
+    for (int i = 0; i < n; ++i) vmax = fmax(vmax, fabs(V[(size_t)i * ld + j]));
     double sgn = 1.0;
     for (int i = 0; i < n; ++i) {
-      const double v = V[(size_t)i * m + j];
+      const double v = V[(size_t)i * ld + j];
       if (fabs(v) > 1e-12 * vmax) {
         sgn = v < 0.0 ? -1.0 : 1.0;
         break;
       }
     }
     const int rk = rank[j];
-    lam[(size_t)b * n + rk] = A[(size_t)j * m + j];
+    lam[(size_t)b * n + rk] = A[(size_t)j * ld + j];
     double* Qb = Q + (size_t)b * n * n;
-    for (int i = 0; i < n; ++i) Qb[(size_t)i * n + rk] = sgn * V[(size_t)i * m + j];
+    for (int i = 0; i < n; ++i) Qb[(size_t)i * n + rk] = sgn * V[(size_t)i * ld + j];
   }
   if (tid == 0 && sweeps_out) sweeps_out[b] = converged ? sweep + 1 : -1;
 }
