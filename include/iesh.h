@@ -167,6 +167,10 @@ typedef struct iesh_run_desc {
                             trajectory keeps its own clock (iesh_traj_clock); the
                             hop uniforms still follow the step count           */
   double hop_gmax;       /* threshold of the adaptive step (> 0 when dt_levels > 0) */
+  int32_t eig_max_iter;  /* secular iterations per root, 0..128 (0 = 128).  A small
+                            cap is a test hook: roots that do not converge set
+                            IESH_TRAJ_NONCONV and freeze their trajectory       */
+  int32_t reserved3;
 } iesh_run_desc;
 
 #define IESH_MAX_STATES 336   /* n = M + 1 limit of the library               */

@@ -63,7 +63,8 @@ class RunDesc(C.Structure):
                 ("record_every", C.c_int32), ("exit_enabled", C.c_int32),
                 ("compact_every", C.c_int32), ("exit_x", C.c_double), ("max_steps", C.c_int64),
                 ("elec_substeps", C.c_int32), ("hop_filter_off", C.c_int32), ("bias", C.c_double),
-                ("exit_dof", C.c_int32), ("dt_levels", C.c_int32), ("hop_gmax", C.c_double)]
+                ("exit_dof", C.c_int32), ("dt_levels", C.c_int32), ("hop_gmax", C.c_double),
+                ("eig_max_iter", C.c_int32), ("reserved3", C.c_int32)]
 
 
 class Event(C.Structure):
@@ -242,6 +243,7 @@ class Ensemble:
         r.exit_dof = int(run.get("exit_dof", 0))
         r.dt_levels = int(run.get("dt_levels", 0))
         r.hop_gmax = float(run.get("hop_gmax", 0.0))
+        r.eig_max_iter = int(run.get("eig_max_iter", 0))
         self.run_desc = r
         tm = None
         if traj_model is not None:

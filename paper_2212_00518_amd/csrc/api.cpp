@@ -689,6 +689,8 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
   if (r.elec_substeps < 0 || r.elec_substeps > 64)
     return (fail(ctx, IESH_EINVAL, "elec_substeps out of range [0, 64]"), bail(IESH_EINVAL));
   if (ctx->run.elec_substeps == 0) ctx->run.elec_substeps = 1;
+  if (r.eig_max_iter < 0 || r.eig_max_iter > 128)
+    return (fail(ctx, IESH_EINVAL, "eig_max_iter out of range [0, 128]"), bail(IESH_EINVAL));
   if (r.dt_levels < 0 || r.dt_levels > 30)
     return (fail(ctx, IESH_EINVAL, "dt_levels out of range [0, 30]"), bail(IESH_EINVAL));
   if (r.dt_levels > 0 && !(r.hop_gmax > 0.0 && std::isfinite(r.hop_gmax)))
@@ -750,6 +752,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     c.md.kind = d.kind;
     c.md.M = d.n_bath;
     c.md.M_red = d.n_bath;
+    c.md.eig_iter = r.eig_max_iter > 0 ? r.eig_max_iter : 128;
     c.md.expand = nullptr;
     c.md.lead0 = nullptr;
     c.md.n = d.n_bath + 1;

@@ -42,6 +42,7 @@ struct ModelDev {
   int kind;
   int M;       // bath levels
   int M_red;   // distinct bath energies (poles of the secular function); M without repeats
+  int eig_iter;  // secular iterations allowed per root
   int n;       // M + 1
   int n_pad;   // n rounded up to 16
   int N;       // electrons

@@ -102,7 +102,7 @@ __device__ inline double quad_root_in(double a2, double a1, double a0, double al
 
 // Root j (0..M) of the secular function.  Returns 1 on convergence.
 __device__ int secular_root(int j, int M, const double* e, const double* V2, double h,
-                            double vnorm, double& tau_out, int& org_out) {
+                            double vnorm, int max_it, double& tau_out, int& org_out) {
   int o;
   double lo, hi, tau, f = 0.0, dl = 0.0, dr = 0.0, err = 0.0;
   bool have_f = false;
@@ -136,7 +136,7 @@ __device__ int secular_root(int j, int M, const double* e, const double* V2, dou
   const double eo = e[o];
   const double emh = eo - h;
   int ok = 0;
-  for (int it = 0; it < 128; ++it) {
+  for (int it = 0; it < max_it; ++it) {
     if (!have_f) secular_eval(j, M, e, V2, eo, emh, tau, f, dl, dr, err);
     have_f = false;
     if (f == 0.0 || fabs(f) <= err) {
@@ -220,7 +220,7 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
   for (int j = tid; j < n; j += kEigThreads) {
     double tau;
     int o;
-    const int ok = secular_root(j, M, L.e, L.V2, ma.h, vnorm, tau, o);
+    const int ok = secular_root(j, M, L.e, L.V2, ma.h, vnorm, md.eig_iter, tau, o);
     L.tau[j] = tau;
     L.org[j] = o;
     L.lam[j] = L.e[o] + tau;

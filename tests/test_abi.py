@@ -205,3 +205,11 @@ def test_dense_eigensolver_rejects_bad_arguments_without_a_gpu(libiesh, n, batch
     assert message in L.iesh_last_error(None).decode()
     # an empty batch is a no-op
     assert L.iesh_eigh_batched(None, 4, 0, None, None, None, 0, None) == _lib.IESH_OK
+
+
+def test_iteration_cap_is_checked():
+    from paper_2212_00518_amd import _lib
+    model, e, w, lead, run = _valid_case()
+    run.update(eig_max_iter=129)
+    with pytest.raises(_lib.IeshError, match="eig_max_iter"):
+        _lib.Ensemble([_lib.model_desc(model, e, w, 6, lead)], run)

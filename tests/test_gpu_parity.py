@@ -1043,3 +1043,73 @@ def test_biased_occupations_with_offset_lead_grids(bias):
     for t in range(T):
         ref = dyn.initial_state(m, x0[t], v0[t], 20, cfg["kT"], cfg["seed"], t, bias=bias)
         assert list(occ[t, :20]) == list(ref.s), t
+
+
+# ------------------------------------------------------------- failure states
+def test_nonconvergence_hook_freezes_every_trajectory():
+    """eig_max_iter = 1 (a host-set cap on the secular iterations): the roots
+    do not converge, every trajectory is marked NONCONV at initialisation and
+    stays frozen through later steps."""
+    from paper_2212_00518_amd import _lib
+    cfg = make_cfg("c1", M=20, N=10)
+    T = 4
+    x0, v0 = boltzmann_harmonic(T, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"], seed=3)
+    ens = ensemble(cfg, T, eig_max_iter=1)
+    ens.init_thermal(x0, v0)
+    s0 = ens.status()
+    before = ens.get_state()
+    ens.run(3)
+    after = ens.get_state()
+    s1 = ens.status()
+    ens.close()
+    assert np.all(s0 & _lib.TRAJ_NONCONV) and np.array_equal(s0, s1)
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+
+
+def test_nonfinite_input_freezes_only_that_trajectory():
+    """A NaN position and an infinite velocity: those two trajectories are
+    frozen with NONFINITE (and NONCONV from the failed solve); the others run
+    exactly as in an ensemble without the bad inputs."""
+    from paper_2212_00518_amd import _lib, unpack_C
+    cfg = make_cfg("c1", M=20, N=10)
+    m = models.from_config(cfg, M=20)
+    T = 6
+    states = random_states(m, 10, T, seed=13, xs=np.linspace(-4.0, 20.0, T), v_scale=4e-3)
+    bad = [s.copy() for s in states]
+    bad[2] = dyn.State([np.nan], bad[2].v, bad[2].C, bad[2].s)
+    bad[4] = dyn.State(bad[4].x, [np.inf], bad[4].C, bad[4].s)
+    out = []
+    for sts in (states, bad):
+        ens = ensemble(cfg, T)
+        upload(ens, sts)
+        ens.run(5)
+        out.append((ens.get_state(), ens.status(), ens.events()[0], ens.n_max, ens.N_max))
+        ens.close()
+    (g, sg, eg, n_max, N_max), (b, sb, eb, _, _) = out
+    assert sb[2] & (_lib.TRAJ_NONFINITE | _lib.TRAJ_NONCONV)
+    assert sb[4] & _lib.TRAJ_NONFINITE
+    for t in (0, 1, 3, 5):
+        assert sg[t] == 0 and sb[t] == 0
+        assert b[0][t] == g[0][t] and b[1][t] == g[1][t]
+        assert np.array_equal(unpack_C(b[2], t, m.n, 10, n_max, N_max), unpack_C(g[2], t, m.n, 10, n_max, N_max))
+        assert np.array_equal(b[3][t], g[3][t])
+    key = lambda e: (e["step"], e["traj"], e["a"], e["b"], e["accepted"])
+    assert [key(e) for e in eb if e["traj"] not in (2, 4)] == [key(e) for e in eg if e["traj"] not in (2, 4)]
+
+
+def test_frustrated_hops_match_the_oracle():
+    """Small velocities and mixed orbitals: selected upward hops that the
+    kinetic energy cannot pay for are frustrated (velocity unchanged), event
+    for event as in the oracle."""
+    cfg = make_cfg("c1", M=20, N=10)
+    m = models.from_config(cfg, M=20)
+    T = 8
+    states = random_states(m, 10, T, seed=5, xs=np.linspace(-4.0, 20.0, T), v_scale=1e-3)
+    ens = ensemble(cfg, T)
+    compared, hops = _steps_vs_oracle(m, ens, states, 40, cfg["dt"], cfg["seed"], 1e-10, 10)
+    evs, _ = ens.events()
+    ens.close()
+    frustrated = sum(1 for e in evs if not e["accepted"])
+    print("compared", compared, "accepted", hops, "frustrated", frustrated, flush=True)
+    assert compared >= T - 1 and frustrated >= 2
