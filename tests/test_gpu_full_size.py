@@ -148,3 +148,55 @@ def test_scattering_16384_trajectories_in_four_bath_classes():
             compared += _compare(m, st0, M // 2, steps, cfg["dt"], cfg["seed"], int(t), got, "mixed",
                                  n_max, N_max)
     assert compared >= 6
+
+
+def test_double_well_m20_all_128_trajectories_1000_steps():
+    """The small double-well workload in full: 128 Boltzmann/Fermi-sampled
+    trajectories x 1000 graph-replayed FP64 steps, every trajectory against
+    the oracle's own run (one process per trajectory on the host cores).
+    Over 1000 steps the two propagators' rounding drifts apart, so positions,
+    velocities and orbitals are compared at 1e-8."""
+    import multiprocessing as mp
+    import os
+    from paper_2212_00518_amd import from_config, unpack_C
+    cfg = get_config("c1")
+    T, steps, N = cfg["n_traj"], cfg["n_steps"], cfg["n_elec"]
+    x0, v0 = boltzmann_harmonic(T, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"],
+                                seed=cfg["seed"], kT_factor=cfg.get("sample_kT_factor", 1.0))
+    ens = from_config(cfg, n_traj=T, precision="fp64")
+    ens.init_thermal(x0, v0)
+    ens.run(steps)
+    x, v, Cf, occ = ens.get_state()
+    evs, _ = ens.events()
+    status = ens.status()
+    n_max, N_max = ens.n_max, ens.N_max
+    ens.close()
+    assert np.all(status == 0)
+    m = models.from_config(cfg)
+    starts = [dyn.initial_state(m, x0[t], v0[t], N, cfg["kT"], cfg["seed"], t) for t in range(T)]
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
+    os.environ["OMP_NUM_THREADS"] = os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    try:
+        with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+            refs = pool.starmap(dyn.run, [(m, starts[t], cfg["dt"], steps, cfg["seed"], t)
+                                          for t in range(T)])
+    finally:
+        for k, val in saved.items():
+            if val is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = val
+    compared = 0
+    for t, (ref, ref_ev, _) in enumerate(refs):
+        if any(e["margin"] < 1e-7 * max(e["g_total"], 1e-300) for e in ref_ev):
+            continue
+        mine = [e for e in evs if e["traj"] == t]
+        assert [(e["step"], e["a"], e["b"], e["accepted"]) for e in mine] == \
+               [(e["step"], e["a"], e["b"], e["accepted"]) for e in ref_ev], t
+        assert abs(x[t] - ref.x[0]) <= 1e-8 * max(1.0, abs(ref.x[0])), t
+        assert abs(v[t] - ref.v[0]) <= 1e-8 * max(1e-3, abs(ref.v[0])), t
+        assert np.max(np.abs(unpack_C(Cf, t, m.n, N, n_max, N_max) - ref.C)) <= 1e-8, t
+        assert list(occ[t, :N]) == list(ref.s), t
+        compared += 1
+    print("compared", compared, "of", T, flush=True)
+    assert compared >= T - 2

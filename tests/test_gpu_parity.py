@@ -66,6 +66,10 @@ def upload(ens, states):
 # --------------------------------------------------------------------- eigen
 @pytest.mark.parametrize("name,M,xs", [
     ("c1", 20, np.linspace(-12, 30, 8)),
+    ("c1", 2, np.linspace(-5, 25, 4)),
+    ("c1", 3, np.linspace(-5, 25, 4)),
+    ("c1", 64, np.linspace(-5, 25, 4)),
+    ("c1", 65, np.linspace(-5, 25, 4)),
     ("c2", 200, np.linspace(-10, 25, 6)),
     ("c2gl", 200, np.linspace(-10, 25, 6)),
     ("c1", 1, np.linspace(-5, 25, 4)),
