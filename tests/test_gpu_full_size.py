@@ -150,17 +150,19 @@ def test_scattering_16384_trajectories_in_four_bath_classes():
     assert compared >= 6
 
 
-def test_double_well_m20_all_128_trajectories_1000_steps():
-    """The small double-well workload in full: 128 Boltzmann/Fermi-sampled
-    trajectories x 1000 graph-replayed FP64 steps, every trajectory against
-    the oracle's own run (one process per trajectory on the host cores).
-    Over 1000 steps the two propagators' rounding drifts apart, so positions,
-    velocities and orbitals are compared at 1e-8."""
+@pytest.mark.parametrize("name,T,steps", [("c1", 128, 1000), ("c2", 16, 300)])
+def test_double_well_trajectories_against_the_oracle(name, T, steps):
+    """Whole trajectories: the small double-well workload in full (128
+    Boltzmann/Fermi-sampled trajectories x 1000 graph-replayed FP64 steps)
+    and the first 16 trajectories of the M = 200 workload over 300 steps;
+    every trajectory against the oracle's own run (one process per trajectory
+    on the host cores).  Over hundreds of steps the two propagators' rounding
+    drifts apart, so positions, velocities and orbitals are compared at 1e-8."""
     import multiprocessing as mp
     import os
     from paper_2212_00518_amd import from_config, unpack_C
-    cfg = get_config("c1")
-    T, steps, N = cfg["n_traj"], cfg["n_steps"], cfg["n_elec"]
+    cfg = get_config(name)
+    N = cfg["n_elec"]
     x0, v0 = boltzmann_harmonic(T, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"],
                                 seed=cfg["seed"], kT_factor=cfg.get("sample_kT_factor", 1.0))
     ens = from_config(cfg, n_traj=T, precision="fp64")
