@@ -509,31 +509,36 @@ def peak_probe():
         out[name + "_batched_208x208x200_x4096"] = {
             "ms": round(ms, 3), "tflops": round(2.0 * bt * npad * npad * cols / (ms * 1e-3) / 1e12, 2)}
         del a, b
-    # the dense Jacobi eigen-solver: 4096 random symmetric matrices of order 96
+    # the dense Jacobi eigen-solver on random symmetric matrices: order 96
+    # (in LDS) and order 201 (the double-well size, in a device workspace)
     import ctypes
     import numpy as np
     from paper_2212_00518_amd import _lib
     rs = np.random.default_rng(0)
-    bt, n = 4096, 96
-    A = rs.normal(size=(bt, n, n))
-    dH = torch.from_numpy(0.5 * (A + np.transpose(A, (0, 2, 1)))).cuda()
-    dlam = torch.zeros((bt, n), dtype=torch.float64, device="cuda")
-    dQ = torch.zeros((bt, n, n), dtype=torch.float64, device="cuda")
-    dsw = torch.zeros(bt, dtype=torch.int32, device="cuda")
     L = _lib.lib()
-    args = (ctypes.c_void_p(dH.data_ptr()), n, bt, ctypes.c_void_p(dlam.data_ptr()),
-            ctypes.c_void_p(dQ.data_ptr()), ctypes.c_void_p(dsw.data_ptr()), _lib.IESH_MEM_DEVICE, None)
-    L.iesh_eigh_batched(*args)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    L.iesh_eigh_batched(*args)
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0)
-    sweeps = float(dsw.float().mean())
-    # 9 m^3 flops per sweep (rows and columns of A and V for m(m-1)/2 rotations)
-    out["jacobi_eigh_96_x4096"] = {"ms": round(ms, 3), "matrices_per_s": round(bt / (ms * 1e-3), 1),
-                                   "mean_sweeps": round(sweeps, 2),
-                                   "tflops": round(9.0 * n ** 3 * sweeps * bt / (ms * 1e-3) / 1e12, 3)}
+    for bt, n in ((4096, 96), (1024, 201)):
+        A = rs.normal(size=(bt, n, n))
+        dH = torch.from_numpy(0.5 * (A + np.transpose(A, (0, 2, 1)))).cuda()
+        del A
+        dlam = torch.zeros((bt, n), dtype=torch.float64, device="cuda")
+        dQ = torch.zeros((bt, n, n), dtype=torch.float64, device="cuda")
+        dsw = torch.zeros(bt, dtype=torch.int32, device="cuda")
+        args = (ctypes.c_void_p(dH.data_ptr()), n, bt, ctypes.c_void_p(dlam.data_ptr()),
+                ctypes.c_void_p(dQ.data_ptr()), ctypes.c_void_p(dsw.data_ptr()), _lib.IESH_MEM_DEVICE,
+                None)
+        L.iesh_eigh_batched(*args)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.iesh_eigh_batched(*args)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        sweeps = float(dsw.float().mean())
+        # 9 m^3 flops per sweep (rows and columns of A and V for m(m-1)/2 rotations)
+        out[f"jacobi_eigh_{n}_x{bt}"] = {
+            "ms": round(ms, 3), "matrices_per_s": round(bt / (ms * 1e-3), 1),
+            "mean_sweeps": round(sweeps, 2),
+            "tflops": round(9.0 * n ** 3 * sweeps * bt / (ms * 1e-3) / 1e12, 3)}
+        del dH, dlam, dQ, dsw
     print(json.dumps({"gemm_peak_probe": out, "published_peak_tflops": PEAK_TFLOPS}), flush=True)
 
 

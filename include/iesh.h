@@ -176,7 +176,8 @@ typedef struct iesh_run_desc {
 #define IESH_MAX_STATES 336   /* n = M + 1 limit of the library               */
 #define IESH_MAX_ELEC 168     /* N limit of the library                       */
 #define IESH_MAX_DOF 6        /* nuclear coordinates per trajectory            */
-#define IESH_JACOBI_MAX_N 96  /* order limit of iesh_eigh_batched              */
+#define IESH_JACOBI_MAX_N IESH_MAX_STATES  /* order limit of iesh_eigh_batched */
+#define IESH_JACOBI_LDS_N 96  /* orders up to this keep the matrix in LDS      */
 
 /* Observables written per record and trajectory by iesh_run, in this order. */
 #define IESH_OBS_PD_SURF 0   /* sum_{a in s} Q[0][a]^2                         */
@@ -396,7 +397,9 @@ int iesh_sync(iesh_ctx* ctx);
    (1 <= n <= IESH_JACOBI_MAX_N): the fallback for a one-electron Hamiltonian
    that is not an arrowhead (Eq. single_electron_discrete_electronic_hamiltonian
    for H of any structure).  Cyclic two-sided Jacobi rotations, FP64, one
-   work-group per matrix with the matrix in LDS.
+   work-group per matrix with the matrix in LDS up to IESH_JACOBI_LDS_N, in a
+   device workspace beyond (2 m (m + 1) doubles per matrix, m = n rounded up to
+   even; the call allocates it, waits for the kernel and frees it).
      H      : batch x n x n row-major (only symmetric input is meaningful)
      lam    : batch x n eigenvalues, ascending
      Q      : batch x n x n row-major, column j = eigenvector of lam[j]; the

@@ -603,9 +603,18 @@ int iesh_eigh_batched(const double* H, int32_t n, int32_t batch, double* lam, do
     g_create_err = "eigh: " + why;
     return IESH_EDEVICE;
   };
+  // global workspace for orders beyond the LDS limit
+  const size_t nwork = jacobi_work_elems(n, batch);
+  double* work = nullptr;
+  if (nwork && hipMalloc(&work, nwork * sizeof(double)) != hipSuccess) {
+    g_create_err = "eigh: device allocation failed";
+    return IESH_ENOMEM;
+  }
   if (mem_kind == IESH_MEM_DEVICE) {
-    if (hipError_t e = launch_jacobi(H, n, batch, lam, Q, sweeps, st); e != hipSuccess)
-      return dev_err(hipGetErrorString(e));
+    hipError_t e = launch_jacobi(H, n, batch, lam, Q, sweeps, work, st);
+    if (e == hipSuccess && work) e = hipStreamSynchronize(st);
+    (void)hipFree(work);
+    if (e != hipSuccess) return dev_err(hipGetErrorString(e));
     return IESH_OK;
   }
   // host arrays: device copies for the call
@@ -617,6 +626,7 @@ int iesh_eigh_batched(const double* H, int32_t n, int32_t batch, double* lam, do
     (void)hipFree(dlam);
     (void)hipFree(dQ);
     (void)hipFree(dsw);
+    (void)hipFree(work);
   };
   if (hipMalloc(&dH, nm * sizeof(double)) != hipSuccess ||
       hipMalloc(&dlam, nl * sizeof(double)) != hipSuccess ||
@@ -627,7 +637,7 @@ int iesh_eigh_batched(const double* H, int32_t n, int32_t batch, double* lam, do
     return IESH_ENOMEM;
   }
   hipError_t e = hipMemcpyAsync(dH, H, nm * sizeof(double), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = launch_jacobi(dH, n, batch, dlam, dQ, dsw, st);
+  if (e == hipSuccess) e = launch_jacobi(dH, n, batch, dlam, dQ, dsw, work, st);
   if (e == hipSuccess) e = hipMemcpyAsync(lam, dlam, nl * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipMemcpyAsync(Q, dQ, nm * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && sweeps)

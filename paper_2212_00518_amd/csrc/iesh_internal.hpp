@@ -277,9 +277,9 @@ hipError_t launch_eig_query(const ClassDev& c, int t0, int nt, hipStream_t s);
 hipError_t launch_init_thermal(const ClassDev& c, double kT, double bias, uint64_t seed,
                                hipStream_t s);
 // dense symmetric eigen-decomposition (k_jacobi.hip)
-size_t jacobi_lds_bytes(int n);
+size_t jacobi_work_elems(int n, int batch);  // doubles of global workspace (0: all in LDS)
 hipError_t launch_jacobi(const double* H, int n, int batch, double* lam, double* Q, int32_t* sweeps,
-                         hipStream_t s);
+                         double* work, hipStream_t s);
 hipError_t launch_forces(const ClassDev& c, hipStream_t s);
 hipError_t launch_prop(const ClassDev& c, int precision, hipStream_t s);
 hipError_t launch_prop_taps(const ClassDev& c, int mode, double* taps, int tap_k, hipStream_t s);

@@ -3,7 +3,8 @@
 // that is not an arrowhead (the arrowhead case has its own secular solver).
 //
 // One work-group per matrix; the matrix A and the accumulated rotations V
-// live in LDS (order n <= IESH_JACOBI_MAX_N).  A sweep visits every index
+// live in LDS for orders up to IESH_JACOBI_LDS_N, beyond that in a global
+// workspace (same code, generic pointers).  A sweep visits every index
 // pair once in m - 1 rounds of m/2 disjoint pairs (round-robin schedule over
 // m = n rounded up to even; pairs with the padding index are skipped), so
 // the rotations of a round are independent: one pass rotates the rows of
@@ -24,22 +25,24 @@ namespace {
 
 constexpr int kJacThreads = 256;
 
-size_t jacobi_lds(int n) {
+// LDS bytes: A and V (when in LDS), the rotations of a round and the pairs.
+size_t jacobi_lds(int n, bool in_lds) {
   const int m = n + (n & 1);
-  return sizeof(double) * (2 * (size_t)m * (m + 1) + m) + sizeof(int) * (m + 4);
+  return sizeof(double) * ((in_lds ? 2 * (size_t)m * (m + 1) : 0) + m) + sizeof(int) * (m + 4);
 }
 
+template <bool kLds>
 __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict__ H, int n,
                                                        double* __restrict__ lam,
                                                        double* __restrict__ Q, int32_t* sweeps_out,
-                                                       int max_sweeps) {
+                                                       int max_sweeps, double* work) {
   extern __shared__ double sm[];
   const int b = blockIdx.x, tid = threadIdx.x;
   const int m = n + (n & 1), half = m / 2;
   const int ld = m + 1;             // row stride: a column walk spreads over the LDS banks
-  double* A = sm;                   // [m][ld]
+  double* A = kLds ? sm : work + (size_t)b * 2 * m * ld;  // [m][ld]
   double* V = A + (size_t)m * ld;   // [m][ld]
-  double* cs = V + (size_t)m * ld;  // [half] cosines of the round
+  double* cs = kLds ? V + (size_t)m * ld : sm;  // [half] cosines of the round
   double* sn = cs + half;           // [half] sines
   int* pq = reinterpret_cast<int*>(sn + half);  // [m]: p, q of each pair
   int* flag = pq + m;               // [1]: a rotation happened in this sweep
@@ -162,15 +165,25 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
 
 }  // namespace
 
-size_t jacobi_lds_bytes(int n) { return jacobi_lds(n); }
+size_t jacobi_work_elems(int n, int batch) {
+  if (n <= IESH_JACOBI_LDS_N) return 0;
+  const size_t m = n + (n & 1);
+  return (size_t)batch * 2 * m * (m + 1);
+}
 
 hipError_t launch_jacobi(const double* H, int n, int batch, double* lam, double* Q, int32_t* sweeps,
-                         hipStream_t s) {
-  const size_t lds = jacobi_lds(n);
-  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+                         double* work, hipStream_t s) {
+  const bool in_lds = n <= IESH_JACOBI_LDS_N;
+  const size_t lds = jacobi_lds(n, in_lds);
+  const void* fn = in_lds ? (const void*)k_jacobi<true> : (const void*)k_jacobi<false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_jacobi, dim3(batch), dim3(kJacThreads), lds, s, H, n, lam, Q, sweeps, 60);
+  if (in_lds)
+    hipLaunchKernelGGL(k_jacobi<true>, dim3(batch), dim3(kJacThreads), lds, s, H, n, lam, Q, sweeps, 60,
+                       work);
+  else
+    hipLaunchKernelGGL(k_jacobi<false>, dim3(batch), dim3(kJacThreads), lds, s, H, n, lam, Q, sweeps, 60,
+                       work);
   return hipGetLastError();
 }
 

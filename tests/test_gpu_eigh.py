@@ -46,8 +46,10 @@ def _check_decomposition(H, lam, Q):
     assert np.max(np.abs(Q.T @ Q - np.eye(len(lam)))) <= 1e-13 * max(1, np.sqrt(len(lam)))
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 16, 33, 64, 95, 96])
+@pytest.mark.parametrize("n", [1, 2, 3, 16, 33, 64, 95, 96, 97, 150, 201, 336])
 def test_random_symmetric_matrices(n):
+    """Orders up to 96 keep the matrix in LDS, larger ones (up to the library
+    limit 336) work in a device workspace."""
     from paper_2212_00518_amd import eigh_batched
     rs = np.random.default_rng(n)
     A = rs.normal(size=(5, n, n))
@@ -59,7 +61,7 @@ def test_random_symmetric_matrices(n):
         _check_decomposition(H[b], lam[b], Q[b])
 
 
-@pytest.mark.parametrize("n", [8, 40, 96])
+@pytest.mark.parametrize("n", [8, 40, 96, 150])
 def test_eigenvectors_of_separated_spectra(n):
     """H = U diag(mu) U^T with gaps of at least 0.02 between the mu: the
     eigenvectors are determined up to sign and equal U's columns."""
@@ -91,7 +93,8 @@ def test_degenerate_spectra():
     _check_decomposition(0.5 * (H + H.T), lam, Q)
 
 
-@pytest.mark.parametrize("name,M,leads", [("c1", 20, 1), ("c1", 60, 1), ("c5", 40, 2), ("c5", 94, 2)])
+@pytest.mark.parametrize("name,M,leads", [("c1", 20, 1), ("c1", 60, 1), ("c5", 40, 2), ("c5", 94, 2),
+                                           ("c2", 200, 1), ("c5", 256, 2)])
 def test_newns_anderson_matrices_agree_with_the_arrowhead_solver(name, M, leads):
     """Dense Jacobi on H(x) of the double-well and the two-lead models: the
     eigenvalues equal the secular solver's (iesh_adiabatic) and the oracle's,

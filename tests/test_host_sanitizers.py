@@ -124,7 +124,7 @@ int main() {
   // the dense eigen-solver's argument checks
   double H[4] = {1, 0, 0, 1}, lam[2], Q[4];
   EXPECT(iesh_eigh_batched(H, 0, 1, lam, Q, nullptr, IESH_MEM_HOST, nullptr) == IESH_EINVAL);
-  EXPECT(iesh_eigh_batched(H, 200, 1, lam, Q, nullptr, IESH_MEM_HOST, nullptr) == IESH_EINVAL);
+  EXPECT(iesh_eigh_batched(H, 337, 1, lam, Q, nullptr, IESH_MEM_HOST, nullptr) == IESH_EINVAL);
   EXPECT(iesh_eigh_batched(H, 2, -1, lam, Q, nullptr, IESH_MEM_HOST, nullptr) == IESH_EINVAL);
   EXPECT(iesh_eigh_batched(H, 2, 1, lam, Q, nullptr, 9, nullptr) == IESH_EINVAL);
   EXPECT(iesh_eigh_batched(nullptr, 2, 0, nullptr, nullptr, nullptr, IESH_MEM_HOST, nullptr) == IESH_OK);
