@@ -653,6 +653,8 @@ def main():
                     help="c5: one bias V (default: the sweep 0, 0.01, 0.02)")
     ap.add_argument("--substeps", type=int, default=1,
                     help="electronic sub-steps per nuclear step (default 1)")
+    ap.add_argument("--error-steps", type=int, default=500,
+                    help="length of the mixed-vs-FP64 comparison (64 trajectories)")
     ap.add_argument("--dt-levels", type=int, default=0,
                     help="adaptive step: halvings allowed (0: fixed step)")
     ap.add_argument("--hop-gmax", type=float, default=0.0,
@@ -757,7 +759,7 @@ def main():
                         "exact_hop_fraction": round(f["exact_hop_fraction"], 4)}
         line["mixed_over_fp64"] = round(r["value"] / f["value"], 3)
     if not a.no_error and "mixed" in res and "fp64" in res:
-        line["mixed_error"] = mixed_vs_fp64(cfg)
+        line["mixed_error"] = mixed_vs_fp64(cfg, steps=a.error_steps)
     if not a.no_adjoint:
         # the adjoint workload's ms/step on a 200-step prefix of its paths
         adj = adjoint_bench(argparse.Namespace(n_traj=None), n_steps=200, report=False)
