@@ -37,7 +37,6 @@ namespace {
 
 constexpr int kPropWaves = 8;
 constexpr int kPropThreads = kPropWaves * 64;
-constexpr int kDepth = 2;  // k-blocks of A operands in flight per wave (the k-block count is a multiple)
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -48,6 +47,10 @@ struct PropCfg;
 template <>
 struct PropCfg<double> {
   typedef v4d acc_t;
+  // k-blocks of A operands in flight per wave (the k-block count is a
+  // multiple); two suffice for the 64-cycle FP64 products and keep the
+  // widest register tier free of spills
+  static constexpr int kDepth = 2;
   static constexpr int kMaxColTiles = 3;
   static constexpr int kMaxPairs = 6;  // output tiles per wave (the slab width is capped to fit)
   __device__ static inline acc_t mma(double a, double b, acc_t c) {
@@ -62,6 +65,7 @@ struct PropCfg<double> {
 template <>
 struct PropCfg<float> {
   typedef v4f acc_t;
+  static constexpr int kDepth = 4;  // two-tile waves; wider ones use 2
   static constexpr int kMaxColTiles = 5;
   static constexpr int kMaxPairs = 9;  // output tiles per wave (the slab width is capped to fit)
   __device__ static inline acc_t mma(float a, float b, acc_t c) {
@@ -128,6 +132,8 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int t0, int tid) {
   typedef PropCfg<T> Cfg;
   typedef typename Cfg::acc_t acc_t;
   constexpr int NQ1 = NQ > 0 ? NQ : 1;
+  // ring depth: the deeper FP32 ring only where its registers cost no occupancy
+  constexpr int kDepth = (NQ <= 2) ? Cfg::kDepth : 2;
   const int lane = tid & 63;
   const int lrow = lane & 15;  // output column within a tile / A row
   const int lk = lane >> 4;    // k index within a block / output row group
@@ -151,15 +157,31 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int t0, int tid) {
         Xq[q][r] = s.Cg[((size_t)o * s.n_pad + prow[q] * 16 + Cfg::out_row(lk, r)) * 2 + (is_re ? 0 : 1)];
     }
   }
-  // A operands through a buffer resource over this trajectory's B: the lane
-  // offset is the only per-lane address, the block offset is scalar.
+  // A operands through a buffer resource over this trajectory's B: the
+  // per-tile offset (lane and row tile) is a register fixed for the whole
+  // loop, the k-block offset is one scalar shared by the wave's tiles.
   const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
       (void*)s.Bt, (short)0, (int)(sizeof(T) * s.n_pad * s.n_pad), 0x00020000);
-  const unsigned voff = lane * sizeof(T);
   const unsigned kb_bytes = s.RT * 64 * sizeof(T);
-  unsigned roff[NQ1];
+  unsigned voff[NQ1];
 #pragma unroll
-  for (int q = 0; q < NQ1; ++q) roff[q] = __builtin_amdgcn_readfirstlane(prow[q] * 64 * (int)sizeof(T));
+  for (int q = 0; q < NQ1; ++q) voff[q] = (unsigned)(lane + prow[q] * 64) * sizeof(T);
+
+  // Y = B b_{k+1}: A fragments from memory through a ring of kDepth k-blocks
+  // in registers.  B is the same in every term, so the ring wraps around: the
+  // loads issued during the last k-blocks of a term fetch the first k-blocks
+  // of the next, and no term starts or ends waiting for memory.
+  T a[kDepth][NQ1];
+  // issue order = order of use, so the waits at the loop head stay partial
+#pragma unroll
+  for (int d = 0; d < kDepth; ++d)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      a[d][q] = load_frag<T>(rsrc, voff[q], d * kb_bytes);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  const unsigned atotal = (unsigned)s.KB * kb_bytes;
+  unsigned aoff = (kDepth * kb_bytes) % atotal;
 
   // Clenshaw: k = K-1 .. 0 produces b_k.  Forward recurrence: k = K-1 .. 1
   // produces t_{K-k} (the loop index only sets the buffer parity).
@@ -172,35 +194,35 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int t0, int tid) {
     const T* b1buf = (k & 1) ? s.X0 : s.X1;
     T* b2buf = (k & 1) ? s.X1 : s.X0;  // holds b_{k+2}, receives b_k
 
-    // Y = B b_{k+1}: A fragments from memory through a ring of kDepth
-    // k-blocks in registers, B operands from LDS one k-block ahead.  Indices
-    // past the last k-block are clamped (harmless reloads), so the loop body
-    // has no branches.
-    T a[kDepth][NQ1];
+    // B operands from LDS one k-block ahead; the index past the last k-block
+    // is clamped (a harmless reread), so the loop body has no branches.
     T xv[2][NQ1];
-    // issue order = order of use, so the waits at the loop head stay partial
-#pragma unroll
-    for (int d = 0; d < kDepth; ++d)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        a[d][q] = load_frag<T>(rsrc, voff, d * kb_bytes + roff[q]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) xv[0][q] = b1buf[lk * s.ldx + pcol[q] * 16 + lrow];
+    // B operands likewise: a per-tile LDS address plus a scalar k-block
+    // offset, one block ahead of the loop index.
+    const T* xq[NQ1];
+#pragma unroll
+    for (int q = 0; q < NQ1; ++q) xq[q] = b1buf + lk * s.ldx + pcol[q] * 16 + lrow;
+    const unsigned xstep = 4u * s.ldx * sizeof(T), xlast = (unsigned)(s.KB - 1) * xstep;
+    unsigned xoff = min(xstep, xlast);
     for (int kb0 = 0; kb0 < s.KB; kb0 += kDepth) {
 #pragma unroll
       for (int d = 0; d < kDepth; ++d) {
-        const int kb = kb0 + d;
-        const int kx = min(kb + 1, s.KB - 1);
-        const T* xrow = b1buf + (kx * 4 + lk) * s.ldx + lrow;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) xv[(d + 1) & 1][q] = xrow[pcol[q] * 16];
+        for (int q = 0; q < NQ; ++q)
+          xv[(d + 1) & 1][q] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(xq[q]) + xoff);
+        xoff = min(xoff + xstep, xlast);
+        // the scheduling barriers keep the LDS reads of block kb + 1 ahead of
+        // the products of block kb (left alone, the scheduler sinks them to
+        // their use and each block waits a full LDS round trip)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) Y[q] = Cfg::mma(a[d][q], xv[d & 1][q], Y[q]);
-        const unsigned kn = (unsigned)min(kb + kDepth, s.KB - 1) * kb_bytes;
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) a[d][q] = load_frag<T>(rsrc, voff, kn + roff[q]);
+        for (int q = 0; q < NQ; ++q) a[d][q] = load_frag<T>(rsrc, voff[q], aoff);
+        aoff = (aoff + kb_bytes == atotal) ? 0u : aoff + kb_bytes;
       }
     }
 
@@ -264,7 +286,7 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c, T* taps, int 
   s.RT = s.n_pad >> 4;
   // k-blocks of the product: rows past n of B and of the slab are zero, so
   // the sum stops at ceil(n / 4) blocks, rounded up to the prefetch ring
-  s.KB = ((((md.n + 3) >> 2) + kDepth - 1) / kDepth) * kDepth;
+  s.KB = ((((md.n + 3) >> 2) + Cfg::kDepth - 1) / Cfg::kDepth) * Cfg::kDepth;
   const int tiles_total = (s.N + 7) >> 3;
   const int base = tiles_total / c.n_slabs, rem = tiles_total % c.n_slabs;
   s.tile0 = slab * base + (slab < rem ? slab : rem);
@@ -364,11 +386,11 @@ template <typename T>
 struct Tiers;
 template <>
 struct Tiers<double> {
-  static constexpr int q[3] = {2, 4, 6};
+  static constexpr int q[4] = {2, 3, 4, 6};
 };
 template <>
 struct Tiers<float> {
-  static constexpr int q[3] = {3, 6, 9};
+  static constexpr int q[4] = {2, 3, 6, 9};
 };
 
 template <typename T, int kMode>
@@ -376,7 +398,8 @@ const void* prop_fn(int tier) {
   switch (tier) {
     case 0: return (const void*)k_prop<T, kMode, Tiers<T>::q[0]>;
     case 1: return (const void*)k_prop<T, kMode, Tiers<T>::q[1]>;
-    default: return (const void*)k_prop<T, kMode, Tiers<T>::q[2]>;
+    case 2: return (const void*)k_prop<T, kMode, Tiers<T>::q[2]>;
+    default: return (const void*)k_prop<T, kMode, Tiers<T>::q[3]>;
   }
 }
 
@@ -384,7 +407,7 @@ template <typename T>
 int prop_tier(const ClassDev& c) {
   const int q = ((c.md.n_pad / 16) * c.nct_max + kPropWaves - 1) / kPropWaves;
   int tier = 0;
-  while (tier < 2 && Tiers<T>::q[tier] < q) ++tier;
+  while (tier < 3 && Tiers<T>::q[tier] < q) ++tier;
   return tier;
 }
 
@@ -400,8 +423,12 @@ hipError_t launch_prop_t(const ClassDev& c, dim3 grid, size_t lds, hipStream_t s
       hipLaunchKernelGGL((k_prop<T, kMode, Tiers<T>::q[1]>), grid, dim3(kPropThreads), lds, s, c, taps,
                          tap_k);
       break;
-    default:
+    case 2:
       hipLaunchKernelGGL((k_prop<T, kMode, Tiers<T>::q[2]>), grid, dim3(kPropThreads), lds, s, c, taps,
+                         tap_k);
+      break;
+    default:
+      hipLaunchKernelGGL((k_prop<T, kMode, Tiers<T>::q[3]>), grid, dim3(kPropThreads), lds, s, c, taps,
                          tap_k);
       break;
   }
@@ -426,7 +453,7 @@ size_t prop_lds_bytes(const ClassDev& c, int precision) {
 hipError_t prop_prepare(const ClassDev& c, int precision) {
   const size_t lds = prop_lds_bytes(c, precision);
   if (lds <= 64 * 1024) return hipSuccess;
-  for (int tier = 0; tier < 3; ++tier) {
+  for (int tier = 0; tier < 4; ++tier) {
     const void* fns[3] = {nullptr, nullptr, nullptr};
     if (precision == IESH_FP64) {
       fns[0] = prop_fn<double, kPropagate>(tier);
