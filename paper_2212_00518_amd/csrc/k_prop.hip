@@ -88,6 +88,19 @@ __device__ inline float load_frag<float>(__amdgpu_buffer_rsrc_t r, unsigned voff
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
+// Value of lane l ^ 8 (the other half of the real/imaginary pair): within a
+// row of 16 lanes that is a rotation by 8, one DPP register move (row_ror:8)
+// instead of a permute through the LDS crossbar.
+__device__ inline float swap8(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x128, 0xf, 0xf, false));
+}
+__device__ inline double swap8(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, 0x128, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x128, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 // Row stride (elements) of the LDS slab: 16 nct, plus 16 when nct is even, so
 // the stride is 16 mod 32 elements.  The rows of one 16x16x4 B operand then
 // start 32 (FP64) or 16 (FP32) four-byte words apart modulo 64 and a read
@@ -236,11 +249,11 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int t0, int tid) {
       for (int r = 0; r < 4; ++r) {
         const int row = prow[q] * 16 + Cfg::out_row(lk, r);
         const T x = Xq[q][r];
-        const T xp = __shfl_xor(x, 8);
+        const T xp = swap8(x);
         const T cx = is_re ? (cr * x - ci * xp) : (cr * x + ci * xp);
         const int e = row * s.ldx + pcol[q] * 16 + lrow;
         const T b1 = b1buf[e];
-        const T yp = __shfl_xor(Y[q][r], 8);
+        const T yp = swap8(Y[q][r]);
         const T atb = s.lam[row] * b1 + (is_re ? yp : -yp);
         if (kMode == kForwardTaps) {
           // t_{j+1} = 2 At t_j - t_{j-1} (t_1 = At t_0) replaces t_{j-1}
