@@ -175,6 +175,19 @@ def test_single_step_random_orbitals(name, M, N, vscale):
     assert _compare_step(cfg, m, states) >= T - 1
 
 
+@pytest.mark.parametrize("M,N", [(1, 1), (15, 7), (16, 8), (47, 20)])
+def test_single_step_mixed_ring_edges(M, N):
+    """Mixed path at the edges of the propagation's fragment ring: n = 2 and
+    n = 16 have exactly as many k-blocks as the ring is deep (it wraps to the
+    next Chebyshev term after every block), n = 17 is one row past that, and
+    n = 48 spans several ring turns per term."""
+    cfg = make_cfg("c1", M=M, N=N)
+    m = models.from_config(cfg, M=M)
+    T = 6
+    states = random_states(m, N, T, seed=11 + M, xs=np.linspace(-5, 15, T), v_scale=0.003)
+    assert _compare_step(cfg, m, states, precision="mixed", tol=1e-5) >= T - 1
+
+
 def test_step_counter_drives_the_hop_uniform():
     cfg = make_cfg("c1", M=20, N=10)
     m = models.from_config(cfg)
