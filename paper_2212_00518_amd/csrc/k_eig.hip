@@ -28,6 +28,7 @@ namespace iesh {
 namespace {
 
 constexpr int kEigThreads = 256;
+static_assert(kEigThreads % 64 == 0, "whole waves: the secular solve relies on it");
 constexpr double kEps = 2.220446049250313e-16;
 
 struct EigLds {
@@ -63,13 +64,27 @@ __device__ inline double rcp_nr(double d) {
 }
 
 // f and its split derivative at tau (origin eo); terms with k < j are left
-// of the root.
-__device__ inline void secular_eval(int j, int M, const double* e, const double* V2, double eo,
-                                    double emh, double tau, double& f, double& dl, double& dr,
-                                    double& err) {
+// of the root.  j0 is the same for all lanes of the wave and no lane's j lies
+// outside [j0, j0 + 64), so poles below j0 are left of every lane's root and
+// poles from j0 + 64 on right of it: only the 64 poles between need the
+// per-lane split.  The terms are summed in the same order either way.
+__device__ inline void secular_eval(int j, int j0, int M, const double* e, const double* V2,
+                                    double eo, double emh, double tau, double& f, double& dl,
+                                    double& dr, double& err) {
   double psi = 0.0, l = 0.0, r = 0.0, abssum = 0.0;
-  for (int k = 0; k < M; ++k) {
+  const int k1 = min(j0, M), k2 = min(j0 + 64, M);
+#pragma unroll 2
+  for (int k = 0; k < k1; ++k) {
     const double d = (e[k] - eo) - tau;  // eps_k - lambda
+    const double inv = rcp_nr(d);
+    const double t = V2[k] * inv;
+    psi += t;
+    abssum += fabs(t);
+    l += t * inv;
+  }
+#pragma unroll 2
+  for (int k = k1; k < k2; ++k) {
+    const double d = (e[k] - eo) - tau;
     const double inv = rcp_nr(d);
     const double t = V2[k] * inv;
     psi += t;
@@ -78,6 +93,15 @@ __device__ inline void secular_eval(int j, int M, const double* e, const double*
       l += t * inv;
     else
       r += t * inv;
+  }
+#pragma unroll 2
+  for (int k = k2; k < M; ++k) {
+    const double d = (e[k] - eo) - tau;
+    const double inv = rcp_nr(d);
+    const double t = V2[k] * inv;
+    psi += t;
+    abssum += fabs(t);
+    r += t * inv;
   }
   f = emh + tau + psi;
   dl = l;
@@ -100,8 +124,9 @@ __device__ inline double quad_root_in(double a2, double a1, double a0, double al
   return fabs(r1) < fabs(r2) ? r1 : r2;
 }
 
-// Root j (0..M) of the secular function.  Returns 1 on convergence.
-__device__ int secular_root(int j, int M, const double* e, const double* V2, double h,
+// Root j (0..M) of the secular function; j0 as in secular_eval.  Returns 1
+// on convergence.
+__device__ int secular_root(int j, int j0, int M, const double* e, const double* V2, double h,
                             double vnorm, int max_it, double& tau_out, int& org_out) {
   int o;
   double lo, hi, tau, f = 0.0, dl = 0.0, dr = 0.0, err = 0.0;
@@ -119,7 +144,7 @@ __device__ int secular_root(int j, int M, const double* e, const double* V2, dou
   } else {
     const double gap = e[j] - e[j - 1];
     const double half = 0.5 * gap;
-    secular_eval(j, M, e, V2, e[j - 1], e[j - 1] - h, half, f, dl, dr, err);
+    secular_eval(j, j0, M, e, V2, e[j - 1], e[j - 1] - h, half, f, dl, dr, err);
     if (f >= 0.0) {
       o = j - 1;
       lo = 0.0;
@@ -137,7 +162,7 @@ __device__ int secular_root(int j, int M, const double* e, const double* V2, dou
   const double emh = eo - h;
   int ok = 0;
   for (int it = 0; it < max_it; ++it) {
-    if (!have_f) secular_eval(j, M, e, V2, eo, emh, tau, f, dl, dr, err);
+    if (!have_f) secular_eval(j, j0, M, e, V2, eo, emh, tau, f, dl, dr, err);
     have_f = false;
     if (f == 0.0 || fabs(f) <= err) {
       ok = 1;
@@ -220,7 +245,10 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
   for (int j = tid; j < n; j += kEigThreads) {
     double tau;
     int o;
-    const int ok = secular_root(j, M, L.e, L.V2, ma.h, vnorm, md.eig_iter, tau, o);
+    // the roots of a wave are the 64 consecutive indices from j0 (the block
+    // has a whole number of waves and steps j by its size)
+    const int j0 = __builtin_amdgcn_readfirstlane(j - (tid & 63));
+    const int ok = secular_root(j, j0, M, L.e, L.V2, ma.h, vnorm, md.eig_iter, tau, o);
     L.tau[j] = tau;
     L.org[j] = o;
     L.lam[j] = L.e[o] + tau;
