@@ -257,18 +257,27 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
   __syncthreads();
   // Loewner couplings: Vh_k^2 = -prod_j (e_k - lambda_j) / prod_{l != k} (e_k - e_l),
   // factors paired so that each ratio stays near 1.
+  // The factors are taken in the order of l; as in the secular sums, only the
+  // 64 indices l inside the wave's own range [k0, k0 + 64) need the per-lane
+  // choice between the two forms.
   for (int k = tid; k < M; k += kEigThreads) {
+    const int k0 = __builtin_amdgcn_readfirstlane(k - (tid & 63));
+    const int l1 = min(k0, M), l2 = min(k0 + 64, M);
     const double ek = L.e[k];
     const double dk = (ek - L.e[L.org[k]]) - L.tau[k];            // e_k - lambda_k  > 0
     const double dk1 = (ek - L.e[L.org[k + 1]]) - L.tau[k + 1];   // e_k - lambda_k+1 < 0
     double prod = dk * (-dk1);
-    for (int l = 0; l < M; ++l) {
+    for (int l = 0; l < l1; ++l)
+      prod *= ((ek - L.e[L.org[l]]) - L.tau[l]) * rcp_nr(ek - L.e[l]);
+    for (int l = l1; l < l2; ++l) {
       if (l < k) {
         prod *= ((ek - L.e[L.org[l]]) - L.tau[l]) * rcp_nr(ek - L.e[l]);
       } else if (l > k) {
         prod *= ((L.e[L.org[l + 1]] - ek) + L.tau[l + 1]) * rcp_nr(L.e[l] - ek);
       }
     }
+    for (int l = l2; l < M; ++l)
+      prod *= ((L.e[L.org[l + 1]] - ek) + L.tau[l + 1]) * rcp_nr(L.e[l] - ek);
     L.Vh2[k] = prod;
   }
   __syncthreads();
