@@ -73,7 +73,7 @@ __device__ inline void secular_eval(int j, int j0, int M, const double* e, const
                                     double& dr, double& err) {
   double psi = 0.0, l = 0.0, r = 0.0, abssum = 0.0;
   const int k1 = min(j0, M), k2 = min(j0 + 64, M);
-#pragma unroll 2
+#pragma unroll 4
   for (int k = 0; k < k1; ++k) {
     const double d = (e[k] - eo) - tau;  // eps_k - lambda
     const double inv = rcp_nr(d);
@@ -94,7 +94,7 @@ __device__ inline void secular_eval(int j, int j0, int M, const double* e, const
     else
       r += t * inv;
   }
-#pragma unroll 2
+#pragma unroll 4
   for (int k = k2; k < M; ++k) {
     const double d = (e[k] - eo) - tau;
     const double inv = rcp_nr(d);
