@@ -138,8 +138,12 @@ def _force(p: Params, x, q0, N, hp):
     return -p.mass * p.omega ** 2 * x - hp * np.sum(q0[:N] ** 2)
 
 
-def loss(p: Params, path, N, dt, terms=(1.0, 1.0, 0.0, 0.0)):
-    """Loss of one prescribed path x_0 .. x_T (array of T + 1 positions)."""
+def loss(p: Params, path, N, dt, terms=(1.0, 1.0, 0.0, 0.0), history=None):
+    """Loss of one prescribed path x_0 .. x_T (array of T + 1 positions).
+
+    history: optional list that receives, per step s = 1 .. T, a dict with the
+    orbitals C(s) and the population P(s), and at s = T also E_exc (for tests
+    that check the forward pass against the dynamics oracle)."""
     cP, cE, cG, cF = terms
     T = len(path) - 1
     C, n0 = _initial(p, path[0], N)
@@ -156,14 +160,20 @@ def loss(p: Params, path, N, dt, terms=(1.0, 1.0, 0.0, 0.0)):
         H1, hp1 = hamiltonian(p, path[s + 1])
         lam1, Q1 = eig(H1)
         z = C.T @ Q1[0, :]
-        total += cP * np.sum(np.abs(z) ** 2) / T
+        Pt = np.sum(np.abs(z) ** 2)
+        total += cP * Pt / T
+        if history is not None:
+            history.append(dict(C=C.copy(), P=Pt))
         if cG:
             total += cG * _hop_sum(C, N, _couplings(lam1, Q1, hp1), v, dt) / T
         if cF:
             total += cF * _force(p, path[s + 1], Q1[0, :], N, hp1) / T
         if s == T - 1:
             rho = np.sum(np.abs(C) ** 2, axis=1)
-            total += cE * np.sum(lam1 * (rho - n0))
+            E_exc = np.sum(lam1 * (rho - n0))
+            total += cE * E_exc
+            if history is not None:
+                history[-1]["E_exc"] = E_exc
     return total
 
 

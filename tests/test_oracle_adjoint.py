@@ -124,3 +124,66 @@ def test_force_term_is_the_hellmann_feynman_force():
         H, hp = adj.hamiltonian(p, x)
         lam, Q = el.eig(H)
         assert abs(adj._force(p, x, Q[0, :], N, hp) - ref) <= 1e-12 * abs(ref)
+
+
+def _forward_by_the_dynamics_oracle(p, path, N, dt, v_sign=1.0):
+    """The adjoint loss's forward pass rebuilt from the dynamics oracle on the
+    dense double-well model: couplings from el.coupling_matrices (dense
+    Q^T dH Q), the midpoint propagator through el.propagator_matrix and
+    el.propagate, and the population from dynamics.observables with the
+    occupations held at the N lowest orbitals.  E_exc comes from the energy of
+    the diabatic orbitals Psi = Q C: tr(Psi^H H Psi) minus the energy of the
+    held configuration."""
+    from oracle import dynamics as dyn
+    from oracle import electronic as el
+    m = _dense_model(p)
+    lam0, _ = el.eig(m.H(np.array([path[0]])))
+    n = len(lam0)
+    C = np.eye(n, N, dtype=np.complex128)
+    out = []
+    for s in range(len(path) - 1):
+        x0, x1 = np.array([path[s]]), np.array([path[s + 1]])
+        xm = 0.5 * (x0 + x1)
+        v = v_sign * (x1 - x0) / dt
+        lam, Q = el.eig(m.H(xm))
+        _, Ds = el.coupling_matrices(lam, Q, m.dH(xm))
+        C = el.propagate(C, el.propagator_matrix(lam, Ds, v), dt)
+        st = dyn.State(x1, v, C, np.arange(N))
+        obs = dyn.observables(m, st)
+        lam1, Q1 = el.eig(m.H(x1))
+        Psi = Q1 @ C
+        E_exc = float(np.real(np.trace(Psi.conj().T @ m.H(x1) @ Psi))) - float(np.sum(lam1[:N]))
+        out.append(dict(C=C.copy(), P=obs["Pd_wf"], E_exc=E_exc))
+    return out
+
+
+def test_adjoint_forward_on_a_moving_path_matches_the_dynamics_oracle():
+    """Pin of the adjoint loss's forward pass (Sec. II.C, Eqs.
+    exponential_integrator and fast_exponential_integrator, midpoint reading):
+    along moving paths (one of the workload's seeded paths and a fast sweep
+    through the level crossings), its orbitals C(t), population P(t) and
+    final excitation energy agree with the dynamics oracle to 1e-12.  The
+    same comparison with the velocity's sign flipped must fail in C, P and
+    E_exc, so that a sign error shared by loss and tangent cannot pass."""
+    p, seeded, N, dt = _case(M=10, N=5, T=20, seed=5)
+    k = np.arange(21)
+    fast = 1.0 + 1e-2 * dt * k + 0.5 * np.sin(0.3 * k)
+    for path in (seeded, fast):
+        assert np.max(np.abs(np.diff(path))) > 1e-3       # the nuclei do move
+        hist = []
+        L = adj.loss(p, path, N, dt, history=hist)
+        ref = _forward_by_the_dynamics_oracle(p, path, N, dt)
+        assert len(hist) == len(ref) == len(path) - 1
+        for t, (a, b) in enumerate(zip(hist, ref)):
+            assert np.max(np.abs(a["C"] - b["C"])) <= 1e-12, t
+            assert abs(a["P"] - b["P"]) <= 1e-12, t
+        assert abs(hist[-1]["E_exc"] - ref[-1]["E_exc"]) <= 1e-12 * max(1e-3, abs(ref[-1]["E_exc"]))
+        T = len(path) - 1
+        assert abs(L - (sum(r["P"] for r in ref) / T + ref[-1]["E_exc"])) <= 1e-12
+        # the orbitals do mix along the path (the comparison is not vacuous)
+        assert np.max(np.abs(ref[-1]["C"][N:, :])) > 1e-4
+        flipped = _forward_by_the_dynamics_oracle(p, path, N, dt, v_sign=-1.0)
+        assert max(np.max(np.abs(a["C"] - b["C"])) for a, b in zip(hist, flipped)) > 1e-6
+        assert max(abs(a["P"] - b["P"]) for a, b in zip(hist, flipped)) > 1e-6
+    assert hist[-1]["E_exc"] > 1e-6
+    assert abs(flipped[-1]["E_exc"] - hist[-1]["E_exc"]) > 1e-9

@@ -263,6 +263,40 @@ def test_selection_canonical_order():
     assert el.select_hop(np.zeros((2, 3)), 0.0)[:2] == (None, None)
 
 
+def _sequential_selection(g, xi):
+    """The plain rule (one uniform, Sec. II.B): one running sum over every
+    pair in the canonical order (rows ascending, then targets ascending); the
+    first pair whose running sum exceeds xi."""
+    acc = 0.0
+    for r in range(g.shape[0]):
+        for b in range(g.shape[1]):
+            acc += g[r, b]
+            if g[r, b] > 0.0 and acc > xi:
+                return r, b
+    return None, None
+
+
+def test_two_level_selection_equals_the_sequential_cumulative_sum():
+    """The two-level running sum of select_hop (row totals, then within the
+    row) picks the same pair as the plain sequential cumulative sum wherever
+    no running sum of either order lies within rounding of xi."""
+    rs = np.random.default_rng(11)
+    compared = hops = 0
+    for trial in range(3000):
+        N, n = rs.integers(1, 9), rs.integers(2, 30)
+        g = rs.exponential(size=(N, n)) * (rs.random((N, n)) < 0.4)
+        g *= rs.uniform(0.05, 1.5) / max(g.sum(), 1e-300)
+        xi = rs.random() if trial % 3 else rs.uniform(0.0, 1.2 * g.sum())
+        r, b, margin = el.select_hop(g, xi)
+        flat = np.cumsum(g.ravel())
+        if margin < 1e-12 or np.min(np.abs(flat - xi)) < 1e-12:
+            continue
+        compared += 1
+        hops += r is not None
+        assert (r, b) == _sequential_selection(g, xi), trial
+    assert compared > 2900 and 500 < hops < compared
+
+
 def test_rescale_conserves_energy_and_frustration():
     mass = np.array([2000.0, 100.0])
     v = np.array([0.01, -0.02])
