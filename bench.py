@@ -38,6 +38,7 @@ if ROOT not in sys.path:
 
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # MI355X dense MFMA FP64 / FP32
 HBM_PEAK_GBS = 8000.0
+STEADY_WARMUP, STEADY_STEPS = 1000, 100
 
 
 def algorithmic_prop_flops(n, N, sum_terms):
@@ -62,7 +63,7 @@ def traffic_from_profile(path_md, kernel_src):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1, **run_options):
+def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1, keep_sample=0, **run_options):
     import torch
     from paper_2212_00518_amd import from_config
 
@@ -84,6 +85,8 @@ def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1, **run_option
     status = ens.status()
     clock_time, _ = ens.clock()
     ens.timing(False)
+    defect = ens.defect_max() if precision == "mixed" else None
+    sample = state_sample(ens, cfg, keep_sample) if keep_sample else None
     ens.close()
     n, N = cfg["bath"]["M"] + 1, cfg["n_elec"]
     flops = algorithmic_prop_flops(n, N, sum_terms)
@@ -99,7 +102,88 @@ def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1, **run_option
         exact_hop_fraction=hop_evals / max(traj_steps, 1),
         frozen=int((status != 0).sum()),
         mean_dt=float(clock_time.sum()) / max(warmup + steps, 1) / T,
+        lowdin_launches=tm["lowdin"][1],
+        lowdin_steps_in_window=sum(1 for k in range(warmup, warmup + steps) if (k + 1) % 100 == 0)
+        if precision == "mixed" else 0,
+        max_orthonormality_defect=defect,
+        sample=sample,
     )
+
+
+def state_sample(ens, cfg, count):
+    """States of `count` trajectories taken from a running ensemble: the most
+    mixed half (largest orbital weight outside the occupied set, where the
+    exact determinant ratios run) and an evenly spaced half."""
+    import numpy as np
+    from paper_2212_00518_amd import unpack_C
+    x, v, Cf, occ = ens.get_state()
+    T, N, n = len(x), cfg["n_elec"], cfg["bath"]["M"] + 1
+    C3 = Cf.reshape(T, ens.N_max, ens.n_max)[:, :N, :n]
+    w_occ = np.take_along_axis(np.sum(np.abs(C3) ** 2, axis=1), occ[:, :N].astype(np.int64), axis=1)
+    mixing = N - np.sum(w_occ, axis=1)
+    picks = list(np.argsort(mixing)[::-1][: count // 2])
+    for t in np.linspace(0, T - 1, count - len(picks)).astype(int):
+        if t not in picks:
+            picks.append(int(t))
+    step = ens.get_step()
+    return dict(step=step, traj=[int(t) for t in picks],
+                states=[(float(x[t]), float(v[t]), unpack_C(Cf, t, n, N, ens.n_max, ens.N_max),
+                         occ[t, :N].copy()) for t in picks])
+
+
+def error_vs_oracle(cfg, sample, precision, steps=20):
+    """Error of a GPU path against the FP64 oracle from the same inputs: the
+    sampled steady-state states are uploaded into a small ensemble, which
+    runs `steps` steps (from the sample's step, so the hop uniforms are those
+    of the running ensemble's step count); the oracle runs the same steps
+    from the same states.  Reports, over the trajectories whose hop events
+    agree (decisions within the near-tie window excluded), the largest
+    deviation of the hop probabilities (iesh_hop_probs at the end, relative to
+    the trajectory's largest), of the impurity population P_d^wf (every
+    step), of the orbitals and of the total energy (relative)."""
+    import numpy as np
+    from oracle import models, dynamics as dyn
+    from paper_2212_00518_amd import from_config, pack_states, unpack_C
+
+    m = models.from_config(cfg)
+    N, n = cfg["n_elec"], cfg["bath"]["M"] + 1
+    states = sample["states"]
+    T = len(states)
+    ens = from_config(cfg, n_traj=T, precision=precision, lowdin_every=100, record_every=1)
+    ens.set_state(*pack_states(states, ens.n_max, ens.N_max))
+    ens.set_step(sample["step"])
+    obs = ens.run(steps, record=True)
+    _, _, Cf, _ = ens.get_state()
+    g = ens.hop_probs()
+    evs, _ = ens.events()
+    n_max, N_max = ens.n_max, ens.N_max
+    ens.close()
+    tie = 1e-7 if precision == "fp64" else 1e-4
+    out = dict(trajectories=T, steps=steps, from_step=sample["step"], compared=0, near_tie_excluded=0,
+               max_rel_dg=0.0, max_abs_dPd_wf=0.0, max_abs_dC=0.0, max_rel_dEtot=0.0, hops=0)
+    for t, (x, v, C, occ) in enumerate(states):
+        st = dyn.State([x], [v], C, occ)
+        ref, ref_ev, recs = dyn.run(m, st, cfg["dt"], steps, cfg["seed"], t, step0=sample["step"],
+                                    record_every=1)
+        if any(e["margin"] < tie * max(e["g_total"], 1e-300) for e in ref_ev):
+            out["near_tie_excluded"] += 1
+            continue
+        mine = [(e["step"], e["a"], e["b"], e["accepted"]) for e in evs if e["traj"] == t]
+        if mine != [(e["step"], e["a"], e["b"], e["accepted"]) for e in ref_ev]:
+            out.setdefault("event_mismatch", []).append(t)
+            continue
+        out["compared"] += 1
+        out["hops"] += sum(e["accepted"] for e in ref_ev)
+        gref = dyn.hop_probs(m, ref, cfg["dt"])
+        gt = g[t, : N * n].reshape(N, n)
+        out["max_rel_dg"] = max(out["max_rel_dg"], float(np.max(np.abs(gt - gref)) / max(np.max(gref), 1e-300)))
+        out["max_abs_dPd_wf"] = max(out["max_abs_dPd_wf"],
+                                    max(abs(obs[q, t, 1] - r["Pd_wf"]) for q, r in enumerate(recs)))
+        out["max_rel_dEtot"] = max(out["max_rel_dEtot"],
+                                   max(abs(obs[q, t, 4] - r["Etot"]) / abs(r["Etot"]) for q, r in enumerate(recs)))
+        out["max_abs_dC"] = max(out["max_abs_dC"],
+                                float(np.max(np.abs(unpack_C(Cf, t, n, N, n_max, N_max) - ref.C))))
+    return out
 
 
 def mixed_vs_fp64(cfg, T=64, steps=500):
@@ -187,9 +271,24 @@ def cpu_baseline(cfg_name, steps_per_worker):
     wall = time.perf_counter() - t0
     total = workers * steps_per_worker
     return dict(value=total / wall, unit="trajectory-steps/s", cores=workers, kind="oracle",
+                cpu_model=cpu_model(),
                 sample=f"{workers} trajectories x {steps_per_worker} steps of the same workload, "
                        f"one process per trajectory, one BLAS thread each",
                 one_core_s_per_traj_step=sum(per) / total, wall_s=wall)
+
+
+def cpu_model():
+    """CPU model name of the host (from /proc/cpuinfo) and its logical CPU count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name} ({os.cpu_count()} logical CPUs on the host)"
 
 
 def scattering_bench(a):
@@ -463,7 +562,7 @@ def adjoint_cpu_baseline(steps_per_worker, n_paths):
     wall = time.perf_counter() - t0
     path_steps = workers * steps_per_worker
     return dict(value=round(1e3 * n_paths * wall / path_steps, 1), unit="ms/step", cores=workers,
-                kind="oracle",
+                kind="oracle", cpu_model=cpu_model(),
                 sample=f"{workers} paths x {steps_per_worker} steps, one process per path, one BLAS "
                        f"thread each; scaled to {n_paths} paths",
                 path_steps_per_s=round(path_steps / wall, 3),
@@ -634,6 +733,31 @@ def adjoint_bench(a, cfg=None, n_steps=None, report=True):
     return out
 
 
+def small_workload():
+    """The small double-well workload in full (M = 20, N = 10, 128
+    trajectories, 1000 FP64 steps, dt = 50): throughput of the graph-replayed
+    step loop at a size where launch latency, not arithmetic, sets the pace."""
+    import torch
+    from paper_2212_00518_amd import from_config
+    from workloads import get_config
+    cfg = get_config("c1")
+    T, steps = cfg["n_traj"], cfg["n_steps"]
+    x0, v0 = initial_sample(cfg, T, cfg["seed"])
+    ens = from_config(cfg, n_traj=T, precision="fp64")
+    ens.init_thermal(x0, v0)
+    ens.run(10)
+    ens.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.run(steps)
+    ens.sync()
+    wall = time.perf_counter() - t0
+    ens.close()
+    return {"workload": cfg["name"], "path": "fp64", "steps": steps,
+            "value": round(T * steps / wall, 1), "unit": "trajectory-steps/s",
+            "ms_per_step": round(1e3 * wall / steps, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -661,6 +785,10 @@ def main():
                     help="adaptive step: bound on the rescaled hop-probability total per step")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint ms/step entry of the default line")
+    ap.add_argument("--no-steady", action="store_true",
+                    help="skip the steady-state window (1000-step pre-roll, 100 timed steps)")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small-workload (M = 20, 128 trajectories) throughput entry")
     ap.add_argument("--forced-lifetimes", action="store_true",
                     help="c3: per-trajectory step caps log-uniform in [200, 20000]")
     ap.add_argument("--peak-probe", action="store_true",
@@ -708,13 +836,26 @@ def main():
     T = a.n_traj or cfg["n_traj"]
     x0, v0 = initial_sample(cfg, T, cfg["seed"])
     precs = ["fp64", "mixed"] if a.precision == "both" else [a.precision]
-    res = {}
+    steady_window = a.warmup >= STEADY_WARMUP and a.steps >= STEADY_STEPS
+    res, steady = {}, {}
+    adapt = dict(dt_levels=a.dt_levels, hop_gmax=a.hop_gmax) if a.dt_levels else {}
     for p in precs:
-        adapt = dict(dt_levels=a.dt_levels, hop_gmax=a.hop_gmax) if a.dt_levels else {}
-        res[p] = time_path(cfg, p, T, a.steps, a.warmup, x0, v0, a.substeps, **adapt)
+        res[p] = time_path(cfg, p, T, a.steps, a.warmup, x0, v0, a.substeps,
+                           keep_sample=8 if steady_window and not a.no_error else 0, **adapt)
         print(f"# {p}: {res[p]['value']:.1f} trajectory-steps/s, {res[p]['ms_per_step']:.2f} ms/step, "
               f"kernels {res[p]['kernels_ms']} ms, propagation {res[p]['prop_tflops']:.2f} TFLOP/s",
               file=sys.stderr, flush=True)
+    if not a.no_steady:
+        # the steady state: a 1000-step pre-roll (orbitals mixed, the exact
+        # ratios needed on a fifth of the trajectory-steps), then a window of
+        # 100 steps that holds one Loewdin step of the mixed path
+        for p in precs:
+            steady[p] = res[p] if steady_window else time_path(
+                cfg, p, T, STEADY_STEPS, STEADY_WARMUP, x0, v0, a.substeps,
+                keep_sample=0 if a.no_error else 8, **adapt)
+            print(f"# steady {p}: {steady[p]['value']:.1f} trajectory-steps/s, "
+                  f"{steady[p]['ms_per_step']:.2f} ms/step, kernels {steady[p]['kernels_ms']} ms",
+                  file=sys.stderr, flush=True)
     head = "mixed" if "mixed" in res else "fp64"
     r = res[head]
     src = os.path.join(ROOT, "paper_2212_00518_amd", "csrc", "k_prop.hip")
@@ -758,8 +899,31 @@ def main():
                         "kernels_ms_per_launch": f["kernels_ms"],
                         "exact_hop_fraction": round(f["exact_hop_fraction"], 4)}
         line["mixed_over_fp64"] = round(r["value"] / f["value"], 3)
+    if steady:
+        line["steady_state"] = {}
+        for p, r2 in steady.items():
+            line["steady_state"][p] = {
+                "value": round(r2["value"], 2), "ms_per_step": round(r2["ms_per_step"], 3),
+                "warmup": STEADY_WARMUP if not steady_window else a.warmup,
+                "steps": STEADY_STEPS if not steady_window else a.steps,
+                "roofline_frac": round(r2["prop_tflops"] / PEAK_TFLOPS[p], 4),
+                "prop_ms_per_launch": round(r2["prop_ms_per_launch"], 4),
+                "kernels_ms_per_launch": r2["kernels_ms"],
+                "kernels_time_share": r2["kernels_share"],
+                "exact_hop_fraction": round(r2["exact_hop_fraction"], 4),
+                "lowdin_steps_in_window": r2["lowdin_steps_in_window"],
+                "max_orthonormality_defect": r2["max_orthonormality_defect"]}
+    if not a.no_error:
+        # error of each path against the FP64 oracle, from steady-state states
+        src = steady if steady else (res if steady_window else {})
+        for p, r2 in src.items():
+            if r2.get("sample"):
+                line[f"{p}_error_vs_oracle"] = error_vs_oracle(cfg, r2["sample"], p)
+                print(f"# {p} vs oracle: {line[f'{p}_error_vs_oracle']}", file=sys.stderr, flush=True)
     if not a.no_error and "mixed" in res and "fp64" in res:
-        line["mixed_error"] = mixed_vs_fp64(cfg, steps=a.error_steps)
+        line["mixed_vs_fp64_gpu"] = mixed_vs_fp64(cfg, steps=a.error_steps)
+    if not a.no_small and a.config == "c2":
+        line["small_workload"] = small_workload()
     if not a.no_adjoint:
         # the adjoint workload's ms/step on a 200-step prefix of its paths
         adj = adjoint_bench(argparse.Namespace(n_traj=None), n_steps=200, report=False)

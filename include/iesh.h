@@ -137,7 +137,15 @@ typedef struct iesh_run_desc {
   double dt;             /* time step > 0                                       */
   double kT;             /* temperature of the initial Fermi occupations >= 0  */
   uint64_t seed;         /* key of the hop uniforms                             */
-  int32_t lowdin_every;  /* IESH_MIXED: re-orthonormalise every L steps (0: never) */
+  int32_t lowdin_every;  /* IESH_MIXED: re-orthonormalise every L steps (0: never).
+                            Each Loewdin step also measures the orthonormality
+                            defect ||C^H C - I||_F the period left (before its
+                            correction); the exact no-hop bound allows the
+                            stored orbitals a defect of max(1e-3, 4 x that
+                            measurement) (1e-8 on the FP64 path).  With 0 the
+                            defect is never measured, so the mixed path then
+                            evaluates the determinant ratios at every step, as
+                            with hop_filter_off = 1 (same results, slower)       */
   int32_t record_every;  /* observables every R steps in iesh_run (0: none)    */
   int32_t exit_enabled;  /* freeze trajectories once x > exit_x (coordinate exit_dof) */
   int32_t compact_every; /* iesh_run: every this many steps, move frozen trajectories
@@ -263,7 +271,10 @@ int iesh_step(iesh_ctx* ctx);
 /* n_steps steps (replayed from a captured HIP graph).  If obs_out is not
    NULL and run.record_every > 0, writes floor(n_steps / record_every)
    records of n_traj * IESH_N_OBS doubles (host memory) taken after every
-   record_every-th step of this call.  Synchronises before returning. */
+   record_every-th step of this call; a trajectory that is frozen (status
+   word with EXITED, NONCONV, NONFINITE or STEPCAP) when a record falls due
+   takes no step and gets NaN in that record.  Synchronises before
+   returning. */
 int iesh_run(iesh_ctx* ctx, int64_t n_steps, double* obs_out);
 
 /* ---- queries ---------------------------------------------------------------- */
@@ -289,7 +300,11 @@ int iesh_traj_clock(iesh_ctx* ctx, double* time_out, double* dt_out);
 
 /* Copy up to cap hop events (sorted by step, then trajectory) recorded
    since the last set_state / clear into out (host); *count receives the
-   number recorded (may exceed cap; the log keeps the first IESH_EVENT_CAP). */
+   number of events that occurred (may exceed cap and IESH_EVENT_CAP).  The
+   device log holds IESH_EVENT_CAP events; once more occurred, the events of
+   the step in which the log overflowed are dropped as well (which of them
+   found a slot depends on the order the work-groups ran in), so the events
+   copied are exactly all events of the steps before that one. */
 #define IESH_EVENT_CAP (1 << 20)
 int iesh_events(iesh_ctx* ctx, iesh_event* out, int64_t cap, int64_t* count);
 int iesh_clear_events(iesh_ctx* ctx);
@@ -346,6 +361,18 @@ int iesh_work(iesh_ctx* ctx, int64_t* sum_cheb_terms, int64_t* traj_steps);
    probabilities had to be evaluated from the determinant ratios (the others
    were completed by the exact no-hop bound); synchronises. */
 int iesh_hop_evals(iesh_ctx* ctx, int64_t* full_evals);
+
+/* Orthonormality defect of the mixed path's FP32 orbitals, as measured by the
+   Loewdin steps (run.lowdin_every): per_traj (host, n_traj, global order, may
+   be NULL) receives ||C^H C - I||_F of each trajectory before its last
+   correction (0 before the first, and on FP64 contexts); max_seen (may be
+   NULL) the largest measurement since the last set_state / init_thermal;
+   violations (may be NULL) the number of measurements that exceeded the
+   defect the exact no-hop bound allowed over the period before them (the
+   allowance is max(1e-3, 4 x the previous measurement)): a nonzero count
+   means the bound may have skipped a hop in those periods.  Synchronises. */
+int iesh_orthonormality_defect(iesh_ctx* ctx, double* per_traj, double* max_seen,
+                               int64_t* violations);
 
 /* ---- adjoint along prescribed nuclear paths -------------------------------
    Reverse-mode gradient of an electronic loss with respect to the model

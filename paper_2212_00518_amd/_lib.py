@@ -45,6 +45,7 @@ SYMBOLS = (
     "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
     "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals", "iesh_class_info",
     "iesh_set_step_caps", "iesh_adjoint_forward", "iesh_adjoint_backward", "iesh_eigh_batched",
+    "iesh_orthonormality_defect",
 )
 TIMERS = ("eig", "prop", "hop", "lowdin", "filter", "adj_prop", "adj_phi", "adj_eig", "adj_hop")
 
@@ -123,6 +124,7 @@ def lib():
         L.iesh_set_step_caps.argtypes = [vp, C.POINTER(C.c_int64)]
         L.iesh_adjoint_forward.argtypes = [vp, dp, C.c_int32, C.c_int32, dp, dp]
         L.iesh_adjoint_backward.argtypes = [vp, dp, dp]
+        L.iesh_orthonormality_defect.argtypes = [vp, dp, dp, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -317,6 +319,11 @@ class Ensemble:
     def set_step(self, step: int):
         self._check(lib().iesh_set_step(self.ctx, int(step)), "iesh_set_step")
 
+    def get_step(self):
+        s = C.c_int64()
+        self._check(lib().iesh_get_step(self.ctx, C.byref(s)), "iesh_get_step")
+        return s.value
+
     # ------------------------------------------------------------- dynamics
     def step(self):
         self._check(lib().iesh_step(self.ctx), "iesh_step")
@@ -444,3 +451,18 @@ class Ensemble:
 
     def clear_events(self):
         self._check(lib().iesh_clear_events(self.ctx), "iesh_clear_events")
+
+    def defect(self):
+        """(per-trajectory defect before the last Loewdin correction, largest
+        measured, measurements above the no-hop bound's allowance)."""
+        d = np.zeros(self.n_traj)
+        mx = C.c_double()
+        nv = C.c_int64()
+        self._check(lib().iesh_orthonormality_defect(self.ctx, d.ctypes.data_as(C.POINTER(C.c_double)),
+                                                     C.byref(mx), C.byref(nv)),
+                    "iesh_orthonormality_defect")
+        return d, mx.value, nv.value
+
+    def defect_max(self):
+        _, mx, nv = self.defect()
+        return {"max": mx, "violations": nv}

@@ -33,7 +33,7 @@ struct iesh_ctx {
   int64_t step = 0;
   size_t device_bytes = 0;
   std::string err;
-  std::vector<void*> allocations;
+  std::vector<std::pair<void*, size_t>> allocations;  // (pointer, bytes)
   // graph cache for iesh_run
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -90,12 +90,27 @@ int dalloc(iesh_ctx* ctx, T** p, size_t count) {
   const size_t bytes = count * sizeof(T);
   hipError_t e = hipMalloc(&q, bytes);
   if (e != hipSuccess) return fail(ctx, IESH_ENOMEM, "hipMalloc failed: " + std::to_string(bytes) + " bytes");
-  ctx->allocations.push_back(q);
+  ctx->allocations.push_back({q, bytes});
   if (hipMemsetAsync(q, 0, bytes, ctx->stream) != hipSuccess)
     return fail(ctx, IESH_EDEVICE, "hipMemsetAsync failed");
   ctx->device_bytes += bytes;
   *p = reinterpret_cast<T*>(q);
   return IESH_OK;
+}
+
+// Free one allocation made by dalloc (after the stream has drained).
+template <typename T>
+void dfree(iesh_ctx* ctx, T*& p) {
+  if (!p) return;
+  for (size_t i = 0; i < ctx->allocations.size(); ++i)
+    if (ctx->allocations[i].first == (void*)p) {
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipFree(p);
+      ctx->device_bytes -= ctx->allocations[i].second;
+      ctx->allocations.erase(ctx->allocations.begin() + i);
+      break;
+    }
+  p = nullptr;
 }
 
 void free_graph(iesh_ctx* ctx) {
@@ -376,8 +391,10 @@ int reset_traj_words(iesh_ctx* ctx) {
   for (auto& c : ctx->cls) {
     HIPTRY(ctx, hipMemsetAsync(c.status, 0, c.n_traj * sizeof(int32_t), ctx->stream));
     HIPTRY(ctx, hipMemsetAsync(c.nsteps, 0, c.n_traj * sizeof(int64_t), ctx->stream));
+    if (c.defect) HIPTRY(ctx, hipMemsetAsync(c.defect, 0, c.n_traj * sizeof(double), ctx->stream));
   }
   HIPTRY(ctx, hipMemsetAsync(&ctx->cnt->n_events, 0, sizeof(int64_t), ctx->stream));
+  HIPTRY(ctx, hipMemsetAsync(&ctx->cnt->defect_max_bits, 0, 2 * sizeof(int64_t), ctx->stream));
   return IESH_OK;
 }
 
@@ -657,7 +674,7 @@ int iesh_destroy(iesh_ctx* ctx) {
   if (!ctx) return IESH_OK;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   free_graph(ctx);
-  for (void* p : ctx->allocations) (void)hipFree(p);
+  for (auto& a : ctx->allocations) (void)hipFree(a.first);
   for (void* p : ctx->adj_allocs) (void)hipFree(p);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -789,7 +806,10 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
       c.md.mass_dof[0] = d.mass;
     }
     c.exit_dof = r.exit_dof;
-    c.exact_hops = r.hop_filter_off;
+    // the mixed path measures the orthonormality defect the no-hop bound
+    // needs only at its Loewdin steps: without them it evaluates the ratios
+    // at every step
+    c.exact_hops = r.hop_filter_off || (r.precision == IESH_MIXED && r.lowdin_every == 0);
     c.dt0 = r.dt;
     c.gmax = r.hop_gmax;
     c.dt_levels = r.dt_levels;
@@ -849,7 +869,8 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     } else {
       if ((rc = dalloc(ctx, &c.C32, (size_t)T * N * n_pad * 2)) ||
           (rc = dalloc(ctx, &c.Bt32, (size_t)T * n_pad * n_pad)) ||
-          (rc = dalloc(ctx, &c.low, lowdin_scratch_elems(c))))
+          (rc = dalloc(ctx, &c.low, lowdin_scratch_elems(c))) ||
+          (rc = dalloc(ctx, &c.defect, (size_t)T)))
         return bail(rc);
     }
     if (hipError_t e = prop_prepare(c, r.precision); e != hipSuccess)
@@ -1093,10 +1114,17 @@ int iesh_run(iesh_ctx* ctx, int64_t n_steps, double* obs_out) {
     free_graph(ctx);  // observable pointers are captured in the graph
     for (auto& c : ctx->cls) {
       if (!c.n_traj) continue;
+      dfree(ctx, c.obs);
       int rc = dalloc(ctx, &c.obs, (size_t)n_rec * c.n_traj * IESH_N_OBS);
       if (rc) return rc;
     }
     ctx->obs_records = n_rec;
+  }
+  if (record) {
+    // records of trajectories that are frozen when they fall due stay NaN
+    for (auto& c : ctx->cls)
+      if (c.n_traj)
+        HIPTRY(ctx, launch_fill(c.obs, (size_t)n_rec * c.n_traj * IESH_N_OBS, NAN, ctx->stream));
   }
   int rc = set_counters(ctx, ctx->step, record ? r.record_every : 0);
   if (rc) return rc;
@@ -1248,15 +1276,21 @@ int iesh_events(iesh_ctx* ctx, iesh_event* out, int64_t cap, int64_t* count) {
   int64_t n = 0;
   HIPTRY(ctx, hipMemcpy(&n, &ctx->cnt->n_events, sizeof(int64_t), hipMemcpyDeviceToHost));
   *count = n;
-  const int64_t have = std::min<int64_t>(n, IESH_EVENT_CAP);
+  int64_t have = std::min<int64_t>(n, IESH_EVENT_CAP);
   if (out && cap > 0 && have > 0) {
     std::vector<iesh_event> ev(have);
     HIPTRY(ctx, hipMemcpy(ev.data(), ctx->events, have * sizeof(iesh_event), hipMemcpyDeviceToHost));
     std::sort(ev.begin(), ev.end(), [](const iesh_event& a, const iesh_event& b) {
       return a.step != b.step ? a.step < b.step : a.traj < b.traj;
     });
+    if (n > IESH_EVENT_CAP) {
+      // which events of the step that overflowed the log got a slot depends
+      // on the order of the work-groups: drop that whole step
+      const int64_t last = ev.back().step;
+      while (have > 0 && ev[have - 1].step == last) --have;
+    }
     const int64_t m = std::min(have, cap);
-    std::memcpy(out, ev.data(), m * sizeof(iesh_event));
+    if (m > 0) std::memcpy(out, ev.data(), m * sizeof(iesh_event));
   }
   return IESH_OK;
 }
@@ -1304,6 +1338,27 @@ int iesh_work(iesh_ctx* ctx, int64_t* sum_cheb_terms, int64_t* traj_steps) {
   HIPTRY(ctx, hipMemcpy(w, &ctx->cnt->sum_cheb, sizeof(w), hipMemcpyDeviceToHost));
   *sum_cheb_terms = w[0];
   *traj_steps = w[1];
+  return IESH_OK;
+}
+
+int iesh_orthonormality_defect(iesh_ctx* ctx, double* per_traj, double* max_seen,
+                               int64_t* violations) {
+  if (!ctx) return IESH_EINVAL;
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  uint64_t w[2] = {0, 0};
+  HIPTRY(ctx, hipMemcpy(w, &ctx->cnt->defect_max_bits, sizeof(w), hipMemcpyDeviceToHost));
+  if (max_seen) std::memcpy(max_seen, &w[0], sizeof(double));
+  if (violations) *violations = (int64_t)w[1];
+  if (per_traj) {
+    for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+      const ClassDev& c = ctx->cls[ci];
+      if (!c.n_traj) continue;
+      std::vector<double> d(c.n_traj, 0.0);
+      if (c.defect)
+        HIPTRY(ctx, hipMemcpy(d.data(), c.defect, d.size() * sizeof(double), hipMemcpyDeviceToHost));
+      for (int hm = 0; hm < c.n_traj; ++hm) per_traj[ctx->members[ci][hm]] = d[hm];
+    }
+  }
   return IESH_OK;
 }
 

@@ -17,6 +17,13 @@ constexpr int kMaxDof = IESH_MAX_DOF;        // nuclear coordinates
 constexpr int kMaxCheb = 64;                 // Chebyshev terms per step
 constexpr int kChebStride = 2 * kMaxCheb + 8;
 constexpr int kGeoStride = 32;
+// The no-hop bound assumes the stored orbitals are orthonormal up to a
+// defect ||C^H C - I|| <= delta.  On the mixed path delta is the larger of a
+// floor and this multiple of the defect the last Loewdin step measured (the
+// growth over one period, before its correction).
+constexpr double kDefectSafety = 4.0;
+constexpr double kDeltaFP64 = 1e-8;
+constexpr double kDeltaMixed = 1e-3;
 
 // Status bits that stop a trajectory.
 constexpr int kFreezeMask = IESH_TRAJ_EXITED | IESH_TRAJ_NONCONV | IESH_TRAJ_NONFINITE |
@@ -107,6 +114,10 @@ struct ClassDev {
   double* gbuf = nullptr;   // [T][N][n_pad] hop probabilities (query mode)
   double* obs = nullptr;    // [records][T][IESH_N_OBS] (class-local records)
   double2* low = nullptr;   // Loewdin scratch (mixed path)
+  // [T] by home index (mixed path): ||C^H C - I||_F before the last Loewdin
+  // correction (0 before the first); the no-hop bound allows a defect of
+  // max(delta floor, kDefectSafety * this) for the stored orbitals
+  double* defect = nullptr;
   int32_t* hopq = nullptr;  // [3 + T] queue for the determinant-ratio kernel: count, -, done, list
   double2* hopx = nullptr;  // [T][N][N] inverse of S (shapes whose registers cannot hold it)
   // prescribed nuclear path (adjoint): x of trajectory g at step n is
@@ -125,6 +136,12 @@ struct Counters {
   int64_t traj_steps;    // trajectory-steps taken
   int64_t hop_evals;     // trajectory-steps that needed the determinant ratios
   int64_t max_cheb;      // largest number of Chebyshev terms used
+  // orthonormality defect ||C^H C - I||_F measured by the Loewdin steps: the
+  // largest one (bit pattern of a non-negative double, which orders like the
+  // value) and the number of measurements above the no-hop bound's allowance
+  // for the period before them
+  uint64_t defect_max_bits;
+  int64_t defect_violations;
 };
 
 // -------------------------------------------------------------------------
@@ -295,10 +312,11 @@ bool hop_needs_scratch(const ClassDev& c);
 hipError_t launch_hop_filter(const ClassDev& c, double dt, uint64_t seed, Counters* cnt, int record,
                              int exit_enabled, double exit_x, int64_t max_steps, int precision,
                              hipStream_t s);
-hipError_t launch_lowdin(const ClassDev& c, const Counters* cnt, int every, double2* scratch,
+hipError_t launch_lowdin(const ClassDev& c, Counters* cnt, int every, double2* scratch,
                          hipStream_t s);
 size_t lowdin_scratch_elems(const ClassDev& c);
 hipError_t launch_advance(Counters* cnt, hipStream_t s);
+hipError_t launch_fill(double* p, size_t count, double value, hipStream_t s);
 // Adjoint along prescribed paths (k_eig.hip, k_adjoint.hip).
 struct AdjTerms {
   double cP, cE, cG, cF;  // weights of the population, excitation, hop and force terms

@@ -11,6 +11,8 @@
 // recomputed at the start of the next step.  The hop uniforms are keyed by the global index, so
 // a trajectory's dynamics do not depend on where it sits.
 
+#include <algorithm>
+
 #include "iesh_internal.hpp"
 
 namespace iesh {
@@ -76,7 +78,19 @@ __global__ __launch_bounds__(kMoveThreads) void k_compact_move(ClassDev c, const
   for (size_t e = threadIdx.x; e < len; e += kMoveThreads) out[e] = src[e];
 }
 
+__global__ __launch_bounds__(256) void k_fill(double* p, size_t count, double value) {
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256)
+    p[e] = value;
+}
+
 }  // namespace
+
+hipError_t launch_fill(double* p, size_t count, double value, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, count, value);
+  return hipGetLastError();
+}
 
 hipError_t launch_compact_rank(const ClassDev& c, int32_t* dst, int32_t* n_active, hipStream_t s) {
   hipLaunchKernelGGL(k_compact_rank, dim3(1), dim3(kRankThreads), 0, s, c, dst, n_active);

@@ -629,8 +629,12 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
 
 // ---------------------------------------------------------------------------
 // Exact hop filter.  For orbitals with orthonormal columns, S^H S =
-// I - C_U^H C_U, so sigma_min(S)^2 >= 1 - ||C_U||_F^2 - delta (delta covers the
-// orthonormality defect of the stored orbitals), and by Cauchy-Schwarz
+// I - C_U^H C_U, so sigma_min(S)^2 >= 1 - ||C_U||_F^2 - delta, where delta
+// bounds the orthonormality defect ||C^H C - I|| of the stored orbitals
+// (FP64: a fixed 1e-8; mixed: the larger of 1e-3 and four times the defect
+// the last Loewdin step measured before correcting, i.e. the growth over one
+// Loewdin period; the mixed path without Loewdin steps never measures it and
+// runs without the filter), and by Cauchy-Schwarz
 //   |W[b][r]| = |C_U[b, :] S^-1 e_r| <= ||C_U[b, :]|| / sigma_min(S).
 // Hence the total hop probability of the step is bounded by
 //   sum_{r, b} g <= 2 dt sum_b ||C_U[b, :]|| sum_r |v D[b][s_r]| / sigma_min(S).
@@ -730,7 +734,7 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
   const double fro2 = L.red[0], S1 = L.red2[0];
   const int64_t step = cnt->step;
   const double xi = philox_uniform(seed, (uint32_t)c.gtraj[t], (uint64_t)step, 0u);
-  const double smin2 = 1.0 - fro2 - delta;
+  const double smin2 = 1.0 - fro2 - (c.defect ? fmax(delta, kDefectSafety * c.defect[c.home[t]]) : delta);
   // no hop when the bound on the total lies below the uniform; an adaptive
   // step also needs the bound to keep the next step at its largest (the
   // total, at most the bound, then selects dt0 exactly)
@@ -906,8 +910,8 @@ hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt
 hipError_t launch_hop_filter(const ClassDev& c, double dt, uint64_t seed, Counters* cnt, int record,
                              int exit_enabled, double exit_x, int64_t max_steps, int precision,
                              hipStream_t s) {
-  // orthonormality defect allowed for the stored orbitals
-  const double delta = (precision == IESH_FP64) ? 1e-8 : 1e-3;
+  // orthonormality defect allowed for the stored orbitals (floor)
+  const double delta = (precision == IESH_FP64) ? kDeltaFP64 : kDeltaMixed;
   if (c.n_live < 1) return hipSuccess;
   if (precision == IESH_FP64)
     hipLaunchKernelGGL(k_hop_filter<false>, dim3(c.n_live), dim3(kFltThreads), 0, s, c, dt, seed,

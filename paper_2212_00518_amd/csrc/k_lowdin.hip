@@ -46,13 +46,14 @@ __device__ inline double2 cmad(double2 acc, double2 a, double2 b) {  // acc + a 
 __device__ inline double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
 
 template <int kRI>
-__global__ __launch_bounds__(kLowThreads) void k_lowdin(ClassDev c, const Counters* cnt,
+__global__ __launch_bounds__(kLowThreads) void k_lowdin(ClassDev c, Counters* cnt,
                                                          int every, double2* scratch) {
   // 32-row slots covering the N orbitals; columns in groups of kCJ slots
   constexpr int kCJ = kRI < 2 ? kRI : 2;
   const int64_t step = cnt->step;     // step just completed
   if (every <= 0 || (step + 1) % every != 0) return;
   __shared__ LowLds L;
+  __shared__ double defect_part[kLowThreads / 64];
   const int N = c.md.N, n_pad = c.md.n_pad, n = c.md.n;
   double2* E = scratch + (size_t)blockIdx.x * ((2 * (size_t)N + 32 * kPassSlots) * N);
   double2* X = E + (size_t)N * N;
@@ -63,7 +64,8 @@ __global__ __launch_bounds__(kLowThreads) void k_lowdin(ClassDev c, const Counte
     if (c.status[t] & kFreezeMask) continue;  // uniform
     float2* C = reinterpret_cast<float2*>(c.C32) + (size_t)t * N * n_pad;  // C[j][s]
 
-    // ---- 1. G[i][j] = sum_s conj(C[i][s]) C[j][s]
+    // ---- 1. G[i][j] = sum_s conj(C[i][s]) C[j][s]; ||E||_F^2 on the way
+    double e2 = 0.0;
     for (int jb = 0; jb < N; jb += 32 * kCJ) {
     double2 acc[kRI][kCJ];
 #pragma unroll
@@ -98,11 +100,30 @@ __global__ __launch_bounds__(kLowThreads) void k_lowdin(ClassDev c, const Counte
 #pragma unroll
       for (int cj = 0; cj < kCJ; ++cj) {
         const int i = ti + 32 * ri, j = jb + tj + 32 * cj;
-        if (i < N && j < N)
-          E[(size_t)i * N + j] = make_double2(acc[ri][cj].x - (i == j ? 1.0 : 0.0), acc[ri][cj].y);
+        if (i < N && j < N) {
+          const double2 e = make_double2(acc[ri][cj].x - (i == j ? 1.0 : 0.0), acc[ri][cj].y);
+          E[(size_t)i * N + j] = e;
+          e2 += e.x * e.x + e.y * e.y;
+        }
       }
     }
+    // the defect this period left, before the correction: it sets the no-hop
+    // bound's allowance for the next period; a defect above the allowance of
+    // the period just ended is counted
+    for (int m = 32; m > 0; m >>= 1) e2 += __shfl_xor(e2, m);
+    if ((tid & 63) == 0) defect_part[tid >> 6] = e2;
     __syncthreads();  // E complete (block-scope visibility of the global writes)
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < kLowThreads / 64; ++w) tot += defect_part[w];
+      const double d = sqrt(tot);
+      double* dp = c.defect + c.home[t];
+      const double allowed = fmax(kDeltaMixed, kDefectSafety * *dp);
+      if (d > allowed) atomicAdd((unsigned long long*)&cnt->defect_violations, 1ull);
+      *dp = d;
+      atomicMax((unsigned long long*)&cnt->defect_max_bits,
+                (unsigned long long)__double_as_longlong(d));
+    }
 
     // ---- 2. X = I - E/2 + 3/8 E^2, E^2[i][j] = sum_k conj(E[k][i]) E[k][j]
     for (int jb = 0; jb < N; jb += 32 * kCJ) {
@@ -225,7 +246,7 @@ size_t lowdin_scratch_elems(const ClassDev& c) {
   return (size_t)lowdin_blocks(c) * ((2 * N + 32 * kPassSlots) * N);
 }
 
-hipError_t launch_lowdin(const ClassDev& c, const Counters* cnt, int every, double2* scratch,
+hipError_t launch_lowdin(const ClassDev& c, Counters* cnt, int every, double2* scratch,
                          hipStream_t s) {
   const int nb = lowdin_blocks(c);
   if (nb <= 0) return hipSuccess;

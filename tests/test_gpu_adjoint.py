@@ -274,3 +274,52 @@ def test_full_ensemble_of_1024_paths_sampled():
         ref = adj.loss(p, x[t], N, dt, TERMS)
         assert abs(loss[t] - ref) <= 1e-10 * abs(ref), (t, loss[t], ref)
         _check_grad(rows[t, :npar], w[t] * adj.gradient(p, x[t], N, dt, TERMS), f"path {t}")
+
+
+def test_workload_length_path_against_the_tangent_in_four_directions():
+    """One path of the adjoint workload's length and model size (M = 100,
+    N = 50, 2000 steps, checkpoints every 100, all four loss terms): the GPU
+    loss against the oracle's loss (1e-9 relative) and the GPU gradient,
+    projected on four parameter directions (eps_d, Gamma, omega and a dense
+    random direction over every parameter), against the oracle's
+    tangent-linear derivative in those directions (1e-7 of the projection's
+    scale sum_i |g_i d_i|).  The oracle runs one process per direction."""
+    import multiprocessing as mp
+    import os
+    p, dt = _model(100)
+    N, n_steps, ckpt = 50, 2000, 100
+    x = _paths(p, 1, n_steps, dt, seed=2024)
+    ens = _ensemble(p, N, 1, dt)
+    loss = ens.adjoint_forward(x, ckpt, TERMS)
+    g = ens.adjoint_backward(np.ones(1))[0, :adj.n_params(100)]
+    ens.close()
+    theta = adj.pack(p)
+    npar = len(theta)
+    dirs = []
+    for i in (0, 1, 2 + 100):   # eps_d, Gamma, omega
+        e = np.zeros(npar)
+        e[i] = 1.0
+        dirs.append(e)
+    rs = np.random.default_rng(7)
+    dirs.append(rs.normal(size=npar) * np.maximum(np.abs(theta), 1e-3))
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
+    os.environ["OMP_NUM_THREADS"] = os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    try:
+        with mp.get_context("spawn").Pool(len(dirs)) as pool:
+            refs = pool.starmap(adj.tangent, [(p, adj.unpack(d, p.w, p.mass), x[0], N, dt, TERMS)
+                                              for d in dirs])
+    finally:
+        for k, val in saved.items():
+            if val is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = val
+    ref_loss = refs[0][0]
+    print(f"loss {loss[0]:.15e} oracle {ref_loss:.15e}", flush=True)
+    assert abs(loss[0] - ref_loss) <= 1e-9 * abs(ref_loss)
+    for d, (_, tan) in zip(dirs, refs):
+        proj = float(g @ d)
+        scale = float(np.sum(np.abs(g * d)))
+        print(f"direction {np.flatnonzero(d)[:3]}: gpu {proj:.12e} tangent {tan:.12e} scale {scale:.3e}",
+              flush=True)
+        assert abs(proj - tan) <= 1e-7 * scale, (proj, tan, scale)

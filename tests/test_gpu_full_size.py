@@ -202,3 +202,67 @@ def test_double_well_trajectories_against_the_oracle(name, T, steps):
         compared += 1
     print("compared", compared, "of", T, flush=True)
     assert compared >= T - 2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_steady_state_step_after_1000_steps_m200(precision):
+    """The headline workload in its steady state: 4096 trajectories at
+    M = 200 pre-rolled for 1000 graph-replayed steps (orbitals mixed, the
+    exact determinant ratios needed on a fifth of the trajectory-steps), then
+    one more step of the whole ensemble.  From each of the 8 most mixed
+    sampled states (largest weight of the orbitals outside the occupied
+    set) the oracle takes the same step: positions, velocities, orbitals,
+    occupations and hop events must agree, and so must the hop
+    probabilities of the new state (iesh_hop_probs, the exact ratios).
+    Near-tie windows: 1e-7 (FP64) and 1e-4 (mixed) of the hop total."""
+    from oracle import rng
+    from paper_2212_00518_amd import from_config, unpack_C
+    cfg = get_config("c2")
+    T, N, pre = cfg["n_traj"], cfg["n_elec"], 1000
+    tx, tc = TOL[precision]
+    tie = 1e-7 if precision == "fp64" else 1e-4
+    x0, v0 = boltzmann_harmonic(T, cfg["model"]["mass"], cfg["model"]["omega"], cfg["kT"],
+                                seed=cfg["seed"], kT_factor=cfg.get("sample_kT_factor", 1.0))
+    ens = from_config(cfg, n_traj=T, precision=precision, lowdin_every=100)
+    ens.init_thermal(x0, v0)
+    ens.run(pre)
+    x, v, Cf, occ = ens.get_state()
+    n_max, N_max = ens.n_max, ens.N_max
+    n = cfg["bath"]["M"] + 1
+    # weight of every trajectory's orbitals on its unoccupied states
+    C3 = Cf.reshape(T, N_max, n_max)[:, :N, :n]
+    w_occ = np.take_along_axis(np.sum(np.abs(C3) ** 2, axis=1), occ[:, :N].astype(np.int64), axis=1)
+    mixing = N - np.sum(w_occ, axis=1)
+    sample = np.argsort(mixing)[-8:]
+    print(f"{precision}: mixing of the sampled states {mixing[sample]}", flush=True)
+    ens.clear_events()
+    ens.timing(True)
+    ens.step()
+    full_evals = ens.hop_evals()
+    ens.timing(False)
+    after = ens.get_state()
+    evs, _ = ens.events()
+    status = ens.status()
+    g = {int(t): ens.hop_probs(int(t), 1)[0] for t in sample}
+    ens.close()
+    assert np.all(status == 0)
+    assert full_evals > 0.05 * T, full_evals  # the exact-ratio kernel runs at its real rate
+    m = models.from_config(cfg)
+    compared = 0
+    for t in map(int, sample):
+        st = dyn.State([x[t]], [v[t]], unpack_C(Cf, t, n, N, n_max, N_max), occ[t, :N])
+        ref, ev, _ = dyn.step(m, st, cfg["dt"], rng.uniform(cfg["seed"], t, pre))
+        gref = dyn.hop_probs(m, ref, cfg["dt"])
+        gt = g[t][: N * n].reshape(N, n)
+        assert np.max(np.abs(gt - gref)) <= tx * np.max(gref), t
+        if ev["attempted"] and ev["margin"] < tie * ev["g_total"]:
+            continue
+        xa, va, Ca, occa = after
+        assert abs(xa[t] - ref.x[0]) <= tx * max(1.0, abs(ref.x[0])), t
+        assert abs(va[t] - ref.v[0]) <= tx * max(1e-3, abs(ref.v[0])), t
+        assert np.max(np.abs(unpack_C(Ca, t, n, N, n_max, N_max) - ref.C)) <= tc, t
+        assert list(occa[t, :N]) == list(ref.s), t
+        mine = [(e["a"], e["b"], e["accepted"]) for e in evs if e["traj"] == t]
+        assert mine == ([(ev["a"], ev["b"], ev["accepted"])] if ev["attempted"] else []), t
+        compared += 1
+    assert compared >= 6
