@@ -186,6 +186,8 @@ typedef struct iesh_run_desc {
 #define IESH_MAX_DOF 6        /* nuclear coordinates per trajectory            */
 #define IESH_JACOBI_MAX_N IESH_MAX_STATES  /* order limit of iesh_eigh_batched */
 #define IESH_JACOBI_LDS_N 96  /* orders up to this keep the matrix in LDS      */
+#define IESH_NOALLOC_SCRATCH_BYTES (64u << 20)  /* fixed device scratch of
+                                                   iesh_eigh_batched_noalloc  */
 
 /* Observables written per record and trajectory by iesh_run, in this order. */
 #define IESH_OBS_PD_SURF 0   /* sum_{a in s} Q[0][a]^2                         */
@@ -438,6 +440,25 @@ int iesh_sync(iesh_ctx* ctx);
    before any device call; iesh_last_error(NULL) gives the reason. */
 int iesh_eigh_batched(const double* H, int32_t n, int32_t batch, double* lam, double* Q,
                       int32_t* sweeps, int32_t mem_kind, void* hip_stream);
+
+/* The same decomposition for callers that cannot allocate device memory
+   (code under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): calls no hipMalloc, hipFree or allocating library routine.
+   The work space of orders above IESH_JACOBI_LDS_N comes from a fixed array
+   of IESH_NOALLOC_SCRATCH_BYTES in device memory that each GPU the library
+   runs on holds until the process ends; a batch whose work space
+   (2 m (m + 1) doubles per matrix, m = n rounded up to even) exceeds it is
+   rejected with IESH_EINVAL (split it), before any device call.  Every call
+   on one GPU shares that array: calls that overlap on one GPU (other streams
+   or host threads) race, calls on one stream are ordered by it.
+     H, lam, Q, sweeps : device pointers on the current device, layouts as in
+                         iesh_eigh_batched (sweeps may be NULL)
+     hip_stream        : hipStream_t (NULL = the null stream); the call only
+                         enqueues the kernel and does not synchronise.
+   Argument errors return IESH_EINVAL, launch errors IESH_EDEVICE;
+   iesh_last_error(NULL) gives the reason. */
+int iesh_eigh_batched_noalloc(const double* H, int32_t n, int32_t batch, double* lam, double* Q,
+                              int32_t* sweeps, void* hip_stream);
 
 /* Description of the last failure on ctx; with ctx = NULL, the reason the
    last context-free call (iesh_create, iesh_eigh_batched) on the calling

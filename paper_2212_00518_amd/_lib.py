@@ -45,7 +45,7 @@ SYMBOLS = (
     "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
     "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals", "iesh_class_info",
     "iesh_set_step_caps", "iesh_adjoint_forward", "iesh_adjoint_backward", "iesh_eigh_batched",
-    "iesh_orthonormality_defect",
+    "iesh_orthonormality_defect", "iesh_eigh_batched_noalloc",
 )
 TIMERS = ("eig", "prop", "hop", "lowdin", "filter", "adj_prop", "adj_phi", "adj_eig", "adj_hop")
 
@@ -109,6 +109,7 @@ def lib():
         L.iesh_traj_status.argtypes = [vp, ip]
         L.iesh_traj_clock.argtypes = [vp, dp, dp]
         L.iesh_eigh_batched.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, vp]
+        L.iesh_eigh_batched_noalloc.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp]
         L.iesh_events.argtypes = [vp, C.POINTER(Event), C.c_int64, C.POINTER(C.c_int64)]
         L.iesh_clear_events.argtypes = [vp]
         L.iesh_query_sizes.argtypes = [vp, C.POINTER(Sizes)]

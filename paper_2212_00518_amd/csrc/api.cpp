@@ -1562,3 +1562,7 @@ int iesh_adjoint_backward(iesh_ctx* ctx, const double* dloss, double* grad_out) 
 }
 
 }  // extern "C"
+
+namespace iesh {
+void set_call_error(const std::string& why) { g_create_err = why; }
+}  // namespace iesh

@@ -339,6 +339,10 @@ hipError_t launch_compact_rank(const ClassDev& c, int32_t* dst, int32_t* n_activ
 hipError_t launch_compact_move(const ClassDev& c, const int32_t* dst, const CompactBufs& b,
                                int precision, hipStream_t s);
 
+// Reason of the last failed context-free call on this thread (api.cpp):
+// what iesh_last_error(NULL) returns.
+void set_call_error(const std::string& why);
+
 // Host-side bath discretisation (bath.cpp).
 int discretize(int kind, int M, double a, double b, double eps_f, double* eps, double* w);
 
