@@ -387,13 +387,12 @@ def desorption_run(cfg, T, steps):
     steps, tiles per propagation work-group)."""
     import numpy as np
     import torch
-    from paper_2212_00518_amd import _lib, bath_grid, electrons_below
+    from paper_2212_00518_amd import _lib, bath_levels
     from workloads.sampling import wigner_harmonic
 
     m, b = cfg["model"], cfg["bath"]
-    eps, w = bath_grid(b, b["M"])
-    # fill the bath states below mu (half of them when the band follows mu)
-    n_elec = electrons_below(eps, b.get("mu", 0.0))
+    # the electrons fill the bath states below mu (half of them when the band follows mu)
+    eps, w, _, n_elec = bath_levels(b, b["M"])
     desc = _lib.model_desc(m, eps, w, n_elec)
     omega = m["a"] * np.sqrt(2.0 * m["De"] / m["mass"])  # harmonic frequency of the Morse U0
     x0, v0 = wigner_harmonic(T, m["mass"], omega, m["x0"], cfg["kT"], seed=cfg["seed"] + 1)

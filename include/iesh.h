@@ -107,7 +107,24 @@ enum iesh_bath_kind {
                                         and M/2 on [eps_f, b] (App. A)        */
 };
 
+enum iesh_band_placement {
+  IESH_BAND_CENTRED = 0,  /* the band [mu - W/2, mu + W/2] follows the chemical
+                             potential (wide-band limit); Gauss-Legendre split at mu */
+  IESH_BAND_FIXED = 1     /* the band stays [-W/2, W/2]; Gauss-Legendre split at mu  */
+};
+
 /* ---- descriptors -------------------------------------------------------- */
+/* Bath of a workload (iesh_bath). */
+typedef struct iesh_bath_desc {
+  int32_t kind;       /* enum iesh_bath_kind                                   */
+  int32_t M;          /* bath levels over all leads (a multiple of n_leads;
+                         Gauss-Legendre needs M / n_leads even)                */
+  int32_t n_leads;    /* 1, or 2: two leads on one grid                         */
+  int32_t placement;  /* enum iesh_band_placement                               */
+  double W;           /* band width > 0                                         */
+  double mu;          /* chemical potential (0: the band centred on 0)          */
+} iesh_bath_desc;
+
 typedef struct iesh_model_desc {
   int32_t kind;        /* enum iesh_model_kind                                */
   int32_t n_bath;      /* M >= 1; n = M + 1 <= IESH_MAX_STATES                */
@@ -229,6 +246,18 @@ int iesh_destroy(iesh_ctx* ctx);
    weights to host arrays.  Pure host computation. */
 int iesh_discretize(int32_t kind, int32_t M, double a, double b, double eps_f, double* eps,
                     double* w);
+
+/* Bath levels of a workload (App. A), placed for the chemical potential mu
+   (Sec. II.B, the paragraph on the chemical potential): a grid of
+   M / n_leads levels on the band of desc->placement by iesh_discretize
+   (Gauss-Legendre halves split at mu); with two leads (each coupled with
+   Gamma / 2, so that the total hybridisation stays Gamma) every grid level
+   is listed twice, lead 0 first, each copy with half its weight.  Writes M
+   energies (ascending) and weights, lead labels (may be NULL) and *n_below
+   (may be NULL), the number of levels strictly below mu: the electron count
+   that fills the bath up to the chemical potential.  Pure host computation;
+   IESH_EINVAL for a bad descriptor. */
+int iesh_bath(const iesh_bath_desc* desc, double* eps, double* w, int32_t* lead, int32_t* n_below);
 
 /* ---- state ----------------------------------------------------------------
    Layouts (both for host and device buffers):

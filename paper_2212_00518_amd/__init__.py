@@ -6,6 +6,5 @@ libiesh.so behind the C ABI of include/iesh.h; this package only marshals
 arguments (``_lib``) and builds ensembles from workload descriptions
 (``ensemble``).
 """
-from ._lib import Ensemble, IeshError, discretize, eigh_batched, model_desc, lib  # noqa: F401
-from .ensemble import (bath_grid, bath_levels, electrons_below, from_config, pack_states,  # noqa: F401
-                       unpack_C)
+from ._lib import Ensemble, IeshError, bath, discretize, eigh_batched, model_desc, lib  # noqa: F401
+from .ensemble import bath_levels, from_config, pack_states, unpack_C  # noqa: F401

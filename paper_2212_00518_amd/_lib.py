@@ -45,7 +45,7 @@ SYMBOLS = (
     "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
     "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals", "iesh_class_info",
     "iesh_set_step_caps", "iesh_adjoint_forward", "iesh_adjoint_backward", "iesh_eigh_batched",
-    "iesh_orthonormality_defect", "iesh_eigh_batched_noalloc",
+    "iesh_orthonormality_defect", "iesh_eigh_batched_noalloc", "iesh_bath",
 )
 TIMERS = ("eig", "prop", "hop", "lowdin", "filter", "adj_prop", "adj_phi", "adj_eig", "adj_hop")
 
@@ -66,6 +66,11 @@ class RunDesc(C.Structure):
                 ("elec_substeps", C.c_int32), ("hop_filter_off", C.c_int32), ("bias", C.c_double),
                 ("exit_dof", C.c_int32), ("dt_levels", C.c_int32), ("hop_gmax", C.c_double),
                 ("eig_max_iter", C.c_int32), ("reserved3", C.c_int32)]
+
+
+class BathDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("M", C.c_int32), ("n_leads", C.c_int32),
+                ("placement", C.c_int32), ("W", C.c_double), ("mu", C.c_double)]
 
 
 class Event(C.Structure):
@@ -97,6 +102,7 @@ def lib():
         L.iesh_destroy.argtypes = [vp]
         L.iesh_discretize.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
                                       dp, dp]
+        L.iesh_bath.argtypes = [C.POINTER(BathDesc), dp, dp, ip, ip]
         L.iesh_set_state.argtypes = [vp, vp, vp, vp, vp, C.c_int32]
         L.iesh_get_state.argtypes = [vp, vp, vp, vp, vp, C.c_int32]
         L.iesh_init_thermal.argtypes = [vp, dp, dp]
@@ -163,8 +169,7 @@ def eigh_batched(H):
 def discretize(kind: str, M: int, W: float, eps_f: float = 0.0, centre: float = 0.0):
     """Bath energies and weights on [centre - W/2, centre + W/2] from the
     library (Appendix A); the Gauss-Legendre halves split at eps_f."""
-    k = {"trapezoid": IESH_BATH_TRAPEZOID, "trapezoid_midpoint": IESH_BATH_TRAPEZOID_MIDPOINT,
-         "gauss_legendre": IESH_BATH_GAUSS_LEGENDRE}[kind]
+    k = BATH_KINDS[kind]
     eps = np.zeros(M)
     w = np.zeros(M)
     rc = lib().iesh_discretize(k, M, centre - 0.5 * W, centre + 0.5 * W, eps_f,
@@ -173,6 +178,29 @@ def discretize(kind: str, M: int, W: float, eps_f: float = 0.0, centre: float = 
     if rc != IESH_OK:
         raise IeshError(f"iesh_discretize failed ({rc})")
     return eps, w
+
+
+BATH_KINDS = {"trapezoid": IESH_BATH_TRAPEZOID, "trapezoid_midpoint": IESH_BATH_TRAPEZOID_MIDPOINT,
+              "gauss_legendre": IESH_BATH_GAUSS_LEGENDRE}
+IESH_BAND_CENTRED, IESH_BAND_FIXED = 0, 1
+
+
+def bath(kind: str, M: int, W: float, mu: float = 0.0, placement: str = "shift", n_leads: int = 1):
+    """iesh_bath: (eps, w, lead or None, levels below mu) of a bath of M
+    levels over n_leads leads, the band following mu ("shift") or fixed at
+    [-W/2, W/2] ("split")."""
+    d = BathDesc(BATH_KINDS[kind], int(M), int(n_leads),
+                 IESH_BAND_CENTRED if placement == "shift" else IESH_BAND_FIXED, float(W), float(mu))
+    eps = np.zeros(M)
+    w = np.zeros(M)
+    lead = np.zeros(M, dtype=np.int32)
+    nb = C.c_int32()
+    rc = lib().iesh_bath(C.byref(d), eps.ctypes.data_as(C.POINTER(C.c_double)),
+                         w.ctypes.data_as(C.POINTER(C.c_double)),
+                         lead.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(nb))
+    if rc != IESH_OK:
+        raise IeshError(f"iesh_bath failed ({rc})")
+    return eps, w, (lead if n_leads == 2 else None), nb.value
 
 
 def model_desc(model: dict, eps, w, n_elec: int, lead=None):

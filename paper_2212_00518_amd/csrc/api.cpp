@@ -670,6 +670,11 @@ int iesh_discretize(int32_t kind, int32_t M, double a, double b, double eps_f, d
   return discretize(kind, M, a, b, eps_f, eps, w);
 }
 
+int iesh_bath(const iesh_bath_desc* desc, double* eps, double* w, int32_t* lead, int32_t* n_below) {
+  if (!desc) return IESH_EINVAL;
+  return bath_levels(*desc, eps, w, lead, n_below);
+}
+
 int iesh_destroy(iesh_ctx* ctx) {
   if (!ctx) return IESH_OK;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);

@@ -80,4 +80,33 @@ int discretize(int kind, int M, double a, double b, double eps_f, double* eps, d
   return IESH_EINVAL;
 }
 
+// Bath of a workload: the band placed for the chemical potential, one or two
+// leads on one grid, and the number of levels below mu.
+int bath_levels(const iesh_bath_desc& d, double* eps, double* w, int32_t* lead,
+                int32_t* n_below) {
+  if (!eps || !w || !(d.W > 0.0) || !std::isfinite(d.W) || !std::isfinite(d.mu)) return IESH_EINVAL;
+  if (d.n_leads != 1 && d.n_leads != 2) return IESH_EINVAL;
+  if (d.M < d.n_leads || d.M % d.n_leads) return IESH_EINVAL;
+  if (d.placement != IESH_BAND_CENTRED && d.placement != IESH_BAND_FIXED) return IESH_EINVAL;
+  const double centre = d.placement == IESH_BAND_CENTRED ? d.mu : 0.0;
+  const double a = centre - 0.5 * d.W, b = centre + 0.5 * d.W;
+  const int Mg = d.M / d.n_leads;  // levels of the shared grid
+  std::vector<double> ge(Mg), gw(Mg);
+  const int rc = discretize(d.kind, Mg, a, b, d.mu, ge.data(), gw.data());
+  if (rc) return rc;
+  int below = 0;
+  for (int k = 0; k < Mg; ++k)
+    for (int l = 0; l < d.n_leads; ++l) {
+      // each lead couples with Gamma / n_leads: every grid level appears once
+      // per lead with that share of its weight, lead 0 first
+      const int q = k * d.n_leads + l;
+      eps[q] = ge[k];
+      w[q] = gw[k] / d.n_leads;
+      if (lead) lead[q] = l;
+      below += ge[k] < d.mu ? 1 : 0;
+    }
+  if (n_below) *n_below = below;
+  return IESH_OK;
+}
+
 }  // namespace iesh

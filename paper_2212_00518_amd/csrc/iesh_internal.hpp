@@ -345,5 +345,6 @@ void set_call_error(const std::string& why);
 
 // Host-side bath discretisation (bath.cpp).
 int discretize(int kind, int M, double a, double b, double eps_f, double* eps, double* w);
+int bath_levels(const iesh_bath_desc& d, double* eps, double* w, int32_t* lead, int32_t* n_below);
 
 }  // namespace iesh

@@ -6,40 +6,14 @@ import numpy as np
 from . import _lib
 
 
-def bath_grid(b: dict, M: int):
-    """Bath of a workload description, placed for its chemical potential mu
-    (default 0).  Placement "shift" moves the whole band so that its centre
-    and the Gauss-Legendre split sit at mu (wide-band limit); "split" keeps
-    the band [-W/2, W/2] and splits the Gauss-Legendre halves at mu
-    (Sec. II.B, chemical potential; App. A)."""
-    mu = b.get("mu", 0.0)
-    if b.get("placement", "shift") == "shift":
-        return _lib.discretize(b["kind"], M, b["W"], eps_f=mu, centre=mu)
-    return _lib.discretize(b["kind"], M, b["W"], eps_f=mu)
-
-
 def bath_levels(b: dict, M: int):
-    """Bath levels of a workload description: (eps, w, lead).  With
-    ``leads: 2`` the M levels are one grid of M/2 levels shared by two leads,
-    each coupled with half the hybridisation (half of every weight), listed
-    in ascending energy with lead 0 first at equal energy; lead is None for
-    one lead."""
-    if b.get("leads", 1) != 2:
-        eps, w = bath_grid(b, M)
-        return eps, w, None
-    if M % 2:
-        raise ValueError("two leads need an even number of bath levels")
-    e1, w1 = bath_grid(b, M // 2)
-    eps = np.repeat(e1, 2)
-    w = np.repeat(0.5 * w1, 2)
-    lead = np.tile(np.array([0, 1], dtype=np.int32), M // 2)
-    return eps, w, lead
-
-
-def electrons_below(eps, mu: float) -> int:
-    """Electron count that fills the bath states below mu in the lowest
-    configuration (Sec. II.B, chemical potential)."""
-    return int(np.sum(np.asarray(eps) < mu))
+    """Bath of a workload description from the library (iesh_bath): (eps, w,
+    lead, levels below mu).  The band follows the chemical potential mu
+    (placement "shift", the default) or keeps [-W/2, W/2] ("split"); with
+    ``leads: 2`` the M levels are one grid of M/2 levels shared by two leads;
+    lead is None for one lead."""
+    return _lib.bath(b["kind"], M, b["W"], mu=b.get("mu", 0.0), placement=b.get("placement", "shift"),
+                     n_leads=b.get("leads", 1))
 
 
 def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M: int | None = None,
@@ -51,7 +25,7 @@ def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M
     b = cfg["bath"]
     M = M if M is not None else b["M"]
     N = n_elec if n_elec is not None else cfg.get("n_elec", M // 2)
-    eps, w, lead = bath_levels(b, M)
+    eps, w, lead, _ = bath_levels(b, M)
     desc = _lib.model_desc(cfg["model"], eps, w, N, lead)
     run = dict(n_traj=n_traj if n_traj is not None else cfg["n_traj"], precision=precision,
                dt=cfg["dt"], kT=cfg.get("kT", 0.0), seed=cfg.get("seed", 0),

@@ -67,18 +67,52 @@ def test_band_placement_for_a_chemical_potential(kind, M, mu, placement):
     """The library's grid for a chemical potential mu equals the oracle's, and
     the states below mu are half of the bath when the band or the
     Gauss-Legendre split follows mu."""
-    from paper_2212_00518_amd import bath_grid, electrons_below
+    from paper_2212_00518_amd import bath_levels
     from oracle import models
     from workloads import get_config
     b = dict(kind=kind, M=M, W=0.1, mu=mu, placement=placement)
-    eps, w = bath_grid(b, M)
+    eps, w, lead, n_below = bath_levels(b, M)
     cfg = get_config("c1")
     cfg["bath"] = b
     m = models.from_config(cfg, M=M)
     e_ref = np.diag(m.H(np.array([0.0])))[1:]
     assert np.max(np.abs(eps - e_ref)) < 1e-15
     assert abs(np.sum(w) - 0.1) < 1e-14
-    assert electrons_below(eps, mu) == M // 2
+    assert lead is None
+    assert n_below == M // 2 == int(np.sum(e_ref < mu))
+
+
+@pytest.mark.parametrize("kind,M,mu,placement", [("trapezoid", 256, 0.0, "shift"),
+                                                 ("gauss_legendre", 200, 0.01, "shift"),
+                                                 ("trapezoid_midpoint", 64, -0.02, "split")])
+def test_two_lead_bath_matches_the_oracle(kind, M, mu, placement):
+    """Two leads on one grid from the library (iesh_bath) equal the oracle's
+    construction: the one-lead grid of M/2 levels with every level listed once
+    per lead at half its weight, lead 0 first; the levels below mu are
+    counted over both leads."""
+    from paper_2212_00518_amd import bath_levels
+    from oracle import bath as obath
+    b = dict(kind=kind, M=M, W=0.1, mu=mu, placement=placement, leads=2)
+    eps, w, lead, n_below = bath_levels(b, M)
+    centre = mu if placement == "shift" else 0.0
+    e1, w1 = obath.discretise(kind, M // 2, 0.1, eps_f=mu, centre=centre)
+    e_ref, w_ref, l_ref = obath.two_leads(e1, w1)
+    assert np.max(np.abs(eps - e_ref)) < 1e-15 and np.max(np.abs(w - w_ref)) < 1e-16
+    assert np.array_equal(lead, l_ref)
+    assert n_below == int(np.sum(e_ref < mu))
+    assert abs(np.sum(w) - 0.1) < 1e-14
+
+
+def test_bath_rejects_bad_descriptors(libiesh):
+    from paper_2212_00518_amd import _lib
+    with pytest.raises(_lib.IeshError):
+        _lib.bath("gauss_legendre", 6, 0.1, n_leads=2)      # 3 levels per lead: odd
+    with pytest.raises(_lib.IeshError):
+        _lib.bath("trapezoid", 7, 0.1, n_leads=2)           # not a multiple of the leads
+    with pytest.raises(_lib.IeshError):
+        _lib.bath("trapezoid", 8, 0.1, n_leads=3)
+    with pytest.raises(_lib.IeshError):
+        _lib.bath("gauss_legendre", 8, 0.1, mu=0.2, placement="split")  # split outside the band
 
 
 def test_discretisation_rejects_bad_arguments(libiesh):

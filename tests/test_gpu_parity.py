@@ -603,12 +603,11 @@ def test_single_step_with_the_band_placed_for_a_chemical_potential(mu_ev, placem
     """Desorption model with the chemical potential moved off the band centre
     (the band or only its Gauss-Legendre split follows mu; the electrons fill
     the bath states below mu): one step from random orbitals matches."""
-    from paper_2212_00518_amd import bath_grid, electrons_below
+    from paper_2212_00518_amd import bath_levels
     cfg = make_cfg("desorption", M=20)
     cfg["bath"]["mu"] = ev_to_ha(mu_ev)
     cfg["bath"]["placement"] = placement
-    eps, _ = bath_grid(cfg["bath"], 20)
-    N = electrons_below(eps, cfg["bath"]["mu"])
+    _, _, _, N = bath_levels(cfg["bath"], 20)
     assert N == 10
     cfg["n_elec"] = N
     m = models.from_config(cfg, M=20)
@@ -619,8 +618,8 @@ def test_single_step_with_the_band_placed_for_a_chemical_potential(mu_ev, placem
 
 # ------------------------------------------------------ electronic sub-steps
 def _substep_ensemble(cfg, T, S, precision="fp64"):
-    from paper_2212_00518_amd import _lib, bath_grid
-    eps, w = bath_grid(cfg["bath"], cfg["bath"]["M"])
+    from paper_2212_00518_amd import _lib, bath_levels
+    eps, w, _, _ = bath_levels(cfg["bath"], cfg["bath"]["M"])
     desc = _lib.model_desc(cfg["model"], eps, w, cfg["n_elec"])
     return _lib.Ensemble([desc], dict(n_traj=T, precision=precision, dt=cfg["dt"], kT=cfg["kT"],
                                       seed=cfg["seed"], elec_substeps=S,

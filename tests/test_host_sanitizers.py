@@ -18,7 +18,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2212_00518_amd", "csrc")
 BUILD = os.path.join(ROOT, "paper_2212_00518_amd", "_build")
-KERNELS = ["k_eig", "k_prop", "k_hop", "k_lowdin", "k_compact", "k_adjoint", "k_jacobi"]
+KERNELS = ["k_eig", "k_prop", "k_hop", "k_lowdin", "k_compact", "k_adjoint", "k_jacobi",
+           "eigh_noalloc"]
 SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
        "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
 
@@ -73,6 +74,30 @@ int main() {
       EXPECT(std::fabs(s - 0.1) < 1e-12);
     }
   EXPECT(iesh_discretize(0, 0, -0.05, 0.05, 0.0, nullptr, nullptr) == IESH_EINVAL);
+  // bath of a workload: one and two leads, both placements, levels below mu
+  for (int kind = 0; kind < 3; ++kind)
+    for (int leads = 1; leads <= 2; ++leads)
+      for (int M = 4; M <= 320; M += 4 * (M < 40 ? 1 : 19)) {
+        iesh_bath_desc d;
+        std::memset(&d, 0, sizeof d);
+        d.kind = kind;
+        d.M = M;
+        d.n_leads = leads;
+        d.placement = (M / 4) % 2;
+        d.W = 0.1;
+        d.mu = 0.01;
+        std::vector<double> e(M), w(M);
+        std::vector<int32_t> l(M);
+        int32_t nb = -1;
+        const int rc = iesh_bath(&d, e.data(), w.data(), l.data(), &nb);
+        if (kind == 2 && (M / leads) % 2) { EXPECT(rc == IESH_EINVAL); continue; }
+        EXPECT(rc == IESH_OK);
+        EXPECT(nb >= 0 && nb <= M);
+        double s = 0.0;
+        for (int k = 0; k < M; ++k) s += w[k];
+        EXPECT(std::fabs(s - 0.1) < 1e-12);
+      }
+  EXPECT(iesh_bath(nullptr, nullptr, nullptr, nullptr, nullptr) == IESH_EINVAL);
   // each argument check of iesh_create, before any device call
   std::vector<double> e(8), w(8, 0.1 / 8);
   for (int k = 0; k < 8; ++k) e[k] = -0.05 + k * 0.1 / 7;
