@@ -204,10 +204,46 @@ class MultiDof(Model):
         return self.Vbar[:, None] * df[None, :]
 
 
+class Dense(Model):
+    """A one-electron Hamiltonian of any symmetric structure, affine in one
+    nuclear coordinate: H(x) = H0 + x H1, dH/dx = H1 (Eq.
+    single_electron_discrete_electronic_hamiltonian for a general H; state 0
+    is the impurity |d> for the observables), with the harmonic nuclear
+    potential U0 = m omega^2 (x - x_c)^2 / 2."""
+
+    def __init__(self, H0, H1, mass, omega, x_c=0.0):
+        H0 = np.asarray(H0, dtype=np.float64)
+        H1 = np.asarray(H1, dtype=np.float64)
+        self.H0, self.H1 = H0.copy(), H1.copy()
+        self.n = H0.shape[0]
+        self.M = self.n - 1
+        self.eps = np.diag(H0)[1:].copy()
+        self.mass = np.atleast_1d(np.asarray(mass, dtype=np.float64))
+        self.omega, self.x_c = float(omega), float(x_c)
+        self.k = self.mass[0] * self.omega ** 2
+
+    def U0(self, x):
+        return 0.5 * self.k * (x[0] - self.x_c) ** 2
+
+    def dU0(self, x):
+        return np.array([self.k * (x[0] - self.x_c)])
+
+    def H(self, x):
+        return self.H0 + np.atleast_1d(x)[0] * self.H1
+
+    def dH(self, x):
+        return [self.H1.copy()]
+
+
 def from_config(cfg: dict, M: int | None = None):
     """Build a model from a workload description (``workloads.configs``)."""
     mcfg, bcfg = cfg["model"], cfg["bath"]
     M = M if M is not None else bcfg["M"]
+    if mcfg["kind"] == "dense":
+        from workloads import dense_matrices
+        H0, H1 = dense_matrices(cfg, M)
+        m = Dense(H0, H1, mcfg["mass"], mcfg["omega"], mcfg.get("x_c", 0.0))
+        return m
     # chemical potential mu: the band moves with mu ("shift", wide-band limit)
     # or only the Gauss-Legendre split does ("split")
     mu = bcfg.get("mu", 0.0)

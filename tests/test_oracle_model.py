@@ -258,3 +258,59 @@ def test_vector_rescaling_conserves_energy_along_the_coupling():
             assert np.max(np.abs(cross)) < 1e-12 * max(np.max(np.abs(dp)), 1e-30)
         else:
             assert np.array_equal(v2, v)
+
+
+# ------------------------------------------------------------- dense model kind
+def test_dense_model_with_rank_one_h1_is_the_double_well():
+    """H0 = the double-well H at x = 0 and H1 = h' e0 e0^T give exactly the
+    double-well model (Sec. III.B): equal H(x), dH/dx, U0, forces and one
+    oracle step from the same state."""
+    from oracle import bath, dynamics as dyn, rng
+    from oracle import electronic as el
+    from workloads.sampling import random_orbitals
+    eps, w = bath.discretise("trapezoid", 12, 0.1)
+    harm = models.Harmonic(eps, w, 0.01, 2000.0, 2e-4, 20.0, -3.8e-3)
+    H0 = harm.H(np.array([0.0]))
+    H1 = harm.dH(np.array([0.0]))[0]
+    dense = models.Dense(H0, H1, 2000.0, 2e-4)
+    for x in (-6.0, 0.0, 3.5, 11.0):
+        X = np.array([x])
+        assert np.max(np.abs(dense.H(X) - harm.H(X))) <= 1e-15
+        assert np.array_equal(dense.dH(X)[0], harm.dH(X)[0])
+        assert dense.U0(X) == harm.U0(X) and dense.dU0(X)[0] == harm.dU0(X)[0]
+    st = dyn.State([2.0], [1e-3], random_orbitals(13, 6, seed=4), [0, 2, 3, 5, 7, 9])
+    for k in range(3):
+        xi = rng.uniform(0, 0, k)
+        a, ea, _ = dyn.step(harm, st, 20.0, xi)
+        b, eb, _ = dyn.step(dense, st, 20.0, xi)
+        assert np.max(np.abs(a.C - b.C)) <= 1e-12 and abs(a.x[0] - b.x[0]) <= 1e-12
+        assert list(a.s) == list(b.s)
+        st = a
+
+
+def test_dense_workload_couplings_and_forces_against_finite_differences():
+    """The dense workload's H(x) (impurity plus a tight-binding chain, x-dependent
+    impurity couplings): D = <j|d/dx k> against central differences of
+    gauge-fixed eigenvectors, the Hellmann-Feynman force against differences of
+    E_pot; every orbital keeps a clear impurity component (the gauge
+    Q[0, j] > 0 is continuous)."""
+    from oracle import electronic as el
+    from workloads import get_config
+    m = models.from_config(get_config("dense"), M=30)
+    h = 1e-6
+    for x in (-4.0, 2.0, 9.0):
+        X = np.array([x])
+        H = m.H(X)
+        off = H - np.diag(np.diag(H))
+        assert np.count_nonzero(off[1:, 1:]) > 0          # not an arrowhead
+        lam, Q = el.eig(H)
+        assert np.min(np.abs(Q[0])) > 1e-4
+        _, Ds = el.coupling_matrices(lam, Q, m.dH(X))
+        _, Qp = el.eig(m.H(X + h))
+        _, Qm = el.eig(m.H(X - h))
+        fd = Q.T @ (Qp - Qm) / (2 * h)
+        assert np.max(np.abs(Ds[0] - fd)) < 1e-6 * np.max(np.abs(Ds[0]))
+        for s in ([0, 1, 2, 3], [2, 5, 9, 20]):
+            F = el.forces(m, X, s)[0]
+            fdF = -(el.potential_energy(m, X + 1e-5, s) - el.potential_energy(m, X - 1e-5, s)) / 2e-5
+            assert abs(F - fdF) < 1e-7 * max(1e-4, abs(F))

@@ -125,8 +125,48 @@ CONFIGS = {
         n_elec=50, kT=9.5e-4, n_traj=1024, n_steps=2000, dt=20.0, ckpt_every=100,
         seed=0,
     ),
+    # General (dense) one-electron Hamiltonian, the fallback for H(x) of any
+    # structure: the double-well impurity on a band of 95 levels whose levels
+    # also couple to their neighbours (a tight-binding chain, hopping t_bath),
+    # with an x-dependent impurity coupling V_k(x) = V_k (1 + alpha x); H(x) =
+    # H0 + x H1 with a rank-2 H1 (workloads.dense_matrices builds both).
+    "dense": dict(
+        name="dense H(x) = H0 + x H1, n=96 (impurity + 95-level chain), N=48, 4096 trajectories, dt=20",
+        model=dict(kind="dense", mass=2000.0, omega=2e-4, g=20.0, dG=-3.8e-3, Gamma=0.01,
+                   t_bath=2.0e-4, alpha=0.02, x_c=0.0),
+        bath=dict(kind="cells", M=95, W=0.1),
+        n_elec=48, kT=9.5e-4, sample_kT_factor=1.0,
+        n_traj=4096, n_steps=2000, dt=20.0, seed=0,
+    ),
 }
 
 
 def get_config(name: str) -> dict:
     return copy.deepcopy(CONFIGS[name])
+
+
+def dense_matrices(cfg: dict, M: int | None = None):
+    """H0 and H1 of a dense workload (H(x) = H0 + x H1), as plain input
+    arrays: impurity level h(x) = m omega^2 (g^2 - 2 g x)/2 + dG of the
+    double well, M bath levels at the cell centres of [-W/2, W/2] (equal
+    widths W/M), impurity couplings V_k (1 + alpha x) with
+    V_k = sqrt(Gamma (W/M) / (2 pi)), and nearest-neighbour couplings t_bath
+    between bath levels."""
+    import numpy as np
+    m, b = cfg["model"], cfg["bath"]
+    M = M if M is not None else b["M"]
+    W = b["W"]
+    eps = -0.5 * W + (np.arange(M) + 0.5) * (W / M)
+    V = np.full(M, np.sqrt(m["Gamma"] * (W / M) / (2.0 * np.pi)))
+    k = m["mass"] * m["omega"] ** 2
+    n = M + 1
+    H0 = np.zeros((n, n))
+    H0[0, 0] = 0.5 * k * m["g"] ** 2 + m["dG"]
+    H0[0, 1:] = H0[1:, 0] = V
+    H0[1:, 1:] = np.diag(eps)
+    idx = np.arange(1, M)
+    H0[idx, idx + 1] = H0[idx + 1, idx] = m["t_bath"]
+    H1 = np.zeros((n, n))
+    H1[0, 0] = -k * m["g"]
+    H1[0, 1:] = H1[1:, 0] = m["alpha"] * V
+    return H0, H1
