@@ -88,7 +88,16 @@ enum iesh_model_kind {
        V_k(R) = Vbar_k f(R),  f(R) = exp(-sum_nu (R_nu - c_nu)^2 / (4 s_nu^2))
      (so Gamma(R) = Gamma f^2 is a Gaussian in R).  params: [0] Delta,
      [1] eps_d; dof: n_dof rows of (mass, D, a, r, g, c, s).               */
-  IESH_MODEL_MULTI_DOF = 2
+  IESH_MODEL_MULTI_DOF = 2,
+  /* A one-electron Hamiltonian of any symmetric structure, affine in one
+     coordinate: H(x) = H0 + x H1, dH/dx = H1 (the caller's matrices, field
+     dense), n = n_bath + 1 <= IESH_DENSE_MAX_N, state 0 the impurity |d>
+     for the observables; U0 = m omega^2 (x - x_c)^2 / 2.  Eigenvectors are
+     sign-fixed so that their first nonzero component is positive (the
+     impurity component unless it vanishes), which is continuous along a
+     path as long as no impurity component passes through zero.  eps, w,
+     Gamma and lead are not used; no bias.  params: [0] omega, [1] x_c.     */
+  IESH_MODEL_DENSE = 3
 };
 
 enum iesh_precision {
@@ -146,6 +155,8 @@ typedef struct iesh_model_desc {
                           (mass > 0, D, a, r, g, c, s > 0); else unused       */
   const int32_t* lead; /* host, M labels 0 or 1 (two leads), or NULL (one lead).
                           Only iesh_init_thermal with run.bias != 0 reads them */
+  const double* dense; /* host, IESH_MODEL_DENSE: H0 then H1, each n x n
+                          row-major and symmetric; else unused (NULL)       */
 } iesh_model_desc;
 
 typedef struct iesh_run_desc {
@@ -201,6 +212,8 @@ typedef struct iesh_run_desc {
 #define IESH_MAX_STATES 336   /* n = M + 1 limit of the library               */
 #define IESH_MAX_ELEC 168     /* N limit of the library                       */
 #define IESH_MAX_DOF 6        /* nuclear coordinates per trajectory            */
+#define IESH_DENSE_MAX_N 96   /* n limit of IESH_MODEL_DENSE (its eigen-solve
+                                 keeps the matrix and the rotations in LDS)    */
 #define IESH_JACOBI_MAX_N IESH_MAX_STATES  /* order limit of iesh_eigh_batched */
 #define IESH_JACOBI_LDS_N 96  /* orders up to this keep the matrix in LDS      */
 #define IESH_NOALLOC_SCRATCH_BYTES (64u << 20)  /* fixed device scratch of

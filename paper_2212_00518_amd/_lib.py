@@ -20,6 +20,8 @@ IESH_EINVAL, IESH_ENOMEM, IESH_EDEVICE, IESH_ESTATE, IESH_ENOTSUP = -1, -2, -3, 
 IESH_MODEL_HARMONIC = 0
 IESH_MODEL_MORSE_TANH = 1
 IESH_MODEL_MULTI_DOF = 2
+IESH_MODEL_DENSE = 3
+IESH_DENSE_MAX_N = 96
 IESH_MAX_DOF = 6
 IESH_FP64 = 0
 IESH_MIXED = 1
@@ -55,7 +57,7 @@ class ModelDesc(C.Structure):
                 ("n_dof", C.c_int32), ("eps", C.POINTER(C.c_double)),
                 ("w", C.POINTER(C.c_double)), ("mass", C.c_double), ("Gamma", C.c_double),
                 ("params", C.c_double * 16), ("dof", C.POINTER(C.c_double)),
-                ("lead", C.POINTER(C.c_int32))]
+                ("lead", C.POINTER(C.c_int32)), ("dense", C.POINTER(C.c_double))]
 
 
 class RunDesc(C.Structure):
@@ -201,6 +203,29 @@ def bath(kind: str, M: int, W: float, mu: float = 0.0, placement: str = "shift",
     if rc != IESH_OK:
         raise IeshError(f"iesh_bath failed ({rc})")
     return eps, w, (lead if n_leads == 2 else None), nb.value
+
+
+def dense_model_desc(H0, H1, mass: float, omega: float, n_elec: int, x_c: float = 0.0):
+    """iesh_model_desc of IESH_MODEL_DENSE: H(x) = H0 + x H1 (n x n
+    symmetric), U0 = m omega^2 (x - x_c)^2 / 2."""
+    H0 = np.ascontiguousarray(H0, dtype=np.float64)
+    H1 = np.ascontiguousarray(H1, dtype=np.float64)
+    if H0.ndim != 2 or H0.shape[0] != H0.shape[1] or H1.shape != H0.shape:
+        raise ValueError("H0, H1: n x n")
+    mats = np.ascontiguousarray(np.concatenate([H0.ravel(), H1.ravel()]))
+    d = ModelDesc()
+    d.kind = IESH_MODEL_DENSE
+    d.n_bath = H0.shape[0] - 1
+    d.n_elec = int(n_elec)
+    d.n_dof = 1
+    d.mass = float(mass)
+    d.Gamma = 0.0
+    p = [0.0] * 16
+    p[:2] = [float(omega), float(x_c)]
+    d.params[:] = p
+    d.dense = mats.ctypes.data_as(C.POINTER(C.c_double))
+    d._keep = (mats,)
+    return d
 
 
 def model_desc(model: dict, eps, w, n_elec: int, lead=None):

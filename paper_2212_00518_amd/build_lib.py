@@ -16,7 +16,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libiesh.so")
 
 SOURCES = ["api.cpp", "bath.cpp", "k_eig.hip", "k_prop.hip", "k_hop.hip", "k_lowdin.hip",
-           "k_compact.hip", "k_adjoint.hip", "k_jacobi.hip", "eigh_noalloc.hip"]
+           "k_compact.hip", "k_adjoint.hip", "k_jacobi.hip", "eigh_noalloc.hip",
+           "k_dense.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.

@@ -257,7 +257,54 @@ BathPoles bath_poles(const iesh_model_desc& d) {
   return b;
 }
 
+int validate_dense(const iesh_model_desc& m, std::string& why) {
+  if (m.n_dof > 1) {
+    why = "IESH_MODEL_DENSE has one coordinate";
+    return 0;
+  }
+  if (m.n_bath < 1 || m.n_bath + 1 > IESH_DENSE_MAX_N) {
+    why = "IESH_MODEL_DENSE: n = n_bath + 1 out of range [2, IESH_DENSE_MAX_N]";
+    return 0;
+  }
+  if (m.n_elec < 1 || m.n_elec > m.n_bath) {
+    why = "n_elec out of range";
+    return 0;
+  }
+  if (!m.dense) {
+    why = "IESH_MODEL_DENSE needs the matrices H0 and H1 (dense)";
+    return 0;
+  }
+  const int n = m.n_bath + 1;
+  for (int h = 0; h < 2; ++h) {
+    const double* H = m.dense + (size_t)h * n * n;
+    double big = 0.0;
+    for (int q = 0; q < n * n; ++q) {
+      if (!std::isfinite(H[q])) {
+        why = "IESH_MODEL_DENSE: non-finite matrix element";
+        return 0;
+      }
+      big = std::max(big, std::fabs(H[q]));
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < i; ++j)
+        if (std::fabs(H[(size_t)i * n + j] - H[(size_t)j * n + i]) > 1e-14 * big) {
+          why = h ? "IESH_MODEL_DENSE: H1 is not symmetric" : "IESH_MODEL_DENSE: H0 is not symmetric";
+          return 0;
+        }
+  }
+  if (!(m.mass > 0.0) || !std::isfinite(m.params[0]) || !std::isfinite(m.params[1])) {
+    why = "mass must be > 0 and omega, x_c finite";
+    return 0;
+  }
+  if (m.lead) {
+    why = "IESH_MODEL_DENSE has no leads";
+    return 0;
+  }
+  return 1;
+}
+
 int validate_model(const iesh_model_desc& m, std::string& why) {
+  if (m.kind == IESH_MODEL_DENSE) return validate_dense(m, why);
   if (m.kind != IESH_MODEL_HARMONIC && m.kind != IESH_MODEL_MORSE_TANH &&
       m.kind != IESH_MODEL_MULTI_DOF) {
     why = "unknown model kind";
@@ -515,16 +562,21 @@ int enqueue_step(iesh_ctx* ctx, int record) {
     hipStream_t s = ctx->stream;
     Counters* cnt = ctx->cnt;
     const int S = r.elec_substeps;
+    // eigen-solve, couplings, propagator set-up and Verlet: the arrowhead
+    // solver, or the dense one for IESH_MODEL_DENSE
+    auto eig = [&](int sub, int nsub) {
+      return c.Gd ? launch_dense_step(c, r.dt, cnt, s, sub, nsub) : launch_eig_step(c, r.dt, cnt, s, sub, nsub);
+    };
     if (S <= 1) {
-      HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return launch_eig_step(c, r.dt, cnt, s); }));
+      HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return eig(-1, 1); }));
       HIPTRY(ctx, timed(ctx, IESH_TIMER_PROP, [&] { return launch_prop(c, r.precision, s); }));
     } else {
       // electronic sub-steps: a propagator and a propagation each, then the end point
       for (int j = 0; j < S; ++j) {
-        HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return launch_eig_step(c, r.dt, cnt, s, j, S); }));
+        HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return eig(j, S); }));
         HIPTRY(ctx, timed(ctx, IESH_TIMER_PROP, [&] { return launch_prop(c, r.precision, s); }));
       }
-      HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return launch_eig_step(c, r.dt, cnt, s, -2, S); }));
+      HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return eig(-2, S); }));
     }
     HIPTRY(ctx, timed(ctx, IESH_TIMER_FILTER, [&] {
              return launch_hop_filter(c, r.dt, r.seed, cnt, record, r.exit_enabled, r.exit_x,
@@ -829,6 +881,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     const int T = c.n_traj, n_pad = c.md.n_pad, N = c.md.N, M = c.md.M;
     if (T == 0) continue;
     const int nd = c.md.ndof;
+    const bool dense = d.kind == IESH_MODEL_DENSE;
     if ((rc = dalloc(ctx, &c.eps, M)) || (rc = dalloc(ctx, &c.vbar, M)) ||
         (rc = dalloc(ctx, &c.x, (size_t)T * nd)) || (rc = dalloc(ctx, &c.v, (size_t)T * nd)) ||
         (rc = dalloc(ctx, &c.F, (size_t)T * nd)) ||
@@ -845,6 +898,26 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
       return bail(rc);
     if (hop_needs_scratch(c) && (rc = dalloc(ctx, &c.hopx, (size_t)T * N * N)))
       return bail(rc);
+    if (dense) {
+      double *h0 = nullptr, *h1 = nullptr;
+      if ((rc = dalloc(ctx, &h0, (size_t)n_pad * n_pad)) || (rc = dalloc(ctx, &h1, (size_t)n_pad * n_pad)) ||
+          (rc = dalloc(ctx, &c.Gd, (size_t)T * n_pad * n_pad)))
+        return bail(rc);
+      const int n = c.md.n;
+      std::vector<double> pad((size_t)2 * n_pad * n_pad, 0.0);
+      for (int h = 0; h < 2; ++h)
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j)
+            pad[(size_t)h * n_pad * n_pad + (size_t)i * n_pad + j] = d.dense[(size_t)h * n * n + (size_t)i * n + j];
+      if (hipMemcpyAsync(h0, pad.data(), (size_t)n_pad * n_pad * sizeof(double), hipMemcpyHostToDevice,
+                         ctx->stream) != hipSuccess ||
+          hipMemcpyAsync(h1, pad.data() + (size_t)n_pad * n_pad, (size_t)n_pad * n_pad * sizeof(double),
+                         hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+          hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return (fail(ctx, IESH_EDEVICE, "upload of the dense model failed"), bail(IESH_EDEVICE));
+      c.H0 = h0;
+      c.H1 = h1;
+    }
     if (r.compact_every > 0) {
       CompactBufs& b = ctx->spare[m];
       const size_t csz = (size_t)T * N * n_pad * 2;
@@ -882,15 +955,21 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
       return (fail(ctx, IESH_EDEVICE, std::string("propagation LDS attribute: ") +
                                          hipGetErrorString(e)),
               bail(IESH_EDEVICE));
+    std::vector<int32_t> gt;
+    for (int t = 0; t < r.n_traj; ++t)
+      if (ctx->traj_class[t] == m) gt.push_back(t);
+    if (dense) {  // no bath poles: the eigen-solve is the dense one
+      if (hipMemcpyAsync(c.gtraj, gt.data(), T * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream) ||
+          hipStreamSynchronize(ctx->stream))
+        return (fail(ctx, IESH_EDEVICE, "upload of model data failed"), bail(IESH_EDEVICE));
+      continue;
+    }
     // poles of the secular function: groups of equal bath energies, each
     // with the summed weight (V^2 of the coupled combination)
     const BathPoles bp = bath_poles(d);
     const int Mr = (int)bp.eps.size();
     std::vector<double> vb(Mr);
     for (int q = 0; q < Mr; ++q) vb[q] = std::sqrt(d.Gamma * bp.w[q] / (2.0 * M_PI));
-    std::vector<int32_t> gt;
-    for (int t = 0; t < r.n_traj; ++t)
-      if (ctx->traj_class[t] == m) gt.push_back(t);
     int32_t* expand = nullptr;
     double* lead0 = nullptr;
     if (Mr < M && (rc = dalloc(ctx, &expand, (size_t)c.md.n))) return bail(rc);
@@ -1011,7 +1090,8 @@ int iesh_set_state(iesh_ctx* ctx, const double* x, const double* v, const double
   if ((rc = upload_state(ctx, x, v, C, occ))) return rc;
   if ((rc = reset_traj_words(ctx))) return rc;
   for (auto& c : ctx->cls)
-    if (c.n_traj) HIPTRY(ctx, launch_forces(c, ctx->stream));
+    if (c.n_traj)
+      HIPTRY(ctx, c.Gd ? launch_dense_query(c, 0, c.n_traj, 1, ctx->stream) : launch_forces(c, ctx->stream));
   HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
   return IESH_OK;
 }
@@ -1023,7 +1103,9 @@ int iesh_init_thermal(iesh_ctx* ctx, const double* x, const double* v) {
   if ((rc = upload_state(ctx, x, v, nullptr, nullptr))) return rc;
   if ((rc = reset_traj_words(ctx))) return rc;
   for (auto& c : ctx->cls)
-    if (c.n_traj) HIPTRY(ctx, launch_init_thermal(c, ctx->run.kT, ctx->run.bias, ctx->run.seed, ctx->stream));
+    if (c.n_traj)
+      HIPTRY(ctx, c.Gd ? launch_dense_init_thermal(c, ctx->run.kT, ctx->run.seed, ctx->stream)
+                       : launch_init_thermal(c, ctx->run.kT, ctx->run.bias, ctx->run.seed, ctx->stream));
   HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
   return IESH_OK;
 }
@@ -1203,7 +1285,7 @@ int iesh_hop_probs(iesh_ctx* ctx, int32_t traj0, int32_t ntraj, double* g_out, i
     const int t = traj0 + q;
     ClassDev& c = ctx->cls[ctx->traj_class[t]];
     const int tl = ctx->home_slot[ctx->traj_class[t]][ctx->traj_local[t]];
-    HIPTRY(ctx, launch_eig_query(c, tl, 1, ctx->stream));
+    HIPTRY(ctx, c.Gd ? launch_dense_query(c, tl, 1, 0, ctx->stream) : launch_eig_query(c, tl, 1, ctx->stream));
     HIPTRY(ctx, launch_hop(c, ctx->run.dt, ctx->run.seed, ctx->cnt, ctx->events, 1, tl, 1, 0, 0,
                            0.0, 0, ctx->run.precision, ctx->stream));
     const int N = c.md.N, n = c.md.n, n_pad = c.md.n_pad;
@@ -1229,7 +1311,7 @@ int iesh_adiabatic(iesh_ctx* ctx, int32_t traj0, int32_t ntraj, double* lam_out,
     const int t = traj0 + q;
     ClassDev& c = ctx->cls[ctx->traj_class[t]];
     const int tl = ctx->home_slot[ctx->traj_class[t]][ctx->traj_local[t]];
-    HIPTRY(ctx, launch_eig_query(c, tl, 1, ctx->stream));
+    HIPTRY(ctx, c.Gd ? launch_dense_query(c, tl, 1, 0, ctx->stream) : launch_eig_query(c, tl, 1, ctx->stream));
     const int n = c.md.n, n_pad = c.md.n_pad;
     std::vector<double> l(n_pad), qq(n_pad);
     HIPTRY(ctx, hipMemcpyAsync(l.data(), c.lam + (size_t)tl * n_pad, n_pad * sizeof(double),

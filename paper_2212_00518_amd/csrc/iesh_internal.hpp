@@ -118,6 +118,12 @@ struct ClassDev {
   // correction (0 before the first); the no-hop bound allows a defect of
   // max(delta floor, kDefectSafety * this) for the stored orbitals
   double* defect = nullptr;
+  // dense model kind (H(x) = H0 + x H1): [n_pad][n_pad] each, zero-padded,
+  // shared by the class; Gd [T][n_pad][n_pad] = Q^T H1 Q at the last solve
+  // (ascending, sign-fixed basis), read by the hop kernels
+  const double* H0 = nullptr;
+  const double* H1 = nullptr;
+  double* Gd = nullptr;
   int32_t* hopq = nullptr;  // [3 + T] queue for the determinant-ratio kernel: count, -, done, list
   double2* hopx = nullptr;  // [T][N][N] inverse of S (shapes whose registers cannot hold it)
   // prescribed nuclear path (adjoint): x of trajectory g at step n is
@@ -298,6 +304,12 @@ size_t jacobi_work_elems(int n, int batch);  // doubles of global workspace (0: 
 hipError_t launch_jacobi(const double* H, int n, int batch, double* lam, double* Q, int32_t* sweeps,
                          double* work, hipStream_t s);
 hipError_t launch_forces(const ClassDev& c, hipStream_t s);
+// dense model kind (k_dense.hip)
+size_t dense_lds_size(int n_pad);
+hipError_t launch_dense_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s, int sub = -1,
+                             int nsub = 1);
+hipError_t launch_dense_query(const ClassDev& c, int t0, int nt, int mode, hipStream_t s);
+hipError_t launch_dense_init_thermal(const ClassDev& c, double kT, uint64_t seed, hipStream_t s);
 hipError_t launch_prop(const ClassDev& c, int precision, hipStream_t s);
 hipError_t launch_prop_taps(const ClassDev& c, int mode, double* taps, int tap_k, hipStream_t s);
 int prop_max_col_tiles(int precision);

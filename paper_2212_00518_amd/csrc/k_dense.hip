@@ -1,0 +1,535 @@
+// Step kernels for a one-electron Hamiltonian of any symmetric structure,
+// affine in one nuclear coordinate: H(x) = H0 + x H1, dH/dx = H1 (Eq.
+// single_electron_discrete_electronic_hamiltonian without the arrowhead
+// structure; the couplings of Sec. II.B, G = Q^T (dH/dx) Q,
+// D_jk = G_jk / (lambda_k - lambda_j), and the Hellmann-Feynman force of
+// Eq. classical_hamiltonian, F = -U0' - sum_{a in s} G_aa).
+//
+// One work-group (8 waves) per trajectory.  The eigen-decomposition of
+// H(x) runs in LDS: the matrix and the accumulated rotations, both padded to
+// n_pad = n rounded up to 16 with a row stride of n_pad + 1 doubles, take
+// 2 n_pad (n_pad + 1) doubles, which bounds n at IESH_DENSE_MAX_N (96).  It
+// is the cyclic two-sided Jacobi method (Golub and Van Loan): every sweep
+// visits each index pair once in m - 1 rounds of m/2 disjoint pairs
+// (round-robin over m = n rounded up to even), so the rotations of a round
+// are independent and one pass rotates rows, a second columns; a pair is
+// skipped once |a_pq| <= eps sqrt(|a_pp a_qq|) (the relative stopping rule
+// of Demmel and Veselic).  Eigenvalues are ranked ascending; each
+// eigenvector's first nonzero component (the impurity component, generically)
+// is made positive.
+//
+// The projection G = V^T (H1 V) is two dense products of order n_pad on the
+// FP64 matrix cores (16x16x4 instructions; A operands from H1 in memory or
+// from V in LDS, B operands from LDS): T = H1 V overwrites the diagonalised
+// matrix in LDS, then G = V^T T is written to the trajectory's block of Gd in
+// the ranked, sign-fixed basis.  The midpoint solve turns G into B = v D in
+// the propagation kernel's tile order with the Gershgorin interval of
+// A = diag(lambda) - i B and the Chebyshev block; the end-point solve leaves
+// lambda, Q[0, :] and G for the hop kernels and completes velocity Verlet.
+
+#include "iesh_cheb.hpp"
+#include "iesh_internal.hpp"
+
+namespace iesh {
+namespace {
+
+constexpr int kDenThreads = 512;
+constexpr int kDenWaves = kDenThreads / 64;
+constexpr int kJacobiSweeps = 60;
+constexpr double kEpsD = 2.220446049250313e-16;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Views of the dynamic LDS of one work-group (np = n_pad, ld = np + 1).
+struct DenLds {
+  double* A;     // [np][ld]: H(x), rotated to diagonal form; then T = H1 V
+  double* V;     // [np][ld]: accumulated rotations, eigenvectors in columns
+  double* lam;   // [np]: eigenvalues, ascending
+  double* q0;    // [np]: impurity components (ascending order, sign-fixed)
+  double* dj;    // [np]: eigenvalue of Jacobi column j
+  double* sg;    // [np]: sign applied to Jacobi column j
+  double* cs;    // [np/2]: cosines of a round
+  double* sn;    // [np/2]: sines of a round
+  double* red;   // [2 kDenWaves]: per-wave partial results
+  double* J;     // [kMaxCheb]: Bessel values
+  double* nuc;   // [4]: half-step velocity, new position, propagator position, force
+  int* rank;     // [np]: position of Jacobi column j in ascending order
+  int* pq;       // [np]: the pairs of a round
+  int* flag;     // [4]: rotation happened, failure bits, scratch
+};
+
+__host__ __device__ inline size_t dense_lds_bytes(int np) {
+  const size_t ld = np + 1;
+  return sizeof(double) * (2 * (size_t)np * ld + 4 * (size_t)np + (size_t)np + 2 * kDenWaves +
+                           kMaxCheb + 4) +
+         sizeof(int) * (2 * (size_t)np + 4);
+}
+
+__device__ inline DenLds dense_lds(double* sm, int np) {
+  DenLds L;
+  const size_t ld = np + 1;
+  L.A = sm;
+  L.V = L.A + (size_t)np * ld;
+  L.lam = L.V + (size_t)np * ld;
+  L.q0 = L.lam + np;
+  L.dj = L.q0 + np;
+  L.sg = L.dj + np;
+  L.cs = L.sg + np;
+  L.sn = L.cs + np / 2;
+  L.red = L.sn + np / 2;
+  L.J = L.red + 2 * kDenWaves;
+  L.nuc = L.J + kMaxCheb;
+  L.rank = reinterpret_cast<int*>(L.nuc + 4);
+  L.pq = L.rank + np;
+  L.flag = L.pq + np;
+  return L;
+}
+
+// Sum of v over the work-group (every thread gets it).
+__device__ inline double block_sum(double v, double* red) {
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kDenWaves; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+__device__ inline double block_min(double v, double* red) {
+  for (int m = 32; m > 0; m >>= 1) v = fmin(v, __shfl_xor(v, m));
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int w = 1; w < kDenWaves; ++w) s = fmin(s, red[w]);
+  __syncthreads();
+  return s;
+}
+
+__device__ inline double block_max(double v, double* red) { return -block_min(-v, red); }
+
+// Eigen-decomposition of H(x) = H0 + x H1 in LDS; afterwards L.lam, L.q0 hold
+// the ascending eigenvalues and impurity components, L.dj / L.sg / L.rank the
+// Jacobi-order eigenvalues, signs and ranks, L.V the eigenvectors (Jacobi
+// order, unsigned).  Returns false when the sweeps did not converge.
+__device__ bool dense_eigen(const ClassDev& c, double x, DenLds& L) {
+  const int tid = threadIdx.x;
+  const int n = c.md.n, np = c.md.n_pad, ld = np + 1;
+  const int m = n + (n & 1), half = m / 2;
+  const double* H0 = c.H0;
+  const double* H1 = c.H1;
+  for (int idx = tid; idx < np * np; idx += kDenThreads) {
+    const int i = idx / np, j = idx - i * np;
+    L.A[(size_t)i * ld + j] = H0[idx] + x * H1[idx];  // zero outside n x n
+    L.V[(size_t)i * ld + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  bool converged = false;
+  for (int sweep = 0; sweep < kJacobiSweeps; ++sweep) {
+    if (tid == 0) L.flag[0] = 0;
+    __syncthreads();
+    for (int r = 0; r < m - 1; ++r) {
+      for (int k = tid; k < half; k += kDenThreads) {
+        int p, q;
+        if (k == 0) {
+          p = r;
+          q = m - 1;
+        } else {
+          p = (r + k) % (m - 1);
+          q = (r - k + (m - 1)) % (m - 1);
+        }
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        double cth = 1.0, sth = 0.0;
+        if (q < n) {
+          const double apq = L.A[(size_t)p * ld + q];
+          const double app = L.A[(size_t)p * ld + p], aqq = L.A[(size_t)q * ld + q];
+          if (apq != 0.0 && fabs(apq) > kEpsD * sqrt(fabs(app) * fabs(aqq))) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double tt = copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            cth = 1.0 / sqrt(1.0 + tt * tt);
+            sth = tt * cth;
+            L.flag[0] = 1;
+          }
+        }
+        L.pq[2 * k] = p;
+        L.pq[2 * k + 1] = q;
+        L.cs[k] = cth;
+        L.sn[k] = sth;
+      }
+      __syncthreads();
+      // rows p, q of every pair
+      for (int idx = tid; idx < half * m; idx += kDenThreads) {
+        const int k = idx / m, j = idx - k * m;
+        const double s = L.sn[k];
+        if (s == 0.0) continue;
+        const double cth = L.cs[k];
+        const int p = L.pq[2 * k], q = L.pq[2 * k + 1];
+        const double ap = L.A[(size_t)p * ld + j], aq = L.A[(size_t)q * ld + j];
+        L.A[(size_t)p * ld + j] = cth * ap - s * aq;
+        L.A[(size_t)q * ld + j] = s * ap + cth * aq;
+      }
+      __syncthreads();
+      // columns p, q of A and V
+      for (int idx = tid; idx < half * m; idx += kDenThreads) {
+        const int k = idx / m, j = idx - k * m;
+        const double s = L.sn[k];
+        if (s == 0.0) continue;
+        const double cth = L.cs[k];
+        const int p = L.pq[2 * k], q = L.pq[2 * k + 1];
+        const double ap = L.A[(size_t)j * ld + p], aq = L.A[(size_t)j * ld + q];
+        L.A[(size_t)j * ld + p] = (j == q) ? 0.0 : cth * ap - s * aq;
+        L.A[(size_t)j * ld + q] = (j == p) ? 0.0 : s * ap + cth * aq;
+        const double vp = L.V[(size_t)j * ld + p], vq = L.V[(size_t)j * ld + q];
+        L.V[(size_t)j * ld + p] = cth * vp - s * vq;
+        L.V[(size_t)j * ld + q] = s * vp + cth * vq;
+      }
+      __syncthreads();
+    }
+    const int any = L.flag[0];
+    __syncthreads();
+    if (!any) {
+      converged = true;
+      break;
+    }
+  }
+  // rank (ascending, ties by index) and sign (first nonzero component > 0)
+  for (int j = tid; j < np; j += kDenThreads) L.dj[j] = (j < n) ? L.A[(size_t)j * ld + j] : 0.0;
+  __syncthreads();
+  for (int j = tid; j < n; j += kDenThreads) {
+    const double d = L.dj[j];
+    int rk = 0;
+    for (int i = 0; i < n; ++i) {
+      const double di = L.dj[i];
+      rk += (di < d || (di == d && i < j)) ? 1 : 0;
+    }
+    double sgn = 1.0;
+    for (int i = 0; i < n; ++i) {
+      const double v = L.V[(size_t)i * ld + j];
+      if (v != 0.0) {
+        sgn = v < 0.0 ? -1.0 : 1.0;
+        break;
+      }
+    }
+    L.rank[j] = rk;
+    L.sg[j] = sgn;
+    L.lam[rk] = d;
+    L.q0[rk] = sgn * L.V[j];
+  }
+  for (int j = n + tid; j < np; j += kDenThreads) {
+    L.rank[j] = j;
+    L.sg[j] = 0.0;  // padding columns carry no state
+    L.lam[j] = 0.0;
+    L.q0[j] = 0.0;
+  }
+  __syncthreads();
+  return converged;
+}
+
+// G = V^T H1 V on the matrix cores into Gd (ranked, sign-fixed basis; rows
+// and columns n .. n_pad - 1 untouched).  T = H1 V overwrites L.A.
+__device__ void dense_project(const ClassDev& c, DenLds& L, double* Gd) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int n = c.md.n, np = c.md.n_pad, ld = np + 1, RT = np / 16, KB = np / 4;
+  const double* H1 = c.H1;
+  // T = H1 V (the diagonalised matrix in L.A is no longer needed)
+  for (int tile = wave; tile < RT * RT; tile += kDenWaves) {
+    const int rt = tile / RT, ct = tile - rt * RT;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const double* arow = H1 + (size_t)(rt * 16 + lr) * np + lk;
+    const double* bcol = L.V + (size_t)lk * ld + ct * 16 + lr;
+    for (int kb = 0; kb < KB; ++kb)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[4 * kb], bcol[(size_t)4 * kb * ld], acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) L.A[(size_t)(rt * 16 + lk + 4 * r) * ld + ct * 16 + lr] = acc[r];
+  }
+  __syncthreads();
+  // G = V^T T, scattered to the ranked basis with the column signs
+  for (int tile = wave; tile < RT * RT; tile += kDenWaves) {
+    const int rt = tile / RT, ct = tile - rt * RT;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const double* acol = L.V + (size_t)lk * ld + rt * 16 + lr;  // V[i][a]: A operand of V^T
+    const double* bcol = L.A + (size_t)lk * ld + ct * 16 + lr;
+    for (int kb = 0; kb < KB; ++kb)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(acol[(size_t)4 * kb * ld], bcol[(size_t)4 * kb * ld],
+                                                 acc, 0, 0, 0);
+    const int b = ct * 16 + lr;
+    for (int r = 0; r < 4; ++r) {
+      const int a = rt * 16 + lk + 4 * r;
+      if (a < n && b < n) Gd[(size_t)L.rank[a] * np + L.rank[b]] = L.sg[a] * L.sg[b] * acc[r];
+    }
+  }
+  __syncthreads();  // Gd complete (work-group visibility of the global writes)
+}
+
+// D_jk = G_jk / (lambda_k - lambda_j); zero on the diagonal and between
+// states whose energies agree to 1e-12 of the largest |lambda|.
+__device__ inline double dense_D(const double* Gd, const DenLds& L, int np, double tol, int j, int k) {
+  const double diff = L.lam[k] - L.lam[j];
+  return (j == k || fabs(diff) <= tol) ? 0.0 : Gd[(size_t)j * np + k] / diff;
+}
+
+__device__ inline double lam_tol(const DenLds& L, int n) {
+  return 1e-12 * fmax(fabs(L.lam[0]), fabs(L.lam[n - 1]));
+}
+
+// Hellmann-Feynman force of the occupied set: -U0'(x) - sum_{a in s} G_aa.
+__device__ double dense_force(const ClassDev& c, const double* Gd, const int32_t* occ, double x,
+                              DenLds& L) {
+  const int np = c.md.n_pad;
+  double part = 0.0;
+  for (int r = threadIdx.x; r < c.md.N; r += kDenThreads) {
+    const int a = occ[r];
+    part += Gd[(size_t)a * np + a];
+  }
+  const double s = block_sum(part, L.red);
+  const double k = c.md.mass * c.md.p[0] * c.md.p[0];
+  return -k * (x - c.md.p[1]) - s;
+}
+
+__device__ inline void dense_geo(double* geo, const ModelDev& md, double x) {
+  const double k = md.mass * md.p[0] * md.p[0];
+  const double u = x - md.p[1];
+  geo[GEO_U0] = 0.5 * k * u * u;
+  geo[GEO_DU0] = k * u;
+  geo[GEO_DU0V] = k * u;
+  geo[GEO_H] = 0.0;
+  geo[GEO_DH] = 0.0;
+  geo[GEO_RHO] = 0.0;
+}
+
+// One step of one trajectory up to the propagation (sub as in k_eig_step:
+// -1 the whole step, j >= 0 the propagator of electronic sub-step j of nsub,
+// -2 the end point only).
+__global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double dt_run, int precision,
+                                                             Counters* cnt, int sub, int nsub) {
+  extern __shared__ double sm[];
+  const int t = blockIdx.x, tid = threadIdx.x;
+  if (c.status[t] & kFreezeMask) return;
+  const ModelDev& md = c.md;
+  const int n = md.n, np = md.n_pad, RT = np / 16;
+  DenLds L = dense_lds(sm, np);
+  const double dt = c.clock ? c.clock[2 * (size_t)t] : dt_run;
+  if (tid == 0) {
+    const double x = c.x[t], v = c.v[t], F = c.F[t];
+    const double vh = v + 0.5 * dt * F / md.mass;
+    const double xn = x + dt * vh;
+    L.nuc[0] = vh;
+    L.nuc[1] = xn;
+    L.nuc[2] = (sub >= 0) ? x + ((sub + 0.5) / nsub) * (xn - x) : 0.5 * (x + xn);
+    L.flag[1] = 0;
+  }
+  __syncthreads();
+  const double vh = L.nuc[0];
+  const double dte = (sub >= 0) ? dt / nsub : dt;
+  double* Gd = c.Gd + (size_t)t * np * np;
+  if (sub != -2) {
+    // ---- propagator geometry: B = v D in the propagation's tile order
+    if (!dense_eigen(c, L.nuc[2], L) && tid == 0) L.flag[1] |= 1;
+    dense_project(c, L, Gd);
+    const double tol = lam_tol(L, n);
+    double* Bt = c.Bt ? c.Bt + (size_t)t * np * np : nullptr;
+    float* Bt32 = c.Bt32 ? c.Bt32 + (size_t)t * np * np : nullptr;
+    double lo_part = 1e300, hi_part = -1e300;
+    for (int j = tid; j < np; j += kDenThreads) {
+      const int rt = j >> 4, lane_lo = j & 15;
+      double rsum = 0.0;
+      for (int k = 0; k < np; ++k) {
+        const double val = (j < n && k < n) ? vh * dense_D(Gd, L, np, tol, j, k) : 0.0;
+        rsum += fabs(val);
+        const size_t off = ((size_t)((k >> 2) * RT + rt) << 6) + lane_lo + ((k & 3) << 4);
+        if (precision == IESH_FP64)
+          Bt[off] = val;
+        else
+          Bt32[off] = (float)val;
+      }
+      if (j < n) {
+        lo_part = fmin(lo_part, L.lam[j] - rsum);
+        hi_part = fmax(hi_part, L.lam[j] + rsum);
+      }
+      c.lam_mid[(size_t)t * np + j] = L.lam[j];
+    }
+    const double lo = block_min(lo_part, L.red), hi = block_max(hi_part, L.red);
+    if (tid == 0) {
+      double* cb = c.cheb + (size_t)t * kChebStride;
+      if (write_cheb(cb, lo, hi, dte, precision, cnt, sub <= 0, L.J) < 0) L.flag[1] |= 2;
+    }
+    __syncthreads();
+    if (sub >= 0) {
+      if (tid == 0 && L.flag[1]) c.status[t] |= IESH_TRAJ_NONCONV;
+      return;
+    }
+  }
+  // ---- end point: energies, amplitudes, couplings for the hop, forces
+  const double xn = L.nuc[1];
+  if (!dense_eigen(c, xn, L) && tid == 0) L.flag[1] |= 1;
+  dense_project(c, L, Gd);
+  for (int j = tid; j < np; j += kDenThreads) {
+    c.lam[(size_t)t * np + j] = L.lam[j];
+    c.q0[(size_t)t * np + j] = L.q0[j];
+  }
+  const double F = dense_force(c, Gd, c.occ + (size_t)t * md.N, xn, L);
+  if (tid == 0) {
+    double* geo = c.geo + (size_t)t * kGeoStride;
+    dense_geo(geo, md, xn);
+    int st = c.status[t];
+    const double vn = vh + 0.5 * dt * F / md.mass;
+    c.x[t] = xn;
+    c.v[t] = vn;
+    c.F[t] = F;
+    if (!isfinite(xn) || !isfinite(vn)) st |= IESH_TRAJ_NONFINITE;
+    if (L.flag[1]) st |= IESH_TRAJ_NONCONV;
+    c.status[t] = st;
+  }
+}
+
+// Eigen-solve and couplings at the current x (no dynamics); mode 1 also
+// refreshes the force of the current occupations.
+__global__ __launch_bounds__(kDenThreads) void k_dense_query(ClassDev c, int t0, int mode) {
+  extern __shared__ double sm[];
+  const int t = t0 + blockIdx.x, tid = threadIdx.x;
+  const ModelDev& md = c.md;
+  const int np = md.n_pad;
+  DenLds L = dense_lds(sm, np);
+  const double x = c.x[t];
+  const bool ok = dense_eigen(c, x, L);
+  double* Gd = c.Gd + (size_t)t * np * np;
+  dense_project(c, L, Gd);
+  for (int j = tid; j < np; j += kDenThreads) {
+    c.lam[(size_t)t * np + j] = L.lam[j];
+    c.q0[(size_t)t * np + j] = L.q0[j];
+  }
+  if (tid == 0) dense_geo(c.geo + (size_t)t * kGeoStride, md, x);
+  if (mode == 1) {
+    const double F = dense_force(c, Gd, c.occ + (size_t)t * md.N, x, L);
+    if (tid == 0) {
+      c.F[t] = F;
+      if (!ok) c.status[t] |= IESH_TRAJ_NONCONV;
+    }
+  }
+}
+
+__device__ inline double fermi_d(double e, double mu, double kT) {
+  const double z = (e - mu) / kT;
+  return (z > 0.0) ? exp(-z) / (1.0 + exp(-z)) : 1.0 / (1.0 + exp(z));
+}
+
+// Initial occupations at kT (fixed N: chemical potential by bisection, one
+// uniform per level and attempt from Philox stream 1, the lowest N after
+// 4096 failed attempts or at kT = 0) and unit-vector orbitals, as for the
+// other model kinds.
+__global__ __launch_bounds__(kDenThreads) void k_dense_init_thermal(ClassDev c, double kT,
+                                                                     uint64_t seed) {
+  extern __shared__ double sm[];
+  const int t = blockIdx.x, tid = threadIdx.x;
+  const ModelDev& md = c.md;
+  const int n = md.n, np = md.n_pad, N = md.N;
+  DenLds L = dense_lds(sm, np);
+  const double x = c.x[t];
+  const bool ok = dense_eigen(c, x, L);
+  double* Gd = c.Gd + (size_t)t * np * np;
+  dense_project(c, L, Gd);
+  int32_t* occ = c.occ + (size_t)t * N;
+  // the chosen levels reuse the rank array (no longer needed)
+  int* chosen = L.rank;
+  bool done = false;
+  if (kT > 0.0) {
+    double lo = L.lam[0] - 50.0 * kT - 1.0, hi = L.lam[n - 1] + 50.0 * kT + 1.0;
+    for (int it = 0; it < 200; ++it) {
+      const double mu = 0.5 * (lo + hi);
+      double part = 0.0;
+      for (int a = tid; a < n; a += kDenThreads) part += fermi_d(L.lam[a], mu, kT);
+      if (block_sum(part, L.red) > (double)N)
+        hi = mu;
+      else
+        lo = mu;
+    }
+    const double mu = 0.5 * (lo + hi);
+    const uint32_t gt = (uint32_t)c.gtraj[t];
+    for (int attempt = 0; attempt < 4096 && !done; ++attempt) {
+      int cntl = 0;
+      for (int a = tid; a < n; a += kDenThreads) {
+        const double u = philox_uniform(seed, gt, (uint64_t)attempt * n + a, 1u);
+        chosen[a] = (u < fermi_d(L.lam[a], mu, kT)) ? 1 : 0;
+        cntl += chosen[a];
+      }
+      done = ((int)block_sum((double)cntl, L.red) == N);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int r = 0;
+    for (int a = 0; a < n; ++a)
+      if (done ? chosen[a] : (a < N)) occ[r++] = a;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < N * np; idx += kDenThreads) {
+    const int j = idx / np, i = idx % np;
+    const double val = (i == occ[j]) ? 1.0 : 0.0;
+    if (c.C64) {
+      c.C64[((size_t)t * N * np + idx) * 2] = val;
+      c.C64[((size_t)t * N * np + idx) * 2 + 1] = 0.0;
+    }
+    if (c.C32) {
+      c.C32[((size_t)t * N * np + idx) * 2] = (float)val;
+      c.C32[((size_t)t * N * np + idx) * 2 + 1] = 0.0f;
+    }
+  }
+  for (int j = tid; j < np; j += kDenThreads) {
+    c.lam[(size_t)t * np + j] = L.lam[j];
+    c.q0[(size_t)t * np + j] = L.q0[j];
+  }
+  const double F = dense_force(c, Gd, occ, x, L);
+  if (tid == 0) {
+    dense_geo(c.geo + (size_t)t * kGeoStride, md, x);
+    c.F[t] = F;
+    c.status[t] = ok ? 0 : IESH_TRAJ_NONCONV;
+  }
+}
+
+hipError_t set_lds(const void* fn, size_t bytes) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace
+
+size_t dense_lds_size(int n_pad) { return dense_lds_bytes(n_pad); }
+
+hipError_t launch_dense_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s, int sub,
+                             int nsub) {
+  const int precision = c.C64 ? IESH_FP64 : IESH_MIXED;
+  if (c.n_live < 1) return hipSuccess;
+  const size_t lds = dense_lds_bytes(c.md.n_pad);
+  hipError_t e = set_lds((const void*)k_dense_step, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dense_step, dim3(c.n_live), dim3(kDenThreads), lds, s, c, dt, precision, cnt,
+                     sub, nsub);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_query(const ClassDev& c, int t0, int nt, int mode, hipStream_t s) {
+  if (nt < 1) return hipSuccess;
+  const size_t lds = dense_lds_bytes(c.md.n_pad);
+  hipError_t e = set_lds((const void*)k_dense_query, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dense_query, dim3(nt), dim3(kDenThreads), lds, s, c, t0, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_init_thermal(const ClassDev& c, double kT, uint64_t seed, hipStream_t s) {
+  if (c.n_traj < 1) return hipSuccess;
+  const size_t lds = dense_lds_bytes(c.md.n_pad);
+  hipError_t e = set_lds((const void*)k_dense_init_thermal, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dense_init_thermal, dim3(c.n_traj), dim3(kDenThreads), lds, s, c, kT, seed);
+  return hipGetLastError();
+}
+
+}  // namespace iesh

@@ -22,6 +22,7 @@
 //
 // One work-group per trajectory; 256 threads; every array lives in LDS.
 
+#include "iesh_cheb.hpp"
 #include "iesh_internal.hpp"
 
 namespace iesh {
@@ -348,53 +349,6 @@ __device__ inline double vD_elem(const EigLds& L, const ModelAt& ma, double v, i
   return g == 0.0 ? 0.0 : v * g * rcp_nr(lam_diff(L, k, j));
 }
 
-// Bessel J_k(rho), k = 0..K, by Miller's downward recurrence normalised with
-// J_0 + 2 sum_{k>=1} J_{2k} = 1.
-__device__ void bessel_j(int K, double rho, double* J) {
-  for (int k = 0; k <= K; ++k) J[k] = 0.0;
-  if (rho < 1e-300) {
-    J[0] = 1.0;
-    return;
-  }
-  const int base = (K > (int)rho ? K : (int)rho);
-  int m = base + 30 + (int)sqrt(40.0 * (base + 1));
-  m += (m & 1);
-  double jp1 = 0.0, jk = 1e-280, norm = 0.0;
-  for (int k = m; k > 0; --k) {
-    const double jm1 = (2.0 * k / rho) * jk - jp1;  // J_{k-1}
-    jp1 = jk;
-    jk = jm1;
-    if (fabs(jk) > 1e250) {
-      jk *= 1e-250;
-      jp1 *= 1e-250;
-      norm *= 1e-250;
-      for (int q = 0; q <= K; ++q) J[q] *= 1e-250;
-    }
-    const int km1 = k - 1;
-    if (km1 <= K) J[km1] = jk;
-    if (km1 > 0 && (km1 & 1) == 0) norm += 2.0 * jk;
-  }
-  norm += jk;  // J_0
-  const double inv = 1.0 / norm;
-  for (int k = 0; k <= K; ++k) J[k] *= inv;
-}
-
-// Number of Chebyshev terms so that the tail sum_{k>K} 2|J_k(rho)| < tol,
-// bounding |J_k(rho)| by (rho/2)^k / k!.
-__device__ int cheb_terms(double rho, double tol) {
-  const double h = 0.5 * rho;
-  double term = 1.0;  // (rho/2)^k / k!
-  for (int k = 0; k < kMaxCheb - 1; ++k) {
-    const double next = term * h / (k + 1);  // bound of |J_{k+1}|
-    if (k + 2 > h) {
-      const double tail = 2.0 * next / (1.0 - h / (k + 2));
-      if (tail < tol) return k > 0 ? k : 1;
-    }
-    term = next;
-  }
-  return -1;
-}
-
 __device__ void write_model_geo(double* geo, const ModelAt& ma) {
   geo[GEO_H] = ma.h;
   geo[GEO_DH] = ma.dh;
@@ -573,40 +527,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt_
   }
   if (tid == 0) {
     double* cb = c.cheb + (size_t)t * kChebStride;
-    const double lo = L.red[0], hi = L.red2[0];
-    const double cc = 0.5 * (lo + hi);
-    const double rr = fmax(0.5 * (hi - lo), 1e-300);
-    const double rho = rr * dte;
-    const int K = cheb_terms(rho, precision == IESH_FP64 ? 2e-16 : 1e-8);
-    if (K < 0) {
-      atomicOr(&L.fail, 2);
-    } else {
-      double* J = L.J;
-      bessel_j(K, rho, J);
-      double sn, cs;
-      sincos(cc * dte, &sn, &cs);
-      // e^{-i c dt} * (2 - delta_k0) * (-i)^k * J_k
-      for (int k = 0; k <= K; ++k) {
-        const double a = (k ? 2.0 : 1.0) * J[k];
-        double ar, ai;  // (-i)^k * a
-        switch (k & 3) {
-          case 0: ar = a; ai = 0.0; break;
-          case 1: ar = 0.0; ai = -a; break;
-          case 2: ar = -a; ai = 0.0; break;
-          default: ar = 0.0; ai = a; break;
-        }
-        cb[CHEB_COEF + 2 * k] = cs * ar + sn * ai;
-        cb[CHEB_COEF + 2 * k + 1] = cs * ai - sn * ar;
-      }
-      cb[CHEB_C] = cc;
-      cb[CHEB_INVR] = 1.0 / rr;
-      cb[CHEB_K] = (double)K;
-      cb[CHEB_RHO] = rho;
-      // work counters (integer sums: independent of the order of the adds)
-      atomicAdd((unsigned long long*)&cnt->sum_cheb, (unsigned long long)K);
-      if (sub <= 0) atomicAdd((unsigned long long*)&cnt->traj_steps, 1ull);
-      atomicMax((unsigned long long*)&cnt->max_cheb, (unsigned long long)K);
-    }
+    if (write_cheb(cb, L.red[0], L.red2[0], dte, precision, cnt, sub <= 0, L.J) < 0) atomicOr(&L.fail, 2);
   }
   __syncthreads();
   }

@@ -84,7 +84,9 @@ constexpr bool x_via_scratch() {
 }
 
 // Everything the step needs for trajectory t (all threads of the work-group).
-template <bool kF32, int kRS, int kRB>
+// kDense: couplings from the stored G = Q^T dH/dx Q of the dense model kind
+// instead of the (lambda, q0) closed form.
+template <bool kF32, int kRS, int kRB, bool kDense>
 __device__ void hop_one(const ClassDev& c, int t, double dt_run, uint64_t seed, Counters* cnt,
                         iesh_event* events, int query_mode, int record, int exit_enabled,
                         double exit_x, int64_t max_steps, HopLds& L, double2* xscr) {
@@ -365,6 +367,14 @@ __device__ void hop_one(const ClassDev& c, int t, double dt_run, uint64_t seed, 
   const double dh = multi ? geo[GEO_VDH] : geo[GEO_DH];
   const double rho = multi ? geo[GEO_VRHO] : geo[GEO_RHO];
   const double v = multi ? 1.0 : c.v[(size_t)t * nd];
+  // dense model kind: G = Q^T dH/dx Q from memory, and D = 0 between states
+  // whose energies agree to 1e-12 of the largest |lambda|
+  const double* Gd = kDense ? c.Gd + (size_t)t * n_pad * n_pad : nullptr;
+  const double gtol = kDense ? 1e-12 * fmax(fabs(L.lam[0]), fabs(L.lam[n - 1])) : 0.0;
+  auto coupling = [&](int b, int a) -> double {  // G[b][a]
+    if constexpr (kDense) return fabs(L.lam[a] - L.lam[b]) <= gtol ? 0.0 : Gd[(size_t)b * n_pad + a];
+    return L.q0[b] * L.q0[a] * (dh + rho * ((L.lam[b] - h) + (L.lam[a] - h)));
+  };
 
   // ---- hop probabilities, formed on the fly from the owned elements of Y
   auto gval = [&](int rb, int cj) -> double {
@@ -372,7 +382,7 @@ __device__ void hop_one(const ClassDev& c, int t, double dt_run, uint64_t seed, 
     if (singular || bi >= nU || j >= N) return 0.0;
     const int bb = L.uocc[bi];
     const int a = L.occ[L.invperm[j]];
-    const double gab = L.q0[bb] * L.q0[a] * (dh + rho * ((L.lam[bb] - h) + (L.lam[a] - h)));
+    const double gab = coupling(bb, a);
     // v <b|d/dx a>.  A deflated state (no impurity part) gives gab = 0: an
     // exact 0 unless two deflated states share their energy (three or more
     // equal bath levels), where 0/0 is NaN and the fmax below (maxNum: the
@@ -492,7 +502,8 @@ __device__ void hop_one(const ClassDev& c, int t, double dt_run, uint64_t seed, 
       double* dv = L.dofd;
       for (int nu = 0; nu < nd; ++nu) {
         const double dhn = geo[GEO_DHV + nu], rhon = geo[GEO_RHOV + nu];
-        const double gba = L.q0[bsel] * L.q0[a] * (dhn + rhon * ((L.lam[bsel] - h) + (L.lam[a] - h)));
+        const double gba = kDense ? coupling(bsel, a)
+                                  : L.q0[bsel] * L.q0[a] * (dhn + rhon * ((L.lam[bsel] - h) + (L.lam[a] - h)));
         dv[nu] = gba == 0.0 ? 0.0 : gba / (L.lam[a] - L.lam[bsel]);
       }
       const double dE = L.lam[bsel] - L.lam[a];
@@ -547,7 +558,7 @@ __device__ void hop_one(const ClassDev& c, int t, double dt_run, uint64_t seed, 
         double s = 0.0;
         for (int r = 0; r < N; ++r) {
           const int a = L.occ[r];
-          s += L.q0[a] * L.q0[a] * (dhn + 2.0 * rhon * (L.lam[a] - h));
+          s += kDense ? Gd[(size_t)a * n_pad + a] : L.q0[a] * L.q0[a] * (dhn + 2.0 * rhon * (L.lam[a] - h));
         }
         c.F[(size_t)t * nd + nu] = -geo[GEO_DU0V + nu] - s;
         c.v[(size_t)t * nd + nu] = vv[nu];
@@ -602,7 +613,7 @@ __device__ void hop_one(const ClassDev& c, int t, double dt_run, uint64_t seed, 
 // once; the dispatcher hands out work-groups in order, so the busy ones fill
 // the compute units first).  The last work-group to finish resets the queue
 // for the next step.  In query mode work-group b handles trajectory t0 + b.
-template <bool kF32, int kRS, int kRB>
+template <bool kF32, int kRS, int kRB, bool kDense>
 __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint64_t seed,
                                                      Counters* cnt, iesh_event* events,
                                                      int query_mode, int t0, int record,
@@ -615,8 +626,8 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
   if (!query_mode) t = (b < q[0]) ? q[3 + b] : -1;
   if (t >= 0) {
     double2* xscr = x_via_scratch<kRS, kRB>() ? c.hopx + (size_t)t * c.md.N * c.md.N : nullptr;
-    hop_one<kF32, kRS, kRB>(c, t, dt, seed, cnt, events, query_mode, record, exit_enabled, exit_x,
-                            max_steps, L, xscr);
+    hop_one<kF32, kRS, kRB, kDense>(c, t, dt, seed, cnt, events, query_mode, record, exit_enabled,
+                                    exit_x, max_steps, L, xscr);
   }
   if (!query_mode && threadIdx.x == 0) {
     __threadfence();
@@ -656,7 +667,7 @@ struct FltLds {
   int occ[kMaxElec];
 };
 
-template <bool kF32>
+template <bool kF32, bool kDense>
 __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double dt_run, uint64_t seed,
                                                             Counters* cnt, int record,
                                                             int exit_enabled, double exit_x,
@@ -710,13 +721,16 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
   const double dh = multi ? geo[GEO_VDH] : geo[GEO_DH];
   const double rho = multi ? geo[GEO_VRHO] : geo[GEO_RHO];
   const double v = multi ? 1.0 : c.v[(size_t)t * nd];
+  const double* Gd = kDense ? c.Gd + (size_t)t * n_pad * n_pad : nullptr;
+  const double gtol = kDense ? 1e-12 * fmax(fabs(L.lam[0]), fabs(L.lam[n - 1])) : 0.0;
   double bnd_part = 0.0;
   for (int b = tid; b < n; b += kFltThreads) {
     if (L.occflag[b]) continue;
     double s = 0.0;
     for (int r = 0; r < N; ++r) {
       const int a = L.occ[r];
-      const double gab = L.q0[b] * L.q0[a] * (dh + rho * ((L.lam[b] - h) + (L.lam[a] - h)));
+      const double gab = kDense ? (fabs(L.lam[a] - L.lam[b]) <= gtol ? 0.0 : Gd[(size_t)b * n_pad + a])
+                                : L.q0[b] * L.q0[a] * (dh + rho * ((L.lam[b] - h) + (L.lam[a] - h)));
       if (gab != 0.0) s += fabs(v * gab / (L.lam[a] - L.lam[b]));
     }
     bnd_part += L.rn[b] * s;
@@ -825,16 +839,23 @@ constexpr int rb_floor(int rb) {
   return rb == 2 ? 0 : rb == 4 ? 2 : rb == 7 ? 4 : rb == 11 ? 7 : rb == 14 ? 11 : 14;
 }
 template <int RS, int RB>
-constexpr bool bucket_possible() {
-  return 16 * rs_floor(RS) + 1 + 16 * rb_floor(RB) + 1 <= kMaxStates;
+constexpr bool bucket_possible(int max_states = kMaxStates) {
+  return 16 * rs_floor(RS) + 1 + 16 * rb_floor(RB) + 1 <= max_states;
 }
 
 template <bool F32, int RS, int RB>
 static void launch_hop_t(const ClassDev& c, dim3 grid, double dt, uint64_t seed, Counters* cnt,
                          iesh_event* events, int query_mode, int t0, int record,
                          int exit_enabled, double exit_x, int64_t max_steps, hipStream_t s) {
+  if (c.Gd) {
+    // the dense model kind: n <= IESH_DENSE_MAX_N
+    if constexpr (bucket_possible<RS, RB>(IESH_DENSE_MAX_N))
+      hipLaunchKernelGGL((k_hop<F32, RS, RB, true>), grid, dim3(kHopThreads), 0, s, c, dt, seed, cnt,
+                         events, query_mode, t0, record, exit_enabled, exit_x, max_steps);
+    return;
+  }
   if constexpr (bucket_possible<RS, RB>())
-    hipLaunchKernelGGL((k_hop<F32, RS, RB>), grid, dim3(kHopThreads), 0, s, c, dt, seed, cnt,
+    hipLaunchKernelGGL((k_hop<F32, RS, RB, false>), grid, dim3(kHopThreads), 0, s, c, dt, seed, cnt,
                        events, query_mode, t0, record, exit_enabled, exit_x, max_steps);
 }
 
@@ -913,12 +934,21 @@ hipError_t launch_hop_filter(const ClassDev& c, double dt, uint64_t seed, Counte
   // orthonormality defect allowed for the stored orbitals (floor)
   const double delta = (precision == IESH_FP64) ? kDeltaFP64 : kDeltaMixed;
   if (c.n_live < 1) return hipSuccess;
-  if (precision == IESH_FP64)
-    hipLaunchKernelGGL(k_hop_filter<false>, dim3(c.n_live), dim3(kFltThreads), 0, s, c, dt, seed,
-                       cnt, record, exit_enabled, exit_x, max_steps, delta);
-  else
-    hipLaunchKernelGGL(k_hop_filter<true>, dim3(c.n_live), dim3(kFltThreads), 0, s, c, dt, seed,
-                       cnt, record, exit_enabled, exit_x, max_steps, delta);
+#define IESH_FILTER(F32, DENSE)                                                                   \
+  hipLaunchKernelGGL((k_hop_filter<F32, DENSE>), dim3(c.n_live), dim3(kFltThreads), 0, s, c, dt, seed, \
+                     cnt, record, exit_enabled, exit_x, max_steps, delta)
+  if (precision == IESH_FP64) {
+    if (c.Gd)
+      IESH_FILTER(false, true);
+    else
+      IESH_FILTER(false, false);
+  } else {
+    if (c.Gd)
+      IESH_FILTER(true, true);
+    else
+      IESH_FILTER(true, false);
+  }
+#undef IESH_FILTER
   return hipGetLastError();
 }
 

@@ -25,8 +25,14 @@ def from_config(cfg: dict, n_traj: int | None = None, precision: str = "fp64", M
     b = cfg["bath"]
     M = M if M is not None else b["M"]
     N = n_elec if n_elec is not None else cfg.get("n_elec", M // 2)
-    eps, w, lead, _ = bath_levels(b, M)
-    desc = _lib.model_desc(cfg["model"], eps, w, N, lead)
+    if cfg["model"]["kind"] == "dense":
+        from workloads import dense_matrices
+        m = cfg["model"]
+        H0, H1 = dense_matrices(cfg, M)
+        desc = _lib.dense_model_desc(H0, H1, m["mass"], m["omega"], N, m.get("x_c", 0.0))
+    else:
+        eps, w, lead, _ = bath_levels(b, M)
+        desc = _lib.model_desc(cfg["model"], eps, w, N, lead)
     run = dict(n_traj=n_traj if n_traj is not None else cfg["n_traj"], precision=precision,
                dt=cfg["dt"], kT=cfg.get("kT", 0.0), seed=cfg.get("seed", 0),
                bias=b.get("bias", 0.0),

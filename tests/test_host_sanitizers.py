@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2212_00518_amd", "csrc")
 BUILD = os.path.join(ROOT, "paper_2212_00518_amd", "_build")
 KERNELS = ["k_eig", "k_prop", "k_hop", "k_lowdin", "k_compact", "k_adjoint", "k_jacobi",
-           "eigh_noalloc"]
+           "eigh_noalloc", "k_dense"]
 SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
        "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
 
