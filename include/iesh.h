@@ -95,7 +95,10 @@ enum iesh_model_kind {
      for the observables; U0 = m omega^2 (x - x_c)^2 / 2.  Eigenvectors are
      sign-fixed so that their first nonzero component is positive (the
      impurity component unless it vanishes), which is continuous along a
-     path as long as no impurity component passes through zero.  eps, w,
+     path as long as no impurity component passes through zero.  Each
+     solve starts from the trajectory's previous eigenvectors (every 256th
+     step of a trajectory from scratch), so a run resumed from a saved state
+     agrees with the uninterrupted run to rounding, not bit for bit.  eps, w,
      Gamma and lead are not used; no bias.  params: [0] omega, [1] x_c.     */
   IESH_MODEL_DENSE = 3
 };

@@ -34,10 +34,13 @@ struct iesh_ctx {
   size_t device_bytes = 0;
   std::string err;
   std::vector<std::pair<void*, size_t>> allocations;  // (pointer, bytes)
-  // graph cache for iesh_run
+  // graph cache for iesh_run: one step, and the device-side compaction
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   int graph_record = -1;
+  hipGraphExec_t compact_exec = nullptr;
+  hipGraph_t compact_graph = nullptr;
+  std::vector<int> live_host;  // live slots per class at the last refresh
   int64_t obs_records = 0;  // capacity of the class observable buffers
   // per-kernel timing with HIP events (diagnostic)
   bool timing = false;
@@ -116,9 +119,13 @@ void dfree(iesh_ctx* ctx, T*& p) {
 void free_graph(iesh_ctx* ctx) {
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->compact_exec) (void)hipGraphExecDestroy(ctx->compact_exec);
+  if (ctx->compact_graph) (void)hipGraphDestroy(ctx->compact_graph);
   ctx->graph_exec = nullptr;
   ctx->graph = nullptr;
   ctx->graph_record = -1;
+  ctx->compact_exec = nullptr;
+  ctx->compact_graph = nullptr;
 }
 
 int round16(int v) { return (v + 15) / 16 * 16; }
@@ -173,7 +180,9 @@ int autotune_slabs(iesh_ctx* ctx, ClassDev& c) {
   hipEvent_t e0 = next_event(ctx), e1 = next_event(ctx);
   if (!e0 || !e1) return fail(ctx, IESH_EDEVICE, "event creation failed");
   const int saved_live = c.n_live;
+  int32_t* saved_dev_live = c.live;
   c.n_live = sample;
+  c.live = nullptr;  // the timing launches cover the sample slots
   int best = widest;
   float best_ms = 1e30f;
   std::vector<int> seen;
@@ -199,6 +208,7 @@ int autotune_slabs(iesh_ctx* ctx, ClassDev& c) {
   }
   ctx->ev_used = 0;
   c.n_live = saved_live;
+  c.live = saved_dev_live;
   set_slabs(c, best);
   HIPTRY(ctx, prop_prepare(c, prec));
   HIPTRY(ctx, hipMemsetAsync(c.cheb, 0, (size_t)sample * kChebStride * sizeof(double), ctx->stream));
@@ -467,52 +477,65 @@ int reset_perm(iesh_ctx* ctx) {
                                  ctx->stream));
       HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
     }
-    if (c.n_live != c.n_traj) free_graph(ctx);
+    if (c.live) {
+      const int32_t nl = c.n_traj;
+      HIPTRY(ctx, hipMemcpyAsync(c.live, &nl, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+      HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
     c.n_live = c.n_traj;
+    ctx->live_host[ci] = c.n_traj;
   }
   HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
   return IESH_OK;
 }
 
-// Move the frozen trajectories of every class behind its active ones and
-// shrink the slots the step kernels visit.
-int compact(iesh_ctx* ctx) {
+// Slot order and live counts of the classes after device-side compaction
+// (for the calls that address trajectories by their global index).
+int refresh_perm(iesh_ctx* ctx) {
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
   for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
     ClassDev& c = ctx->cls[ci];
-    CompactBufs& b = ctx->spare[ci];
-    if (c.n_live < 1 || !b.dst) continue;
-    HIPTRY(ctx, launch_compact_rank(c, b.dst, b.n_active, ctx->stream));
-    int32_t n_active = 0;
-    HIPTRY(ctx, hipMemcpyAsync(&n_active, b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost,
-                               ctx->stream));
-    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
-    if (n_active == c.n_live) continue;
-    const int nl = c.n_live, N = c.md.N;
-    HIPTRY(ctx, launch_compact_move(c, b.dst, b, ctx->run.precision, ctx->stream));
-    const size_t esz = ctx->run.precision == IESH_FP64 ? sizeof(double) : sizeof(float);
-    void* Cdst = ctx->run.precision == IESH_FP64 ? (void*)c.C64 : (void*)c.C32;
-    auto cp = [&](void* dst, const void* src, size_t bytes) {
-      return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream);
-    };
-    const size_t nds = (size_t)nl * c.md.ndof * sizeof(double);
-    HIPTRY(ctx, cp(c.x, b.x, nds));
-    HIPTRY(ctx, cp(c.v, b.v, nds));
-    HIPTRY(ctx, cp(c.F, b.F, nds));
-    HIPTRY(ctx, cp(c.status, b.status, nl * sizeof(int32_t)));
-    HIPTRY(ctx, cp(c.gtraj, b.gtraj, nl * sizeof(int32_t)));
-    HIPTRY(ctx, cp(c.home, b.home, nl * sizeof(int32_t)));
-    HIPTRY(ctx, cp(c.nsteps, b.nsteps, nl * sizeof(int64_t)));
-    HIPTRY(ctx, cp(c.stepcap, b.stepcap, nl * sizeof(int64_t)));
-    HIPTRY(ctx, cp(c.occ, b.occ, (size_t)nl * N * sizeof(int32_t)));
-    HIPTRY(ctx, cp(c.clock, b.clock, (size_t)nl * 2 * sizeof(double)));
-    HIPTRY(ctx, cp(Cdst, b.C, (size_t)nl * N * c.md.n_pad * 2 * esz));
+    if (!c.n_traj || !ctx->spare[ci].dst) continue;
+    int32_t nl = 0;
+    HIPTRY(ctx, hipMemcpy(&nl, c.live, sizeof(int32_t), hipMemcpyDeviceToHost));
     auto& sh = ctx->slot_home[ci];
-    HIPTRY(ctx, hipMemcpyAsync(sh.data(), c.home, nl * sizeof(int32_t), hipMemcpyDeviceToHost,
-                               ctx->stream));
-    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
-    for (int s = 0; s < nl; ++s) ctx->home_slot[ci][sh[s]] = s;
-    c.n_live = n_active;
-    free_graph(ctx);  // launch sizes changed
+    HIPTRY(ctx, hipMemcpy(sh.data(), c.home, c.n_traj * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int sl = 0; sl < c.n_traj; ++sl) ctx->home_slot[ci][sh[sl]] = sl;
+    ctx->live_host[ci] = nl;
+  }
+  return IESH_OK;
+}
+
+// The non-empty classes of one kind (arrowhead or dense) in sets of at most
+// kFuseMax for the fused launches, largest first in each set; block ranges
+// cover every slot of a class (the kernels skip slots past the live count).
+std::vector<ClassSet> class_sets(const iesh_ctx* ctx, bool dense) {
+  std::vector<int> idx;
+  for (size_t ci = 0; ci < ctx->cls.size(); ++ci)
+    if (ctx->cls[ci].n_traj && ((ctx->cls[ci].Gd != nullptr) == dense)) idx.push_back((int)ci);
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](int a, int b) { return ctx->cls[a].md.n_pad > ctx->cls[b].md.n_pad; });
+  std::vector<ClassSet> sets;
+  for (size_t i = 0; i < idx.size(); i += kFuseMax) {
+    ClassSet set{};
+    set.n = 0;
+    set.first[0] = 0;
+    for (size_t j = i; j < idx.size() && j < i + kFuseMax; ++j) {
+      set.c[set.n] = ctx->cls[idx[j]];
+      set.first[set.n + 1] = set.first[set.n] + ctx->cls[idx[j]].n_live;
+      ++set.n;
+    }
+    sets.push_back(set);
+  }
+  return sets;
+}
+
+// Device-side compaction of every class that has spare arrays.
+int enqueue_compact(iesh_ctx* ctx) {
+  for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {
+    ClassDev& c = ctx->cls[ci];
+    if (!c.n_traj || !ctx->spare[ci].dst) continue;
+    HIPTRY(ctx, launch_compact(c, ctx->spare[ci], ctx->run.precision, ctx->stream));
   }
   return IESH_OK;
 }
@@ -554,34 +577,49 @@ hipError_t timed(iesh_ctx* ctx, int timer, F fn) {
   return e;
 }
 
-// Kernel sequence of one step for every class.
+// Kernel sequence of one step for every class.  The eigen-solves of the
+// arrowhead classes run in one launch whose blocks cover every class, largest
+// class first, so that the small classes fill the compute units behind the
+// large ones; so does the no-hop bound.  Propagation, ratios and Loewdin
+// steps are per class (their register and LDS shapes depend on n and N).
+// Every kernel reads the live-slot count of its class from the device.
 int enqueue_step(iesh_ctx* ctx, int record) {
   const iesh_run_desc& r = ctx->run;
+  hipStream_t s = ctx->stream;
+  Counters* cnt = ctx->cnt;
+  const int S = r.elec_substeps;
+  const std::vector<ClassSet> arrow = class_sets(ctx, false), dense = class_sets(ctx, true);
+  auto eig = [&](int sub, int nsub) -> int {
+    for (const ClassSet& set : arrow)
+      HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG,
+                        [&] { return launch_eig_fused(set, r.dt, r.precision, cnt, s, sub, nsub); }));
+    for (auto& c : ctx->cls)
+      if (c.n_traj && c.Gd)
+        HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return launch_dense_step(c, r.dt, cnt, s, sub, nsub); }));
+    return IESH_OK;
+  };
+  auto prop = [&]() -> int {
+    for (auto& c : ctx->cls)
+      if (c.n_traj) HIPTRY(ctx, timed(ctx, IESH_TIMER_PROP, [&] { return launch_prop(c, r.precision, s); }));
+    return IESH_OK;
+  };
+  int rc;
+  if (S <= 1) {
+    if ((rc = eig(-1, 1)) || (rc = prop())) return rc;
+  } else {
+    // electronic sub-steps: a propagator and a propagation each, then the end point
+    for (int j = 0; j < S; ++j)
+      if ((rc = eig(j, S)) || (rc = prop())) return rc;
+    if ((rc = eig(-2, S))) return rc;
+  }
+  for (const auto* sets : {&arrow, &dense})
+    for (const ClassSet& set : *sets)
+      HIPTRY(ctx, timed(ctx, IESH_TIMER_FILTER, [&] {
+               return launch_filter_fused(set, r.dt, r.seed, cnt, record, r.exit_enabled, r.exit_x,
+                                          r.max_steps, r.precision, s);
+             }));
   for (auto& c : ctx->cls) {
     if (c.n_traj == 0) continue;
-    hipStream_t s = ctx->stream;
-    Counters* cnt = ctx->cnt;
-    const int S = r.elec_substeps;
-    // eigen-solve, couplings, propagator set-up and Verlet: the arrowhead
-    // solver, or the dense one for IESH_MODEL_DENSE
-    auto eig = [&](int sub, int nsub) {
-      return c.Gd ? launch_dense_step(c, r.dt, cnt, s, sub, nsub) : launch_eig_step(c, r.dt, cnt, s, sub, nsub);
-    };
-    if (S <= 1) {
-      HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return eig(-1, 1); }));
-      HIPTRY(ctx, timed(ctx, IESH_TIMER_PROP, [&] { return launch_prop(c, r.precision, s); }));
-    } else {
-      // electronic sub-steps: a propagator and a propagation each, then the end point
-      for (int j = 0; j < S; ++j) {
-        HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return eig(j, S); }));
-        HIPTRY(ctx, timed(ctx, IESH_TIMER_PROP, [&] { return launch_prop(c, r.precision, s); }));
-      }
-      HIPTRY(ctx, timed(ctx, IESH_TIMER_EIG, [&] { return eig(-2, S); }));
-    }
-    HIPTRY(ctx, timed(ctx, IESH_TIMER_FILTER, [&] {
-             return launch_hop_filter(c, r.dt, r.seed, cnt, record, r.exit_enabled, r.exit_x,
-                                      r.max_steps, r.precision, s);
-           }));
     HIPTRY(ctx, timed(ctx, IESH_TIMER_HOP, [&] {
              return launch_hop(c, r.dt, r.seed, cnt, ctx->events, 0, 0, c.n_traj, record,
                                r.exit_enabled, r.exit_x, r.max_steps, r.precision, s);
@@ -823,6 +861,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
   if (rc) return bail(rc);
   rc = dalloc(ctx, &ctx->events, (size_t)IESH_EVENT_CAP);
   if (rc) return bail(rc);
+  ctx->live_host.assign(n_models, 0);
   ctx->cls.resize(n_models);
   ctx->members.assign(n_models, {});
   ctx->slot_home.assign(n_models, {});
@@ -894,14 +933,15 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
         (rc = dalloc(ctx, &c.cheb, (size_t)T * kChebStride)) ||
         (rc = dalloc(ctx, &c.gbuf, (size_t)T * N * n_pad)) ||
         (rc = dalloc(ctx, &c.clock, (size_t)2 * T)) ||
-        (rc = dalloc(ctx, &c.hopq, (size_t)3 + T)))
+        (rc = dalloc(ctx, &c.hopq, (size_t)3 + T)) || (rc = dalloc(ctx, &c.live, 1)))
       return bail(rc);
     if (hop_needs_scratch(c) && (rc = dalloc(ctx, &c.hopx, (size_t)T * N * N)))
       return bail(rc);
     if (dense) {
       double *h0 = nullptr, *h1 = nullptr;
       if ((rc = dalloc(ctx, &h0, (size_t)n_pad * n_pad)) || (rc = dalloc(ctx, &h1, (size_t)n_pad * n_pad)) ||
-          (rc = dalloc(ctx, &c.Gd, (size_t)T * n_pad * n_pad)))
+          (rc = dalloc(ctx, &c.Gd, (size_t)T * n_pad * n_pad)) ||
+          (rc = dalloc(ctx, &c.Qw, (size_t)T * n_pad * n_pad)))
         return bail(rc);
       const int n = c.md.n;
       std::vector<double> pad((size_t)2 * n_pad * n_pad, 0.0);
@@ -991,6 +1031,10 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
     return (fail(ctx, IESH_EDEVICE, "device synchronisation failed"), bail(IESH_EDEVICE));
   for (auto& c : ctx->cls)
     if (c.n_traj && autotune_slabs(ctx, c)) return bail(IESH_EDEVICE);
+  // the ratio kernel is persistent over its queue: as many work-groups as
+  // are resident at once
+  for (auto& c : ctx->cls)
+    if (c.n_traj) c.hop_groups = hop_resident_groups(c, r.precision, ctx->n_cu);
   if (set_counters(ctx, 0, 0)) return bail(IESH_EDEVICE);
   if (reset_perm(ctx)) return bail(IESH_EDEVICE);
   *out = ctx;
@@ -1020,7 +1064,7 @@ int iesh_class_info(const iesh_ctx* ctx, int32_t cls, int32_t* info) {
   if (!ctx || !info || cls < 0 || cls >= (int)ctx->cls.size()) return IESH_EINVAL;
   const ClassDev& c = ctx->cls[cls];
   info[0] = c.n_traj;
-  info[1] = c.n_live;
+  info[1] = ctx->live_host[cls];
   info[2] = c.md.n;
   info[3] = c.md.N;
   info[4] = c.nct_max;
@@ -1250,11 +1294,30 @@ int iesh_run(iesh_ctx* ctx, int64_t n_steps, double* obs_out) {
     }
     left -= chunk;
     if (r.compact_every > 0) {
-      HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
-      if ((rc = compact(ctx))) return rc;
+      // compaction on the device: no host round trip, no re-capture
+      if (ctx->timing) {
+        if ((rc = enqueue_compact(ctx))) return rc;
+      } else {
+        if (!ctx->compact_exec) {
+          HIPTRY(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+          rc = enqueue_compact(ctx);
+          hipGraph_t g = nullptr;
+          hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+          if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+          }
+          if (e != hipSuccess)
+            return fail(ctx, IESH_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+          ctx->compact_graph = g;
+          HIPTRY(ctx, hipGraphInstantiate(&ctx->compact_exec, g, nullptr, nullptr, 0));
+        }
+        HIPTRY(ctx, hipGraphLaunch(ctx->compact_exec, ctx->stream));
+      }
     }
   }
   HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (r.compact_every > 0 && (rc = refresh_perm(ctx))) return rc;
   if (record) {
     const int T = r.n_traj;
     for (size_t ci = 0; ci < ctx->cls.size(); ++ci) {

@@ -78,10 +78,14 @@ struct ModelDev {
 struct ClassDev {
   ModelDev md;
   int n_traj;           // trajectories in this class (allocated slots)
-  int n_live;           // leading slots the step kernels visit (the others are frozen)
+  int n_live;           // host: slots a launch covers (the class size, except while autotuning)
+  int32_t* live = nullptr;  // [1] device: leading slots the step kernels visit (the
+                            // others hold frozen trajectories); lowered by the
+                            // compaction kernels without a host round trip
   int traj_offset;      // first global trajectory index of this class
   int nct_max;          // column tiles per propagation work-group
   int n_slabs;          // propagation work-groups per trajectory
+  int hop_groups = 0;   // work-groups of a persistent ratio-kernel launch (0: one per slot)
   int exit_dof = 0;     // coordinate compared with the exit distance
   int exact_hops = 0;   // 1: determinant ratios at every step (no-hop bound unused)
   // step clock: [T][2] = (dt of the next step, elapsed time); the step kernels
@@ -124,6 +128,8 @@ struct ClassDev {
   const double* H0 = nullptr;
   const double* H1 = nullptr;
   double* Gd = nullptr;
+  double* Qw = nullptr;  // [T][n_pad][n_pad] by home index: eigenvectors of the
+                         // trajectory's last solve (warm start of the next)
   int32_t* hopq = nullptr;  // [3 + T] queue for the determinant-ratio kernel: count, -, done, list
   double2* hopx = nullptr;  // [T][N][N] inverse of S (shapes whose registers cannot hold it)
   // prescribed nuclear path (adjoint): x of trajectory g at step n is
@@ -261,6 +267,18 @@ __host__ __device__ inline ModelAt model_at(const ModelDev& md, const double* xv
   return r;
 }
 
+// Leading slots of a class that the step kernels visit.
+__device__ inline int live_slots(const ClassDev& c) { return c.live ? *c.live : c.n_live; }
+
+// Several classes for one launch (kernel argument: up to kFuseMax classes);
+// block b belongs to class k for first[k] <= b < first[k + 1].
+constexpr int kFuseMax = 4;
+struct ClassSet {
+  ClassDev c[kFuseMax];
+  int first[kFuseMax + 1];
+  int n;
+};
+
 // Spare copies of the state that moves with a trajectory (compaction).
 // Step clock after a step whose hop probabilities total g_total: the next
 // step is the largest dt0 / 2^k (k <= dt_levels) for which g_total rescaled
@@ -297,6 +315,9 @@ struct CompactBufs {
 hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStream_t s, int sub = -1,
                            int nsub = 1);
 hipError_t launch_eig_query(const ClassDev& c, int t0, int nt, hipStream_t s);
+// the step of several arrowhead classes in one launch
+hipError_t launch_eig_fused(const ClassSet& set, double dt, int precision, Counters* cnt, hipStream_t s,
+                            int sub = -1, int nsub = 1);
 hipError_t launch_init_thermal(const ClassDev& c, double kT, double bias, uint64_t seed,
                                hipStream_t s);
 // dense symmetric eigen-decomposition (k_jacobi.hip)
@@ -313,6 +334,7 @@ hipError_t launch_dense_init_thermal(const ClassDev& c, double kT, uint64_t seed
 hipError_t launch_prop(const ClassDev& c, int precision, hipStream_t s);
 hipError_t launch_prop_taps(const ClassDev& c, int mode, double* taps, int tap_k, hipStream_t s);
 int prop_max_col_tiles(int precision);
+int hop_resident_groups(const ClassDev& c, int precision, int n_cu);
 int prop_max_tiles_per_wave(int precision);
 hipError_t prop_prepare(const ClassDev& c, int precision);
 size_t prop_lds_bytes(const ClassDev& c, int precision);
@@ -321,9 +343,10 @@ hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt
                       int exit_enabled, double exit_x, int64_t max_steps, int precision,
                       hipStream_t s);
 bool hop_needs_scratch(const ClassDev& c);
-hipError_t launch_hop_filter(const ClassDev& c, double dt, uint64_t seed, Counters* cnt, int record,
-                             int exit_enabled, double exit_x, int64_t max_steps, int precision,
-                             hipStream_t s);
+// the no-hop bound of several classes of one kind in one launch
+hipError_t launch_filter_fused(const ClassSet& set, double dt, uint64_t seed, Counters* cnt, int record,
+                               int exit_enabled, double exit_x, int64_t max_steps, int precision,
+                               hipStream_t s);
 hipError_t launch_lowdin(const ClassDev& c, Counters* cnt, int every, double2* scratch,
                          hipStream_t s);
 size_t lowdin_scratch_elems(const ClassDev& c);
@@ -350,6 +373,7 @@ hipError_t launch_adj_phi(const ClassDev& c, const double* taps_s, const double*
 hipError_t launch_compact_rank(const ClassDev& c, int32_t* dst, int32_t* n_active, hipStream_t s);
 hipError_t launch_compact_move(const ClassDev& c, const int32_t* dst, const CompactBufs& b,
                                int precision, hipStream_t s);
+hipError_t launch_compact(const ClassDev& c, const CompactBufs& b, int precision, hipStream_t s);
 
 // Reason of the last failed context-free call on this thread (api.cpp):
 // what iesh_last_error(NULL) returns.

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const do
   __shared__ int piv[kMaxElec];
   extern __shared__ double2 hop_smem[];
   const int t = blockIdx.x, tid = threadIdx.x;
-  if (t >= c.n_live) return;
+  if (t >= live_slots(c)) return;
   const int n = c.md.n, n_pad = c.md.n_pad, N = c.md.N, nU = n - N;
   const double* C = Cs + (size_t)t * N * n_pad * 2;
   const double* lam = c.lam + (size_t)t * n_pad;
@@ -506,7 +506,7 @@ __global__ __launch_bounds__(kPhiThreads) void k_adj_phi(ClassDev c, const doubl
   const int b = blockIdx.x, xcd = b & 7, local = b >> 3;
   const int blk = local % n_blk;
   const int t = (local / n_blk) * 8 + xcd;
-  if (t >= c.n_live) return;
+  if (t >= live_slots(c)) return;
   PhiJob J;
   J.r0 = blk * nr_max;
   const int nr = min(nr_max, RT - J.r0);

@@ -6,7 +6,8 @@
 // Eq. classical_hamiltonian, F = -U0' - sum_{a in s} G_aa).
 //
 // One work-group (8 waves) per trajectory.  The eigen-decomposition of
-// H(x) runs in LDS: the matrix and the accumulated rotations, both padded to
+// H(x) runs in LDS, warm-started from the trajectory's previous eigenvectors
+// (see warm_start): the matrix and the accumulated rotations, both padded to
 // n_pad = n rounded up to 16 with a row stride of n_pad + 1 doubles, take
 // 2 n_pad (n_pad + 1) doubles, which bounds n at IESH_DENSE_MAX_N (96).  It
 // is the cyclic two-sided Jacobi method (Golub and Van Loan): every sweep
@@ -36,6 +37,7 @@ namespace {
 constexpr int kDenThreads = 512;
 constexpr int kDenWaves = kDenThreads / 64;
 constexpr int kJacobiSweeps = 60;
+constexpr int64_t kDenseColdEvery = 256;  // steps between cold eigen-solves of a trajectory
 constexpr double kEpsD = 2.220446049250313e-16;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -112,27 +114,89 @@ __device__ inline double block_min(double v, double* red) {
 
 __device__ inline double block_max(double v, double* red) { return -block_min(-v, red); }
 
-// Eigen-decomposition of H(x) = H0 + x H1 in LDS; afterwards L.lam, L.q0 hold
+// Warm start: the rotations start from the eigenvectors W of the
+// trajectory's previous solve (the geometry moved by one half step), so the
+// matrix to diagonalise is W^T H(x) W, nearly diagonal, and the sweeps
+// converge in two or three instead of about ten.  Both products run on the
+// matrix cores: T1 = H(x) W into the scratch block tmp (global), then
+// W^T T1 into L.A, symmetrised.
+__device__ void warm_start(const ClassDev& c, double x, DenLds& L, const double* W, double* tmp) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int np = c.md.n_pad, ld = np + 1, RT = np / 16, KB = np / 4;
+  for (int idx = tid; idx < np * np; idx += kDenThreads) {
+    const int i = idx / np, j = idx - i * np;
+    L.V[(size_t)i * ld + j] = W[idx];
+  }
+  __syncthreads();
+  const double* H0 = c.H0;
+  const double* H1 = c.H1;
+  for (int tile = wave; tile < RT * RT; tile += kDenWaves) {
+    const int rt = tile / RT, ct = tile - rt * RT;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const size_t arow = (size_t)(rt * 16 + lr) * np + lk;
+    const double* bcol = L.V + (size_t)lk * ld + ct * 16 + lr;
+    for (int kb = 0; kb < KB; ++kb)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(H0[arow + 4 * kb] + x * H1[arow + 4 * kb],
+                                                 bcol[(size_t)4 * kb * ld], acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) tmp[(size_t)(rt * 16 + lk + 4 * r) * np + ct * 16 + lr] = acc[r];
+  }
+  __syncthreads();  // T1 complete (work-group visibility of the global writes)
+  for (int tile = wave; tile < RT * RT; tile += kDenWaves) {
+    const int rt = tile / RT, ct = tile - rt * RT;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const double* acol = L.V + (size_t)lk * ld + rt * 16 + lr;
+    const double* bcol = tmp + (size_t)lk * np + ct * 16 + lr;
+    for (int kb = 0; kb < KB; ++kb)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(acol[(size_t)4 * kb * ld], bcol[(size_t)4 * kb * np],
+                                                 acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) L.A[(size_t)(rt * 16 + lk + 4 * r) * ld + ct * 16 + lr] = acc[r];
+  }
+  __syncthreads();
+  // the two halves of the product differ by rounding: symmetrise
+  for (int idx = tid; idx < np * np; idx += kDenThreads) {
+    const int i = idx / np, j = idx - i * np;
+    if (j > i) {
+      const double a = 0.5 * (L.A[(size_t)i * ld + j] + L.A[(size_t)j * ld + i]);
+      L.A[(size_t)i * ld + j] = a;
+      L.A[(size_t)j * ld + i] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// Eigen-decomposition of H(x) = H0 + x H1 in LDS, cold (from H(x) and the
+// identity) or warm (W != nullptr: from the eigenvectors W of the previous
+// solve, tmp a scratch block of n_pad^2 doubles); afterwards L.lam, L.q0 hold
 // the ascending eigenvalues and impurity components, L.dj / L.sg / L.rank the
 // Jacobi-order eigenvalues, signs and ranks, L.V the eigenvectors (Jacobi
 // order, unsigned).  Returns false when the sweeps did not converge.
-__device__ bool dense_eigen(const ClassDev& c, double x, DenLds& L) {
+__device__ bool dense_eigen(const ClassDev& c, double x, DenLds& L, const double* W = nullptr,
+                            double* tmp = nullptr) {
   const int tid = threadIdx.x;
   const int n = c.md.n, np = c.md.n_pad, ld = np + 1;
   const int m = n + (n & 1), half = m / 2;
-  const double* H0 = c.H0;
-  const double* H1 = c.H1;
-  for (int idx = tid; idx < np * np; idx += kDenThreads) {
-    const int i = idx / np, j = idx - i * np;
-    L.A[(size_t)i * ld + j] = H0[idx] + x * H1[idx];  // zero outside n x n
-    L.V[(size_t)i * ld + j] = (i == j) ? 1.0 : 0.0;
+  if (W) {
+    warm_start(c, x, L, W, tmp);
+  } else {
+    const double* H0 = c.H0;
+    const double* H1 = c.H1;
+    for (int idx = tid; idx < np * np; idx += kDenThreads) {
+      const int i = idx / np, j = idx - i * np;
+      L.A[(size_t)i * ld + j] = H0[idx] + x * H1[idx];  // zero outside n x n
+      L.V[(size_t)i * ld + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   bool converged = false;
   for (int sweep = 0; sweep < kJacobiSweeps; ++sweep) {
-    if (tid == 0) L.flag[0] = 0;
+    if (tid == 0) {
+      L.flag[0] = 0;
+      L.flag[2] = 0;  // round 0 has no rotation yet
+    }
     __syncthreads();
     for (int r = 0; r < m - 1; ++r) {
+      int* rot = L.flag + 2 + (r & 1);  // a rotation in this round (slots alternate by round)
       for (int k = tid; k < half; k += kDenThreads) {
         int p, q;
         if (k == 0) {
@@ -157,6 +221,7 @@ __device__ bool dense_eigen(const ClassDev& c, double x, DenLds& L) {
             cth = 1.0 / sqrt(1.0 + tt * tt);
             sth = tt * cth;
             L.flag[0] = 1;
+            *rot = 1;
           }
         }
         L.pq[2 * k] = p;
@@ -165,6 +230,14 @@ __device__ bool dense_eigen(const ClassDev& c, double x, DenLds& L) {
         L.sn[k] = sth;
       }
       __syncthreads();
+      // a round without rotations (most rounds of the last sweeps) has
+      // nothing to apply.  Every thread reads this round's slot between the
+      // two barriers; the next round's slot, last read two rounds ago, is
+      // cleared there too, before any thread can start that round
+      const int rotated = *rot;
+      if (tid == 0) L.flag[2 + ((r + 1) & 1)] = 0;
+      __syncthreads();
+      if (!rotated) continue;
       // rows p, q of every pair
       for (int idx = tid; idx < half * m; idx += kDenThreads) {
         const int k = idx / m, j = idx - k * m;
@@ -231,6 +304,16 @@ __device__ bool dense_eigen(const ClassDev& c, double x, DenLds& L) {
   }
   __syncthreads();
   return converged;
+}
+
+// The eigenvectors of the last solve (Jacobi order) into the trajectory's
+// warm-start block.
+__device__ inline void save_basis(const ClassDev& c, const DenLds& L, double* W) {
+  const int np = c.md.n_pad, ld = np + 1;
+  for (int idx = threadIdx.x; idx < np * np; idx += kDenThreads) {
+    const int i = idx / np, j = idx - i * np;
+    W[idx] = L.V[(size_t)i * ld + j];
+  }
 }
 
 // G = V^T H1 V on the matrix cores into Gd (ranked, sign-fixed basis; rows
@@ -312,7 +395,7 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double d
                                                              Counters* cnt, int sub, int nsub) {
   extern __shared__ double sm[];
   const int t = blockIdx.x, tid = threadIdx.x;
-  if (c.status[t] & kFreezeMask) return;
+  if (t >= live_slots(c) || (c.status[t] & kFreezeMask)) return;
   const ModelDev& md = c.md;
   const int n = md.n, np = md.n_pad, RT = np / 16;
   DenLds L = dense_lds(sm, np);
@@ -330,9 +413,16 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double d
   const double vh = L.nuc[0];
   const double dte = (sub >= 0) ? dt / nsub : dt;
   double* Gd = c.Gd + (size_t)t * np * np;
+  // warm starts from the previous solve of this trajectory (its block is
+  // keyed by the home index, so it needs no move when slots are compacted);
+  // every kDenseColdEvery steps the solves start cold, which keeps rounding
+  // in the carried basis from accumulating
+  double* W = c.Qw + (size_t)c.home[t] * np * np;
+  const bool warm = (c.nsteps[t] % kDenseColdEvery) != 0;
   if (sub != -2) {
     // ---- propagator geometry: B = v D in the propagation's tile order
-    if (!dense_eigen(c, L.nuc[2], L) && tid == 0) L.flag[1] |= 1;
+    if (!dense_eigen(c, L.nuc[2], L, warm ? W : nullptr, Gd) && tid == 0) L.flag[1] |= 1;
+    save_basis(c, L, W);
     dense_project(c, L, Gd);
     const double tol = lam_tol(L, n);
     double* Bt = c.Bt ? c.Bt + (size_t)t * np * np : nullptr;
@@ -369,7 +459,8 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double d
   }
   // ---- end point: energies, amplitudes, couplings for the hop, forces
   const double xn = L.nuc[1];
-  if (!dense_eigen(c, xn, L) && tid == 0) L.flag[1] |= 1;
+  if (!dense_eigen(c, xn, L, warm ? W : nullptr, Gd) && tid == 0) L.flag[1] |= 1;
+  save_basis(c, L, W);
   dense_project(c, L, Gd);
   for (int j = tid; j < np; j += kDenThreads) {
     c.lam[(size_t)t * np + j] = L.lam[j];
@@ -400,6 +491,9 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_query(ClassDev c, int t0,
   DenLds L = dense_lds(sm, np);
   const double x = c.x[t];
   const bool ok = dense_eigen(c, x, L);
+  // a state upload (mode 1) sets the warm-start basis; a plain query leaves
+  // it, so that queries do not change the dynamics
+  if (mode == 1) save_basis(c, L, c.Qw + (size_t)c.home[t] * np * np);
   double* Gd = c.Gd + (size_t)t * np * np;
   dense_project(c, L, Gd);
   for (int j = tid; j < np; j += kDenThreads) {
@@ -434,6 +528,7 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_init_thermal(ClassDev c, 
   DenLds L = dense_lds(sm, np);
   const double x = c.x[t];
   const bool ok = dense_eigen(c, x, L);
+  save_basis(c, L, c.Qw + (size_t)c.home[t] * np * np);
   double* Gd = c.Gd + (size_t)t * np * np;
   dense_project(c, L, Gd);
   int32_t* occ = c.occ + (size_t)t * N;

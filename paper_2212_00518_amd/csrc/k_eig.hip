@@ -442,12 +442,10 @@ __device__ void load_bath(const ClassDev& c, EigLds& L) {
 // end point); sub = j in [0, nsub): only the propagator of electronic
 // sub-step j, frozen at x_n + (j + 1/2)/nsub (x_{n+1} - x_n) for dt/nsub;
 // sub = -2: only the end point (after the sub-steps).
-__global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt_run, int precision,
-                                                           Counters* cnt, int sub, int nsub) {
-  __shared__ EigLds L;
-  const int t = blockIdx.x;
+__device__ void eig_step_one(const ClassDev& c, int t, double dt_run, int precision, Counters* cnt,
+                             int sub, int nsub, EigLds& L) {
   const int tid = threadIdx.x;
-  if (c.status[t] & kFreezeMask) return;
+  if (t >= live_slots(c) || (c.status[t] & kFreezeMask)) return;
   const double dt = c.clock ? c.clock[2 * (size_t)t] : dt_run;  // this trajectory's step
   const ModelDev& md = c.md;
   load_bath(c, L);
@@ -567,6 +565,25 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt_
     if (L.fail & 2) st |= IESH_TRAJ_NONCONV;
     c.status[t] = st;
   }
+}
+
+__global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt_run, int precision,
+                                                           Counters* cnt, int sub, int nsub) {
+  __shared__ EigLds L;
+  eig_step_one(c, blockIdx.x, dt_run, precision, cnt, sub, nsub, L);
+}
+
+// The same step for several arrowhead classes in one launch: block b works
+// on slot b - first[k] of class k (first[k] <= b < first[k + 1]).  The classes
+// come largest first, so the dispatcher hands out the long work-groups
+// first and the small classes fill the compute units behind them.
+__global__ __launch_bounds__(kEigThreads) void k_eig_fused(ClassSet set, double dt_run, int precision,
+                                                            Counters* cnt, int sub, int nsub) {
+  __shared__ EigLds L;
+  const int b = blockIdx.x;
+  int k = 0;
+  while (k + 1 < set.n && b >= set.first[k + 1]) ++k;
+  eig_step_one(set.c[k], b - set.first[k], dt_run, precision, cnt, sub, nsub, L);
 }
 
 // Eigen-solve at the current x (no dynamics): energies, amplitudes, model
@@ -964,6 +981,14 @@ hipError_t launch_eig_step(const ClassDev& c, double dt, Counters* cnt, hipStrea
   if (c.n_live < 1) return hipSuccess;
   hipLaunchKernelGGL(k_eig_step, dim3(c.n_live), dim3(kEigThreads), 0, s, c, dt, precision, cnt, sub,
                      nsub);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_fused(const ClassSet& set, double dt, int precision, Counters* cnt, hipStream_t s,
+                            int sub, int nsub) {
+  if (set.n < 1 || set.first[set.n] < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_eig_fused, dim3(set.first[set.n]), dim3(kEigThreads), 0, s, set, dt, precision, cnt,
+                     sub, nsub);
   return hipGetLastError();
 }
 

@@ -608,11 +608,10 @@ __device__ void hop_one(const ClassDev& c, int t, double dt_run, uint64_t seed, 
 }
 
 
-// Work-group b takes entry b of the class queue hopq = [count, unused, done,
-// list...] that the bound kernel fills (work-groups past the count exit at
-// once; the dispatcher hands out work-groups in order, so the busy ones fill
-// the compute units first).  The last work-group to finish resets the queue
-// for the next step.  In query mode work-group b handles trajectory t0 + b.
+// Work-group b takes entries b, b + G, ... (G the grid) of the class queue
+// hopq = [count, unused, done, list...] that the bound kernel fills; the
+// last work-group to finish resets the queue for the next step.  In query
+// mode work-group b handles trajectory t0 + b.
 template <bool kF32, int kRS, int kRB, bool kDense>
 __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint64_t seed,
                                                      Counters* cnt, iesh_event* events,
@@ -622,9 +621,10 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
   __shared__ HopLds L;
   int32_t* q = c.hopq;
   const int b = blockIdx.x;
-  int t = t0 + b;
-  if (!query_mode) t = (b < q[0]) ? q[3 + b] : -1;
-  if (t >= 0) {
+  // persistent: entries b, b + G, b + 2G, ... of the queue (G the grid)
+  const int n_items = query_mode ? 1 : q[0];
+  for (int e = query_mode ? 0 : b; e < n_items; e += gridDim.x) {
+    const int t = query_mode ? t0 + b : q[3 + e];
     double2* xscr = x_via_scratch<kRS, kRB>() ? c.hopx + (size_t)t * c.md.N * c.md.N : nullptr;
     hop_one<kF32, kRS, kRB, kDense>(c, t, dt, seed, cnt, events, query_mode, record, exit_enabled,
                                     exit_x, max_steps, L, xscr);
@@ -668,16 +668,13 @@ struct FltLds {
 };
 
 template <bool kF32, bool kDense>
-__global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double dt_run, uint64_t seed,
-                                                            Counters* cnt, int record,
-                                                            int exit_enabled, double exit_x,
-                                                            int64_t max_steps, double delta) {
-  __shared__ FltLds L;
-  const int t = blockIdx.x;
+__device__ void filter_one(const ClassDev& c, int t, double dt_run, uint64_t seed, Counters* cnt,
+                           int record, int exit_enabled, double exit_x, int64_t max_steps,
+                           double delta, FltLds& L) {
   const int tid = threadIdx.x;
   const ModelDev& md = c.md;
   const int n = md.n, n_pad = md.n_pad, N = md.N;
-  if (c.status[t] & kFreezeMask) return;
+  if (t >= live_slots(c) || (c.status[t] & kFreezeMask)) return;
   const double dt = c.clock ? c.clock[2 * (size_t)t] : dt_run;  // this trajectory's step
   for (int k = tid; k < n_pad; k += kFltThreads) {
     L.lam[k] = c.lam[(size_t)t * n_pad + k];
@@ -825,6 +822,20 @@ __global__ __launch_bounds__(kFltThreads) void k_hop_filter(ClassDev c, double d
   }
 }
 
+// The bound for several classes (all of one kind) in one launch: block b
+// works on slot b - first[k] of class k, classes largest first.
+template <bool kF32, bool kDense>
+__global__ __launch_bounds__(kFltThreads) void k_filter_fused(ClassSet set, double dt_run, uint64_t seed,
+                                                              Counters* cnt, int record, int exit_enabled,
+                                                              double exit_x, int64_t max_steps, double delta) {
+  __shared__ FltLds L;
+  const int b = blockIdx.x;
+  int k = 0;
+  while (k + 1 < set.n && b >= set.first[k + 1]) ++k;
+  filter_one<kF32, kDense>(set.c[k], b - set.first[k], dt_run, seed, cnt, record, exit_enabled, exit_x,
+                           max_steps, delta, L);
+}
+
 __global__ void k_advance(Counters* cnt) {
   if (threadIdx.x == 0 && blockIdx.x == 0) cnt->step = cnt->step + 1;
 }
@@ -857,6 +868,42 @@ static void launch_hop_t(const ClassDev& c, dim3 grid, double dt, uint64_t seed,
   if constexpr (bucket_possible<RS, RB>())
     hipLaunchKernelGGL((k_hop<F32, RS, RB, false>), grid, dim3(kHopThreads), 0, s, c, dt, seed, cnt,
                        events, query_mode, t0, record, exit_enabled, exit_x, max_steps);
+}
+
+template <bool F32, int RS, int RB>
+static const void* hop_fn_t(bool dense) {
+  if (dense) {
+    if constexpr (bucket_possible<RS, RB>(IESH_DENSE_MAX_N)) return (const void*)k_hop<F32, RS, RB, true>;
+    return nullptr;
+  }
+  if constexpr (bucket_possible<RS, RB>()) return (const void*)k_hop<F32, RS, RB, false>;
+  return nullptr;
+}
+
+template <bool F32, int RS>
+static const void* hop_fn_rs(const ClassDev& c) {
+  const int rb = (c.md.n - c.md.N + 15) / 16;
+  const bool d = c.Gd != nullptr;
+  if (rb <= 2) return hop_fn_t<F32, RS, 2>(d);
+  if (rb <= 4) return hop_fn_t<F32, RS, 4>(d);
+  if (rb <= 7) return hop_fn_t<F32, RS, 7>(d);
+  if (rb <= 11) return hop_fn_t<F32, RS, 11>(d);
+  if (rb <= 14) return hop_fn_t<F32, RS, 14>(d);
+  return hop_fn_t<F32, RS, 21>(d);
+}
+
+template <bool F32>
+static const void* hop_fn_p(const ClassDev& c) {
+  const int rs = (c.md.N + 15) / 16;
+  if (rs <= 2) return hop_fn_rs<F32, 2>(c);
+  if (rs <= 4) return hop_fn_rs<F32, 4>(c);
+  if (rs <= 7) return hop_fn_rs<F32, 7>(c);
+  if (rs <= 10) return hop_fn_rs<F32, 10>(c);
+  return hop_fn_rs<F32, 11>(c);
+}
+
+static const void* hop_fn(const ClassDev& c, int precision) {
+  return precision == IESH_FP64 ? hop_fn_p<false>(c) : hop_fn_p<true>(c);
 }
 
 template <bool F32, int RS>
@@ -904,6 +951,18 @@ static void launch_hop_p(const ClassDev& c, dim3 grid, double dt, uint64_t seed,
 #undef IESH_HOP_RS
 }
 
+// Work-groups of the ratio kernel resident at once (one trajectory each).
+int hop_resident_groups(const ClassDev& c, int precision, int n_cu) {
+  // every instantiation has 512 threads and the same static LDS; registers
+  // differ by shape, so take the occupancy of the class's own kernel
+  int per_cu = 0;
+  const void* fn = hop_fn(c, precision);
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kHopThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu * n_cu;
+}
+
 bool hop_needs_scratch(const ClassDev& c) {
   const int rs = (c.md.N + 15) / 16, rb = (c.md.n - c.md.N + 15) / 16;
   const int RS = rs <= 2 ? 2 : rs <= 4 ? 4 : rs <= 7 ? 7 : rs <= 10 ? 10 : 11;
@@ -917,7 +976,8 @@ hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt
                       int exit_enabled, double exit_x, int64_t max_steps, int precision,
                       hipStream_t s) {
   if (!query_mode && c.n_live < 1) return hipSuccess;
-  const dim3 grid(query_mode ? nt : c.n_live);
+  const int full = c.hop_groups > 0 && c.hop_groups < c.n_live ? c.hop_groups : c.n_live;
+  const dim3 grid(query_mode ? nt : full);
   const int t0e = query_mode ? t0 : 0;
   if (precision == IESH_FP64)
     launch_hop_p<false>(c, grid, dt, seed, cnt, events, query_mode, t0e, record, exit_enabled,
@@ -928,27 +988,28 @@ hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt
   return hipGetLastError();
 }
 
-hipError_t launch_hop_filter(const ClassDev& c, double dt, uint64_t seed, Counters* cnt, int record,
-                             int exit_enabled, double exit_x, int64_t max_steps, int precision,
-                             hipStream_t s) {
-  // orthonormality defect allowed for the stored orbitals (floor)
+hipError_t launch_filter_fused(const ClassSet& set, double dt, uint64_t seed, Counters* cnt, int record,
+                               int exit_enabled, double exit_x, int64_t max_steps, int precision,
+                               hipStream_t s) {
+  if (set.n < 1 || set.first[set.n] < 1) return hipSuccess;
   const double delta = (precision == IESH_FP64) ? kDeltaFP64 : kDeltaMixed;
-  if (c.n_live < 1) return hipSuccess;
-#define IESH_FILTER(F32, DENSE)                                                                   \
-  hipLaunchKernelGGL((k_hop_filter<F32, DENSE>), dim3(c.n_live), dim3(kFltThreads), 0, s, c, dt, seed, \
-                     cnt, record, exit_enabled, exit_x, max_steps, delta)
+  const bool dense = set.c[0].Gd != nullptr;
+  const dim3 grid(set.first[set.n]);
+#define IESH_FUSED(F32, DENSE)                                                                           \
+  hipLaunchKernelGGL((k_filter_fused<F32, DENSE>), grid, dim3(kFltThreads), 0, s, set, dt, seed, cnt, record, \
+                     exit_enabled, exit_x, max_steps, delta)
   if (precision == IESH_FP64) {
-    if (c.Gd)
-      IESH_FILTER(false, true);
+    if (dense)
+      IESH_FUSED(false, true);
     else
-      IESH_FILTER(false, false);
+      IESH_FUSED(false, false);
   } else {
-    if (c.Gd)
-      IESH_FILTER(true, true);
+    if (dense)
+      IESH_FUSED(true, true);
     else
-      IESH_FILTER(true, false);
+      IESH_FUSED(true, false);
   }
-#undef IESH_FILTER
+#undef IESH_FUSED
   return hipGetLastError();
 }
 

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kLowThreads) void k_lowdin(ClassDev c, Counters* cn
   double2* Y = X + (size_t)N * N;  // [N][32 kPassSlots]: a state pass of the new orbitals
   const int tid = threadIdx.x, ti = tid & 31, tj = tid >> 5;
 
-  for (int t = blockIdx.x; t < c.n_live; t += gridDim.x) {
+  for (int t = blockIdx.x; t < live_slots(c); t += gridDim.x) {
     if (c.status[t] & kFreezeMask) continue;  // uniform
     float2* C = reinterpret_cast<float2*>(c.C32) + (size_t)t * N * n_pad;  // C[j][s]
 

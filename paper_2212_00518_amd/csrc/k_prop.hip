@@ -279,17 +279,15 @@ __device__ void clenshaw_tiles(const Slab<T>& s, int t0, int tid) {
 // few tiers so that narrow slabs get a kernel with fewer registers (more
 // work-groups per CU).
 template <typename T, int kMode, int kQ>
-__global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c, T* taps, int tap_k) {
+__device__ void prop_item(const ClassDev& c, T* taps, int tap_k, int b, unsigned char* smem_raw) {
   typedef PropCfg<T> Cfg;
-  extern __shared__ unsigned char smem_raw[];
 
   // XCD-aware id mapping: blocks b, b+8, b+16, ... share an XCD.
-  const int b = blockIdx.x;
   const int xcd = b & 7;
   const int local = b >> 3;
   const int slab = local % c.n_slabs;
   const int t = (local / c.n_slabs) * 8 + xcd;
-  if (t >= c.n_live) return;
+  if (t >= live_slots(c)) return;
   if (c.status[t] & kFreezeMask) return;
 
   const ModelDev& md = c.md;
@@ -383,6 +381,14 @@ __global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c, T* taps, int 
       Cg[((size_t)o * s.n_pad + i) * 2 + 1] = s.X0[i * s.ldx + col + 8];
     }
   }
+}
+
+// One work-group per (trajectory, slab) item; items of slots past the live
+// count (read from the device) end at once.
+template <typename T, int kMode, int kQ>
+__global__ __launch_bounds__(kPropThreads) void k_prop(ClassDev c, T* taps, int tap_k) {
+  extern __shared__ unsigned char smem_raw[];
+  prop_item<T, kMode, kQ>(c, taps, tap_k, blockIdx.x, smem_raw);
 }
 
 template <typename T>
