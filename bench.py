@@ -291,9 +291,12 @@ def cpu_model():
     return f"{name} ({os.cpu_count()} logical CPUs on the host)"
 
 
-def scattering_bench(a):
-    """Uneven batched scattering workload: useful (active) trajectory-steps/s
-    with compaction every 100 steps."""
+def scattering_run(steps, forced_lifetimes, n_traj=None, timed_steps=50, report_progress=True):
+    """Uneven batched scattering workload (bath classes M = 40, 80, 160, 320,
+    N = M/2, mixed path, compaction every 100 steps on the device): useful
+    (active) trajectory-steps/s over `steps` graph-replayed steps, then a
+    window of `timed_steps` steps with per-kernel HIP events for the
+    propagation roofline (flops from the per-class Chebyshev sums)."""
     import numpy as np
     import torch
     from paper_2212_00518_amd import _lib
@@ -301,7 +304,7 @@ def scattering_bench(a):
     from workloads.sampling import bath_classes, scattering_initial
 
     cfg = get_config("c3")
-    T = a.n_traj or cfg["n_traj"]
+    T = n_traj or cfg["n_traj"]
     classes = cfg["bath"]["M_classes"]
     cls = bath_classes(T, classes, seed=cfg["seed"])
     descs = []
@@ -318,7 +321,7 @@ def scattering_bench(a):
     ens = _lib.Ensemble(descs, run, traj_model=cls)
     t_create = time.perf_counter() - t_create
     ens.init_thermal(x0, v0)
-    if a.forced_lifetimes:
+    if forced_lifetimes:
         rng = np.random.default_rng(cfg["seed"] + 2)
         caps = np.exp(rng.uniform(np.log(200.0), np.log(20000.0), size=T)).astype(np.int64)
         ens.set_step_caps(caps)
@@ -329,20 +332,50 @@ def scattering_bench(a):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
-    while done < a.steps:
-        k = min(chunk, a.steps - done)
+    while done < steps:
+        k = min(chunk, steps - done)
         live = sum(ens.class_info(c)["live"] for c in range(len(classes)))
         visited += live * k
         ens.run(k)
         done += k
-        print(f"# step {done}: live slots {live}", file=sys.stderr, flush=True)
+        if report_progress:
+            print(f"# step {done}: live slots {live}", file=sys.stderr, flush=True)
     ens.sync()
     wall = time.perf_counter() - t0
     _, traj_steps = ens.work()
+    # propagation roofline over a short window with HIP events on every launch
+    ens.timing(True)
+    ens.run(timed_steps)
+    tm = ens.timing_read()
+    flops = 0.0
+    for k, M in enumerate(classes):
+        kt, _ = ens.class_work(k)
+        flops += algorithmic_prop_flops(M + 1, M // 2, kt)
+    ens.timing(False)
     status = ens.status()
     info1 = [ens.class_info(k) for k in range(len(classes))]
     _, v_end, _, _ = ens.get_state()
     ens.close()
+    prop_ms = tm["prop"][0]
+    achieved = flops / (prop_ms * 1e-3) / 1e12 if prop_ms > 0 else 0.0
+    return dict(cfg=cfg, T=T, classes=classes, wall=wall, traj_steps=traj_steps, visited=visited,
+                status=status, info0=info0, info1=info1, v_end=v_end, e_inc=e_inc, t_create=t_create,
+                roofline={"bound": "mfma", "kernel": "k_prop (all classes)", "achieved": round(achieved, 3),
+                          "peak": PEAK_TFLOPS["mixed"], "unit": "TFLOP/s",
+                          "frac": round(achieved / PEAK_TFLOPS["mixed"], 4), "traffic": None,
+                          "window_steps": timed_steps,
+                          "prop_ms_per_step": round(prop_ms / timed_steps, 4)},
+                kernels_ms_per_step={k: round(v[0] / timed_steps, 4) for k, v in tm.items() if v[1]})
+
+
+def scattering_bench(a):
+    """Uneven batched scattering workload: useful (active) trajectory-steps/s
+    with compaction every 100 steps."""
+    import numpy as np
+    from paper_2212_00518_amd import _lib
+
+    r = scattering_run(a.steps, a.forced_lifetimes, a.n_traj)
+    cfg, classes, status, v_end, e_inc = r["cfg"], r["classes"], r["status"], r["v_end"], r["e_inc"]
     # kinetic-energy loss of the trajectories that rebounded past the exit
     # distance: 1 - E_kin(final) / E_inc, by incidence energy (Sec. III.D)
     out = (status & _lib.TRAJ_EXITED) > 0
@@ -356,27 +389,29 @@ def scattering_bench(a):
                         "mean_ke_loss": round(float(loss[sel].mean()), 4) if sel.any() else None})
     line = {
         "metric": "useful trajectory-steps/s (scattering, uneven M, compaction every 100 steps)",
-        "value": round(traj_steps / wall, 2),
+        "value": round(r["traj_steps"] / r["wall"], 2),
         "unit": "trajectory-steps/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": 0,
-        "ms_per_step": round(1e3 * wall / a.steps, 3),
+        "ms_per_step": round(1e3 * r["wall"] / a.steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "M_classes": classes, "n_traj": T, "dt": cfg["dt"],
+        "config": {"workload": cfg["name"], "M_classes": classes, "n_traj": r["T"], "dt": cfg["dt"],
                    "forced_lifetimes": bool(a.forced_lifetimes), "path": "mixed"},
-        "active_trajectory_steps": int(traj_steps),
-        "visited_slot_steps": int(visited),
-        "compaction_efficiency": round(traj_steps / max(visited, 1), 4),
+        "roofline": r["roofline"],
+        "kernels_ms_per_step": r["kernels_ms_per_step"],
+        "active_trajectory_steps": int(r["traj_steps"]),
+        "visited_slot_steps": int(r["visited"]),
+        "compaction_efficiency": round(r["traj_steps"] / max(r["visited"], 1), 4),
         "frozen_at_end": int((status != 0).sum()),
-        "tiles_per_group": {str(M): i["tiles_per_group"] for M, i in zip(classes, info0)},
-        "live_slots_at_end": {str(M): i["live"] for M, i in zip(classes, info1)},
-        "trajectories_per_class": {str(M): i["n_traj"] for M, i in zip(classes, info0)},
-        "context_creation_s": round(t_create, 2),
+        "tiles_per_group": {str(M): i["tiles_per_group"] for M, i in zip(classes, r["info0"])},
+        "live_slots_at_end": {str(M): i["live"] for M, i in zip(classes, r["info1"])},
+        "trajectories_per_class": {str(M): i["n_traj"] for M, i in zip(classes, r["info0"])},
+        "context_creation_s": round(r["t_create"], 2),
         "kinetic_energy_loss": ke_loss,
     }
     print(json.dumps(line), flush=True)
@@ -786,6 +821,8 @@ def main():
                     help="skip the adjoint ms/step entry of the default line")
     ap.add_argument("--no-steady", action="store_true",
                     help="skip the steady-state window (1000-step pre-roll, 100 timed steps)")
+    ap.add_argument("--no-scattering", action="store_true",
+                    help="skip the 300-step scattering (uneven batching) entry of the default line")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the small-workload (M = 20, 128 trajectories) throughput entry")
     ap.add_argument("--forced-lifetimes", action="store_true",
@@ -923,6 +960,19 @@ def main():
         line["mixed_vs_fp64_gpu"] = mixed_vs_fp64(cfg, steps=a.error_steps)
     if not a.no_small and a.config == "c2":
         line["small_workload"] = small_workload()
+    if not a.no_scattering and a.config == "c2":
+        # the batched scattering workload (four bath-size classes, device-side
+        # compaction) over a 300-step prefix with forced lifetimes
+        sc = scattering_run(300, True, report_progress=False)
+        line["scattering"] = {
+            "metric": "useful trajectory-steps/s (scattering, M in {40,80,160,320}, 16384 trajectories)",
+            "value": round(sc["traj_steps"] / sc["wall"], 2), "unit": "trajectory-steps/s", "steps": 300,
+            "ms_per_step": round(1e3 * sc["wall"] / 300, 3),
+            "compaction_efficiency": round(sc["traj_steps"] / max(sc["visited"], 1), 4),
+            "live_slots_at_end": {str(M): i["live"] for M, i in zip(sc["classes"], sc["info1"])},
+            "roofline": sc["roofline"], "kernels_ms_per_step": sc["kernels_ms_per_step"]}
+        print(f"# scattering: {line['scattering']['value']:.1f} useful trajectory-steps/s", file=sys.stderr,
+              flush=True)
     if not a.no_adjoint:
         # the adjoint workload's ms/step on a 200-step prefix of its paths
         adj = adjoint_bench(argparse.Namespace(n_traj=None), n_steps=200, report=False)

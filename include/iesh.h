@@ -404,6 +404,11 @@ int iesh_timing_read(iesh_ctx* ctx, double* ms, int64_t* launches);
    propagation of a trajectory costs 4 K n^2 N real flops for K terms) and
    the number of trajectory-steps. */
 int iesh_work(iesh_ctx* ctx, int64_t* sum_cheb_terms, int64_t* traj_steps);
+/* The same two sums for the trajectories of one bath-size class (model index
+   cls), for per-class work: one propagation of a trajectory of that class
+   costs 4 K n^2 N real flops with its own n and N. */
+int iesh_class_work(iesh_ctx* ctx, int32_t cls, int64_t* sum_cheb_terms, int64_t* traj_steps);
+
 /* Trajectory-steps since iesh_timing was last called whose hop
    probabilities had to be evaluated from the determinant ratios (the others
    were completed by the exact no-hop bound); synchronises. */

@@ -244,6 +244,24 @@ def next_dt(g_total, dt_cur, dt0, g_max, levels):
     return dtn
 
 
+def run_to_exit(model, st: State, dt: float, n_max: int, seed: int, traj: int, exit_x: float,
+                exit_dof: int = 0):
+    """Run until the step that takes coordinate exit_dof past exit_x (the
+    trajectory leaves and is frozen there, as a scattering trajectory that has
+    rebounded, Sec. III.D), at most n_max steps.  Returns (state, steps taken,
+    events)."""
+    F = el.forces(model, st.x, st.s)
+    events = []
+    for k in range(n_max):
+        st, ev, F = step(model, st, dt, _rng.uniform(seed, traj, k), F)
+        ev["step"] = k
+        if ev["attempted"]:
+            events.append(ev)
+        if st.x[exit_dof] > exit_x:
+            return st, k + 1, events
+    return st, n_max, events
+
+
 def run(model, st: State, dt: float, n_steps: int, seed: int, traj: int, step0: int = 0,
         record_every: int = 0, substeps: int = 1, adapt=None):
     """Run n_steps; the hop uniform of step k (0-based, counted from step0) is

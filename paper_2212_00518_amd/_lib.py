@@ -47,7 +47,7 @@ SYMBOLS = (
     "iesh_clear_events", "iesh_query_sizes", "iesh_sync", "iesh_last_error", "iesh_version",
     "iesh_timing", "iesh_timing_read", "iesh_work", "iesh_hop_evals", "iesh_class_info",
     "iesh_set_step_caps", "iesh_adjoint_forward", "iesh_adjoint_backward", "iesh_eigh_batched",
-    "iesh_orthonormality_defect", "iesh_eigh_batched_noalloc", "iesh_bath",
+    "iesh_orthonormality_defect", "iesh_eigh_batched_noalloc", "iesh_bath", "iesh_class_work",
 )
 TIMERS = ("eig", "prop", "hop", "lowdin", "filter", "adj_prop", "adj_phi", "adj_eig", "adj_hop")
 
@@ -129,6 +129,7 @@ def lib():
         L.iesh_timing_read.argtypes = [vp, dp, C.POINTER(C.c_int64)]
         L.iesh_work.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.iesh_hop_evals.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.iesh_class_work.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.iesh_class_info.argtypes = [vp, C.c_int32, ip]
         L.iesh_set_step_caps.argtypes = [vp, C.POINTER(C.c_int64)]
         L.iesh_adjoint_forward.argtypes = [vp, dp, C.c_int32, C.c_int32, dp, dp]
@@ -451,6 +452,13 @@ class Ensemble:
     def work(self):
         a, b = C.c_int64(), C.c_int64()
         self._check(lib().iesh_work(self.ctx, C.byref(a), C.byref(b)), "iesh_work")
+        return a.value, b.value
+
+    def class_work(self, cls: int):
+        """(Chebyshev terms summed, trajectory-steps) of one class since
+        iesh_timing was last called."""
+        a, b = C.c_int64(), C.c_int64()
+        self._check(lib().iesh_class_work(self.ctx, int(cls), C.byref(a), C.byref(b)), "iesh_class_work")
         return a.value, b.value
 
     def set_step_caps(self, caps):

@@ -933,7 +933,8 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
         (rc = dalloc(ctx, &c.cheb, (size_t)T * kChebStride)) ||
         (rc = dalloc(ctx, &c.gbuf, (size_t)T * N * n_pad)) ||
         (rc = dalloc(ctx, &c.clock, (size_t)2 * T)) ||
-        (rc = dalloc(ctx, &c.hopq, (size_t)3 + T)) || (rc = dalloc(ctx, &c.live, 1)))
+        (rc = dalloc(ctx, &c.hopq, (size_t)3 + T)) || (rc = dalloc(ctx, &c.live, 1)) ||
+        (rc = dalloc(ctx, &c.work, 2)))
       return bail(rc);
     if (hop_needs_scratch(c) && (rc = dalloc(ctx, &c.hopx, (size_t)T * N * N)))
       return bail(rc);
@@ -1460,6 +1461,20 @@ int iesh_timing(iesh_ctx* ctx, int32_t enable) {
   ctx->ev_marks.clear();
   const int64_t zero[3] = {0, 0, 0};
   HIPTRY(ctx, hipMemcpy(&ctx->cnt->sum_cheb, zero, sizeof(zero), hipMemcpyHostToDevice));
+  for (auto& c : ctx->cls)
+    if (c.work) HIPTRY(ctx, hipMemcpy(c.work, zero, 2 * sizeof(int64_t), hipMemcpyHostToDevice));
+  return IESH_OK;
+}
+
+int iesh_class_work(iesh_ctx* ctx, int32_t cls, int64_t* sum_cheb_terms, int64_t* traj_steps) {
+  if (!ctx || cls < 0 || cls >= (int)ctx->cls.size() || !sum_cheb_terms || !traj_steps)
+    return fail(ctx, IESH_EINVAL, "class index or null pointer");
+  HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+  int64_t w[2] = {0, 0};
+  if (ctx->cls[cls].work)
+    HIPTRY(ctx, hipMemcpy(w, ctx->cls[cls].work, sizeof(w), hipMemcpyDeviceToHost));
+  *sum_cheb_terms = w[0];
+  *traj_steps = w[1];
   return IESH_OK;
 }
 

@@ -59,11 +59,11 @@ __device__ inline int cheb_terms(double rho, double tol) {
 // Hermitian matrix has its spectrum in [lo, hi] (Gershgorin bounds): centre,
 // 1/radius, number of terms K and the coefficients
 //   c_k = e^{-i c dte} (2 - delta_k0) (-i)^k J_k(r dte).
-// Counts the terms in the work counters (count_step: also one
-// trajectory-step).  J: scratch of kMaxCheb doubles.  Returns K, or -1 when
+// Counts the terms in the work counters, the context's and (cls_work, may be
+// null) the class's (count_step: also one trajectory-step).  J: scratch of kMaxCheb doubles.  Returns K, or -1 when
 // the series would need more than kMaxCheb terms.
 __device__ inline int write_cheb(double* cb, double lo, double hi, double dte, int precision,
-                                 Counters* cnt, bool count_step, double* J) {
+                                 Counters* cnt, bool count_step, double* J, int64_t* cls_work) {
   const double cc = 0.5 * (lo + hi);
   const double rr = fmax(0.5 * (hi - lo), 1e-300);
   const double rho = rr * dte;
@@ -93,6 +93,10 @@ __device__ inline int write_cheb(double* cb, double lo, double hi, double dte, i
   atomicAdd((unsigned long long*)&cnt->sum_cheb, (unsigned long long)K);
   if (count_step) atomicAdd((unsigned long long*)&cnt->traj_steps, 1ull);
   atomicMax((unsigned long long*)&cnt->max_cheb, (unsigned long long)K);
+  if (cls_work) {  // the same two sums for the trajectory's class
+    atomicAdd((unsigned long long*)&cls_work[0], (unsigned long long)K);
+    if (count_step) atomicAdd((unsigned long long*)&cls_work[1], 1ull);
+  }
   return K;
 }
 

@@ -79,6 +79,7 @@ struct ClassDev {
   ModelDev md;
   int n_traj;           // trajectories in this class (allocated slots)
   int n_live;           // host: slots a launch covers (the class size, except while autotuning)
+  int64_t* work = nullptr;  // [2] device: Chebyshev terms summed, trajectory-steps (this class)
   int32_t* live = nullptr;  // [1] device: leading slots the step kernels visit (the
                             // others hold frozen trajectories); lowered by the
                             // compaction kernels without a host round trip

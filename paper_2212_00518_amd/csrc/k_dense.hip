@@ -449,7 +449,7 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double d
     const double lo = block_min(lo_part, L.red), hi = block_max(hi_part, L.red);
     if (tid == 0) {
       double* cb = c.cheb + (size_t)t * kChebStride;
-      if (write_cheb(cb, lo, hi, dte, precision, cnt, sub <= 0, L.J) < 0) L.flag[1] |= 2;
+      if (write_cheb(cb, lo, hi, dte, precision, cnt, sub <= 0, L.J, c.work) < 0) L.flag[1] |= 2;
     }
     __syncthreads();
     if (sub >= 0) {

@@ -525,7 +525,8 @@ __device__ void eig_step_one(const ClassDev& c, int t, double dt_run, int precis
   }
   if (tid == 0) {
     double* cb = c.cheb + (size_t)t * kChebStride;
-    if (write_cheb(cb, L.red[0], L.red2[0], dte, precision, cnt, sub <= 0, L.J) < 0) atomicOr(&L.fail, 2);
+    if (write_cheb(cb, L.red[0], L.red2[0], dte, precision, cnt, sub <= 0, L.J, c.work) < 0)
+      atomicOr(&L.fail, 2);
   }
   __syncthreads();
   }

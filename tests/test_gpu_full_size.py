@@ -266,3 +266,93 @@ def test_steady_state_step_after_1000_steps_m200(precision):
         assert mine == ([(ev["a"], ev["b"], ev["accepted"])] if ev["attempted"] else []), t
         compared += 1
     assert compared >= 6
+
+
+def test_scattering_2000_steps_with_exits_and_device_compaction():
+    """The batched scattering workload as the benchmark runs it, long enough
+    for real exits: 16384 trajectories in the classes M = 40, 80, 160, 320,
+    forced lifetimes (step caps log-uniform in [200, 20000]), 2000 steps with
+    compaction on the device every 100 steps.  Per class, the trajectory with
+    the earliest cap is run by the oracle for its capped length (frozen at the
+    cap, then moved behind the active slots), and trajectories that left
+    through the exit plane (x > 15 bohr) are checked against the oracle's
+    exit step; the live-slot counts equal the trajectories still active."""
+    import multiprocessing as mp
+    import os
+    from paper_2212_00518_amd import _lib, unpack_C
+    cfg = get_config("c3")
+    T, steps = cfg["n_traj"], 2000
+    classes = cfg["bath"]["M_classes"]
+    cls = bath_classes(T, classes, seed=cfg["seed"])
+    descs = []
+    for M in classes:
+        eps, w = _lib.discretize(cfg["bath"]["kind"], M, cfg["bath"]["W"])
+        descs.append(_lib.model_desc(cfg["model"], eps, w, M // 2))
+    x0, v0, _ = scattering_initial(T, cfg["model"]["mass"], cfg["x_start"], cfg["E_inc"],
+                                   seed=cfg["seed"] + 1)
+    run = dict(n_traj=T, precision="mixed", dt=cfg["dt"], kT=0.0, seed=cfg["seed"],
+               lowdin_every=100, exit_enabled=1, exit_x=cfg["exit_x"],
+               max_steps=cfg["max_steps"], compact_every=100)
+    caps = np.exp(np.random.default_rng(cfg["seed"] + 2).uniform(np.log(200.0), np.log(20000.0),
+                                                                   size=T)).astype(np.int64)
+    ens = _lib.Ensemble(descs, run, traj_model=cls)
+    ens.init_thermal(x0, v0)
+    ens.set_step_caps(caps)
+    for k in range(steps // 500):
+        ens.run(500)
+        print(f"step {500 * (k + 1)}: live {[ens.class_info(c)['live'] for c in range(4)]}", flush=True)
+    status = ens.status()
+    live = [ens.class_info(c)["live"] for c in range(4)]
+    clock, _ = ens.clock()
+    x, v, Cf, occ = ens.get_state()
+    n_max, N_max = ens.n_max, ens.N_max
+    ens.close()
+    taken = np.rint(clock / cfg["dt"]).astype(np.int64)
+    active = [int(np.sum((cls == k) & ((status & 0x1b) == 0))) for k in range(4)]
+    assert live == active, (live, active)
+    exited = (status & _lib.TRAJ_EXITED) > 0
+    capped = (status & _lib.TRAJ_STEPCAP) > 0
+    print(f"exited {exited.sum()}, capped {capped.sum()}", flush=True)
+    assert capped.sum() > 2000 and exited.sum() > 0
+    # oracle runs: the earliest-capped trajectory of every class, and up to two
+    # exited trajectories of the two smallest classes
+    jobs = []
+    for k, M in enumerate(classes):
+        members = np.flatnonzero(cls == k)
+        t = int(members[np.argmin(caps[members])])
+        jobs.append((k, t, int(caps[t])))
+        if k < 2:
+            for t in np.flatnonzero((cls == k) & exited)[:2]:
+                jobs.append((k, int(t), steps))
+    models_ = [models.from_config(cfg, M=M) for M in classes]
+    starts = [dyn.initial_state(models_[k], x0[t], v0[t], classes[k] // 2, 0.0, cfg["seed"], t)
+              for k, t, _ in jobs]
+    saved = {q: os.environ.get(q) for q in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
+    os.environ["OMP_NUM_THREADS"] = os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    try:
+        with mp.get_context("spawn").Pool(min(16, len(jobs))) as pool:
+            refs = pool.starmap(dyn.run_to_exit, [(models_[k], st, cfg["dt"], n, cfg["seed"], t,
+                                                   cfg["exit_x"]) for (k, t, n), st in zip(jobs, starts)])
+    finally:
+        for q, val in saved.items():
+            if val is None:
+                os.environ.pop(q, None)
+            else:
+                os.environ[q] = val
+    compared = 0
+    for (k, t, n), (ref, n_taken, ref_ev) in zip(jobs, refs):
+        M = classes[k]
+        print(f"M={M} traj {t}: oracle steps {n_taken}, GPU steps {taken[t]} (cap {caps[t]}), "
+              f"exited {bool(exited[t])}", flush=True)
+        if any(e["margin"] < 1e-4 * e["g_total"] for e in ref_ev):
+            continue            # a near-tie hop decision: not comparable
+        assert taken[t] == n_taken, t
+        if n == steps:          # left through the exit plane
+            assert exited[t] and n_taken < steps, t
+        else:                   # frozen at its cap
+            assert capped[t] and n_taken == n, t
+        assert abs(x[t] - ref.x[0]) <= 1e-6 * max(1.0, abs(ref.x[0])), t
+        assert list(occ[t, :M // 2]) == list(ref.s), t
+        assert np.max(np.abs(unpack_C(Cf, t, M + 1, M // 2, n_max, N_max) - ref.C)) <= 1e-3, t
+        compared += 1
+    assert compared >= len(jobs) - 2
