@@ -288,7 +288,10 @@ int iesh_bath(const iesh_bath_desc* desc, double* eps, double* w, int32_t* lead,
               occupied adiabatic indices.
    mem_kind says whether the pointers are host or device (same device as the
    context) memory.  set_state also recomputes the forces and clears status
-   words and the hop event log; the step counter is kept. */
+   words and the hop event log; the step counter is kept.  During a run each
+   eigen-solve starts from the trajectory's previous solution, after
+   set_state from the uploaded geometry's own, so a run resumed from a saved
+   state agrees with the uninterrupted run to rounding, not bit for bit. */
 int iesh_set_state(iesh_ctx* ctx, const double* x, const double* v, const double* C,
                    const int32_t* occ, int32_t mem_kind);
 int iesh_get_state(iesh_ctx* ctx, double* x, double* v, double* C, int32_t* occ,

@@ -129,6 +129,12 @@ struct ClassDev {
   const double* H0 = nullptr;
   const double* H1 = nullptr;
   double* Gd = nullptr;
+  // arrowhead classes, by home index: the secular roots of the trajectory's
+  // last solve ([T][n_pad] relative to their origin poles, [T][n_pad] the
+  // poles) and its geometry ([T][4]: h, f, valid), the warm start of the next
+  double* root_tau = nullptr;
+  int32_t* root_org = nullptr;
+  double* root_geo = nullptr;
   double* Qw = nullptr;  // [T][n_pad][n_pad] by home index: eigenvectors of the
                          // trajectory's last solve (warm start of the next)
   int32_t* hopq = nullptr;  // [3 + T] queue for the determinant-ratio kernel: count, -, done, list

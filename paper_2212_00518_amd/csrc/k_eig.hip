@@ -126,13 +126,50 @@ __device__ inline double quad_root_in(double a2, double a1, double a0, double al
 }
 
 // Root j (0..M) of the secular function; j0 as in secular_eval.  Returns 1
-// on convergence.
+// on convergence.  Warm start (dlt >= 0): the root is known to lie within dlt
+// of lam_g (the same root of a nearby geometry, see solve_arrowhead); when
+// that interval lies on one side of the gap's midpoint, the origin pole is
+// the near one without evaluating f there, the bracket shrinks to the
+// interval and the iteration starts at lam_g.
 __device__ int secular_root(int j, int j0, int M, const double* e, const double* V2, double h,
-                            double vnorm, int max_it, double& tau_out, int& org_out) {
+                            double vnorm, int max_it, double lam_g, double dlt, double& tau_out,
+                            int& org_out) {
   int o;
   double lo, hi, tau, f = 0.0, dl = 0.0, dr = 0.0, err = 0.0;
   bool have_f = false;
-  if (j == 0) {
+  bool warm = dlt >= 0.0;
+  if (warm && j > 0 && j < M) {
+    const double mid = e[j - 1] + 0.5 * (e[j] - e[j - 1]);
+    if (lam_g + dlt < mid) {
+      o = j - 1;
+      lo = fmax(0.0, (lam_g - dlt) - e[o]);
+      hi = fmin(0.5 * (e[j] - e[j - 1]), (lam_g + dlt) - e[o]);
+    } else if (lam_g - dlt > mid) {
+      o = j;
+      lo = fmax(-0.5 * (e[j] - e[j - 1]) * (1.0 + 4.0 * kEps), (lam_g - dlt) - e[o]);
+      hi = fmin(0.0, (lam_g + dlt) - e[o]);
+    } else {
+      warm = false;  // the root may sit on either side of the midpoint
+    }
+    if (warm) tau = fmin(fmax(lam_g - e[o], lo), hi);
+  }
+  if (warm && (j == 0 || j == M)) {
+    o = (j == 0) ? 0 : M - 1;
+    if (j == 0) {
+      lo = fmax((fmin(h, e[0]) - vnorm) - e[0], (lam_g - dlt) - e[0]);
+      hi = fmin(0.0, (lam_g + dlt) - e[0]);
+    } else {
+      lo = fmax(0.0, (lam_g - dlt) - e[M - 1]);
+      hi = fmin((fmax(h, e[M - 1]) + vnorm) - e[M - 1], (lam_g + dlt) - e[M - 1]);
+    }
+    tau = fmin(fmax(lam_g - e[o], lo), hi);
+  }
+  if (warm) {
+    // an empty interval (it cannot happen while the bound holds) falls back
+    if (!(lo <= hi)) warm = false;
+  }
+  if (warm) {
+  } else if (j == 0) {
     o = 0;
     lo = (fmin(h, e[0]) - vnorm) - e[0];
     hi = 0.0;
@@ -219,10 +256,32 @@ __device__ int secular_root(int j, int j0, int M, const double* e, const double*
   return ok;
 }
 
+// Roots of a trajectory's last arrowhead solve (per secular root, before
+// the deflated states are placed) and that solve's geometry, to start the
+// next solve from (keyed by the trajectory's home index).
+struct RootStore {
+  double* tau;     // [n_pad] root relative to its origin pole
+  int32_t* org;    // [n_pad] origin pole
+  double* geo;     // [4]: h, f, valid (1), unused
+};
+
+__device__ inline RootStore root_store(const ClassDev& c, int t) {
+  const size_t hm = (size_t)c.home[t];
+  return RootStore{c.root_tau + hm * c.md.n_pad, c.root_org + hm * c.md.n_pad, c.root_geo + 4 * hm};
+}
+
 // Solve the arrowhead problem of geometry x; fills lam, tau, org, q0 in LDS
 // (entries n..n_pad-1 of lam/q0 set to 0).  Returns model scalars.
+// rs (may be null): warm = start every root from the stored one of the last
+// solve, store = keep this solve's roots there.  By Weyl's inequality each
+// eigenvalue moves by at most ||H' - H||_2 <= |dh| + ||dV|| between the two
+// geometries (the bath energies are fixed and V = Vbar f(x), so
+// ||dV|| = |df| ||Vbar||); with that bound, doubled, every root gets a bracket
+// that contains it, and the safeguarded iteration converges in a couple of
+// steps instead of starting from the gap.
 __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict__ vbar,
-                                   const double* x, EigLds& L) {
+                                   const double* x, EigLds& L, RootStore rs = RootStore{},
+                                   bool warm = false, bool store = false) {
   // the secular problem over the distinct bath energies (M = M_red poles,
   // M + 1 roots); repeated energies are expanded into deflated states below
   const int M = md.M_red, n = M + 1, tid = threadIdx.x;
@@ -243,19 +302,35 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
   }
   const double vnorm = sqrt(L.red[0]);
   __syncthreads();
+  // warm start: the bound on how far every root moved since the stored solve
+  double dlt = -1.0;
+  if (rs.geo && warm && rs.geo[2] == 1.0) {
+    const double bound = fabs(ma.h - rs.geo[0]) + fabs(ma.f - rs.geo[1]) * (vnorm / ma.f);
+    dlt = 2.0 * bound + 64.0 * kEps * (fabs(ma.h) + vnorm + fabs(L.e[0]) + fabs(L.e[M - 1]));
+  }
   for (int j = tid; j < n; j += kEigThreads) {
     double tau;
     int o;
     // the roots of a wave are the 64 consecutive indices from j0 (the block
     // has a whole number of waves and steps j by its size)
     const int j0 = __builtin_amdgcn_readfirstlane(j - (tid & 63));
-    const int ok = secular_root(j, j0, M, L.e, L.V2, ma.h, vnorm, md.eig_iter, tau, o);
+    const double lam_g = dlt >= 0.0 ? L.e[rs.org[j]] + rs.tau[j] : 0.0;
+    const int ok = secular_root(j, j0, M, L.e, L.V2, ma.h, vnorm, md.eig_iter, lam_g, dlt, tau, o);
     L.tau[j] = tau;
     L.org[j] = o;
     L.lam[j] = L.e[o] + tau;
     if (!ok) atomicOr(&L.fail, 1);
+    if (rs.geo && store) {
+      rs.tau[j] = tau;
+      rs.org[j] = o;
+    }
   }
   __syncthreads();
+  if (rs.geo && store && tid == 0) {
+    rs.geo[0] = ma.h;
+    rs.geo[1] = ma.f;
+    rs.geo[2] = L.fail ? 0.0 : 1.0;
+  }
   // Loewner couplings: Vh_k^2 = -prod_j (e_k - lambda_j) / prod_{l != k} (e_k - e_l),
   // factors paired so that each ratio stays near 1.
   // The factors are taken in the order of l; as in the secular sums, only the
@@ -476,7 +551,12 @@ __device__ void eig_step_one(const ClassDev& c, int t, double dt_run, int precis
   const int n = md.n, n_pad = md.n_pad, RT = n_pad / 16;
   if (sub != -2) {
   // ---- midpoint geometry: couplings for the propagator
-  ModelAt mm = solve_arrowhead(md, c.vbar, L.nuc[2], L);
+  // warm starts from the trajectory's previous solve (not along prescribed
+  // paths, whose backward pass revisits steps out of order)
+  const bool warm = c.root_tau && !c.path;
+  RootStore rs{};
+  if (warm) rs = root_store(c, t);
+  ModelAt mm = solve_arrowhead(md, c.vbar, L.nuc[2], L, rs, warm, warm);
   double vfac = vh;
   if (nd > 1) {
     // v . D over the coordinates: the gradients enter through v.grad h and v.grad f / f
@@ -537,7 +617,10 @@ __device__ void eig_step_one(const ClassDev& c, int t, double dt_run, int precis
   }
 
   // ---- end-point geometry: energies, amplitudes, forces
-  const ModelAt mn = solve_arrowhead(md, c.vbar, L.nuc[1], L);
+  const bool warm_end = c.root_tau && !c.path;
+  RootStore rse{};
+  if (warm_end) rse = root_store(c, t);
+  const ModelAt mn = solve_arrowhead(md, c.vbar, L.nuc[1], L, rse, warm_end, warm_end);
   for (int j = tid; j < n_pad; j += kEigThreads) {
     c.lam[(size_t)t * n_pad + j] = L.lam[j];
     c.q0[(size_t)t * n_pad + j] = L.q0[j];
@@ -598,7 +681,13 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_query(ClassDev c, int t0, i
   const int nd = md.ndof;
   if (tid < nd) L.nuc[1][tid] = c.x[(size_t)t * nd + tid];
   __syncthreads();
-  const ModelAt ma = solve_arrowhead(md, c.vbar, L.nuc[1], L);
+  // a state upload (mode 1) keeps the roots for the warm start of the first
+  // step; a plain query leaves the stored ones, so queries do not change the
+  // dynamics
+  RootStore rs{};
+  const bool store = mode == 1 && c.root_tau && !c.path;
+  if (store) rs = root_store(c, t);
+  const ModelAt ma = solve_arrowhead(md, c.vbar, L.nuc[1], L, rs, false, store);
   for (int j = tid; j < md.n_pad; j += kEigThreads) {
     c.lam[(size_t)t * md.n_pad + j] = L.lam[j];
     c.q0[(size_t)t * md.n_pad + j] = L.q0[j];
@@ -671,7 +760,10 @@ __global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double
   load_bath(c, L);
   if (tid < md.ndof) L.nuc[1][tid] = c.x[(size_t)t * md.ndof + tid];
   __syncthreads();
-  const ModelAt ma = solve_arrowhead(md, c.vbar, L.nuc[1], L);
+  RootStore rs{};
+  const bool store = c.root_tau && !c.path;
+  if (store) rs = root_store(c, t);
+  const ModelAt ma = solve_arrowhead(md, c.vbar, L.nuc[1], L, rs, false, store);
   int32_t* occ = c.occ + (size_t)t * N;
   __shared__ int chosen[kMaxStates];
   bool done = false;
