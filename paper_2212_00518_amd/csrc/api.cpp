@@ -938,7 +938,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
       return bail(rc);
     if (hop_needs_scratch(c) && (rc = dalloc(ctx, &c.hopx, (size_t)T * N * N)))
       return bail(rc);
-    if (!dense && ((rc = dalloc(ctx, &c.root_tau, (size_t)T * n_pad)) ||
+    if (!dense && ((rc = dalloc(ctx, &c.root_tau, (size_t)T * 2 * n_pad)) ||
                    (rc = dalloc(ctx, &c.root_org, (size_t)T * n_pad)) ||
                    (rc = dalloc(ctx, &c.root_geo, (size_t)T * 4))))
       return bail(rc);

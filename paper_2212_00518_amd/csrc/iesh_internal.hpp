@@ -130,8 +130,9 @@ struct ClassDev {
   const double* H1 = nullptr;
   double* Gd = nullptr;
   // arrowhead classes, by home index: the secular roots of the trajectory's
-  // last solve ([T][n_pad] relative to their origin poles, [T][n_pad] the
-  // poles) and its geometry ([T][4]: h, f, valid), the warm start of the next
+  // last solve ([T][2][n_pad]: relative to their origin poles, then the
+  // impurity components q0; [T][n_pad] the poles) and its geometry ([T][4]:
+  // h, f, valid), the warm start of the next
   double* root_tau = nullptr;
   int32_t* root_org = nullptr;
   double* root_geo = nullptr;

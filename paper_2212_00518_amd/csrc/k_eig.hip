@@ -11,11 +11,12 @@
 // found relative to its nearest pole, tau = lambda - eps_o, so that the
 // differences lambda_j - eps_k stay accurate for closely spaced levels; the
 // iteration fits a two-pole rational model to f and f' at the current point
-// (quadratic convergence) inside a bisection bracket.  The bath components
-// of the eigenvectors use couplings recomputed from the roots (Loewner
-// formula), which keeps the computed vectors orthogonal; only the impurity
-// components q0_j are kept, since every quantity of the step is a function
-// of (lambda, q0) alone:
+// (quadratic convergence) inside a bisection bracket.  Only the impurity
+// components q0_j of the eigenvectors are kept, since every quantity of the
+// step is a function of (lambda, q0) alone; q0_j^2 = 1 / f'(lambda_j) comes
+// with the root's last secular evaluation (the bath components, which the
+// lead weights of a biased start need, use couplings recomputed from the
+// roots by the Loewner formula, for which the computed roots are exact):
 //   G_jk = (Q^T dH/dx Q)_jk = q0_j q0_k (h' + rho (lambda_j + lambda_k - 2h)),
 // with V_k(x) = Vbar_k f(x) and rho = f'/f (row 0 of the eigen-equation gives
 // sum_k V_k Q_kj = (lambda_j - h) q0_j).
@@ -130,10 +131,13 @@ __device__ inline double quad_root_in(double a2, double a1, double a0, double al
 // of lam_g (the same root of a nearby geometry, see solve_arrowhead); when
 // that interval lies on one side of the gap's midpoint, the origin pole is
 // the near one without evaluating f there, the bracket shrinks to the
-// interval and the iteration starts at lam_g.
+// interval and the iteration starts at the predicted root lam_s when that
+// lies strictly inside it.  dsum_out: sum_k V_k^2 / (eps_k - lambda)^2 at the
+// last point evaluated (within two units in the last place of the returned
+// root, so f' there is f' at the root to rounding).
 __device__ int secular_root(int j, int j0, int M, const double* e, const double* V2, double h,
-                            double vnorm, int max_it, double lam_g, double dlt, double& tau_out,
-                            int& org_out) {
+                            double vnorm, int max_it, double lam_g, double dlt, double lam_s,
+                            double& tau_out, int& org_out, double& dsum_out) {
   int o;
   double lo, hi, tau, f = 0.0, dl = 0.0, dr = 0.0, err = 0.0;
   bool have_f = false;
@@ -151,7 +155,6 @@ __device__ int secular_root(int j, int j0, int M, const double* e, const double*
     } else {
       warm = false;  // the root may sit on either side of the midpoint
     }
-    if (warm) tau = fmin(fmax(lam_g - e[o], lo), hi);
   }
   if (warm && (j == 0 || j == M)) {
     o = (j == 0) ? 0 : M - 1;
@@ -162,11 +165,21 @@ __device__ int secular_root(int j, int j0, int M, const double* e, const double*
       lo = fmax(0.0, (lam_g - dlt) - e[M - 1]);
       hi = fmin((fmax(h, e[M - 1]) + vnorm) - e[M - 1], (lam_g + dlt) - e[M - 1]);
     }
-    tau = fmin(fmax(lam_g - e[o], lo), hi);
   }
   if (warm) {
-    // an empty interval (it cannot happen while the bound holds) falls back
-    if (!(lo <= hi)) warm = false;
+    // an empty interval (it cannot happen while the bound holds) falls back.
+    // The start lies strictly inside the bracket: one end may be the origin
+    // pole itself (tau = 0), where f is not defined, and a predicted start
+    // can overshoot onto it near an avoided crossing; the previous root, else
+    // the bracket's middle, replaces such a start.
+    if (!(lo < hi)) {
+      warm = false;
+    } else {
+      double t0 = lam_s - e[o];
+      if (!(t0 > lo && t0 < hi)) t0 = lam_g - e[o];
+      if (!(t0 > lo && t0 < hi)) t0 = 0.5 * (lo + hi);
+      tau = t0;
+    }
   }
   if (warm) {
   } else if (j == 0) {
@@ -202,6 +215,7 @@ __device__ int secular_root(int j, int j0, int M, const double* e, const double*
   for (int it = 0; it < max_it; ++it) {
     if (!have_f) secular_eval(j, j0, M, e, V2, eo, emh, tau, f, dl, dr, err);
     have_f = false;
+    dsum_out = dl + dr;
     if (f == 0.0 || fabs(f) <= err) {
       ok = 1;
       break;
@@ -261,17 +275,25 @@ __device__ int secular_root(int j, int j0, int M, const double* e, const double*
 // next solve from (keyed by the trajectory's home index).
 struct RootStore {
   double* tau;     // [n_pad] root relative to its origin pole
+  double* q0;      // [n_pad] impurity component of the root's eigenvector
   int32_t* org;    // [n_pad] origin pole
   double* geo;     // [4]: h, f, valid (1), unused
 };
 
 __device__ inline RootStore root_store(const ClassDev& c, int t) {
-  const size_t hm = (size_t)c.home[t];
-  return RootStore{c.root_tau + hm * c.md.n_pad, c.root_org + hm * c.md.n_pad, c.root_geo + 4 * hm};
+  const size_t hm = (size_t)c.home[t], np = c.md.n_pad;
+  return RootStore{c.root_tau + hm * 2 * np, c.root_tau + hm * 2 * np + np, c.root_org + hm * np,
+                   c.root_geo + 4 * hm};
 }
 
 // Solve the arrowhead problem of geometry x; fills lam, tau, org, q0 in LDS
 // (entries n..n_pad-1 of lam/q0 set to 0).  Returns model scalars.
+// The eigenvector of root lambda_j is proportional to (1, V_k / (lambda_j -
+// eps_k)), so its impurity component is q0_j = f'(lambda_j)^(-1/2), read off
+// the secular iteration's last evaluation; the pole-relative differences it
+// sums are the same ones the root was found from.  kLoewner also leaves the
+// Loewner couplings (the couplings for which the computed roots are exact,
+// which give the bath components of the eigenvectors) in L.Vh2.
 // rs (may be null): warm = start every root from the stored one of the last
 // solve, store = keep this solve's roots there.  By Weyl's inequality each
 // eigenvalue moves by at most ||H' - H||_2 <= |dh| + ||dV|| between the two
@@ -279,6 +301,7 @@ __device__ inline RootStore root_store(const ClassDev& c, int t) {
 // ||dV|| = |df| ||Vbar||); with that bound, doubled, every root gets a bracket
 // that contains it, and the safeguarded iteration converges in a couple of
 // steps instead of starting from the gap.
+template <bool kLoewner = false>
 __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict__ vbar,
                                    const double* x, EigLds& L, RootStore rs = RootStore{},
                                    bool warm = false, bool store = false) {
@@ -302,10 +325,17 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
   }
   const double vnorm = sqrt(L.red[0]);
   __syncthreads();
-  // warm start: the bound on how far every root moved since the stored solve
-  double dlt = -1.0;
+  // warm start: the bound on how far every root moved since the stored solve,
+  // and the first-order move of each (q_j^T (H' - H) q_j with the stored
+  // vectors: dh q0_j^2 + 2 q0_j^2 (lambda_j - h) df / f, since
+  // sum_k V_k Q_kj = (lambda_j - h) q0_j) as the starting point
+  double dlt = -1.0, dh0 = 0.0, dfr = 0.0, h0 = 0.0;
   if (rs.geo && warm && rs.geo[2] == 1.0) {
-    const double bound = fabs(ma.h - rs.geo[0]) + fabs(ma.f - rs.geo[1]) * (vnorm / ma.f);
+    h0 = rs.geo[0];
+    dh0 = ma.h - h0;
+    const double df = ma.f - rs.geo[1];
+    dfr = rs.geo[1] != 0.0 ? df / rs.geo[1] : 0.0;  // f = 0: no coupling, no move from V
+    const double bound = fabs(dh0) + fabs(df) * (vnorm / ma.f);
     dlt = 2.0 * bound + 64.0 * kEps * (fabs(ma.h) + vnorm + fabs(L.e[0]) + fabs(L.e[M - 1]));
   }
   for (int j = tid; j < n; j += kEigThreads) {
@@ -314,14 +344,23 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
     // the roots of a wave are the 64 consecutive indices from j0 (the block
     // has a whole number of waves and steps j by its size)
     const int j0 = __builtin_amdgcn_readfirstlane(j - (tid & 63));
-    const double lam_g = dlt >= 0.0 ? L.e[rs.org[j]] + rs.tau[j] : 0.0;
-    const int ok = secular_root(j, j0, M, L.e, L.V2, ma.h, vnorm, md.eig_iter, lam_g, dlt, tau, o);
+    double lam_g = 0.0, lam_s = 0.0;
+    if (dlt >= 0.0) {
+      lam_g = L.e[rs.org[j]] + rs.tau[j];
+      const double q2 = rs.q0[j] * rs.q0[j];
+      lam_s = lam_g + q2 * (dh0 + 2.0 * (lam_g - h0) * dfr);
+    }
+    double dsum = 0.0;
+    const int ok =
+        secular_root(j, j0, M, L.e, L.V2, ma.h, vnorm, md.eig_iter, lam_g, dlt, lam_s, tau, o, dsum);
     L.tau[j] = tau;
     L.org[j] = o;
     L.lam[j] = L.e[o] + tau;
+    L.q0[j] = 1.0 / sqrt(1.0 + dsum);
     if (!ok) atomicOr(&L.fail, 1);
     if (rs.geo && store) {
       rs.tau[j] = tau;
+      rs.q0[j] = L.q0[j];
       rs.org[j] = o;
     }
   }
@@ -336,6 +375,7 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
   // The factors are taken in the order of l; as in the secular sums, only the
   // 64 indices l inside the wave's own range [k0, k0 + 64) need the per-lane
   // choice between the two forms.
+  if constexpr (kLoewner) {
   for (int k = tid; k < M; k += kEigThreads) {
     const int k0 = __builtin_amdgcn_readfirstlane(k - (tid & 63));
     const int l1 = min(k0, M), l2 = min(k0 + 64, M);
@@ -356,21 +396,10 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
       prod *= ((L.e[L.org[l + 1]] - ek) + L.tau[l + 1]) * rcp_nr(L.e[l] - ek);
     L.Vh2[k] = prod;
   }
-  __syncthreads();
-  for (int j = tid; j < md.n_pad; j += kEigThreads) {
-    if (j < n) {
-      const double eo = L.e[L.org[j]], tj = L.tau[j];
-      double s = 1.0;
-      for (int k = 0; k < M; ++k) {
-        const double d = (L.e[k] - eo) - tj;
-        const double id = rcp_nr(d);
-        s += L.Vh2[k] * (id * id);
-      }
-      L.q0[j] = 1.0 / sqrt(s);
-    } else if (j >= md.n) {
-      L.q0[j] = 0.0;
-      L.lam[j] = 0.0;
-    }
+  }
+  for (int j = md.n + tid; j < md.n_pad; j += kEigThreads) {
+    L.q0[j] = 0.0;
+    L.lam[j] = 0.0;
   }
   __syncthreads();
   if (md.expand) {
@@ -763,7 +792,7 @@ __global__ __launch_bounds__(kEigThreads) void k_init_thermal(ClassDev c, double
   RootStore rs{};
   const bool store = c.root_tau && !c.path;
   if (store) rs = root_store(c, t);
-  const ModelAt ma = solve_arrowhead(md, c.vbar, L.nuc[1], L, rs, false, store);
+  const ModelAt ma = solve_arrowhead<true>(md, c.vbar, L.nuc[1], L, rs, false, store);
   int32_t* occ = c.occ + (size_t)t * N;
   __shared__ int chosen[kMaxStates];
   bool done = false;
