@@ -645,10 +645,11 @@ __global__ __launch_bounds__(kHopThreads) void k_hop(ClassDev c, double dt, uint
 // (FP64: a fixed 1e-8; mixed: the larger of 1e-3 and four times the defect
 // the last Loewdin step measured before correcting, i.e. the growth over one
 // Loewdin period; the mixed path without Loewdin steps never measures it and
-// runs without the filter), and by Cauchy-Schwarz
-//   |W[b][r]| = |C_U[b, :] S^-1 e_r| <= ||C_U[b, :]|| / sigma_min(S).
-// Hence the total hop probability of the step is bounded by
-//   sum_{r, b} g <= 2 dt sum_b ||C_U[b, :]|| sum_r |v D[b][s_r]| / sigma_min(S).
+// runs without the filter).  Row b of the ratios, W[b][:] = C_U[b, :] S^-1,
+// has norm ||W[b][:]|| <= ||C_U[b, :]|| / sigma_min(S), and g <= 2 dt
+// |v D[b][s_r]| |W[b][r]|, so by Cauchy-Schwarz over r the total hop
+// probability of the step is bounded by
+//   sum_{r, b} g <= 2 dt sum_b ||C_U[b, :]|| (sum_r |v D[b][s_r]|^2)^(1/2) / sigma_min(S).
 // When that bound does not exceed the step's uniform xi, no pair can be
 // selected and the step ends without a hop: the filter completes such
 // trajectories (counters, exit checks, observables) and the determinant-ratio
@@ -710,7 +711,7 @@ __device__ void filter_one(const ClassDev& c, int t, double dt_run, uint64_t see
     if (b < n && !L.occflag[b]) fro_part += s2;
   }
   __syncthreads();
-  // sum_b ||C_U[b]|| sum_r |v D[b][s_r]|
+  // sum_b ||C_U[b]|| (sum_r |v D[b][s_r]|^2)^(1/2)
   const double* geo = c.geo + (size_t)t * kGeoStride;
   const int nd = md.ndof;
   const double h = geo[GEO_H];
@@ -728,9 +729,12 @@ __device__ void filter_one(const ClassDev& c, int t, double dt_run, uint64_t see
       const int a = L.occ[r];
       const double gab = kDense ? (fabs(L.lam[a] - L.lam[b]) <= gtol ? 0.0 : Gd[(size_t)b * n_pad + a])
                                 : L.q0[b] * L.q0[a] * (dh + rho * ((L.lam[b] - h) + (L.lam[a] - h)));
-      if (gab != 0.0) s += fabs(v * gab / (L.lam[a] - L.lam[b]));
+      if (gab != 0.0) {
+        const double d = v * gab / (L.lam[a] - L.lam[b]);
+        s = fma(d, d, s);
+      }
     }
-    bnd_part += L.rn[b] * s;
+    bnd_part += L.rn[b] * sqrt(s);
   }
   L.red[tid] = fro_part;
   L.red2[tid] = bnd_part;

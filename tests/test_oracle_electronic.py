@@ -155,6 +155,41 @@ def test_ratio_formula_equals_bruteforce_determinants(seed):
         assert np.any(g > 0)
 
 
+@pytest.mark.parametrize("eps_rot", [0.05, 0.15, 0.3])
+def test_no_hop_bound_is_an_upper_bound_of_the_total(eps_rot):
+    """The bound that lets a step skip the ratios (Eq. hopping-estimate, with
+    Cauchy-Schwarz over the occupied orbitals):
+        sum g <= 2 dt sum_{b unocc} ||C[b, :]|| (sum_r |vD[b, s_r]|^2)^(1/2) / s_min,
+        s_min^2 = 1 - ||C_U||_F^2 <= sigma_min(S)^2,
+    checked against the oracle's determinant-ratio probabilities on orthonormal
+    orbitals rotated away from the occupied unit vectors (larger rotations,
+    larger C_U); the l2 form never exceeds the l1 form sum_r |vD|."""
+    m, X, lam, Q, Ds, _, v = _random_state(0)
+    rs = np.random.default_rng(7)
+    N, dt = 3, 10.0
+    checked = 0
+    for trial in range(20):
+        K = rs.normal(size=(m.n, m.n)) + 1j * rs.normal(size=(m.n, m.n))
+        U = expm(1j * eps_rot * (K + K.conj().T) / 2)
+        s = np.sort(rs.choice(m.n, N, replace=False))
+        C = U[:, s]
+        vD = el.vdot_D(Ds, v * (1.0 + 5.0 * trial))
+        g, _, _ = el.hop_probabilities(C, s, vD, dt)
+        unocc = np.setdiff1d(np.arange(m.n), s)
+        rn = np.linalg.norm(C[unocc, :], axis=1)
+        smin2 = 1.0 - np.sum(rn ** 2)
+        if smin2 <= 0.0:
+            continue
+        assert np.linalg.svd(C[s, :], compute_uv=False)[-1] ** 2 >= smin2 - 1e-12
+        l2 = np.sqrt(np.sum(vD[np.ix_(unocc, s)] ** 2, axis=1))
+        l1 = np.sum(np.abs(vD[np.ix_(unocc, s)]), axis=1)
+        bound = 2.0 * dt * np.sum(rn * l2) / np.sqrt(smin2)
+        assert np.sum(g) <= bound * (1 + 1e-12)
+        assert bound <= 2.0 * dt * np.sum(rn * l1) / np.sqrt(smin2) * (1 + 1e-15)
+        checked += 1
+    assert checked >= 5
+
+
 def test_ratio_formula_equals_literal_manybody_fd():
     """Same as above but with the many-body coupling <J|d/dx K> taken by
     finite differences of N-electron determinant overlaps, with no
