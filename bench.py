@@ -63,12 +63,13 @@ def traffic_from_profile(path_md, kernel_src):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1, keep_sample=0, **run_options):
+def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1, keep_sample=0, lowdin_every=100,
+              **run_options):
     import torch
     from paper_2212_00518_amd import from_config
 
-    ens = from_config(cfg, n_traj=T, precision=precision, lowdin_every=100, elec_substeps=substeps,
-                      **run_options)
+    ens = from_config(cfg, n_traj=T, precision=precision, lowdin_every=lowdin_every,
+                      elec_substeps=substeps, **run_options)
     ens.init_thermal(x0, v0)
     ens.run(warmup)
     ens.sync()
@@ -103,8 +104,8 @@ def time_path(cfg, precision, T, steps, warmup, x0, v0, substeps=1, keep_sample=
         frozen=int((status != 0).sum()),
         mean_dt=float(clock_time.sum()) / max(warmup + steps, 1) / T,
         lowdin_launches=tm["lowdin"][1],
-        lowdin_steps_in_window=sum(1 for k in range(warmup, warmup + steps) if (k + 1) % 100 == 0)
-        if precision == "mixed" else 0,
+        lowdin_steps_in_window=sum(1 for k in range(warmup, warmup + steps) if (k + 1) % lowdin_every == 0)
+        if precision == "mixed" and lowdin_every > 0 else 0,
         max_orthonormality_defect=defect,
         sample=sample,
     )
@@ -184,6 +185,81 @@ def error_vs_oracle(cfg, sample, precision, steps=20):
         out["max_abs_dC"] = max(out["max_abs_dC"],
                                 float(np.max(np.abs(unpack_C(Cf, t, n, N, n_max, N_max) - ref.C))))
     return out
+
+
+def _oracle_run_worker(args):
+    """One FP64 oracle trajectory from a sampled state (pool worker)."""
+    cfg_name, x, v, C, occ, steps, step0, t = args
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        from oracle import models, dynamics as dyn
+        from workloads import get_config
+        cfg = get_config(cfg_name)
+        m = models.from_config(cfg)
+        ref, ev, recs = dyn.run(m, dyn.State([x], [v], C, occ), cfg["dt"], steps, cfg["seed"], t,
+                                step0=step0, record_every=1)
+        return ([(e["step"], e["a"], e["b"], e["accepted"]) for e in ev],
+                min([e["margin"] / max(e["g_total"], 1e-300) for e in ev], default=1.0),
+                [r["Pd_wf"] for r in recs], dyn.hop_probs(m, ref, cfg["dt"]))
+
+
+def lowdin_sweep(a, periods=(25, 50, 100, 200, 400), n_sample=8, steps=800):
+    """Mixed path against the Loewdin period L: throughput of the full
+    workload (4096 trajectories, L in the timed window) and the error against
+    the FP64 oracle of n_sample steady-state trajectories run for `steps`
+    steps (at least two Loewdin steps for every L) from the same states: the
+    largest |dP_d^wf| over the steps, the largest hop-probability deviation at
+    the end (relative to the trajectory's largest), and the largest
+    orthonormality defect the Loewdin steps measured."""
+    import multiprocessing as mp
+    import numpy as np
+    from paper_2212_00518_amd import from_config, pack_states
+    from workloads import get_config
+    cfg = get_config("c2")
+    T = cfg["n_traj"]
+    N, n = cfg["n_elec"], cfg["bath"]["M"] + 1
+    x0, v0 = initial_sample(cfg, T, cfg["seed"])
+    pre = time_path(cfg, "mixed", T, 50, 1000, x0, v0, keep_sample=n_sample)
+    sample = pre["sample"]
+    print(f"# pre-roll done: step {sample['step']}, {len(sample['traj'])} sampled trajectories", flush=True)
+    os.environ["OMP_NUM_THREADS"] = "1"
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(min(16, n_sample)) as pool:
+        refs = pool.map(_oracle_run_worker,
+                        [("c2", x, v, C, occ, steps, sample["step"], t)
+                         for t, (x, v, C, occ) in enumerate(sample["states"])])
+    print(f"# oracle runs done ({n_sample} x {steps} steps)", flush=True)
+    rows = []
+    for L in periods:
+        tp = time_path(cfg, "mixed", T, max(100, 2 * L), 1000, x0, v0, lowdin_every=L)
+        ens = from_config(cfg, n_traj=n_sample, precision="mixed", lowdin_every=L, record_every=1)
+        ens.set_state(*pack_states(sample["states"], ens.n_max, ens.N_max))
+        ens.set_step(sample["step"])
+        obs = ens.run(steps, record=True)
+        g = ens.hop_probs()
+        evs, _ = ens.events()
+        defect = ens.defect_max()
+        ens.close()
+        d_pd = d_g = 0.0
+        compared = 0
+        for t, (ev_ref, rel_margin, pd_ref, g_ref) in enumerate(refs):
+            mine = [(e["step"], e["a"], e["b"], e["accepted"]) for e in evs if e["traj"] == t]
+            if rel_margin < 1e-4 or mine != ev_ref:
+                continue
+            compared += 1
+            d_pd = max(d_pd, float(np.max(np.abs(obs[:, t, 1] - np.asarray(pd_ref)))))
+            gt = g[t, : N * n].reshape(N, n)
+            d_g = max(d_g, float(np.max(np.abs(gt - g_ref)) / max(np.max(g_ref), 1e-300)))
+        row = dict(L=L, value=round(tp["value"], 1), ms_per_step=round(tp["ms_per_step"], 3),
+                   lowdin_ms_per_launch=tp["kernels_ms"].get("lowdin"),
+                   lowdin_steps_in_window=tp["lowdin_steps_in_window"],
+                   compared=compared, max_abs_dPd_wf=d_pd, max_rel_dg_end=d_g,
+                   max_orthonormality_defect=defect)
+        rows.append(row)
+        print(f"# L={L}: {row}", flush=True)
+    print(json.dumps(dict(metric="mixed path against the Loewdin period", config="c2",
+                          sample_trajectories=n_sample, steps=steps, from_step=sample["step"],
+                          sweep=rows)), flush=True)
 
 
 def mixed_vs_fp64(cfg, T=64, steps=500):
@@ -829,6 +905,8 @@ def main():
                     help="c3: per-trajectory step caps log-uniform in [200, 20000]")
     ap.add_argument("--peak-probe", action="store_true",
                     help="only time library FP32 / FP64 GEMMs (8192^3) for the achievable MFMA rate")
+    ap.add_argument("--lowdin-sweep", action="store_true",
+                    help="mixed path against the Loewdin period L (throughput and error against the oracle)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference dispatch for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -845,6 +923,9 @@ def main():
     torch.cuda.set_device(0)
     if a.peak_probe:
         peak_probe()
+        return
+    if a.lowdin_sweep:
+        lowdin_sweep(a)
         return
     if a.copy_calibration:
         x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
