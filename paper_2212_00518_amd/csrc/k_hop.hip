@@ -16,9 +16,12 @@
 // Re W enters g, so Y is accumulated as a real product over the 2N real and
 // imaginary parts.
 //
-// One 512-thread work-group per trajectory that the exact no-hop bound could
-// not settle, taken in order from a per-class queue filled by the bound
-// kernel.  Thread (ti, tj), tid =
+// Two kernels evaluate these ratios, one 512-thread work-group per
+// trajectory that the exact no-hop bound could not settle, taken in order
+// from a per-class queue filled by the bound kernel: for N <= kMmCols the
+// matrix-core kernel further below (panels of rows, rank-kPanel updates and
+// the product Y on the FP64 matrix instructions); for wider occupied sets the
+// register kernel described here.  Thread (ti, tj), tid =
 // ti + 16 tj, owns rows ti + 16 ri and columns tj + 32 cj of X and rows
 // ti + 16 rb (positions in the unoccupied list) and columns tj + 32 cj of Y in
 // registers (the slot counts are template parameters sized to the problem).
@@ -81,6 +84,212 @@ __device__ inline double2 orb(const ClassDev& c, size_t base, int n_pad, int j, 
 template <int kRS, int kRB>
 constexpr bool x_via_scratch() {
   return 4 * kRS * ((kRS + 1) / 2) + 2 * kRB * ((kRS + 1) / 2) > 170;
+}
+
+// Hop selection (Sec. II.B: one uniform per trajectory and step, pairs in
+// canonical order): the occupied row r from the cumulative row totals
+// L.rowsum, whose entry is the first total above the step's uniform.
+// Returns r (-1: no hop); sel_prev = cumulative total before row r,
+// sel_margin = smallest |cumulative - xi| seen, sel_total = sum of all rows.
+template <class LDS>
+__device__ __forceinline__ int hop_select(const ClassDev& c, int t, uint64_t seed, Counters* cnt, bool singular, int N,
+                          LDS& L, double& sel_prev_out, double& sel_margin_out, double& sel_total_out) {
+  const int tid = threadIdx.x;
+  const int64_t step = cnt->step;
+  __shared__ int sel_r;
+  __shared__ double sel_prev, sel_margin, sel_total;
+  if (tid == 0) {
+    sel_r = -1;
+    sel_margin = 1e300;
+    sel_total = 0.0;
+    if (!singular) {
+      const double xi = philox_uniform(seed, (uint32_t)c.gtraj[t], (uint64_t)step, 0u);
+      double cum = 0.0, margin = 1e300;
+      for (int r = 0; r < N; ++r) {
+        const double prev = cum;
+        cum = cum + L.rowsum[r];
+        margin = fmin(margin, fabs(cum - xi));
+        if (sel_r < 0 && cum > xi) {
+          sel_r = r;
+          sel_prev = prev;
+          break;
+        }
+      }
+      double tot = 0.0;
+      for (int r = 0; r < N; ++r) tot += L.rowsum[r];
+      sel_total = tot;
+      sel_margin = margin;
+      L.sc_xi = xi;
+    }
+  }
+  __syncthreads();
+  sel_prev_out = sel_prev;
+  sel_margin_out = sel_margin;
+  sel_total_out = sel_total;
+  const int r = sel_r;
+  __syncthreads();  // every thread has read the selection before it is reused
+  return r;
+}
+
+// The rest of the step once L.grow holds g of the selected row rsel by
+// unoccupied position: the target b from the cumulative sum continued within
+// the row, momentum rescaling along d = <b|d/dR a> (frustrated when the
+// kinetic energy along d is too small), the occupation update, the force of
+// the new occupations, the hop event, the step's status checks and the
+// observable record.
+template <bool kDense, class LDS>
+__device__ __forceinline__ void hop_apply(const ClassDev& c, int t, Counters* cnt, iesh_event* events, int record,
+                          int exit_enabled, double exit_x, int64_t max_steps, bool singular, int rsel,
+                          double sel_prev, double sel_margin, double sel_total, LDS& L) {
+  const int tid = threadIdx.x;
+  const ModelDev& md = c.md;
+  const int n = md.n, n_pad = md.n_pad, N = md.N, nU = n - N;
+  const int nd = md.ndof;
+  const double* geo = c.geo + (size_t)t * kGeoStride;
+  const double h = geo[GEO_H];
+  const double* Gd = kDense ? c.Gd + (size_t)t * n_pad * n_pad : nullptr;
+  const double gtol = kDense ? 1e-12 * fmax(fabs(L.lam[0]), fabs(L.lam[n - 1])) : 0.0;
+  auto coupling = [&](int b, int a) -> double {  // G[b][a]
+    if constexpr (kDense) return fabs(L.lam[a] - L.lam[b]) <= gtol ? 0.0 : Gd[(size_t)b * n_pad + a];
+    return 0.0;
+  };
+  const int64_t step = cnt->step;
+  if (tid == 0) {
+    double* vv = L.dofv;
+    for (int nu = 0; nu < nd; ++nu) vv[nu] = c.v[(size_t)t * nd + nu];
+    int32_t st = c.status[t];
+    if (singular) st |= IESH_TRAJ_SINGULAR_S;
+    int occ_changed = 0;
+    if (rsel >= 0) {
+      const double xi = L.sc_xi;
+      double acc = sel_prev, margin = sel_margin;
+      int bsel = -1;
+      for (int bi = 0; bi < nU; ++bi) {  // b ascending over the unoccupied states
+        const double g = L.grow[bi];
+        if (g == 0.0) continue;
+        acc = acc + g;
+        margin = fmin(margin, fabs(acc - xi));
+        if (acc > xi) {
+          bsel = L.uocc[bi];
+          break;
+        }
+      }
+      if (bsel < 0) {
+        for (int bi = nU - 1; bi >= 0; --bi)
+          if (L.grow[bi] > 0.0) {
+            bsel = L.uocc[bi];
+            break;
+          }
+        margin = 0.0;
+      }
+      const int a = L.occ[rsel];
+      // rescale along d_nu = <b|d/dR_nu a> (momentum change gamma d)
+      double* dv = L.dofd;
+      for (int nu = 0; nu < nd; ++nu) {
+        const double dhn = geo[GEO_DHV + nu], rhon = geo[GEO_RHOV + nu];
+        const double gba = kDense ? coupling(bsel, a)
+                                  : L.q0[bsel] * L.q0[a] * (dhn + rhon * ((L.lam[bsel] - h) + (L.lam[a] - h)));
+        dv[nu] = gba == 0.0 ? 0.0 : gba / (L.lam[a] - L.lam[bsel]);
+      }
+      const double dE = L.lam[bsel] - L.lam[a];
+      double A2 = dv[0] * dv[0] / (2.0 * md.mass_dof[0]);
+      double B1 = vv[0] * dv[0];
+      for (int nu = 1; nu < nd; ++nu) {
+        A2 += dv[nu] * dv[nu] / (2.0 * md.mass_dof[nu]);
+        B1 += vv[nu] * dv[nu];
+      }
+      const double disc = B1 * B1 - 4.0 * A2 * dE;
+      int accepted = 0;
+      if (A2 != 0.0 && disc >= 0.0) {
+        const double root = sqrt(disc);
+        const double q = B1 + (B1 >= 0.0 ? root : -root);
+        const double gamma = (q != 0.0) ? 2.0 * dE / q : 0.0;
+        for (int nu = 0; nu < nd; ++nu) vv[nu] = vv[nu] - gamma * dv[nu] / md.mass_dof[nu];
+        accepted = 1;
+        // occupation update, keep sorted
+        int* o = L.occ;
+        o[rsel] = bsel;
+        int r = rsel;
+        while (r > 0 && o[r - 1] > o[r]) {
+          const int tmp = o[r - 1];
+          o[r - 1] = o[r];
+          o[r] = tmp;
+          --r;
+        }
+        while (r < N - 1 && o[r + 1] < o[r]) {
+          const int tmp = o[r + 1];
+          o[r + 1] = o[r];
+          o[r] = tmp;
+          ++r;
+        }
+        occ_changed = 1;
+      }
+      const int64_t slot = atomicAdd((unsigned long long*)&cnt->n_events, 1ull);
+      if (slot < IESH_EVENT_CAP) {
+        iesh_event* ev = events + slot;
+        ev->step = step;
+        ev->traj = c.gtraj[t];
+        ev->a = a;
+        ev->b = bsel;
+        ev->accepted = accepted;
+        ev->margin = margin;
+        ev->g_total = sel_total;
+      }
+    }
+    // force refresh for the (possibly new) occupations
+    if (occ_changed) {
+      for (int nu = 0; nu < nd; ++nu) {
+        const double dhn = geo[GEO_DHV + nu], rhon = geo[GEO_RHOV + nu];
+        double s = 0.0;
+        for (int r = 0; r < N; ++r) {
+          const int a = L.occ[r];
+          s += kDense ? Gd[(size_t)a * n_pad + a] : L.q0[a] * L.q0[a] * (dhn + 2.0 * rhon * (L.lam[a] - h));
+        }
+        c.F[(size_t)t * nd + nu] = -geo[GEO_DU0V + nu] - s;
+        c.v[(size_t)t * nd + nu] = vv[nu];
+      }
+    }
+    const int64_t ns = c.nsteps[t] + 1;
+    c.nsteps[t] = ns;
+    const double x = c.x[(size_t)t * nd + c.exit_dof];
+    if (exit_enabled && x > exit_x) st |= IESH_TRAJ_EXITED;
+    if ((max_steps > 0 && ns >= max_steps) || (c.stepcap[t] > 0 && ns >= c.stepcap[t]))
+      st |= IESH_TRAJ_STEPCAP;
+    double ekin = 0.0;
+    for (int nu = 0; nu < nd; ++nu) {
+      if (!isfinite(vv[nu])) st |= IESH_TRAJ_NONFINITE;
+      ekin += 0.5 * md.mass_dof[nu] * vv[nu] * vv[nu];
+    }
+    c.status[t] = st;
+    if (c.clock) advance_clock(c, t, sel_total);
+    L.sc_occ_changed = occ_changed;
+    L.sc_ekin = ekin;
+  }
+  __syncthreads();
+  if (L.sc_occ_changed) {
+    for (int r = tid; r < N; r += blockDim.x) c.occ[(size_t)t * N + r] = L.occ[r];
+  }
+  if (record && tid == 0) {
+    const int64_t rel = step - cnt->run_step0 + 1;
+    if (cnt->record_every > 0 && rel % cnt->record_every == 0) {
+      const int64_t rec = rel / cnt->record_every - 1;
+      double pds = 0.0, elam = 0.0, pdw = 0.0;
+      for (int r = 0; r < N; ++r) {
+        const int a = L.occ[r];
+        pds += L.q0[a] * L.q0[a];
+        elam += L.lam[a];
+        pdw += L.zz[r];
+      }
+      const double ekin = L.sc_ekin;
+      const double epot = geo[GEO_U0] + elam;
+      double* o = c.obs + ((size_t)rec * c.n_traj + c.home[t]) * IESH_N_OBS;
+      o[IESH_OBS_PD_SURF] = pds;
+      o[IESH_OBS_PD_WF] = pdw;
+      o[IESH_OBS_EKIN] = ekin;
+      o[IESH_OBS_EPOT] = epot;
+      o[IESH_OBS_ETOT] = ekin + epot;
+    }
+  }
 }
 
 // Everything the step needs for trajectory t (all threads of the work-group).
@@ -421,35 +630,8 @@ __device__ void hop_one(const ClassDev& c, int t, double dt_run, uint64_t seed, 
   }
   __syncthreads();
 
-  const int64_t step = cnt->step;
-  __shared__ int sel_r;
-  __shared__ double sel_prev, sel_margin, sel_total;
-  if (tid == 0) {
-    sel_r = -1;
-    sel_margin = 1e300;
-    sel_total = 0.0;
-    if (!singular) {
-      const double xi = philox_uniform(seed, (uint32_t)c.gtraj[t], (uint64_t)step, 0u);
-      double cum = 0.0, margin = 1e300;
-      for (int r = 0; r < N; ++r) {
-        const double prev = cum;
-        cum = cum + L.rowsum[r];
-        margin = fmin(margin, fabs(cum - xi));
-        if (sel_r < 0 && cum > xi) {
-          sel_r = r;
-          sel_prev = prev;
-          break;
-        }
-      }
-      double tot = 0.0;
-      for (int r = 0; r < N; ++r) tot += L.rowsum[r];
-      sel_total = tot;
-      sel_margin = margin;
-      L.sc_xi = xi;
-    }
-  }
-  __syncthreads();
-  const int rsel = sel_r;
+  double sel_prev = 0.0, sel_margin = 0.0, sel_total = 0.0;
+  const int rsel = hop_select(c, t, seed, cnt, singular, N, L, sel_prev, sel_margin, sel_total);
   if (rsel >= 0) {
     const int csel = L.perm[rsel];
     if (tj == (csel & 31)) {
@@ -469,144 +651,509 @@ __device__ void hop_one(const ClassDev& c, int t, double dt_run, uint64_t seed, 
   }
   __syncthreads();
 
-  if (tid == 0) {
-    double* vv = L.dofv;
-    for (int nu = 0; nu < nd; ++nu) vv[nu] = c.v[(size_t)t * nd + nu];
-    int32_t st = c.status[t];
-    if (singular) st |= IESH_TRAJ_SINGULAR_S;
-    int occ_changed = 0;
-    if (rsel >= 0) {
-      const double xi = L.sc_xi;
-      double acc = sel_prev, margin = sel_margin;
-      int bsel = -1;
-      for (int bi = 0; bi < nU; ++bi) {  // b ascending over the unoccupied states
-        const double g = L.grow[bi];
-        if (g == 0.0) continue;
-        acc = acc + g;
-        margin = fmin(margin, fabs(acc - xi));
-        if (acc > xi) {
-          bsel = L.uocc[bi];
-          break;
-        }
+  hop_apply<kDense>(c, t, cnt, events, record, exit_enabled, exit_x, max_steps, singular, rsel,
+                    sel_prev, sel_margin, sel_total, L);
+}
+
+// ---------------------------------------------------------------------------
+// Ratio kernel on the matrix cores (N <= kMmCols).  The same in-place
+// Gauss-Jordan inversion with column pivoting, taken kPanel rows at a time.
+// For the rows R of a panel, elimination of those rows alone (their pivots
+// chosen one after another by the rule above) gives their final values
+// P = [A^-1 | -A^-1 B] in the layout of the in-place array, where A = X[R][Q]
+// and B = X[R][others] for the panel's pivot columns Q, and every other row
+// then becomes
+//     X[i][:] += X[i][Q] E,   E = P - I_Q  (I_Q: ones at (k, Q_k)),
+// a rank-kPanel complex update on the FP64 matrix instructions; the panel
+// rows take P.  The pivots come out as in the register kernel up to the
+// pivot keys' resolution (13 significant bits of |X|^2 here), so the two
+// kernels agree to rounding.  Wave 0 eliminates (lane l holds columns l and
+// l + 64 of the panel rows: no barrier inside a panel) while waves 1..7, which hold column
+// tiles 0..6 of X, apply the previous panel's update: the row tile of the
+// next panel first, then, beside the elimination of that panel, the others.
+// A panel costs three barriers.  X lives in the accumulator layout of the
+// 16x16x4 FP64 instruction (lane l, element e: row lk + 4 e, column lr of the
+// tile, with lr = l & 15, lk = l >> 4).  Element e of an accumulator tile is
+// also the B operand of k-block e of the product Y = C_U[:, perm] X, whose
+// A operand comes from LDS, 16 unoccupied states at a time (the next block
+// loaded while the current one is multiplied); g goes to the trajectory's g
+// buffer and the row totals are reduced inside the owning wave.
+constexpr int kMmThreads = 512;
+constexpr int kMmTiles = kMmThreads / 64 - 1;  // column tiles of X (waves 1..7)
+constexpr int kMmCols = 16 * kMmTiles;         // N limit of the matrix-core path
+constexpr int kPanel = 4;                      // rows per panel (a multiple of 4 dividing 16)
+static_assert(kPanel % 4 == 0 && 16 % kPanel == 0, "panel rows");
+static_assert(kMmCols <= 112, "panel columns: two per lane of the eliminating wave, 127 - j > 0 in the pivot keys");
+constexpr int kCuLoads = (16 * kMmCols + kMmThreads - 1) / kMmThreads;  // C_U elements per thread
+
+struct HopMmLds {
+  double2 pan[kPanel][kMmCols];        // rows of the next panel before their elimination
+  double2 ebuf[2][kPanel][kMmCols];    // E of a panel (by panel parity)
+  double2 gq[2][kMmCols][kPanel + 1];  // X[:, Q] of a panel before its update
+  double2 cu[2][16][kMmCols + 1];      // C[perm[q]][u_b] for 16 unoccupied states
+  int qk[2][kPanel];                   // pivot columns of a panel (-1: none)
+  double lam[kMaxStates];
+  double q0[kMaxStates];
+  double rowsum[kMaxElec];
+  double grow[kMaxStates];  // g of the selected row, by unoccupied position
+  double zz[kMaxElec];
+  int occflag[kMaxStates];
+  int uocc[kMaxStates];  // unoccupied states, ascending
+  int perm[kMaxElec];
+  int invperm[kMaxElec];
+  int occ[kMaxElec];
+  int singular;
+  int sc_occ_changed;
+  double sc_xi;
+  double sc_ekin;
+  double dofv[kMaxDof];
+  double dofd[kMaxDof];
+};
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4d mfma64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Value of lane `src` (wave-uniform) of a per-lane double.
+__device__ inline double lane_value(double v, int src) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)u, src);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// 1/d for a normal d > 0: the hardware estimate and two Newton steps
+// (each squares the relative error; the estimate is good to about 2^-23).
+__device__ inline double rcp_pos(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Maximum of a 32-bit key over the wave (wave-uniform result): within each
+// row of 16 lanes by two quad permutations and two row rotations (every lane
+// ends with its row's maximum), then across the four rows.
+template <int kCtrl>
+__device__ inline unsigned dpp_u32(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, 0xf, 0xf, false);
+}
+__device__ inline unsigned wave_max_u32(unsigned k) {
+  k = max(k, dpp_u32<0xB1>(k));   // quad_perm [1, 0, 3, 2]
+  k = max(k, dpp_u32<0x4E>(k));   // quad_perm [2, 3, 0, 1]
+  k = max(k, dpp_u32<0x124>(k));  // row_ror:4
+  k = max(k, dpp_u32<0x128>(k));  // row_ror:8
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)k, 0);
+  const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)k, 16);
+  const unsigned c2 = (unsigned)__builtin_amdgcn_readlane((int)k, 32);
+  const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)k, 48);
+  return max(max(a, b), max(c2, d));
+}
+
+// Elimination of the panel rows held in L.pan (rows < rows) among the
+// columns not yet used (bit s of `used`: column l + 64 s), final values
+// minus I_Q into L.ebuf[buf], pivots into L.qk[buf].  One wave; returns false
+// when no finite nonzero pivot is left (S singular).  Pivot: the largest
+// |X[i][j]|^2 to 13 significant bits (the high word of the double with its
+// low 7 bits replaced by 127 - j: the bit pattern of a non-negative double
+// orders like its value), ties to the smallest j; any pivot within a
+// relative 2^-13 of the largest is as stable.
+__device__ bool panel_eliminate(HopMmLds& L, int buf, int rows, int N, unsigned& used) {
+  const int l = threadIdx.x & 63;
+  double2 P[kPanel][2];
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) {
+    P[i][0] = L.pan[i][l];
+    P[i][1] = (l + 64 < kMmCols) ? L.pan[i][l + 64] : make_double2(0.0, 0.0);
+  }
+  bool ok = true;
+  int qk[kPanel];
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) {
+    qk[i] = -1;
+    if (i < rows && ok) {  // uniform
+      unsigned k = 0u;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int col = l + 64 * s;
+        const double m = P[i][s].x * P[i][s].x + P[i][s].y * P[i][s].y;
+        const unsigned kj = ((unsigned)(__double_as_longlong(m) >> 32) & ~0x7Fu) | (unsigned)(127 - col);
+        const bool cand = col < N && !((used >> s) & 1u) && m > 0.0 && m < INFINITY;
+        k = cand ? max(k, kj) : k;
       }
-      if (bsel < 0) {
-        for (int bi = nU - 1; bi >= 0; --bi)
-          if (L.grow[bi] > 0.0) {
-            bsel = L.uocc[bi];
-            break;
+      k = wave_max_u32(k);
+      if (k == 0u) {
+        ok = false;  // no finite nonzero candidate
+      } else {
+        const int pc = 127 - (int)(k & 0x7Fu);
+        const int owner = pc & 63, ps = pc >> 6;
+        if (l == owner) used |= 1u << ps;
+        const double2 pv = ps ? P[i][1] : P[i][0];
+        const double2 piv = make_double2(lane_value(pv.x, owner), lane_value(pv.y, owner));
+        const double mp = piv.x * piv.x + piv.y * piv.y;
+        const double inv_m = mp > 1e-290 ? rcp_pos(mp) : 1.0 / mp;  // uniform
+        const double2 pinv = make_double2(piv.x * inv_m, -piv.y * inv_m);
+        const double2 rv0 = P[i][0], rv1 = P[i][1];
+        P[i][0] = make_double2(0.0, 0.0);
+        P[i][1] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i2 = 0; i2 < kPanel; ++i2) {
+          if (i2 < rows) {  // uniform
+            double2 f;
+            if (i2 == i) {
+              f = pinv;
+            } else {
+              const double2 cv = ps ? P[i2][1] : P[i2][0];
+              f = cmul(make_double2(lane_value(cv.x, owner), lane_value(cv.y, owner)), pinv);
+            }
+            // X[i2][j] -= X[i][j] f for every column (the pivot column then
+            // takes f)
+            P[i2][0].x = fma(-rv0.x, f.x, P[i2][0].x);
+            P[i2][0].x = fma(rv0.y, f.y, P[i2][0].x);
+            P[i2][0].y = fma(-rv0.x, f.y, P[i2][0].y);
+            P[i2][0].y = fma(-rv0.y, f.x, P[i2][0].y);
+            P[i2][1].x = fma(-rv1.x, f.x, P[i2][1].x);
+            P[i2][1].x = fma(rv1.y, f.y, P[i2][1].x);
+            P[i2][1].y = fma(-rv1.x, f.y, P[i2][1].y);
+            P[i2][1].y = fma(-rv1.y, f.x, P[i2][1].y);
+            if (l == owner) {
+              if (ps)
+                P[i2][1] = f;
+              else
+                P[i2][0] = f;
+            }
           }
-        margin = 0.0;
-      }
-      const int a = L.occ[rsel];
-      // rescale along d_nu = <b|d/dR_nu a> (momentum change gamma d)
-      double* dv = L.dofd;
-      for (int nu = 0; nu < nd; ++nu) {
-        const double dhn = geo[GEO_DHV + nu], rhon = geo[GEO_RHOV + nu];
-        const double gba = kDense ? coupling(bsel, a)
-                                  : L.q0[bsel] * L.q0[a] * (dhn + rhon * ((L.lam[bsel] - h) + (L.lam[a] - h)));
-        dv[nu] = gba == 0.0 ? 0.0 : gba / (L.lam[a] - L.lam[bsel]);
-      }
-      const double dE = L.lam[bsel] - L.lam[a];
-      double A2 = dv[0] * dv[0] / (2.0 * md.mass_dof[0]);
-      double B1 = vv[0] * dv[0];
-      for (int nu = 1; nu < nd; ++nu) {
-        A2 += dv[nu] * dv[nu] / (2.0 * md.mass_dof[nu]);
-        B1 += vv[nu] * dv[nu];
-      }
-      const double disc = B1 * B1 - 4.0 * A2 * dE;
-      int accepted = 0;
-      if (A2 != 0.0 && disc >= 0.0) {
-        const double root = sqrt(disc);
-        const double q = B1 + (B1 >= 0.0 ? root : -root);
-        const double gamma = (q != 0.0) ? 2.0 * dE / q : 0.0;
-        for (int nu = 0; nu < nd; ++nu) vv[nu] = vv[nu] - gamma * dv[nu] / md.mass_dof[nu];
-        accepted = 1;
-        // occupation update, keep sorted
-        int* o = L.occ;
-        o[rsel] = bsel;
-        int r = rsel;
-        while (r > 0 && o[r - 1] > o[r]) {
-          const int tmp = o[r - 1];
-          o[r - 1] = o[r];
-          o[r] = tmp;
-          --r;
         }
-        while (r < N - 1 && o[r + 1] < o[r]) {
-          const int tmp = o[r + 1];
-          o[r + 1] = o[r];
-          o[r] = tmp;
-          ++r;
-        }
-        occ_changed = 1;
-      }
-      const int64_t slot = atomicAdd((unsigned long long*)&cnt->n_events, 1ull);
-      if (slot < IESH_EVENT_CAP) {
-        iesh_event* ev = events + slot;
-        ev->step = step;
-        ev->traj = c.gtraj[t];
-        ev->a = a;
-        ev->b = bsel;
-        ev->accepted = accepted;
-        ev->margin = margin;
-        ev->g_total = sel_total;
+        qk[i] = pc;
       }
     }
-    // force refresh for the (possibly new) occupations
-    if (occ_changed) {
-      for (int nu = 0; nu < nd; ++nu) {
-        const double dhn = geo[GEO_DHV + nu], rhon = geo[GEO_RHOV + nu];
-        double s = 0.0;
-        for (int r = 0; r < N; ++r) {
-          const int a = L.occ[r];
-          s += kDense ? Gd[(size_t)a * n_pad + a] : L.q0[a] * L.q0[a] * (dhn + 2.0 * rhon * (L.lam[a] - h));
-        }
-        c.F[(size_t)t * nd + nu] = -geo[GEO_DU0V + nu] - s;
-        c.v[(size_t)t * nd + nu] = vv[nu];
-      }
+  }
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) {
+    double2 e0v = P[i][0], e1v = P[i][1];
+    if (!ok || qk[i] < 0) {
+      e0v = make_double2(0.0, 0.0);
+      e1v = make_double2(0.0, 0.0);
+    } else {
+      if (qk[i] == l) e0v.x -= 1.0;
+      if (qk[i] == l + 64) e1v.x -= 1.0;
     }
-    const int64_t ns = c.nsteps[t] + 1;
-    c.nsteps[t] = ns;
-    const double x = c.x[(size_t)t * nd + c.exit_dof];
-    if (exit_enabled && x > exit_x) st |= IESH_TRAJ_EXITED;
-    if ((max_steps > 0 && ns >= max_steps) || (c.stepcap[t] > 0 && ns >= c.stepcap[t]))
-      st |= IESH_TRAJ_STEPCAP;
-    double ekin = 0.0;
-    for (int nu = 0; nu < nd; ++nu) {
-      if (!isfinite(vv[nu])) st |= IESH_TRAJ_NONFINITE;
-      ekin += 0.5 * md.mass_dof[nu] * vv[nu] * vv[nu];
-    }
-    c.status[t] = st;
-    if (c.clock) advance_clock(c, t, sel_total);
-    L.sc_occ_changed = occ_changed;
-    L.sc_ekin = ekin;
+    L.ebuf[buf][i][l] = e0v;
+    if (l + 64 < kMmCols) L.ebuf[buf][i][l + 64] = e1v;
+    if (l == 0) L.qk[buf][i] = ok ? qk[i] : -1;
+  }
+  return ok;
+}
+
+template <bool kF32, bool kDense>
+__device__ __forceinline__ void hop_one_mm(const ClassDev& c, int t, double dt_run, uint64_t seed,
+                                           Counters* cnt, iesh_event* events, int query_mode, int record,
+                                           int exit_enabled, double exit_x, int64_t max_steps, HopMmLds& L) {
+  const double dt = c.clock ? c.clock[2 * (size_t)t] : dt_run;  // this trajectory's step
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+  const ModelDev& md = c.md;
+  const int n = md.n, n_pad = md.n_pad, N = md.N, nU = n - N;
+  const int RT = (N + 15) >> 4;
+  const int ct = w - 1;                       // this wave's column tile of X
+  const bool owns = w >= 1 && ct < RT;        // uniform
+  const int col = 16 * ct + lr;               // this lane's column of X (owners)
+  if (!query_mode && (c.status[t] & kFreezeMask)) return;  // uniform
+  const size_t base = (size_t)t * N * n_pad;
+  if (!query_mode && tid == 0) atomicAdd((unsigned long long*)&cnt->hop_evals, 1ull);
+  __syncthreads();  // the previous trajectory of this work-group is done with L
+
+  for (int k = tid; k < n_pad; k += kMmThreads) {
+    L.lam[k] = c.lam[(size_t)t * n_pad + k];
+    L.q0[k] = c.q0[(size_t)t * n_pad + k];
+    L.occflag[k] = 0;
+  }
+  if (tid == 0) L.singular = 0;
+  __syncthreads();
+  for (int r = tid; r < N; r += kMmThreads) {
+    const int a = c.occ[(size_t)t * N + r];
+    L.occ[r] = a;
+    L.occflag[a] = 1;
   }
   __syncthreads();
-  if (L.sc_occ_changed) {
-    for (int r = tid; r < N; r += kHopThreads) c.occ[(size_t)t * N + r] = L.occ[r];
+  // unoccupied list: b sits at position b - #{occupied < b}
+  for (int b = tid; b < n; b += kMmThreads) {
+    if (L.occflag[b]) continue;
+    int lo = 0, hi = N;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (L.occ[mid] < b)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    L.uocc[b - lo] = b;
   }
-  if (record && tid == 0) {
-    const int64_t rel = step - cnt->run_step0 + 1;
-    if (cnt->record_every > 0 && rel % cnt->record_every == 0) {
-      const int64_t rec = rel / cnt->record_every - 1;
-      double pds = 0.0, elam = 0.0, pdw = 0.0;
-      for (int r = 0; r < N; ++r) {
-        const int a = L.occ[r];
-        pds += L.q0[a] * L.q0[a];
-        elam += L.lam[a];
-        pdw += L.zz[r];
+  // impurity amplitude of every orbital, sum_i q0_i C[i][j] (observable)
+  if (record && !query_mode) {
+    for (int j = w; j < N; j += kMmThreads / 64) {
+      double zr = 0.0, zi = 0.0;
+      for (int i = l; i < n_pad; i += 64) {
+        const double2 z = orb<kF32>(c, base, n_pad, j, i);
+        zr += L.q0[i] * z.x;
+        zi += L.q0[i] * z.y;
       }
-      const double ekin = L.sc_ekin;
-      const double epot = geo[GEO_U0] + elam;
-      double* o = c.obs + ((size_t)rec * c.n_traj + c.home[t]) * IESH_N_OBS;
-      o[IESH_OBS_PD_SURF] = pds;
-      o[IESH_OBS_PD_WF] = pdw;
-      o[IESH_OBS_EKIN] = ekin;
-      o[IESH_OBS_EPOT] = epot;
-      o[IESH_OBS_ETOT] = ekin + epot;
+      for (int m = 32; m > 0; m >>= 1) {
+        zr += __shfl_xor(zr, m);
+        zi += __shfl_xor(zi, m);
+      }
+      if (l == 0) L.zz[j] = zr * zr + zi * zi;
+    }
+  }
+  // columns of the panel rows that no wave holds stay zero
+  for (int e = tid; e < kPanel * kMmCols; e += kMmThreads) {
+    if (e % kMmCols >= 16 * RT) L.pan[e / kMmCols][e % kMmCols] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+
+  // ---- X = S = C[s, :]: xr/xi[it] is tile (it, ct)
+  // (every load in bounds and unconditional, so that they are all in flight
+  // at once; elements outside S are then set to zero)
+  v4d xr[kMmTiles], xi[kMmTiles];
+#pragma unroll
+  for (int it = 0; it < kMmTiles; ++it) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * it + lk + 4 * e;
+      const bool in = owns && row < N && col < N;
+      const double2 z = orb<kF32>(c, base, n_pad, in ? col : 0, L.occ[in ? row : 0]);
+      xr[it][e] = in ? z.x : 0.0;
+      xi[it][e] = in ? z.y : 0.0;
+    }
+  }
+
+  // update of tile it by panel pp (buffer pb), then the panel's own rows take P
+  auto update_tile = [&](v4d& tr, v4d& ti, int it, int pp) {
+    const int pb = pp & 1;
+#pragma unroll
+    for (int kb = 0; kb < kPanel / 4; ++kb) {
+      const double2 eb = L.ebuf[pb][4 * kb + lk][col];
+      const double2 ga = L.gq[pb][16 * it + lr][4 * kb + lk];
+      tr = mfma64(ga.x, eb.x, tr);
+      tr = mfma64(-ga.y, eb.y, tr);
+      ti = mfma64(ga.x, eb.y, ti);
+      ti = mfma64(ga.y, eb.x, ti);
+    }
+    if (it == (kPanel * pp) >> 4) {
+      // selects, not conditional stores: merged stores would index the
+      // register tile at run time
+      const int e0 = ((kPanel * pp) & 15) >> 2;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool in = e >= e0 && e < e0 + kPanel / 4;
+        const int i = in ? lk + 4 * (e - e0) : 0;
+        const double2 ev = L.ebuf[pb][i][col];
+        const double nx = ev.x + (L.qk[pb][i] == col ? 1.0 : 0.0);
+        tr[e] = in ? nx : tr[e];
+        ti[e] = in ? ev.y : ti[e];
+      }
+    }
+  };
+  // rows of panel pp (before elimination) to L.pan
+  auto panel_rows = [&](const v4d& tr, const v4d& ti, int pp) {
+    const int e0 = ((kPanel * pp) & 15) >> 2;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (e >= e0 && e < e0 + kPanel / 4) L.pan[lk + 4 * (e - e0)][col] = make_double2(tr[e], ti[e]);
+  };
+  // pivot columns of X for panel pp (buffer pb) to L.gq, before its update:
+  // the lanes whose column is a pivot write it, all pivots at once
+  auto gather_q = [&](int pp) {
+    const int pb = pp & 1;
+    int kk = -1;
+#pragma unroll
+    for (int k = 0; k < kPanel; ++k)
+      if (L.qk[pb][k] == col) kk = k;
+    if (owns && kk >= 0) {
+#pragma unroll
+      for (int it = 0; it < kMmTiles; ++it)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) L.gq[pb][16 * it + lk + 4 * e][kk] = make_double2(xr[it][e], xi[it][e]);
+    }
+#pragma unroll
+    for (int k = 0; k < kPanel; ++k) {
+      const int q = L.qk[pb][k];
+      if (q < 0) {
+        // no pivot (rows past N, or S singular): a zero column
+        for (int row = tid; row < kMmCols; row += kMmThreads) L.gq[pb][row][k] = make_double2(0.0, 0.0);
+      } else if (tid == 0) {
+        L.perm[kPanel * pp + k] = q;
+      }
+    }
+  };
+
+  // ---- panels
+  unsigned used = 0u;  // wave 0: bit s, column l + 64 s has been a pivot
+  const int n_panels = (N + kPanel - 1) / kPanel;
+  if (owns) panel_rows(xr[0], xi[0], 0);
+  __syncthreads();
+  if (w == 0 && !panel_eliminate(L, 0, min(kPanel, N), N, used) && l == 0) L.singular = 1;
+  __syncthreads();
+  gather_q(0);
+  __syncthreads();
+  for (int p = 0; p < n_panels; ++p) {
+    const bool next = p + 1 < n_panels;
+    const int itn = (kPanel * (p + 1)) >> 4;  // row tile of the next panel
+    // (a) the next panel's row tile first, and its rows to L.pan
+    if (owns && next) {
+#pragma unroll
+      for (int it = 0; it < kMmTiles; ++it) {
+        if (it == itn) {
+          update_tile(xr[it], xi[it], it, p);
+          panel_rows(xr[it], xi[it], p + 1);
+        }
+      }
+    }
+    __syncthreads();
+    // (b) wave 0 eliminates the next panel while the others finish the update
+    if (w == 0) {
+      if (next && !panel_eliminate(L, (p + 1) & 1, min(kPanel, N - kPanel * (p + 1)), N, used) && l == 0)
+        L.singular = 1;
+    } else if (owns) {
+#pragma unroll
+      for (int it = 0; it < kMmTiles; ++it)
+        if (it < RT && !(next && it == itn)) update_tile(xr[it], xi[it], it, p);
+    }
+    __syncthreads();
+    // (c) the next panel's pivot columns
+    if (next) gather_q(p + 1);
+    __syncthreads();
+  }
+  const bool singular = L.singular != 0;
+  if (!singular) {
+    for (int r = tid; r < N; r += kMmThreads) L.invperm[L.perm[r]] = r;
+  }
+  double* gout = c.gbuf + (size_t)t * N * n_pad;
+  if (query_mode) {
+    for (int e = tid; e < N * n_pad; e += kMmThreads) gout[e] = 0.0;
+  }
+  __syncthreads();
+
+  // ---- Y[b][c] = Re sum_q C[perm[q]][u_b] X[q][c], 16 unoccupied states at a
+  // time, and g of every (occupied, unoccupied) pair
+  const double* geo = c.geo + (size_t)t * kGeoStride;
+  const int nd = md.ndof;
+  const double h = geo[GEO_H];
+  const bool multi = nd > 1;
+  const double dh = multi ? geo[GEO_VDH] : geo[GEO_DH];
+  const double rho = multi ? geo[GEO_VRHO] : geo[GEO_RHO];
+  const double v = multi ? 1.0 : c.v[(size_t)t * nd];
+  const double* Gd = kDense ? c.Gd + (size_t)t * n_pad * n_pad : nullptr;
+  const double gtol = kDense ? 1e-12 * fmax(fabs(L.lam[0]), fabs(L.lam[n - 1])) : 0.0;
+  // element e = tid + kMmThreads j of a block: unoccupied position 16 bt + e % 16, column e / 16
+  auto load_cu = [&](int bt, double2* r) {
+#pragma unroll
+    for (int j = 0; j < kCuLoads; ++j) {
+      const int e = tid + kMmThreads * j;
+      const int bi = 16 * bt + (e & 15), q = e >> 4;
+      const bool in = e < 16 * kMmCols && q < N && bi < nU && !singular;
+      // (perm is complete only when S is not singular: index 0 otherwise)
+      const int orbital = in ? L.perm[q] : 0, state = in ? L.uocc[bi] : 0;
+      const double2 z = orb<kF32>(c, base, n_pad, orbital, state);
+      r[j] = in ? z : make_double2(0.0, 0.0);
+    }
+  };
+  auto store_cu = [&](int buf, const double2* r) {
+#pragma unroll
+    for (int j = 0; j < kCuLoads; ++j) {
+      const int e = tid + kMmThreads * j;
+      if (e < 16 * kMmCols) L.cu[buf][e & 15][e >> 4] = r[j];
+    }
+  };
+  double rsum = 0.0;
+  const int r_own = (owns && col < N && !singular) ? L.invperm[col] : 0;
+  const int a_own = L.occ[r_own];
+  const int BT = (nU + 15) >> 4;
+  double2 pre[kCuLoads];
+  load_cu(0, pre);
+  store_cu(0, pre);
+  __syncthreads();
+  for (int bt = 0; bt < BT; ++bt) {
+    const int cb = bt & 1;
+    if (bt + 1 < BT) load_cu(bt + 1, pre);
+    if (owns) {
+      v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int qt = 0; qt < kMmTiles; ++qt) {
+        if (qt < RT) {
+#pragma unroll
+          for (int kb = 0; kb < 4; ++kb) {
+            const double2 av = L.cu[cb][lr][16 * qt + 4 * kb + lk];
+            acc = mfma64(av.x, xr[qt][kb], acc);
+            acc = mfma64(-av.y, xi[qt][kb], acc);
+          }
+        }
+      }
+      if (col < N && !singular) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int bi = 16 * bt + lk + 4 * e;
+          if (bi < nU) {
+            const int bb = L.uocc[bi];
+            const double gab =
+                kDense ? (fabs(L.lam[a_own] - L.lam[bb]) <= gtol ? 0.0 : Gd[(size_t)bb * n_pad + a_own])
+                       : L.q0[bb] * L.q0[a_own] * (dh + rho * ((L.lam[bb] - h) + (L.lam[a_own] - h)));
+            // v <b|d/dx a> (the deflated cases as in the register kernel)
+            const double vD = v * gab / (L.lam[a_own] - L.lam[bb]);
+            const double g = fmax(-2.0 * dt * vD * acc[e], 0.0);
+            rsum += g;
+            gout[(size_t)r_own * n_pad + bb] = g;
+          }
+        }
+      }
+    }
+    if (bt + 1 < BT) store_cu(cb ^ 1, pre);
+    __syncthreads();
+  }
+  // row totals: the four lanes of a column hold its rows lk + 4 e
+  rsum += __shfl_xor(rsum, 16);
+  rsum += __shfl_xor(rsum, 32);
+  if (owns && lk == 0 && col < N && !singular) L.rowsum[r_own] = rsum;
+  __syncthreads();
+  if (query_mode) {
+    if (singular && tid == 0) c.status[t] |= IESH_TRAJ_SINGULAR_S;
+    return;
+  }
+  double sel_prev = 0.0, sel_margin = 0.0, sel_total = 0.0;
+  const int rsel = hop_select(c, t, seed, cnt, singular, N, L, sel_prev, sel_margin, sel_total);
+  if (rsel >= 0) {
+    for (int bi = tid; bi < nU; bi += kMmThreads) L.grow[bi] = gout[(size_t)rsel * n_pad + L.uocc[bi]];
+  }
+  __syncthreads();
+  hop_apply<kDense>(c, t, cnt, events, record, exit_enabled, exit_x, max_steps, singular, rsel,
+                    sel_prev, sel_margin, sel_total, L);
+}
+
+template <bool kF32, bool kDense>
+__global__ __launch_bounds__(kMmThreads) void k_hop_mm(ClassDev c, double dt, uint64_t seed, Counters* cnt,
+                                                       iesh_event* events, int query_mode, int t0,
+                                                       int record, int exit_enabled, double exit_x,
+                                                       int64_t max_steps) {
+  __shared__ HopMmLds L;
+  int32_t* q = c.hopq;
+  const int b = blockIdx.x;
+  const int n_items = query_mode ? 1 : q[0];
+  for (int e = query_mode ? 0 : b; e < n_items; e += gridDim.x) {
+    const int t = query_mode ? t0 + b : q[3 + e];
+    hop_one_mm<kF32, kDense>(c, t, dt, seed, cnt, events, query_mode, record, exit_enabled, exit_x,
+                             max_steps, L);
+  }
+  if (!query_mode && threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&q[2], 1) == (int)gridDim.x - 1) {
+      q[0] = 0;
+      q[2] = 0;
     }
   }
 }
-
 
 // Work-group b takes entries b, b + G, ... (G the grid) of the class queue
 // hopq = [count, unused, done, list...] that the bound kernel fills; the
@@ -906,7 +1453,18 @@ static const void* hop_fn_p(const ClassDev& c) {
   return hop_fn_rs<F32, 11>(c);
 }
 
+// The matrix-core kernel serves N <= kMmCols; wider occupied sets keep the
+// register kernel.
+static bool hop_mm(const ClassDev& c) { return c.md.N <= kMmCols; }
+
+static const void* hop_mm_fn(const ClassDev& c, int precision) {
+  const bool d = c.Gd != nullptr;
+  if (precision == IESH_FP64) return d ? (const void*)k_hop_mm<false, true> : (const void*)k_hop_mm<false, false>;
+  return d ? (const void*)k_hop_mm<true, true> : (const void*)k_hop_mm<true, false>;
+}
+
 static const void* hop_fn(const ClassDev& c, int precision) {
+  if (hop_mm(c)) return hop_mm_fn(c, precision);
   return precision == IESH_FP64 ? hop_fn_p<false>(c) : hop_fn_p<true>(c);
 }
 
@@ -957,17 +1515,19 @@ static void launch_hop_p(const ClassDev& c, dim3 grid, double dt, uint64_t seed,
 
 // Work-groups of the ratio kernel resident at once (one trajectory each).
 int hop_resident_groups(const ClassDev& c, int precision, int n_cu) {
-  // every instantiation has 512 threads and the same static LDS; registers
-  // differ by shape, so take the occupancy of the class's own kernel
+  // registers and LDS differ by kernel and shape, so take the occupancy of
+  // the class's own kernel
   int per_cu = 0;
   const void* fn = hop_fn(c, precision);
-  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kHopThreads, 0) != hipSuccess ||
+  const int threads = hop_mm(c) ? kMmThreads : kHopThreads;
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   return per_cu * n_cu;
 }
 
 bool hop_needs_scratch(const ClassDev& c) {
+  if (hop_mm(c)) return false;
   const int rs = (c.md.N + 15) / 16, rb = (c.md.n - c.md.N + 15) / 16;
   const int RS = rs <= 2 ? 2 : rs <= 4 ? 4 : rs <= 7 ? 7 : rs <= 10 ? 10 : 11;
   const int RB = rb <= 2 ? 2 : rb <= 4 ? 4 : rb <= 7 ? 7 : rb <= 11 ? 11 : rb <= 14 ? 14 : 21;
@@ -983,6 +1543,25 @@ hipError_t launch_hop(const ClassDev& c, double dt, uint64_t seed, Counters* cnt
   const int full = c.hop_groups > 0 && c.hop_groups < c.n_live ? c.hop_groups : c.n_live;
   const dim3 grid(query_mode ? nt : full);
   const int t0e = query_mode ? t0 : 0;
+  if (hop_mm(c)) {
+    const bool d = c.Gd != nullptr;
+#define IESH_MM(F32, DENSE)                                                                        \
+  hipLaunchKernelGGL((k_hop_mm<F32, DENSE>), grid, dim3(kMmThreads), 0, s, c, dt, seed, cnt, events, \
+                     query_mode, t0e, record, exit_enabled, exit_x, max_steps)
+    if (precision == IESH_FP64) {
+      if (d)
+        IESH_MM(false, true);
+      else
+        IESH_MM(false, false);
+    } else {
+      if (d)
+        IESH_MM(true, true);
+      else
+        IESH_MM(true, false);
+    }
+#undef IESH_MM
+    return hipGetLastError();
+  }
   if (precision == IESH_FP64)
     launch_hop_p<false>(c, grid, dt, seed, cnt, events, query_mode, t0e, record, exit_enabled,
                         exit_x, max_steps, s);
