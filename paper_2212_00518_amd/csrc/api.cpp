@@ -932,6 +932,7 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
         (rc = dalloc(ctx, &c.geo, (size_t)T * kGeoStride)) ||
         (rc = dalloc(ctx, &c.cheb, (size_t)T * kChebStride)) ||
         (rc = dalloc(ctx, &c.gbuf, (size_t)T * N * n_pad)) ||
+        (rc = dalloc(ctx, &c.rown, (size_t)T * ((N + 7) / 8) * n_pad)) ||
         (rc = dalloc(ctx, &c.clock, (size_t)2 * T)) ||
         (rc = dalloc(ctx, &c.hopq, (size_t)3 + T)) || (rc = dalloc(ctx, &c.live, 1)) ||
         (rc = dalloc(ctx, &c.work, 2)))

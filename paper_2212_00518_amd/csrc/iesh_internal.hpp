@@ -86,6 +86,10 @@ struct ClassDev {
   int traj_offset;      // first global trajectory index of this class
   int nct_max;          // column tiles per propagation work-group
   int n_slabs;          // propagation work-groups per trajectory
+  // [T][ceil(N / 8)][n_pad]: for propagation slab s of trajectory t, the
+  // squared norms over the slab's orbitals of every row of C after the last
+  // propagation (sum_j |C[i][j]|^2), read by the no-hop bound
+  double* rown = nullptr;
   int hop_groups = 0;   // work-groups of a persistent ratio-kernel launch (0: one per slot)
   int exit_dof = 0;     // coordinate compared with the exit distance
   int exact_hops = 0;   // 1: determinant ratios at every step (no-hop bound unused)

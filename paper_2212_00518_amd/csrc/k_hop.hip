@@ -1236,23 +1236,30 @@ __device__ void filter_one(const ClassDev& c, int t, double dt_run, uint64_t see
     L.occflag[a] = 1;
   }
   __syncthreads();
-  // row norms of C (state b over all orbitals); ||C_U||_F^2 over unoccupied b
+  // row norms of C (state b over all orbitals); ||C_U||_F^2 over unoccupied b.
+  // The propagation leaves the squared norms per slab of orbitals (c.rown);
+  // without them the orbitals are read here.
   const size_t base = (size_t)t * N * n_pad;
   double fro_part = 0.0;
+  const int slabs_max = (N + 7) >> 3;
   for (int b = tid; b < n_pad; b += kFltThreads) {
     double s2 = 0.0;
-    for (int j = 0; j < N; ++j) {
-      double re, im;
-      if (kF32) {
-        const float2 z = reinterpret_cast<const float2*>(c.C32)[base + (size_t)j * n_pad + b];
-        re = z.x;
-        im = z.y;
-      } else {
-        const double2 z = reinterpret_cast<const double2*>(c.C64)[base + (size_t)j * n_pad + b];
-        re = z.x;
-        im = z.y;
+    if (c.rown) {
+      for (int sl = 0; sl < c.n_slabs; ++sl) s2 += c.rown[((size_t)t * slabs_max + sl) * n_pad + b];
+    } else {
+      for (int j = 0; j < N; ++j) {
+        double re, im;
+        if (kF32) {
+          const float2 z = reinterpret_cast<const float2*>(c.C32)[base + (size_t)j * n_pad + b];
+          re = z.x;
+          im = z.y;
+        } else {
+          const double2 z = reinterpret_cast<const double2*>(c.C64)[base + (size_t)j * n_pad + b];
+          re = z.x;
+          im = z.y;
+        }
+        s2 += re * re + im * im;
       }
-      s2 += re * re + im * im;
     }
     L.rn[b] = sqrt(s2);
     if (b < n && !L.occflag[b]) fro_part += s2;

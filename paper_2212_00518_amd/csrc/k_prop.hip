@@ -381,6 +381,21 @@ __device__ void prop_item(const ClassDev& c, T* taps, int tap_k, int b, unsigned
       Cg[((size_t)o * s.n_pad + i) * 2 + 1] = s.X0[i * s.ldx + col + 8];
     }
   }
+  // squared row norms over the slab's orbitals (of the stored values, summed
+  // in FP64 in orbital order), so that the no-hop bound need not read C again
+  if (kMode == kPropagate && c.rown) {
+    double* rn = c.rown + ((size_t)t * ((s.N + 7) >> 3) + slab) * s.n_pad;
+    for (int i = tid; i < s.n_pad; i += kPropThreads) {
+      double acc = 0.0;
+      for (int ol = 0; ol < n_orb && s.tile0 * 8 + ol < s.N; ++ol) {
+        const int col = (ol >> 3) * 16 + (ol & 7);
+        const double re = (double)s.X0[i * s.ldx + col], im = (double)s.X0[i * s.ldx + col + 8];
+        acc = fma(re, re, acc);
+        acc = fma(im, im, acc);
+      }
+      rn[i] = acc;
+    }
+  }
 }
 
 // One work-group per (trajectory, slab) item; items of slots past the live
