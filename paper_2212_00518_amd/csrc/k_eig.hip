@@ -31,6 +31,9 @@ namespace {
 
 constexpr int kEigThreads = 256;
 static_assert(kEigThreads % 64 == 0, "whole waves: the secular solve relies on it");
+// Register budget of the step kernels: 5 waves per SIMD (at most 96 VGPRs)
+// fit without spills; the LDS of a work-group would allow 7.
+constexpr int kEigWavesPerSimd = 5;
 constexpr double kEps = 2.220446049250313e-16;
 
 struct EigLds {
@@ -53,8 +56,7 @@ struct EigLds {
 // 1/d from the hardware reciprocal estimate and two Newton steps
 // r <- r + r (1 - d r) (each squares the relative error).  Measured on gfx950
 // over 4M values spanning 1e-9 .. 5e8: the estimate is within 4.7e-8, one
-// step within 2.2e-15, two steps within 1.2e-16 (one unit in the last place);
-// one step would be too coarse for the secular function near its roots.
+// step within 2.2e-15, two steps within 1.2e-16 (one unit in the last place).
 // d != 0 at every call (poles are excluded from the root brackets, the
 // secular poles are distinct and the roots interlace them strictly).
 __device__ inline double rcp_nr(double d) {
@@ -65,50 +67,60 @@ __device__ inline double rcp_nr(double d) {
   return fma(r, e, r);
 }
 
+// The same with one Newton step (within 2.2e-15): the secular sums.
+__device__ inline double rcp_nr1(double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
 // f and its split derivative at tau (origin eo); terms with k < j are left
 // of the root.  j0 is the same for all lanes of the wave and no lane's j lies
 // outside [j0, j0 + 64), so poles below j0 are left of every lane's root and
 // poles from j0 + 64 on right of it: only the 64 poles between need the
-// per-lane split.  The terms are summed in the same order either way.
+// per-lane split.  Every point evaluated lies inside the root's gap, so a
+// left term V_k^2 / (eps_k - lambda) is negative and a right one positive,
+// and the sum of their moduli (for the rounding bound err) is the right sum
+// minus the left sum outside the per-lane range.  Each term carries the
+// one-step reciprocal's 2.2e-15, so f is known to about 3e-15 of that sum;
+// err = 16 eps of it.  A root accurate to that is accurate to about 3e-15
+// relative to its distance from the nearest pole.
 __device__ inline void secular_eval(int j, int j0, int M, const double* e, const double* V2,
                                     double eo, double emh, double tau, double& f, double& dl,
                                     double& dr, double& err) {
-  double psi = 0.0, l = 0.0, r = 0.0, abssum = 0.0;
+  double pl = 0.0, pm = 0.0, pr = 0.0, am = 0.0, l = 0.0, r = 0.0;
   const int k1 = min(j0, M), k2 = min(j0 + 64, M);
 #pragma unroll 4
   for (int k = 0; k < k1; ++k) {
-    const double d = (e[k] - eo) - tau;  // eps_k - lambda
-    const double inv = rcp_nr(d);
+    const double d = (e[k] - eo) - tau;  // eps_k - lambda < 0
+    const double inv = rcp_nr1(d);
     const double t = V2[k] * inv;
-    psi += t;
-    abssum += fabs(t);
-    l += t * inv;
+    pl += t;
+    l = fma(t, inv, l);
   }
 #pragma unroll 2
   for (int k = k1; k < k2; ++k) {
     const double d = (e[k] - eo) - tau;
-    const double inv = rcp_nr(d);
+    const double inv = rcp_nr1(d);
     const double t = V2[k] * inv;
-    psi += t;
-    abssum += fabs(t);
+    pm += t;
+    am += fabs(t);
     if (k < j)
-      l += t * inv;
+      l = fma(t, inv, l);
     else
-      r += t * inv;
+      r = fma(t, inv, r);
   }
 #pragma unroll 4
   for (int k = k2; k < M; ++k) {
-    const double d = (e[k] - eo) - tau;
-    const double inv = rcp_nr(d);
+    const double d = (e[k] - eo) - tau;  // eps_k - lambda > 0
+    const double inv = rcp_nr1(d);
     const double t = V2[k] * inv;
-    psi += t;
-    abssum += fabs(t);
-    r += t * inv;
+    pr += t;
+    r = fma(t, inv, r);
   }
-  f = emh + tau + psi;
+  f = emh + tau + ((pl + pm) + pr);
   dl = l;
   dr = r;
-  err = 4.0 * kEps * (fabs(emh) + fabs(tau) + abssum);
+  err = 16.0 * kEps * (fabs(emh) + fabs(tau) + ((pr - pl) + am));
 }
 
 // Root of a2 eta^2 + a1 eta + a0 inside (alpha, beta).
@@ -126,15 +138,25 @@ __device__ inline double quad_root_in(double a2, double a1, double a0, double al
   return fabs(r1) < fabs(r2) ? r1 : r2;
 }
 
+// A step of the iteration shorter than this, relative to the new point, ends
+// it without evaluating f there: near the root the error falls quadratically
+// (the next error is about the step squared over the distance to the nearest
+// pole, far below rounding), and f' at the accepted point differs from f' at
+// the last evaluated one by about twice the step over that distance.
+constexpr double kStepAccept = 1e-13;
+
 // Root j (0..M) of the secular function; j0 as in secular_eval.  Returns 1
 // on convergence.  Warm start (dlt >= 0): the root is known to lie within dlt
-// of lam_g (the same root of a nearby geometry, see solve_arrowhead); when
-// that interval lies on one side of the gap's midpoint, the origin pole is
-// the near one without evaluating f there, the bracket shrinks to the
-// interval and the iteration starts at the predicted root lam_s when that
-// lies strictly inside it.  dsum_out: sum_k V_k^2 / (eps_k - lambda)^2 at the
-// last point evaluated (within two units in the last place of the returned
-// root, so f' there is f' at the root to rounding).
+// of lam_g (the same root of a nearby geometry, see solve_arrowhead); the
+// bracket shrinks to that interval (intersected with the root's gap) and the
+// iteration starts at the predicted root lam_s when that lies strictly inside
+// it.  The origin pole is the near one when the interval lies on one side of
+// the gap's midpoint, else the one on the predicted root's side: the root is
+// then within dlt of the midpoint, about half a gap from either pole, and
+// both origins give the differences eps_k - lambda to full relative accuracy.
+// dsum_out: sum_k V_k^2 / (eps_k - lambda)^2 at the last point evaluated
+// (within a relative 2 kStepAccept of the returned root, so f' there is f' at
+// the root to about 1e-13).
 __device__ int secular_root(int j, int j0, int M, const double* e, const double* V2, double h,
                             double vnorm, int max_it, double lam_g, double dlt, double lam_s,
                             double& tau_out, int& org_out, double& dsum_out) {
@@ -152,8 +174,17 @@ __device__ int secular_root(int j, int j0, int M, const double* e, const double*
       o = j;
       lo = fmax(-0.5 * (e[j] - e[j - 1]) * (1.0 + 4.0 * kEps), (lam_g - dlt) - e[o]);
       hi = fmin(0.0, (lam_g + dlt) - e[o]);
+    } else if (lam_s < mid) {
+      // the root may sit on either side of the midpoint; the gap's far pole
+      // stays outside the bracket (the rounded pole difference is within half
+      // a unit of the exact one)
+      o = j - 1;
+      lo = fmax(0.0, (lam_g - dlt) - e[o]);
+      hi = fmin((e[j] - e[o]) * (1.0 - 4.0 * kEps), (lam_g + dlt) - e[o]);
     } else {
-      warm = false;  // the root may sit on either side of the midpoint
+      o = j;
+      lo = fmax((e[j - 1] - e[o]) * (1.0 - 4.0 * kEps), (lam_g - dlt) - e[o]);
+      hi = fmin(0.0, (lam_g + dlt) - e[o]);
     }
   }
   if (warm && (j == 0 || j == M)) {
@@ -257,7 +288,7 @@ __device__ int secular_root(int j, int j0, int M, const double* e, const double*
     }
     double tn = tau + eta;
     if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-    if (fabs(tn - tau) <= 2.0 * kEps * fabs(tn) ||
+    if (fabs(tn - tau) <= kStepAccept * fabs(tn) ||
         hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi))) {
       tau = tn;
       ok = 1;
@@ -680,7 +711,7 @@ __device__ void eig_step_one(const ClassDev& c, int t, double dt_run, int precis
   }
 }
 
-__global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt_run, int precision,
+__global__ __launch_bounds__(kEigThreads) __attribute__((amdgpu_waves_per_eu(kEigWavesPerSimd))) void k_eig_step(ClassDev c, double dt_run, int precision,
                                                            Counters* cnt, int sub, int nsub) {
   __shared__ EigLds L;
   eig_step_one(c, blockIdx.x, dt_run, precision, cnt, sub, nsub, L);
@@ -690,7 +721,7 @@ __global__ __launch_bounds__(kEigThreads) void k_eig_step(ClassDev c, double dt_
 // on slot b - first[k] of class k (first[k] <= b < first[k + 1]).  The classes
 // come largest first, so the dispatcher hands out the long work-groups
 // first and the small classes fill the compute units behind them.
-__global__ __launch_bounds__(kEigThreads) void k_eig_fused(ClassSet set, double dt_run, int precision,
+__global__ __launch_bounds__(kEigThreads) __attribute__((amdgpu_waves_per_eu(kEigWavesPerSimd))) void k_eig_fused(ClassSet set, double dt_run, int precision,
                                                             Counters* cnt, int sub, int nsub) {
   __shared__ EigLds L;
   const int b = blockIdx.x;
