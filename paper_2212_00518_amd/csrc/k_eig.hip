@@ -43,6 +43,7 @@ struct EigLds {
   double Vh2[kMaxStates];    // Loewner couplings squared
   double q0[kMaxStates];     // impurity amplitudes
   double lam[kMaxStates];    // eigenvalues (eps_o + tau)
+  double eo[kMaxStates];     // origin pole energy eps_o of each state (coupling build)
   double red[kEigThreads];   // reductions
   double red2[kEigThreads];
   int org[kMaxStates];       // origin pole index of each root
@@ -477,13 +478,6 @@ __device__ inline double lam_diff(const EigLds& L, int k, int j) {
   return (L.e[L.org[k]] - L.e[L.org[j]]) + (L.tau[k] - L.tau[j]);
 }
 
-// v * D[j][k] for j != k < n (zero when either state has no impurity part:
-// deflated states of equal bath energies, possibly degenerate with each other).
-__device__ inline double vD_elem(const EigLds& L, const ModelAt& ma, double v, int j, int k) {
-  const double g = L.q0[j] * L.q0[k] * (ma.dh + ma.rho * ((L.lam[j] - ma.h) + (L.lam[k] - ma.h)));
-  return g == 0.0 ? 0.0 : v * g * rcp_nr(lam_diff(L, k, j));
-}
-
 __device__ void write_model_geo(double* geo, const ModelAt& ma) {
   geo[GEO_H] = ma.h;
   geo[GEO_DH] = ma.dh;
@@ -634,18 +628,36 @@ __device__ void eig_step_one(const ClassDev& c, int t, double dt_run, int precis
   double* Bt = c.Bt + (size_t)t * n_pad * n_pad;
   float* Bt32 = c.Bt32 ? c.Bt32 + (size_t)t * n_pad * n_pad : nullptr;
   double lo_part = 1e300, hi_part = -1e300;
+  for (int k = tid; k < n; k += kEigThreads) L.eo[k] = L.e[L.org[k]];
+  __syncthreads();
   for (int j = tid; j < n_pad; j += kEigThreads) {
-    const int rt = j >> 4, lane_lo = j & 15;
+    const int lane_off = ((j >> 4) << 6) + (j & 15);
+    // v D[j][k] = q0_k (a_j + b_j (lambda_k - h)) / (lambda_k - lambda_j) with
+    // a_j = v q0_j (h' + rho (lambda_j - h)) and b_j = v q0_j rho, since
+    // G_jk = q0_j q0_k (h' + rho (lambda_j + lambda_k - 2h)); q0 = 0 on the
+    // padding rows.  Zero where the numerator vanishes: deflated states (no
+    // impurity part), possibly degenerate with each other.
+    const double q0j = L.q0[j];
+    const double aj = vfac * q0j * (mm.dh + mm.rho * (L.lam[j] - mm.h));
+    const double bj = vfac * q0j * mm.rho;
+    const double eoj = (j < n) ? L.eo[j] : 0.0, tj = (j < n) ? L.tau[j] : 0.0;
     double rsum = 0.0;
     for (int k = 0; k < n_pad; ++k) {
       double val = 0.0;
-      if (j < n && k < n && j != k) val = vD_elem(L, mm, vfac, j, k);
+      if (k < n) {
+        const double num = L.q0[k] * fma(bj, L.lam[k] - mm.h, aj);
+        const double dif = (L.eo[k] - eoj) + (L.tau[k] - tj);  // lambda_k - lambda_j
+        val = (num == 0.0 || k == j) ? 0.0 : num * rcp_nr1(dif);
+      }
       rsum += fabs(val);
-      const size_t off = ((size_t)((k >> 2) * RT + rt) << 6) + lane_lo + ((k & 3) << 4);
+      // element (j, k) of the tile-ordered matrix: the part set by k is the
+      // same for every lane, so the stores take a uniform base and a fixed
+      // per-lane offset (n_pad^2 < 2^31)
+      const int koff = (((k >> 2) * RT) << 6) + ((k & 3) << 4);
       if (precision == IESH_FP64)
-        Bt[off] = val;
+        (Bt + koff)[lane_off] = val;
       else
-        Bt32[off] = (float)val;
+        (Bt32 + koff)[lane_off] = (float)val;
     }
     if (j < n) {
       lo_part = fmin(lo_part, L.lam[j] - rsum);
