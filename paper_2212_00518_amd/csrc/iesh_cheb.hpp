@@ -67,7 +67,9 @@ __device__ inline int write_cheb(double* cb, double lo, double hi, double dte, i
   const double cc = 0.5 * (lo + hi);
   const double rr = fmax(0.5 * (hi - lo), 1e-300);
   const double rho = rr * dte;
-  const int K = cheb_terms(rho, precision == IESH_FP64 ? 2e-16 : 1e-8);
+  // truncation: the tail bound stays under about two units of FP64 rounding,
+  // or a quarter of one unit of FP32 rounding (2^-26) for the FP32 series
+  const int K = cheb_terms(rho, precision == IESH_FP64 ? 2e-16 : 0x1p-26);
   if (K < 0) return -1;
   bessel_j(K, rho, J);
   double sn, cs;
