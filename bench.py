@@ -979,7 +979,10 @@ def main():
     traffic = traffic_from_profile(os.path.join(ROOT, "profiles", f"k_prop_{head}_{a.config}_traffic.md"), src)
     achieved = r["prop_tflops"]
     line = {
-        "metric": "trajectory-steps/s (M=200,N=100) mixed vs FP64 at stated error; adjoint ms/step",
+        # the headline metric on the headline workload; any other workload run
+        # through this path names itself
+        "metric": ("trajectory-steps/s (M=200,N=100) mixed vs FP64 at stated error; adjoint ms/step"
+                   if a.config == "c2" else f"trajectory-steps/s ({cfg['name']})"),
         "value": round(r["value"], 2),
         "unit": "trajectory-steps/s",
         "n_gpus": 1,
