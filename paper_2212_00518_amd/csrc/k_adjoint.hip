@@ -107,11 +107,14 @@ inline size_t hop_adj_lds(int N) {
   return b <= kHopAdjLdsMax ? b : 0;
 }
 
+// kLds: the inverse lives in LDS, known at compile time so that its accesses
+// are LDS instructions (a pointer that may point either way compiles to flat
+// accesses, which take the memory path even for LDS).
+template <bool kLds>
 __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const double* Cs, double* Gh,
                                                             double* scr, const double* weights,
                                                             double* loss, double* hopbar, int s,
-                                                            int T, double dt, double cG, int reverse,
-                                                            int in_lds) {
+                                                            int T, double dt, double cG, int reverse) {
   __shared__ int mark[kMaxStates];
   __shared__ int uidx[kMaxStates];
   __shared__ double2 fcol[kMaxElec];
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(kHopAdjThreads) void k_adj_hop(ClassDev c, const do
   const double hp = -c.md.mass * omega * omega * gg;
   double* base = scr + (size_t)t * hop_adj_scratch(n_pad, N);
   // X: [N][N] (S in, S^-1 out), in LDS when the launch gave it room
-  double2* Mg = in_lds ? hop_smem : reinterpret_cast<double2*>(base);
+  double2* Mg = kLds ? hop_smem : reinterpret_cast<double2*>(base);
   double2* Wg = reinterpret_cast<double2*>(base + 2 * N * N);  // [nU][N]
   double2* Gu = Wg + (size_t)n_pad * N;                        // [nU][N]
   double* Rg = reinterpret_cast<double*>(Gu + (size_t)n_pad * N);  // [nU][N]
@@ -564,13 +567,18 @@ hipError_t launch_adj_hop(const ClassDev& c, const double* Cs, double* Gh, doubl
                           double dt, double cG, int reverse, hipStream_t st) {
   if (c.n_live < 1) return hipSuccess;
   const size_t lds = hop_adj_lds(c.md.N);
+  if (lds == 0) {
+    hipLaunchKernelGGL(k_adj_hop<false>, dim3(c.n_live), dim3(kHopAdjThreads), 0, st, c, Cs, Gh, scr,
+                       weights, loss, hopbar, s, T, dt, cG, reverse);
+    return hipGetLastError();
+  }
   if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_adj_hop,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_adj_hop<true>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_adj_hop, dim3(c.n_live), dim3(kHopAdjThreads), lds, st, c, Cs, Gh, scr, weights,
-                     loss, hopbar, s, T, dt, cG, reverse, lds > 0 ? 1 : 0);
+  hipLaunchKernelGGL(k_adj_hop<true>, dim3(c.n_live), dim3(kHopAdjThreads), lds, st, c, Cs, Gh, scr,
+                     weights, loss, hopbar, s, T, dt, cG, reverse);
   return hipGetLastError();
 }
 
