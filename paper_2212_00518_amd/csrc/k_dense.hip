@@ -39,6 +39,15 @@ constexpr int kDenWaves = kDenThreads / 64;
 constexpr int kJacobiSweeps = 60;
 constexpr int64_t kDenseColdEvery = 256;  // steps between cold eigen-solves of a trajectory
 constexpr double kEpsD = 2.220446049250313e-16;
+// A sweep whose rotations all have |tan| below this ends the iteration: the
+// off-diagonal elements it leaves are about the square of its largest
+// rotation relative to the level gaps, so the next sweep would rotate by
+// angles near rounding (the confirming sweep without rotations is skipped).
+constexpr double kJacobiSmallRot = 1e-8;
+// Rotations a wave applies per round and columns (rows) a lane covers, for
+// n <= IESH_DENSE_MAX_N.
+constexpr int kPairsPerWave = (IESH_DENSE_MAX_N / 2 + kDenWaves - 1) / kDenWaves;
+constexpr int kColsPerLane = (IESH_DENSE_MAX_N + 63) / 64;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -57,14 +66,15 @@ struct DenLds {
   double* nuc;   // [4]: half-step velocity, new position, propagator position, force
   int* rank;     // [np]: position of Jacobi column j in ascending order
   int* pq;       // [np]: the pairs of a round
-  int* flag;     // [4]: rotation happened, failure bits, scratch
+  int* flag;     // [5]: rotation happened, failure bits, unused, unused, a large rotation
+                 // in this sweep
 };
 
 __host__ __device__ inline size_t dense_lds_bytes(int np) {
   const size_t ld = np + 1;
   return sizeof(double) * (2 * (size_t)np * ld + 4 * (size_t)np + (size_t)np + 2 * kDenWaves +
                            kMaxCheb + 4) +
-         sizeof(int) * (2 * (size_t)np + 4);
+         sizeof(int) * (2 * (size_t)np + 5);
 }
 
 __device__ inline DenLds dense_lds(double* sm, int np) {
@@ -85,6 +95,14 @@ __device__ inline DenLds dense_lds(double* sm, int np) {
   L.pq = L.rank + np;
   L.flag = L.pq + np;
   return L;
+}
+
+// Value of lane `src` (wave-uniform) of a per-lane double.
+__device__ inline double lane_value(double v, int src) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)u, src);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 // Sum of v over the work-group (every thread gets it).
@@ -192,83 +210,118 @@ __device__ bool dense_eigen(const ClassDev& c, double x, DenLds& L, const double
   for (int sweep = 0; sweep < kJacobiSweeps; ++sweep) {
     if (tid == 0) {
       L.flag[0] = 0;
-      L.flag[2] = 0;  // round 0 has no rotation yet
+      L.flag[4] = 0;
     }
     __syncthreads();
+    // the pairs of a round are disjoint, so a wave takes pairs wave, wave + 8,
+    // ... (its lane i computes the rotation of the i-th) and a lane columns
+    // (rows) lane and lane + 64; the rotations need no exchange between
+    // waves, and a round costs two barriers
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     for (int r = 0; r < m - 1; ++r) {
-      int* rot = L.flag + 2 + (r & 1);  // a rotation in this round (slots alternate by round)
-      for (int k = tid; k < half; k += kDenThreads) {
-        int p, q;
-        if (k == 0) {
-          p = r;
-          q = m - 1;
-        } else {
-          p = (r + k) % (m - 1);
-          q = (r - k + (m - 1)) % (m - 1);
-        }
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        double cth = 1.0, sth = 0.0;
-        if (q < n) {
-          const double apq = L.A[(size_t)p * ld + q];
-          const double app = L.A[(size_t)p * ld + p], aqq = L.A[(size_t)q * ld + q];
-          if (apq != 0.0 && fabs(apq) > kEpsD * sqrt(fabs(app) * fabs(aqq))) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double tt = copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            cth = 1.0 / sqrt(1.0 + tt * tt);
-            sth = tt * cth;
-            L.flag[0] = 1;
-            *rot = 1;
+      int pl = 0, ql = 0;
+      double cl = 1.0, sl = 0.0;
+      {
+        const int k = wave + kDenWaves * lane;
+        if (lane < kPairsPerWave && k < half) {
+          int p, q;
+          if (k == 0) {
+            p = r;
+            q = m - 1;
+          } else {
+            p = (r + k) % (m - 1);
+            q = (r - k + (m - 1)) % (m - 1);
+          }
+          if (p > q) {
+            const int tmp = p;
+            p = q;
+            q = tmp;
+          }
+          pl = p;
+          ql = q;
+          if (q < n) {
+            const double apq = L.A[p * ld + q];
+            const double app = L.A[p * ld + p], aqq = L.A[q * ld + q];
+            // |a_pq| > eps sqrt(|a_pp a_qq|), squared
+            if (apq != 0.0 && apq * apq > (kEpsD * kEpsD) * fabs(app * aqq)) {
+              // t = tan of the rotation angle, the smaller root of
+              // t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp) / (2 a_pq)
+              const double d = aqq - app;
+              const double tt = (d >= 0.0 ? 2.0 : -2.0) * apq / (fabs(d) + sqrt(d * d + 4.0 * apq * apq));
+              cl = 1.0 / sqrt(1.0 + tt * tt);
+              sl = tt * cl;
+              L.flag[0] = 1;
+              if (fabs(tt) > kJacobiSmallRot) L.flag[4] = 1;
+            }
           }
         }
-        L.pq[2 * k] = p;
-        L.pq[2 * k + 1] = q;
-        L.cs[k] = cth;
-        L.sn[k] = sth;
+      }
+      int pp[kPairsPerWave], qq[kPairsPerWave];
+      double cc[kPairsPerWave], ss[kPairsPerWave];
+#pragma unroll
+      for (int i = 0; i < kPairsPerWave; ++i) {
+        pp[i] = __builtin_amdgcn_readlane(pl, i);
+        qq[i] = __builtin_amdgcn_readlane(ql, i);
+        cc[i] = lane_value(cl, i);
+        ss[i] = lane_value(sl, i);  // 0: nothing to apply (uniform)
+      }
+      {
+        double ap[kPairsPerWave][kColsPerLane], aq[kPairsPerWave][kColsPerLane];
+#pragma unroll
+        for (int i = 0; i < kPairsPerWave; ++i)
+#pragma unroll
+          for (int u = 0; u < kColsPerLane; ++u) {
+            const int j = lane + 64 * u;
+            if (ss[i] != 0.0 && j < m) {
+              ap[i][u] = L.A[pp[i] * ld + j];
+              aq[i][u] = L.A[qq[i] * ld + j];
+            }
+          }
+#pragma unroll
+        for (int i = 0; i < kPairsPerWave; ++i)
+#pragma unroll
+          for (int u = 0; u < kColsPerLane; ++u) {
+            const int j = lane + 64 * u;
+            if (ss[i] != 0.0 && j < m) {
+              L.A[pp[i] * ld + j] = cc[i] * ap[i][u] - ss[i] * aq[i][u];
+              L.A[qq[i] * ld + j] = ss[i] * ap[i][u] + cc[i] * aq[i][u];
+            }
+          }
       }
       __syncthreads();
-      // a round without rotations (most rounds of the last sweeps) has
-      // nothing to apply.  Every thread reads this round's slot between the
-      // two barriers; the next round's slot, last read two rounds ago, is
-      // cleared there too, before any thread can start that round
-      const int rotated = *rot;
-      if (tid == 0) L.flag[2 + ((r + 1) & 1)] = 0;
-      __syncthreads();
-      if (!rotated) continue;
-      // rows p, q of every pair
-      for (int idx = tid; idx < half * m; idx += kDenThreads) {
-        const int k = idx / m, j = idx - k * m;
-        const double s = L.sn[k];
-        if (s == 0.0) continue;
-        const double cth = L.cs[k];
-        const int p = L.pq[2 * k], q = L.pq[2 * k + 1];
-        const double ap = L.A[(size_t)p * ld + j], aq = L.A[(size_t)q * ld + j];
-        L.A[(size_t)p * ld + j] = cth * ap - s * aq;
-        L.A[(size_t)q * ld + j] = s * ap + cth * aq;
-      }
-      __syncthreads();
-      // columns p, q of A and V
-      for (int idx = tid; idx < half * m; idx += kDenThreads) {
-        const int k = idx / m, j = idx - k * m;
-        const double s = L.sn[k];
-        if (s == 0.0) continue;
-        const double cth = L.cs[k];
-        const int p = L.pq[2 * k], q = L.pq[2 * k + 1];
-        const double ap = L.A[(size_t)j * ld + p], aq = L.A[(size_t)j * ld + q];
-        L.A[(size_t)j * ld + p] = (j == q) ? 0.0 : cth * ap - s * aq;
-        L.A[(size_t)j * ld + q] = (j == p) ? 0.0 : s * ap + cth * aq;
-        const double vp = L.V[(size_t)j * ld + p], vq = L.V[(size_t)j * ld + q];
-        L.V[(size_t)j * ld + p] = cth * vp - s * vq;
-        L.V[(size_t)j * ld + q] = s * vp + cth * vq;
+      {
+        double ap[kPairsPerWave][kColsPerLane], aq[kPairsPerWave][kColsPerLane];
+        double vp[kPairsPerWave][kColsPerLane], vq[kPairsPerWave][kColsPerLane];
+#pragma unroll
+        for (int i = 0; i < kPairsPerWave; ++i)
+#pragma unroll
+          for (int u = 0; u < kColsPerLane; ++u) {
+            const int j = lane + 64 * u;
+            if (ss[i] != 0.0 && j < m) {
+              ap[i][u] = L.A[j * ld + pp[i]];
+              aq[i][u] = L.A[j * ld + qq[i]];
+              vp[i][u] = L.V[j * ld + pp[i]];
+              vq[i][u] = L.V[j * ld + qq[i]];
+            }
+          }
+#pragma unroll
+        for (int i = 0; i < kPairsPerWave; ++i)
+#pragma unroll
+          for (int u = 0; u < kColsPerLane; ++u) {
+            const int j = lane + 64 * u;
+            if (ss[i] != 0.0 && j < m) {
+              L.A[j * ld + pp[i]] = (j == qq[i]) ? 0.0 : cc[i] * ap[i][u] - ss[i] * aq[i][u];
+              L.A[j * ld + qq[i]] = (j == pp[i]) ? 0.0 : ss[i] * ap[i][u] + cc[i] * aq[i][u];
+              L.V[j * ld + pp[i]] = cc[i] * vp[i][u] - ss[i] * vq[i][u];
+              L.V[j * ld + qq[i]] = ss[i] * vp[i][u] + cc[i] * vq[i][u];
+            }
+          }
       }
       __syncthreads();
     }
-    const int any = L.flag[0];
+    const int any = L.flag[0], large = L.flag[4];
     __syncthreads();
-    if (!any) {
+    if (!any || !large) {
       converged = true;
       break;
     }
