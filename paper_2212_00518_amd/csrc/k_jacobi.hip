@@ -15,8 +15,9 @@
 // with J the identity except J_pp = J_qq = c, J_pq = s, J_qp = -s.  A pair is
 // skipped once |a_pq| <= eps sqrt(|a_pp a_qq|) (eps the FP64 unit roundoff
 // times 2; the relative-accuracy stopping rule of Demmel and Veselic) or
-// a_pq = 0; the iteration ends after a sweep without rotations (or reports
-// non-convergence after max_sweeps).
+// a_pq = 0; the iteration ends after a sweep without rotations or whose
+// rotations were all below kSmallRot (or reports non-convergence after
+// max_sweeps).
 
 #include "iesh_internal.hpp"
 
@@ -24,6 +25,13 @@ namespace iesh {
 namespace {
 
 constexpr int kJacThreads = 256;
+constexpr int kJacWaves = kJacThreads / 64;
+constexpr int kChunk = 2;  // pairs a wave rotates per batch of loads
+// A sweep whose rotations all have |tan| below this ends the iteration: the
+// off-diagonal elements it leaves are about the square of its largest
+// rotation relative to the gaps, so the next sweep would only rotate by
+// angles near rounding.
+constexpr double kSmallRot = 1e-8;
 
 // LDS bytes: A and V (when in LDS), the rotations of a round and the pairs.
 size_t jacobi_lds(int n, bool in_lds) {
@@ -38,6 +46,7 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
                                                        int max_sweeps, double* work) {
   extern __shared__ double sm[];
   const int b = blockIdx.x, tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int m = n + (n & 1), half = m / 2;
   const int ld = m + 1;             // row stride: a column walk spreads over the LDS banks
   double* A = kLds ? sm : work + (size_t)b * 2 * m * ld;  // [m][ld]
@@ -45,7 +54,7 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   double* cs = kLds ? V + (size_t)m * ld : sm;  // [half] cosines of the round
   double* sn = cs + half;           // [half] sines
   int* pq = reinterpret_cast<int*>(sn + half);  // [m]: p, q of each pair
-  int* flag = pq + m;               // [1]: a rotation happened in this sweep
+  int* flag = pq + m;               // [2]: a rotation, a rotation above kSmallRot in this sweep
 
   const double* Hb = H + (size_t)b * n * n;
   for (int idx = tid; idx < m * m; idx += kJacThreads) {
@@ -58,7 +67,10 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   int sweep = 0;
   bool converged = false;
   for (; sweep < max_sweeps; ++sweep) {
-    if (tid == 0) flag[0] = 0;
+    if (tid == 0) {
+      flag[0] = 0;
+      flag[1] = 0;
+    }
     __syncthreads();
     for (int r = 0; r < m - 1; ++r) {
       // the pairs of round r and their rotations
@@ -86,6 +98,7 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
             flag[0] = 1;
+            if (fabs(t) > kSmallRot) flag[1] = 1;
           }
         }
         pq[2 * k] = p;
@@ -94,38 +107,77 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
         sn[k] = s;
       }
       __syncthreads();
-      // rows p, q of every pair: rows <- J^T rows
-      for (int idx = tid; idx < half * m; idx += kJacThreads) {
-        const int k = idx / m, j = idx - k * m;
-        const double s = sn[k];
-        if (s == 0.0) continue;
-        const double c = cs[k];
-        const int p = pq[2 * k], q = pq[2 * k + 1];
-        const double ap = A[(size_t)p * ld + j], aq = A[(size_t)q * ld + j];
-        A[(size_t)p * ld + j] = c * ap - s * aq;
-        A[(size_t)q * ld + j] = s * ap + c * aq;
+      // rows p, q of every pair: rows <- J^T rows.  A wave takes pairs wave,
+      // wave + 4, ... (kChunk at a time) and a lane columns lane, lane + 64,
+      // ...; the elements of a chunk are all loaded before any is stored.
+      for (int k0 = wave; k0 < half; k0 += kJacWaves * kChunk) {
+        int pp[kChunk], qq[kChunk];
+        double cc[kChunk], ss[kChunk];
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) {
+          const int k = k0 + kJacWaves * i, kk = (k < half) ? k : 0;
+          ss[i] = (k < half) ? sn[kk] : 0.0;  // 0: nothing to apply (uniform)
+          cc[i] = cs[kk];
+          pp[i] = pq[2 * kk];
+          qq[i] = pq[2 * kk + 1];
+        }
+#pragma unroll 1
+        for (int j = lane; j < m; j += 64) {
+          double ap[kChunk], aq[kChunk];
+#pragma unroll
+          for (int i = 0; i < kChunk; ++i)
+            if (ss[i] != 0.0) {
+              ap[i] = A[pp[i] * ld + j];
+              aq[i] = A[qq[i] * ld + j];
+            }
+#pragma unroll
+          for (int i = 0; i < kChunk; ++i)
+            if (ss[i] != 0.0) {
+              A[pp[i] * ld + j] = cc[i] * ap[i] - ss[i] * aq[i];
+              A[qq[i] * ld + j] = ss[i] * ap[i] + cc[i] * aq[i];
+            }
+        }
       }
       __syncthreads();
-      // columns p, q of A and V: columns <- columns J
-      for (int idx = tid; idx < half * m; idx += kJacThreads) {
-        const int k = idx / m, j = idx - k * m;
-        const double s = sn[k];
-        if (s == 0.0) continue;
-        const double c = cs[k];
-        const int p = pq[2 * k], q = pq[2 * k + 1];
-        const double ap = A[(size_t)j * ld + p], aq = A[(size_t)j * ld + q];
-        // the annihilated pair (rows p and q of columns q and p) is set to zero
-        A[(size_t)j * ld + p] = (j == q) ? 0.0 : c * ap - s * aq;
-        A[(size_t)j * ld + q] = (j == p) ? 0.0 : s * ap + c * aq;
-        const double vp = V[(size_t)j * ld + p], vq = V[(size_t)j * ld + q];
-        V[(size_t)j * ld + p] = c * vp - s * vq;
-        V[(size_t)j * ld + q] = s * vp + c * vq;
+      // columns p, q of A and V: columns <- columns J (a lane per row)
+      for (int k0 = wave; k0 < half; k0 += kJacWaves * kChunk) {
+        int pp[kChunk], qq[kChunk];
+        double cc[kChunk], ss[kChunk];
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) {
+          const int k = k0 + kJacWaves * i, kk = (k < half) ? k : 0;
+          ss[i] = (k < half) ? sn[kk] : 0.0;
+          cc[i] = cs[kk];
+          pp[i] = pq[2 * kk];
+          qq[i] = pq[2 * kk + 1];
+        }
+#pragma unroll 1
+        for (int j = lane; j < m; j += 64) {
+          double ap[kChunk], aq[kChunk], vp[kChunk], vq[kChunk];
+#pragma unroll
+          for (int i = 0; i < kChunk; ++i)
+            if (ss[i] != 0.0) {
+              ap[i] = A[j * ld + pp[i]];
+              aq[i] = A[j * ld + qq[i]];
+              vp[i] = V[j * ld + pp[i]];
+              vq[i] = V[j * ld + qq[i]];
+            }
+#pragma unroll
+          for (int i = 0; i < kChunk; ++i)
+            if (ss[i] != 0.0) {
+              // the annihilated pair (rows p and q of columns q and p) is set to zero
+              A[j * ld + pp[i]] = (j == qq[i]) ? 0.0 : cc[i] * ap[i] - ss[i] * aq[i];
+              A[j * ld + qq[i]] = (j == pp[i]) ? 0.0 : ss[i] * ap[i] + cc[i] * aq[i];
+              V[j * ld + pp[i]] = cc[i] * vp[i] - ss[i] * vq[i];
+              V[j * ld + qq[i]] = ss[i] * vp[i] + cc[i] * vq[i];
+            }
+        }
       }
       __syncthreads();
     }
-    const int any = flag[0];
+    const int any = flag[0], large = flag[1];
     __syncthreads();
-    if (!any) {
+    if (!any || !large) {
       converged = true;
       break;
     }
