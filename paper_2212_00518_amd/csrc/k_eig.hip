@@ -85,9 +85,47 @@ __device__ inline double rcp_nr1(double d) {
 // one-step reciprocal's 2.2e-15, so f is known to about 3e-15 of that sum;
 // err = 16 eps of it.  A root accurate to that is accurate to about 3e-15
 // relative to its distance from the nearest pole.
+// The same for a root whose pole sum is shared by a group of G lanes (G a
+// power of two, the group's lanes adjacent and G > 1): lane g of the group
+// sums the poles k = g, g + G, ... with the per-lane left/right split, and the
+// group combines its partial sums (every lane of it gets the totals).  It
+// serves the last, partly filled wave of roots, whose idle lanes would
+// otherwise cost as many instructions as a full wave.
+__device__ inline void secular_eval_group(int j, int g, int G, int M, const double* e,
+                                          const double* V2, double eo, double emh, double tau,
+                                          double& f, double& dl, double& dr, double& err) {
+  double pl = 0.0, pr = 0.0, l = 0.0, r = 0.0;
+  for (int k = g; k < M; k += G) {
+    const double d = (e[k] - eo) - tau;
+    const double inv = rcp_nr1(d);
+    const double t = V2[k] * inv;
+    if (k < j) {
+      pl += t;
+      l = fma(t, inv, l);
+    } else {
+      pr += t;
+      r = fma(t, inv, r);
+    }
+  }
+  for (int sh = 1; sh < G; sh <<= 1) {
+    pl += __shfl_xor(pl, sh);
+    pr += __shfl_xor(pr, sh);
+    l += __shfl_xor(l, sh);
+    r += __shfl_xor(r, sh);
+  }
+  f = emh + tau + (pl + pr);
+  dl = l;
+  dr = r;
+  err = 16.0 * kEps * (fabs(emh) + fabs(tau) + (pr - pl));
+}
+
 __device__ inline void secular_eval(int j, int j0, int M, const double* e, const double* V2,
                                     double eo, double emh, double tau, double& f, double& dl,
-                                    double& dr, double& err) {
+                                    double& dr, double& err, int g = 0, int G = 1) {
+  if (G > 1) {
+    secular_eval_group(j, g, G, M, e, V2, eo, emh, tau, f, dl, dr, err);
+    return;
+  }
   double pl = 0.0, pm = 0.0, pr = 0.0, am = 0.0, l = 0.0, r = 0.0;
   const int k1 = min(j0, M), k2 = min(j0 + 64, M);
 #pragma unroll 4
@@ -160,7 +198,7 @@ constexpr double kStepAccept = 1e-13;
 // the root to about 1e-13).
 __device__ int secular_root(int j, int j0, int M, const double* e, const double* V2, double h,
                             double vnorm, int max_it, double lam_g, double dlt, double lam_s,
-                            double& tau_out, int& org_out, double& dsum_out) {
+                            double& tau_out, int& org_out, double& dsum_out, int g = 0, int G = 1) {
   int o;
   double lo, hi, tau, f = 0.0, dl = 0.0, dr = 0.0, err = 0.0;
   bool have_f = false;
@@ -227,7 +265,7 @@ __device__ int secular_root(int j, int j0, int M, const double* e, const double*
   } else {
     const double gap = e[j] - e[j - 1];
     const double half = 0.5 * gap;
-    secular_eval(j, j0, M, e, V2, e[j - 1], e[j - 1] - h, half, f, dl, dr, err);
+    secular_eval(j, j0, M, e, V2, e[j - 1], e[j - 1] - h, half, f, dl, dr, err, g, G);
     if (f >= 0.0) {
       o = j - 1;
       lo = 0.0;
@@ -245,7 +283,7 @@ __device__ int secular_root(int j, int j0, int M, const double* e, const double*
   const double emh = eo - h;
   int ok = 0;
   for (int it = 0; it < max_it; ++it) {
-    if (!have_f) secular_eval(j, j0, M, e, V2, eo, emh, tau, f, dl, dr, err);
+    if (!have_f) secular_eval(j, j0, M, e, V2, eo, emh, tau, f, dl, dr, err, g, G);
     have_f = false;
     dsum_out = dl + dr;
     if (f == 0.0 || fabs(f) <= err) {
@@ -370,12 +408,19 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
     const double bound = fabs(dh0) + fabs(df) * (vnorm / ma.f);
     dlt = 2.0 * bound + 64.0 * kEps * (fabs(ma.h) + vnorm + fabs(L.e[0]) + fabs(L.e[M - 1]));
   }
-  for (int j = tid; j < n; j += kEigThreads) {
+  // A wave solves the 64 consecutive roots from jb.  In the last, partly
+  // filled wave (T < 64 roots) groups of G lanes share a root's pole sums,
+  // G the largest power of two with G T <= 64; lane g == 0 of a group keeps
+  // the result.
+  const int lane = tid & 63;
+  for (int jb = tid - lane; jb < n; jb += kEigThreads) {
+    const int T = min(64, n - jb);
+    int G = 1;
+    while (2 * G * T <= 64) G *= 2;
+    const int j = jb + lane / G, g = lane & (G - 1);
+    if (j >= jb + T) continue;
     double tau;
     int o;
-    // the roots of a wave are the 64 consecutive indices from j0 (the block
-    // has a whole number of waves and steps j by its size)
-    const int j0 = __builtin_amdgcn_readfirstlane(j - (tid & 63));
     double lam_g = 0.0, lam_s = 0.0;
     if (dlt >= 0.0) {
       lam_g = L.e[rs.org[j]] + rs.tau[j];
@@ -383,17 +428,19 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
       lam_s = lam_g + q2 * (dh0 + 2.0 * (lam_g - h0) * dfr);
     }
     double dsum = 0.0;
-    const int ok =
-        secular_root(j, j0, M, L.e, L.V2, ma.h, vnorm, md.eig_iter, lam_g, dlt, lam_s, tau, o, dsum);
-    L.tau[j] = tau;
-    L.org[j] = o;
-    L.lam[j] = L.e[o] + tau;
-    L.q0[j] = 1.0 / sqrt(1.0 + dsum);
-    if (!ok) atomicOr(&L.fail, 1);
-    if (rs.geo && store) {
-      rs.tau[j] = tau;
-      rs.q0[j] = L.q0[j];
-      rs.org[j] = o;
+    const int ok = secular_root(j, jb, M, L.e, L.V2, ma.h, vnorm, md.eig_iter, lam_g, dlt, lam_s, tau,
+                                o, dsum, g, G);
+    if (g == 0) {
+      L.tau[j] = tau;
+      L.org[j] = o;
+      L.lam[j] = L.e[o] + tau;
+      L.q0[j] = 1.0 / sqrt(1.0 + dsum);
+      if (!ok) atomicOr(&L.fail, 1);
+      if (rs.geo && store) {
+        rs.tau[j] = tau;
+        rs.q0[j] = L.q0[j];
+        rs.org[j] = o;
+      }
     }
   }
   __syncthreads();
