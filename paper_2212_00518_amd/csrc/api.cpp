@@ -950,11 +950,16 @@ int iesh_create(const iesh_model_desc* models, int32_t n_models, const int32_t* 
           (rc = dalloc(ctx, &c.Qw, (size_t)T * n_pad * n_pad)))
         return bail(rc);
       const int n = c.md.n;
+      // padded to n_pad and symmetrised (validation bounds the asymmetry by
+      // 1e-14 of the largest element): the kernels read either triangle
       std::vector<double> pad((size_t)2 * n_pad * n_pad, 0.0);
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < 2; ++h) {
+        const double* H = d.dense + (size_t)h * n * n;
         for (int i = 0; i < n; ++i)
           for (int j = 0; j < n; ++j)
-            pad[(size_t)h * n_pad * n_pad + (size_t)i * n_pad + j] = d.dense[(size_t)h * n * n + (size_t)i * n + j];
+            pad[(size_t)h * n_pad * n_pad + (size_t)i * n_pad + j] =
+                0.5 * (H[(size_t)i * n + j] + H[(size_t)j * n + i]);
+      }
       if (hipMemcpyAsync(h0, pad.data(), (size_t)n_pad * n_pad * sizeof(double), hipMemcpyHostToDevice,
                          ctx->stream) != hipSuccess ||
           hipMemcpyAsync(h1, pad.data() + (size_t)n_pad * n_pad, (size_t)n_pad * n_pad * sizeof(double),

@@ -77,7 +77,7 @@ __host__ __device__ inline size_t dense_lds_bytes(int np) {
          sizeof(int) * (2 * (size_t)np + 5);
 }
 
-__device__ inline DenLds dense_lds(double* sm, int np) {
+__device__ __forceinline__ DenLds dense_lds(double* sm, int np) {
   DenLds L;
   const size_t ld = np + 1;
   L.A = sm;
@@ -98,7 +98,7 @@ __device__ inline DenLds dense_lds(double* sm, int np) {
 }
 
 // Value of lane `src` (wave-uniform) of a per-lane double.
-__device__ inline double lane_value(double v, int src) {
+__device__ __forceinline__ double lane_value(double v, int src) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
   const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)u, src);
   const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
@@ -106,7 +106,7 @@ __device__ inline double lane_value(double v, int src) {
 }
 
 // Sum of v over the work-group (every thread gets it).
-__device__ inline double block_sum(double v, double* red) {
+__device__ __forceinline__ double block_sum(double v, double* red) {
   for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
   const int tid = threadIdx.x;
   __syncthreads();
@@ -118,7 +118,7 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-__device__ inline double block_min(double v, double* red) {
+__device__ __forceinline__ double block_min(double v, double* red) {
   for (int m = 32; m > 0; m >>= 1) v = fmin(v, __shfl_xor(v, m));
   const int tid = threadIdx.x;
   __syncthreads();
@@ -130,57 +130,299 @@ __device__ inline double block_min(double v, double* red) {
   return s;
 }
 
-__device__ inline double block_max(double v, double* red) { return -block_min(-v, red); }
+__device__ __forceinline__ double block_max(double v, double* red) { return -block_min(-v, red); }
 
-// Warm start: the rotations start from the eigenvectors W of the
-// trajectory's previous solve (the geometry moved by one half step), so the
-// matrix to diagonalise is W^T H(x) W, nearly diagonal, and the sweeps
-// converge in two or three instead of about ten.  Both products run on the
-// matrix cores: T1 = H(x) W into the scratch block tmp (global), then
-// W^T T1 into L.A, symmetrised.
-__device__ void warm_start(const ClassDev& c, double x, DenLds& L, const double* W, double* tmp) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// A copy of a wave-uniform int that the compiler cannot see through: the
+// addresses computed from it in one stage of the eigen-solve are neither
+// shared with nor hoisted into earlier stages (the two solves of a step and
+// the updates of the refinement would otherwise keep them all live at once).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// 16x16 output tiles a wave takes in a product of order n_pad.
+constexpr int kTilesPerWave =
+    ((IESH_DENSE_MAX_N / 16) * (IESH_DENSE_MAX_N / 16) + kDenWaves - 1) / kDenWaves;
+
+// Row and column block of the u-th 16x16 output tile of a wave: tiles
+// wave, wave + kDenWaves, ... of the RT x RT blocks (row-major), or of the
+// RT (RT + 1) / 2 blocks on and above the diagonal when kUpper.
+template <bool kUpper>
+__device__ __forceinline__ bool tile_of(int wave, int u, int RT, int& rt, int& ct) {
+  int t = wave + u * kDenWaves;
+  if (!kUpper) {
+    rt = t / RT;
+    ct = t - rt * RT;
+    return t < RT * RT;
+  }
+  rt = 0;
+  while (rt < RT && t >= RT - rt) {
+    t -= RT - rt;
+    ++rt;
+  }
+  ct = rt + t;
+  return rt < RT;
+}
+
+// Element (i, k) of a matrix operand at p[i * rs + k * cs] (LDS or global).
+struct MatView {
+  const double* p;
+  int rs, cs;
+};
+
+// acc1[u] (acc2[u]) = the u-th 16x16 tile of this wave (tile_of) of X1 Y
+// (X2 Y, kTwo: one B operand serves both), n_pad = 16 RT; with kIdY the B
+// operand is I + ysc Y.  Lane (lr, lk) holds rows lk + 4 r, column lr of a
+// tile (16x16x4 layout).  The operands of two k-blocks of every tile are
+// loaded before their products, and a wave's tiles beyond its share load
+// those of tile 0 and skip the products, so no load waits behind a branch.
+template <bool kUpper, bool kTwo, bool kIdY = false>
+__device__ __forceinline__ void mm_tiles(v4d (&acc1)[kTilesPerWave], v4d (&acc2)[kTilesPerWave], int RT,
+                                         int wave, int lane, MatView X1, MatView X2, MatView Y,
+                                         double ysc = 1.0) {
+  const int lr = lane & 15, lk = lane >> 4, KB = 4 * RT;
+  const double* x1p[kTilesPerWave];
+  const double* x2p[kTilesPerWave];
+  const double* yp[kTilesPerWave];
+  int jc[kTilesPerWave];
+  bool on[kTilesPerWave];
+#pragma unroll
+  for (int u = 0; u < kTilesPerWave; ++u) {
+    int rt, ct;
+    on[u] = tile_of<kUpper>(wave, u, RT, rt, ct);
+    if (!on[u]) rt = ct = 0;
+    x1p[u] = X1.p + (rt * 16 + lr) * X1.rs + lk * X1.cs;
+    x2p[u] = X2.p + (rt * 16 + lr) * X2.rs + lk * X2.cs;
+    yp[u] = Y.p + lk * Y.rs + (ct * 16 + lr) * Y.cs;
+    jc[u] = ct * 16 + lr - lk;  // k == j at k-block kb when 4 kb == jc
+    acc1[u] = v4d{0.0, 0.0, 0.0, 0.0};
+    acc2[u] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  const int sx1 = 4 * X1.cs, sx2 = 4 * X2.cs, sy = 4 * Y.rs;
+#pragma unroll 1
+  for (int kb = 0; kb < KB; kb += 2) {
+    double a1[2][kTilesPerWave], a2[2][kTilesPerWave], bb[2][kTilesPerWave];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int u = 0; u < kTilesPerWave; ++u) {
+        a1[h][u] = x1p[u][(kb + h) * sx1];
+        if constexpr (kTwo) a2[h][u] = x2p[u][(kb + h) * sx2];
+        bb[h][u] = yp[u][(kb + h) * sy];
+        if constexpr (kIdY) bb[h][u] = ysc * bb[h][u] + (4 * (kb + h) == jc[u] ? 1.0 : 0.0);
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int u = 0; u < kTilesPerWave; ++u) {
+        if (on[u]) {
+          acc1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[h][u], bb[h][u], acc1[u], 0, 0, 0);
+          if constexpr (kTwo)
+            acc2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[h][u], bb[h][u], acc2[u], 0, 0, 0);
+        }
+      }
+  }
+}
+
+// T = H(x) V = H0 V + x H1 V on the matrix cores (one B operand, V in LDS,
+// serves both products), stored at out[i * os + j].  H0 and H1 are
+// symmetric (symmetrised on upload), so their A operands are read by
+// columns, 16 consecutive doubles per row of four lanes.
+__device__ __forceinline__ void hv_product(const ClassDev& c, double x, const DenLds& L, int np, int ld,
+                                           double* out, int os) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lr = lane & 15, lk = lane >> 4, RT = np / 16;
+  v4d acc[kTilesPerWave], acc2[kTilesPerWave];
+  mm_tiles<false, true>(acc, acc2, RT, wave, lane, MatView{c.H0, 1, np}, MatView{c.H1, 1, np},
+                        MatView{L.V, ld, 1});
+#pragma unroll
+  for (int u = 0; u < kTilesPerWave; ++u) {
+    int rt, ct;
+    if (!tile_of<false>(wave, u, RT, rt, ct)) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      out[(rt * 16 + lk + 4 * r) * os + ct * 16 + lr] = acc[u][r] + x * acc2[u][r];
+  }
+}
+
+// A = V^T H(x) V in full into L.A (for the Jacobi sweeps), through T = H V
+// in the scratch block tmp.
+__device__ __forceinline__ void full_rayleigh(const ClassDev& c, double x, DenLds& L, double* tmp) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
-  const int np = c.md.n_pad, ld = np + 1, RT = np / 16, KB = np / 4;
-  for (int idx = tid; idx < np * np; idx += kDenThreads) {
-    const int i = idx / np, j = idx - i * np;
-    L.V[(size_t)i * ld + j] = W[idx];
-  }
-  __syncthreads();
-  const double* H0 = c.H0;
-  const double* H1 = c.H1;
-  for (int tile = wave; tile < RT * RT; tile += kDenWaves) {
-    const int rt = tile / RT, ct = tile - rt * RT;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    const size_t arow = (size_t)(rt * 16 + lr) * np + lk;
-    const double* bcol = L.V + (size_t)lk * ld + ct * 16 + lr;
-    for (int kb = 0; kb < KB; ++kb)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(H0[arow + 4 * kb] + x * H1[arow + 4 * kb],
-                                                 bcol[(size_t)4 * kb * ld], acc, 0, 0, 0);
-    for (int r = 0; r < 4; ++r) tmp[(size_t)(rt * 16 + lk + 4 * r) * np + ct * 16 + lr] = acc[r];
-  }
-  __syncthreads();  // T1 complete (work-group visibility of the global writes)
-  for (int tile = wave; tile < RT * RT; tile += kDenWaves) {
-    const int rt = tile / RT, ct = tile - rt * RT;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    const double* acol = L.V + (size_t)lk * ld + rt * 16 + lr;
-    const double* bcol = tmp + (size_t)lk * np + ct * 16 + lr;
-    for (int kb = 0; kb < KB; ++kb)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(acol[(size_t)4 * kb * ld], bcol[(size_t)4 * kb * np],
-                                                 acc, 0, 0, 0);
-    for (int r = 0; r < 4; ++r) L.A[(size_t)(rt * 16 + lk + 4 * r) * ld + ct * 16 + lr] = acc[r];
-  }
-  __syncthreads();
-  // the two halves of the product differ by rounding: symmetrise
-  for (int idx = tid; idx < np * np; idx += kDenThreads) {
-    const int i = idx / np, j = idx - i * np;
-    if (j > i) {
-      const double a = 0.5 * (L.A[(size_t)i * ld + j] + L.A[(size_t)j * ld + i]);
-      L.A[(size_t)i * ld + j] = a;
-      L.A[(size_t)j * ld + i] = a;
+  const int np = opaque(c.md.n_pad), ld = np + 1, RT = np / 16;
+  hv_product(c, x, L, np, ld, tmp, np);
+  __syncthreads();  // T complete (work-group visibility of the global writes)
+  v4d acc[kTilesPerWave], acc2[kTilesPerWave];
+  mm_tiles<true, false>(acc, acc2, RT, wave, lane, MatView{L.V, 1, ld}, MatView{L.V, 1, ld},
+                        MatView{tmp, np, 1});
+#pragma unroll
+  for (int u = 0; u < kTilesPerWave; ++u) {
+    int rt, ct;
+    if (!tile_of<true>(wave, u, RT, rt, ct)) continue;
+    const int j = ct * 16 + lr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = rt * 16 + lk + 4 * r;
+      if (i <= j) {
+        L.A[i * ld + j] = acc[u][r];
+        L.A[j * ld + i] = acc[u][r];
+      }
     }
   }
   __syncthreads();
+}
+
+// Perturbative refinement of a warm start.  With V = W, the eigenvectors of
+// the trajectory's previous solve (the geometry has moved by half a step),
+// A = V^T H V is nearly diagonal, and the antisymmetric generator
+// K_ij = A_ij / (A_jj - A_ii) (i != j) removes its off-diagonal part to first
+// order: with U = exp(K), U^T A U is diagonal up to terms of order
+// |K| |A_off|, so every update squares the off-diagonal part relative to the
+// level gaps (the quadratic convergence of the Jacobi method, without its
+// n - 1 rounds of rotations per sweep).  The update S = exp(K) - I is its
+// Taylor series in Horner form, cut where the next term's Frobenius norm
+// falls below kExpTrunc (U is then orthogonal to rounding), and
+// V <- V + V S.  A is recomputed from the new V each time, V^T (H V), rather
+// than carried, so no rounding accumulates in it.  The update whose largest
+// |K_ij| is below kPertDone is the last (what it leaves is below rounding
+// relative to the gaps, as after the last Jacobi sweep); the eigenvalues are
+// then the diagonal of V^T H V.  A generator whose norm exceeds kPertMax
+// (close levels, a poor start) or kPertUpdates updates without convergence
+// hand A = V^T H V to the Jacobi sweeps.
+constexpr int kPertUpdates = 4;
+constexpr double kPertDone = 1e-8;
+constexpr double kPertMax = 1e-2;
+constexpr double kExpTrunc = 1e-17;
+constexpr int kMaxExpOrder = 8;
+
+// Refines V (in L.V) for H(x); L.A and L.dj are its working space, tmp a
+// scratch block of n_pad^2 doubles in global memory (the partial products of
+// a series above second order).  True: L.A's diagonal holds the eigenvalues
+// (Jacobi order of L.V).  False: L.A = V^T H V in full, for the sweeps.
+__device__ __forceinline__ bool perturb_refine(const ClassDev& c, double x, DenLds& L, double* tmp) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int n = c.md.n, RT = c.md.n_pad / 16;
+  // the strides are made opaque at the start of every stage (see opaque)
+  int np = c.md.n_pad, ld = np + 1;
+  const auto fresh = [&] {
+    np = opaque(np);
+    ld = opaque(ld);
+  };
+  double* T = L.A;  // H V, then K, then S
+  double* V = L.V;
+  v4d acc[kTilesPerWave], acc2[kTilesPerWave];
+  fresh();
+  hv_product(c, x, L, np, ld, T, ld);
+  __syncthreads();
+  for (int upd = 0; upd < kPertUpdates; ++upd) {
+    // A = V^T T on and above the diagonal (registers); its diagonal to L.dj
+    fresh();
+    mm_tiles<true, false>(acc, acc2, RT, wave, lane, MatView{V, 1, ld}, MatView{V, 1, ld}, MatView{T, ld, 1});
+#pragma unroll
+    for (int u = 0; u < kTilesPerWave; ++u) {
+      int rt, ct;
+      if (!tile_of<true>(wave, u, RT, rt, ct) || rt != ct) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (lk + 4 * r == lr) L.dj[rt * 16 + lr] = acc[u][r];
+    }
+    __syncthreads();  // diagonal complete, every wave done reading T
+    // K into L.A (K_ji = -K_ij), its largest element and Frobenius norm
+    fresh();
+    double kmax = 0.0, ksq = 0.0;
+#pragma unroll
+    for (int u = 0; u < kTilesPerWave; ++u) {
+      int rt, ct;
+      if (!tile_of<true>(wave, u, RT, rt, ct)) continue;
+      const int j = ct * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = rt * 16 + lk + 4 * r;
+        if (i <= j) {
+          const double a = acc[u][r];
+          double k = 0.0;
+          if (i < j && j < n && a != 0.0) k = a / (L.dj[j] - L.dj[i]);
+          T[i * ld + j] = k;
+          T[j * ld + i] = -k;
+          kmax = fmax(kmax, fabs(k));
+          ksq += 2.0 * k * k;
+        }
+      }
+    }
+    kmax = block_max(kmax, L.red);  // its barriers also publish K
+    const double f = sqrt(block_sum(ksq, L.red));
+    if (!(f <= kPertMax)) break;  // also a gap of zero (inf) or NaN
+    int p = 1;
+    for (double term = 0.5 * f * f; term > kExpTrunc && p < kMaxExpOrder;) {
+      ++p;
+      term *= f / (p + 1);
+    }
+    // S = K R_1 with R_q = I + K R_{q+1} / (q + 1), R_{p-1} = I + K / p (p = 1:
+    // S = K); the R_q of a series above second order go to tmp, S replaces K
+    for (int q = p - 2; q >= 0; --q) {
+      fresh();
+      if (q == p - 2)
+        mm_tiles<false, false, true>(acc, acc2, RT, wave, lane, MatView{T, ld, 1}, MatView{T, ld, 1},
+                                     MatView{T, ld, 1}, 1.0 / p);
+      else
+        mm_tiles<false, false>(acc, acc2, RT, wave, lane, MatView{T, ld, 1}, MatView{T, ld, 1},
+                               MatView{tmp, np, 1});
+      __syncthreads();  // every wave done reading K and R
+      fresh();
+      const double sc = 1.0 / (q + 1);
+#pragma unroll
+      for (int u = 0; u < kTilesPerWave; ++u) {
+        int rt, ct;
+        if (!tile_of<false>(wave, u, RT, rt, ct)) continue;
+        const int j = ct * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rt * 16 + lk + 4 * r;
+          if (q >= 1)
+            tmp[i * np + j] = (i == j ? 1.0 : 0.0) + sc * acc[u][r];
+          else
+            T[i * ld + j] = acc[u][r];
+        }
+      }
+      __syncthreads();
+    }
+    // V <- V + V S
+    fresh();
+    mm_tiles<false, false>(acc, acc2, RT, wave, lane, MatView{V, ld, 1}, MatView{V, ld, 1}, MatView{T, ld, 1});
+    __syncthreads();  // every wave done reading V and S
+    fresh();
+#pragma unroll
+    for (int u = 0; u < kTilesPerWave; ++u) {
+      int rt, ct;
+      if (!tile_of<false>(wave, u, RT, rt, ct)) continue;
+      const int j = ct * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) V[(rt * 16 + lk + 4 * r) * ld + j] += acc[u][r];
+    }
+    __syncthreads();
+    fresh();
+    hv_product(c, x, L, np, ld, T, ld);
+    __syncthreads();
+    if (kmax <= kPertDone) {
+      // eigenvalues: the diagonal of V^T T (thread i reads column i only)
+      fresh();
+      for (int i = tid; i < n; i += kDenThreads) {
+        double d = 0.0;
+        for (int k = 0; k < n; ++k) d += V[k * ld + i] * T[k * ld + i];
+        T[i * ld + i] = d;
+      }
+      __syncthreads();
+      return true;
+    }
+  }
+  full_rayleigh(c, x, L, tmp);
+  return false;
 }
 
 // Eigen-decomposition of H(x) = H0 + x H1 in LDS, cold (from H(x) and the
@@ -189,13 +431,19 @@ __device__ void warm_start(const ClassDev& c, double x, DenLds& L, const double*
 // the ascending eigenvalues and impurity components, L.dj / L.sg / L.rank the
 // Jacobi-order eigenvalues, signs and ranks, L.V the eigenvectors (Jacobi
 // order, unsigned).  Returns false when the sweeps did not converge.
-__device__ bool dense_eigen(const ClassDev& c, double x, DenLds& L, const double* W = nullptr,
-                            double* tmp = nullptr) {
+__device__ __forceinline__ bool dense_eigen(const ClassDev& c, double x, DenLds& L,
+                                            const double* W = nullptr, double* tmp = nullptr) {
   const int tid = threadIdx.x;
   const int n = c.md.n, np = c.md.n_pad, ld = np + 1;
   const int m = n + (n & 1), half = m / 2;
+  bool converged = false;
   if (W) {
-    warm_start(c, x, L, W, tmp);
+    for (int idx = tid; idx < np * np; idx += kDenThreads) {
+      const int i = idx / np, j = idx - i * np;
+      L.V[(size_t)i * ld + j] = W[idx];
+    }
+    __syncthreads();
+    converged = perturb_refine(c, x, L, tmp);
   } else {
     const double* H0 = c.H0;
     const double* H1 = c.H1;
@@ -206,8 +454,7 @@ __device__ bool dense_eigen(const ClassDev& c, double x, DenLds& L, const double
     }
     __syncthreads();
   }
-  bool converged = false;
-  for (int sweep = 0; sweep < kJacobiSweeps; ++sweep) {
+  for (int sweep = 0; !converged && sweep < kJacobiSweeps; ++sweep) {
     if (tid == 0) {
       L.flag[0] = 0;
       L.flag[4] = 0;
@@ -361,7 +608,7 @@ __device__ bool dense_eigen(const ClassDev& c, double x, DenLds& L, const double
 
 // The eigenvectors of the last solve (Jacobi order) into the trajectory's
 // warm-start block.
-__device__ inline void save_basis(const ClassDev& c, const DenLds& L, double* W) {
+__device__ __forceinline__ void save_basis(const ClassDev& c, const DenLds& L, double* W) {
   const int np = c.md.n_pad, ld = np + 1;
   for (int idx = threadIdx.x; idx < np * np; idx += kDenThreads) {
     const int i = idx / np, j = idx - i * np;
@@ -370,36 +617,41 @@ __device__ inline void save_basis(const ClassDev& c, const DenLds& L, double* W)
 }
 
 // G = V^T H1 V on the matrix cores into Gd (ranked, sign-fixed basis; rows
-// and columns n .. n_pad - 1 untouched).  T = H1 V overwrites L.A.
-__device__ void dense_project(const ClassDev& c, DenLds& L, double* Gd) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// and columns n .. n_pad - 1 untouched; G on and above the diagonal,
+// mirrored below).  T = H1 V overwrites L.A.
+__device__ __forceinline__ void dense_project(const ClassDev& c, DenLds& L, double* Gd) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 15, lk = lane >> 4;
-  const int n = c.md.n, np = c.md.n_pad, ld = np + 1, RT = np / 16, KB = np / 4;
-  const double* H1 = c.H1;
+  const int n = c.md.n, np = opaque(c.md.n_pad), ld = np + 1, RT = np / 16;
+  v4d acc[kTilesPerWave], acc2[kTilesPerWave];
   // T = H1 V (the diagonalised matrix in L.A is no longer needed)
-  for (int tile = wave; tile < RT * RT; tile += kDenWaves) {
-    const int rt = tile / RT, ct = tile - rt * RT;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    const double* arow = H1 + (size_t)(rt * 16 + lr) * np + lk;
-    const double* bcol = L.V + (size_t)lk * ld + ct * 16 + lr;
-    for (int kb = 0; kb < KB; ++kb)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[4 * kb], bcol[(size_t)4 * kb * ld], acc, 0, 0, 0);
-    for (int r = 0; r < 4; ++r) L.A[(size_t)(rt * 16 + lk + 4 * r) * ld + ct * 16 + lr] = acc[r];
+  mm_tiles<false, false>(acc, acc2, RT, wave, lane, MatView{c.H1, 1, np}, MatView{c.H1, 1, np},
+                         MatView{L.V, ld, 1});
+#pragma unroll
+  for (int u = 0; u < kTilesPerWave; ++u) {
+    int rt, ct;
+    if (!tile_of<false>(wave, u, RT, rt, ct)) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) L.A[(size_t)(rt * 16 + lk + 4 * r) * ld + ct * 16 + lr] = acc[u][r];
   }
   __syncthreads();
   // G = V^T T, scattered to the ranked basis with the column signs
-  for (int tile = wave; tile < RT * RT; tile += kDenWaves) {
-    const int rt = tile / RT, ct = tile - rt * RT;
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    const double* acol = L.V + (size_t)lk * ld + rt * 16 + lr;  // V[i][a]: A operand of V^T
-    const double* bcol = L.A + (size_t)lk * ld + ct * 16 + lr;
-    for (int kb = 0; kb < KB; ++kb)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(acol[(size_t)4 * kb * ld], bcol[(size_t)4 * kb * ld],
-                                                 acc, 0, 0, 0);
+  mm_tiles<true, false>(acc, acc2, RT, wave, lane, MatView{L.V, 1, ld}, MatView{L.V, 1, ld},
+                        MatView{L.A, ld, 1});
+#pragma unroll
+  for (int u = 0; u < kTilesPerWave; ++u) {
+    int rt, ct;
+    if (!tile_of<true>(wave, u, RT, rt, ct)) continue;
     const int b = ct * 16 + lr;
+#pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int a = rt * 16 + lk + 4 * r;
-      if (a < n && b < n) Gd[(size_t)L.rank[a] * np + L.rank[b]] = L.sg[a] * L.sg[b] * acc[r];
+      if (a <= b && b < n) {
+        const double g = L.sg[a] * L.sg[b] * acc[u][r];
+        Gd[(size_t)L.rank[a] * np + L.rank[b]] = g;
+        Gd[(size_t)L.rank[b] * np + L.rank[a]] = g;
+      }
     }
   }
   __syncthreads();  // Gd complete (work-group visibility of the global writes)
@@ -407,17 +659,17 @@ __device__ void dense_project(const ClassDev& c, DenLds& L, double* Gd) {
 
 // D_jk = G_jk / (lambda_k - lambda_j); zero on the diagonal and between
 // states whose energies agree to 1e-12 of the largest |lambda|.
-__device__ inline double dense_D(const double* Gd, const DenLds& L, int np, double tol, int j, int k) {
+__device__ __forceinline__ double dense_D(const double* Gd, const DenLds& L, int np, double tol, int j, int k) {
   const double diff = L.lam[k] - L.lam[j];
   return (j == k || fabs(diff) <= tol) ? 0.0 : Gd[(size_t)j * np + k] / diff;
 }
 
-__device__ inline double lam_tol(const DenLds& L, int n) {
+__device__ __forceinline__ double lam_tol(const DenLds& L, int n) {
   return 1e-12 * fmax(fabs(L.lam[0]), fabs(L.lam[n - 1]));
 }
 
 // Hellmann-Feynman force of the occupied set: -U0'(x) - sum_{a in s} G_aa.
-__device__ double dense_force(const ClassDev& c, const double* Gd, const int32_t* occ, double x,
+__device__ __forceinline__ double dense_force(const ClassDev& c, const double* Gd, const int32_t* occ, double x,
                               DenLds& L) {
   const int np = c.md.n_pad;
   double part = 0.0;
@@ -430,7 +682,7 @@ __device__ double dense_force(const ClassDev& c, const double* Gd, const int32_t
   return -k * (x - c.md.p[1]) - s;
 }
 
-__device__ inline void dense_geo(double* geo, const ModelDev& md, double x) {
+__device__ __forceinline__ void dense_geo(double* geo, const ModelDev& md, double x) {
   const double k = md.mass * md.p[0] * md.p[0];
   const double u = x - md.p[1];
   geo[GEO_U0] = 0.5 * k * u * u;
@@ -563,7 +815,7 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_query(ClassDev c, int t0,
   }
 }
 
-__device__ inline double fermi_d(double e, double mu, double kT) {
+__device__ __forceinline__ double fermi_d(double e, double mu, double kT) {
   const double z = (e - mu) / kT;
   return (z > 0.0) ? exp(-z) / (1.0 + exp(-z)) : 1.0 / (1.0 + exp(z));
 }
