@@ -171,21 +171,25 @@ struct MatView {
   int rs, cs;
 };
 
-// acc1[u] (acc2[u]) = the u-th 16x16 tile of this wave (tile_of) of X1 Y
-// (X2 Y, kTwo: one B operand serves both), n_pad = 16 RT; with kIdY the B
-// operand is I + ysc Y.  Lane (lr, lk) holds rows lk + 4 r, column lr of a
-// tile (16x16x4 layout).  The operands of two k-blocks of every tile are
-// loaded before their products, and a wave's tiles beyond its share load
-// those of tile 0 and skip the products, so no load waits behind a branch.
-template <bool kUpper, bool kTwo, bool kIdY = false>
+// Products a wave forms in one pass of mm_tiles.
+enum MmMode { kOne, kTwoX, kTwoY };
+
+// acc1[u] = the u-th 16x16 tile of this wave (tile_of) of X1 Y1, n_pad =
+// 16 RT; with kTwoX also acc2[u] of X2 Y1 (one B operand serves both), with
+// kTwoY acc2[u] of X1 Y2 (one A operand serves both).  Lane (lr, lk) holds
+// rows lk + 4 r, column lr of a tile (16x16x4 layout).  The operands of the
+// next k-block of every tile are requested before the products of the
+// current one, and a wave's tiles beyond its share load those of tile 0 and
+// skip the products, so no load waits behind a branch.
+template <bool kUpper, MmMode kMode>
 __device__ __forceinline__ void mm_tiles(v4d (&acc1)[kTilesPerWave], v4d (&acc2)[kTilesPerWave], int RT,
-                                         int wave, int lane, MatView X1, MatView X2, MatView Y,
-                                         double ysc = 1.0) {
+                                         int wave, int lane, MatView X1, MatView X2, MatView Y1,
+                                         MatView Y2) {
   const int lr = lane & 15, lk = lane >> 4, KB = 4 * RT;
   const double* x1p[kTilesPerWave];
   const double* x2p[kTilesPerWave];
-  const double* yp[kTilesPerWave];
-  int jc[kTilesPerWave];
+  const double* y1p[kTilesPerWave];
+  const double* y2p[kTilesPerWave];
   bool on[kTilesPerWave];
 #pragma unroll
   for (int u = 0; u < kTilesPerWave; ++u) {
@@ -194,71 +198,81 @@ __device__ __forceinline__ void mm_tiles(v4d (&acc1)[kTilesPerWave], v4d (&acc2)
     if (!on[u]) rt = ct = 0;
     x1p[u] = X1.p + (rt * 16 + lr) * X1.rs + lk * X1.cs;
     x2p[u] = X2.p + (rt * 16 + lr) * X2.rs + lk * X2.cs;
-    yp[u] = Y.p + lk * Y.rs + (ct * 16 + lr) * Y.cs;
-    jc[u] = ct * 16 + lr - lk;  // k == j at k-block kb when 4 kb == jc
+    y1p[u] = Y1.p + lk * Y1.rs + (ct * 16 + lr) * Y1.cs;
+    y2p[u] = Y2.p + lk * Y2.rs + (ct * 16 + lr) * Y2.cs;
     acc1[u] = v4d{0.0, 0.0, 0.0, 0.0};
     acc2[u] = v4d{0.0, 0.0, 0.0, 0.0};
   }
-  const int sx1 = 4 * X1.cs, sx2 = 4 * X2.cs, sy = 4 * Y.rs;
-#pragma unroll 1
-  for (int kb = 0; kb < KB; kb += 2) {
-    double a1[2][kTilesPerWave], a2[2][kTilesPerWave], bb[2][kTilesPerWave];
+  const int sx1 = 4 * X1.cs, sx2 = 4 * X2.cs, sy1 = 4 * Y1.rs, sy2 = 4 * Y2.rs;
+  // software pipelined: the operands of k-block kb + 1 are requested before
+  // the products of k-block kb (the last request repeats k-block KB - 1)
+  double a1[kTilesPerWave], a2[kTilesPerWave], b1[kTilesPerWave], b2[kTilesPerWave];
+  const auto fetch = [&](int kb, double* f1, double* f2, double* g1, double* g2) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int u = 0; u < kTilesPerWave; ++u) {
+      f1[u] = x1p[u][kb * sx1];
+      if constexpr (kMode == kTwoX) f2[u] = x2p[u][kb * sx2];
+      g1[u] = y1p[u][kb * sy1];
+      if constexpr (kMode == kTwoY) g2[u] = y2p[u][kb * sy2];
+    }
+  };
+  fetch(0, a1, a2, b1, b2);
+#pragma unroll 2
+  for (int kb = 0; kb < KB; ++kb) {
+    double n1[kTilesPerWave], n2[kTilesPerWave], m1[kTilesPerWave], m2[kTilesPerWave];
+    fetch(kb + 1 < KB ? kb + 1 : kb, n1, n2, m1, m2);
 #pragma unroll
-      for (int u = 0; u < kTilesPerWave; ++u) {
-        a1[h][u] = x1p[u][(kb + h) * sx1];
-        if constexpr (kTwo) a2[h][u] = x2p[u][(kb + h) * sx2];
-        bb[h][u] = yp[u][(kb + h) * sy];
-        if constexpr (kIdY) bb[h][u] = ysc * bb[h][u] + (4 * (kb + h) == jc[u] ? 1.0 : 0.0);
+    for (int u = 0; u < kTilesPerWave; ++u) {
+      if (on[u]) {
+        acc1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u], acc1[u], 0, 0, 0);
+        if constexpr (kMode == kTwoX)
+          acc2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[u], b1[u], acc2[u], 0, 0, 0);
+        if constexpr (kMode == kTwoY)
+          acc2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b2[u], acc2[u], 0, 0, 0);
       }
+    }
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int u = 0; u < kTilesPerWave; ++u) {
-        if (on[u]) {
-          acc1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[h][u], bb[h][u], acc1[u], 0, 0, 0);
-          if constexpr (kTwo)
-            acc2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[h][u], bb[h][u], acc2[u], 0, 0, 0);
-        }
-      }
+    for (int u = 0; u < kTilesPerWave; ++u) {
+      a1[u] = n1[u];
+      if constexpr (kMode == kTwoX) a2[u] = n2[u];
+      b1[u] = m1[u];
+      if constexpr (kMode == kTwoY) b2[u] = m2[u];
+    }
   }
 }
 
-// T = H(x) V = H0 V + x H1 V on the matrix cores (one B operand, V in LDS,
-// serves both products), stored at out[i * os + j].  H0 and H1 are
-// symmetric (symmetrised on upload), so their A operands are read by
-// columns, 16 consecutive doubles per row of four lanes.
-__device__ __forceinline__ void hv_product(const ClassDev& c, double x, const DenLds& L, int np, int ld,
-                                           double* out, int os) {
+// T = Hx V on the matrix cores, Hx = H(x) (symmetric, n_pad x n_pad in
+// global memory, read by columns: 16 consecutive doubles per row of four
+// lanes), V in LDS; T stored at out[i * os + j].
+__device__ __forceinline__ void hv_product(const double* Hx, const DenLds& L, int np, int ld, double* out,
+                                           int os) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4, RT = np / 16;
   v4d acc[kTilesPerWave], acc2[kTilesPerWave];
-  mm_tiles<false, true>(acc, acc2, RT, wave, lane, MatView{c.H0, 1, np}, MatView{c.H1, 1, np},
-                        MatView{L.V, ld, 1});
+  const MatView h{Hx, 1, np}, v{L.V, ld, 1};
+  mm_tiles<false, kOne>(acc, acc2, RT, wave, lane, h, h, v, v);
 #pragma unroll
   for (int u = 0; u < kTilesPerWave; ++u) {
     int rt, ct;
     if (!tile_of<false>(wave, u, RT, rt, ct)) continue;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      out[(rt * 16 + lk + 4 * r) * os + ct * 16 + lr] = acc[u][r] + x * acc2[u][r];
+    for (int r = 0; r < 4; ++r) out[(rt * 16 + lk + 4 * r) * os + ct * 16 + lr] = acc[u][r];
   }
 }
 
-// A = V^T H(x) V in full into L.A (for the Jacobi sweeps), through T = H V
-// in the scratch block tmp.
-__device__ __forceinline__ void full_rayleigh(const ClassDev& c, double x, DenLds& L, double* tmp) {
+// A = V^T Hx V in full into L.A (for the Jacobi sweeps), through T = Hx V in
+// the scratch block tmp.
+__device__ __forceinline__ void full_rayleigh(const ClassDev& c, const double* Hx, DenLds& L, double* tmp) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   const int np = opaque(c.md.n_pad), ld = np + 1, RT = np / 16;
-  hv_product(c, x, L, np, ld, tmp, np);
+  hv_product(Hx, L, np, ld, tmp, np);
   __syncthreads();  // T complete (work-group visibility of the global writes)
   v4d acc[kTilesPerWave], acc2[kTilesPerWave];
-  mm_tiles<true, false>(acc, acc2, RT, wave, lane, MatView{L.V, 1, ld}, MatView{L.V, 1, ld},
-                        MatView{tmp, np, 1});
+  const MatView vt{L.V, 1, ld}, t{tmp, np, 1};
+  mm_tiles<true, kOne>(acc, acc2, RT, wave, lane, vt, vt, t, t);
 #pragma unroll
   for (int u = 0; u < kTilesPerWave; ++u) {
     int rt, ct;
@@ -276,34 +290,31 @@ __device__ __forceinline__ void full_rayleigh(const ClassDev& c, double x, DenLd
   __syncthreads();
 }
 
-// Perturbative refinement of a warm start.  With V = W, the eigenvectors of
-// the trajectory's previous solve (the geometry has moved by half a step),
-// A = V^T H V is nearly diagonal, and the antisymmetric generator
-// K_ij = A_ij / (A_jj - A_ii) (i != j) removes its off-diagonal part to first
-// order: with U = exp(K), U^T A U is diagonal up to terms of order
-// |K| |A_off|, so every update squares the off-diagonal part relative to the
-// level gaps (the quadratic convergence of the Jacobi method, without its
-// n - 1 rounds of rotations per sweep).  The update S = exp(K) - I is its
-// Taylor series in Horner form, cut where the next term's Frobenius norm
-// falls below kExpTrunc (U is then orthogonal to rounding), and
-// V <- V + V S.  A is recomputed from the new V each time, V^T (H V), rather
-// than carried, so no rounding accumulates in it.  The update whose largest
-// |K_ij| is below kPertDone is the last (what it leaves is below rounding
-// relative to the gaps, as after the last Jacobi sweep); the eigenvalues are
-// then the diagonal of V^T H V.  A generator whose norm exceeds kPertMax
-// (close levels, a poor start) or kPertUpdates updates without convergence
-// hand A = V^T H V to the Jacobi sweeps.
-constexpr int kPertUpdates = 4;
+// Perturbative refinement of a warm start.  V starts as W, the eigenvectors
+// of the trajectory's previous solve (the geometry has moved by half a step):
+// A = V^T H V is nearly diagonal and E = V^T V - I nearly zero.  One update
+// V <- V (I + X) with
+//   X_ij = (A_ij - A_jj E_ij) / (A_jj - A_ii)  (i != j),  X_ii = -E_ii / 2
+// removes, to first order, both A's off-diagonal part and E (X + X^T = -E,
+// and (I + X)^T A (I + X) has no first-order off-diagonal part), so every
+// update squares both relative to the level gaps: the quadratic convergence
+// of the Jacobi method without its n - 1 rounds of rotations per sweep, and
+// orthonormality restored at each update instead of carried (no exponential
+// series is needed).  A and E are recomputed from the current V each time.
+// The update whose largest |X_ij| is below kPertDone is the last (what it
+// leaves is below rounding relative to the gaps, as after the last Jacobi
+// sweep); the eigenvalues are then the diagonal of V^T H V.  An update whose
+// Frobenius norm exceeds kPertMax (close levels, a poor start) or
+// kPertUpdates updates without convergence hand A = V^T H V to the sweeps.
+constexpr int kPertUpdates = 6;
 constexpr double kPertDone = 1e-8;
-constexpr double kPertMax = 1e-2;
-constexpr double kExpTrunc = 1e-17;
-constexpr int kMaxExpOrder = 8;
+constexpr double kPertMax = 0.1;
 
-// Refines V (in L.V) for H(x); L.A and L.dj are its working space, tmp a
-// scratch block of n_pad^2 doubles in global memory (the partial products of
-// a series above second order).  True: L.A's diagonal holds the eigenvalues
-// (Jacobi order of L.V).  False: L.A = V^T H V in full, for the sweeps.
-__device__ __forceinline__ bool perturb_refine(const ClassDev& c, double x, DenLds& L, double* tmp) {
+// Refines V (in L.V) for Hx = H(x) (n_pad x n_pad, global); L.A and L.dj
+// are its working space, tmp a scratch block of n_pad^2 doubles (for the
+// fallback).  True: L.A's diagonal holds the eigenvalues (Jacobi order of
+// L.V).  False: L.A = V^T H V in full, for the sweeps.
+__device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* Hx, DenLds& L, double* tmp) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 15, lk = lane >> 4;
@@ -314,16 +325,20 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, double x, DenL
     np = opaque(np);
     ld = opaque(ld);
   };
-  double* T = L.A;  // H V, then K, then S
+  double* T = L.A;  // H V, then X
   double* V = L.V;
   v4d acc[kTilesPerWave], acc2[kTilesPerWave];
   fresh();
-  hv_product(c, x, L, np, ld, T, ld);
+  hv_product(Hx, L, np, ld, T, ld);
   __syncthreads();
   for (int upd = 0; upd < kPertUpdates; ++upd) {
-    // A = V^T T on and above the diagonal (registers); its diagonal to L.dj
+    // A = V^T T and E + I = V^T V on and above the diagonal (registers); the
+    // diagonal of A to L.dj
     fresh();
-    mm_tiles<true, false>(acc, acc2, RT, wave, lane, MatView{V, 1, ld}, MatView{V, 1, ld}, MatView{T, ld, 1});
+    {
+      const MatView vt{V, 1, ld};
+      mm_tiles<true, kTwoY>(acc, acc2, RT, wave, lane, vt, vt, MatView{T, ld, 1}, MatView{V, ld, 1});
+    }
 #pragma unroll
     for (int u = 0; u < kTilesPerWave; ++u) {
       int rt, ct;
@@ -333,9 +348,9 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, double x, DenL
         if (lk + 4 * r == lr) L.dj[rt * 16 + lr] = acc[u][r];
     }
     __syncthreads();  // diagonal complete, every wave done reading T
-    // K into L.A (K_ji = -K_ij), its largest element and Frobenius norm
+    // X into L.A, its largest element and Frobenius norm
     fresh();
-    double kmax = 0.0, ksq = 0.0;
+    double xmax = 0.0, xsq = 0.0;
 #pragma unroll
     for (int u = 0; u < kTilesPerWave; ++u) {
       int rt, ct;
@@ -344,58 +359,36 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, double x, DenL
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = rt * 16 + lk + 4 * r;
-        if (i <= j) {
-          const double a = acc[u][r];
-          double k = 0.0;
-          if (i < j && j < n && a != 0.0) k = a / (L.dj[j] - L.dj[i]);
-          T[i * ld + j] = k;
-          T[j * ld + i] = -k;
-          kmax = fmax(kmax, fabs(k));
-          ksq += 2.0 * k * k;
+        if (i > j) continue;
+        const double a = acc[u][r];
+        const double e = acc2[u][r] - (i == j ? 1.0 : 0.0);
+        double xij = 0.0, xji = 0.0;
+        if (j < n) {
+          if (i == j) {
+            xij = xji = -0.5 * e;
+          } else {
+            const double di = L.dj[i], dj = L.dj[j];
+            const double nij = a - dj * e, nji = a - di * e;
+            if (nij != 0.0) xij = nij / (dj - di);
+            if (nji != 0.0) xji = nji / (di - dj);
+          }
         }
+        T[i * ld + j] = xij;
+        T[j * ld + i] = xji;
+        xmax = fmax(xmax, fmax(fabs(xij), fabs(xji)));
+        xsq += (i == j) ? xij * xij : xij * xij + xji * xji;
       }
     }
-    kmax = block_max(kmax, L.red);  // its barriers also publish K
-    const double f = sqrt(block_sum(ksq, L.red));
+    xmax = block_max(xmax, L.red);  // its barriers also publish X
+    const double f = sqrt(block_sum(xsq, L.red));
     if (!(f <= kPertMax)) break;  // also a gap of zero (inf) or NaN
-    int p = 1;
-    for (double term = 0.5 * f * f; term > kExpTrunc && p < kMaxExpOrder;) {
-      ++p;
-      term *= f / (p + 1);
-    }
-    // S = K R_1 with R_q = I + K R_{q+1} / (q + 1), R_{p-1} = I + K / p (p = 1:
-    // S = K); the R_q of a series above second order go to tmp, S replaces K
-    for (int q = p - 2; q >= 0; --q) {
-      fresh();
-      if (q == p - 2)
-        mm_tiles<false, false, true>(acc, acc2, RT, wave, lane, MatView{T, ld, 1}, MatView{T, ld, 1},
-                                     MatView{T, ld, 1}, 1.0 / p);
-      else
-        mm_tiles<false, false>(acc, acc2, RT, wave, lane, MatView{T, ld, 1}, MatView{T, ld, 1},
-                               MatView{tmp, np, 1});
-      __syncthreads();  // every wave done reading K and R
-      fresh();
-      const double sc = 1.0 / (q + 1);
-#pragma unroll
-      for (int u = 0; u < kTilesPerWave; ++u) {
-        int rt, ct;
-        if (!tile_of<false>(wave, u, RT, rt, ct)) continue;
-        const int j = ct * 16 + lr;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = rt * 16 + lk + 4 * r;
-          if (q >= 1)
-            tmp[i * np + j] = (i == j ? 1.0 : 0.0) + sc * acc[u][r];
-          else
-            T[i * ld + j] = acc[u][r];
-        }
-      }
-      __syncthreads();
-    }
-    // V <- V + V S
+    // V <- V + V X
     fresh();
-    mm_tiles<false, false>(acc, acc2, RT, wave, lane, MatView{V, ld, 1}, MatView{V, ld, 1}, MatView{T, ld, 1});
-    __syncthreads();  // every wave done reading V and S
+    {
+      const MatView v{V, ld, 1}, x{T, ld, 1};
+      mm_tiles<false, kOne>(acc, acc2, RT, wave, lane, v, v, x, x);
+    }
+    __syncthreads();  // every wave done reading V and X
     fresh();
 #pragma unroll
     for (int u = 0; u < kTilesPerWave; ++u) {
@@ -407,9 +400,9 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, double x, DenL
     }
     __syncthreads();
     fresh();
-    hv_product(c, x, L, np, ld, T, ld);
+    hv_product(Hx, L, np, ld, T, ld);
     __syncthreads();
-    if (kmax <= kPertDone) {
+    if (xmax <= kPertDone) {
       // eigenvalues: the diagonal of V^T T (thread i reads column i only)
       fresh();
       for (int i = tid; i < n; i += kDenThreads) {
@@ -421,7 +414,7 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, double x, DenL
       return true;
     }
   }
-  full_rayleigh(c, x, L, tmp);
+  full_rayleigh(c, Hx, L, tmp);
   return false;
 }
 
@@ -431,19 +424,22 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, double x, DenL
 // the ascending eigenvalues and impurity components, L.dj / L.sg / L.rank the
 // Jacobi-order eigenvalues, signs and ranks, L.V the eigenvectors (Jacobi
 // order, unsigned).  Returns false when the sweeps did not converge.
-__device__ __forceinline__ bool dense_eigen(const ClassDev& c, double x, DenLds& L,
-                                            const double* W = nullptr, double* tmp = nullptr) {
+__device__ __forceinline__ bool dense_eigen(const ClassDev& c, double x, DenLds& L, double* W = nullptr,
+                                            double* tmp = nullptr) {
   const int tid = threadIdx.x;
   const int n = c.md.n, np = c.md.n_pad, ld = np + 1;
   const int m = n + (n & 1), half = m / 2;
   bool converged = false;
   if (W) {
+    // V = W; W's block then holds H(x) until save_basis (H0 and H1 are
+    // symmetric, so H(x) is exactly symmetric)
     for (int idx = tid; idx < np * np; idx += kDenThreads) {
       const int i = idx / np, j = idx - i * np;
       L.V[(size_t)i * ld + j] = W[idx];
+      W[idx] = c.H0[idx] + x * c.H1[idx];
     }
-    __syncthreads();
-    converged = perturb_refine(c, x, L, tmp);
+    __syncthreads();  // (work-group visibility of the global writes)
+    converged = perturb_refine(c, W, L, tmp);
   } else {
     const double* H0 = c.H0;
     const double* H1 = c.H1;
@@ -626,8 +622,10 @@ __device__ __forceinline__ void dense_project(const ClassDev& c, DenLds& L, doub
   const int n = c.md.n, np = opaque(c.md.n_pad), ld = np + 1, RT = np / 16;
   v4d acc[kTilesPerWave], acc2[kTilesPerWave];
   // T = H1 V (the diagonalised matrix in L.A is no longer needed)
-  mm_tiles<false, false>(acc, acc2, RT, wave, lane, MatView{c.H1, 1, np}, MatView{c.H1, 1, np},
-                         MatView{L.V, ld, 1});
+  {
+    const MatView h{c.H1, 1, np}, v{L.V, ld, 1};
+    mm_tiles<false, kOne>(acc, acc2, RT, wave, lane, h, h, v, v);
+  }
 #pragma unroll
   for (int u = 0; u < kTilesPerWave; ++u) {
     int rt, ct;
@@ -637,8 +635,10 @@ __device__ __forceinline__ void dense_project(const ClassDev& c, DenLds& L, doub
   }
   __syncthreads();
   // G = V^T T, scattered to the ranked basis with the column signs
-  mm_tiles<true, false>(acc, acc2, RT, wave, lane, MatView{L.V, 1, ld}, MatView{L.V, 1, ld},
-                        MatView{L.A, ld, 1});
+  {
+    const MatView vt{L.V, 1, ld}, t{L.A, ld, 1};
+    mm_tiles<true, kOne>(acc, acc2, RT, wave, lane, vt, vt, t, t);
+  }
 #pragma unroll
   for (int u = 0; u < kTilesPerWave; ++u) {
     int rt, ct;
