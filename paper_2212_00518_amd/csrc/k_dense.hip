@@ -48,6 +48,7 @@ constexpr double kJacobiSmallRot = 1e-8;
 // n <= IESH_DENSE_MAX_N.
 constexpr int kPairsPerWave = (IESH_DENSE_MAX_N / 2 + kDenWaves - 1) / kDenWaves;
 constexpr int kColsPerLane = (IESH_DENSE_MAX_N + 63) / 64;
+static_assert(IESH_DENSE_MAX_N / 16 <= kDenWaves, "the coupling rows take one wave per 16 rows");
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -59,8 +60,7 @@ struct DenLds {
   double* q0;    // [np]: impurity components (ascending order, sign-fixed)
   double* dj;    // [np]: eigenvalue of Jacobi column j
   double* sg;    // [np]: sign applied to Jacobi column j
-  double* cs;    // [np/2]: cosines of a round
-  double* sn;    // [np/2]: sines of a round
+  double* rs;    // [np]: row sums of |B| (the Gershgorin interval)
   double* red;   // [2 kDenWaves]: per-wave partial results
   double* J;     // [kMaxCheb]: Bessel values
   double* nuc;   // [4]: half-step velocity, new position, propagator position, force
@@ -86,9 +86,8 @@ __device__ __forceinline__ DenLds dense_lds(double* sm, int np) {
   L.q0 = L.lam + np;
   L.dj = L.q0 + np;
   L.sg = L.dj + np;
-  L.cs = L.sg + np;
-  L.sn = L.cs + np / 2;
-  L.red = L.sn + np / 2;
+  L.rs = L.sg + np;
+  L.red = L.rs + np;
   L.J = L.red + 2 * kDenWaves;
   L.nuc = L.J + kMaxCheb;
   L.rank = reinterpret_cast<int*>(L.nuc + 4);
@@ -379,8 +378,24 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
         xsq += (i == j) ? xij * xij : xij * xij + xji * xji;
       }
     }
-    xmax = block_max(xmax, L.red);  // its barriers also publish X
-    const double f = sqrt(block_sum(xsq, L.red));
+    // the wave's largest element and sum of squares to L.red; the barrier
+    // publishes them with X
+    for (int m = 32; m > 0; m >>= 1) {
+      xmax = fmax(xmax, __shfl_xor(xmax, m));
+      xsq += __shfl_xor(xsq, m);
+    }
+    if (lane == 0) {
+      L.red[wave] = xmax;
+      L.red[kDenWaves + wave] = xsq;
+    }
+    __syncthreads();
+    xmax = L.red[0];
+    xsq = L.red[kDenWaves];
+    for (int w = 1; w < kDenWaves; ++w) {
+      xmax = fmax(xmax, L.red[w]);
+      xsq += L.red[kDenWaves + w];
+    }
+    const double f = sqrt(xsq);
     if (!(f <= kPertMax)) break;  // also a gap of zero (inf) or NaN
     // V <- V + V X
     fresh();
@@ -388,7 +403,7 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
       const MatView v{V, ld, 1}, x{T, ld, 1};
       mm_tiles<false, kOne>(acc, acc2, RT, wave, lane, v, v, x, x);
     }
-    __syncthreads();  // every wave done reading V and X
+    __syncthreads();  // every wave done reading V, X and L.red
     fresh();
 #pragma unroll
     for (int u = 0; u < kTilesPerWave; ++u) {
@@ -732,22 +747,34 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double d
     const double tol = lam_tol(L, n);
     double* Bt = c.Bt ? c.Bt + (size_t)t * np * np : nullptr;
     float* Bt32 = c.Bt32 ? c.Bt32 + (size_t)t * np * np : nullptr;
+    // a thread per (row j, quarter of the columns): rows rt*16 .. rt*16 + 15
+    // of wave rt, quarter (lane >> 4); the quarters' sums of |B_jk| meet by
+    // lane exchanges (a fixed order, so the interval is reproducible)
+    {
+      const int lane = tid & 63, rt = tid >> 6, lane_lo = lane & 15, qtr = lane >> 4;
+      const int j = rt * 16 + lane_lo, kq = np / 4;
+      double rsum = 0.0;
+      if (rt < RT) {
+        for (int k = qtr * kq; k < (qtr + 1) * kq; ++k) {
+          const double val = (j < n && k < n) ? vh * dense_D(Gd, L, np, tol, j, k) : 0.0;
+          rsum += fabs(val);
+          const size_t off = ((size_t)((k >> 2) * RT + rt) << 6) + lane_lo + ((k & 3) << 4);
+          if (precision == IESH_FP64)
+            Bt[off] = val;
+          else
+            Bt32[off] = (float)val;
+        }
+      }
+      rsum += __shfl_xor(rsum, 16);
+      rsum += __shfl_xor(rsum, 32);
+      if (rt < RT && qtr == 0) L.rs[j] = rsum;
+    }
+    __syncthreads();
     double lo_part = 1e300, hi_part = -1e300;
     for (int j = tid; j < np; j += kDenThreads) {
-      const int rt = j >> 4, lane_lo = j & 15;
-      double rsum = 0.0;
-      for (int k = 0; k < np; ++k) {
-        const double val = (j < n && k < n) ? vh * dense_D(Gd, L, np, tol, j, k) : 0.0;
-        rsum += fabs(val);
-        const size_t off = ((size_t)((k >> 2) * RT + rt) << 6) + lane_lo + ((k & 3) << 4);
-        if (precision == IESH_FP64)
-          Bt[off] = val;
-        else
-          Bt32[off] = (float)val;
-      }
       if (j < n) {
-        lo_part = fmin(lo_part, L.lam[j] - rsum);
-        hi_part = fmax(hi_part, L.lam[j] + rsum);
+        lo_part = fmin(lo_part, L.lam[j] - L.rs[j]);
+        hi_part = fmax(hi_part, L.lam[j] + L.rs[j]);
       }
       c.lam_mid[(size_t)t * np + j] = L.lam[j];
     }
