@@ -6,24 +6,25 @@
 // Eq. classical_hamiltonian, F = -U0' - sum_{a in s} G_aa).
 //
 // One work-group (8 waves) per trajectory.  The eigen-decomposition of
-// H(x) runs in LDS, warm-started from the trajectory's previous eigenvectors
-// (see warm_start): the matrix and the accumulated rotations, both padded to
-// n_pad = n rounded up to 16 with a row stride of n_pad + 1 doubles, take
-// 2 n_pad (n_pad + 1) doubles, which bounds n at IESH_DENSE_MAX_N (96).  It
-// is the cyclic two-sided Jacobi method (Golub and Van Loan): every sweep
-// visits each index pair once in m - 1 rounds of m/2 disjoint pairs
-// (round-robin over m = n rounded up to even), so the rotations of a round
-// are independent and one pass rotates rows, a second columns; a pair is
-// skipped once |a_pq| <= eps sqrt(|a_pp a_qq|) (the relative stopping rule
-// of Demmel and Veselic).  Eigenvalues are ranked ascending; each
-// eigenvector's first nonzero component (the impurity component, generically)
-// is made positive.
+// H(x) runs in LDS: two matrices padded to n_pad = n rounded up to 16 with a
+// row stride of n_pad + 1 doubles (2 n_pad (n_pad + 1) doubles, which bounds
+// n at IESH_DENSE_MAX_N, 96).  A warm solve starts from the trajectory's
+// previous eigenvectors and refines them by first-order perturbation updates
+// whose products run on the FP64 matrix cores (see perturb_refine); a cold
+// solve, and the fallback of a warm one, is the cyclic two-sided Jacobi
+// method (Golub and Van Loan): every sweep visits each index pair once in
+// m - 1 rounds of m/2 disjoint pairs (round-robin over m = n rounded up to
+// even), so the rotations of a round are independent and one pass rotates
+// rows, a second columns; a pair is skipped once |a_pq| <= eps
+// sqrt(|a_pp a_qq|) (the relative stopping rule of Demmel and Veselic).
+// Eigenvalues are ranked ascending; each eigenvector's first nonzero
+// component (the impurity component, generically) is made positive.
 //
 // The projection G = V^T (H1 V) is two dense products of order n_pad on the
-// FP64 matrix cores (16x16x4 instructions; A operands from H1 in memory or
-// from V in LDS, B operands from LDS): T = H1 V overwrites the diagonalised
-// matrix in LDS, then G = V^T T is written to the trajectory's block of Gd in
-// the ranked, sign-fixed basis.  The midpoint solve turns G into B = v D in
+// FP64 matrix cores (16x16x4 instructions, see mm_tiles): T = H1 V overwrites
+// the diagonalised matrix in LDS, then G = V^T T (on and above the diagonal,
+// mirrored) is written to the trajectory's block of Gd in the ranked,
+// sign-fixed basis.  The midpoint solve turns G into B = v D in
 // the propagation kernel's tile order with the Gershgorin interval of
 // A = diag(lambda) - i B and the Chebyshev block; the end-point solve leaves
 // lambda, Q[0, :] and G for the hop kernels and completes velocity Verlet.
@@ -433,12 +434,14 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
   return false;
 }
 
-// Eigen-decomposition of H(x) = H0 + x H1 in LDS, cold (from H(x) and the
-// identity) or warm (W != nullptr: from the eigenvectors W of the previous
-// solve, tmp a scratch block of n_pad^2 doubles); afterwards L.lam, L.q0 hold
-// the ascending eigenvalues and impurity components, L.dj / L.sg / L.rank the
-// Jacobi-order eigenvalues, signs and ranks, L.V the eigenvectors (Jacobi
-// order, unsigned).  Returns false when the sweeps did not converge.
+// Eigen-decomposition of H(x) = H0 + x H1 in LDS, cold (Jacobi sweeps from
+// H(x) and the identity) or warm (W != nullptr: perturbative refinement of
+// the eigenvectors W of the previous solve, whose block then holds H(x), with
+// the sweeps as fallback; tmp a scratch block of n_pad^2 doubles); afterwards
+// L.lam, L.q0 hold the ascending eigenvalues and impurity components,
+// L.dj / L.sg / L.rank the Jacobi-order eigenvalues, signs and ranks, L.V the
+// eigenvectors (Jacobi order, unsigned).  Returns false when the sweeps did
+// not converge.
 __device__ __forceinline__ bool dense_eigen(const ClassDev& c, double x, DenLds& L, double* W = nullptr,
                                             double* tmp = nullptr) {
   const int tid = threadIdx.x;
@@ -735,8 +738,9 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double d
   double* Gd = c.Gd + (size_t)t * np * np;
   // warm starts from the previous solve of this trajectory (its block is
   // keyed by the home index, so it needs no move when slots are compacted);
-  // every kDenseColdEvery steps the solves start cold, which keeps rounding
-  // in the carried basis from accumulating
+  // every kDenseColdEvery steps the solves start cold (a bound on how long
+  // a trajectory's solves depend on a carried basis; the refinement itself
+  // restores orthonormality at every update)
   double* W = c.Qw + (size_t)c.home[t] * np * np;
   const bool warm = (c.nsteps[t] % kDenseColdEvery) != 0;
   if (sub != -2) {
