@@ -208,7 +208,10 @@ typedef struct iesh_run_desc {
   double hop_gmax;       /* threshold of the adaptive step (> 0 when dt_levels > 0) */
   int32_t eig_max_iter;  /* secular iterations per root, 0..128 (0 = 128).  A small
                             cap is a test hook: roots that do not converge set
-                            IESH_TRAJ_NONCONV and freeze their trajectory       */
+                            IESH_TRAJ_NONCONV and freeze their trajectory.
+                            IESH_MODEL_DENSE: at most this many perturbative
+                            updates of a warm eigen-solve (6 when larger) before
+                            the Jacobi sweeps take over                        */
   int32_t reserved3;
 } iesh_run_desc;
 

@@ -305,15 +305,19 @@ __device__ __forceinline__ void full_rayleigh(const ClassDev& c, const double* H
 // leaves is below rounding relative to the gaps, as after the last Jacobi
 // sweep); the eigenvalues are then the diagonal of V^T H V.  An update whose
 // Frobenius norm exceeds kPertMax (close levels, a poor start) or
-// kPertUpdates updates without convergence hand A = V^T H V to the sweeps.
+// kPertUpdates updates without convergence (fewer when the run caps the
+// eigen-solve's iterations, eig_max_iter) hand A = V^T H V to the sweeps.
 constexpr int kPertUpdates = 6;
 constexpr double kPertDone = 1e-8;
 constexpr double kPertMax = 0.1;
 
 // Refines V (in L.V) for Hx = H(x) (n_pad x n_pad, global); L.A and L.dj
-// are its working space, tmp a scratch block of n_pad^2 doubles (for the
-// fallback).  True: L.A's diagonal holds the eigenvalues (Jacobi order of
-// L.V).  False: L.A = V^T H V in full, for the sweeps.
+// are its working space, tmp a scratch block of n_pad^2 doubles.  True:
+// L.A's diagonal holds the eigenvalues (Jacobi order of L.V).  False: a
+// start for the sweeps, which keep V's orthonormality as they find it: the
+// warm start itself, L.A = W^T H W, when the first update is refused; else
+// (the updates leave V orthonormal only once they converge) the cold start,
+// L.A = H(x) and V = I.
 __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* Hx, DenLds& L, double* tmp) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -331,7 +335,9 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
   fresh();
   hv_product(Hx, L, np, ld, T, ld);
   __syncthreads();
-  for (int upd = 0; upd < kPertUpdates; ++upd) {
+  const int max_upd = min(kPertUpdates, c.md.eig_iter);
+  int applied = 0;  // updates applied to V
+  for (int upd = 0; upd < max_upd; ++upd) {
     // A = V^T T and E + I = V^T V on and above the diagonal (registers); the
     // diagonal of A to L.dj
     fresh();
@@ -414,6 +420,7 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
 #pragma unroll
       for (int r = 0; r < 4; ++r) V[(rt * 16 + lk + 4 * r) * ld + j] += acc[u][r];
     }
+    ++applied;
     __syncthreads();
     fresh();
     hv_product(Hx, L, np, ld, T, ld);
@@ -430,7 +437,17 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
       return true;
     }
   }
-  full_rayleigh(c, Hx, L, tmp);
+  if (applied == 0) {
+    full_rayleigh(c, Hx, L, tmp);
+  } else {
+    fresh();
+    for (int idx = tid; idx < np * np; idx += kDenThreads) {
+      const int i = idx / np, j = idx - i * np;
+      L.A[i * ld + j] = Hx[idx];
+      V[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+  }
   return false;
 }
 
