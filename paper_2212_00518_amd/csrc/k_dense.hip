@@ -339,11 +339,16 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
   int applied = 0;  // updates applied to V
   for (int upd = 0; upd < max_upd; ++upd) {
     // A = V^T T and E + I = V^T V on and above the diagonal (registers); the
-    // diagonal of A to L.dj
+    // diagonal of A to L.dj.  The first update takes E = 0: W is orthonormal
+    // to rounding (the last update of the previous solve converged, or the
+    // sweeps produced it), and the next update measures what it leaves
     fresh();
     {
-      const MatView vt{V, 1, ld};
-      mm_tiles<true, kTwoY>(acc, acc2, RT, wave, lane, vt, vt, MatView{T, ld, 1}, MatView{V, ld, 1});
+      const MatView vt{V, 1, ld}, tv{T, ld, 1};
+      if (upd == 0)
+        mm_tiles<true, kOne>(acc, acc2, RT, wave, lane, vt, vt, tv, tv);
+      else
+        mm_tiles<true, kTwoY>(acc, acc2, RT, wave, lane, vt, vt, tv, MatView{V, ld, 1});
     }
 #pragma unroll
     for (int u = 0; u < kTilesPerWave; ++u) {
@@ -367,7 +372,7 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
         const int i = rt * 16 + lk + 4 * r;
         if (i > j) continue;
         const double a = acc[u][r];
-        const double e = acc2[u][r] - (i == j ? 1.0 : 0.0);
+        const double e = (upd == 0) ? 0.0 : acc2[u][r] - (i == j ? 1.0 : 0.0);
         double xij = 0.0, xji = 0.0;
         if (j < n) {
           if (i == j) {
