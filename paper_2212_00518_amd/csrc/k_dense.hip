@@ -654,7 +654,8 @@ __device__ __forceinline__ void save_basis(const ClassDev& c, const DenLds& L, d
 
 // G = V^T H1 V on the matrix cores into Gd (ranked, sign-fixed basis; rows
 // and columns n .. n_pad - 1 untouched; G on and above the diagonal,
-// mirrored below).  T = H1 V overwrites L.A.
+// mirrored below), and the same n x n block into L.A (row stride
+// n_pad + 1) for the couplings; T = H1 V passes through L.A before.
 __device__ __forceinline__ void dense_project(const ClassDev& c, DenLds& L, double* Gd) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -679,6 +680,7 @@ __device__ __forceinline__ void dense_project(const ClassDev& c, DenLds& L, doub
     const MatView vt{L.V, 1, ld}, t{L.A, ld, 1};
     mm_tiles<true, kOne>(acc, acc2, RT, wave, lane, vt, vt, t, t);
   }
+  __syncthreads();  // every wave done reading T
 #pragma unroll
   for (int u = 0; u < kTilesPerWave; ++u) {
     int rt, ct;
@@ -689,19 +691,23 @@ __device__ __forceinline__ void dense_project(const ClassDev& c, DenLds& L, doub
       const int a = rt * 16 + lk + 4 * r;
       if (a <= b && b < n) {
         const double g = L.sg[a] * L.sg[b] * acc[u][r];
-        Gd[(size_t)L.rank[a] * np + L.rank[b]] = g;
-        Gd[(size_t)L.rank[b] * np + L.rank[a]] = g;
+        const int ra = L.rank[a], rb = L.rank[b];
+        Gd[(size_t)ra * np + rb] = g;
+        Gd[(size_t)rb * np + ra] = g;
+        L.A[ra * ld + rb] = g;
+        L.A[rb * ld + ra] = g;
       }
     }
   }
   __syncthreads();  // Gd complete (work-group visibility of the global writes)
 }
 
-// D_jk = G_jk / (lambda_k - lambda_j); zero on the diagonal and between
-// states whose energies agree to 1e-12 of the largest |lambda|.
-__device__ __forceinline__ double dense_D(const double* Gd, const DenLds& L, int np, double tol, int j, int k) {
+// D_jk = G_jk / (lambda_k - lambda_j) with G from L.A (left there by
+// dense_project); zero on the diagonal and between states whose energies
+// agree to 1e-12 of the largest |lambda|.
+__device__ __forceinline__ double dense_D(const DenLds& L, int ld, double tol, int j, int k) {
   const double diff = L.lam[k] - L.lam[j];
-  return (j == k || fabs(diff) <= tol) ? 0.0 : Gd[(size_t)j * np + k] / diff;
+  return (j == k || fabs(diff) <= tol) ? 0.0 : L.A[j * ld + k] / diff;
 }
 
 __device__ __forceinline__ double lam_tol(const DenLds& L, int n) {
@@ -782,7 +788,7 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double d
       double rsum = 0.0;
       if (rt < RT) {
         for (int k = qtr * kq; k < (qtr + 1) * kq; ++k) {
-          const double val = (j < n && k < n) ? vh * dense_D(Gd, L, np, tol, j, k) : 0.0;
+          const double val = (j < n && k < n) ? vh * dense_D(L, np + 1, tol, j, k) : 0.0;
           rsum += fabs(val);
           const size_t off = ((size_t)((k >> 2) * RT + rt) << 6) + lane_lo + ((k & 3) << 4);
           if (precision == IESH_FP64)
