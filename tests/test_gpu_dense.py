@@ -160,6 +160,40 @@ def test_dense_thirty_step_trajectories_match_the_oracle(M, cap):
     assert compared >= T - 1 and hops >= 5
 
 
+def test_dense_three_hundred_steps_cross_the_cold_solve():
+    """300 FP64 steps at n = 16: the warm eigen-solves refine the carried
+    basis for 255 steps, step 256 solves cold, and the states and hop events
+    still match the oracle's run (no drift of the carried basis)."""
+    from paper_2212_00518_amd import unpack_C
+    M = 15
+    cfg = _cfg(M, N=8)
+    m = models.from_config(cfg, M=M)
+    N, T, steps = cfg["n_elec"], 8, 300
+    states = _states(m, N, T, seed=91, xs=np.linspace(-4.0, 14.0, T), v_scale=0.004)
+    ens = _ensemble(cfg, T)
+    _upload(ens, states)
+    ens.run(steps)
+    x, v, Cf, occ = ens.get_state()
+    evs, _ = ens.events()
+    status = ens.status()
+    ens.close()
+    assert np.all(status == 0)
+    compared = 0
+    for t in range(T):
+        ref, ref_ev, _ = dyn.run(m, states[t], cfg["dt"], steps, cfg["seed"], t)
+        if any(e["margin"] < 1e-7 * max(e["g_total"], 1e-300) for e in ref_ev):
+            continue
+        mine = [(e["step"], e["a"], e["b"], e["accepted"]) for e in evs if e["traj"] == t]
+        assert mine == [(e["step"], e["a"], e["b"], e["accepted"]) for e in ref_ev], t
+        assert abs(x[t] - ref.x[0]) <= 1e-8 * max(1.0, abs(ref.x[0])), t
+        assert abs(v[t] - ref.v[0]) <= 1e-8 * max(1e-3, abs(ref.v[0])), t
+        assert np.max(np.abs(unpack_C(Cf, t, m.n, N, ens.n_max, ens.N_max) - ref.C)) <= 1e-8, t
+        assert list(occ[t, :N]) == list(ref.s), t
+        compared += 1
+    print(f"compared {compared} of {T}", flush=True)
+    assert compared >= T - 1
+
+
 def test_dense_thermal_initialisation_matches_the_oracle():
     """iesh_init_thermal on the dense kind: Fermi occupations at kT over the
     dense eigenvalues (same rule and uniforms as the oracle) and unit-vector
