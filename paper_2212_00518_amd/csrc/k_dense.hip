@@ -303,7 +303,8 @@ __device__ __forceinline__ void full_rayleigh(const ClassDev& c, const double* H
 // series is needed).  A and E are recomputed from the current V each time.
 // The update whose largest |X_ij| is below kPertDone is the last (what it
 // leaves is below rounding relative to the gaps, as after the last Jacobi
-// sweep); the eigenvalues are then the diagonal of V^T H V.  An update whose
+// sweep); the eigenvalues then follow from A, E and that last X to second
+// order, without a last product H V.  An update whose
 // Frobenius norm exceeds kPertMax (close levels, a poor start) or
 // kPertUpdates updates without convergence (fewer when the run caps the
 // eigen-solve's iterations, eig_max_iter) hand A = V^T H V to the sweeps.
@@ -330,6 +331,7 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
     ld = opaque(ld);
   };
   double* T = L.A;  // H V, then X
+  double* const Xm = L.A;
   double* V = L.V;
   v4d acc[kTilesPerWave], acc2[kTilesPerWave];
   fresh();
@@ -384,8 +386,8 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
             if (nji != 0.0) xji = nji / (di - dj);
           }
         }
-        T[i * ld + j] = xij;
-        T[j * ld + i] = xji;
+        Xm[i * ld + j] = xij;
+        Xm[j * ld + i] = xji;
         xmax = fmax(xmax, fmax(fabs(xij), fabs(xji)));
         xsq += (i == j) ? xij * xij : xij * xij + xji * xji;
       }
@@ -412,7 +414,7 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
     // V <- V + V X
     fresh();
     {
-      const MatView v{V, ld, 1}, x{T, ld, 1};
+      const MatView v{V, ld, 1}, x{Xm, ld, 1};
       mm_tiles<false, kOne>(acc, acc2, RT, wave, lane, v, v, x, x);
     }
     __syncthreads();  // every wave done reading V, X and L.red
@@ -426,21 +428,29 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
       for (int r = 0; r < 4; ++r) V[(rt * 16 + lk + 4 * r) * ld + j] += acc[u][r];
     }
     ++applied;
-    __syncthreads();
-    fresh();
-    hv_product(Hx, L, np, ld, T, ld);
-    __syncthreads();
     if (xmax <= kPertDone) {
-      // eigenvalues: the diagonal of V^T T (thread i reads column i only)
+      // eigenvalues of the updated V to second order in X (the first-order
+      // relation A_kj = X_kj (A_jj - A_kk) + A_jj E_kj, E_jj = -2 X_jj):
+      //   lambda_j = A_jj (1 + 2 X_jj) + sum_{k != j} X_kj^2 (A_jj - A_kk),
+      // the neglected terms below 1e-20 relative for |X| <= kPertDone; thread
+      // j reads column j of X only and leaves lambda_j on L.A's diagonal
       fresh();
-      for (int i = tid; i < n; i += kDenThreads) {
-        double d = 0.0;
-        for (int k = 0; k < n; ++k) d += V[k * ld + i] * T[k * ld + i];
-        T[i * ld + i] = d;
+      for (int j = tid; j < n; j += kDenThreads) {
+        const double dj = L.dj[j];
+        double s2 = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double xk = Xm[k * ld + j];
+          if (k != j) s2 += xk * xk * (dj - L.dj[k]);
+        }
+        Xm[j * ld + j] = dj * (1.0 + 2.0 * Xm[j * ld + j]) + s2;
       }
       __syncthreads();
       return true;
     }
+    __syncthreads();
+    fresh();
+    hv_product(Hx, L, np, ld, T, ld);
+    __syncthreads();
   }
   if (applied == 0) {
     full_rayleigh(c, Hx, L, tmp);
