@@ -304,10 +304,10 @@ __device__ __forceinline__ void full_rayleigh(const ClassDev& c, const double* H
 // The update whose largest |X_ij| is below kPertDone is the last (what it
 // leaves is below rounding relative to the gaps, as after the last Jacobi
 // sweep); the eigenvalues then follow from A, E and that last X to second
-// order, without a last product H V.  An update whose
-// Frobenius norm exceeds kPertMax (close levels, a poor start) or
-// kPertUpdates updates without convergence (fewer when the run caps the
-// eigen-solve's iterations, eig_max_iter) hand A = V^T H V to the sweeps.
+// order, without a last product H V.  An update whose Frobenius norm
+// exceeds kPertMax (close levels, a poor start) or kPertUpdates updates
+// without convergence (fewer when the run caps the eigen-solve's
+// iterations, eig_max_iter) hand over to the Jacobi sweeps.
 constexpr int kPertUpdates = 6;
 constexpr double kPertDone = 1e-8;
 constexpr double kPertMax = 0.1;
