@@ -8,7 +8,10 @@
 // pair once in m - 1 rounds of m/2 disjoint pairs (round-robin schedule over
 // m = n rounded up to even; pairs with the padding index are skipped), so
 // the rotations of a round are independent: one pass rotates the rows of
-// every pair, a second the columns of A and V.  The rotation of pair (p, q)
+// every pair, a second the columns of A and V.  In the global workspace V is
+// kept transposed (row j holds eigenvector j), so its update walks rows and
+// only A's column update reads one cache line per element.  The rotation of
+// pair (p, q)
 // annihilates a_pq (Golub and Van Loan, symmetric Schur decomposition):
 //   tau = (a_qq - a_pp) / (2 a_pq),  t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
 //   c = 1 / sqrt(1 + t^2),  s = t c,  A <- J^T A J,  V <- V J,
@@ -50,7 +53,9 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   const int m = n + (n & 1), half = m / 2;
   const int ld = m + 1;             // row stride: a column walk spreads over the LDS banks
   double* A = kLds ? sm : work + (size_t)b * 2 * m * ld;  // [m][ld]
-  double* V = A + (size_t)m * ld;   // [m][ld]
+  double* V = A + (size_t)m * ld;   // [m][ld]: V, transposed in the workspace
+  // element (i, j) of V: row-major in LDS, column-major in the workspace
+  const auto vix = [ld](int i, int j) { return kLds ? i * ld + j : j * ld + i; };
   double* cs = kLds ? V + (size_t)m * ld : sm;  // [half] cosines of the round
   double* sn = cs + half;           // [half] sines
   int* pq = reinterpret_cast<int*>(sn + half);  // [m]: p, q of each pair
@@ -60,7 +65,7 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   for (int idx = tid; idx < m * m; idx += kJacThreads) {
     const int i = idx / m, j = idx - i * m;
     A[(size_t)i * ld + j] = (i < n && j < n) ? Hb[(size_t)i * n + j] : 0.0;
-    V[(size_t)i * ld + j] = (i == j) ? 1.0 : 0.0;
+    V[vix(i, j)] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
 
@@ -159,8 +164,8 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
             if (ss[i] != 0.0) {
               ap[i] = A[j * ld + pp[i]];
               aq[i] = A[j * ld + qq[i]];
-              vp[i] = V[j * ld + pp[i]];
-              vq[i] = V[j * ld + qq[i]];
+              vp[i] = V[vix(j, pp[i])];
+              vq[i] = V[vix(j, qq[i])];
             }
 #pragma unroll
           for (int i = 0; i < kChunk; ++i)
@@ -168,8 +173,8 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
               // the annihilated pair (rows p and q of columns q and p) is set to zero
               A[j * ld + pp[i]] = (j == qq[i]) ? 0.0 : cc[i] * ap[i] - ss[i] * aq[i];
               A[j * ld + qq[i]] = (j == pp[i]) ? 0.0 : ss[i] * ap[i] + cc[i] * aq[i];
-              V[j * ld + pp[i]] = cc[i] * vp[i] - ss[i] * vq[i];
-              V[j * ld + qq[i]] = ss[i] * vp[i] + cc[i] * vq[i];
+              V[vix(j, pp[i])] = cc[i] * vp[i] - ss[i] * vq[i];
+              V[vix(j, qq[i])] = ss[i] * vp[i] + cc[i] * vq[i];
             }
         }
       }
@@ -198,10 +203,10 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
   __syncthreads();
   for (int j = tid; j < n; j += kJacThreads) {
     double vmax = 0.0;
-    for (int i = 0; i < n; ++i) vmax = fmax(vmax, fabs(V[(size_t)i * ld + j]));
+    for (int i = 0; i < n; ++i) vmax = fmax(vmax, fabs(V[vix(i, j)]));
     double sgn = 1.0;
     for (int i = 0; i < n; ++i) {
-      const double v = V[(size_t)i * ld + j];
+      const double v = V[vix(i, j)];
       if (fabs(v) > 1e-12 * vmax) {
         sgn = v < 0.0 ? -1.0 : 1.0;
         break;
@@ -210,7 +215,7 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
     const int rk = rank[j];
     lam[(size_t)b * n + rk] = A[(size_t)j * ld + j];
     double* Qb = Q + (size_t)b * n * n;
-    for (int i = 0; i < n; ++i) Qb[(size_t)i * n + rk] = sgn * V[(size_t)i * ld + j];
+    for (int i = 0; i < n; ++i) Qb[(size_t)i * n + rk] = sgn * V[vix(i, j)];
   }
   if (tid == 0 && sweeps_out) sweeps_out[b] = converged ? sweep + 1 : -1;
 }
