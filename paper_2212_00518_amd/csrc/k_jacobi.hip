@@ -7,11 +7,11 @@
 // workspace (same code, generic pointers).  A sweep visits every index
 // pair once in m - 1 rounds of m/2 disjoint pairs (round-robin schedule over
 // m = n rounded up to even; pairs with the padding index are skipped), so
-// the rotations of a round are independent: one pass rotates the rows of
-// every pair, a second the columns of A and V.  In the global workspace V is
-// kept transposed (row j holds eigenvector j), so its update walks rows and
-// only A's column update reads one cache line per element.  The rotation of
-// pair (p, q)
+// the rotations of a round are independent, and A <- J^T A J takes one pass
+// over 2x2 blocks (rows of one pair, columns of another), each a function of
+// itself alone, so a round touches A by rows only and in place.  In the
+// global workspace V is kept transposed (row j holds eigenvector j), so its
+// update walks rows too.  The rotation of pair (p, q)
 // annihilates a_pq (Golub and Van Loan, symmetric Schur decomposition):
 //   tau = (a_qq - a_pp) / (2 a_pq),  t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
 //   c = 1 / sqrt(1 + t^2),  s = t c,  A <- J^T A J,  V <- V J,
@@ -29,7 +29,6 @@ namespace {
 
 constexpr int kJacThreads = 256;
 constexpr int kJacWaves = kJacThreads / 64;
-constexpr int kChunk = 2;  // pairs a wave rotates per batch of loads
 // A sweep whose rotations all have |tan| below this ends the iteration: the
 // off-diagonal elements it leaves are about the square of its largest
 // rotation relative to the gaps, so the next sweep would only rotate by
@@ -112,70 +111,40 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
         sn[k] = s;
       }
       __syncthreads();
-      // rows p, q of every pair: rows <- J^T rows.  A wave takes pairs wave,
-      // wave + 4, ... (kChunk at a time) and a lane columns lane, lane + 64,
-      // ...; the elements of a chunk are all loaded before any is stored.
-      for (int k0 = wave; k0 < half; k0 += kJacWaves * kChunk) {
-        int pp[kChunk], qq[kChunk];
-        double cc[kChunk], ss[kChunk];
-#pragma unroll
-        for (int i = 0; i < kChunk; ++i) {
-          const int k = k0 + kJacWaves * i, kk = (k < half) ? k : 0;
-          ss[i] = (k < half) ? sn[kk] : 0.0;  // 0: nothing to apply (uniform)
-          cc[i] = cs[kk];
-          pp[i] = pq[2 * kk];
-          qq[i] = pq[2 * kk + 1];
-        }
+      // A <- J^T A J in one pass: the 2x2 block of rows (p_a, q_a) and
+      // columns (p_b, q_b) becomes J_a^T B J_b and depends on that block
+      // only, so a lane reads and then writes its own four elements (a wave
+      // takes row pairs a = wave, wave + 4, ..., a lane column pairs
+      // b = lane, lane + 64, ...; blocks of two pairs without rotation stay).
+      // V <- V J_a in the same pass (columns p_a, q_a of V).
+      for (int a = wave; a < half; a += kJacWaves) {
+        const int pa = pq[2 * a], qa = pq[2 * a + 1];
+        const double ca = cs[a], sa = sn[a];
+        double* rp = A + (size_t)pa * ld;
+        double* rq = A + (size_t)qa * ld;
 #pragma unroll 1
-        for (int j = lane; j < m; j += 64) {
-          double ap[kChunk], aq[kChunk];
-#pragma unroll
-          for (int i = 0; i < kChunk; ++i)
-            if (ss[i] != 0.0) {
-              ap[i] = A[pp[i] * ld + j];
-              aq[i] = A[qq[i] * ld + j];
-            }
-#pragma unroll
-          for (int i = 0; i < kChunk; ++i)
-            if (ss[i] != 0.0) {
-              A[pp[i] * ld + j] = cc[i] * ap[i] - ss[i] * aq[i];
-              A[qq[i] * ld + j] = ss[i] * ap[i] + cc[i] * aq[i];
-            }
+        for (int bb = lane; bb < half; bb += 64) {
+          const double sb = sn[bb];
+          if (sa == 0.0 && sb == 0.0) continue;
+          const int pb = pq[2 * bb], qb = pq[2 * bb + 1];
+          const double cb = cs[bb];
+          const double a_pp = rp[pb], a_pq = rp[qb], a_qp = rq[pb], a_qq = rq[qb];
+          // rows: J_a^T B
+          const double xpp = ca * a_pp - sa * a_qp, xpq = ca * a_pq - sa * a_qq;
+          const double xqp = sa * a_pp + ca * a_qp, xqq = sa * a_pq + ca * a_qq;
+          // columns: (J_a^T B) J_b; the annihilated pair is set to zero
+          rp[pb] = cb * xpp - sb * xpq;
+          rp[qb] = (bb == a) ? 0.0 : sb * xpp + cb * xpq;
+          rq[pb] = (bb == a) ? 0.0 : cb * xqp - sb * xqq;
+          rq[qb] = sb * xqp + cb * xqq;
         }
-      }
-      __syncthreads();
-      // columns p, q of A and V: columns <- columns J (a lane per row)
-      for (int k0 = wave; k0 < half; k0 += kJacWaves * kChunk) {
-        int pp[kChunk], qq[kChunk];
-        double cc[kChunk], ss[kChunk];
-#pragma unroll
-        for (int i = 0; i < kChunk; ++i) {
-          const int k = k0 + kJacWaves * i, kk = (k < half) ? k : 0;
-          ss[i] = (k < half) ? sn[kk] : 0.0;
-          cc[i] = cs[kk];
-          pp[i] = pq[2 * kk];
-          qq[i] = pq[2 * kk + 1];
-        }
+        if (sa != 0.0) {
 #pragma unroll 1
-        for (int j = lane; j < m; j += 64) {
-          double ap[kChunk], aq[kChunk], vp[kChunk], vq[kChunk];
-#pragma unroll
-          for (int i = 0; i < kChunk; ++i)
-            if (ss[i] != 0.0) {
-              ap[i] = A[j * ld + pp[i]];
-              aq[i] = A[j * ld + qq[i]];
-              vp[i] = V[vix(j, pp[i])];
-              vq[i] = V[vix(j, qq[i])];
-            }
-#pragma unroll
-          for (int i = 0; i < kChunk; ++i)
-            if (ss[i] != 0.0) {
-              // the annihilated pair (rows p and q of columns q and p) is set to zero
-              A[j * ld + pp[i]] = (j == qq[i]) ? 0.0 : cc[i] * ap[i] - ss[i] * aq[i];
-              A[j * ld + qq[i]] = (j == pp[i]) ? 0.0 : ss[i] * ap[i] + cc[i] * aq[i];
-              V[vix(j, pp[i])] = cc[i] * vp[i] - ss[i] * vq[i];
-              V[vix(j, qq[i])] = ss[i] * vp[i] + cc[i] * vq[i];
-            }
+          for (int j = lane; j < m; j += 64) {
+            const double vp = V[vix(j, pa)], vq = V[vix(j, qa)];
+            V[vix(j, pa)] = ca * vp - sa * vq;
+            V[vix(j, qa)] = sa * vp + ca * vq;
+          }
         }
       }
       __syncthreads();
