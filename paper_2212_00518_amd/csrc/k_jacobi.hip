@@ -27,7 +27,7 @@
 namespace iesh {
 namespace {
 
-constexpr int kJacThreads = 256;
+constexpr int kJacThreads = 1024;
 constexpr int kJacWaves = kJacThreads / 64;
 // A sweep whose rotations all have |tan| below this ends the iteration: the
 // off-diagonal elements it leaves are about the square of its largest
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kJacThreads) void k_jacobi(const double* __restrict
       // A <- J^T A J in one pass: the 2x2 block of rows (p_a, q_a) and
       // columns (p_b, q_b) becomes J_a^T B J_b and depends on that block
       // only, so a lane reads and then writes its own four elements (a wave
-      // takes row pairs a = wave, wave + 4, ..., a lane column pairs
+      // takes row pairs a = wave, wave + 16, ..., a lane column pairs
       // b = lane, lane + 64, ...; blocks of two pairs without rotation stay).
       // V <- V J_a in the same pass (columns p_a, q_a of V).
       for (int a = wave; a < half; a += kJacWaves) {
