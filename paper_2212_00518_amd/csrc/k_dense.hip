@@ -776,9 +776,10 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double d
   double* Gd = c.Gd + (size_t)t * np * np;
   // warm starts from the previous solve of this trajectory (its block is
   // keyed by the home index, so it needs no move when slots are compacted);
-  // every kDenseColdEvery steps the solves start cold (a bound on how long
-  // a trajectory's solves depend on a carried basis; the refinement itself
-  // restores orthonormality at every update)
+  // every kDenseColdEvery steps the midpoint solve starts cold (a bound on
+  // how long a trajectory's solves depend on a carried basis; the refinement
+  // itself restores orthonormality at every update), and the end-point solve
+  // always starts from the midpoint solve of its own step
   double* W = c.Qw + (size_t)c.home[t] * np * np;
   const bool warm = (c.nsteps[t] % kDenseColdEvery) != 0;
   if (sub != -2) {
@@ -833,7 +834,7 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double d
   }
   // ---- end point: energies, amplitudes, couplings for the hop, forces
   const double xn = L.nuc[1];
-  if (!dense_eigen(c, xn, L, warm ? W : nullptr, Gd) && tid == 0) L.flag[1] |= 1;
+  if (!dense_eigen(c, xn, L, W, Gd) && tid == 0) L.flag[1] |= 1;
   save_basis(c, L, W);
   dense_project(c, L, Gd);
   for (int j = tid; j < np; j += kDenThreads) {
