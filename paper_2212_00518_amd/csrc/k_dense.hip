@@ -302,14 +302,17 @@ __device__ __forceinline__ void full_rayleigh(const ClassDev& c, const double* H
 // orthonormality restored at each update instead of carried (no exponential
 // series is needed).  A and E are recomputed from the current V each time.
 // The update whose largest |X_ij| is below kPertDone is the last (what it
-// leaves is below rounding relative to the gaps, as after the last Jacobi
-// sweep); the eigenvalues then follow from A, E and that last X to second
+// leaves is below FP64 rounding relative to the gaps, as after the last
+// Jacobi sweep; on the mixed path kPertDoneMixed, which leaves eigenvector
+// errors of a few 1e-10, far below the FP32 propagation's rounding and its
+// 2^-26 series truncation); the eigenvalues then follow from A, E and that last X to second
 // order, without a last product H V.  An update whose Frobenius norm
 // exceeds kPertMax (close levels, a poor start) or kPertUpdates updates
 // without convergence (fewer when the run caps the eigen-solve's
 // iterations, eig_max_iter) hand over to the Jacobi sweeps.
 constexpr int kPertUpdates = 6;
 constexpr double kPertDone = 1e-8;
+constexpr double kPertDoneMixed = 1e-5;
 constexpr double kPertMax = 0.1;
 
 // Refines V (in L.V) for Hx = H(x) (n_pad x n_pad, global); L.A and L.dj
@@ -319,7 +322,8 @@ constexpr double kPertMax = 0.1;
 // warm start itself, L.A = W^T H W, when the first update is refused; else
 // (the updates leave V orthonormal only once they converge) the cold start,
 // L.A = H(x) and V = I.
-__device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* Hx, DenLds& L, double* tmp) {
+__device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* Hx, DenLds& L, double* tmp,
+                                               double done) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lr = lane & 15, lk = lane >> 4;
@@ -428,11 +432,13 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
       for (int r = 0; r < 4; ++r) V[(rt * 16 + lk + 4 * r) * ld + j] += acc[u][r];
     }
     ++applied;
-    if (xmax <= kPertDone) {
+    if (xmax <= done) {
       // eigenvalues of the updated V to second order in X (the first-order
       // relation A_kj = X_kj (A_jj - A_kk) + A_jj E_kj, E_jj = -2 X_jj):
       //   lambda_j = A_jj (1 + 2 X_jj) + sum_{k != j} X_kj^2 (A_jj - A_kk),
-      // the neglected terms below 1e-20 relative for |X| <= kPertDone; thread
+      // the neglected terms are of order |X|^3 and E_jj^2 (the E X terms
+      // cancel against the normalisation): below 1e-20 relative after
+      // kPertDone, 1e-12 after kPertDoneMixed; thread
       // j reads column j of X only and leaves lambda_j on L.A's diagonal
       fresh();
       for (int j = tid; j < n; j += kDenThreads) {
@@ -475,7 +481,7 @@ __device__ __forceinline__ bool perturb_refine(const ClassDev& c, const double* 
 // eigenvectors (Jacobi order, unsigned).  Returns false when the sweeps did
 // not converge.
 __device__ __forceinline__ bool dense_eigen(const ClassDev& c, double x, DenLds& L, double* W = nullptr,
-                                            double* tmp = nullptr) {
+                                            double* tmp = nullptr, double done = kPertDone) {
   const int tid = threadIdx.x;
   const int n = c.md.n, np = c.md.n_pad, ld = np + 1;
   const int m = n + (n & 1), half = m / 2;
@@ -489,7 +495,7 @@ __device__ __forceinline__ bool dense_eigen(const ClassDev& c, double x, DenLds&
       W[idx] = c.H0[idx] + x * c.H1[idx];
     }
     __syncthreads();  // (work-group visibility of the global writes)
-    converged = perturb_refine(c, W, L, tmp);
+    converged = perturb_refine(c, W, L, tmp, done);
   } else {
     const double* H0 = c.H0;
     const double* H1 = c.H1;
@@ -782,9 +788,10 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double d
   // always starts from the midpoint solve of its own step
   double* W = c.Qw + (size_t)c.home[t] * np * np;
   const bool warm = (c.nsteps[t] % kDenseColdEvery) != 0;
+  const double done = (precision == IESH_FP64) ? kPertDone : kPertDoneMixed;
   if (sub != -2) {
     // ---- propagator geometry: B = v D in the propagation's tile order
-    if (!dense_eigen(c, L.nuc[2], L, warm ? W : nullptr, Gd) && tid == 0) L.flag[1] |= 1;
+    if (!dense_eigen(c, L.nuc[2], L, warm ? W : nullptr, Gd, done) && tid == 0) L.flag[1] |= 1;
     save_basis(c, L, W);
     dense_project(c, L, Gd);
     const double tol = lam_tol(L, n);
@@ -834,7 +841,7 @@ __global__ __launch_bounds__(kDenThreads) void k_dense_step(ClassDev c, double d
   }
   // ---- end point: energies, amplitudes, couplings for the hop, forces
   const double xn = L.nuc[1];
-  if (!dense_eigen(c, xn, L, W, Gd) && tid == 0) L.flag[1] |= 1;
+  if (!dense_eigen(c, xn, L, W, Gd, done) && tid == 0) L.flag[1] |= 1;
   save_basis(c, L, W);
   dense_project(c, L, Gd);
   for (int j = tid; j < np; j += kDenThreads) {
