@@ -183,6 +183,11 @@ __device__ inline double quad_root_in(double a2, double a1, double a0, double al
 // pole, far below rounding), and f' at the accepted point differs from f' at
 // the last evaluated one by about twice the step over that distance.
 constexpr double kStepAccept = 1e-13;
+// The same on the mixed path's step solves: the accepted root is still
+// accurate to about the step squared (1e-18 relative), and f' (so Q0) to
+// about 2e-9, far below the FP32 propagation's rounding; it saves the last
+// evaluation of most roots.
+constexpr double kStepAcceptMixed = 1e-9;
 
 // Root j (0..M) of the secular function; j0 as in secular_eval.  Returns 1
 // on convergence.  Warm start (dlt >= 0): the root is known to lie within dlt
@@ -197,7 +202,7 @@ constexpr double kStepAccept = 1e-13;
 // (within a relative 2 kStepAccept of the returned root, so f' there is f' at
 // the root to about 1e-13).
 __device__ int secular_root(int j, int j0, int M, const double* e, const double* V2, double h,
-                            double vnorm, int max_it, double lam_g, double dlt, double lam_s,
+                            double vnorm, int max_it, double accept, double lam_g, double dlt, double lam_s,
                             double& tau_out, int& org_out, double& dsum_out, int g = 0, int G = 1) {
   int o;
   double lo, hi, tau, f = 0.0, dl = 0.0, dr = 0.0, err = 0.0;
@@ -327,7 +332,7 @@ __device__ int secular_root(int j, int j0, int M, const double* e, const double*
     }
     double tn = tau + eta;
     if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-    if (fabs(tn - tau) <= kStepAccept * fabs(tn) ||
+    if (fabs(tn - tau) <= accept * fabs(tn) ||
         hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi))) {
       tau = tn;
       ok = 1;
@@ -374,7 +379,8 @@ __device__ inline RootStore root_store(const ClassDev& c, int t) {
 template <bool kLoewner = false>
 __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict__ vbar,
                                    const double* x, EigLds& L, RootStore rs = RootStore{},
-                                   bool warm = false, bool store = false) {
+                                   bool warm = false, bool store = false,
+                                   double accept = kStepAccept) {
   // the secular problem over the distinct bath energies (M = M_red poles,
   // M + 1 roots); repeated energies are expanded into deflated states below
   const int M = md.M_red, n = M + 1, tid = threadIdx.x;
@@ -428,7 +434,7 @@ __device__ ModelAt solve_arrowhead(const ModelDev& md, const double* __restrict_
       lam_s = lam_g + q2 * (dh0 + 2.0 * (lam_g - h0) * dfr);
     }
     double dsum = 0.0;
-    const int ok = secular_root(j, jb, M, L.e, L.V2, ma.h, vnorm, md.eig_iter, lam_g, dlt, lam_s, tau,
+    const int ok = secular_root(j, jb, M, L.e, L.V2, ma.h, vnorm, md.eig_iter, accept, lam_g, dlt, lam_s, tau,
                                 o, dsum, g, G);
     if (g == 0) {
       L.tau[j] = tau;
@@ -655,9 +661,12 @@ __device__ void eig_step_one(const ClassDev& c, int t, double dt_run, int precis
   // warm starts from the trajectory's previous solve (not along prescribed
   // paths, whose backward pass revisits steps out of order)
   const bool warm = c.root_tau && !c.path;
+  // the mixed path's step solves stop the secular iteration earlier (not
+  // along prescribed paths, whose gradients are FP64)
+  const double accept = (precision == IESH_FP64 || c.path) ? kStepAccept : kStepAcceptMixed;
   RootStore rs{};
   if (warm) rs = root_store(c, t);
-  ModelAt mm = solve_arrowhead(md, c.vbar, L.nuc[2], L, rs, warm, warm);
+  ModelAt mm = solve_arrowhead(md, c.vbar, L.nuc[2], L, rs, warm, warm, accept);
   double vfac = vh;
   if (nd > 1) {
     // v . D over the coordinates: the gradients enter through v.grad h and v.grad f / f
@@ -739,7 +748,8 @@ __device__ void eig_step_one(const ClassDev& c, int t, double dt_run, int precis
   const bool warm_end = c.root_tau && !c.path;
   RootStore rse{};
   if (warm_end) rse = root_store(c, t);
-  const ModelAt mn = solve_arrowhead(md, c.vbar, L.nuc[1], L, rse, warm_end, warm_end);
+  const ModelAt mn = solve_arrowhead(md, c.vbar, L.nuc[1], L, rse, warm_end, warm_end,
+                                     (precision == IESH_FP64 || c.path) ? kStepAccept : kStepAcceptMixed);
   for (int j = tid; j < n_pad; j += kEigThreads) {
     c.lam[(size_t)t * n_pad + j] = L.lam[j];
     c.q0[(size_t)t * n_pad + j] = L.q0[j];
